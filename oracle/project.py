@@ -1,0 +1,113 @@
+"""Galerkin projection of the global system and the reduced solve (test infrastructure).
+
+Section 6, step 3: Q^T A Q is built block by block (eq. 6.1) without forming A
+or Q.  Diagonal blocks come from the local step.  An off-diagonal block
+Q_i^T A_ij Q_j is non-zero only for neighbouring subdomains; its entries depend
+only on the elements of omega_0 (elements in two or more subdomains), so it is
+computed from a stiffness matrix A_0 assembled on omega_0 and the rows of Q_i
+and Q_j on the shared nodes.  The reduced system is then solved; the paper uses
+PCG with a diagonal preconditioner, here a dense Cholesky factorization gives
+the same solution.
+"""
+from __future__ import annotations
+
+import numpy as np
+import scipy.linalg as la
+import scipy.sparse as sp
+
+from . import decomp, fem
+
+
+def offsets(results) -> np.ndarray:
+    return np.concatenate([[0], np.cumsum([r.k_eff + 1 for r in results])]).astype(np.int64)
+
+
+def omega0_stiffness(mesh, kappa, subdomains) -> sp.csr_matrix:
+    """A_0: the stiffness matrix assembled over omega_0 only, on all free nodes."""
+    t0 = decomp.omega0_tets(mesh, subdomains)
+    free = np.flatnonzero(mesh.dirichlet == 0)
+    gmap = -np.ones(mesh.n_nodes, dtype=np.int64)
+    gmap[free] = np.arange(free.size)
+    Ke, _, _ = fem.element_matrices(mesh.xyz, mesh.tets[t0], kappa[t0])
+    A0 = fem.assemble(Ke, mesh.tets[t0], gmap, free.size)
+    return A0, free, gmap
+
+
+def neighbour_blocks(mesh, kappa, subdomains, results):
+    """Off-diagonal blocks {(i, j): Q_i^T A_ij Q_j} for i != j, from A_0 and the interface rows."""
+    sets = [r.sets for r in results]
+    owner = decomp.owner_map(mesh, sets)
+    A0, free, gmap = omega0_stiffness(mesh, kappa, subdomains)
+    coo = A0.tocoo()
+    gi, gj = free[coo.row], free[coo.col]
+    oi, oj = owner[gi], owner[gj]
+    cross = oi != oj
+    pos = []
+    for r in results:
+        m = -np.ones(mesh.n_nodes, dtype=np.int64)
+        m[r.sets.P] = np.arange(r.sets.P.size)
+        pos.append(m)
+    blocks = {}
+    pairs = np.unique(np.stack([oi[cross], oj[cross]], axis=1), axis=0)
+    for i, j in pairs:
+        sel = cross & (oi == i) & (oj == j)
+        rows_g, cols_g, vals = gi[sel], gj[sel], coo.data[sel]
+        Gij = np.unique(rows_g)       # Gamma_ij: nodes of P_i coupled to P_j
+        Gji = np.unique(cols_g)
+        rloc = np.searchsorted(Gij, rows_g)
+        cloc = np.searchsorted(Gji, cols_g)
+        Asub = sp.coo_matrix((vals, (rloc, cloc)), shape=(Gij.size, Gji.size)).toarray()
+        Vi = results[i].Vloc[pos[i][Gij]]
+        Vj = results[j].Vloc[pos[j][Gji]]
+        blocks[(int(i), int(j))] = Vi.T @ Asub @ Vj
+    return blocks
+
+
+def reduced_system(mesh, kappa, subdomains, results):
+    """Dense reduced matrix Q^T A Q and load Q^T b, assembled block by block."""
+    off = offsets(results)
+    n = int(off[-1])
+    At = np.zeros((n, n))
+    bt = np.zeros(n)
+    for i, r in enumerate(results):
+        At[off[i]:off[i + 1], off[i]:off[i + 1]] = r.Aii
+        bt[off[i]:off[i + 1]] = r.bi
+    for (i, j), blk in neighbour_blocks(mesh, kappa, subdomains, results).items():
+        At[off[i]:off[i + 1], off[j]:off[j + 1]] = blk
+    return 0.5 * (At + At.T), bt, off
+
+
+def solve_reduced(At: np.ndarray, bt: np.ndarray, pinv_rtol: float | None = None) -> np.ndarray:
+    """Cholesky solve; with pinv_rtol, a pseudo-inverse that drops eigenvalues below
+    pinv_rtol * lambda_max (for full-rank bases whose stitched columns are dependent)."""
+    if pinv_rtol is None:
+        return la.cho_solve(la.cho_factor(At, lower=False), bt)
+    w, U = la.eigh(At)
+    keep = w > pinv_rtol * w.max()
+    return U[:, keep] @ ((U[:, keep].T @ bt) / w[keep])
+
+
+def reconstruct(mesh, results, x: np.ndarray) -> np.ndarray:
+    """u~ = sum_i S_i (Q_i x_i): on P_i the value is Vloc_i x_i; zero on the Dirichlet nodes."""
+    off = offsets(results)
+    u = np.zeros(mesh.n_nodes)
+    for i, r in enumerate(results):
+        u[r.sets.P] = r.Vloc @ x[off[i]:off[i + 1]]
+    return u
+
+
+def dense_QtAQ(mesh, kappa, results):
+    """The straightforward projection: form Q (free nodes x reduced) and A, multiply."""
+    A, _, free, gmap = fem.global_system(mesh, kappa, None)
+    off = offsets(results)
+    rows, cols, vals = [], [], []
+    for i, r in enumerate(results):
+        k1 = r.k_eff + 1
+        rr = np.repeat(gmap[r.sets.P], k1)
+        cc = np.tile(np.arange(off[i], off[i] + k1), r.sets.P.size)
+        rows.append(rr)
+        cols.append(cc)
+        vals.append(r.Vloc.ravel())
+    Q = sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
+                      shape=(free.size, int(off[-1])))
+    return (Q.T @ (A @ Q)).toarray(), Q

@@ -1,0 +1,180 @@
+"""Local reduction on one subdomain, in float64 (test infrastructure, see package docstring).
+
+Steps, in the paper's order (Section 6, step 2, built on Sections 3 and 4):
+  1. assemble the stiffness A_i^+ on omega_i^+ and split it into the I/B blocks;
+  2. solve the zero-boundary load problem (Problem 3.2) for q_0 and the lifting
+     problems (Problem 3.3) for every interface basis function: the matrix of the
+     lifting operator Z_i = C_i (A_II^+)^{-1} A_IB^+ (Section 4), taken with the
+     minus sign of the true harmonic extension (the paper drops it; the sign changes
+     neither the singular values nor the spans);
+  3. the weights: R_i = Cholesky factor of the H1 matrix on omega_i (Section 4) and
+     R_BB = Cholesky factor of the Schur complement of the H1 matrix on omega_i^+
+     onto B (Lemmas 4.1 and 4.2);
+  4. the SVD  R_i Z_i R_BB^{-1} = U Lambda V^T  (eq. 4.4 of Section 4) and the
+     truncation to the leading singular triplets (eq. 4.5);
+  5. the basis R_i^{-1} U_k, then D_i restricts it to the interior of omega_i
+     (the stitching, Definition 3.1), together with q_0;
+  6. the local projected block Q_i^T A_ii Q_i and load Q_i^T f_i (Section 6, step 2).
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+
+import numpy as np
+import scipy.linalg as la
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+
+from . import decomp, fem
+
+CLUSTER_GAP = 1e-4
+
+
+@dataclass
+class LocalMatrices:
+    sets: decomp.LocalSets
+    A_plus: sp.csr_matrix   # stiffness (kappa) on [I, B]
+    K_plus: sp.csr_matrix   # H1 matrix (unweighted stiffness + mass) on [I, B]
+    f_plus: np.ndarray      # load on [I, B]
+    K_i: sp.csr_matrix      # H1 matrix on omega_i over V
+    nI: int
+    nB: int
+    C_idx: np.ndarray       # positions of V inside I (the restriction C_i)
+    D_idx: np.ndarray       # positions of P inside V (the restriction D_i)
+
+
+@dataclass
+class LocalResult:
+    sets: decomp.LocalSets
+    sigma: np.ndarray       # singular values of R_i Z_i R_BB^{-1}, descending
+    k_eff: int              # number of lifting modes kept
+    q0: np.ndarray          # (|V|,) zero-boundary load solution restricted to omega_i
+    Phi: np.ndarray         # (|V|, k_eff) = R_i^{-1} U_k: H1(omega_i)-orthonormal lifting modes
+    Vloc: np.ndarray        # (|P|, k_eff+1) stitched basis D_i [q0, Phi]
+    Aii: np.ndarray         # (k_eff+1, k_eff+1) = Vloc^T A_PP Vloc
+    bi: np.ndarray          # (k_eff+1,) = Vloc^T f_P
+
+
+def local_matrices(mesh, kappa, f_nodal, sets: decomp.LocalSets) -> LocalMatrices:
+    L = np.concatenate([sets.I, sets.B])
+    lmap = -np.ones(mesh.n_nodes, dtype=np.int64)
+    lmap[L] = np.arange(L.size)
+    ext = mesh.tets[sets.ext_tets]
+    Ke, G, Me = fem.element_matrices(mesh.xyz, ext, kappa[sets.ext_tets])
+    A_plus = fem.assemble(Ke, ext, lmap, L.size)
+    K_plus = fem.assemble(G + Me, ext, lmap, L.size)
+    f_plus = fem.load_vector(Me, ext, f_nodal, mesh.n_nodes, lmap, L.size)
+    vmap = -np.ones(mesh.n_nodes, dtype=np.int64)
+    vmap[sets.V] = np.arange(sets.V.size)
+    core = mesh.tets[sets.core_tets]
+    _, Gc, Mc = fem.element_matrices(mesh.xyz, core, kappa[sets.core_tets])
+    K_i = fem.assemble(Gc + Mc, core, vmap, sets.V.size)
+    C_idx = np.searchsorted(sets.I, sets.V)
+    if not np.array_equal(sets.I[C_idx], sets.V):
+        raise ValueError("omega_i is not inside the interior of omega_i^+ (need r >= 1)")
+    D_idx = np.searchsorted(sets.V, sets.P)
+    return LocalMatrices(sets=sets, A_plus=A_plus, K_plus=K_plus, f_plus=f_plus, K_i=K_i,
+                         nI=sets.I.size, nB=sets.B.size, C_idx=C_idx, D_idx=D_idx)
+
+
+def blocks(Mat: sp.csr_matrix, nI: int):
+    return Mat[:nI, :nI].tocsc(), Mat[:nI, nI:], Mat[nI:, :nI], Mat[nI:, nI:]
+
+
+def lifting(lm: LocalMatrices):
+    """Solve A_II X = [-A_IB, f_I] (Problems 3.2-3.3): columns 0..M-1 lift the interface
+    hat functions, column M is the zero-boundary load solution."""
+    A_II, A_IB, _, _ = blocks(lm.A_plus, lm.nI)
+    rhs = np.hstack([-A_IB.toarray(), lm.f_plus[:lm.nI, None]])
+    lu = spla.splu(A_II)
+    return lu.solve(rhs)
+
+
+def schur_H1(lm: LocalMatrices) -> np.ndarray:
+    """Schur complement K_BB - K_BI K_II^{-1} K_IB of the H1 matrix on omega_i^+ (Lemma 4.1)."""
+    K_II, K_IB, K_BI, K_BB = blocks(lm.K_plus, lm.nI)
+    lu = spla.splu(K_II)
+    Y = lu.solve(K_IB.toarray())
+    S = K_BB.toarray() - K_BI @ Y
+    return 0.5 * (S + S.T)
+
+
+def truncation_rank(sigma: np.ndarray, rank: int | None, tol: float | None, gap: float = CLUSTER_GAP) -> int:
+    """Number of leading singular triplets kept.
+
+    rank > 0: the top-`rank`, widened to the end of a cluster of (numerically)
+    equal singular values so that the kept subspace is well defined: the smallest
+    k' >= rank with (s_k' - s_{k'+1}) / s_k' > gap.  Otherwise keep s > tol
+    (eq. 4.5), widened the same way.
+    """
+    M = sigma.size
+    if rank is not None and rank > 0:
+        k = min(rank, M)
+    else:
+        if tol is None:
+            raise ValueError("need rank > 0 or a tolerance")
+        k = int(np.count_nonzero(sigma > tol))
+    if k == 0:
+        return 0
+    while k < M:
+        if sigma[k - 1] <= 0.0 or (sigma[k - 1] - sigma[k]) / sigma[k - 1] > gap:
+            break
+        k += 1
+    return k
+
+
+def reduce_local(mesh, kappa, f_nodal, sets: decomp.LocalSets, rank: int | None, tol: float | None = None,
+                 keep: bool = False):
+    lm = local_matrices(mesh, kappa, f_nodal, sets)
+    M = lm.nB
+    X = lifting(lm)
+    Z = X[lm.C_idx, :M]                     # lifting matrix on V
+    q0 = X[lm.C_idx, M]
+    S_B = schur_H1(lm)
+    R_BB = la.cholesky(S_B, lower=False)    # S_B = R_BB^T R_BB
+    R_i = la.cholesky(lm.K_i.toarray(), lower=False)
+    # R_i Z R_BB^{-1}:  (Z R_BB^{-1})^T = R_BB^{-T} Z^T
+    ZRinv = la.solve_triangular(R_BB, Z.T, trans="T", lower=False).T
+    Bw = R_i @ ZRinv
+    U, s, _ = la.svd(Bw, full_matrices=False)
+    k = truncation_rank(s, rank, tol)
+    Phi = la.solve_triangular(R_i, U[:, :k], lower=False)
+    Vfull = np.hstack([q0[:, None], Phi])
+    Vloc = Vfull[lm.D_idx]
+    # A restricted to P: P lies in I and every star of a P node lies in omega_i^+
+    P_in_I = lm.C_idx[lm.D_idx]
+    A_PP = lm.A_plus[P_in_I][:, P_in_I]
+    Aii = Vloc.T @ (A_PP @ Vloc)
+    Aii = 0.5 * (Aii + Aii.T)
+    bi = Vloc.T @ lm.f_plus[P_in_I]
+    res = LocalResult(sets=sets, sigma=s, k_eff=k, q0=q0, Phi=Phi, Vloc=Vloc, Aii=Aii, bi=bi)
+    if keep:
+        return res, dict(lm=lm, X=X, Z=Z, S_B=S_B, R_BB=R_BB, R_i=R_i, Bw=Bw, U=U)
+    return res
+
+
+# ----------------------------------------------------------------------------------
+# whole-problem driver (serial, or a process pool over subdomains)
+
+_G = {}
+
+
+def _work(i):
+    p, sets, rank, tol = _G["p"], _G["sets"], _G["rank"], _G["tol"]
+    r = p.ranks[i] if (p.ranks is not None and rank is None) else rank
+    return reduce_local(p.mesh, p.kappa, p.f_nodal, sets[i], int(r) if r is not None else None, tol)
+
+
+def reduce_all(problem, rank: int | None = None, tol: float | None = None, workers: int = 1,
+               subset=None) -> list[LocalResult]:
+    sets = decomp.all_local_sets(problem.mesh, problem.subdomains)
+    if rank is None and tol is None and problem.ranks is None:
+        rank = problem.rank
+    idx = list(range(problem.subdomains.n_sub)) if subset is None else list(subset)
+    _G.update(p=problem, sets=sets, rank=rank, tol=tol)
+    if workers <= 1:
+        return [_work(i) for i in idx]
+    import multiprocessing as mp
+    ctx = mp.get_context("fork")
+    with ctx.Pool(workers) as pool:
+        return pool.map(_work, idx, chunksize=1)

@@ -1,0 +1,83 @@
+"""Pins of the oracle's global part (Sections 3, 5, 6 and 7.1) against exact statements.
+
+  partition of unity    every free node lies in exactly one P_i; sum_i S_i(v|omega_i) = v
+  full rank             with every lifting mode kept, u~ equals the FE solution (Section 3)
+  nested spaces         the energy error does not increase with the rank
+  projection            the memory-efficient Q^T A Q equals the directly formed product
+  Galerkin identity     ||u - u~||_A^2 = u^T b - x^T Q^T b (Section 7.1)
+"""
+import numpy as np
+import pytest
+
+import workloads as w
+from oracle import decomp, project, reduce, solve
+
+
+def test_partition_of_unity_and_ownership():
+    for p in (w.make_config("C1"), w.make_problem(12, (3, 2, 1), r=2)):
+        sets = decomp.all_local_sets(p.mesh, p.subdomains)
+        owner = decomp.owner_map(p.mesh, sets)
+        v = np.random.default_rng(0).standard_normal(p.mesh.n_nodes) * (p.mesh.dirichlet == 0)
+        acc = np.zeros_like(v)
+        for s in sets:
+            acc[s.P] += v[s.P]          # S_i(v|omega_i): keep the interior of omega_i, zero elsewhere
+        np.testing.assert_array_equal(acc, v)
+        assert np.all(owner[p.mesh.dirichlet == 0] >= 0)
+        for s in sets:
+            assert np.all(np.isin(s.P, s.V)) and np.all(np.isin(s.V, s.I))
+
+
+def test_single_layer_overlap():
+    """Two cores share either nothing or one element layer (Section 3)."""
+    p = w.make_problem(12, (3, 3, 2), r=2)
+    sd = p.subdomains
+    for i in range(sd.n_sub):
+        (ci, _) = sd.boxes[i]
+        for j in range(i + 1, sd.n_sub):
+            (cj, _) = sd.boxes[j]
+            widths = [min(a[1], b[1]) - max(a[0], b[0]) for a, b in zip(ci, cj)]
+            if min(widths) > 0:
+                assert sorted(widths)[0] == 1
+
+
+def test_full_rank_reproduces_fe_solution():
+    p = w.make_problem(8, (2, 2, 2), r=1, rank=10 ** 6, kappa="lognormal", seed=9)
+    out = solve.run(p, rank=10 ** 6, pinv_rtol=1e-13)
+    assert all(r.k_eff == r.sets.B.size for r in out["results"])
+    rel = out["red_err"] / out["u_energy"]
+    assert rel < 1e-9, rel
+    np.testing.assert_allclose(out["u_tilde"], out["u_fe"], atol=1e-9 * np.abs(out["u_fe"]).max())
+
+
+def test_error_monotone_in_rank():
+    p = w.make_problem(12, (2, 2, 2), r=2, kappa="lognormal", seed=4)
+    errs = []
+    for k in (1, 2, 4, 8, 16, 32):
+        out = solve.run(p, rank=k)
+        errs.append(out["red_err"])
+    assert all(e2 <= e1 * (1 + 1e-10) for e1, e2 in zip(errs, errs[1:])), errs
+    assert errs[-1] < 0.05 * errs[0]
+
+
+@pytest.mark.parametrize("cfg", ["C1", "lognormal-uneven"])
+def test_memory_efficient_projection_equals_dense(cfg):
+    if cfg == "C1":
+        p = w.make_config("C1")
+    else:
+        rng = np.random.default_rng(3)
+        cuts = tuple(w.cuts_random(12, k, 3, rng) for k in (3, 2, 2))
+        p = w.make_problem(12, cuts=cuts, r=2, rank=5, kappa="lognormal", seed=2)
+    res = reduce.reduce_all(p, workers=1)
+    At, bt, off = project.reduced_system(p.mesh, p.kappa, p.subdomains, res)
+    D, _ = project.dense_QtAQ(p.mesh, p.kappa, res)
+    np.testing.assert_allclose(At, D, atol=1e-12 * np.abs(D).max())
+    np.linalg.cholesky(At)                       # SPD when Q has full column rank
+
+
+def test_galerkin_error_identity():
+    p = w.make_problem(12, (2, 2, 2), r=2, rank=4, kappa="lognormal", seed=8, load="poly")
+    out = solve.run(p)
+    u = out["u_fe"][out["free"]]
+    lhs = out["red_err"] ** 2
+    rhs = u @ out["b"] - out["x"] @ out["bt"]
+    assert abs(lhs - rhs) < 1e-10 * (u @ out["b"])

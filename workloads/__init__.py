@@ -1,0 +1,323 @@
+"""Seeded synthetic inputs: meshes, coefficients, box decompositions, request streams.
+
+This module holds no arithmetic of the reduction method.  It only produces the
+*inputs* that the problem statement of the paper (Section 6, first paragraph)
+names: a tetrahedral mesh, a coefficient field, a load, and an overlapping
+decomposition into subdomains omega_i with their extensions omega_i^+
+(Section 3).  Both the FP64 CPU oracle and the HIP library consume these
+arrays; neither side imports the other.
+
+Workloads follow the paper's scaling tests (Section 7.1): the unit cube meshed
+with evenly spaced tetrahedra and Dirichlet data on the whole boundary, split
+into box subdomains with a few thousand degrees of freedom each and an
+extension that roughly doubles the subdomain diameter.
+
+Mesh: the unit cube cut into n^3 hexahedral cells, each split into the 6 Kuhn
+tetrahedra {v, v+e_a, v+e_a+e_b, v+(1,1,1)} over the 6 axis orders (a,b,c).
+Node (i,j,k) has id i + (n+1)*(j + (n+1)*k); cell (i,j,k) has id
+i + n*(j + n*k) and owns tets 6*cell .. 6*cell+5.  Every tet is stored with
+positive orientation.
+
+Decomposition (boxes): per-axis cuts 0 = c_0 < ... < c_p = n.  Box (a,b,c)
+has core cells [c_a, min(c_{a+1}+1, n)) per axis (one cell of overlap on the
++ side, so two neighbouring cores share exactly one element layer, Section 3)
+and extension cells [max(c_a - r, 0), min(c_{a+1}+1+r, n)) (the extension by
+r cell layers, the box analogue of the paper's r-hop extension).
+"""
+from __future__ import annotations
+
+import itertools
+from dataclasses import dataclass, field
+
+import numpy as np
+
+# The 6 axis orders; the tet for order (a,b,c) is v, v+e_a, v+e_a+e_b, v+1.
+_KUHN_ORDERS = list(itertools.permutations(range(3)))
+
+
+@dataclass
+class Mesh:
+    n: int                      # cells per axis
+    xyz: np.ndarray             # (n_nodes, 3) float64
+    tets: np.ndarray            # (n_tets, 4) int32, positively oriented
+    dirichlet: np.ndarray       # (n_nodes,) uint8, 1 on the boundary of the cube
+
+    @property
+    def n_nodes(self) -> int:
+        return self.xyz.shape[0]
+
+    @property
+    def n_tets(self) -> int:
+        return self.tets.shape[0]
+
+
+@dataclass
+class Subdomains:
+    """Overlapping decomposition as tet lists (CSR over subdomains)."""
+    ext_tet_ptr: np.ndarray     # (n_sub+1,) int64
+    ext_tets: np.ndarray        # (nnz,) int32: tets of omega_i^+
+    in_core: np.ndarray         # (nnz,) uint8: 1 if the tet also lies in omega_i
+    boxes: list = field(default_factory=list)  # per subdomain ((lo,hi) core, (lo,hi) ext) cell ranges per axis
+
+    @property
+    def n_sub(self) -> int:
+        return self.ext_tet_ptr.shape[0] - 1
+
+    def ext(self, i: int) -> np.ndarray:
+        return self.ext_tets[self.ext_tet_ptr[i]:self.ext_tet_ptr[i + 1]]
+
+    def core(self, i: int) -> np.ndarray:
+        s = slice(self.ext_tet_ptr[i], self.ext_tet_ptr[i + 1])
+        return self.ext_tets[s][self.in_core[s] != 0]
+
+
+@dataclass
+class Problem:
+    name: str
+    mesh: Mesh
+    kappa: np.ndarray           # (n_tets,) float64, piecewise constant per cell
+    f_nodal: np.ndarray | None  # (n_nodes,) float64 nodal load values, None => f = 1
+    subdomains: Subdomains
+    rank: int                   # number of lifting modes kept per subdomain (plus q0)
+    ranks: np.ndarray | None = None   # per-subdomain ranks (serving stream)
+    precision: str = "fp64"
+    meta: dict = field(default_factory=dict)
+
+
+def kuhn_cube(n: int, jitter: float = 0.0, seed: int | None = None) -> Mesh:
+    """Kuhn-tetrahedral mesh of [0,1]^3 with n cells per axis.
+
+    jitter > 0 moves every interior coordinate (0 < index < n along that axis)
+    by U(-jitter*h, +jitter*h), so the domain stays the unit cube.
+    """
+    n1 = n + 1
+    h = 1.0 / n
+    idx = np.arange(n1)
+    k3, j3, i3 = np.meshgrid(idx, idx, idx, indexing="ij")
+    ijk = np.stack([i3.ravel(), j3.ravel(), k3.ravel()], axis=1)  # node id order
+    xyz = ijk.astype(np.float64) * h
+    if jitter > 0.0:
+        rng = np.random.default_rng(seed)
+        d = rng.uniform(-jitter * h, jitter * h, size=xyz.shape)
+        interior = (ijk > 0) & (ijk < n)
+        xyz = xyz + np.where(interior, d, 0.0)
+    dirichlet = np.any((ijk == 0) | (ijk == n), axis=1).astype(np.uint8)
+
+    c = np.arange(n)
+    ck, cj, ci = np.meshgrid(c, c, c, indexing="ij")
+    base = np.stack([ci.ravel(), cj.ravel(), ck.ravel()], axis=1)  # cell id order
+    tets = np.empty((n ** 3, 6, 4), dtype=np.int64)
+
+    def nid(p):
+        return p[:, 0] + n1 * (p[:, 1] + n1 * p[:, 2])
+
+    eye = np.eye(3, dtype=np.int64)
+    for t, (a, b, _) in enumerate(_KUHN_ORDERS):
+        v0 = base
+        v1 = base + eye[a]
+        v2 = v1 + eye[b]
+        v3 = base + 1
+        tets[:, t, :] = np.stack([nid(v0), nid(v1), nid(v2), nid(v3)], axis=1)
+    tets = tets.reshape(-1, 4)
+    # orient positively: swap two vertices where the signed volume is negative
+    e = xyz[tets[:, 1:]] - xyz[tets[:, :1]]
+    det = np.einsum("ti,ti->t", e[:, 0], np.cross(e[:, 1], e[:, 2]))
+    neg = det < 0
+    tets[neg, 1], tets[neg, 2] = tets[neg, 2].copy(), tets[neg, 1].copy()
+    e = xyz[tets[:, 1:]] - xyz[tets[:, :1]]
+    det = np.einsum("ti,ti->t", e[:, 0], np.cross(e[:, 1], e[:, 2]))
+    if not np.all(det > 0):
+        raise ValueError("mesh generation produced a degenerate or inverted tet")
+    return Mesh(n=n, xyz=xyz, tets=tets.astype(np.int32), dirichlet=dirichlet)
+
+
+# ----------------------------------------------------------------------------------
+# coefficient fields (per cell, replicated to the 6 tets of the cell)
+
+def kappa_constant(mesh: Mesh, value: float = 1.0) -> np.ndarray:
+    return np.full(mesh.n_tets, value, dtype=np.float64)
+
+
+def kappa_lognormal(mesh: Mesh, sigma: float, seed: int) -> np.ndarray:
+    """kappa = exp(sigma * g), g ~ N(0,1) i.i.d. per cell."""
+    rng = np.random.default_rng(seed)
+    g = rng.standard_normal(mesh.n ** 3)
+    return np.repeat(np.exp(sigma * g), 6)
+
+
+def kappa_inclusions(mesh: Mesh, seed: int, n_spheres: int = 20, high: float = 1e4,
+                     rmin: float = 0.05, rmax: float = 0.15) -> np.ndarray:
+    """kappa = 1 with kappa = high in cells whose centroid lies in any sphere."""
+    rng = np.random.default_rng(seed)
+    centres = rng.uniform(0.0, 1.0, size=(n_spheres, 3))
+    radii = rng.uniform(rmin, rmax, size=n_spheres)
+    n = mesh.n
+    c = (np.arange(n) + 0.5) / n
+    ck, cj, ci = np.meshgrid(c, c, c, indexing="ij")
+    cen = np.stack([ci.ravel(), cj.ravel(), ck.ravel()], axis=1)
+    inside = np.zeros(n ** 3, dtype=bool)
+    for s in range(n_spheres):
+        inside |= np.sum((cen - centres[s]) ** 2, axis=1) < radii[s] ** 2
+    return np.repeat(np.where(inside, high, 1.0), 6)
+
+
+def load_polynomial(mesh: Mesh) -> np.ndarray:
+    """Nodal values of the scaling-test load of Section 7.1,
+    f = 2*sqrt(900)*((1-x)x(1-y)y + (1-x)x(1-z)z + (1-y)y(1-z)z)."""
+    x, y, z = mesh.xyz.T
+    gx, gy, gz = (1 - x) * x, (1 - y) * y, (1 - z) * z
+    return 2.0 * 30.0 * (gx * gy + gx * gz + gy * gz)
+
+
+def load_sine(mesh: Mesh) -> np.ndarray:
+    """Nodal values of f = 3 pi^2 sin(pi x) sin(pi y) sin(pi z)."""
+    x, y, z = mesh.xyz.T
+    return 3.0 * np.pi ** 2 * np.sin(np.pi * x) * np.sin(np.pi * y) * np.sin(np.pi * z)
+
+
+# ----------------------------------------------------------------------------------
+# box decompositions
+
+def cuts_equal(n: int, parts: int) -> np.ndarray:
+    if n % parts:
+        raise ValueError("equal cuts need parts | n")
+    return np.arange(parts + 1, dtype=np.int64) * (n // parts)
+
+
+def cuts_random(n: int, parts: int, min_width: int, rng: np.random.Generator) -> np.ndarray:
+    """Seeded uneven cuts: widths = min_width + multinomial share of the rest."""
+    rest = n - parts * min_width
+    if rest < 0:
+        raise ValueError("too many parts for the minimum width")
+    w = min_width + rng.multinomial(rest, [1.0 / parts] * parts)
+    return np.concatenate([[0], np.cumsum(w)]).astype(np.int64)
+
+
+def cuts_uniform_widths(n: int, wmin: int, wmax: int, rng: np.random.Generator) -> np.ndarray:
+    """Widths drawn from U{wmin..wmax} until n is closed (all widths stay in range)."""
+    widths = []
+    remaining = n
+    while remaining > 0:
+        if remaining <= wmax:
+            w = remaining
+        else:
+            w = int(rng.integers(wmin, wmax + 1))
+            if remaining - w < wmin:
+                w = remaining - wmin
+        widths.append(w)
+        remaining -= w
+    return np.concatenate([[0], np.cumsum(widths)]).astype(np.int64)
+
+
+def box_subdomains(n: int, cuts: tuple, r: int) -> Subdomains:
+    """Boxes with one-cell overlap on the + side and extension by r cell layers."""
+    ptr = [0]
+    ext_all = []
+    core_all = []
+    boxes = []
+    tet6 = np.arange(6, dtype=np.int64)
+    for kc in range(len(cuts[2]) - 1):
+        for jc in range(len(cuts[1]) - 1):
+            for ic in range(len(cuts[0]) - 1):
+                core = []
+                ext = []
+                for ax, a in zip(range(3), (ic, jc, kc)):
+                    c = cuts[ax]
+                    lo, hi = int(c[a]), int(min(c[a + 1] + 1, n))
+                    core.append((lo, hi))
+                    ext.append((max(lo - r, 0), min(hi + r, n)))
+                ranges = [np.arange(lo, hi) for lo, hi in ext]
+                kk, jj, ii = np.meshgrid(ranges[2], ranges[1], ranges[0], indexing="ij")
+                ci, cj, ck = ii.ravel(), jj.ravel(), kk.ravel()
+                cell = ci + n * (cj + n * ck)
+                incore = ((ci >= core[0][0]) & (ci < core[0][1]) &
+                          (cj >= core[1][0]) & (cj < core[1][1]) &
+                          (ck >= core[2][0]) & (ck < core[2][1]))
+                t = (6 * cell[:, None] + tet6[None, :]).ravel()
+                ext_all.append(t.astype(np.int32))
+                core_all.append(np.repeat(incore, 6).astype(np.uint8))
+                ptr.append(ptr[-1] + t.size)
+                boxes.append((tuple(core), tuple(ext)))
+    return Subdomains(ext_tet_ptr=np.asarray(ptr, dtype=np.int64),
+                      ext_tets=np.concatenate(ext_all),
+                      in_core=np.concatenate(core_all),
+                      boxes=boxes)
+
+
+# ----------------------------------------------------------------------------------
+# named workloads
+
+def make_problem(n: int, parts=(2, 2, 2), r: int = 1, rank: int = 8, kappa: str = "one",
+                 kappa_sigma: float = 1.0, seed: int = 0, jitter: float = 0.0,
+                 load: str = "one", cuts=None, precision: str = "fp64", name: str = "custom") -> Problem:
+    mesh = kuhn_cube(n, jitter=jitter, seed=seed + 2 if jitter > 0 else None)
+    if kappa == "one":
+        kap = kappa_constant(mesh)
+    elif kappa == "lognormal":
+        kap = kappa_lognormal(mesh, kappa_sigma, seed)
+    elif kappa == "inclusions":
+        kap = kappa_inclusions(mesh, seed)
+    else:
+        raise ValueError(kappa)
+    if load == "one":
+        f = None
+    elif load == "poly":
+        f = load_polynomial(mesh)
+    elif load == "sine":
+        f = load_sine(mesh)
+    else:
+        raise ValueError(load)
+    if cuts is None:
+        cuts = tuple(cuts_equal(n, p) for p in parts)
+    sd = box_subdomains(n, cuts, r)
+    return Problem(name=name, mesh=mesh, kappa=kap, f_nodal=f, subdomains=sd, rank=rank,
+                   precision=precision, meta=dict(n=n, r=r, cuts=[c.tolist() for c in cuts]))
+
+
+CONFIG_NAMES = ("C1", "C2", "C3", "C4", "C5")
+
+
+def make_config(name: str) -> Problem:
+    """The five named workloads.
+
+    C1  16^3 cells, kappa = 1, f = 1, 2x2x2 equal boxes, r = 1, k = 8, plain FP64.
+    C2  48^3, kappa = exp(N(0,1)) per cell (seed 1), 4x4x4 boxes, r = 6, k = 16,
+        FP32 block CG with FP64 refinement.
+    C3  64^3 with node jitter U(+-0.2h) (seed 2), 6x5x4 boxes at seeded random cuts
+        (seed 3, min width 4), r = 6, k = 24, FP32.
+    C4  96^3, kappa = exp(2 N(0,1)) (seed 4), 8^3 boxes, r = 6, k = 32, BF16 Gram.
+    C5  128^3, kappa = 1 with 20 spheres of kappa = 1e4 (seed 5), boxes with widths
+        U{10..40} per axis (seed 6), r = 6, ranks U{8..48} per request (seed 8).
+    """
+    if name == "C1":
+        return make_problem(16, (2, 2, 2), r=1, rank=8, name="C1", precision="fp64")
+    if name == "C2":
+        p = make_problem(48, (4, 4, 4), r=6, rank=16, kappa="lognormal", kappa_sigma=1.0, seed=1,
+                         name="C2", precision="fp32_refine")
+        return p
+    if name == "C3":
+        rng = np.random.default_rng(3)
+        cuts = tuple(cuts_random(64, p, 4, rng) for p in (6, 5, 4))
+        mesh = kuhn_cube(64, jitter=0.2, seed=2)
+        sd = box_subdomains(64, cuts, 6)
+        return Problem(name="C3", mesh=mesh, kappa=kappa_constant(mesh), f_nodal=None, subdomains=sd,
+                       rank=24, precision="fp32", meta=dict(n=64, r=6, cuts=[c.tolist() for c in cuts]))
+    if name == "C4":
+        return make_problem(96, (8, 8, 8), r=6, rank=32, kappa="lognormal", kappa_sigma=2.0, seed=4,
+                            name="C4", precision="bf16_split")
+    if name == "C5":
+        mesh = kuhn_cube(128)
+        kap = kappa_inclusions(mesh, seed=5)
+        rng = np.random.default_rng(6)
+        cuts = tuple(cuts_uniform_widths(128, 10, 40, rng) for _ in range(3))
+        sd = box_subdomains(128, cuts, 6)
+        ranks = np.random.default_rng(8).integers(8, 49, size=sd.n_sub)
+        return Problem(name="C5", mesh=mesh, kappa=kap, f_nodal=None, subdomains=sd, rank=int(ranks.max()),
+                       ranks=ranks, precision="mixed", meta=dict(n=128, r=6, cuts=[c.tolist() for c in cuts]))
+    raise ValueError(name)
+
+
+def poisson_arrivals(n_requests: int, rate: float, seed: int = 7) -> np.ndarray:
+    """Arrival times (seconds) of a Poisson stream with the given rate."""
+    rng = np.random.default_rng(seed)
+    return np.cumsum(rng.exponential(1.0 / rate, size=n_requests))
