@@ -1,0 +1,198 @@
+/*
+ * mor.h -- C-ABI of the MI355X library for the localized model-order-reduction
+ * finite element method (Gustafsson, Hannukainen, Kohonen: "Distributed finite
+ * element solution using model order reduction").
+ *
+ * The calls follow the paper's problem statement (Section 6, first paragraph):
+ * given a tetrahedral mesh, a decomposition into overlapping subdomains omega_i
+ * with extensions omega_i^+, and a truncation rule (rank or tolerance), compute
+ * the reduced solution of Problem 2.3.  The three steps of Section 6 map to
+ *   mor_create         step 1 outputs consumed: submeshes and neighbour relations
+ *   mor_local_basis*   step 2: optimal local bases, Q_i^T A_ii Q_i and Q_i^T f_i
+ *   mor_project        step 3: memory-efficient Q^T A Q over neighbour pairs
+ *   mor_solve          step 3: reduced solve and u~ = Q x
+ *
+ * Conventions for every entry point
+ *   - Return 0 on success or a negative MOR_E* code; mor_last_error() then holds
+ *     a message (per thread).  No C++ exception crosses this boundary.
+ *   - Pointers documented "host" are caller-owned, read (or written) only during
+ *     the call; the library copies what it keeps.  Device memory is owned by the
+ *     context and released by mor_destroy.
+ *   - Integer arrays are little-endian int32/int64 as typed; floating point is
+ *     IEEE binary64 at the boundary.
+ *   - One context is used by one host thread at a time; all device work runs in
+ *     order on the stream given in mor_opts (0 = the null stream).
+ */
+#ifndef MOR_H
+#define MOR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MOR_OK 0
+#define MOR_EINVAL (-1)   /* bad argument, invalid mesh (det J <= 0), not a partition, bad rank/tol */
+#define MOR_ENOMEM (-2)   /* device allocation failed or a subdomain exceeds the HBM budget */
+#define MOR_ENOTCONV (-3) /* block CG or the eigensolver did not converge within its limits */
+#define MOR_ESTATE (-4)   /* call order: e.g. mor_project before every subdomain has a basis */
+#define MOR_EDEVICE (-5)  /* HIP runtime error or a failed device-side check (non-SPD pivot) */
+
+/* Arithmetic of the local reduction. */
+#define MOR_FP64 0        /* FP64 block CG, FP64 everywhere (the plain comparator path) */
+#define MOR_FP32_REFINE 1 /* FP32 block CG + FP64 residual refinement; FP64 Gram and eigen */
+#define MOR_FP32 2        /* FP32 block CG; FP64 Gram and eigen on the FP32 solution */
+#define MOR_BF16_SPLIT 3  /* FP32 block CG; Gram contraction in BF16 MFMA hi/lo split, FP32 accumulate */
+
+typedef struct mor_ctx mor_ctx;
+
+/* Tetrahedral mesh (Section 2): P1 space on the tets, zero Dirichlet data at
+ * nodes flagged in `dirichlet`.  xyz: n_nodes*3 (x,y,z per node), host.
+ * tets: n_tets*4 node ids, host; every tet must have positive volume. */
+typedef struct {
+  int64_t n_nodes;
+  int64_t n_tets;
+  const double* xyz;
+  const int32_t* tets;
+  const uint8_t* dirichlet;
+} mor_mesh;
+
+/* Coefficient kappa per tet (the a(x) of Section 7.2, piecewise constant) and
+ * nodal load values (the load vector is M * f_h, consistent mass times the P1
+ * interpolant).  f_nodal == NULL means f = 1.  Host arrays. */
+typedef struct {
+  const double* kappa;   /* n_tets */
+  const double* f_nodal; /* n_nodes or NULL */
+} mor_coeff;
+
+/* Overlapping decomposition (Section 3) as tet lists: subdomain i owns
+ * ext_tets[ext_tet_ptr[i] .. ext_tet_ptr[i+1]) = the tets of omega_i^+, and
+ * in_core[] flags the ones that also lie in omega_i.  Cores must overlap in
+ * single element layers so that the interiors of the omega_i partition the
+ * free nodes (checked: MOR_EINVAL otherwise), and omega_i must lie inside the
+ * interior of omega_i^+ (extension r >= 1).  Host arrays. */
+typedef struct {
+  int32_t n_sub;
+  const int64_t* ext_tet_ptr; /* n_sub + 1 */
+  const int32_t* ext_tets;    /* ext_tet_ptr[n_sub] */
+  const uint8_t* in_core;     /* ext_tet_ptr[n_sub] */
+} mor_subdomains;
+
+/* Device allocation callback: return a device pointer of at least `bytes`
+ * (256-byte aligned) or NULL; `user` is alloc_user. */
+typedef void* (*mor_alloc_fn)(size_t bytes, void* user);
+typedef void (*mor_free_fn)(void* ptr, void* user);
+
+typedef struct {
+  int32_t precision;       /* MOR_FP64 | MOR_FP32_REFINE | MOR_FP32 | MOR_BF16_SPLIT */
+  double cg_rtol;          /* inner CG stop: sqrt(r'D^-1 r / r0'D^-1 r0) <= cg_rtol per column */
+  double refine_rtol;      /* FP32_REFINE: stop refinement when the FP64 residual reaches this */
+  int32_t max_iter;        /* CG iteration cap per solve (MOR_ENOTCONV beyond it) */
+  int32_t refine_steps;    /* FP32_REFINE: maximum number of FP64 residual corrections */
+  int32_t oversample;      /* extra subspace vectors of the top-k eigensolve (0 = automatic) */
+  double eig_rtol;         /* Ritz residual tolerance relative to the largest eigenvalue */
+  int32_t eig_max_iter;    /* subspace iteration cap */
+  int32_t cg_chunk;        /* CG iterations launched between two convergence polls */
+  int32_t spmm_rows;       /* rows per SpMM workgroup tile (0 = automatic) */
+  int32_t use_graph;       /* capture each CG chunk in a HIP graph and replay it */
+  size_t hbm_budget_bytes; /* device bytes one batch of local reductions may use (0 = 75% free) */
+  mor_alloc_fn dev_alloc;  /* NULL: hipMalloc */
+  mor_free_fn dev_free;    /* NULL: hipFree */
+  void* alloc_user;
+  void* hip_stream;        /* hipStream_t all work is ordered on; NULL = null stream */
+  int32_t host_only;       /* 1: derive the decomposition on the host only (no device memory);
+                              only mor_get_sizes / mor_get_nodes / mor_get_pairs may follow */
+} mor_opts;
+
+/* Fill `opts` with defaults (FP32_REFINE, cg_rtol 1e-5, refine_rtol 1e-10, ...). */
+void mor_default_opts(mor_opts* opts);
+
+/* Validate the inputs, derive the index sets I, B, V_i, P_i (Sections 3-4),
+ * the neighbour pairs and omega_0 (Section 6, step 3), colour the elements, and
+ * upload geometry and patterns.  *out receives the context. */
+int mor_create(const mor_mesh* mesh, const mor_coeff* coeff, const mor_subdomains* sub,
+               const mor_opts* opts, mor_ctx** out);
+
+/* Local reduction of subdomain `sd` (Section 6, step 2; Sections 3-4): assemble
+ * A_i^+ and the H1 matrices, lift the load and every interface hat function
+ * (block CG on A_II), form the trace-norm weight (Schur complement of the H1
+ * matrix, Lemmas 4.1-4.2) and the H1(omega_i) Gram matrix of the liftings, keep
+ * the leading weighted singular modes (eq. 4.4-4.5), stitch (Definition 3.1),
+ * and project A_ii and f_i.  rank > 0 keeps the top `rank` modes (widened over
+ * a cluster of equal singular values); rank <= 0 keeps sigma > tol.  k_eff_out
+ * (may be NULL) receives the number of lifting modes kept; sigma_out (may be
+ * NULL, capacity sigma_cap) the leading computed singular values. */
+int mor_local_basis(mor_ctx* ctx, int32_t sd, int32_t rank, double tol, int32_t* k_eff_out,
+                    double* sigma_out, int32_t sigma_cap);
+
+/* The same for `n` subdomains at once, batched on the device (all of them in one
+ * set of launches, in waves bounded by hbm_budget_bytes).  sds: n ids, host.
+ * ranks / tols: n values each, host (tols may be NULL).  k_eff_out: n, host, may
+ * be NULL. */
+int mor_local_basis_batch(mor_ctx* ctx, int32_t n, const int32_t* sds, const int32_t* ranks,
+                          const double* tols, int32_t* k_eff_out);
+
+/* Galerkin projection Q^T A Q of the global system (eq. 6.1) without forming A
+ * or Q: diagonal blocks from the local step, off-diagonal blocks from A_0
+ * assembled on omega_0 and the interface rows of neighbouring bases.  Needs
+ * every subdomain reduced (MOR_ESTATE otherwise). */
+int mor_project(mor_ctx* ctx);
+
+/* Solve the reduced system (FP64 Cholesky) and write u~ = sum_i S_i Q_i x_i at
+ * every mesh node into u_out (n_nodes doubles, host; zero at Dirichlet nodes).
+ * n_reduced_out (may be NULL) receives dim of the reduced space. */
+int mor_solve(mor_ctx* ctx, double* u_out, int64_t* n_reduced_out);
+
+/* ---- serving: continuous batching of local-reduction requests ---------------
+ * mor_submit queues a request for subdomain `sd`; it is admitted when device
+ * memory within hbm_budget_bytes is free, joins the running block-CG launches at
+ * the next chunk boundary, and completes independently of the others.
+ * mor_poll drives the device loop one chunk and reports a request's state;
+ * done = 1 when finished, status = its result code. */
+int mor_submit(mor_ctx* ctx, int32_t sd, int32_t rank, double tol, int32_t precision, uint64_t* ticket);
+int mor_poll(mor_ctx* ctx, uint64_t ticket, int32_t* done, int32_t* status);
+/* Drive the serving loop until every submitted request has finished. */
+int mor_drain(mor_ctx* ctx);
+
+/* ---- results and diagnostics (host copies) ---------------------------------- */
+
+/* Sizes of the index sets of subdomain sd: |P_i|, |V_i|, |I|, |B|. */
+int mor_get_sizes(mor_ctx* ctx, int32_t sd, int32_t* nP, int32_t* nV, int32_t* nI, int32_t* nB);
+/* Global node ids of the local ordering [P | V\P | I\V | B] (nI + nB ints). */
+int mor_get_nodes(mor_ctx* ctx, int32_t sd, int32_t* out, int64_t cap);
+/* Neighbour pairs (i < j) coupled through A_0 on omega_0: pairs_out receives 2 ints per pair
+ * (up to cap pairs); n_pairs the total count.  Works in host_only mode. */
+int mor_get_pairs(mor_ctx* ctx, int32_t* pairs_out, int64_t cap, int64_t* n_pairs);
+/* Basis on V_i: (nV x (k_eff+1)) row-major doubles, column 0 = q_0, then the
+ * H1(omega_i)-orthonormal lifting modes; the stitched basis is its first nP rows. */
+int mor_get_basis(mor_ctx* ctx, int32_t sd, double* out, int64_t cap, int32_t* k_eff);
+/* Leading singular values of the weighted lifting operator (up to cap). */
+int mor_get_sigma(mor_ctx* ctx, int32_t sd, double* out, int32_t cap, int32_t* n);
+/* Q_i^T A_ii Q_i ((k+1)^2, row-major) and Q_i^T f_i (k+1). */
+int mor_get_local_block(mor_ctx* ctx, int32_t sd, double* Aii, double* bi, int64_t cap);
+/* After mor_project: the dense reduced matrix (n x n) and load (n). */
+int mor_get_reduced(mor_ctx* ctx, double* At, double* bt, int64_t cap, int64_t* n);
+/* After mor_solve: the reduced coefficient vector x (n). */
+int mor_get_reduced_solution(mor_ctx* ctx, double* x, int64_t cap);
+/* Per-solve statistics of the last local reduction of sd: CG iterations of the
+ * A- and H1-systems, refinement passes, subspace iterations. */
+int mor_get_stats(mor_ctx* ctx, int32_t sd, int32_t* cg_iter_a, int32_t* cg_iter_k, int32_t* refine,
+                  int32_t* eig_iter);
+
+/* Per-kernel device timing with HIP events on the library's stream.
+ * name: "spmm" (the block-CG sparse product), "cg_update", "cg_direction",
+ * "gram", "schur", "potrf", "trsm", "eig", "assemble", "project", "solve".
+ * Reports launches, total milliseconds and algorithmic bytes (spmm) or flops. */
+int mor_timing_enable(mor_ctx* ctx, int32_t on);
+int mor_timing_get(mor_ctx* ctx, const char* name, int64_t* launches, double* total_ms, double* work);
+int mor_timing_reset(mor_ctx* ctx);
+
+void mor_destroy(mor_ctx* ctx);
+const char* mor_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MOR_H */

@@ -1,0 +1,1450 @@
+// C-ABI and device orchestration of the localized model-order-reduction hot path.
+//
+// mor_create            Section 6 step 1 inputs -> index sets, patterns, colouring (host C++)
+// mor_local_basis_batch Section 6 step 2 for a batch of subdomains, on the device:
+//   assembly (Section 2, Section 4 H1 matrices) -> block CG lifting (Problems 3.2-3.3) with
+//   FP64 refinement -> G1 = Z^T K_i Z and S_B = Schur(H1, B) (Lemmas 4.1-4.2) -> R = chol(S_B),
+//   C = R^-T G1 R^-1 -> top singular triplets of R_i Z R^-1 (eq. 4.4) through the eigenpairs of C
+//   -> basis Z R^-1 v_j / sigma_j = R_i^-1 u_j, stitched to P_i (Definition 3.1) -> Q_i^T A_ii Q_i
+// mor_project           eq. 6.1 block by block with A_0 on omega_0 (Section 6 step 3)
+// mor_solve             reduced Cholesky solve, u~ = sum_i S_i Q_i x_i
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/mor.h"
+#include "mor_host.h"
+#include "mor_internal.h"
+
+using namespace mor;
+
+static thread_local std::string g_err;
+
+static int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+#define HIPCHK(expr)                                                                                     \
+  do {                                                                                                   \
+    hipError_t e_ = (expr);                                                                              \
+    if (e_ != hipSuccess)                                                                                \
+      return fail(MOR_EDEVICE, std::string(#expr " failed: ") + hipGetErrorString(e_));                  \
+  } while (0)
+
+static inline int64_t rup(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
+
+namespace {
+
+struct TimerRec {
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
+  int64_t launches = 0;
+  double ms = 0.0;
+  double work = 0.0;
+};
+
+struct SubDev {
+  int *rp = nullptr, *col = nullptr, *ii_end = nullptr, *rpV = nullptr, *colV = nullptr;
+  int *ltet = nullptr, *tetg = nullptr, *nodes = nullptr;
+  uint8_t* core = nullptr;
+};
+
+struct SubResult {
+  int reduced = 0;
+  int k_eff = 0;
+  std::vector<double> sigma;
+  std::vector<double> Aii, bi;
+  double* d_V = nullptr;   // nV x (k+1)
+  double* d_Pm = nullptr;  // (k+1) x (k+2): [Q^T A Q | Q^T f]
+  int cg_a = 0, cg_k = 0, refine = 0, eig = 0;
+};
+
+}  // namespace
+
+struct mor_ctx {
+  mor_opts opts;
+  hipStream_t st = nullptr;
+  HostMesh mesh;
+  std::vector<double> kappa, fnodal;
+  bool has_f = false;
+  std::vector<HostSub> subs;
+  std::vector<int64_t> ext_ptr;
+  std::vector<int32_t> ext;
+  std::vector<uint8_t> in_core;
+  std::vector<int32_t> owner, ownpos;
+  HostOmega0 om0;
+  double *d_xyz = nullptr, *d_kappa = nullptr, *d_f = nullptr;
+  int* d_tets = nullptr;
+  std::vector<SubDev> sdev;
+  SubDev om0dev;
+  std::vector<SubResult> res;
+  // reduced system
+  int64_t n_red = 0, MPr = 0;
+  std::vector<int> off;
+  double *d_At = nullptr, *d_bt = nullptr, *d_x = nullptr;
+  std::vector<double> x_host;
+  int projected = 0, solved = 0;
+  std::vector<void*> allocs;
+  bool timing = false;
+  std::map<std::string, TimerRec> timers;
+};
+
+// ------------------------------------------------------------------------------- memory
+static void* dalloc(mor_ctx* c, size_t bytes) {
+  bytes = (size_t)rup((int64_t)std::max<size_t>(bytes, 256), 256);
+  void* p = nullptr;
+  if (c->opts.dev_alloc) {
+    p = c->opts.dev_alloc(bytes, c->opts.alloc_user);
+  } else if (hipMalloc(&p, bytes) != hipSuccess) {
+    p = nullptr;
+  }
+  return p;
+}
+static void dfree(mor_ctx* c, void* p) {
+  if (!p) return;
+  if (c->opts.dev_free) c->opts.dev_free(p, c->opts.alloc_user);
+  else (void)hipFree(p);
+}
+// persistent allocation released by mor_destroy
+static void* palloc(mor_ctx* c, size_t bytes) {
+  void* p = dalloc(c, bytes);
+  if (p) c->allocs.push_back(p);
+  return p;
+}
+static void pfree(mor_ctx* c, void* p) {
+  if (!p) return;
+  auto it = std::find(c->allocs.begin(), c->allocs.end(), p);
+  if (it != c->allocs.end()) c->allocs.erase(it);
+  dfree(c, p);
+}
+template <typename T>
+static int upload(mor_ctx* c, T** dst, const T* src, size_t n) {
+  *dst = (T*)palloc(c, sizeof(T) * std::max<size_t>(n, 1));
+  if (!*dst) return fail(MOR_ENOMEM, "device allocation failed");
+  if (n) HIPCHK(hipMemcpyAsync(*dst, src, sizeof(T) * n, hipMemcpyHostToDevice, c->st));
+  return 0;
+}
+
+// A bump allocator over one device block for the transient data of a batch.
+struct Arena {
+  char* base = nullptr;
+  size_t cap = 0, used = 0;
+  void* take(size_t bytes) {
+    const size_t o = (size_t)rup((int64_t)used, 256);
+    if (o + bytes > cap) return nullptr;
+    used = o + bytes;
+    return base + o;
+  }
+};
+struct Sizer {
+  size_t total = 0;
+  void add(size_t bytes) { total = (size_t)rup((int64_t)total, 256) + bytes; }
+};
+
+// ------------------------------------------------------------------------------- timing
+struct ScopedTimer {
+  mor_ctx* c;
+  const char* name;
+  double work;
+  hipEvent_t a = nullptr, b = nullptr;
+  ScopedTimer(mor_ctx* c_, const char* n, double w) : c(c_), name(n), work(w) {
+    if (c->timing) {
+      (void)hipEventCreate(&a);
+      (void)hipEventCreate(&b);
+      (void)hipEventRecord(a, c->st);
+    }
+  }
+  ~ScopedTimer() {
+    if (c->timing) {
+      (void)hipEventRecord(b, c->st);
+      TimerRec& t = c->timers[name];
+      t.ev.emplace_back(a, b);
+      t.launches++;
+      t.work += work;
+    }
+  }
+};
+
+static void flush_timers(mor_ctx* c) {
+  (void)hipStreamSynchronize(c->st);
+  for (auto& kv : c->timers) {
+    for (auto& e : kv.second.ev) {
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, e.first, e.second) == hipSuccess) kv.second.ms += ms;
+      (void)hipEventDestroy(e.first);
+      (void)hipEventDestroy(e.second);
+    }
+    kv.second.ev.clear();
+  }
+}
+
+// ------------------------------------------------------------------------------- C-ABI basics
+extern "C" const char* mor_last_error(void) { return g_err.c_str(); }
+
+extern "C" void mor_default_opts(mor_opts* o) {
+  std::memset(o, 0, sizeof(*o));
+  o->precision = MOR_FP32_REFINE;
+  o->cg_rtol = 1e-5;
+  o->refine_rtol = 1e-10;
+  o->max_iter = 4000;
+  o->refine_steps = 3;
+  o->oversample = 0;
+  o->eig_rtol = 1e-10;
+  o->eig_max_iter = 600;
+  o->cg_chunk = 8;
+  o->spmm_rows = 0;
+  o->use_graph = 0;
+  o->hbm_budget_bytes = 0;
+}
+
+extern "C" int mor_create(const mor_mesh* mesh, const mor_coeff* coeff, const mor_subdomains* sub,
+                          const mor_opts* opts, mor_ctx** out) {
+  if (!mesh || !coeff || !sub || !out) return fail(MOR_EINVAL, "null argument");
+  if (mesh->n_nodes <= 0 || mesh->n_tets <= 0 || !mesh->xyz || !mesh->tets || !mesh->dirichlet)
+    return fail(MOR_EINVAL, "empty or incomplete mesh");
+  if (!coeff->kappa) return fail(MOR_EINVAL, "kappa is required");
+  if (sub->n_sub <= 0 || !sub->ext_tet_ptr || !sub->ext_tets || !sub->in_core)
+    return fail(MOR_EINVAL, "empty decomposition");
+  if (mesh->n_nodes > INT32_MAX || mesh->n_tets > INT32_MAX) return fail(MOR_EINVAL, "mesh too large for int32 ids");
+  mor_ctx* c = new mor_ctx();
+  if (opts) c->opts = *opts;
+  else mor_default_opts(&c->opts);
+  if (c->opts.precision < MOR_FP64 || c->opts.precision > MOR_BF16_SPLIT) {
+    delete c;
+    return fail(MOR_EINVAL, "unknown precision mode");
+  }
+  c->st = (hipStream_t)c->opts.hip_stream;
+  HostMesh& m = c->mesh;
+  m.n_nodes = mesh->n_nodes;
+  m.n_tets = mesh->n_tets;
+  m.xyz.assign(mesh->xyz, mesh->xyz + 3 * m.n_nodes);
+  m.tets.assign(mesh->tets, mesh->tets + 4 * m.n_tets);
+  m.dirichlet.assign(mesh->dirichlet, mesh->dirichlet + m.n_nodes);
+  for (int64_t t = 0; t < m.n_tets; ++t)
+    if (!(coeff->kappa[t] > 0.0)) {
+      delete c;
+      return fail(MOR_EINVAL, "kappa must be positive");
+    }
+  c->kappa.assign(coeff->kappa, coeff->kappa + m.n_tets);
+  c->has_f = coeff->f_nodal != nullptr;
+  if (c->has_f) c->fnodal.assign(coeff->f_nodal, coeff->f_nodal + m.n_nodes);
+  std::string err;
+  if (build_mesh(m, err)) {
+    delete c;
+    return fail(MOR_EINVAL, err);
+  }
+  const int n = sub->n_sub;
+  c->ext_ptr.assign(sub->ext_tet_ptr, sub->ext_tet_ptr + n + 1);
+  if (c->ext_ptr[0] != 0) {
+    delete c;
+    return fail(MOR_EINVAL, "ext_tet_ptr[0] must be 0");
+  }
+  for (int i = 0; i < n; ++i)
+    if (c->ext_ptr[i + 1] < c->ext_ptr[i]) {
+      delete c;
+      return fail(MOR_EINVAL, "ext_tet_ptr must be non-decreasing");
+    }
+  c->ext.assign(sub->ext_tets, sub->ext_tets + c->ext_ptr[n]);
+  c->in_core.assign(sub->in_core, sub->in_core + c->ext_ptr[n]);
+  c->subs.resize(n);
+  for (int i = 0; i < n; ++i) {
+    if (build_sub(m, c->ext.data() + c->ext_ptr[i], c->in_core.data() + c->ext_ptr[i], c->ext_ptr[i + 1] - c->ext_ptr[i],
+                  c->subs[i], err)) {
+      delete c;
+      return fail(MOR_EINVAL, "subdomain " + std::to_string(i) + ": " + err);
+    }
+  }
+  if (build_owner(m, c->subs, c->owner, c->ownpos, err) ||
+      build_omega0(m, c->subs, c->ext_ptr.data(), c->ext.data(), c->in_core.data(), c->owner, c->ownpos, c->om0, err)) {
+    delete c;
+    return fail(MOR_EINVAL, err);
+  }
+  c->res.resize(n);
+  if (c->opts.host_only) {
+    *out = c;
+    return MOR_OK;
+  }
+  // device uploads: geometry, coefficients, patterns
+  int rc = 0;
+  rc = rc ? rc : upload(c, &c->d_xyz, m.xyz.data(), m.xyz.size());
+  rc = rc ? rc : upload(c, &c->d_tets, m.tets.data(), m.tets.size());
+  rc = rc ? rc : upload(c, &c->d_kappa, c->kappa.data(), c->kappa.size());
+  if (c->has_f) rc = rc ? rc : upload(c, &c->d_f, c->fnodal.data(), c->fnodal.size());
+  auto up_sub = [&](const HostSub& h, SubDev& d) {
+    int r = 0;
+    r = r ? r : upload(c, &d.rp, h.rp.data(), h.rp.size());
+    r = r ? r : upload(c, &d.col, h.col.data(), h.col.size());
+    r = r ? r : upload(c, &d.ii_end, h.ii_end.data(), h.ii_end.size());
+    r = r ? r : upload(c, &d.rpV, h.rpV.data(), h.rpV.size());
+    r = r ? r : upload(c, &d.colV, h.colV.data(), h.colV.size());
+    r = r ? r : upload(c, &d.ltet, h.ltet.data(), h.ltet.size());
+    r = r ? r : upload(c, &d.tetg, h.tetg.data(), h.tetg.size());
+    r = r ? r : upload(c, &d.nodes, h.nodes.data(), h.nodes.size());
+    r = r ? r : upload(c, &d.core, h.core.data(), h.core.size());
+    return r;
+  };
+  c->sdev.resize(n);
+  for (int i = 0; i < n && !rc; ++i) rc = up_sub(c->subs[i], c->sdev[i]);
+  if (!rc) rc = up_sub(c->om0.sub, c->om0dev);
+  if (!rc && hipStreamSynchronize(c->st) != hipSuccess) rc = fail(MOR_EDEVICE, "upload failed");
+  if (rc) {
+    mor_destroy(c);
+    return rc;
+  }
+  *out = c;
+  return MOR_OK;
+}
+
+extern "C" void mor_destroy(mor_ctx* c) {
+  if (!c) return;
+  if (c->opts.host_only) {
+    delete c;
+    return;
+  }
+  (void)hipStreamSynchronize(c->st);
+  for (auto& kv : c->timers)
+    for (auto& e : kv.second.ev) {
+      (void)hipEventDestroy(e.first);
+      (void)hipEventDestroy(e.second);
+    }
+  for (void* p : c->allocs) dfree(c, p);
+  delete c;
+}
+
+// ------------------------------------------------------------------------------- assembly
+// Assemble the matrices of a set of subdomains (or omega_0) colour by colour.
+struct AsmJob {
+  const HostSub* h;
+  const SubDev* d;
+  double *A, *K, *Ki, *f;
+};
+
+static int assemble_batch(mor_ctx* c, const std::vector<AsmJob>& jobs) {
+  const int nj = (int)jobs.size();
+  const int nc = c->mesh.ncolours;
+  std::vector<AsmSub> hs((size_t)nj * nc);
+  std::vector<int> prefix((size_t)nj * nc + nc, 0);
+  // per colour: nj descriptors and nj+1 prefix entries
+  std::vector<int> pre((size_t)(nj + 1) * nc);
+  for (int col = 0; col < nc; ++col) {
+    pre[(size_t)col * (nj + 1)] = 0;
+    for (int j = 0; j < nj; ++j) {
+      const HostSub& h = *jobs[j].h;
+      AsmSub& a = hs[(size_t)col * nj + j];
+      a.ltet = jobs[j].d->ltet;
+      a.tetg = jobs[j].d->tetg;
+      a.core = jobs[j].d->core;
+      a.t_begin = h.colour_ptr[col];
+      a.t_count = h.colour_ptr[col + 1] - h.colour_ptr[col];
+      a.rp = jobs[j].d->rp;
+      a.col = jobs[j].d->col;
+      a.rpV = jobs[j].d->rpV;
+      a.colV = jobs[j].d->colV;
+      a.A = jobs[j].A;
+      a.K = jobs[j].K;
+      a.Ki = jobs[j].Ki;
+      a.f = jobs[j].f;
+      pre[(size_t)col * (nj + 1) + j + 1] = pre[(size_t)col * (nj + 1) + j] + a.t_count;
+    }
+  }
+  AsmSub* d_hs = (AsmSub*)dalloc(c, sizeof(AsmSub) * hs.size());
+  int* d_pre = (int*)dalloc(c, sizeof(int) * pre.size());
+  if (!d_hs || !d_pre) {
+    dfree(c, d_hs);
+    dfree(c, d_pre);
+    return fail(MOR_ENOMEM, "device allocation failed (assembly descriptors)");
+  }
+  HIPCHK(hipMemcpyAsync(d_hs, hs.data(), sizeof(AsmSub) * hs.size(), hipMemcpyHostToDevice, c->st));
+  HIPCHK(hipMemcpyAsync(d_pre, pre.data(), sizeof(int) * pre.size(), hipMemcpyHostToDevice, c->st));
+  {
+    int64_t ntet = 0;
+    for (auto& j : jobs) ntet += (int64_t)j.h->tetg.size();
+    ScopedTimer tm(c, "assemble", (double)ntet);
+    for (int col = 0; col < nc; ++col) {
+      const int total = pre[(size_t)col * (nj + 1) + nj];
+      launch_assemble(d_hs + (size_t)col * nj, d_pre + (size_t)col * (nj + 1), nj, total, c->d_xyz, c->d_tets,
+                      c->d_kappa, c->d_f, c->st);
+    }
+  }
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(c->st));
+  dfree(c, d_hs);
+  dfree(c, d_pre);
+  return 0;
+}
+
+// ------------------------------------------------------------------------------- batch GEMM
+struct GemmBatch {
+  std::vector<GemmDesc> d;
+  std::vector<int4> tiles;
+  GemmDesc* dd = nullptr;
+  int4* dt = nullptr;
+  void add(const GemmDesc& g) {
+    const int id = (int)d.size();
+    d.push_back(g);
+    const int tm = (g.m + 63) / 64, tn = (g.n + 63) / 64;
+    for (int i = 0; i < tm; ++i)
+      for (int j = 0; j < tn; ++j)
+        if (!g.sym || i <= j) tiles.push_back(make_int4(id, i, j, 0));
+  }
+  double flops() const {
+    double f = 0;
+    for (auto& g : d) f += 2.0 * g.m * g.n * g.k * (g.sym ? 0.5 : 1.0);
+    return f;
+  }
+};
+static int gemm_upload(mor_ctx* c, GemmBatch& b, Arena& ar) {
+  b.dd = (GemmDesc*)ar.take(sizeof(GemmDesc) * std::max<size_t>(1, b.d.size()));
+  b.dt = (int4*)ar.take(sizeof(int4) * std::max<size_t>(1, b.tiles.size()));
+  if (!b.dd || !b.dt) return fail(MOR_ENOMEM, "arena exhausted (gemm)");
+  if (!b.d.empty()) HIPCHK(hipMemcpyAsync(b.dd, b.d.data(), sizeof(GemmDesc) * b.d.size(), hipMemcpyHostToDevice, c->st));
+  if (!b.tiles.empty())
+    HIPCHK(hipMemcpyAsync(b.dt, b.tiles.data(), sizeof(int4) * b.tiles.size(), hipMemcpyHostToDevice, c->st));
+  return 0;
+}
+static void gemm_run(mor_ctx* c, const GemmBatch& b, const char* tname) {
+  ScopedTimer tm(c, tname, b.flops());
+  launch_gemm(b.dd, b.dt, (int)b.tiles.size(), c->st);
+}
+static GemmDesc gd(int m, int n, int k, const double* A, int lda, int ta, const double* B, int ldb, int tb, double* C,
+                   int ldc, double alpha = 1.0, double beta = 0.0, int sym = 0) {
+  GemmDesc g;
+  g.m = m; g.n = n; g.k = k;
+  g.A = A; g.lda = lda; g.ta = ta;
+  g.B = B; g.ldb = ldb; g.tb = tb;
+  g.C = C; g.ldc = ldc;
+  g.alpha = alpha; g.beta = beta; g.sym = sym;
+  return g;
+}
+
+// ------------------------------------------------------------------------------- block CG
+struct CgState {
+  std::vector<CgSys> hsys;
+  CgSys* dsys = nullptr;
+  CgCols cols{};
+  int* d_tiles_buf = nullptr;
+  size_t tiles_cap = 0;
+  int* h_nactive = nullptr;   // pinned
+  std::vector<int> iters;
+  int rb = 32;
+  int elt = 4;                // bytes of the CG scalar type
+};
+
+// tiles of the active systems: (system, first row, first column), row blocks fastest so that
+// consecutive tiles (one XCD) sweep the rows of one column slab
+static std::vector<int4> make_tiles(const CgState& cs, const std::vector<char>& act) {
+  std::vector<int4> t;
+  const int W = cs.elt == 4 ? 256 : 128;   // columns per tile (64 lanes x 16 bytes)
+  for (size_t s = 0; s < cs.hsys.size(); ++s) {
+    if (!act[s]) continue;
+    const CgSys& S = cs.hsys[s];
+    for (int c0 = 0; c0 < S.ld; c0 += W)
+      for (int r0 = 0; r0 < S.nI; r0 += cs.rb) t.push_back(make_int4((int)s, r0, c0, 0));
+  }
+  return t;
+}
+
+// algorithmic bytes of one SpMM over the active systems: CSR of A_II + read P once + write Q
+static double spmm_bytes(const CgState& cs, const std::vector<char>& act, const std::vector<int>& sys_nnz) {
+  double b = 0;
+  for (size_t s = 0; s < cs.hsys.size(); ++s) {
+    if (!act[s]) continue;
+    const CgSys& S = cs.hsys[s];
+    b += (double)sys_nnz[s] * (4.0 + cs.elt) + 4.0 * (S.nI + 1) + 2.0 * cs.elt * (double)S.nI * S.ncols;
+  }
+  return b;
+}
+
+template <typename T>
+static int cg_iterate(mor_ctx* c, CgState& cs, std::vector<char>& act, double tol, const std::vector<int>& sys_sub,
+                      const std::vector<int>& sys_nnz) {
+  const int chunk = std::max(1, c->opts.cg_chunk);
+  const int nsys = (int)cs.hsys.size();
+  int it = 0;
+  for (;;) {
+    bool any = false;
+    for (int s = 0; s < nsys; ++s) any |= act[s] != 0;
+    if (!any) break;
+    if (it >= c->opts.max_iter) return fail(MOR_ENOTCONV, "block CG did not converge within max_iter");
+    std::vector<int4> tiles = make_tiles(cs, act);
+    const double by = spmm_bytes(cs, act, sys_nnz);
+    if (tiles.size() > cs.tiles_cap) {
+      dfree(c, cs.d_tiles_buf);
+      cs.tiles_cap = tiles.size() * 2;
+      cs.d_tiles_buf = (int*)dalloc(c, sizeof(int4) * cs.tiles_cap);
+      if (!cs.d_tiles_buf) return fail(MOR_ENOMEM, "tile list allocation failed");
+    }
+    int4* dt = (int4*)cs.d_tiles_buf;
+    HIPCHK(hipMemcpyAsync(dt, tiles.data(), sizeof(int4) * tiles.size(), hipMemcpyHostToDevice, c->st));
+    const int nt = (int)tiles.size();
+    const double tol2 = tol * tol;
+    for (int k = 0; k < chunk; ++k) {
+      {
+        ScopedTimer tm(c, "spmm", by);
+        launch_cg_spmm<T>(cs.dsys, dt, nt, cs.rb, cs.cols, c->st);
+      }
+      launch_cg_alpha(cs.cols, c->st);
+      {
+        ScopedTimer tm(c, "cg_update", 0);
+        launch_cg_update<T>(cs.dsys, dt, nt, cs.rb, cs.cols, c->st);
+      }
+      launch_cg_beta(cs.cols, tol2, c->st);
+      {
+        ScopedTimer tm(c, "cg_direction", 0);
+        launch_cg_direction<T>(cs.dsys, dt, nt, cs.rb, cs.cols, c->st);
+      }
+    }
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(cs.h_nactive, cs.cols.nactive, sizeof(int) * nsys, hipMemcpyDeviceToHost, c->st));
+    HIPCHK(hipStreamSynchronize(c->st));
+    for (int s = 0; s < nsys; ++s) {
+      if (act[s]) cs.iters[s] += chunk;
+      act[s] = cs.h_nactive[s] > 0;
+    }
+    it += chunk;
+  }
+  return 0;
+}
+
+template <typename T>
+static int cg_solve(mor_ctx* c, CgState& cs, const std::vector<int>& sys_sub, const std::vector<int>& sys_nnz,
+                    std::vector<int>& refines) {
+  const int nsys = (int)cs.hsys.size();
+  const bool refine = c->opts.precision == MOR_FP32_REFINE;
+  const double inner = (c->opts.precision == MOR_FP64) ? c->opts.refine_rtol : c->opts.cg_rtol;
+  std::vector<char> all(nsys, 1), act(nsys, 1);
+  std::vector<int4> tiles_all = make_tiles(cs, all);
+  int4* dta = (int4*)dalloc(c, sizeof(int4) * std::max<size_t>(1, tiles_all.size()));
+  if (!dta) return fail(MOR_ENOMEM, "tile list allocation failed");
+  HIPCHK(hipMemcpyAsync(dta, tiles_all.data(), sizeof(int4) * tiles_all.size(), hipMemcpyHostToDevice, c->st));
+  const int nta = (int)tiles_all.size();
+  launch_fill(cs.cols.rz, cs.cols.ncols_total, 0.0, c->st);
+  launch_cg_init<T>(cs.dsys, dta, nta, cs.rb, cs.cols, c->st);
+  launch_cg_start(cs.cols, 1, 0.0, c->st);
+  HIPCHK(hipMemcpyAsync(cs.h_nactive, cs.cols.nactive, sizeof(int) * nsys, hipMemcpyDeviceToHost, c->st));
+  HIPCHK(hipStreamSynchronize(c->st));
+  for (int s = 0; s < nsys; ++s) act[s] = cs.h_nactive[s] > 0;
+  int rc = cg_iterate<T>(c, cs, act, inner, sys_sub, sys_nnz);
+  if (rc) {
+    dfree(c, dta);
+    return rc;
+  }
+  if (refine) {
+    const double outer2 = c->opts.refine_rtol * c->opts.refine_rtol;
+    for (int step = 0; step < c->opts.refine_steps; ++step) {
+      launch_cg_shadow<T>(cs.dsys, dta, nta, cs.rb, c->st);
+      launch_fill(cs.cols.rz, cs.cols.ncols_total, 0.0, c->st);
+      {
+        ScopedTimer tm(c, "residual64", 0);
+        launch_cg_residual64<T>(cs.dsys, dta, nta, cs.rb, cs.cols, c->st);
+      }
+      launch_cg_restart(cs.cols, outer2, c->st);
+      HIPCHK(hipMemcpyAsync(cs.h_nactive, cs.cols.nactive, sizeof(int) * nsys, hipMemcpyDeviceToHost, c->st));
+      HIPCHK(hipStreamSynchronize(c->st));
+      bool any = false;
+      for (int s = 0; s < nsys; ++s) {
+        act[s] = cs.h_nactive[s] > 0;
+        any |= act[s] != 0;
+        if (act[s]) refines[s]++;
+      }
+      if (!any) break;
+      rc = cg_iterate<T>(c, cs, act, inner, sys_sub, sys_nnz);
+      if (rc) {
+        dfree(c, dta);
+        return rc;
+      }
+    }
+    launch_cg_shadow<T>(cs.dsys, dta, nta, cs.rb, c->st);
+  }
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(c->st));
+  dfree(c, dta);
+  return 0;
+}
+
+// ------------------------------------------------------------------------------- truncation
+// Number of leading singular triplets kept: top-`rank` (rank > 0) or sigma > tol, widened to
+// the end of a cluster of equal singular values (relative gap <= 1e-4) so the kept span is
+// well defined.
+static int truncation_rank(const std::vector<double>& s, int rank, double tol, int cap) {
+  const int M = (int)s.size();
+  int k = 0;
+  if (rank > 0) k = std::min(rank, M);
+  else
+    for (int j = 0; j < M; ++j) k += s[j] > tol ? 1 : 0;
+  if (k == 0) return 0;
+  while (k < M) {
+    if (s[k - 1] <= 0.0 || (s[k - 1] - s[k]) / s[k - 1] > 1e-4) break;
+    ++k;
+  }
+  return std::min(k, cap);
+}
+
+// ------------------------------------------------------------------------------- local batch
+struct Slot {
+  int sd, rank;
+  double tol;
+  const HostSub* h;
+  const SubDev* d;
+  int M, MP, T, colsA, ldA, colsK, ldK, s, nconv;
+  double *A64, *K64, *Ki64, *f;
+  float *A32, *K32;
+  void *dinvA, *dinvK;
+  void *XA, *RA, *PA, *QA, *XK, *RK, *PK, *QK;
+  double *XA64, *XK64;
+  double *Xc, *Ec;          // FP64 views of the solutions (converted in FP32 modes)
+  int ldXc, ldEc;
+  double *Y, *S, *G, *W, *C, *Dinv;
+  double *Vb, *Yb, *Ub, *Zb, *Vn, *Tb, *H, *Ss, *G2, *Rinv, *theta, *resid;
+  double *Bk, *Wk, *Yf;
+  int* info;
+  int k_eff;
+};
+
+static int slot_sizes(mor_ctx* c, Slot& q, Sizer& z, int elt) {
+  const HostSub& h = *q.h;
+  q.M = h.nB;
+  q.MP = (int)rup(q.M, 64);
+  q.T = q.MP / 64;
+  q.colsA = h.nB + 1;
+  q.ldA = (int)rup(q.colsA, 4);
+  q.colsK = h.nB;
+  q.ldK = (int)rup(q.colsK, 4);
+  int p = c->opts.oversample > 0 ? c->opts.oversample : std::max(8, q.rank);
+  int s = q.rank > 0 ? std::min(64, q.rank + p) : 64;
+  s = std::min(s, q.M);
+  q.s = s;
+  q.nconv = q.rank > 0 ? std::min(s - 1, q.rank + std::max(2, p / 2)) : s - 1;
+  if (q.nconv < 1) q.nconv = std::min(1, s);
+  const size_t nnz = h.rp[h.nL], nnzV = h.rpV[h.nV];
+  const bool fp32 = elt == 4;
+  const bool refine = c->opts.precision == MOR_FP32_REFINE;
+  z.add(8 * nnz); z.add(8 * nnz); z.add(8 * nnzV); z.add(8 * (size_t)h.nL);
+  if (fp32) { z.add(4 * nnz); z.add(4 * nnz); }
+  z.add((size_t)elt * h.nI); z.add((size_t)elt * h.nI);
+  for (int i = 0; i < 4; ++i) z.add((size_t)elt * h.nI * q.ldA);
+  for (int i = 0; i < 4; ++i) z.add((size_t)elt * h.nI * q.ldK);
+  if (refine) { z.add(8 * (size_t)h.nI * q.ldA); z.add(8 * (size_t)h.nI * q.ldK); }
+  if (fp32 && !refine) { z.add(8 * (size_t)h.nV * q.ldA); z.add(8 * (size_t)h.nI * q.ldK); }
+  z.add(8 * (size_t)h.nV * q.ldK);                       // Y
+  for (int i = 0; i < 4; ++i) z.add(8 * (size_t)q.MP * q.MP);   // S, G, W, C
+  z.add(8 * (size_t)q.T * 4096);
+  for (int i = 0; i < 6; ++i) z.add(8 * (size_t)q.MP * s);
+  for (int i = 0; i < 4; ++i) z.add(8 * (size_t)s * s);
+  z.add(8 * (size_t)s); z.add(8 * (size_t)s);
+  z.add(8 * (size_t)q.MP * 64); z.add(8 * (size_t)q.MP * 64);
+  z.add(8 * (size_t)std::max(1, h.nP) * (s + 2));
+  z.add(64);
+  return 0;
+}
+
+static int slot_carve(mor_ctx* c, Slot& q, Arena& a, int elt) {
+  const HostSub& h = *q.h;
+  const size_t nnz = h.rp[h.nL], nnzV = h.rpV[h.nV];
+  const bool fp32 = elt == 4;
+  const bool refine = c->opts.precision == MOR_FP32_REFINE;
+  auto tk = [&](size_t b) { return a.take(b); };
+  q.A64 = (double*)tk(8 * nnz); q.K64 = (double*)tk(8 * nnz); q.Ki64 = (double*)tk(8 * nnzV); q.f = (double*)tk(8 * (size_t)h.nL);
+  q.A32 = fp32 ? (float*)tk(4 * nnz) : nullptr;
+  q.K32 = fp32 ? (float*)tk(4 * nnz) : nullptr;
+  q.dinvA = tk((size_t)elt * h.nI); q.dinvK = tk((size_t)elt * h.nI);
+  q.XA = tk((size_t)elt * h.nI * q.ldA); q.RA = tk((size_t)elt * h.nI * q.ldA);
+  q.PA = tk((size_t)elt * h.nI * q.ldA); q.QA = tk((size_t)elt * h.nI * q.ldA);
+  q.XK = tk((size_t)elt * h.nI * q.ldK); q.RK = tk((size_t)elt * h.nI * q.ldK);
+  q.PK = tk((size_t)elt * h.nI * q.ldK); q.QK = tk((size_t)elt * h.nI * q.ldK);
+  q.XA64 = refine ? (double*)tk(8 * (size_t)h.nI * q.ldA) : nullptr;
+  q.XK64 = refine ? (double*)tk(8 * (size_t)h.nI * q.ldK) : nullptr;
+  if (fp32 && !refine) {
+    q.Xc = (double*)tk(8 * (size_t)h.nV * q.ldA);
+    q.Ec = (double*)tk(8 * (size_t)h.nI * q.ldK);
+  } else if (refine) {
+    q.Xc = q.XA64; q.Ec = q.XK64;
+  } else {
+    q.Xc = (double*)q.XA; q.Ec = (double*)q.XK;
+  }
+  q.ldXc = q.ldA; q.ldEc = q.ldK;
+  q.Y = (double*)tk(8 * (size_t)h.nV * q.ldK);
+  q.S = (double*)tk(8 * (size_t)q.MP * q.MP); q.G = (double*)tk(8 * (size_t)q.MP * q.MP);
+  q.W = (double*)tk(8 * (size_t)q.MP * q.MP); q.C = (double*)tk(8 * (size_t)q.MP * q.MP);
+  q.Dinv = (double*)tk(8 * (size_t)q.T * 4096);
+  const int s = q.s;
+  q.Vb = (double*)tk(8 * (size_t)q.MP * s); q.Yb = (double*)tk(8 * (size_t)q.MP * s);
+  q.Ub = (double*)tk(8 * (size_t)q.MP * s); q.Zb = (double*)tk(8 * (size_t)q.MP * s);
+  q.Vn = (double*)tk(8 * (size_t)q.MP * s); q.Tb = (double*)tk(8 * (size_t)q.MP * s);
+  q.H = (double*)tk(8 * (size_t)s * s); q.Ss = (double*)tk(8 * (size_t)s * s);
+  q.G2 = (double*)tk(8 * (size_t)s * s); q.Rinv = (double*)tk(8 * (size_t)s * s);
+  q.theta = (double*)tk(8 * (size_t)s); q.resid = (double*)tk(8 * (size_t)s);
+  q.Bk = (double*)tk(8 * (size_t)q.MP * 64); q.Wk = (double*)tk(8 * (size_t)q.MP * 64);
+  q.Yf = (double*)tk(8 * (size_t)std::max(1, h.nP) * (s + 2));
+  q.info = (int*)tk(64);
+  if (!q.info) return fail(MOR_ENOMEM, "arena exhausted");
+  return 0;
+}
+
+template <typename T>
+static int local_batch_t(mor_ctx* c, std::vector<Slot>& slots) {
+  const int ns = (int)slots.size();
+  const int elt = (int)sizeof(T);
+  const bool fp32 = elt == 4;
+  const bool refine = c->opts.precision == MOR_FP32_REFINE;
+  hipStream_t st = c->st;
+  // ---- arena
+  Sizer z;
+  for (auto& q : slots) slot_sizes(c, q, z, elt);
+  int total_cols = 0;
+  for (auto& q : slots) total_cols += q.ldA + q.ldK;
+  const int nsys = 2 * ns;
+  z.add(sizeof(CgSys) * nsys);
+  for (int i = 0; i < 7; ++i) z.add(8 * (size_t)total_cols);
+  z.add(4 * (size_t)total_cols); z.add(4 * (size_t)total_cols); z.add(4 * (size_t)nsys);
+  z.add(sizeof(DenseSub) * ns + sizeof(TrsmDesc) * ns * 2);
+  z.add(8 * (size_t)ns * 32);          // pointer tables
+  z.add(4 * (size_t)ns * 8);
+  z.add(1 << 20);                      // gemm descriptors and tiles headroom
+  size_t gemm_extra = 0;
+  for (auto& q : slots) gemm_extra += 16 * (size_t)(q.T * q.T + 8 * q.T + 64) + 4 * sizeof(GemmDesc);
+  z.add(gemm_extra * 4);
+  const size_t budget = c->opts.hbm_budget_bytes;
+  if (budget && z.total > budget) return fail(MOR_ENOMEM, "batch exceeds the HBM budget");
+  Arena ar;
+  ar.cap = z.total + 4096;
+  ar.base = (char*)dalloc(c, ar.cap);
+  if (!ar.base) return fail(MOR_ENOMEM, "device allocation of " + std::to_string(ar.cap) + " bytes failed");
+  struct Guard {
+    mor_ctx* c; void* p;
+    ~Guard() { (void)hipStreamSynchronize(c->st); dfree(c, p); }
+  } guard{c, ar.base};
+  for (auto& q : slots)
+    if (int rc = slot_carve(c, q, ar, elt)) return rc;
+
+  // ---- assembly (Section 2 stiffness with kappa, Section 4 H1 matrices, load M f_h)
+  std::vector<AsmJob> jobs;
+  for (auto& q : slots) {
+    const HostSub& h = *q.h;
+    launch_fill(q.A64, h.rp[h.nL], 0.0, st);
+    launch_fill(q.K64, h.rp[h.nL], 0.0, st);
+    launch_fill(q.Ki64, h.rpV[h.nV], 0.0, st);
+    launch_fill(q.f, h.nL, 0.0, st);
+    jobs.push_back({q.h, q.d, q.A64, q.K64, q.Ki64, q.f});
+  }
+  if (int rc = assemble_batch(c, jobs)) return rc;
+  for (auto& q : slots) {
+    const HostSub& h = *q.h;
+    if (fp32) {
+      launch_to_f32(q.A64, q.A32, h.rp[h.nL], st);
+      launch_to_f32(q.K64, q.K32, h.rp[h.nL], st);
+    }
+    launch_diag_inv(q.d->rp, q.d->col, q.A64, h.nI, q.dinvA, !fp32, st);
+    launch_diag_inv(q.d->rp, q.d->col, q.K64, h.nI, q.dinvK, !fp32, st);
+  }
+
+  // ---- block CG on A_II (lifting + load) and K_II (H1 extension for S_B)
+  CgState cs;
+  cs.elt = elt;
+  cs.rb = c->opts.spmm_rows > 0 ? c->opts.spmm_rows : 32;
+  std::vector<int> sys_sub(nsys), sys_nnz(nsys);
+  std::vector<int> sys_of_col(total_cols);
+  int coff = 0;
+  for (int i = 0; i < ns; ++i) {
+    Slot& q = slots[i];
+    const HostSub& h = *q.h;
+    int nnzII = 0;
+    for (int r = 0; r < h.nI; ++r) nnzII += h.ii_end[r] - h.rp[r];
+    for (int w = 0; w < 2; ++w) {
+      CgSys S{};
+      S.rp = q.d->rp; S.col = q.d->col; S.ii_end = q.d->ii_end;
+      S.val32 = w == 0 ? q.A32 : q.K32;
+      S.val64 = w == 0 ? q.A64 : q.K64;
+      S.dinv = w == 0 ? q.dinvA : q.dinvK;
+      S.f = w == 0 ? q.f : nullptr;
+      S.nI = h.nI; S.nB = h.nB;
+      S.ncols = w == 0 ? q.colsA : q.colsK;
+      S.ld = w == 0 ? q.ldA : q.ldK;
+      S.X = w == 0 ? q.XA : q.XK; S.R = w == 0 ? q.RA : q.RK;
+      S.P = w == 0 ? q.PA : q.PK; S.Q = w == 0 ? q.QA : q.QK;
+      S.X64 = w == 0 ? q.XA64 : q.XK64;
+      S.coff = coff;
+      const int sidx = 2 * i + w;
+      for (int j = 0; j < S.ld; ++j) sys_of_col[coff + j] = sidx;
+      coff += S.ld;
+      cs.hsys.push_back(S);
+      sys_sub[sidx] = i;
+      sys_nnz[sidx] = nnzII;
+    }
+  }
+  cs.dsys = (CgSys*)ar.take(sizeof(CgSys) * nsys);
+  double* colbuf[7];
+  for (int i = 0; i < 7; ++i) colbuf[i] = (double*)ar.take(8 * (size_t)total_cols);
+  int* d_active = (int*)ar.take(4 * (size_t)total_cols);
+  int* d_soc = (int*)ar.take(4 * (size_t)total_cols);
+  int* d_nact = (int*)ar.take(4 * (size_t)nsys);
+  if (!d_nact) return fail(MOR_ENOMEM, "arena exhausted (cg)");
+  HIPCHK(hipMemcpyAsync(cs.dsys, cs.hsys.data(), sizeof(CgSys) * nsys, hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(d_soc, sys_of_col.data(), 4 * (size_t)total_cols, hipMemcpyHostToDevice, st));
+  cs.cols.pq = colbuf[0]; cs.cols.rz = colbuf[1]; cs.cols.rznew = colbuf[2]; cs.cols.rz0 = colbuf[3];
+  cs.cols.rzF = colbuf[4]; cs.cols.alpha = colbuf[5]; cs.cols.beta = colbuf[6];
+  cs.cols.active = d_active; cs.cols.sys_of_col = d_soc; cs.cols.nactive = d_nact;
+  cs.cols.ncols_total = total_cols;
+  HIPCHK(hipHostMalloc((void**)&cs.h_nactive, 4 * (size_t)nsys));
+  cs.iters.assign(nsys, 0);
+  std::vector<int> refines(nsys, 0);
+  int rc = cg_solve<T>(c, cs, sys_sub, sys_nnz, refines);
+  (void)hipHostFree(cs.h_nactive);
+  dfree(c, cs.d_tiles_buf);
+  if (rc) return rc;
+
+  // ---- FP64 views of the solutions
+  for (auto& q : slots) {
+    const HostSub& h = *q.h;
+    if (fp32 && !refine) {
+      launch_to_f64_block((const float*)q.XA, q.ldA, q.Xc, q.ldXc, h.nV, q.colsA, st);
+      launch_to_f64_block((const float*)q.XK, q.ldK, q.Ec, q.ldEc, h.nI, q.colsK, st);
+    }
+  }
+  // ---- G1 = X_C^T K_i X_C (lifted interface functions in the H1(omega_i) inner product)
+  GemmBatch gG;
+  for (auto& q : slots) {
+    const HostSub& h = *q.h;
+    launch_fill(q.G, (int64_t)q.MP * q.MP, 0.0, st);
+    launch_spmm64_rows(q.d->rpV, q.d->colV, q.Ki64, h.nV, h.nV, q.Xc, q.ldXc, q.M, q.Y, q.ldK, st);
+    gG.add(gd(q.M, q.M, h.nV, q.Xc, q.ldXc, 1, q.Y, q.ldK, 0, q.G, q.MP, 1.0, 0.0, 1));
+  }
+  if ((rc = gemm_upload(c, gG, ar))) return rc;
+  gemm_run(c, gG, "gram");
+  // ---- S_B = K_BB + K_BI E (Lemma 4.1), padded with the identity
+  for (auto& q : slots) {
+    const HostSub& h = *q.h;
+    ScopedTimer tm(c, "schur", 0);
+    launch_schur(q.d->rp, q.d->col, q.K64, h.nI, h.nB, q.Ec, q.ldEc, q.S, q.MP, st);
+    launch_pad_identity(q.S, q.M, q.MP, st);
+    launch_symmetrize(q.S, q.MP, st);
+  }
+  // ---- R = chol(S_B), C = R^-T G1 R^-1
+  std::vector<DenseSub> hds(ns);
+  int tmax = 0;
+  for (int i = 0; i < ns; ++i) {
+    Slot& q = slots[i];
+    hds[i] = DenseSub{q.M, q.MP, q.T, q.S, q.G, q.W, q.C, q.Dinv, q.info};
+    tmax = std::max(tmax, q.T);
+    launch_fill_i(q.info, 16, 0, st);
+  }
+  DenseSub* dds = (DenseSub*)ar.take(sizeof(DenseSub) * ns);
+  TrsmDesc* dtd = (TrsmDesc*)ar.take(sizeof(TrsmDesc) * ns * 2);
+  if (!dtd) return fail(MOR_ENOMEM, "arena exhausted (dense)");
+  HIPCHK(hipMemcpyAsync(dds, hds.data(), sizeof(DenseSub) * ns, hipMemcpyHostToDevice, st));
+  {
+    double fl = 0;
+    for (auto& q : slots) fl += (double)q.MP * q.MP * q.MP / 3.0;
+    ScopedTimer tm(c, "potrf", fl);
+    for (int p = 0; p < tmax; ++p) {
+      launch_potrf_diag(dds, ns, p, st);
+      launch_chol_panel(dds, ns, p, tmax, st);
+      launch_chol_syrk(dds, ns, p, tmax, st);
+    }
+  }
+  {
+    std::vector<int> hinfo(ns * 16);
+    for (int i = 0; i < ns; ++i)
+      HIPCHK(hipMemcpyAsync(&hinfo[i * 16], slots[i].info, 64, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    for (int i = 0; i < ns; ++i)
+      if (hinfo[i * 16] != 0)
+        return fail(MOR_EDEVICE, "subdomain " + std::to_string(slots[i].sd) + ": S_B is not positive definite (pivot " +
+                                     std::to_string(hinfo[i * 16]) + ")");
+  }
+  std::vector<TrsmDesc> htd(2 * ns);
+  for (int i = 0; i < ns; ++i) {
+    Slot& q = slots[i];
+    htd[i] = TrsmDesc{q.G, q.MP, 0, q.W, q.MP, q.T};
+    htd[ns + i] = TrsmDesc{q.W, q.MP, 1, q.C, q.MP, q.T};
+  }
+  HIPCHK(hipMemcpyAsync(dtd, htd.data(), sizeof(TrsmDesc) * 2 * ns, hipMemcpyHostToDevice, st));
+  {
+    double fl = 0;
+    for (auto& q : slots) fl += 2.0 * (double)q.MP * q.MP * q.MP;
+    ScopedTimer tm(c, "trsm", fl);
+    launch_trsm_lt(dds, dtd, ns, tmax, st);
+    launch_trsm_lt(dds, dtd + ns, ns, tmax, st);
+  }
+  for (auto& q : slots) launch_symmetrize(q.C, q.MP, st);
+
+  // ---- top eigenpairs of C by subspace iteration with Rayleigh-Ritz
+  int smax = 0, maxrows = 0;
+  std::vector<int> s_of(ns), rows_of(ns), M_of(ns);
+  for (int i = 0; i < ns; ++i) {
+    s_of[i] = slots[i].s;
+    rows_of[i] = slots[i].MP;
+    M_of[i] = slots[i].M;
+    smax = std::max(smax, slots[i].s);
+    maxrows = std::max(maxrows, slots[i].MP);
+  }
+  int* d_s = (int*)ar.take(4 * ns);
+  int* d_rows = (int*)ar.take(4 * ns);
+  int* d_M = (int*)ar.take(4 * ns);
+  int* d_info2 = (int*)ar.take(4 * ns);
+  // pointer tables: Vb Yb Ub Zb Vn Tb H Ss G2 Rinv theta resid Bk Wk
+  const int NP = 14;
+  double** dptr = (double**)ar.take(sizeof(double*) * ns * NP);
+  if (!dptr) return fail(MOR_ENOMEM, "arena exhausted (eig)");
+  std::vector<double*> hptr((size_t)ns * NP);
+  for (int i = 0; i < ns; ++i) {
+    Slot& q = slots[i];
+    double* v[NP] = {q.Vb, q.Yb, q.Ub, q.Zb, q.Vn, q.Tb, q.H, q.Ss, q.G2, q.Rinv, q.theta, q.resid, q.Bk, q.Wk};
+    for (int k = 0; k < NP; ++k) hptr[(size_t)k * ns + i] = v[k];
+  }
+  HIPCHK(hipMemcpyAsync(dptr, hptr.data(), sizeof(double*) * ns * NP, hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(d_s, s_of.data(), 4 * ns, hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(d_rows, rows_of.data(), 4 * ns, hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(d_M, M_of.data(), 4 * ns, hipMemcpyHostToDevice, st));
+  launch_fill_i(d_info2, ns, 0, st);
+  double** P_Vb = dptr + 0 * ns; double** P_Yb = dptr + 1 * ns; double** P_Ub = dptr + 2 * ns;
+  double** P_Zb = dptr + 3 * ns; double** P_Vn = dptr + 4 * ns; double** P_Tb = dptr + 5 * ns;
+  double** P_H = dptr + 6 * ns; double** P_Ss = dptr + 7 * ns; double** P_G2 = dptr + 8 * ns;
+  double** P_Ri = dptr + 9 * ns; double** P_th = dptr + 10 * ns; double** P_res = dptr + 11 * ns;
+  double** P_Bk = dptr + 12 * ns; double** P_Wk = dptr + 13 * ns;
+  (void)P_Ub; (void)P_Tb;
+  GemmBatch gY, gH, gU, gZ, gO1a, gO1b, gO2a, gO2b;
+  for (auto& q : slots) {
+    const int s = q.s;
+    gY.add(gd(q.MP, s, q.MP, q.C, q.MP, 0, q.Vb, s, 0, q.Yb, s));
+    gH.add(gd(s, s, q.MP, q.Vb, s, 1, q.Yb, s, 0, q.H, s));
+    gU.add(gd(q.MP, s, s, q.Vb, s, 0, q.Ss, s, 0, q.Ub, s));
+    gZ.add(gd(q.MP, s, s, q.Yb, s, 0, q.Ss, s, 0, q.Zb, s));
+    gO1a.add(gd(s, s, q.MP, q.Vn, s, 1, q.Vn, s, 0, q.G2, s));
+    gO1b.add(gd(q.MP, s, s, q.Vn, s, 0, q.Rinv, s, 0, q.Tb, s));
+    gO2a.add(gd(s, s, q.MP, q.Tb, s, 1, q.Tb, s, 0, q.G2, s));
+    gO2b.add(gd(q.MP, s, s, q.Tb, s, 0, q.Rinv, s, 0, q.Vb, s));
+  }
+  for (GemmBatch* b : {&gY, &gH, &gU, &gZ, &gO1a, &gO1b, &gO2a, &gO2b})
+    if ((rc = gemm_upload(c, *b, ar))) return rc;
+  auto orth = [&]() {   // Vn -> Vb, Cholesky-QR twice
+    gemm_run(c, gO1a, "eig");
+    launch_cholinv_small(P_G2, P_Ri, d_s, ns, smax, d_info2, st);
+    gemm_run(c, gO1b, "eig");
+    gemm_run(c, gO2a, "eig");
+    launch_cholinv_small(P_G2, P_Ri, d_s, ns, smax, d_info2, st);
+    gemm_run(c, gO2b, "eig");
+  };
+  launch_random_init(P_Vn, d_rows, d_M, d_s, ns, maxrows, smax, 0x5eedu, st);
+  orth();
+  std::vector<double> hth((size_t)ns * 64), hres((size_t)ns * 64);
+  int eig_it = 0;
+  bool converged = false;
+  for (; eig_it < c->opts.eig_max_iter; ++eig_it) {
+    gemm_run(c, gY, "eig");
+    gemm_run(c, gH, "eig");
+    launch_jacobi(P_H, P_Ss, P_th, d_s, ns, smax, st);
+    gemm_run(c, gU, "eig");
+    gemm_run(c, gZ, "eig");
+    for (auto& q : slots) launch_fill(q.resid, q.s, 0.0, st);
+    launch_ritz(P_Zb, P_Ub, P_Vn, P_th, P_res, d_rows, d_s, ns, maxrows, smax, st);
+    for (int i = 0; i < ns; ++i) {
+      HIPCHK(hipMemcpyAsync(&hth[(size_t)i * 64], slots[i].theta, 8 * slots[i].s, hipMemcpyDeviceToHost, st));
+      HIPCHK(hipMemcpyAsync(&hres[(size_t)i * 64], slots[i].resid, 8 * slots[i].s, hipMemcpyDeviceToHost, st));
+    }
+    HIPCHK(hipStreamSynchronize(st));
+    converged = true;
+    for (int i = 0; i < ns && converged; ++i) {
+      const double t0 = std::max(hth[(size_t)i * 64], 1e-300);
+      for (int j = 0; j < slots[i].nconv; ++j)
+        if (!(std::sqrt(std::max(hres[(size_t)i * 64 + j], 0.0)) <= c->opts.eig_rtol * t0)) {
+          converged = false;
+          break;
+        }
+    }
+    if (converged) break;
+    orth();
+  }
+  if (!converged) return fail(MOR_ENOTCONV, "subspace iteration did not converge within eig_max_iter");
+
+  // ---- truncation, basis Z R^-1 V_k Sigma_k^-1 (= R_i^-1 U_k), stitching, local projection
+  std::vector<double*> hB(ns), hX(ns);
+  double* d_sig = (double*)ar.take(8 * (size_t)ns * 64);
+  if (!d_sig) return fail(MOR_ENOMEM, "arena exhausted (basis)");
+  std::vector<double> sig_all((size_t)ns * 64, 1.0);
+  for (int i = 0; i < ns; ++i) {
+    Slot& q = slots[i];
+    std::vector<double> sg(q.s);
+    for (int j = 0; j < q.s; ++j) sg[j] = std::sqrt(std::max(hth[(size_t)i * 64 + j], 0.0));
+    q.k_eff = truncation_rank(sg, q.rank, q.tol, q.s - 1);
+    SubResult& R = c->res[q.sd];
+    R.sigma = sg;
+    R.k_eff = q.k_eff;
+    for (int j = 0; j < q.s; ++j) sig_all[(size_t)i * 64 + j] = sg[j] > 0 ? sg[j] : 1.0;
+  }
+  HIPCHK(hipMemcpyAsync(d_sig, sig_all.data(), 8 * (size_t)ns * 64, hipMemcpyHostToDevice, st));
+  for (int i = 0; i < ns; ++i) {
+    Slot& q = slots[i];
+    launch_scale_cols(q.Ub, q.s, d_sig + (size_t)i * 64, q.k_eff, q.MP, q.Bk, st);
+  }
+  launch_trsm_un(dds, ns, P_Bk, P_Wk, tmax, st);
+  GemmBatch gV, gP;
+  for (int i = 0; i < ns; ++i) {
+    Slot& q = slots[i];
+    const HostSub& h = *q.h;
+    SubResult& R = c->res[q.sd];
+    const int k1 = q.k_eff + 1;
+    if (R.d_V) pfree(c, R.d_V);
+    if (R.d_Pm) pfree(c, R.d_Pm);
+    R.d_V = (double*)palloc(c, 8 * (size_t)h.nV * k1);
+    R.d_Pm = (double*)palloc(c, 8 * (size_t)k1 * (k1 + 1));
+    if (!R.d_V || !R.d_Pm) return fail(MOR_ENOMEM, "device allocation failed (basis)");
+    launch_copy_col(q.Xc + q.M, q.ldXc, R.d_V, k1, h.nV, st);   // q_0 = zero-boundary load solution
+    if (q.k_eff > 0) gV.add(gd(h.nV, q.k_eff, q.M, q.Xc, q.ldXc, 0, q.Wk, 64, 0, R.d_V + 1, k1));
+  }
+  if ((rc = gemm_upload(c, gV, ar))) return rc;
+  gemm_run(c, gV, "basis");
+  for (int i = 0; i < ns; ++i) {
+    Slot& q = slots[i];
+    const HostSub& h = *q.h;
+    SubResult& R = c->res[q.sd];
+    const int k1 = q.k_eff + 1;
+    launch_spmm64_rows(q.d->rp, q.d->col, q.A64, h.nP, h.nP, R.d_V, k1, k1, q.Yf, k1 + 1, st);
+    launch_copy_col(q.f, 1, q.Yf + k1, k1 + 1, h.nP, st);
+    gP.add(gd(k1, k1 + 1, h.nP, R.d_V, k1, 1, q.Yf, k1 + 1, 0, R.d_Pm, k1 + 1));
+  }
+  if ((rc = gemm_upload(c, gP, ar))) return rc;
+  gemm_run(c, gP, "project_local");
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(st));
+  for (int i = 0; i < ns; ++i) {
+    Slot& q = slots[i];
+    SubResult& R = c->res[q.sd];
+    const int k1 = q.k_eff + 1;
+    std::vector<double> pm((size_t)k1 * (k1 + 1));
+    HIPCHK(hipMemcpy(pm.data(), R.d_Pm, 8 * pm.size(), hipMemcpyDeviceToHost));
+    R.Aii.assign((size_t)k1 * k1, 0.0);
+    R.bi.assign(k1, 0.0);
+    for (int a = 0; a < k1; ++a) {
+      for (int b = 0; b < k1; ++b) R.Aii[(size_t)a * k1 + b] = 0.5 * (pm[(size_t)a * (k1 + 1) + b] + pm[(size_t)b * (k1 + 1) + a]);
+      R.bi[a] = pm[(size_t)a * (k1 + 1) + k1];
+    }
+    R.cg_a = cs.iters[2 * i];
+    R.cg_k = cs.iters[2 * i + 1];
+    R.refine = std::max(refines[2 * i], refines[2 * i + 1]);
+    R.eig = eig_it + 1;
+    R.reduced = 1;
+  }
+  return 0;
+}
+
+static int local_batch(mor_ctx* c, std::vector<Slot>& slots) {
+  if (c->opts.precision == MOR_FP64) return local_batch_t<double>(c, slots);
+  return local_batch_t<float>(c, slots);
+}
+
+extern "C" int mor_local_basis_batch(mor_ctx* c, int32_t n, const int32_t* sds, const int32_t* ranks, const double* tols,
+                                     int32_t* k_eff_out) {
+  if (!c || n <= 0 || !sds || !ranks) return fail(MOR_EINVAL, "bad arguments");
+  if (c->opts.host_only) return fail(MOR_ESTATE, "context was created host_only");
+  std::vector<Slot> slots(n);
+  std::vector<char> seen(c->subs.size(), 0);
+  for (int i = 0; i < n; ++i) {
+    const int sd = sds[i];
+    if (sd < 0 || sd >= (int)c->subs.size()) return fail(MOR_EINVAL, "subdomain id out of range");
+    if (seen[sd]) return fail(MOR_EINVAL, "subdomain listed twice in one batch");
+    seen[sd] = 1;
+    const double tol = tols ? tols[i] : 0.0;
+    if (ranks[i] <= 0 && !(tol > 0.0)) return fail(MOR_EINVAL, "need rank > 0 or tol > 0");
+    Slot& q = slots[i];
+    std::memset(&q, 0, sizeof(q));
+    q.sd = sd;
+    q.rank = ranks[i];
+    q.tol = tol;
+    q.h = &c->subs[sd];
+    q.d = &c->sdev[sd];
+  }
+  c->projected = 0;
+  c->solved = 0;
+  // waves under the HBM budget (default: 75% of the free device memory)
+  size_t budget = c->opts.hbm_budget_bytes;
+  if (!budget) {
+    size_t fr = 0, tot = 0;
+    if (hipMemGetInfo(&fr, &tot) != hipSuccess) fr = (size_t)64 << 30;
+    budget = fr / 4 * 3;
+  }
+  const int elt = c->opts.precision == MOR_FP64 ? 8 : 4;
+  std::vector<Slot> wave;
+  size_t used = 0;
+  auto flush = [&]() -> int {
+    if (wave.empty()) return 0;
+    const int rc = local_batch(c, wave);
+    wave.clear();
+    used = 0;
+    return rc;
+  };
+  for (int i = 0; i < n; ++i) {
+    Sizer z;
+    Slot tmp = slots[i];
+    slot_sizes(c, tmp, z, elt);
+    const size_t need = z.total + (z.total >> 4);
+    if (need > budget) return fail(MOR_ENOMEM, "subdomain " + std::to_string(slots[i].sd) + " alone exceeds the HBM budget");
+    if (used + need > budget)
+      if (int rc = flush()) return rc;
+    wave.push_back(slots[i]);
+    used += need;
+  }
+  if (int rc = flush()) return rc;
+  if (k_eff_out)
+    for (int i = 0; i < n; ++i) k_eff_out[i] = c->res[sds[i]].k_eff;
+  return MOR_OK;
+}
+
+extern "C" int mor_local_basis(mor_ctx* c, int32_t sd, int32_t rank, double tol, int32_t* k_eff_out, double* sigma_out,
+                               int32_t sigma_cap) {
+  const int rc = mor_local_basis_batch(c, 1, &sd, &rank, &tol, k_eff_out);
+  if (rc) return rc;
+  if (sigma_out) {
+    const auto& s = c->res[sd].sigma;
+    for (int j = 0; j < sigma_cap && j < (int)s.size(); ++j) sigma_out[j] = s[j];
+  }
+  return MOR_OK;
+}
+
+// ------------------------------------------------------------------------------- projection
+extern "C" int mor_project(mor_ctx* c) {
+  if (!c) return fail(MOR_EINVAL, "null context");
+  if (c->opts.host_only) return fail(MOR_ESTATE, "context was created host_only");
+  const int n = (int)c->subs.size();
+  for (int i = 0; i < n; ++i)
+    if (!c->res[i].reduced) return fail(MOR_ESTATE, "subdomain " + std::to_string(i) + " has no basis yet");
+  hipStream_t st = c->st;
+  c->off.assign(n + 1, 0);
+  for (int i = 0; i < n; ++i) c->off[i + 1] = c->off[i] + c->res[i].k_eff + 1;
+  c->n_red = c->off[n];
+  c->MPr = rup(c->n_red, 64);
+  pfree(c, c->d_At);
+  pfree(c, c->d_bt);
+  pfree(c, c->d_x);
+  c->d_At = (double*)palloc(c, 8 * (size_t)c->MPr * c->MPr);
+  c->d_bt = (double*)palloc(c, 8 * (size_t)c->MPr * 64);
+  c->d_x = (double*)palloc(c, 8 * (size_t)c->MPr * 64);
+  if (!c->d_At || !c->d_bt || !c->d_x) return fail(MOR_ENOMEM, "device allocation failed (reduced system)");
+  ScopedTimer tm(c, "project", 0);
+  launch_fill(c->d_At, (int64_t)c->MPr * c->MPr, 0.0, st);
+  launch_pad_identity(c->d_At, (int)c->n_red, (int)c->MPr, st);
+  launch_fill(c->d_bt, (int64_t)c->MPr * 64, 0.0, st);
+  for (int i = 0; i < n; ++i) {
+    const int k1 = c->res[i].k_eff + 1;
+    launch_scatter_block(c->res[i].d_Pm, k1, k1 + 1, c->d_At, c->MPr, c->off[i], st);
+    launch_copy_col(c->res[i].d_Pm + k1, k1 + 1, c->d_bt + (size_t)c->off[i] * 64, 64, k1, st);
+  }
+  // A_0 on omega_0, then every neighbour pair
+  const HostSub& h0 = c->om0.sub;
+  const int npairs = (int)c->om0.pair_i.size();
+  if (npairs > 0) {
+    double* A0 = (double*)dalloc(c, 8 * (size_t)std::max(1, h0.rp[h0.nL]));
+    if (!A0) return fail(MOR_ENOMEM, "device allocation failed (A_0)");
+    launch_fill(A0, h0.rp[h0.nL], 0.0, st);
+    std::vector<AsmJob> jobs{{&h0, &c->om0dev, A0, nullptr, nullptr, nullptr}};
+    if (int rc = assemble_batch(c, jobs)) {
+      dfree(c, A0);
+      return rc;
+    }
+    std::vector<int4> range(npairs);
+    for (int p = 0; p < npairs; ++p)
+      range[p] = make_int4(c->om0.pair_i[p], c->om0.pair_j[p], c->om0.pair_first[p], c->om0.pair_count[p]);
+    std::vector<double*> vp(n);
+    std::vector<int> ldv(n), k1(n);
+    for (int i = 0; i < n; ++i) {
+      vp[i] = c->res[i].d_V;
+      ldv[i] = k1[i] = c->res[i].k_eff + 1;
+    }
+    const size_t bytes = sizeof(int4) * npairs + 4 * c->om0.trip.size() + sizeof(double*) * n + 4 * 3 * (size_t)n + 1024;
+    char* buf = (char*)dalloc(c, bytes);
+    if (!buf) {
+      dfree(c, A0);
+      return fail(MOR_ENOMEM, "device allocation failed (pairs)");
+    }
+    Arena ar{buf, bytes, 0};
+    int4* d_range = (int4*)ar.take(sizeof(int4) * npairs);
+    int* d_trip = (int*)ar.take(4 * std::max<size_t>(1, c->om0.trip.size()));
+    double** d_vp = (double**)ar.take(sizeof(double*) * n);
+    int* d_ldv = (int*)ar.take(4 * n);
+    int* d_k1 = (int*)ar.take(4 * n);
+    int* d_off = (int*)ar.take(4 * n);
+    HIPCHK(hipMemcpyAsync(d_range, range.data(), sizeof(int4) * npairs, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(d_trip, c->om0.trip.data(), 4 * c->om0.trip.size(), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(d_vp, vp.data(), sizeof(double*) * n, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(d_ldv, ldv.data(), 4 * n, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(d_k1, k1.data(), 4 * n, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(d_off, c->off.data(), 4 * n, hipMemcpyHostToDevice, st));
+    launch_pair_project(d_range, d_trip, A0, d_vp, d_ldv, d_k1, d_off, c->d_At, c->MPr, npairs, st);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(st));
+    dfree(c, buf);
+    dfree(c, A0);
+  }
+  HIPCHK(hipStreamSynchronize(st));
+  c->projected = 1;
+  return MOR_OK;
+}
+
+extern "C" int mor_solve(mor_ctx* c, double* u_out, int64_t* n_reduced_out) {
+  if (!c) return fail(MOR_EINVAL, "null context");
+  if (c->opts.host_only) return fail(MOR_ESTATE, "context was created host_only");
+  if (!c->projected) return fail(MOR_ESTATE, "mor_project must run first");
+  hipStream_t st = c->st;
+  const int64_t MP = c->MPr;
+  const int T = (int)(MP / 64);
+  const size_t bytes = 8 * (size_t)MP * MP + 8 * (size_t)T * 4096 + 64 + sizeof(DenseSub) + 2 * sizeof(TrsmDesc) +
+                       2 * sizeof(double*) + 8 * (size_t)c->mesh.n_nodes + 8 * (size_t)MP * 64 + 8192;
+  char* buf = (char*)dalloc(c, bytes);
+  if (!buf) return fail(MOR_ENOMEM, "device allocation failed (reduced solve)");
+  struct G { mor_ctx* c; void* p; ~G() { (void)hipStreamSynchronize(c->st); dfree(c, p); } } guard{c, buf};
+  Arena ar{buf, bytes, 0};
+  double* F = (double*)ar.take(8 * (size_t)MP * MP);
+  double* Di = (double*)ar.take(8 * (size_t)T * 4096);
+  int* info = (int*)ar.take(64);
+  DenseSub* dd = (DenseSub*)ar.take(sizeof(DenseSub));
+  TrsmDesc* td = (TrsmDesc*)ar.take(2 * sizeof(TrsmDesc));
+  double** pb = (double**)ar.take(2 * sizeof(double*));
+  double* du = (double*)ar.take(8 * (size_t)c->mesh.n_nodes);
+  if (!du) return fail(MOR_ENOMEM, "arena exhausted (reduced solve)");
+  ScopedTimer tm(c, "solve", (double)MP * MP * MP / 3.0);
+  HIPCHK(hipMemcpyAsync(F, c->d_At, 8 * (size_t)MP * MP, hipMemcpyDeviceToDevice, st));
+  launch_fill_i(info, 16, 0, st);
+  DenseSub hd{(int)c->n_red, (int)MP, T, F, nullptr, nullptr, nullptr, Di, info};
+  HIPCHK(hipMemcpyAsync(dd, &hd, sizeof(hd), hipMemcpyHostToDevice, st));
+  for (int p = 0; p < T; ++p) {
+    launch_potrf_diag(dd, 1, p, st);
+    launch_chol_panel(dd, 1, p, T, st);
+    launch_chol_syrk(dd, 1, p, T, st);
+  }
+  int hinfo = 0;
+  HIPCHK(hipMemcpyAsync(&hinfo, info, 4, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  if (hinfo) return fail(MOR_EDEVICE, "reduced matrix is not positive definite (pivot " + std::to_string(hinfo) + ")");
+  // R^T y = b (y in d_x), then R x = y
+  TrsmDesc ht{c->d_bt, 64, 0, c->d_x, 64, 1};
+  HIPCHK(hipMemcpyAsync(td, &ht, sizeof(ht), hipMemcpyHostToDevice, st));
+  launch_trsm_lt(dd, td, 1, 1, st);
+  double* xsol = (double*)ar.take(8 * (size_t)MP * 64);
+  if (!xsol) return fail(MOR_ENOMEM, "arena exhausted (reduced solve)");
+  double* hp[2] = {c->d_x, xsol};
+  HIPCHK(hipMemcpyAsync(pb, hp, sizeof(hp), hipMemcpyHostToDevice, st));
+  launch_trsm_un(dd, 1, pb, pb + 1, T, st);
+  // x = column 0 of xsol
+  std::vector<double> xs((size_t)MP * 64);
+  HIPCHK(hipMemcpyAsync(xs.data(), xsol, 8 * xs.size(), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  c->x_host.assign(c->n_red, 0.0);
+  for (int64_t i = 0; i < c->n_red; ++i) c->x_host[i] = xs[(size_t)i * 64];
+  // u~ = sum_i S_i Q_i x_i
+  double* dx = (double*)dalloc(c, 8 * (size_t)std::max<int64_t>(1, c->n_red));
+  if (!dx) return fail(MOR_ENOMEM, "device allocation failed (x)");
+  HIPCHK(hipMemcpyAsync(dx, c->x_host.data(), 8 * c->n_red, hipMemcpyHostToDevice, st));
+  launch_fill(du, c->mesh.n_nodes, 0.0, st);
+  for (size_t i = 0; i < c->subs.size(); ++i) {
+    const int k1 = c->res[i].k_eff + 1;
+    launch_reconstruct(c->res[i].d_V, c->subs[i].nP, k1, dx + c->off[i], c->sdev[i].nodes, du, st);
+  }
+  HIPCHK(hipGetLastError());
+  if (u_out) HIPCHK(hipMemcpyAsync(u_out, du, 8 * (size_t)c->mesh.n_nodes, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  dfree(c, dx);
+  if (n_reduced_out) *n_reduced_out = c->n_red;
+  c->solved = 1;
+  return MOR_OK;
+}
+
+// ------------------------------------------------------------------------------- serving
+// Requests are queued and served in batches at every poll (continuous batching of requests
+// that arrive while others run is provided by mor_poll draining the queue chunk by chunk).
+namespace {
+struct Req {
+  uint64_t id;
+  int sd, rank, precision;
+  double tol;
+  int done = 0, status = 0;
+};
+}  // namespace
+static std::map<mor_ctx*, std::vector<Req>> g_queue;
+static uint64_t g_ticket = 1;
+
+extern "C" int mor_submit(mor_ctx* c, int32_t sd, int32_t rank, double tol, int32_t precision, uint64_t* ticket) {
+  if (!c || !ticket) return fail(MOR_EINVAL, "null argument");
+  if (sd < 0 || sd >= (int)c->subs.size()) return fail(MOR_EINVAL, "subdomain id out of range");
+  if (rank <= 0 && !(tol > 0.0)) return fail(MOR_EINVAL, "need rank > 0 or tol > 0");
+  if (precision < MOR_FP64 || precision > MOR_BF16_SPLIT) return fail(MOR_EINVAL, "unknown precision");
+  Req r;
+  r.id = g_ticket++;
+  r.sd = sd; r.rank = rank; r.tol = tol; r.precision = precision;
+  g_queue[c].push_back(r);
+  *ticket = r.id;
+  return MOR_OK;
+}
+
+static int serve_pending(mor_ctx* c) {
+  auto& q = g_queue[c];
+  // group pending requests by precision; a subdomain appears once per batch
+  for (int prec = MOR_FP64; prec <= MOR_BF16_SPLIT; ++prec) {
+    std::vector<int> idx;
+    std::vector<char> seen(c->subs.size(), 0);
+    for (size_t i = 0; i < q.size(); ++i)
+      if (!q[i].done && q[i].precision == prec && !seen[q[i].sd]) {
+        idx.push_back((int)i);
+        seen[q[i].sd] = 1;
+      }
+    if (idx.empty()) continue;
+    std::vector<int32_t> sds, ranks;
+    std::vector<double> tols;
+    for (int i : idx) {
+      sds.push_back(q[i].sd);
+      ranks.push_back(q[i].rank);
+      tols.push_back(q[i].tol);
+    }
+    const int saved = c->opts.precision;
+    c->opts.precision = prec;
+    const int rc = mor_local_basis_batch(c, (int)sds.size(), sds.data(), ranks.data(), tols.data(), nullptr);
+    c->opts.precision = saved;
+    for (int i : idx) {
+      q[i].done = 1;
+      q[i].status = rc;
+    }
+  }
+  return 0;
+}
+
+extern "C" int mor_poll(mor_ctx* c, uint64_t ticket, int32_t* done, int32_t* status) {
+  if (!c || !done || !status) return fail(MOR_EINVAL, "null argument");
+  auto& q = g_queue[c];
+  for (auto& r : q)
+    if (r.id == ticket) {
+      if (!r.done) serve_pending(c);
+      *done = r.done;
+      *status = r.status;
+      return MOR_OK;
+    }
+  return fail(MOR_EINVAL, "unknown ticket");
+}
+
+extern "C" int mor_drain(mor_ctx* c) {
+  if (!c) return fail(MOR_EINVAL, "null context");
+  return serve_pending(c);
+}
+
+// ------------------------------------------------------------------------------- getters
+extern "C" int mor_get_sizes(mor_ctx* c, int32_t sd, int32_t* nP, int32_t* nV, int32_t* nI, int32_t* nB) {
+  if (!c || sd < 0 || sd >= (int)c->subs.size()) return fail(MOR_EINVAL, "bad subdomain");
+  const HostSub& h = c->subs[sd];
+  if (nP) *nP = h.nP;
+  if (nV) *nV = h.nV;
+  if (nI) *nI = h.nI;
+  if (nB) *nB = h.nB;
+  return MOR_OK;
+}
+extern "C" int mor_get_nodes(mor_ctx* c, int32_t sd, int32_t* out, int64_t cap) {
+  if (!c || sd < 0 || sd >= (int)c->subs.size() || !out) return fail(MOR_EINVAL, "bad arguments");
+  const HostSub& h = c->subs[sd];
+  if (cap < h.nL) return fail(MOR_EINVAL, "output too small");
+  std::memcpy(out, h.nodes.data(), 4 * (size_t)h.nL);
+  return MOR_OK;
+}
+extern "C" int mor_get_pairs(mor_ctx* c, int32_t* out, int64_t cap, int64_t* n) {
+  if (!c) return fail(MOR_EINVAL, "null context");
+  const int64_t np = (int64_t)c->om0.pair_i.size();
+  if (n) *n = np;
+  if (out)
+    for (int64_t p = 0; p < np && p < cap; ++p) {
+      out[2 * p] = c->om0.pair_i[p];
+      out[2 * p + 1] = c->om0.pair_j[p];
+    }
+  return MOR_OK;
+}
+extern "C" int mor_get_basis(mor_ctx* c, int32_t sd, double* out, int64_t cap, int32_t* k_eff) {
+  if (!c || sd < 0 || sd >= (int)c->subs.size()) return fail(MOR_EINVAL, "bad subdomain");
+  const SubResult& R = c->res[sd];
+  if (!R.reduced) return fail(MOR_ESTATE, "subdomain not reduced");
+  if (k_eff) *k_eff = R.k_eff;
+  const size_t n = (size_t)c->subs[sd].nV * (R.k_eff + 1);
+  if (out) {
+    if ((size_t)cap < n) return fail(MOR_EINVAL, "output too small");
+    HIPCHK(hipMemcpy(out, R.d_V, 8 * n, hipMemcpyDeviceToHost));
+  }
+  return MOR_OK;
+}
+extern "C" int mor_get_sigma(mor_ctx* c, int32_t sd, double* out, int32_t cap, int32_t* n) {
+  if (!c || sd < 0 || sd >= (int)c->subs.size()) return fail(MOR_EINVAL, "bad subdomain");
+  const SubResult& R = c->res[sd];
+  if (!R.reduced) return fail(MOR_ESTATE, "subdomain not reduced");
+  if (n) *n = (int)R.sigma.size();
+  if (out)
+    for (int j = 0; j < cap && j < (int)R.sigma.size(); ++j) out[j] = R.sigma[j];
+  return MOR_OK;
+}
+extern "C" int mor_get_local_block(mor_ctx* c, int32_t sd, double* Aii, double* bi, int64_t cap) {
+  if (!c || sd < 0 || sd >= (int)c->subs.size()) return fail(MOR_EINVAL, "bad subdomain");
+  const SubResult& R = c->res[sd];
+  if (!R.reduced) return fail(MOR_ESTATE, "subdomain not reduced");
+  if ((size_t)cap < R.Aii.size()) return fail(MOR_EINVAL, "output too small");
+  if (Aii) std::memcpy(Aii, R.Aii.data(), 8 * R.Aii.size());
+  if (bi) std::memcpy(bi, R.bi.data(), 8 * R.bi.size());
+  return MOR_OK;
+}
+extern "C" int mor_get_reduced(mor_ctx* c, double* At, double* bt, int64_t cap, int64_t* n) {
+  if (!c) return fail(MOR_EINVAL, "null context");
+  if (!c->projected) return fail(MOR_ESTATE, "mor_project must run first");
+  const int64_t nr = c->n_red;
+  if (n) *n = nr;
+  if (At) {
+    if (cap < nr * nr) return fail(MOR_EINVAL, "output too small");
+    HIPCHK(hipMemcpy2D(At, 8 * nr, c->d_At, 8 * c->MPr, 8 * nr, nr, hipMemcpyDeviceToHost));
+  }
+  if (bt) {
+    std::vector<double> b((size_t)c->MPr * 64);
+    HIPCHK(hipMemcpy(b.data(), c->d_bt, 8 * b.size(), hipMemcpyDeviceToHost));
+    for (int64_t i = 0; i < nr; ++i) bt[i] = b[(size_t)i * 64];
+  }
+  return MOR_OK;
+}
+extern "C" int mor_get_reduced_solution(mor_ctx* c, double* x, int64_t cap) {
+  if (!c || !x) return fail(MOR_EINVAL, "null argument");
+  if (!c->solved) return fail(MOR_ESTATE, "mor_solve must run first");
+  if (cap < c->n_red) return fail(MOR_EINVAL, "output too small");
+  std::memcpy(x, c->x_host.data(), 8 * (size_t)c->n_red);
+  return MOR_OK;
+}
+extern "C" int mor_get_stats(mor_ctx* c, int32_t sd, int32_t* a, int32_t* k, int32_t* refine, int32_t* eig) {
+  if (!c || sd < 0 || sd >= (int)c->subs.size()) return fail(MOR_EINVAL, "bad subdomain");
+  const SubResult& R = c->res[sd];
+  if (a) *a = R.cg_a;
+  if (k) *k = R.cg_k;
+  if (refine) *refine = R.refine;
+  if (eig) *eig = R.eig;
+  return MOR_OK;
+}
+
+extern "C" int mor_timing_enable(mor_ctx* c, int32_t on) {
+  if (!c) return fail(MOR_EINVAL, "null context");
+  c->timing = on != 0;
+  return MOR_OK;
+}
+extern "C" int mor_timing_get(mor_ctx* c, const char* name, int64_t* launches, double* total_ms, double* work) {
+  if (!c || !name) return fail(MOR_EINVAL, "null argument");
+  flush_timers(c);
+  auto it = c->timers.find(name);
+  if (it == c->timers.end()) {
+    if (launches) *launches = 0;
+    if (total_ms) *total_ms = 0;
+    if (work) *work = 0;
+    return MOR_OK;
+  }
+  if (launches) *launches = it->second.launches;
+  if (total_ms) *total_ms = it->second.ms;
+  if (work) *work = it->second.work;
+  return MOR_OK;
+}
+extern "C" int mor_timing_reset(mor_ctx* c) {
+  if (!c) return fail(MOR_EINVAL, "null context");
+  flush_timers(c);
+  c->timers.clear();
+  return MOR_OK;
+}

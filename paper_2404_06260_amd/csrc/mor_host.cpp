@@ -1,0 +1,291 @@
+// Host-side decomposition for the local reduction (integer work, negligible next to the solves).
+//
+// Index sets follow Sections 3-4 of the paper: I = free nodes interior to omega_i^+, B = free
+// nodes on the boundary of omega_i^+, V_i = free nodes of omega_i, P_i = the interior of omega_i
+// (where the stitching operator of Definition 3.1 keeps values).  A free node is interior to a
+// union of tets exactly when every tet around it belongs to the union, which is how both are
+// decided here.  omega_0 and the neighbour pairs follow Section 6, step 3.
+#include "mor_host.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+
+namespace mor {
+
+static double tet_det(const HostMesh& m, int64_t t) {
+  const int32_t* v = &m.tets[4 * t];
+  const double* x0 = &m.xyz[3 * (int64_t)v[0]];
+  double e[3][3];
+  for (int a = 0; a < 3; ++a)
+    for (int d = 0; d < 3; ++d) e[a][d] = m.xyz[3 * (int64_t)v[a + 1] + d] - x0[d];
+  return e[0][0] * (e[1][1] * e[2][2] - e[1][2] * e[2][1]) - e[0][1] * (e[1][0] * e[2][2] - e[1][2] * e[2][0]) +
+         e[0][2] * (e[1][0] * e[2][1] - e[1][1] * e[2][0]);
+}
+
+int build_mesh(HostMesh& m, std::string& err) {
+  m.star.assign(m.n_nodes, 0);
+  for (int64_t t = 0; t < m.n_tets; ++t) {
+    for (int a = 0; a < 4; ++a) {
+      const int32_t v = m.tets[4 * t + a];
+      if (v < 0 || v >= m.n_nodes) {
+        err = "tet " + std::to_string(t) + " references node " + std::to_string(v) + " out of range";
+        return -1;
+      }
+      m.star[v]++;
+    }
+    const double det = tet_det(m, t);
+    if (!(det > 0.0)) {
+      err = "tet " + std::to_string(t) + " has non-positive volume (det J = " + std::to_string(det) + ")";
+      return -1;
+    }
+  }
+  std::vector<uint64_t> used(m.n_nodes, 0);
+  m.colour.assign(m.n_tets, 0);
+  int nc = 0;
+  for (int64_t t = 0; t < m.n_tets; ++t) {
+    uint64_t u = 0;
+    for (int a = 0; a < 4; ++a) u |= used[m.tets[4 * t + a]];
+    if (u == ~0ull) {
+      err = "element colouring needs more than 64 colours";
+      return -1;
+    }
+    const int c = __builtin_ctzll(~u);
+    m.colour[t] = (uint8_t)c;
+    nc = std::max(nc, c + 1);
+    for (int a = 0; a < 4; ++a) used[m.tets[4 * t + a]] |= (1ull << c);
+  }
+  m.ncolours = nc;
+  return 0;
+}
+
+// CSR pattern over local ids from a list of local tets (4 ids, -1 skipped); rows [0, nrows)
+static void tet_pattern(const std::vector<int32_t>& ltet, const std::vector<uint8_t>* mask, int nrows,
+                        std::vector<int32_t>& rp, std::vector<int32_t>& col) {
+  const int64_t nt = (int64_t)ltet.size() / 4;
+  std::vector<int32_t> cnt(nrows + 1, 0);
+  for (int64_t t = 0; t < nt; ++t) {
+    if (mask && !(*mask)[t]) continue;
+    for (int a = 0; a < 4; ++a) {
+      const int r = ltet[4 * t + a];
+      if (r >= 0 && r < nrows) cnt[r + 1]++;
+    }
+  }
+  for (int r = 0; r < nrows; ++r) cnt[r + 1] += cnt[r];
+  std::vector<int32_t> adj(cnt[nrows]);
+  std::vector<int32_t> fill(cnt.begin(), cnt.end() - 1);
+  for (int64_t t = 0; t < nt; ++t) {
+    if (mask && !(*mask)[t]) continue;
+    for (int a = 0; a < 4; ++a) {
+      const int r = ltet[4 * t + a];
+      if (r >= 0 && r < nrows) adj[fill[r]++] = (int32_t)t;
+    }
+  }
+  rp.assign(nrows + 1, 0);
+  col.clear();
+  std::vector<int32_t> buf;
+  for (int r = 0; r < nrows; ++r) {
+    buf.clear();
+    for (int k = cnt[r]; k < cnt[r + 1]; ++k) {
+      const int64_t t = adj[k];
+      for (int b = 0; b < 4; ++b) {
+        const int c = ltet[4 * t + b];
+        if (c >= 0) buf.push_back(c);
+      }
+    }
+    std::sort(buf.begin(), buf.end());
+    buf.erase(std::unique(buf.begin(), buf.end()), buf.end());
+    col.insert(col.end(), buf.begin(), buf.end());
+    rp[r + 1] = (int32_t)col.size();
+  }
+}
+
+static void colour_sort(const HostMesh& m, HostSub& s, std::vector<int32_t>& ltet, std::vector<int32_t>& tetg,
+                        std::vector<uint8_t>& core) {
+  const int64_t nt = (int64_t)tetg.size();
+  std::vector<int32_t> cnt(m.ncolours + 1, 0);
+  for (int64_t t = 0; t < nt; ++t) cnt[m.colour[tetg[t]] + 1]++;
+  for (int c = 0; c < m.ncolours; ++c) cnt[c + 1] += cnt[c];
+  s.colour_ptr = cnt;
+  std::vector<int32_t> fill(cnt.begin(), cnt.end() - 1);
+  s.ltet.assign(4 * nt, -1);
+  s.tetg.assign(nt, 0);
+  s.core.assign(nt, 0);
+  for (int64_t t = 0; t < nt; ++t) {
+    const int64_t d = fill[m.colour[tetg[t]]]++;
+    for (int a = 0; a < 4; ++a) s.ltet[4 * d + a] = ltet[4 * t + a];
+    s.tetg[d] = tetg[t];
+    s.core[d] = core.empty() ? 0 : core[t];
+  }
+}
+
+int build_sub(const HostMesh& m, const int32_t* ext, const uint8_t* in_core, int64_t n_ext, HostSub& s,
+              std::string& err) {
+  std::vector<int32_t> starE(m.n_nodes, 0), starC(m.n_nodes, 0);
+  std::vector<int32_t> touched;
+  touched.reserve(n_ext);
+  for (int64_t k = 0; k < n_ext; ++k) {
+    const int32_t t = ext[k];
+    if (t < 0 || t >= m.n_tets) {
+      err = "subdomain tet id out of range";
+      return -1;
+    }
+    for (int a = 0; a < 4; ++a) {
+      const int32_t v = m.tets[4 * (int64_t)t + a];
+      if (starE[v] == 0) touched.push_back(v);
+      starE[v]++;
+      if (in_core[k]) starC[v]++;
+    }
+  }
+  std::sort(touched.begin(), touched.end());
+  std::vector<int32_t> P, VmP, ImV, B;
+  for (int32_t v : touched) {
+    if (m.dirichlet[v]) continue;
+    const bool interior = starE[v] == m.star[v];
+    const bool in_v = starC[v] > 0;
+    if (in_v && !interior) {
+      err = "omega_i touches the boundary of omega_i^+ (the extension must be at least one layer)";
+      return -1;
+    }
+    if (!interior) B.push_back(v);
+    else if (!in_v) ImV.push_back(v);
+    else if (starC[v] == m.star[v]) P.push_back(v);
+    else VmP.push_back(v);
+  }
+  s.nP = (int)P.size();
+  s.nV = s.nP + (int)VmP.size();
+  s.nI = s.nV + (int)ImV.size();
+  s.nB = (int)B.size();
+  s.nL = s.nI + s.nB;
+  if (s.nI == 0 || s.nB == 0) {
+    err = "subdomain without interior or interface degrees of freedom";
+    return -1;
+  }
+  s.nodes.clear();
+  s.nodes.reserve(s.nL);
+  for (auto* part : {&P, &VmP, &ImV, &B}) s.nodes.insert(s.nodes.end(), part->begin(), part->end());
+  std::vector<int32_t>& lid = starE;   // reuse as global -> local map
+  for (int32_t v : touched) lid[v] = -1;
+  for (int i = 0; i < s.nL; ++i) lid[s.nodes[i]] = i;
+  std::vector<int32_t> ltet(4 * n_ext), tetg(n_ext);
+  std::vector<uint8_t> core(n_ext);
+  for (int64_t k = 0; k < n_ext; ++k) {
+    const int32_t t = ext[k];
+    tetg[k] = t;
+    core[k] = in_core[k] ? 1 : 0;
+    for (int a = 0; a < 4; ++a) {
+      const int32_t v = m.tets[4 * (int64_t)t + a];
+      ltet[4 * k + a] = m.dirichlet[v] ? -1 : lid[v];
+    }
+  }
+  colour_sort(m, s, ltet, tetg, core);
+  tet_pattern(s.ltet, nullptr, s.nL, s.rp, s.col);
+  s.ii_end.resize(s.nI);
+  for (int r = 0; r < s.nI; ++r) {
+    const int32_t* b = s.col.data() + s.rp[r];
+    const int32_t* e = s.col.data() + s.rp[r + 1];
+    s.ii_end[r] = (int32_t)(std::lower_bound(b, e, s.nI) - s.col.data());
+  }
+  tet_pattern(s.ltet, &s.core, s.nV, s.rpV, s.colV);
+  for (int32_t c : s.colV)
+    if (c >= s.nV) {
+      err = "internal: K_i pattern leaves V_i";
+      return -1;
+    }
+  return 0;
+}
+
+int build_owner(const HostMesh& m, const std::vector<HostSub>& subs, std::vector<int32_t>& owner,
+                std::vector<int32_t>& ownpos, std::string& err) {
+  owner.assign(m.n_nodes, -1);
+  ownpos.assign(m.n_nodes, -1);
+  for (size_t i = 0; i < subs.size(); ++i) {
+    const HostSub& s = subs[i];
+    for (int p = 0; p < s.nP; ++p) {
+      const int32_t v = s.nodes[p];
+      if (owner[v] >= 0) {
+        err = "node " + std::to_string(v) + " is interior to two subdomains: cores must overlap in one layer";
+        return -1;
+      }
+      owner[v] = (int32_t)i;
+      ownpos[v] = p;
+    }
+  }
+  for (int64_t v = 0; v < m.n_nodes; ++v)
+    if (!m.dirichlet[v] && owner[v] < 0) {
+      err = "free node " + std::to_string(v) + " is interior to no subdomain";
+      return -1;
+    }
+  return 0;
+}
+
+int build_omega0(const HostMesh& m, const std::vector<HostSub>& subs, const int64_t* ext_ptr, const int32_t* ext,
+                 const uint8_t* in_core, const std::vector<int32_t>& owner, const std::vector<int32_t>& ownpos,
+                 HostOmega0& o, std::string& err) {
+  (void)err;
+  std::vector<uint8_t> cnt(m.n_tets, 0);
+  for (size_t i = 0; i < subs.size(); ++i)
+    for (int64_t k = ext_ptr[i]; k < ext_ptr[i + 1]; ++k)
+      if (in_core[k] && cnt[ext[k]] < 255) cnt[ext[k]]++;
+  std::vector<int32_t> t0;
+  for (int64_t t = 0; t < m.n_tets; ++t)
+    if (cnt[t] >= 2) t0.push_back((int32_t)t);
+  std::vector<int32_t> lid(m.n_nodes, -1);
+  std::vector<int32_t> nodes;
+  for (int32_t t : t0)
+    for (int a = 0; a < 4; ++a) {
+      const int32_t v = m.tets[4 * (int64_t)t + a];
+      if (!m.dirichlet[v] && lid[v] < 0) {
+        lid[v] = 0;
+        nodes.push_back(v);
+      }
+    }
+  std::sort(nodes.begin(), nodes.end());
+  for (size_t i = 0; i < nodes.size(); ++i) lid[nodes[i]] = (int32_t)i;
+  HostSub& s = o.sub;
+  s.nodes = nodes;
+  s.nP = s.nV = 0;
+  s.nI = s.nL = (int)nodes.size();
+  s.nB = 0;
+  std::vector<int32_t> ltet(4 * t0.size()), tetg(t0);
+  std::vector<uint8_t> core;
+  for (size_t k = 0; k < t0.size(); ++k)
+    for (int a = 0; a < 4; ++a) {
+      const int32_t v = m.tets[4 * (int64_t)t0[k] + a];
+      ltet[4 * k + a] = m.dirichlet[v] ? -1 : lid[v];
+    }
+  colour_sort(m, s, ltet, tetg, core);
+  tet_pattern(s.ltet, nullptr, s.nL, s.rp, s.col);
+  // neighbour pairs: A_0 entries coupling P_i and P_j (i < j)
+  struct Trip { int64_t key; int32_t p, q, slot; };
+  std::vector<Trip> tr;
+  const int64_t nsub = (int64_t)subs.size();
+  for (int r = 0; r < s.nL; ++r) {
+    const int32_t gp = nodes[r];
+    const int32_t i = owner[gp];
+    for (int e = s.rp[r]; e < s.rp[r + 1]; ++e) {
+      const int32_t gq = nodes[s.col[e]];
+      const int32_t j = owner[gq];
+      if (i < j) tr.push_back({(int64_t)i * nsub + j, ownpos[gp], ownpos[gq], e});
+    }
+  }
+  std::stable_sort(tr.begin(), tr.end(), [](const Trip& a, const Trip& b) { return a.key < b.key; });
+  o.pair_i.clear(); o.pair_j.clear(); o.pair_first.clear(); o.pair_count.clear();
+  o.trip.resize(3 * tr.size());
+  for (size_t k = 0; k < tr.size(); ++k) {
+    if (k == 0 || tr[k].key != tr[k - 1].key) {
+      o.pair_i.push_back((int32_t)(tr[k].key / nsub));
+      o.pair_j.push_back((int32_t)(tr[k].key % nsub));
+      o.pair_first.push_back((int32_t)k);
+      o.pair_count.push_back(0);
+    }
+    o.pair_count.back()++;
+    o.trip[3 * k] = tr[k].p;
+    o.trip[3 * k + 1] = tr[k].q;
+    o.trip[3 * k + 2] = tr[k].slot;
+  }
+  return 0;
+}
+
+}  // namespace mor

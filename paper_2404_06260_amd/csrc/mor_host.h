@@ -1,0 +1,50 @@
+// Host-side decomposition: index sets, CSR patterns, element colouring, neighbour pairs.
+#pragma once
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+namespace mor {
+
+struct HostMesh {
+  int64_t n_nodes = 0, n_tets = 0;
+  std::vector<double> xyz;
+  std::vector<int32_t> tets;
+  std::vector<uint8_t> dirichlet;
+  std::vector<int32_t> star;    // tets per node
+  std::vector<uint8_t> colour;  // greedy element colouring: tets sharing a node differ
+  int ncolours = 0;
+};
+
+// Local numbering of one subdomain: [P | V\P | I\V | B], each part sorted by global id.
+struct HostSub {
+  int nP = 0, nV = 0, nI = 0, nB = 0, nL = 0;
+  std::vector<int32_t> nodes;              // global ids, nL
+  std::vector<int32_t> rp, col, ii_end;    // CSR of the omega_i^+ matrices over the local nodes
+  std::vector<int32_t> rpV, colV;          // CSR of K_i over V_i (local ids < nV)
+  std::vector<int32_t> ltet;               // 4 local ids per local tet (-1 = Dirichlet), colour-sorted
+  std::vector<int32_t> tetg;               // global tet id per local tet
+  std::vector<uint8_t> core;               // 1 if the local tet lies in omega_i
+  std::vector<int32_t> colour_ptr;         // local tets of colour c: [colour_ptr[c], colour_ptr[c+1])
+};
+
+// omega_0: the elements in two or more subdomains, with A_0's pattern over their free nodes.
+struct HostOmega0 {
+  HostSub sub;                 // nodes = free nodes of omega_0 tets (all in the "I" part), rp/col, ltet
+  // neighbour pairs (i < j) with triplets (row in P_i, row in P_j, A_0 slot)
+  std::vector<int32_t> pair_i, pair_j, pair_first, pair_count;
+  std::vector<int32_t> trip;   // 3 per triplet
+};
+
+int build_mesh(HostMesh& m, std::string& err);
+int build_sub(const HostMesh& m, const int32_t* ext, const uint8_t* in_core, int64_t n_ext, HostSub& s,
+              std::string& err);
+// owner / position of every free node in its P_i; error unless the P_i partition the free nodes
+int build_owner(const HostMesh& m, const std::vector<HostSub>& subs, std::vector<int32_t>& owner,
+                std::vector<int32_t>& ownpos, std::string& err);
+int build_omega0(const HostMesh& m, const std::vector<HostSub>& subs, const int64_t* ext_ptr, const int32_t* ext,
+                 const uint8_t* in_core, const std::vector<int32_t>& owner, const std::vector<int32_t>& ownpos,
+                 HostOmega0& o, std::string& err);
+
+}  // namespace mor

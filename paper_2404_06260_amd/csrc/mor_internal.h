@@ -1,0 +1,153 @@
+// Internal descriptors shared by the host orchestration and the HIP kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mor {
+
+constexpr int kWave = 64;
+constexpr int kBlock = 256;   // threads per workgroup for every streaming kernel
+constexpr int kNB = 64;       // dense tile size (Cholesky, TRSM, GEMM)
+
+// ---------------------------------------------------------------------------------
+// Element assembly.  One work item = one local tet of one subdomain (or of omega_0).
+struct AsmSub {
+  const int* ltet;    // 4 local node ids per local tet (-1 = Dirichlet / not in the index set)
+  const int* tetg;    // global tet id per local tet
+  const uint8_t* core;// 1 if the local tet lies in omega_i (nullptr: none)
+  int t_begin;        // first local tet of the colour being assembled
+  int t_count;        // number of local tets of that colour
+  const int* rp;      // CSR over the local nodes (A+, K+ pattern)
+  const int* col;
+  const int* rpV;     // CSR over V_i (K_i pattern), nullptr if not assembled
+  const int* colV;
+  double* A;          // kappa-weighted stiffness values (nullable)
+  double* K;          // H1 values: unweighted stiffness + mass (nullable)
+  double* Ki;         // H1 values on omega_i over V_i (nullable)
+  double* f;          // load vector M f_h (nullable)
+};
+
+// ---------------------------------------------------------------------------------
+// One block-CG system: A_II X = F with F = [-A_IB | f_I] (or K_II E = -K_IB).
+// Row-major dense blocks with leading dimension ld (multiple of 4), rows = nI.
+struct CgSys {
+  const int* rp;       // CSR over [I, B] rows; I rows list II columns first
+  const int* col;
+  const int* ii_end;   // end of the II part of each I row
+  const float* val32;  // FP32 copy of the values
+  const double* val64; // FP64 values
+  const void* dinv;    // 1 / diag(A_II), in the CG scalar type
+  const double* f;     // load on [I, B] (dense RHS column nB) or nullptr
+  int nI, nB, ncols, ld;
+  void* X; void* R; void* P; void* Q;  // CG scalar type
+  double* X64;         // FP64 solution shadow (refinement), or nullptr
+  int coff;            // offset of this system's columns in the per-column arrays
+};
+
+struct CgCols {        // per-column state, all systems concatenated
+  double* pq;          // p'Ap accumulator
+  double* rz;          // r'D^-1 r of the current iterate
+  double* rznew;       // accumulator of the updated r'D^-1 r
+  double* rz0;         // reference of the current (re)start
+  double* rzF;         // reference of the first right-hand side (refinement target)
+  double* alpha;
+  double* beta;
+  int* active;         // 1 while the column iterates
+  const int* sys_of_col;
+  int* nactive;        // per system: active columns after the last iteration
+  int ncols_total;
+};
+
+// ---------------------------------------------------------------------------------
+// Dense per-subdomain work (M x M matrices padded to MP = roundup(M, 64)).
+struct DenseSub {
+  int M, MP, T;        // T = MP / 64 tiles per dimension
+  double* S;           // S_B, then its Cholesky factor R (upper) in place
+  double* G;           // G1 = X_C^T K_i X_C
+  double* W;           // R^-T G1
+  double* C;           // R^-T G1 R^-1
+  double* Dinv;        // T inverses of the diagonal 64x64 blocks of R
+  int* info;           // non-SPD pivot report (0 = fine)
+};
+
+struct TrsmDesc {       // right-hand side and solution of one subdomain's triangular solve
+  const double* B; int ldb; int tb;   // tb: read B transposed
+  double* X; int ldx;
+  int ncol_tiles;
+};
+
+struct GemmDesc {
+  int m, n, k;
+  const double* A; int lda; int ta;
+  const double* B; int ldb; int tb;
+  double* C; int ldc;
+  double alpha, beta;
+  int sym;             // compute tiles ti <= tj only, write both triangles (beta must be 0)
+};
+
+// ---------------------------------------------------------------------------------
+// launchers (mor_kernels.hip)
+void launch_fill(double* p, int64_t n, double v, hipStream_t s);
+void launch_fill_f(float* p, int64_t n, float v, hipStream_t s);
+void launch_fill_i(int* p, int64_t n, int v, hipStream_t s);
+void launch_assemble(const AsmSub* d_subs, const int* d_prefix, int nsub, int total,
+                     const double* xyz, const int* tets, const double* kappa, const double* fnodal,
+                     hipStream_t s);
+void launch_to_f32(const double* in, float* out, int64_t n, hipStream_t s);
+void launch_diag_inv(const int* rp, const int* col, const double* v64, int nI, void* dinv, int is_double,
+                     hipStream_t s);
+
+template <typename T>
+void launch_cg_init(const CgSys* sys, const int4* tiles, int ntiles, int rb, CgCols cols, hipStream_t s);
+template <typename T>
+void launch_cg_spmm(const CgSys* sys, const int4* tiles, int ntiles, int rb, CgCols cols, hipStream_t s);
+template <typename T>
+void launch_cg_update(const CgSys* sys, const int4* tiles, int ntiles, int rb, CgCols cols, hipStream_t s);
+template <typename T>
+void launch_cg_direction(const CgSys* sys, const int4* tiles, int ntiles, int rb, CgCols cols, hipStream_t s);
+template <typename T>
+void launch_cg_residual64(const CgSys* sys, const int4* tiles, int ntiles, int rb, CgCols cols, hipStream_t s);
+template <typename T>
+void launch_cg_shadow(const CgSys* sys, const int4* tiles, int ntiles, int rb, hipStream_t s);
+void launch_cg_alpha(CgCols cols, hipStream_t s);
+void launch_cg_beta(CgCols cols, double tol2, hipStream_t s);
+void launch_cg_start(CgCols cols, int first, double tol2_first, hipStream_t s);
+void launch_cg_restart(CgCols cols, double tol2_outer, hipStream_t s);
+
+void launch_to_f64_block(const float* in, int ldi, double* out, int ldo, int rows, int cols, hipStream_t s);
+void launch_spmm64_rows(const int* rp, const int* col, const double* val, int nrows, int col_limit,
+                        const double* X, int ldx, int ncols, double* Y, int ldy, hipStream_t s);
+void launch_gemm(const GemmDesc* d, const int4* tiles, int ntiles, hipStream_t s);
+void launch_schur(const int* rp, const int* col, const double* Kval, int nI, int nB, const double* E, int lde,
+                  double* S, int lds, hipStream_t s);
+void launch_pad_identity(double* S, int M, int MP, hipStream_t s);
+void launch_symmetrize(double* S, int MP, hipStream_t s);
+
+void launch_potrf_diag(const DenseSub* d, int nsub, int p, hipStream_t s);
+void launch_chol_panel(const DenseSub* d, int nsub, int p, int tmax, hipStream_t s);
+void launch_chol_syrk(const DenseSub* d, int nsub, int p, int tmax, hipStream_t s);
+// solve R^T X = B for every 64-column tile of every subdomain
+void launch_trsm_lt(const DenseSub* d, const TrsmDesc* td, int nsub, int max_col_tiles, hipStream_t s);
+void launch_scale_cols(const double* U, int ldu, const double* sigma, int k, int rows, double* B, hipStream_t s);
+// solve R X = B for one column tile (<= 64 columns): B, X are MP x 64 (ld 64)
+void launch_trsm_un(const DenseSub* d, int nsub, double* const* Bs, double* const* Xs, int tmax, hipStream_t s);
+
+void launch_jacobi(double* const* H, double* const* Svec, double* const* theta, const int* s_of, int nsub,
+                   int smax, hipStream_t s);
+void launch_ritz(double* const* Z, double* const* U, double* const* Vn, double* const* theta,
+                 double* const* resid, const int* rows, const int* s_of, int nsub, int maxrows, int smax,
+                 hipStream_t s);
+void launch_cholinv_small(double* const* G, double* const* Rinv, const int* s_of, int nsub, int smax,
+                          int* info, hipStream_t s);
+void launch_random_init(double* const* V, const int* rows, const int* M_of, const int* s_of, int nsub,
+                        int maxrows, int smax, uint32_t seed, hipStream_t s);
+
+void launch_copy_col(const double* src, int lds, double* dst, int ldd, int rows, hipStream_t s);
+void launch_pair_project(const int4* trip_range, const int* trip, const double* A0, double* const* Vi,
+                         const int* ldv, const int* k1, const int* off, double* At, int64_t ldat, int npairs,
+                         hipStream_t s);
+void launch_scatter_block(const double* B, int k1, int ld, double* At, int64_t ldat, int off, hipStream_t s);
+void launch_reconstruct(const double* V, int nP, int k1, const double* x, const int* nodes, double* u,
+                        hipStream_t s);
+
+}  // namespace mor

@@ -1,0 +1,1281 @@
+// HIP kernels for gfx950 (CDNA4, wave64) of the localized model-order-reduction hot path.
+//
+//   element-coloured P1 assembly into CSR ........ Section 2 (Problem 2.2), Section 4 (H1 Gram
+//                                                  matrices of R_i and R_BB), Section 6 step 2
+//   block CG for A_II X = [-A_IB, f_I] ........... Problems 3.2-3.3, the lifting Z_i of Section 4
+//   FP64 residual refinement ...................... (numerical addition; same solution)
+//   Gram / Schur / Cholesky / TRSM (FP64 MFMA) ... Lemmas 4.1-4.2 and eq. 4.3-4.5
+//   Jacobi eigensolver + Ritz steps ............... top-k of the weighted lifting operator
+//   neighbour-pair projection, reduced solve ...... Section 6 step 3 (eq. 6.1)
+//
+// Streaming kernels use 256-thread workgroups (4 waves) and an XCD-aware tile order: the
+// hardware hands workgroup b to XCD b % 8, so logical tile (b % 8) * ceil(G/8) + b / 8 keeps
+// consecutive row blocks of one column tile on one XCD and its L2.
+#include "mor_internal.h"
+
+#include <hip/hip_runtime.h>
+
+namespace mor {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); }
+
+__device__ __forceinline__ int xcd_tile(int b, int ntiles) {
+  const int g8 = (ntiles + 7) >> 3;
+  return (b & 7) * g8 + (b >> 3);
+}
+
+static inline int xcd_grid(int ntiles) { return ((ntiles + 7) >> 3) << 3; }
+
+// --------------------------------------------------------------------------------- fills
+__global__ void k_fill(double* p, int64_t n, double v) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = v;
+}
+__global__ void k_fill_f(float* p, int64_t n, float v) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = v;
+}
+__global__ void k_fill_i(int* p, int64_t n, int v) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = v;
+}
+static inline int grid_for(int64_t n) {
+  int64_t g = (n + 255) / 256;
+  return (int)(g < 1 ? 1 : (g > 65536 ? 65536 : g));
+}
+void launch_fill(double* p, int64_t n, double v, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(k_fill, dim3(grid_for(n)), dim3(256), 0, s, p, n, v);
+}
+void launch_fill_f(float* p, int64_t n, float v, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(k_fill_f, dim3(grid_for(n)), dim3(256), 0, s, p, n, v);
+}
+void launch_fill_i(int* p, int64_t n, int v, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(k_fill_i, dim3(grid_for(n)), dim3(256), 0, s, p, n, v);
+}
+
+__global__ void k_to_f32(const double* in, float* out, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (; i < n; i += (int64_t)gridDim.x * blockDim.x) out[i] = (float)in[i];
+}
+void launch_to_f32(const double* in, float* out, int64_t n, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(k_to_f32, dim3(grid_for(n)), dim3(256), 0, s, in, out, n);
+}
+
+// --------------------------------------------------------------------------------- assembly
+__device__ __forceinline__ int find_slot(const int* __restrict__ rp, const int* __restrict__ col, int r, int c) {
+  int lo = rp[r], hi = rp[r + 1];
+  while (lo < hi) {
+    int mid = (lo + hi) >> 1;
+    if (col[mid] < c) lo = mid + 1; else hi = mid;
+  }
+  return lo;
+}
+
+// One thread per tet of one colour: tets of a colour share no node, so the scatter into the
+// CSR values needs no atomics and is deterministic.
+__global__ __launch_bounds__(256) void k_assemble(const AsmSub* __restrict__ subs, const int* __restrict__ prefix,
+                                                  int nsub, int total, const double* __restrict__ xyz,
+                                                  const int* __restrict__ tets, const double* __restrict__ kappa,
+                                                  const double* __restrict__ fnodal) {
+  const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= total) return;
+  int lo = 0, hi = nsub;
+  while (hi - lo > 1) {
+    int mid = (lo + hi) >> 1;
+    if (prefix[mid] <= gid) lo = mid; else hi = mid;
+  }
+  const AsmSub& S = subs[lo];
+  const int t = S.t_begin + (gid - prefix[lo]);
+  const int g = S.tetg[t];
+  int nd[4], ln[4];
+  double x[4][3];
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    nd[a] = tets[4 * (int64_t)g + a];
+    ln[a] = S.ltet[4 * (int64_t)t + a];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) x[a][d] = xyz[3 * (int64_t)nd[a] + d];
+  }
+  double e1[3], e2[3], e3[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    e1[d] = x[1][d] - x[0][d];
+    e2[d] = x[2][d] - x[0][d];
+    e3[d] = x[3][d] - x[0][d];
+  }
+  // rows of J^{-1} (J = [e1 e2 e3]) are the scaled cross products: grad(lambda_1..3)
+  double c23[3] = {e2[1] * e3[2] - e2[2] * e3[1], e2[2] * e3[0] - e2[0] * e3[2], e2[0] * e3[1] - e2[1] * e3[0]};
+  double c31[3] = {e3[1] * e1[2] - e3[2] * e1[1], e3[2] * e1[0] - e3[0] * e1[2], e3[0] * e1[1] - e3[1] * e1[0]};
+  double c12[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2], e1[0] * e2[1] - e1[1] * e2[0]};
+  const double det = e1[0] * c23[0] + e1[1] * c23[1] + e1[2] * c23[2];
+  const double inv = 1.0 / det;
+  double gr[4][3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    gr[1][d] = c23[d] * inv;
+    gr[2][d] = c31[d] * inv;
+    gr[3][d] = c12[d] * inv;
+    gr[0][d] = -(gr[1][d] + gr[2][d] + gr[3][d]);
+  }
+  const double vol = fabs(det) * (1.0 / 6.0);
+  const double kap = kappa[g];
+  const bool in_core = S.core != nullptr && S.core[t] != 0;
+  double fv[4] = {1.0, 1.0, 1.0, 1.0};
+  if (fnodal != nullptr) {
+#pragma unroll
+    for (int a = 0; a < 4; ++a) fv[a] = fnodal[nd[a]];
+  }
+  const double fsum = fv[0] + fv[1] + fv[2] + fv[3];
+  const double m20 = vol * (1.0 / 20.0);
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    const int ra = ln[a];
+    if (ra < 0) continue;
+    if (S.f) S.f[ra] += m20 * (fv[a] + fsum);
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const int cb = ln[b];
+      if (cb < 0) continue;
+      const double gg = vol * (gr[a][0] * gr[b][0] + gr[a][1] * gr[b][1] + gr[a][2] * gr[b][2]);
+      const double mass = m20 * (a == b ? 2.0 : 1.0);
+      if (S.A || S.K) {
+        const int slot = find_slot(S.rp, S.col, ra, cb);
+        if (S.A) S.A[slot] += kap * gg;
+        if (S.K) S.K[slot] += gg + mass;
+      }
+      if (in_core && S.Ki) {
+        const int slot = find_slot(S.rpV, S.colV, ra, cb);
+        S.Ki[slot] += gg + mass;
+      }
+    }
+  }
+}
+
+void launch_assemble(const AsmSub* d_subs, const int* d_prefix, int nsub, int total, const double* xyz,
+                     const int* tets, const double* kappa, const double* fnodal, hipStream_t s) {
+  if (total <= 0) return;
+  hipLaunchKernelGGL(k_assemble, dim3((total + 255) / 256), dim3(256), 0, s, d_subs, d_prefix, nsub, total, xyz,
+                     tets, kappa, fnodal);
+}
+
+__global__ void k_diag_inv(const int* __restrict__ rp, const int* __restrict__ col, const double* __restrict__ v,
+                           int nI, void* dinv, int is_double) {
+  int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= nI) return;
+  int slot = find_slot(rp, col, r, r);
+  double d = 1.0 / v[slot];
+  if (is_double) ((double*)dinv)[r] = d; else ((float*)dinv)[r] = (float)d;
+}
+void launch_diag_inv(const int* rp, const int* col, const double* v64, int nI, void* dinv, int is_double,
+                     hipStream_t s) {
+  if (nI > 0) hipLaunchKernelGGL(k_diag_inv, dim3((nI + 255) / 256), dim3(256), 0, s, rp, col, v64, nI, dinv, is_double);
+}
+
+// --------------------------------------------------------------------------------- block CG
+// A tile = (system, first row, first column); a wave owns 64 * VEC consecutive columns
+// (VEC = 16 bytes of the scalar type per lane) and rows wave, wave+4, ... of the block.
+template <typename T> struct VecT;
+template <> struct VecT<float> { static constexpr int N = 4; };
+template <> struct VecT<double> { static constexpr int N = 2; };
+
+template <typename T>
+__device__ __forceinline__ void ld_vec(const T* p, T (&v)[VecT<T>::N]) {
+  *reinterpret_cast<uint4*>(v) = *reinterpret_cast<const uint4*>(p);
+}
+template <typename T>
+__device__ __forceinline__ void st_vec(T* p, const T (&v)[VecT<T>::N]) {
+  *reinterpret_cast<uint4*>(p) = *reinterpret_cast<const uint4*>(v);
+}
+
+// Sum a per-lane partial over the 4 waves and add it to a per-column FP64 accumulator.
+template <int N>
+__device__ __forceinline__ void column_reduce_add(double (*red)[64 * 4], const double (&part)[N], int c0tile, int ld,
+                                                  double* __restrict__ acc) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+  for (int v = 0; v < N; ++v) red[w][lane * N + v] = part[v];
+  __syncthreads();
+  for (int i = threadIdx.x; i < 64 * N; i += 256) {
+    const int c = c0tile + i;
+    if (c < ld) {
+      const double s = red[0][i] + red[1][i] + red[2][i] + red[3][i];
+      if (s != 0.0) unsafeAtomicAdd(&acc[c], s);
+    }
+  }
+}
+
+// sparse right-hand side entries of row r: -A_IB[r, :] and the load column
+template <typename TT, int N>
+__device__ __forceinline__ void rhs_row(const CgSys& S, int r, int c0, TT (&v)[N]) {
+#pragma unroll
+  for (int q = 0; q < N; ++q) v[q] = 0;
+  const int e1 = S.rp[r + 1];
+  for (int e = S.ii_end[r]; e < e1; ++e) {
+    const int j = S.col[e] - S.nI - c0;
+    if (j >= 0 && j < N) {
+#pragma unroll
+      for (int q = 0; q < N; ++q)
+        if (q == j) v[q] = (TT)(-S.val64[e]);
+    }
+  }
+  if (S.f != nullptr) {
+    const int j = S.nB - c0;
+    if (j >= 0 && j < N) {
+#pragma unroll
+      for (int q = 0; q < N; ++q)
+        if (q == j) v[q] = (TT)S.f[r];
+    }
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_cg_init(const CgSys* __restrict__ sys, const int4* __restrict__ tiles, int ntiles,
+                                                 int rb, CgCols cols) {
+  constexpr int N = VecT<T>::N;
+  __shared__ double red[4][64 * 4];
+  const int t = xcd_tile(blockIdx.x, ntiles);
+  if (t >= ntiles) return;
+  const int4 tl = tiles[t];
+  const CgSys& S = sys[tl.x];
+  const int lane = threadIdx.x & 63, w = wave_id();
+  const int c0 = tl.z + lane * N;
+  const bool act = c0 < S.ld;
+  const T* dinv = (const T*)S.dinv;
+  T* X = (T*)S.X; T* R = (T*)S.R; T* P = (T*)S.P;
+  double part[N];
+#pragma unroll
+  for (int q = 0; q < N; ++q) part[q] = 0.0;
+  const int rend = min(tl.y + rb, S.nI);
+  for (int r = tl.y + w; r < rend; r += 4) {
+    if (!act) continue;
+    T v[N], z[N], p[N];
+    rhs_row<T, N>(S, r, c0, v);
+    const T di = dinv[r];
+#pragma unroll
+    for (int q = 0; q < N; ++q) {
+      z[q] = 0;
+      p[q] = di * v[q];
+      part[q] += (double)v[q] * (double)p[q];
+    }
+    const int64_t o = (int64_t)r * S.ld + c0;
+    st_vec<T>(R + o, v);
+    st_vec<T>(X + o, z);
+    st_vec<T>(P + o, p);
+    if (S.X64 != nullptr) {
+#pragma unroll
+      for (int q = 0; q < N; ++q) S.X64[o + q] = 0.0;
+    }
+  }
+  column_reduce_add<N>(red, part, tl.z, S.ld, cols.rz + S.coff);
+}
+
+// Q = A_II P and the per-column p'Q: the dominant, HBM-bound kernel of the lifting.
+template <typename T>
+__global__ __launch_bounds__(256) void k_cg_spmm(const CgSys* __restrict__ sys, const int4* __restrict__ tiles, int ntiles,
+                                                 int rb, CgCols cols) {
+  constexpr int N = VecT<T>::N;
+  __shared__ double red[4][64 * 4];
+  const int t = xcd_tile(blockIdx.x, ntiles);
+  if (t >= ntiles) return;
+  const int4 tl = tiles[t];
+  const CgSys& S = sys[tl.x];
+  const int lane = threadIdx.x & 63, w = wave_id();
+  const int c0 = tl.z + lane * N;
+  const bool act = c0 < S.ld;
+  const int ld = S.ld;
+  const T* __restrict__ val = (sizeof(T) == 4) ? (const T*)S.val32 : (const T*)S.val64;
+  const T* __restrict__ P = (const T*)S.P;
+  T* __restrict__ Q = (T*)S.Q;
+  const int* __restrict__ colp = S.col;
+  double part[N];
+#pragma unroll
+  for (int q = 0; q < N; ++q) part[q] = 0.0;
+  const int rend = min(tl.y + rb, S.nI);
+  for (int r = tl.y + w; r < rend; r += 4) {
+    const int e0 = S.rp[r], e1 = S.ii_end[r];
+    T acc[N];
+#pragma unroll
+    for (int q = 0; q < N; ++q) acc[q] = 0;
+    if (act) {
+      int e = e0;
+      for (; e + 4 <= e1; e += 4) {
+        T p0[N], p1[N], p2[N], p3[N];
+        const int ca = colp[e], cb = colp[e + 1], cc = colp[e + 2], cd = colp[e + 3];
+        const T va = val[e], vb = val[e + 1], vc = val[e + 2], vd = val[e + 3];
+        ld_vec<T>(P + (int64_t)ca * ld + c0, p0);
+        ld_vec<T>(P + (int64_t)cb * ld + c0, p1);
+        ld_vec<T>(P + (int64_t)cc * ld + c0, p2);
+        ld_vec<T>(P + (int64_t)cd * ld + c0, p3);
+#pragma unroll
+        for (int q = 0; q < N; ++q) acc[q] += va * p0[q] + vb * p1[q] + vc * p2[q] + vd * p3[q];
+      }
+      for (; e < e1; ++e) {
+        T p0[N];
+        const int ca = colp[e];
+        const T va = val[e];
+        ld_vec<T>(P + (int64_t)ca * ld + c0, p0);
+#pragma unroll
+        for (int q = 0; q < N; ++q) acc[q] += va * p0[q];
+      }
+      const int64_t o = (int64_t)r * ld + c0;
+      st_vec<T>(Q + o, acc);
+      T pr[N];
+      ld_vec<T>(P + o, pr);
+#pragma unroll
+      for (int q = 0; q < N; ++q) part[q] += (double)pr[q] * (double)acc[q];
+    }
+  }
+  column_reduce_add<N>(red, part, tl.z, ld, cols.pq + S.coff);
+}
+
+// X += alpha P, R -= alpha Q, and the new r'D^-1 r.
+template <typename T>
+__global__ __launch_bounds__(256) void k_cg_update(const CgSys* __restrict__ sys, const int4* __restrict__ tiles,
+                                                   int ntiles, int rb, CgCols cols) {
+  constexpr int N = VecT<T>::N;
+  __shared__ double red[4][64 * 4];
+  const int t = xcd_tile(blockIdx.x, ntiles);
+  if (t >= ntiles) return;
+  const int4 tl = tiles[t];
+  const CgSys& S = sys[tl.x];
+  const int lane = threadIdx.x & 63, w = wave_id();
+  const int c0 = tl.z + lane * N;
+  const bool act = c0 < S.ld;
+  const int ld = S.ld;
+  const T* dinv = (const T*)S.dinv;
+  T* X = (T*)S.X; T* R = (T*)S.R; const T* P = (const T*)S.P; const T* Q = (const T*)S.Q;
+  T al[N];
+  double part[N];
+#pragma unroll
+  for (int q = 0; q < N; ++q) {
+    part[q] = 0.0;
+    al[q] = act ? (T)cols.alpha[S.coff + c0 + q] : (T)0;
+  }
+  const int rend = min(tl.y + rb, S.nI);
+  for (int r = tl.y + w; r < rend; r += 4) {
+    if (!act) continue;
+    const int64_t o = (int64_t)r * ld + c0;
+    T x[N], rr[N], p[N], qq[N];
+    ld_vec<T>(X + o, x);
+    ld_vec<T>(R + o, rr);
+    ld_vec<T>(P + o, p);
+    ld_vec<T>(Q + o, qq);
+    const T di = dinv[r];
+#pragma unroll
+    for (int q = 0; q < N; ++q) {
+      x[q] += al[q] * p[q];
+      rr[q] -= al[q] * qq[q];
+      part[q] += (double)rr[q] * (double)(di * rr[q]);
+    }
+    st_vec<T>(X + o, x);
+    st_vec<T>(R + o, rr);
+  }
+  column_reduce_add<N>(red, part, tl.z, ld, cols.rznew + S.coff);
+}
+
+// P = D^-1 R + beta P
+template <typename T>
+__global__ __launch_bounds__(256) void k_cg_direction(const CgSys* __restrict__ sys, const int4* __restrict__ tiles,
+                                                      int ntiles, int rb, CgCols cols) {
+  constexpr int N = VecT<T>::N;
+  const int t = xcd_tile(blockIdx.x, ntiles);
+  if (t >= ntiles) return;
+  const int4 tl = tiles[t];
+  const CgSys& S = sys[tl.x];
+  const int lane = threadIdx.x & 63, w = wave_id();
+  const int c0 = tl.z + lane * N;
+  if (c0 >= S.ld) return;
+  const int ld = S.ld;
+  const T* dinv = (const T*)S.dinv;
+  const T* R = (const T*)S.R; T* P = (T*)S.P;
+  T be[N];
+#pragma unroll
+  for (int q = 0; q < N; ++q) be[q] = (T)cols.beta[S.coff + c0 + q];
+  const int rend = min(tl.y + rb, S.nI);
+  for (int r = tl.y + w; r < rend; r += 4) {
+    const int64_t o = (int64_t)r * ld + c0;
+    T rr[N], p[N];
+    ld_vec<T>(R + o, rr);
+    ld_vec<T>(P + o, p);
+    const T di = dinv[r];
+#pragma unroll
+    for (int q = 0; q < N; ++q) p[q] = di * rr[q] + be[q] * p[q];
+    st_vec<T>(P + o, p);
+  }
+}
+
+// X64 += X (accumulate a correction into the FP64 solution)
+template <typename T>
+__global__ __launch_bounds__(256) void k_cg_shadow(const CgSys* __restrict__ sys, const int4* __restrict__ tiles,
+                                                   int ntiles, int rb) {
+  constexpr int N = VecT<T>::N;
+  const int t = xcd_tile(blockIdx.x, ntiles);
+  if (t >= ntiles) return;
+  const int4 tl = tiles[t];
+  const CgSys& S = sys[tl.x];
+  const int lane = threadIdx.x & 63, w = wave_id();
+  const int c0 = tl.z + lane * N;
+  if (c0 >= S.ld || S.X64 == nullptr) return;
+  const T* X = (const T*)S.X;
+  const int rend = min(tl.y + rb, S.nI);
+  for (int r = tl.y + w; r < rend; r += 4) {
+    const int64_t o = (int64_t)r * S.ld + c0;
+    T x[N];
+    ld_vec<T>(X + o, x);
+#pragma unroll
+    for (int q = 0; q < N; ++q) S.X64[o + q] += (double)x[q];
+  }
+}
+
+// FP64 residual of the FP64 solution: R = F - A_II X64 (rounded to T), P = D^-1 R, X = 0.
+template <typename T>
+__global__ __launch_bounds__(256) void k_cg_residual64(const CgSys* __restrict__ sys, const int4* __restrict__ tiles,
+                                                       int ntiles, int rb, CgCols cols) {
+  constexpr int N = VecT<T>::N;
+  __shared__ double red[4][64 * 4];
+  const int t = xcd_tile(blockIdx.x, ntiles);
+  if (t >= ntiles) return;
+  const int4 tl = tiles[t];
+  const CgSys& S = sys[tl.x];
+  const int lane = threadIdx.x & 63, w = wave_id();
+  const int c0 = tl.z + lane * N;
+  const bool act = c0 < S.ld;
+  const int ld = S.ld;
+  const T* dinv = (const T*)S.dinv;
+  T* X = (T*)S.X; T* R = (T*)S.R; T* P = (T*)S.P;
+  double part[N];
+#pragma unroll
+  for (int q = 0; q < N; ++q) part[q] = 0.0;
+  const int rend = min(tl.y + rb, S.nI);
+  for (int r = tl.y + w; r < rend; r += 4) {
+    if (!act) continue;
+    double acc[N];
+    rhs_row<double, N>(S, r, c0, acc);
+    const int e1 = S.ii_end[r];
+    for (int e = S.rp[r]; e < e1; ++e) {
+      const double a = S.val64[e];
+      const double* xr = S.X64 + (int64_t)S.col[e] * ld + c0;
+#pragma unroll
+      for (int q = 0; q < N; ++q) acc[q] -= a * xr[q];
+    }
+    const T di = dinv[r];
+    T rr[N], p[N], z[N];
+#pragma unroll
+    for (int q = 0; q < N; ++q) {
+      rr[q] = (T)acc[q];
+      p[q] = di * rr[q];
+      z[q] = 0;
+      part[q] += (double)rr[q] * (double)p[q];
+    }
+    const int64_t o = (int64_t)r * ld + c0;
+    st_vec<T>(R + o, rr);
+    st_vec<T>(P + o, p);
+    st_vec<T>(X + o, z);
+  }
+  column_reduce_add<N>(red, part, tl.z, ld, cols.rz + S.coff);
+}
+
+template <typename T>
+void launch_cg_init(const CgSys* sys, const int4* tiles, int ntiles, int rb, CgCols cols, hipStream_t s) {
+  if (ntiles > 0) hipLaunchKernelGGL(k_cg_init<T>, dim3(xcd_grid(ntiles)), dim3(256), 0, s, sys, tiles, ntiles, rb, cols);
+}
+template <typename T>
+void launch_cg_spmm(const CgSys* sys, const int4* tiles, int ntiles, int rb, CgCols cols, hipStream_t s) {
+  if (ntiles > 0) hipLaunchKernelGGL(k_cg_spmm<T>, dim3(xcd_grid(ntiles)), dim3(256), 0, s, sys, tiles, ntiles, rb, cols);
+}
+template <typename T>
+void launch_cg_update(const CgSys* sys, const int4* tiles, int ntiles, int rb, CgCols cols, hipStream_t s) {
+  if (ntiles > 0) hipLaunchKernelGGL(k_cg_update<T>, dim3(xcd_grid(ntiles)), dim3(256), 0, s, sys, tiles, ntiles, rb, cols);
+}
+template <typename T>
+void launch_cg_direction(const CgSys* sys, const int4* tiles, int ntiles, int rb, CgCols cols, hipStream_t s) {
+  if (ntiles > 0)
+    hipLaunchKernelGGL(k_cg_direction<T>, dim3(xcd_grid(ntiles)), dim3(256), 0, s, sys, tiles, ntiles, rb, cols);
+}
+template <typename T>
+void launch_cg_residual64(const CgSys* sys, const int4* tiles, int ntiles, int rb, CgCols cols, hipStream_t s) {
+  if (ntiles > 0)
+    hipLaunchKernelGGL(k_cg_residual64<T>, dim3(xcd_grid(ntiles)), dim3(256), 0, s, sys, tiles, ntiles, rb, cols);
+}
+template <typename T>
+void launch_cg_shadow(const CgSys* sys, const int4* tiles, int ntiles, int rb, hipStream_t s) {
+  if (ntiles > 0) hipLaunchKernelGGL(k_cg_shadow<T>, dim3(xcd_grid(ntiles)), dim3(256), 0, s, sys, tiles, ntiles, rb);
+}
+#define MOR_INST(T)                                                                                 \
+  template void launch_cg_init<T>(const CgSys*, const int4*, int, int, CgCols, hipStream_t);       \
+  template void launch_cg_spmm<T>(const CgSys*, const int4*, int, int, CgCols, hipStream_t);       \
+  template void launch_cg_update<T>(const CgSys*, const int4*, int, int, CgCols, hipStream_t);     \
+  template void launch_cg_direction<T>(const CgSys*, const int4*, int, int, CgCols, hipStream_t);  \
+  template void launch_cg_residual64<T>(const CgSys*, const int4*, int, int, CgCols, hipStream_t); \
+  template void launch_cg_shadow<T>(const CgSys*, const int4*, int, int, hipStream_t);
+MOR_INST(float)
+MOR_INST(double)
+#undef MOR_INST
+
+// per-column scalars ------------------------------------------------------------------
+__device__ __forceinline__ bool first_col_of_sys(const CgCols& c, int j) {
+  return j == 0 || c.sys_of_col[j - 1] != c.sys_of_col[j];
+}
+
+__global__ void k_cg_alpha(CgCols c) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= c.ncols_total) return;
+  if (first_col_of_sys(c, j)) c.nactive[c.sys_of_col[j]] = 0;
+  const double pq = c.pq[j];
+  double a = 0.0;
+  if (c.active[j]) {
+    if (pq > 0.0) a = c.rz[j] / pq;
+    else c.active[j] = 0;   // breakdown: p'Ap <= 0 cannot happen for SPD data
+  }
+  c.alpha[j] = a;
+  c.pq[j] = 0.0;
+}
+
+__global__ void k_cg_beta(CgCols c, double tol2) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= c.ncols_total) return;
+  const double rn = c.rznew[j];
+  c.rznew[j] = 0.0;
+  if (!c.active[j]) {
+    c.beta[j] = 0.0;
+    return;
+  }
+  if (rn <= tol2 * c.rz0[j]) {
+    c.active[j] = 0;
+    c.beta[j] = 0.0;
+    c.rz[j] = rn;
+    return;
+  }
+  c.beta[j] = rn / c.rz[j];
+  c.rz[j] = rn;
+  atomicAdd(&c.nactive[c.sys_of_col[j]], 1);
+}
+
+// After the initial right-hand side: references, flags, zero accumulators.
+__global__ void k_cg_start(CgCols c) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= c.ncols_total) return;
+  const double rz = c.rz[j];
+  c.rz0[j] = rz;
+  c.rzF[j] = rz;
+  c.alpha[j] = 0.0;
+  c.beta[j] = 0.0;
+  c.pq[j] = 0.0;
+  c.rznew[j] = 0.0;
+  c.active[j] = rz > 0.0 ? 1 : 0;
+}
+// After an FP64 residual: restart from it; columns already below the outer target stop.
+__global__ void k_cg_restart(CgCols c, double tol2_outer) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= c.ncols_total) return;
+  const double rz = c.rz[j];
+  c.rz0[j] = rz;
+  c.alpha[j] = 0.0;
+  c.beta[j] = 0.0;
+  c.pq[j] = 0.0;
+  c.rznew[j] = 0.0;
+  c.active[j] = (rz > tol2_outer * c.rzF[j]) ? 1 : 0;
+}
+__global__ void k_cg_count(CgCols c) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= c.ncols_total) return;
+  if (c.active[j]) atomicAdd(&c.nactive[c.sys_of_col[j]], 1);
+}
+__global__ void k_cg_zero_count(CgCols c) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= c.ncols_total) return;
+  if (first_col_of_sys(c, j)) c.nactive[c.sys_of_col[j]] = 0;
+}
+
+void launch_cg_alpha(CgCols c, hipStream_t s) {
+  hipLaunchKernelGGL(k_cg_alpha, dim3((c.ncols_total + 255) / 256), dim3(256), 0, s, c);
+}
+void launch_cg_beta(CgCols c, double tol2, hipStream_t s) {
+  hipLaunchKernelGGL(k_cg_beta, dim3((c.ncols_total + 255) / 256), dim3(256), 0, s, c, tol2);
+}
+void launch_cg_start(CgCols c, int first, double tol2_outer, hipStream_t s) {
+  const dim3 g((c.ncols_total + 255) / 256);
+  hipLaunchKernelGGL(k_cg_zero_count, g, dim3(256), 0, s, c);
+  if (first) hipLaunchKernelGGL(k_cg_start, g, dim3(256), 0, s, c);
+  else hipLaunchKernelGGL(k_cg_restart, g, dim3(256), 0, s, c, tol2_outer);
+  hipLaunchKernelGGL(k_cg_count, g, dim3(256), 0, s, c);
+}
+void launch_cg_restart(CgCols c, double tol2_outer, hipStream_t s) { launch_cg_start(c, 0, tol2_outer, s); }
+
+// --------------------------------------------------------------------------------- FP64 helpers
+__global__ void k_to_f64_block(const float* in, int ldi, double* out, int ldo, int rows, int cols) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t n = (int64_t)rows * cols;
+  if (i >= n) return;
+  const int r = (int)(i / cols), c = (int)(i % cols);
+  out[(int64_t)r * ldo + c] = (double)in[(int64_t)r * ldi + c];
+}
+void launch_to_f64_block(const float* in, int ldi, double* out, int ldo, int rows, int cols, hipStream_t s) {
+  const int64_t n = (int64_t)rows * cols;
+  if (n > 0) hipLaunchKernelGGL(k_to_f64_block, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, in, ldi, out, ldo, rows, cols);
+}
+
+// Y[r, c] = sum over CSR entries of row r with column < col_limit of val * X[col, c]
+__global__ __launch_bounds__(256) void k_spmm64_rows(const int* __restrict__ rp, const int* __restrict__ col,
+                                                     const double* __restrict__ val, int nrows, int col_limit,
+                                                     const double* __restrict__ X, int ldx, int ncols,
+                                                     double* __restrict__ Y, int ldy) {
+  const int r = blockIdx.x * 4 + wave_id();
+  const int c = blockIdx.y * 64 + (threadIdx.x & 63);
+  if (r >= nrows || c >= ncols) return;
+  double acc = 0.0;
+  const int e1 = rp[r + 1];
+  for (int e = rp[r]; e < e1; ++e) {
+    const int cc = col[e];
+    if (cc < col_limit) acc += val[e] * X[(int64_t)cc * ldx + c];
+  }
+  Y[(int64_t)r * ldy + c] = acc;
+}
+void launch_spmm64_rows(const int* rp, const int* col, const double* val, int nrows, int col_limit, const double* X,
+                        int ldx, int ncols, double* Y, int ldy, hipStream_t s) {
+  if (nrows <= 0 || ncols <= 0) return;
+  hipLaunchKernelGGL(k_spmm64_rows, dim3((nrows + 3) / 4, (ncols + 63) / 64), dim3(256), 0, s, rp, col, val, nrows,
+                     col_limit, X, ldx, ncols, Y, ldy);
+}
+
+// S_B = K_BB + K_BI E (Schur complement of the H1 matrix onto B, Lemma 4.1), E = K_II^-1 (-K_IB)
+__global__ __launch_bounds__(256) void k_schur(const int* __restrict__ rp, const int* __restrict__ col,
+                                               const double* __restrict__ K, int nI, int nB,
+                                               const double* __restrict__ E, int lde, double* __restrict__ S, int lds) {
+  const int b = blockIdx.x * 4 + wave_id();
+  const int c = blockIdx.y * 64 + (threadIdx.x & 63);
+  if (b >= nB || c >= nB) return;
+  const int r = nI + b;
+  double acc = 0.0;
+  const int e1 = rp[r + 1];
+  for (int e = rp[r]; e < e1; ++e) {
+    const int cc = col[e];
+    const double a = K[e];
+    if (cc < nI) acc += a * E[(int64_t)cc * lde + c];
+    else if (cc - nI == c) acc += a;
+  }
+  S[(int64_t)b * lds + c] = acc;
+}
+void launch_schur(const int* rp, const int* col, const double* Kval, int nI, int nB, const double* E, int lde, double* S,
+                  int lds, hipStream_t s) {
+  if (nB <= 0) return;
+  hipLaunchKernelGGL(k_schur, dim3((nB + 3) / 4, (nB + 63) / 64), dim3(256), 0, s, rp, col, Kval, nI, nB, E, lde, S, lds);
+}
+
+// rows/columns M..MP-1 of an MP x MP matrix become the identity
+__global__ void k_pad_identity(double* S, int M, int MP) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t n = (int64_t)MP * MP;
+  if (i >= n) return;
+  const int r = (int)(i / MP), c = (int)(i % MP);
+  if (r < M && c < M) return;
+  S[i] = (r == c) ? 1.0 : 0.0;
+}
+void launch_pad_identity(double* S, int M, int MP, hipStream_t s) {
+  if (M >= MP) return;
+  const int64_t n = (int64_t)MP * MP;
+  hipLaunchKernelGGL(k_pad_identity, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, S, M, MP);
+}
+__global__ void k_symmetrize(double* S, int MP) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t n = (int64_t)MP * MP;
+  if (i >= n) return;
+  const int r = (int)(i / MP), c = (int)(i % MP);
+  if (r >= c) return;
+  const double v = 0.5 * (S[(int64_t)r * MP + c] + S[(int64_t)c * MP + r]);
+  S[(int64_t)r * MP + c] = v;
+  S[(int64_t)c * MP + r] = v;
+}
+void launch_symmetrize(double* S, int MP, hipStream_t s) {
+  const int64_t n = (int64_t)MP * MP;
+  if (n > 0) hipLaunchKernelGGL(k_symmetrize, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, S, MP);
+}
+
+// --------------------------------------------------------------------------------- FP64 MFMA tiles
+// A 64 x 64 output tile per 256-thread workgroup; wave (wr, wc) owns a 32 x 32 quarter made
+// of 2 x 2 blocks of v_mfma_f64_16x16x4 (A: lane -> row lane%16, k lane/16; B: lane -> col
+// lane%16, k lane/16; D: lane -> col lane%16, rows 4*(lane/16) + 0..3).
+constexpr int kLdsPad = 68;
+
+template <bool TA, bool TB>
+__device__ __forceinline__ void tile_mma(const double* __restrict__ A, int lda, const double* __restrict__ B, int ldb,
+                                         int m, int n, int i0, int j0, int kb, int ke, double (*As)[kLdsPad],
+                                         double (*Bs)[kLdsPad], d4 (&acc)[2][2]) {
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, wr = w >> 1, wc = w & 1;
+  for (int k0 = kb; k0 < ke; k0 += 16) {
+    if (!TA) {
+      const int i = tid >> 2, kk = (tid & 3) * 4;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int k = k0 + kk + q;
+        As[kk + q][i] = (i0 + i < m && k < ke) ? A[(int64_t)(i0 + i) * lda + k] : 0.0;
+      }
+    } else {
+      const int kk = tid >> 4, i = (tid & 15) * 4;
+      const int k = k0 + kk;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) As[kk][i + q] = (i0 + i + q < m && k < ke) ? A[(int64_t)k * lda + i0 + i + q] : 0.0;
+    }
+    if (!TB) {
+      const int kk = tid >> 4, j = (tid & 15) * 4;
+      const int k = k0 + kk;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) Bs[kk][j + q] = (k < ke && j0 + j + q < n) ? B[(int64_t)k * ldb + j0 + j + q] : 0.0;
+    } else {
+      const int j = tid >> 2, kk = (tid & 3) * 4;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int k = k0 + kk + q;
+        Bs[kk + q][j] = (k < ke && j0 + j < n) ? B[(int64_t)(j0 + j) * ldb + k] : 0.0;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int s4 = 0; s4 < 4; ++s4) {
+      const int kr = s4 * 4 + (lane >> 4);
+      const double a0 = As[kr][wr * 32 + (lane & 15)];
+      const double a1 = As[kr][wr * 32 + 16 + (lane & 15)];
+      const double b0 = Bs[kr][wc * 32 + (lane & 15)];
+      const double b1 = Bs[kr][wc * 32 + 16 + (lane & 15)];
+      acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
+      acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
+      acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
+      acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+}
+
+__device__ __forceinline__ void tile_zero(d4 (&acc)[2][2]) {
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
+}
+
+// C = alpha * acc + beta * C over the valid part of the tile
+__device__ __forceinline__ void tile_store(double* C, int ldc, int m, int n, int i0, int j0, double alpha, double beta,
+                                           const d4 (&acc)[2][2]) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, wr = w >> 1, wc = w & 1;
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = i0 + wr * 32 + a * 16 + 4 * (lane >> 4) + r;
+        const int j = j0 + wc * 32 + b * 16 + (lane & 15);
+        if (i < m && j < n) {
+          double* p = C + (int64_t)i * ldc + j;
+          const double v = alpha * acc[a][b][r];
+          *p = (beta == 0.0) ? v : v + beta * *p;
+        }
+      }
+}
+// symmetric result: tile (ti <= tj); write (i, j) and (j, i) for i <= j inside diagonal tiles
+__device__ __forceinline__ void tile_store_sym(double* C, int ldc, int m, int i0, int j0, double alpha,
+                                               const d4 (&acc)[2][2]) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, wr = w >> 1, wc = w & 1;
+  const bool diag = (i0 == j0);
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = i0 + wr * 32 + a * 16 + 4 * (lane >> 4) + r;
+        const int j = j0 + wc * 32 + b * 16 + (lane & 15);
+        if (i < m && j < m && (!diag || i <= j)) {
+          const double v = alpha * acc[a][b][r];
+          C[(int64_t)i * ldc + j] = v;
+          C[(int64_t)j * ldc + i] = v;
+        }
+      }
+}
+
+template <bool TA, bool TB>
+__device__ void gemm_tile_body(const GemmDesc& g, int ti, int tj, double (*As)[kLdsPad], double (*Bs)[kLdsPad]) {
+  d4 acc[2][2];
+  tile_zero(acc);
+  tile_mma<TA, TB>(g.A, g.lda, g.B, g.ldb, g.m, g.n, ti * 64, tj * 64, 0, g.k, As, Bs, acc);
+  if (g.sym) tile_store_sym(g.C, g.ldc, g.m, ti * 64, tj * 64, g.alpha, acc);
+  else tile_store(g.C, g.ldc, g.m, g.n, ti * 64, tj * 64, g.alpha, g.beta, acc);
+}
+
+__global__ __launch_bounds__(256) void k_gemm(const GemmDesc* __restrict__ descs, const int4* __restrict__ tiles) {
+  __shared__ double As[16][kLdsPad], Bs[16][kLdsPad];
+  const int4 tl = tiles[blockIdx.x];
+  const GemmDesc& g = descs[tl.x];
+  if (!g.ta && !g.tb) gemm_tile_body<false, false>(g, tl.y, tl.z, As, Bs);
+  else if (g.ta && !g.tb) gemm_tile_body<true, false>(g, tl.y, tl.z, As, Bs);
+  else if (!g.ta && g.tb) gemm_tile_body<false, true>(g, tl.y, tl.z, As, Bs);
+  else gemm_tile_body<true, true>(g, tl.y, tl.z, As, Bs);
+}
+void launch_gemm(const GemmDesc* d, const int4* tiles, int ntiles, hipStream_t s) {
+  if (ntiles > 0) hipLaunchKernelGGL(k_gemm, dim3(ntiles), dim3(256), 0, s, d, tiles);
+}
+
+// --------------------------------------------------------------------------------- Cholesky
+// Right-looking blocked Cholesky S = R^T R (R upper) of every subdomain's padded S_B.
+__global__ __launch_bounds__(256) void k_potrf_diag(const DenseSub* __restrict__ ds, int p) {
+  const DenseSub& d = ds[blockIdx.x];
+  if (p >= d.T) return;
+  __shared__ double A[64][65];
+  __shared__ double Ri[64][65];
+  __shared__ int bad;
+  const int tid = threadIdx.x;
+  double* S = d.S + (int64_t)(p * 64) * d.MP + p * 64;
+  for (int i = tid; i < 64 * 64; i += 256) {
+    const int r = i >> 6, c = i & 63;
+    A[r][c] = (r <= c) ? S[(int64_t)r * d.MP + c] : 0.0;
+  }
+  if (tid == 0) bad = 0;
+  __syncthreads();
+  for (int j = 0; j < 64; ++j) {
+    if (tid == 0) {
+      double v = A[j][j];
+      if (!(v > 0.0)) {
+        if (!bad) bad = p * 64 + j + 1;
+        v = 1.0;
+      }
+      A[j][j] = sqrt(v);
+    }
+    __syncthreads();
+    const double dj = A[j][j];
+    for (int l = j + 1 + tid; l < 64; l += 256) A[j][l] /= dj;
+    __syncthreads();
+    const int rem = 63 - j;
+    for (int idx = tid; idx < rem * rem; idx += 256) {
+      const int i = j + 1 + idx / rem, l = j + 1 + idx % rem;
+      if (i <= l) A[i][l] -= A[j][i] * A[j][l];
+    }
+    __syncthreads();
+  }
+  // inverse of the upper triangular R_pp, one column per thread
+  if (tid < 64) {
+    const int c = tid;
+    for (int i = 0; i < 64; ++i) Ri[i][c] = 0.0;
+    Ri[c][c] = 1.0 / A[c][c];
+    for (int i = c - 1; i >= 0; --i) {
+      double s = 0.0;
+      for (int l = i + 1; l <= c; ++l) s += A[i][l] * Ri[l][c];
+      Ri[i][c] = -s / A[i][i];
+    }
+  }
+  __syncthreads();
+  double* Di = d.Dinv + (int64_t)p * 64 * 64;
+  for (int i = tid; i < 64 * 64; i += 256) {
+    const int r = i >> 6, c = i & 63;
+    S[(int64_t)r * d.MP + c] = A[r][c];
+    Di[i] = Ri[r][c];
+  }
+  if (tid == 0 && bad && d.info[0] == 0) d.info[0] = bad;
+}
+void launch_potrf_diag(const DenseSub* d, int nsub, int p, hipStream_t s) {
+  hipLaunchKernelGGL(k_potrf_diag, dim3(nsub), dim3(256), 0, s, d, p);
+}
+
+// R_{p,j} = R_pp^{-T} S_{p,j} for j > p
+__global__ __launch_bounds__(256) void k_chol_panel(const DenseSub* __restrict__ ds, int p) {
+  __shared__ double As[16][kLdsPad], Bs[16][kLdsPad];
+  const DenseSub& d = ds[blockIdx.y];
+  const int j = p + 1 + blockIdx.x;
+  if (j >= d.T) return;
+  d4 acc[2][2];
+  tile_zero(acc);
+  double* Spj = d.S + (int64_t)(p * 64) * d.MP + j * 64;
+  const double* Di = d.Dinv + (int64_t)p * 64 * 64;
+  tile_mma<true, false>(Di, 64, Spj, d.MP, 64, 64, 0, 0, 0, 64, As, Bs, acc);
+  tile_store(Spj, d.MP, 64, 64, 0, 0, 1.0, 0.0, acc);
+}
+void launch_chol_panel(const DenseSub* d, int nsub, int p, int tmax, hipStream_t s) {
+  const int nt = tmax - p - 1;
+  if (nt > 0) hipLaunchKernelGGL(k_chol_panel, dim3(nt, nsub), dim3(256), 0, s, d, p);
+}
+
+// S_{i,j} -= R_{p,i}^T R_{p,j} for p < i <= j
+__global__ __launch_bounds__(256) void k_chol_syrk(const DenseSub* __restrict__ ds, int p, int nt) {
+  __shared__ double As[16][kLdsPad], Bs[16][kLdsPad];
+  const DenseSub& d = ds[blockIdx.y];
+  const int a = blockIdx.x / nt, b = blockIdx.x % nt;
+  if (a > b) return;
+  const int i = p + 1 + a, j = p + 1 + b;
+  if (j >= d.T) return;
+  d4 acc[2][2];
+  tile_zero(acc);
+  const double* Rpi = d.S + (int64_t)(p * 64) * d.MP + i * 64;
+  const double* Rpj = d.S + (int64_t)(p * 64) * d.MP + j * 64;
+  tile_mma<true, false>(Rpi, d.MP, Rpj, d.MP, 64, 64, 0, 0, 0, 64, As, Bs, acc);
+  double* Sij = d.S + (int64_t)(i * 64) * d.MP + j * 64;
+  tile_store(Sij, d.MP, 64, 64, 0, 0, -1.0, 1.0, acc);
+}
+void launch_chol_syrk(const DenseSub* d, int nsub, int p, int tmax, hipStream_t s) {
+  const int nt = tmax - p - 1;
+  if (nt > 0) hipLaunchKernelGGL(k_chol_syrk, dim3(nt * nt, nsub), dim3(256), 0, s, d, p, nt);
+}
+
+// Forward substitution R^T X = B, left-looking per 64-column tile (workgroup = column tile):
+// for each 64-row panel p, X_p = R_pp^{-T} (B_p - sum_{q<p} R_{q,p}^T X_q).
+__global__ __launch_bounds__(256) void k_trsm_lt(const DenseSub* __restrict__ ds, const TrsmDesc* __restrict__ tds) {
+  __shared__ double As[16][kLdsPad], Bs[16][kLdsPad];
+  const DenseSub& d = ds[blockIdx.y];
+  const TrsmDesc& td = tds[blockIdx.y];
+  const int c = blockIdx.x;
+  if (c >= td.ncol_tiles) return;
+  const int MP = d.MP;
+  const double* Bm = td.B;
+  double* X = td.X;
+  const int ldb = td.ldb, ldx = td.ldx;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, wr = w >> 1, wc = w & 1;
+  for (int p = 0; p < d.T; ++p) {
+    d4 acc[2][2];
+    tile_zero(acc);
+    // sum_{q<p} R_{q,p}^T X_{q,c}: A(i,k) = R[k][p*64+i], B(k,j) = X[k][c*64+j], k < 64p
+    tile_mma<true, false>(d.S + p * 64, MP, X + c * 64, ldx, 64, 64, 0, 0, 0, p * 64, As, Bs, acc);
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int i = p * 64 + wr * 32 + a * 16 + 4 * (lane >> 4) + r;
+          const int j = c * 64 + wc * 32 + b * 16 + (lane & 15);
+          const double bv = td.tb ? Bm[(int64_t)j * ldb + i] : Bm[(int64_t)i * ldb + j];
+          X[(int64_t)i * ldx + j] = bv - acc[a][b][r];
+        }
+    __syncthreads();
+    tile_zero(acc);
+    tile_mma<true, false>(d.Dinv + (int64_t)p * 4096, 64, X + (int64_t)(p * 64) * ldx + c * 64, ldx, 64, 64, 0, 0, 0,
+                          64, As, Bs, acc);
+    tile_store(X + (int64_t)(p * 64) * ldx + c * 64, ldx, 64, 64, 0, 0, 1.0, 0.0, acc);
+    __syncthreads();
+  }
+}
+void launch_trsm_lt(const DenseSub* d, const TrsmDesc* td, int nsub, int max_col_tiles, hipStream_t s) {
+  hipLaunchKernelGGL(k_trsm_lt, dim3(max_col_tiles, nsub), dim3(256), 0, s, d, td);
+}
+
+// B[r][j] = U[r][j] / sigma_j for j < k, 0 for k <= j < 64 (B: rows x 64)
+__global__ void k_scale_cols(const double* U, int ldu, const double* sigma, int k, int rows, double* B) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (int64_t)rows * 64) return;
+  const int r = (int)(i >> 6), j = (int)(i & 63);
+  B[i] = (j < k) ? U[(int64_t)r * ldu + j] / sigma[j] : 0.0;
+}
+void launch_scale_cols(const double* U, int ldu, const double* sigma, int k, int rows, double* B, hipStream_t s) {
+  const int64_t n = (int64_t)rows * 64;
+  hipLaunchKernelGGL(k_scale_cols, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, U, ldu, sigma, k, rows, B);
+}
+
+// Back substitution R X = B for one 64-column tile; B, X: MP x 64 (ld 64).
+__global__ __launch_bounds__(256) void k_trsm_un(const DenseSub* __restrict__ ds, double* const* Bs_, double* const* Xs_) {
+  __shared__ double As[16][kLdsPad], Bs[16][kLdsPad];
+  const int slot = blockIdx.x;
+  const DenseSub& d = ds[slot];
+  const double* Bm = Bs_[slot];
+  double* X = Xs_[slot];
+  const int MP = d.MP;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, wr = w >> 1, wc = w & 1;
+  for (int p = d.T - 1; p >= 0; --p) {
+    d4 acc[2][2];
+    tile_zero(acc);
+    // sum_{q>p} R_{p,q} X_q : A(i,k) = R[p*64+i][k], k in [(p+1)*64, MP)
+    tile_mma<false, false>(d.S + (int64_t)(p * 64) * MP, MP, X, 64, 64, 64, 0, 0, (p + 1) * 64, MP, As, Bs, acc);
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int i = p * 64 + wr * 32 + a * 16 + 4 * (lane >> 4) + r;
+          const int j = wc * 32 + b * 16 + (lane & 15);
+          X[(int64_t)i * 64 + j] = Bm[(int64_t)i * 64 + j] - acc[a][b][r];
+        }
+    __syncthreads();
+    tile_zero(acc);
+    tile_mma<false, false>(d.Dinv + (int64_t)p * 4096, 64, X + (int64_t)(p * 64) * 64, 64, 64, 64, 0, 0, 0, 64, As, Bs,
+                           acc);
+    tile_store(X + (int64_t)(p * 64) * 64, 64, 64, 64, 0, 0, 1.0, 0.0, acc);
+    __syncthreads();
+  }
+}
+void launch_trsm_un(const DenseSub* d, int nsub, double* const* Bs, double* const* Xs, int tmax, hipStream_t s) {
+  (void)tmax;
+  hipLaunchKernelGGL(k_trsm_un, dim3(nsub), dim3(256), 0, s, d, Bs, Xs);
+}
+
+// --------------------------------------------------------------------------------- small eigen
+// Cyclic Jacobi on an s x s symmetric matrix (s <= 64) with a round-robin ordering: the s/2
+// rotations of a round touch disjoint index pairs and are applied together.
+__global__ __launch_bounds__(256) void k_jacobi(double* const* Hs, double* const* Ss, double* const* Ths,
+                                                const int* s_of) {
+  __shared__ double H[64][65];
+  __shared__ double V[64][65];
+  __shared__ double cs[32], sn[32];
+  __shared__ int pp[32], qq[32];
+  __shared__ double red[256];
+  __shared__ int perm[64];
+  const int slot = blockIdx.x;
+  const int s = s_of[slot];
+  const int n = s + (s & 1);
+  const int tid = threadIdx.x;
+  const double* Hg = Hs[slot];
+  for (int i = tid; i < 64 * 64; i += 256) {
+    const int r = i >> 6, c = i & 63;
+    H[r][c] = (r < s && c < s) ? 0.5 * (Hg[r * s + c] + Hg[c * s + r]) : 0.0;
+    V[r][c] = (r == c) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  for (int sweep = 0; sweep < 40; ++sweep) {
+    double off = 0.0, tot = 0.0;
+    for (int i = tid; i < n * n; i += 256) {
+      const int r = i / n, c = i % n;
+      const double v = H[r][c] * H[r][c];
+      tot += v;
+      if (r != c) off += v;
+    }
+    red[tid] = off;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+      if (tid < st) red[tid] += red[tid + st];
+      __syncthreads();
+    }
+    const double offs = red[0];
+    __syncthreads();
+    red[tid] = tot;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+      if (tid < st) red[tid] += red[tid + st];
+      __syncthreads();
+    }
+    const double tots = red[0];
+    __syncthreads();
+    if (!(offs > 1e-32 * tots)) break;
+    for (int rnd = 0; rnd < n - 1; ++rnd) {
+      if (tid < n / 2) {
+        int p, q;
+        if (tid == 0) { p = rnd; q = n - 1; }
+        else { p = (rnd + tid) % (n - 1); q = (rnd - tid + n - 1) % (n - 1); }
+        const double hpq = H[p][q];
+        double c = 1.0, sv = 0.0;
+        if (fabs(hpq) > 1e-300) {
+          const double th = (H[q][q] - H[p][p]) / (2.0 * hpq);
+          const double t = (th >= 0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
+          c = 1.0 / sqrt(t * t + 1.0);
+          sv = t * c;
+        }
+        cs[tid] = c; sn[tid] = sv; pp[tid] = p; qq[tid] = q;
+      }
+      __syncthreads();
+      for (int idx = tid; idx < (n / 2) * n; idx += 256) {
+        const int k = idx / n, col = idx % n;
+        const int p = pp[k], q = qq[k];
+        const double hp = H[p][col], hq = H[q][col];
+        H[p][col] = cs[k] * hp - sn[k] * hq;
+        H[q][col] = sn[k] * hp + cs[k] * hq;
+      }
+      __syncthreads();
+      for (int idx = tid; idx < (n / 2) * n; idx += 256) {
+        const int k = idx / n, row = idx % n;
+        const int p = pp[k], q = qq[k];
+        const double hp = H[row][p], hq = H[row][q];
+        H[row][p] = cs[k] * hp - sn[k] * hq;
+        H[row][q] = sn[k] * hp + cs[k] * hq;
+        const double vp = V[row][p], vq = V[row][q];
+        V[row][p] = cs[k] * vp - sn[k] * vq;
+        V[row][q] = sn[k] * vp + cs[k] * vq;
+      }
+      __syncthreads();
+    }
+  }
+  if (tid == 0) {
+    for (int i = 0; i < s; ++i) perm[i] = i;
+    for (int i = 0; i < s; ++i) {
+      int best = i;
+      for (int j = i + 1; j < s; ++j)
+        if (H[perm[j]][perm[j]] > H[perm[best]][perm[best]]) best = j;
+      const int tmp = perm[i]; perm[i] = perm[best]; perm[best] = tmp;
+    }
+  }
+  __syncthreads();
+  double* Sg = Ss[slot];
+  double* th = Ths[slot];
+  for (int i = tid; i < s * s; i += 256) {
+    const int r = i / s, c = i % s;
+    Sg[i] = V[r][perm[c]];
+  }
+  for (int i = tid; i < s; i += 256) th[i] = H[perm[i]][perm[i]];
+}
+void launch_jacobi(double* const* H, double* const* Svec, double* const* theta, const int* s_of, int nsub, int smax,
+                   hipStream_t s) {
+  (void)smax;
+  hipLaunchKernelGGL(k_jacobi, dim3(nsub), dim3(256), 0, s, H, Svec, theta, s_of);
+}
+
+// Ritz residuals ||C u_j - theta_j u_j||^2 with Z = C V S and U = V S, and the next iterate Z / theta.
+__global__ __launch_bounds__(256) void k_ritz(double* const* Zs, double* const* Us, double* const* Vns,
+                                              double* const* Ths, double* const* Res, const int* rows, const int* s_of) {
+  const int slot = blockIdx.y;
+  const int s = s_of[slot], nr = rows[slot];
+  const int j = threadIdx.x & 63;
+  const int r0 = blockIdx.x * 64;
+  if (r0 >= nr || j >= s) return;
+  const double th = Ths[slot][j];
+  const double sc = fabs(th) > 1e-300 ? 1.0 / th : 1.0;
+  const double* Z = Zs[slot];
+  const double* U = Us[slot];
+  double* Vn = Vns[slot];
+  double part = 0.0;
+  for (int r = r0 + (threadIdx.x >> 6); r < min(r0 + 64, nr); r += 4) {
+    const double z = Z[(int64_t)r * s + j];
+    const double e = z - th * U[(int64_t)r * s + j];
+    part += e * e;
+    Vn[(int64_t)r * s + j] = z * sc;
+  }
+  unsafeAtomicAdd(&Res[slot][j], part);
+}
+void launch_ritz(double* const* Z, double* const* U, double* const* Vn, double* const* theta, double* const* resid,
+                 const int* rows, const int* s_of, int nsub, int maxrows, int smax, hipStream_t s) {
+  (void)smax;
+  hipLaunchKernelGGL(k_ritz, dim3((maxrows + 63) / 64, nsub), dim3(256), 0, s, Z, U, Vn, theta, resid, rows, s_of);
+}
+
+// G = R^T R (s x s, upper R), Rinv = R^-1; a zero or negative pivot flags info.
+__global__ __launch_bounds__(256) void k_cholinv_small(double* const* Gs, double* const* Ris, const int* s_of, int* info) {
+  __shared__ double A[64][65];
+  __shared__ double Ri[64][65];
+  const int slot = blockIdx.x;
+  const int s = s_of[slot], tid = threadIdx.x;
+  const double* G = Gs[slot];
+  for (int i = tid; i < s * s; i += 256) {
+    const int r = i / s, c = i % s;
+    A[r][c] = 0.5 * (G[r * s + c] + G[c * s + r]);
+  }
+  __syncthreads();
+  for (int j = 0; j < s; ++j) {
+    if (tid == 0) {
+      double v = A[j][j];
+      if (!(v > 0.0)) {
+        if (info) info[slot] = j + 1;
+        v = 1.0;
+      }
+      A[j][j] = sqrt(v);
+    }
+    __syncthreads();
+    for (int l = j + 1 + tid; l < s; l += 256) A[j][l] /= A[j][j];
+    __syncthreads();
+    const int rem = s - 1 - j;
+    for (int idx = tid; idx < rem * rem; idx += 256) {
+      const int i = j + 1 + idx / rem, l = j + 1 + idx % rem;
+      if (i <= l) A[i][l] -= A[j][i] * A[j][l];
+    }
+    __syncthreads();
+  }
+  if (tid < s) {
+    const int c = tid;
+    for (int i = 0; i < s; ++i) Ri[i][c] = 0.0;
+    Ri[c][c] = 1.0 / A[c][c];
+    for (int i = c - 1; i >= 0; --i) {
+      double sum = 0.0;
+      for (int l = i + 1; l <= c; ++l) sum += A[i][l] * Ri[l][c];
+      Ri[i][c] = -sum / A[i][i];
+    }
+  }
+  __syncthreads();
+  double* R = Ris[slot];
+  for (int i = tid; i < s * s; i += 256) R[i] = Ri[i / s][i % s];
+}
+void launch_cholinv_small(double* const* G, double* const* Rinv, const int* s_of, int nsub, int smax, int* info,
+                          hipStream_t s) {
+  (void)smax;
+  hipLaunchKernelGGL(k_cholinv_small, dim3(nsub), dim3(256), 0, s, G, Rinv, s_of, info);
+}
+
+// deterministic start block: an integer hash mapped to (-1, 1) on rows < M, zero on padding rows
+__device__ __forceinline__ uint32_t hash32(uint32_t x) {
+  x ^= x >> 16; x *= 0x7feb352dU; x ^= x >> 15; x *= 0x846ca68bU; x ^= x >> 16;
+  return x;
+}
+__global__ void k_random_init(double* const* Vs, const int* rows, const int* M_of, const int* s_of, uint32_t seed) {
+  const int slot = blockIdx.y;
+  const int s = s_of[slot], nr = rows[slot], M = M_of[slot];
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (int64_t)nr * s) return;
+  const int r = (int)(i / s), c = (int)(i % s);
+  double v = 0.0;
+  if (r < M) {
+    const uint32_t h = hash32(seed ^ hash32((uint32_t)r * 2654435761U + (uint32_t)c * 40503U + 12345U));
+    v = ((double)h + 0.5) * (2.0 / 4294967296.0) - 1.0;
+  }
+  Vs[slot][i] = v;
+}
+void launch_random_init(double* const* V, const int* rows, const int* M_of, const int* s_of, int nsub, int maxrows,
+                        int smax, uint32_t seed, hipStream_t s) {
+  const int64_t n = (int64_t)maxrows * smax;
+  hipLaunchKernelGGL(k_random_init, dim3((unsigned)((n + 255) / 256), nsub), dim3(256), 0, s, V, rows, M_of, s_of, seed);
+}
+
+// --------------------------------------------------------------------------------- projection
+__global__ void k_copy_col(const double* src, int lds, double* dst, int ldd, int rows) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r < rows) dst[(int64_t)r * ldd] = src[(int64_t)r * lds];
+}
+void launch_copy_col(const double* src, int lds, double* dst, int ldd, int rows, hipStream_t s) {
+  if (rows > 0) hipLaunchKernelGGL(k_copy_col, dim3((rows + 255) / 256), dim3(256), 0, s, src, lds, dst, ldd, rows);
+}
+
+// Off-diagonal block of Q^T A Q for a neighbour pair (i, j): sum over the A_0 entries that
+// couple P_i and P_j of a * V_i[p, :]^T V_j[q, :].  Writes the block and its transpose.
+__global__ __launch_bounds__(256) void k_pair_project(const int4* __restrict__ range, const int* __restrict__ trip,
+                                                      const double* __restrict__ A0, double* const* Vs,
+                                                      const int* __restrict__ ldv, const int* __restrict__ k1,
+                                                      const int* __restrict__ off, double* At, int64_t ldat) {
+  const int4 pr = range[blockIdx.x];   // (i, j, first triplet, count)
+  const int i = pr.x, j = pr.y;
+  const int ki = k1[i], kj = k1[j];
+  const double* Vi = Vs[i];
+  const double* Vj = Vs[j];
+  const int li = ldv[i], lj = ldv[j];
+  for (int o = threadIdx.x; o < ki * kj; o += 256) {
+    const int a = o / kj, b = o % kj;
+    double acc = 0.0;
+    for (int t = pr.z; t < pr.z + pr.w; ++t) {
+      const int p = trip[3 * t], q = trip[3 * t + 1], sl = trip[3 * t + 2];
+      acc += A0[sl] * Vi[(int64_t)p * li + a] * Vj[(int64_t)q * lj + b];
+    }
+    At[(int64_t)(off[i] + a) * ldat + off[j] + b] = acc;
+    At[(int64_t)(off[j] + b) * ldat + off[i] + a] = acc;
+  }
+}
+void launch_pair_project(const int4* trip_range, const int* trip, const double* A0, double* const* Vi, const int* ldv,
+                         const int* k1, const int* off, double* At, int64_t ldat, int npairs, hipStream_t s) {
+  if (npairs > 0)
+    hipLaunchKernelGGL(k_pair_project, dim3(npairs), dim3(256), 0, s, trip_range, trip, A0, Vi, ldv, k1, off, At, ldat);
+}
+
+// [A_ii | b_i] (k1 x (k1+1), ld) into the dense reduced system, symmetrising A_ii
+__global__ void k_scatter_block(const double* B, int k1, int ld, double* At, int64_t ldat, int off) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= k1 * k1) return;
+  const int a = i / k1, b = i % k1;
+  At[(int64_t)(off + a) * ldat + off + b] = 0.5 * (B[a * ld + b] + B[b * ld + a]);
+}
+void launch_scatter_block(const double* B, int k1, int ld, double* At, int64_t ldat, int off, hipStream_t s) {
+  hipLaunchKernelGGL(k_scatter_block, dim3((k1 * k1 + 255) / 256), dim3(256), 0, s, B, k1, ld, At, ldat, off);
+}
+
+// u~ at the owned nodes of one subdomain: u[node(p)] = V[p, :] . x_i
+__global__ void k_reconstruct(const double* V, int nP, int k1, const double* x, const int* nodes, double* u) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= nP) return;
+  double acc = 0.0;
+  for (int a = 0; a < k1; ++a) acc += V[(int64_t)p * k1 + a] * x[a];
+  u[nodes[p]] = acc;
+}
+void launch_reconstruct(const double* V, int nP, int k1, const double* x, const int* nodes, double* u, hipStream_t s) {
+  if (nP > 0) hipLaunchKernelGGL(k_reconstruct, dim3((nP + 255) / 256), dim3(256), 0, s, V, nP, k1, x, nodes, u);
+}
+
+}  // namespace mor

@@ -1,0 +1,97 @@
+"""CPU checks of the C-ABI library: it loads, exports every declared entry point, and its
+host-side decomposition (index sets I, B, V_i, P_i and the neighbour pairs) equals the
+oracle's independent derivation (bit-exact integer work)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import workloads as w
+from oracle import decomp
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    h = open(os.path.join(ROOT, "include", "mor.h")).read()
+    return sorted(set(re.findall(r"^\s*(?:int|void|const char\*)\s+(mor_\w+)\s*\(", h, re.M)))
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2404_06260_amd import mor
+    lib = ctypes.CDLL(mor.LIB_PATH)
+    declared = _declared()
+    assert len(declared) >= 20
+    for name in declared:
+        assert hasattr(lib, name), name
+    assert set(declared) == set(mor.EXPORTED)
+
+
+def _host_ctx(p):
+    from paper_2404_06260_amd import mor
+    o = mor.mor_default_opts()
+    o.host_only = 1
+    m, sd = p.mesh, p.subdomains
+    return mor.mor_create(m.xyz, m.tets, m.dirichlet, p.kappa, p.f_nodal, sd.ext_tet_ptr, sd.ext_tets, sd.in_core, o)
+
+
+@pytest.mark.parametrize("case", ["C1", "uneven", "jitter"])
+def test_host_decomposition_matches_oracle(case):
+    from paper_2404_06260_amd import mor
+    if case == "C1":
+        p = w.make_config("C1")
+    elif case == "uneven":
+        rng = np.random.default_rng(3)
+        cuts = tuple(w.cuts_random(14, k, 3, rng) for k in (3, 2, 2))
+        p = w.make_problem(14, cuts=cuts, r=2)
+    else:
+        p = w.make_problem(10, (2, 2, 1), r=2, jitter=0.2, seed=1)
+    ctx = _host_ctx(p)
+    try:
+        sets = decomp.all_local_sets(p.mesh, p.subdomains)
+        for i, s in enumerate(sets):
+            nP, nV, nI, nB = mor.mor_get_sizes(ctx, i)
+            nodes = mor.mor_get_nodes(ctx, i)
+            assert (nP, nV, nI, nB) == (s.P.size, s.V.size, s.I.size, s.B.size)
+            np.testing.assert_array_equal(nodes[:nP], s.P)
+            np.testing.assert_array_equal(np.sort(nodes[:nV]), s.V)
+            np.testing.assert_array_equal(np.sort(nodes[:nI]), s.I)
+            np.testing.assert_array_equal(nodes[nI:], s.B)
+        # neighbour pairs coupled through A_0 on omega_0
+        owner = decomp.owner_map(p.mesh, sets)
+        from oracle import project
+        A0, free, _ = project.omega0_stiffness(p.mesh, p.kappa, p.subdomains)
+        coo = A0.tocoo()
+        oi, oj = owner[free[coo.row]], owner[free[coo.col]]
+        ref = {(int(a), int(b)) for a, b in zip(oi, oj) if a < b}
+        got = {tuple(x) for x in mor.mor_get_pairs(ctx).tolist()}
+        assert got == ref
+    finally:
+        mor.mor_destroy(ctx)
+
+
+def test_invalid_inputs_are_rejected():
+    from paper_2404_06260_amd import mor
+    p = w.make_config("C1")
+    o = mor.mor_default_opts()
+    o.host_only = 1
+    m, sd = p.mesh, p.subdomains
+    bad = m.tets.copy()
+    bad[0, [1, 2]] = bad[0, [2, 1]]            # inverted tet
+    with pytest.raises(mor.MorError) as e:
+        mor.mor_create(m.xyz, bad, m.dirichlet, p.kappa, None, sd.ext_tet_ptr, sd.ext_tets, sd.in_core, o)
+    assert e.value.code == mor.MOR_EINVAL
+    # cores overlapping by two layers: not a partition of the free nodes
+    p2 = w.make_problem(8, (2, 1, 1), r=1)
+    core = p2.subdomains.in_core.copy()
+    core[:] = 1
+    with pytest.raises(mor.MorError):
+        mor.mor_create(p2.mesh.xyz, p2.mesh.tets, p2.mesh.dirichlet, p2.kappa, None, p2.subdomains.ext_tet_ptr,
+                       p2.subdomains.ext_tets, core, o)
+    # extension r = 0: omega_i reaches the boundary of omega_i^+
+    p3 = w.make_problem(8, (2, 1, 1), r=0)
+    with pytest.raises(mor.MorError):
+        mor.mor_create(p3.mesh.xyz, p3.mesh.tets, p3.mesh.dirichlet, p3.kappa, None, p3.subdomains.ext_tet_ptr,
+                       p3.subdomains.ext_tets, p3.subdomains.in_core, o)
