@@ -569,6 +569,21 @@ static int cg_solve(mor_ctx* c, CgState& cs, const std::vector<int>& sys_sub, co
   return 0;
 }
 
+// ------------------------------------------------------------------------------- debug dumps
+// MOR_DUMP=<dir> writes intermediate device arrays of the first batch slot as raw files.
+static void dump(mor_ctx* c, const char* name, const void* dptr, size_t bytes) {
+  const char* dir = getenv("MOR_DUMP");
+  if (!dir || !dptr || !bytes) return;
+  std::vector<char> h(bytes);
+  if (hipStreamSynchronize(c->st) != hipSuccess) return;
+  if (hipMemcpy(h.data(), dptr, bytes, hipMemcpyDeviceToHost) != hipSuccess) return;
+  const std::string path = std::string(dir) + "/" + name + ".bin";
+  FILE* f = fopen(path.c_str(), "wb");
+  if (!f) return;
+  fwrite(h.data(), 1, bytes, f);
+  fclose(f);
+}
+
 // ------------------------------------------------------------------------------- truncation
 // Number of leading singular triplets kept: top-`rank` (rank > 0) or sigma > tol, widened to
 // the end of a cluster of equal singular values (relative gap <= 1e-4) so the kept span is
@@ -800,6 +815,14 @@ static int local_batch_t(mor_ctx* c, std::vector<Slot>& slots) {
   dfree(c, cs.d_tiles_buf);
   if (rc) return rc;
 
+  {
+    Slot& q = slots[0];
+    const HostSub& h = *q.h;
+    dump(c, "A64", q.A64, 8 * (size_t)h.rp[h.nL]);
+    dump(c, "K64", q.K64, 8 * (size_t)h.rp[h.nL]);
+    dump(c, "Ki64", q.Ki64, 8 * (size_t)h.rpV[h.nV]);
+    dump(c, "f", q.f, 8 * (size_t)h.nL);
+  }
   // ---- FP64 views of the solutions
   for (auto& q : slots) {
     const HostSub& h = *q.h;
@@ -825,6 +848,15 @@ static int local_batch_t(mor_ctx* c, std::vector<Slot>& slots) {
     launch_schur(q.d->rp, q.d->col, q.K64, h.nI, h.nB, q.Ec, q.ldEc, q.S, q.MP, st);
     launch_pad_identity(q.S, q.M, q.MP, st);
     launch_symmetrize(q.S, q.MP, st);
+  }
+  {
+    Slot& q = slots[0];
+    const HostSub& h = *q.h;
+    dump(c, "Xc", q.Xc, 8 * (size_t)h.nV * q.ldXc);
+    dump(c, "Ec", q.Ec, 8 * (size_t)h.nI * q.ldEc);
+    dump(c, "Y", q.Y, 8 * (size_t)h.nV * q.ldK);
+    dump(c, "G", q.G, 8 * (size_t)q.MP * q.MP);
+    dump(c, "S", q.S, 8 * (size_t)q.MP * q.MP);
   }
   // ---- R = chol(S_B), C = R^-T G1 R^-1
   std::vector<DenseSub> hds(ns);
@@ -874,6 +906,13 @@ static int local_batch_t(mor_ctx* c, std::vector<Slot>& slots) {
     launch_trsm_lt(dds, dtd + ns, ns, tmax, st);
   }
   for (auto& q : slots) launch_symmetrize(q.C, q.MP, st);
+  {
+    Slot& q = slots[0];
+    dump(c, "R", q.S, 8 * (size_t)q.MP * q.MP);
+    dump(c, "W", q.W, 8 * (size_t)q.MP * q.MP);
+    dump(c, "C", q.C, 8 * (size_t)q.MP * q.MP);
+    dump(c, "Dinv", q.Dinv, 8 * (size_t)q.T * 4096);
+  }
 
   // ---- top eigenpairs of C by subspace iteration with Rayleigh-Ritz
   int smax = 0, maxrows = 0;
@@ -950,6 +989,18 @@ static int local_batch_t(mor_ctx* c, std::vector<Slot>& slots) {
       HIPCHK(hipMemcpyAsync(&hres[(size_t)i * 64], slots[i].resid, 8 * slots[i].s, hipMemcpyDeviceToHost, st));
     }
     HIPCHK(hipStreamSynchronize(st));
+    if (getenv("MOR_DUMP") && (eig_it < 3 || eig_it % 50 == 0)) {
+      fprintf(stderr, "eig it %d theta0 %.6e th[1] %.6e res0 %.3e res_last %.3e\n", eig_it, hth[0], hth[1],
+              std::sqrt(std::max(hres[0], 0.0)), std::sqrt(std::max(hres[slots[0].nconv - 1], 0.0)));
+      if (eig_it == 0) {
+        Slot& q = slots[0];
+        dump(c, "Vb0", q.Vb, 8 * (size_t)q.MP * q.s);
+        dump(c, "Yb0", q.Yb, 8 * (size_t)q.MP * q.s);
+        dump(c, "H0", q.H, 8 * (size_t)q.s * q.s);
+        dump(c, "Ss0", q.Ss, 8 * (size_t)q.s * q.s);
+        dump(c, "th0", q.theta, 8 * (size_t)q.s);
+      }
+    }
     converged = true;
     for (int i = 0; i < ns && converged; ++i) {
       const double t0 = std::max(hth[(size_t)i * 64], 1e-300);
@@ -1157,7 +1208,7 @@ extern "C" int mor_project(mor_ctx* c) {
       vp[i] = c->res[i].d_V;
       ldv[i] = k1[i] = c->res[i].k_eff + 1;
     }
-    const size_t bytes = sizeof(int4) * npairs + 4 * c->om0.trip.size() + sizeof(double*) * n + 4 * 3 * (size_t)n + 1024;
+    const size_t bytes = sizeof(int4) * npairs + 4 * c->om0.trip.size() + sizeof(double*) * n + 4 * 3 * (size_t)n + 8 * 256;
     char* buf = (char*)dalloc(c, bytes);
     if (!buf) {
       dfree(c, A0);
@@ -1170,6 +1221,11 @@ extern "C" int mor_project(mor_ctx* c) {
     int* d_ldv = (int*)ar.take(4 * n);
     int* d_k1 = (int*)ar.take(4 * n);
     int* d_off = (int*)ar.take(4 * n);
+    if (!d_off) {
+      dfree(c, buf);
+      dfree(c, A0);
+      return fail(MOR_ENOMEM, "arena exhausted (pairs)");
+    }
     HIPCHK(hipMemcpyAsync(d_range, range.data(), sizeof(int4) * npairs, hipMemcpyHostToDevice, st));
     HIPCHK(hipMemcpyAsync(d_trip, c->om0.trip.data(), 4 * c->om0.trip.size(), hipMemcpyHostToDevice, st));
     HIPCHK(hipMemcpyAsync(d_vp, vp.data(), sizeof(double*) * n, hipMemcpyHostToDevice, st));

@@ -696,7 +696,7 @@ void launch_symmetrize(double* S, int MP, hipStream_t s) {
 // --------------------------------------------------------------------------------- FP64 MFMA tiles
 // A 64 x 64 output tile per 256-thread workgroup; wave (wr, wc) owns a 32 x 32 quarter made
 // of 2 x 2 blocks of v_mfma_f64_16x16x4 (A: lane -> row lane%16, k lane/16; B: lane -> col
-// lane%16, k lane/16; D: lane -> col lane%16, rows 4*(lane/16) + 0..3).
+// lane%16, k lane/16; D: lane -> col lane%16, register r -> row lane/16 + 4r).
 constexpr int kLdsPad = 68;
 
 template <bool TA, bool TB>
@@ -765,7 +765,7 @@ __device__ __forceinline__ void tile_store(double* C, int ldc, int m, int n, int
     for (int b = 0; b < 2; ++b)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int i = i0 + wr * 32 + a * 16 + 4 * (lane >> 4) + r;
+        const int i = i0 + wr * 32 + a * 16 + (lane >> 4) + 4 * r;
         const int j = j0 + wc * 32 + b * 16 + (lane & 15);
         if (i < m && j < n) {
           double* p = C + (int64_t)i * ldc + j;
@@ -785,7 +785,7 @@ __device__ __forceinline__ void tile_store_sym(double* C, int ldc, int m, int i0
     for (int b = 0; b < 2; ++b)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int i = i0 + wr * 32 + a * 16 + 4 * (lane >> 4) + r;
+        const int i = i0 + wr * 32 + a * 16 + (lane >> 4) + 4 * r;
         const int j = j0 + wc * 32 + b * 16 + (lane & 15);
         if (i < m && j < m && (!diag || i <= j)) {
           const double v = alpha * acc[a][b][r];
@@ -940,7 +940,7 @@ __global__ __launch_bounds__(256) void k_trsm_lt(const DenseSub* __restrict__ ds
       for (int b = 0; b < 2; ++b)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const int i = p * 64 + wr * 32 + a * 16 + 4 * (lane >> 4) + r;
+          const int i = p * 64 + wr * 32 + a * 16 + (lane >> 4) + 4 * r;
           const int j = c * 64 + wc * 32 + b * 16 + (lane & 15);
           const double bv = td.tb ? Bm[(int64_t)j * ldb + i] : Bm[(int64_t)i * ldb + j];
           X[(int64_t)i * ldx + j] = bv - acc[a][b][r];
@@ -989,7 +989,7 @@ __global__ __launch_bounds__(256) void k_trsm_un(const DenseSub* __restrict__ ds
       for (int b = 0; b < 2; ++b)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const int i = p * 64 + wr * 32 + a * 16 + 4 * (lane >> 4) + r;
+          const int i = p * 64 + wr * 32 + a * 16 + (lane >> 4) + 4 * r;
           const int j = wc * 32 + b * 16 + (lane & 15);
           X[(int64_t)i * 64 + j] = Bm[(int64_t)i * 64 + j] - acc[a][b][r];
         }

@@ -21,7 +21,7 @@ from oracle import solve as osolve
 
 pytestmark = pytest.mark.gpu
 
-TOL_ENERGY = {"fp64": 1e-9, "fp32_refine": 1e-6, "fp32": 1e-6}
+TOL_ENERGY = {"fp64": 1e-9, "fp32_refine": 1e-6, "fp32": 1e-4}   # fp32: CG to 1e-5, no FP64 refinement
 TOL_SIGMA = {"fp64": 1e-9, "fp32_refine": 1e-7, "fp32": 1e-4}
 TOL_ANGLE = {"fp64": 1e-7, "fp32_refine": 1e-5, "fp32": 1e-2}
 
