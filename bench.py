@@ -68,6 +68,8 @@ def main():
     ap.add_argument("--spmm-rows", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
+    ap.add_argument("--calibrate-copy", type=int, default=0,
+                    help="MiB copied by one plain device copy before the steps (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU; multi-GPU sharding of the subdomains is a "
@@ -83,7 +85,14 @@ def main():
     prec = args.precision or PRECISION_OF[args.config]
     p = w.make_config(args.config)
     print(f"[bench] {args.config}: {p.subdomains.n_sub} subdomains, precision {prec}", file=sys.stderr, flush=True)
-    m = mor.Mor(p, precision=prec, spmm_rows=args.spmm_rows)
+    spmm_vec, spmm_rows = 0, args.spmm_rows
+    if not spmm_rows:
+        from paper_2404_06260_amd import autotune
+        tuned = autotune.best(p, prec)
+        if tuned:
+            spmm_vec, spmm_rows = tuned
+            print(f"[bench] autotuned SpMM tile: {64 * spmm_vec} columns x {spmm_rows} rows", file=sys.stderr, flush=True)
+    m = mor.Mor(p, precision=prec, spmm_rows=spmm_rows, spmm_vec=spmm_vec)
     n_sub = p.subdomains.n_sub
 
     def step():
@@ -91,6 +100,12 @@ def main():
         m.project()
         return m.solve()
 
+    if args.calibrate_copy:
+        src = torch.ones(args.calibrate_copy * (1 << 20) // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     for i in range(args.warmup):
         step()
         print(f"[bench] warmup {i} done", file=sys.stderr, flush=True)
@@ -136,7 +151,8 @@ def main():
         "dtype": {"fp64": "f64", "fp32_refine": "f32+f64", "fp32": "f32", "bf16_split": "bf16+f32"}[prec],
         "data": "synthetic",
         "config": {"workload": WORKLOAD_OF[args.config], "name": args.config, "subdomains": n_sub,
-                   "precision": prec, "reduced_dim": int(nred)},
+                   "precision": prec, "reduced_dim": int(nred),
+                   "spmm_tile": [64 * (spmm_vec or 4), spmm_rows or 32]},
         "roofline": {"bound": "hbm", "kernel": "k_cg_spmm (block-CG SpMM Q = A_II P)", "achieved": round(achieved, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": None, "avg_launch_ms": round(avg_ms, 4), "launches": n_launch,

@@ -96,6 +96,7 @@ typedef struct {
   int32_t eig_max_iter;    /* subspace iteration cap */
   int32_t cg_chunk;        /* CG iterations launched between two convergence polls */
   int32_t spmm_rows;       /* rows per SpMM workgroup tile (0 = automatic) */
+  int32_t spmm_vec;        /* SpMM tile width in units of 64 columns: 1, 2 or 4 (0 = automatic) */
   int32_t use_graph;       /* capture each CG chunk in a HIP graph and replay it */
   size_t hbm_budget_bytes; /* device bytes one batch of local reductions may use (0 = 75% free) */
   mor_alloc_fn dev_alloc;  /* NULL: hipMalloc */
@@ -106,7 +107,7 @@ typedef struct {
                               only mor_get_sizes / mor_get_nodes / mor_get_pairs may follow */
 } mor_opts;
 
-/* Fill `opts` with defaults (FP32_REFINE, cg_rtol 1e-5, refine_rtol 1e-10, ...). */
+/* Fill `opts` with defaults (FP32_REFINE, cg_rtol 1e-5, refine_rtol 1e-8, ...). */
 void mor_default_opts(mor_opts* opts);
 
 /* Validate the inputs, derive the index sets I, B, V_i, P_i (Sections 3-4),

@@ -192,7 +192,7 @@ extern "C" void mor_default_opts(mor_opts* o) {
   std::memset(o, 0, sizeof(*o));
   o->precision = MOR_FP32_REFINE;
   o->cg_rtol = 1e-5;
-  o->refine_rtol = 1e-10;
+  o->refine_rtol = 1e-8;
   o->max_iter = 4000;
   o->refine_steps = 3;
   o->oversample = 0;
@@ -425,30 +425,55 @@ static GemmDesc gd(int m, int n, int k, const double* A, int lda, int ta, const 
 }
 
 // ------------------------------------------------------------------------------- block CG
+struct TileCfg {
+  int v = 4;    // elements per lane: tile width 64 v columns
+  int rb = 32;  // rows per tile
+};
+
 struct CgState {
   std::vector<CgSys> hsys;
   CgSys* dsys = nullptr;
   CgCols cols{};
-  int* d_tiles_buf = nullptr;
+  int* d_tiles_buf = nullptr;   // SpMM tiles, then streaming tiles
   size_t tiles_cap = 0;
-  int* h_nactive = nullptr;   // pinned
+  int* h_nactive = nullptr;     // pinned
   std::vector<int> iters;
-  int rb = 32;
-  int elt = 4;                // bytes of the CG scalar type
+  TileCfg sp, stm;              // SpMM-like kernels (neighbour reads) and streaming kernels
+  int elt = 4;                  // bytes of the CG scalar type
 };
 
 // tiles of the active systems: (system, first row, first column), row blocks fastest so that
 // consecutive tiles (one XCD) sweep the rows of one column slab
-static std::vector<int4> make_tiles(const CgState& cs, const std::vector<char>& act) {
-  std::vector<int4> t;
-  const int W = cs.elt == 4 ? 256 : 128;   // columns per tile (64 lanes x 16 bytes)
+static void make_tiles(const CgState& cs, const std::vector<char>& act, const TileCfg& tc, std::vector<int4>& t) {
+  const int W = 64 * tc.v;
   for (size_t s = 0; s < cs.hsys.size(); ++s) {
     if (!act[s]) continue;
     const CgSys& S = cs.hsys[s];
     for (int c0 = 0; c0 < S.ld; c0 += W)
-      for (int r0 = 0; r0 < S.nI; r0 += cs.rb) t.push_back(make_int4((int)s, r0, c0, 0));
+      for (int r0 = 0; r0 < S.nI; r0 += tc.rb) t.push_back(make_int4((int)s, r0, c0, 0));
   }
-  return t;
+}
+
+// Both tile lists of the active systems in one device buffer: [spmm tiles | streaming tiles].
+static int upload_tiles(mor_ctx* c, CgState& cs, const std::vector<char>& act, int4** sp, int* nsp, int4** st,
+                        int* nst) {
+  std::vector<int4> t;
+  make_tiles(cs, act, cs.sp, t);
+  *nsp = (int)t.size();
+  make_tiles(cs, act, cs.stm, t);
+  *nst = (int)t.size() - *nsp;
+  if (t.size() > cs.tiles_cap) {
+    dfree(c, cs.d_tiles_buf);
+    cs.tiles_cap = t.size() + t.size() / 2;
+    cs.d_tiles_buf = (int*)dalloc(c, sizeof(int4) * cs.tiles_cap);
+    if (!cs.d_tiles_buf) return fail(MOR_ENOMEM, "tile list allocation failed");
+  }
+  if (!t.empty())
+    HIPCHK(hipMemcpyAsync(cs.d_tiles_buf, t.data(), sizeof(int4) * t.size(), hipMemcpyHostToDevice, c->st));
+  HIPCHK(hipStreamSynchronize(c->st));   // t is pageable host memory
+  *sp = (int4*)cs.d_tiles_buf;
+  *st = *sp + *nsp;
+  return 0;
 }
 
 // algorithmic bytes of one SpMM over the active systems: CSR of A_II + read P once + write Q
@@ -473,32 +498,25 @@ static int cg_iterate(mor_ctx* c, CgState& cs, std::vector<char>& act, double to
     for (int s = 0; s < nsys; ++s) any |= act[s] != 0;
     if (!any) break;
     if (it >= c->opts.max_iter) return fail(MOR_ENOTCONV, "block CG did not converge within max_iter");
-    std::vector<int4> tiles = make_tiles(cs, act);
+    int4 *dsp, *dst;
+    int nsp, nst;
+    if (int rc = upload_tiles(c, cs, act, &dsp, &nsp, &dst, &nst)) return rc;
     const double by = spmm_bytes(cs, act, sys_nnz);
-    if (tiles.size() > cs.tiles_cap) {
-      dfree(c, cs.d_tiles_buf);
-      cs.tiles_cap = tiles.size() * 2;
-      cs.d_tiles_buf = (int*)dalloc(c, sizeof(int4) * cs.tiles_cap);
-      if (!cs.d_tiles_buf) return fail(MOR_ENOMEM, "tile list allocation failed");
-    }
-    int4* dt = (int4*)cs.d_tiles_buf;
-    HIPCHK(hipMemcpyAsync(dt, tiles.data(), sizeof(int4) * tiles.size(), hipMemcpyHostToDevice, c->st));
-    const int nt = (int)tiles.size();
     const double tol2 = tol * tol;
     for (int k = 0; k < chunk; ++k) {
       {
         ScopedTimer tm(c, "spmm", by);
-        launch_cg_spmm<T>(cs.dsys, dt, nt, cs.rb, cs.cols, c->st);
+        launch_cg_spmm<T>(cs.dsys, dsp, nsp, cs.sp.rb, cs.sp.v, cs.cols, c->st);
       }
       launch_cg_alpha(cs.cols, c->st);
       {
         ScopedTimer tm(c, "cg_update", 0);
-        launch_cg_update<T>(cs.dsys, dt, nt, cs.rb, cs.cols, c->st);
+        launch_cg_update<T>(cs.dsys, dst, nst, cs.stm.rb, cs.stm.v, cs.cols, c->st);
       }
       launch_cg_beta(cs.cols, tol2, c->st);
       {
         ScopedTimer tm(c, "cg_direction", 0);
-        launch_cg_direction<T>(cs.dsys, dt, nt, cs.rb, cs.cols, c->st);
+        launch_cg_direction<T>(cs.dsys, dst, nst, cs.stm.rb, cs.stm.v, cs.cols, c->st);
       }
     }
     HIPCHK(hipGetLastError());
@@ -520,30 +538,36 @@ static int cg_solve(mor_ctx* c, CgState& cs, const std::vector<int>& sys_sub, co
   const bool refine = c->opts.precision == MOR_FP32_REFINE;
   const double inner = (c->opts.precision == MOR_FP64) ? c->opts.refine_rtol : c->opts.cg_rtol;
   std::vector<char> all(nsys, 1), act(nsys, 1);
-  std::vector<int4> tiles_all = make_tiles(cs, all);
-  int4* dta = (int4*)dalloc(c, sizeof(int4) * std::max<size_t>(1, tiles_all.size()));
-  if (!dta) return fail(MOR_ENOMEM, "tile list allocation failed");
-  HIPCHK(hipMemcpyAsync(dta, tiles_all.data(), sizeof(int4) * tiles_all.size(), hipMemcpyHostToDevice, c->st));
-  const int nta = (int)tiles_all.size();
+  // tile lists over every system (init, refinement passes) kept apart from the iteration lists
+  std::vector<int4> ta;
+  make_tiles(cs, all, cs.sp, ta);
+  const int nta_sp = (int)ta.size();
+  make_tiles(cs, all, cs.stm, ta);
+  const int nta = (int)ta.size() - nta_sp;
+  int4* dta_sp = (int4*)dalloc(c, sizeof(int4) * std::max<size_t>(1, ta.size()));
+  if (!dta_sp) return fail(MOR_ENOMEM, "tile list allocation failed");
+  int4* dta = dta_sp + nta_sp;
+  HIPCHK(hipMemcpyAsync(dta_sp, ta.data(), sizeof(int4) * ta.size(), hipMemcpyHostToDevice, c->st));
+  HIPCHK(hipStreamSynchronize(c->st));
   launch_fill(cs.cols.rz, cs.cols.ncols_total, 0.0, c->st);
-  launch_cg_init<T>(cs.dsys, dta, nta, cs.rb, cs.cols, c->st);
+  launch_cg_init<T>(cs.dsys, dta, nta, cs.stm.rb, cs.stm.v, cs.cols, c->st);
   launch_cg_start(cs.cols, 1, 0.0, c->st);
   HIPCHK(hipMemcpyAsync(cs.h_nactive, cs.cols.nactive, sizeof(int) * nsys, hipMemcpyDeviceToHost, c->st));
   HIPCHK(hipStreamSynchronize(c->st));
   for (int s = 0; s < nsys; ++s) act[s] = cs.h_nactive[s] > 0;
   int rc = cg_iterate<T>(c, cs, act, inner, sys_sub, sys_nnz);
   if (rc) {
-    dfree(c, dta);
+    dfree(c, dta_sp);
     return rc;
   }
   if (refine) {
     const double outer2 = c->opts.refine_rtol * c->opts.refine_rtol;
     for (int step = 0; step < c->opts.refine_steps; ++step) {
-      launch_cg_shadow<T>(cs.dsys, dta, nta, cs.rb, c->st);
+      launch_cg_shadow<T>(cs.dsys, dta, nta, cs.stm.rb, cs.stm.v, c->st);
       launch_fill(cs.cols.rz, cs.cols.ncols_total, 0.0, c->st);
       {
         ScopedTimer tm(c, "residual64", 0);
-        launch_cg_residual64<T>(cs.dsys, dta, nta, cs.rb, cs.cols, c->st);
+        launch_cg_residual64<T>(cs.dsys, dta_sp, nta_sp, cs.sp.rb, cs.sp.v, cs.cols, c->st);
       }
       launch_cg_restart(cs.cols, outer2, c->st);
       HIPCHK(hipMemcpyAsync(cs.h_nactive, cs.cols.nactive, sizeof(int) * nsys, hipMemcpyDeviceToHost, c->st));
@@ -557,15 +581,15 @@ static int cg_solve(mor_ctx* c, CgState& cs, const std::vector<int>& sys_sub, co
       if (!any) break;
       rc = cg_iterate<T>(c, cs, act, inner, sys_sub, sys_nnz);
       if (rc) {
-        dfree(c, dta);
+        dfree(c, dta_sp);
         return rc;
       }
     }
-    launch_cg_shadow<T>(cs.dsys, dta, nta, cs.rb, c->st);
+    launch_cg_shadow<T>(cs.dsys, dta, nta, cs.stm.rb, cs.stm.v, c->st);
   }
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(c->st));
-  dfree(c, dta);
+  dfree(c, dta_sp);
   return 0;
 }
 
@@ -763,7 +787,13 @@ static int local_batch_t(mor_ctx* c, std::vector<Slot>& slots) {
   // ---- block CG on A_II (lifting + load) and K_II (H1 extension for S_B)
   CgState cs;
   cs.elt = elt;
-  cs.rb = c->opts.spmm_rows > 0 ? c->opts.spmm_rows : 32;
+  // SpMM tiles: 64 columns (256 B of FP32 per row) x 32 rows keep one XCD's rows in flight
+  // and their stencil halo inside its L2; streaming kernels use 16-byte lanes.
+  cs.sp.v = c->opts.spmm_vec > 0 ? c->opts.spmm_vec : 4;
+  cs.sp.rb = c->opts.spmm_rows > 0 ? std::min(c->opts.spmm_rows, 64) : 8;
+  if (!fp32 && cs.sp.v > 2) cs.sp.v = 2;
+  cs.stm.v = fp32 ? 4 : 2;
+  cs.stm.rb = 32;
   std::vector<int> sys_sub(nsys), sys_nnz(nsys);
   std::vector<int> sys_of_col(total_cols);
   int coff = 0;

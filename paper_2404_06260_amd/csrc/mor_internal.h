@@ -97,18 +97,19 @@ void launch_to_f32(const double* in, float* out, int64_t n, hipStream_t s);
 void launch_diag_inv(const int* rp, const int* col, const double* v64, int nI, void* dinv, int is_double,
                      hipStream_t s);
 
+// v = elements per lane (tile width 64 v columns): 1, 2 or 4 for float, 1 or 2 for double
 template <typename T>
-void launch_cg_init(const CgSys* sys, const int4* tiles, int ntiles, int rb, CgCols cols, hipStream_t s);
+void launch_cg_init(const CgSys* sys, const int4* tiles, int ntiles, int rb, int v, CgCols cols, hipStream_t s);
 template <typename T>
-void launch_cg_spmm(const CgSys* sys, const int4* tiles, int ntiles, int rb, CgCols cols, hipStream_t s);
+void launch_cg_spmm(const CgSys* sys, const int4* tiles, int ntiles, int rb, int v, CgCols cols, hipStream_t s);
 template <typename T>
-void launch_cg_update(const CgSys* sys, const int4* tiles, int ntiles, int rb, CgCols cols, hipStream_t s);
+void launch_cg_update(const CgSys* sys, const int4* tiles, int ntiles, int rb, int v, CgCols cols, hipStream_t s);
 template <typename T>
-void launch_cg_direction(const CgSys* sys, const int4* tiles, int ntiles, int rb, CgCols cols, hipStream_t s);
+void launch_cg_direction(const CgSys* sys, const int4* tiles, int ntiles, int rb, int v, CgCols cols, hipStream_t s);
 template <typename T>
-void launch_cg_residual64(const CgSys* sys, const int4* tiles, int ntiles, int rb, CgCols cols, hipStream_t s);
+void launch_cg_residual64(const CgSys* sys, const int4* tiles, int ntiles, int rb, int v, CgCols cols, hipStream_t s);
 template <typename T>
-void launch_cg_shadow(const CgSys* sys, const int4* tiles, int ntiles, int rb, hipStream_t s);
+void launch_cg_shadow(const CgSys* sys, const int4* tiles, int ntiles, int rb, int v, hipStream_t s);
 void launch_cg_alpha(CgCols cols, hipStream_t s);
 void launch_cg_beta(CgCols cols, double tol2, hipStream_t s);
 void launch_cg_start(CgCols cols, int first, double tol2_first, hipStream_t s);

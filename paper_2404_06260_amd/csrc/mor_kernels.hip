@@ -15,6 +15,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 namespace mor {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
@@ -174,30 +176,42 @@ void launch_diag_inv(const int* rp, const int* col, const double* v64, int nI, v
 }
 
 // --------------------------------------------------------------------------------- block CG
-// A tile = (system, first row, first column); a wave owns 64 * VEC consecutive columns
-// (VEC = 16 bytes of the scalar type per lane) and rows wave, wave+4, ... of the block.
-template <typename T> struct VecT;
-template <> struct VecT<float> { static constexpr int N = 4; };
-template <> struct VecT<double> { static constexpr int N = 2; };
+// A tile = (system, first row, first column).  A wave owns 64 * V consecutive columns (V
+// elements per lane) and rows wave, wave + 4, ... of the tile's row block.  The SpMM tile width
+// (64 V) and rows per tile are tuned so that the rows in flight on one XCD plus the stencil halo
+// of the neighbour rows stay inside that XCD's L2; the streaming kernels use wide tiles.
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+template <int B> struct Raw;
+template <> struct Raw<4> { using t = uint32_t; };
+template <> struct Raw<8> { using t = u32x2; };
+template <> struct Raw<16> { using t = u32x4; };
 
-template <typename T>
-__device__ __forceinline__ void ld_vec(const T* p, T (&v)[VecT<T>::N]) {
-  *reinterpret_cast<uint4*>(v) = *reinterpret_cast<const uint4*>(p);
+// Pointers read from descriptors are generic; casting them to the global address space lets
+// the compiler emit global_load/global_store instead of flat accesses.
+#define MOR_GLOBAL __attribute__((address_space(1)))
+template <typename T, int V>
+__device__ __forceinline__ void ld_vec(const T* p, T (&v)[V]) {
+  using R = typename Raw<V * sizeof(T)>::t;
+  *reinterpret_cast<R*>(v) = *((const MOR_GLOBAL R*)(p));
+}
+template <typename T, int V>
+__device__ __forceinline__ void st_vec(T* p, const T (&v)[V]) {
+  using R = typename Raw<V * sizeof(T)>::t;
+  *((MOR_GLOBAL R*)(p)) = *reinterpret_cast<const R*>(v);
 }
 template <typename T>
-__device__ __forceinline__ void st_vec(T* p, const T (&v)[VecT<T>::N]) {
-  *reinterpret_cast<uint4*>(p) = *reinterpret_cast<const uint4*>(v);
-}
+__device__ __forceinline__ T gld(const T* p) { return *((const MOR_GLOBAL T*)(p)); }
 
 // Sum a per-lane partial over the 4 waves and add it to a per-column FP64 accumulator.
-template <int N>
-__device__ __forceinline__ void column_reduce_add(double (*red)[64 * 4], const double (&part)[N], int c0tile, int ld,
+template <int V>
+__device__ __forceinline__ void column_reduce_add(double (*red)[64 * 4], const double (&part)[V], int c0tile, int ld,
                                                   double* __restrict__ acc) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
 #pragma unroll
-  for (int v = 0; v < N; ++v) red[w][lane * N + v] = part[v];
+  for (int v = 0; v < V; ++v) red[w][lane * V + v] = part[v];
   __syncthreads();
-  for (int i = threadIdx.x; i < 64 * N; i += 256) {
+  for (int i = threadIdx.x; i < 64 * V; i += 256) {
     const int c = c0tile + i;
     if (c < ld) {
       const double s = red[0][i] + red[1][i] + red[2][i] + red[3][i];
@@ -207,309 +221,336 @@ __device__ __forceinline__ void column_reduce_add(double (*red)[64 * 4], const d
 }
 
 // sparse right-hand side entries of row r: -A_IB[r, :] and the load column
-template <typename TT, int N>
-__device__ __forceinline__ void rhs_row(const CgSys& S, int r, int c0, TT (&v)[N]) {
+template <typename TT, int V>
+__device__ __forceinline__ void rhs_row(const CgSys& S, int r, int c0, TT (&v)[V]) {
 #pragma unroll
-  for (int q = 0; q < N; ++q) v[q] = 0;
+  for (int q = 0; q < V; ++q) v[q] = 0;
   const int e1 = S.rp[r + 1];
   for (int e = S.ii_end[r]; e < e1; ++e) {
     const int j = S.col[e] - S.nI - c0;
-    if (j >= 0 && j < N) {
+    if (j >= 0 && j < V) {
 #pragma unroll
-      for (int q = 0; q < N; ++q)
+      for (int q = 0; q < V; ++q)
         if (q == j) v[q] = (TT)(-S.val64[e]);
     }
   }
   if (S.f != nullptr) {
     const int j = S.nB - c0;
-    if (j >= 0 && j < N) {
+    if (j >= 0 && j < V) {
 #pragma unroll
-      for (int q = 0; q < N; ++q)
+      for (int q = 0; q < V; ++q)
         if (q == j) v[q] = (TT)S.f[r];
     }
   }
 }
 
-template <typename T>
+#define MOR_TILE_PROLOGUE(V)                                  \
+  const int t = xcd_tile(blockIdx.x, ntiles);                 \
+  if (t >= ntiles) return;                                    \
+  const int4 tl = tiles[t];                                   \
+  const CgSys& S = sys[tl.x];                                 \
+  const int lane = threadIdx.x & 63, w = wave_id();           \
+  const int c0 = tl.z + lane * (V);                           \
+  const bool act = c0 < S.ld;                                 \
+  const int ld = S.ld;                                        \
+  const int rend = min(tl.y + rb, S.nI);
+
+template <typename T, int V>
 __global__ __launch_bounds__(256) void k_cg_init(const CgSys* __restrict__ sys, const int4* __restrict__ tiles, int ntiles,
                                                  int rb, CgCols cols) {
-  constexpr int N = VecT<T>::N;
   __shared__ double red[4][64 * 4];
-  const int t = xcd_tile(blockIdx.x, ntiles);
-  if (t >= ntiles) return;
-  const int4 tl = tiles[t];
-  const CgSys& S = sys[tl.x];
-  const int lane = threadIdx.x & 63, w = wave_id();
-  const int c0 = tl.z + lane * N;
-  const bool act = c0 < S.ld;
+  MOR_TILE_PROLOGUE(V)
   const T* dinv = (const T*)S.dinv;
   T* X = (T*)S.X; T* R = (T*)S.R; T* P = (T*)S.P;
-  double part[N];
+  double part[V];
 #pragma unroll
-  for (int q = 0; q < N; ++q) part[q] = 0.0;
-  const int rend = min(tl.y + rb, S.nI);
+  for (int q = 0; q < V; ++q) part[q] = 0.0;
   for (int r = tl.y + w; r < rend; r += 4) {
     if (!act) continue;
-    T v[N], z[N], p[N];
-    rhs_row<T, N>(S, r, c0, v);
+    T v[V], z[V], p[V];
+    rhs_row<T, V>(S, r, c0, v);
     const T di = dinv[r];
 #pragma unroll
-    for (int q = 0; q < N; ++q) {
+    for (int q = 0; q < V; ++q) {
       z[q] = 0;
       p[q] = di * v[q];
       part[q] += (double)v[q] * (double)p[q];
     }
-    const int64_t o = (int64_t)r * S.ld + c0;
-    st_vec<T>(R + o, v);
-    st_vec<T>(X + o, z);
-    st_vec<T>(P + o, p);
+    const int64_t o = (int64_t)r * ld + c0;
+    st_vec<T, V>(R + o, v);
+    st_vec<T, V>(X + o, z);
+    st_vec<T, V>(P + o, p);
     if (S.X64 != nullptr) {
 #pragma unroll
-      for (int q = 0; q < N; ++q) S.X64[o + q] = 0.0;
+      for (int q = 0; q < V; ++q) S.X64[o + q] = 0.0;
     }
   }
-  column_reduce_add<N>(red, part, tl.z, S.ld, cols.rz + S.coff);
+  column_reduce_add<V>(red, part, tl.z, ld, cols.rz + S.coff);
 }
 
 // Q = A_II P and the per-column p'Q: the dominant, HBM-bound kernel of the lifting.
+// The tile's CSR rows (column ids and values of the II block) are staged in LDS first, so each
+// wave issues the neighbour-row loads of a row back to back instead of chasing the CSR in
+// global memory; tiles whose rows exceed the LDS capacity read the CSR from global memory.
+constexpr int kSpmmMaxRows = 64;
+constexpr int kSpmmNnzCap = 1536;
+
+// One row of Q = A P over this lane's V columns: the CSR entries come in chunks of 8; a chunk
+// always issues 8 loads (entries past the row end read the row itself with weight 0) so the
+// loads of a chunk go out back to back without branches or waits in between.
+template <typename T, int V, typename IdxFn, typename ValFn>
+__device__ __forceinline__ void spmm_row(const T* __restrict__ P, int ld, int c0, int self, int cnt, IdxFn idx,
+                                         ValFn vals, T (&acc)[V]) {
+  for (int e = 0; e < cnt; e += 8) {
+    int cl[8];
+    T a[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const bool ok = e + k < cnt;
+      cl[k] = ok ? idx(e + k) : self;
+      a[k] = ok ? vals(e + k) : (T)0;
+    }
+    T p[8][V];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) ld_vec<T, V>(P + (int64_t)cl[k] * ld + c0, p[k]);
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+#pragma unroll
+      for (int q = 0; q < V; ++q) acc[q] += a[k] * p[k][q];
+  }
+}
+
 template <typename T>
+__device__ __forceinline__ void st_nt(T* p, T v) {
+  __builtin_nontemporal_store(v, (MOR_GLOBAL T*)p);
+}
+template <typename T>
+__device__ __forceinline__ T ld_nt(const T* p) {
+  return __builtin_nontemporal_load((const MOR_GLOBAL T*)p);
+}
+
+template <typename T, int V>
 __global__ __launch_bounds__(256) void k_cg_spmm(const CgSys* __restrict__ sys, const int4* __restrict__ tiles, int ntiles,
                                                  int rb, CgCols cols) {
-  constexpr int N = VecT<T>::N;
   __shared__ double red[4][64 * 4];
-  const int t = xcd_tile(blockIdx.x, ntiles);
-  if (t >= ntiles) return;
-  const int4 tl = tiles[t];
-  const CgSys& S = sys[tl.x];
-  const int lane = threadIdx.x & 63, w = wave_id();
-  const int c0 = tl.z + lane * N;
-  const bool act = c0 < S.ld;
-  const int ld = S.ld;
+  __shared__ int s_beg[kSpmmMaxRows + 1], s_off[kSpmmMaxRows + 1];
+  __shared__ int s_col[kSpmmNnzCap];
+  __shared__ T s_val[kSpmmNnzCap];
+  MOR_TILE_PROLOGUE(V)
   const T* __restrict__ val = (sizeof(T) == 4) ? (const T*)S.val32 : (const T*)S.val64;
   const T* __restrict__ P = (const T*)S.P;
   T* __restrict__ Q = (T*)S.Q;
-  const int* __restrict__ colp = S.col;
-  double part[N];
-#pragma unroll
-  for (int q = 0; q < N; ++q) part[q] = 0.0;
-  const int rend = min(tl.y + rb, S.nI);
-  for (int r = tl.y + w; r < rend; r += 4) {
-    const int e0 = S.rp[r], e1 = S.ii_end[r];
-    T acc[N];
-#pragma unroll
-    for (int q = 0; q < N; ++q) acc[q] = 0;
-    if (act) {
-      int e = e0;
-      for (; e + 4 <= e1; e += 4) {
-        T p0[N], p1[N], p2[N], p3[N];
-        const int ca = colp[e], cb = colp[e + 1], cc = colp[e + 2], cd = colp[e + 3];
-        const T va = val[e], vb = val[e + 1], vc = val[e + 2], vd = val[e + 3];
-        ld_vec<T>(P + (int64_t)ca * ld + c0, p0);
-        ld_vec<T>(P + (int64_t)cb * ld + c0, p1);
-        ld_vec<T>(P + (int64_t)cc * ld + c0, p2);
-        ld_vec<T>(P + (int64_t)cd * ld + c0, p3);
-#pragma unroll
-        for (int q = 0; q < N; ++q) acc[q] += va * p0[q] + vb * p1[q] + vc * p2[q] + vd * p3[q];
+  const int nr = rend - tl.y;
+  const int tid = threadIdx.x;
+  if (tid < nr) {
+    const int r = tl.y + tid;
+    s_beg[tid] = gld(S.rp + r);
+    s_off[tid + 1] = gld(S.ii_end + r) - s_beg[tid];
+  }
+  if (tid == 0) s_off[0] = 0;
+  __syncthreads();
+  if (tid == 0)
+    for (int i = 0; i < nr; ++i) s_off[i + 1] += s_off[i];
+  __syncthreads();
+  const bool staged = s_off[nr] <= kSpmmNnzCap;
+  if (staged) {
+    for (int i = w; i < nr; i += 4) {
+      const int cnt = s_off[i + 1] - s_off[i];
+      for (int e = lane; e < cnt; e += 64) {
+        s_col[s_off[i] + e] = gld(S.col + s_beg[i] + e);
+        s_val[s_off[i] + e] = gld(val + s_beg[i] + e);
       }
-      for (; e < e1; ++e) {
-        T p0[N];
-        const int ca = colp[e];
-        const T va = val[e];
-        ld_vec<T>(P + (int64_t)ca * ld + c0, p0);
-#pragma unroll
-        for (int q = 0; q < N; ++q) acc[q] += va * p0[q];
-      }
-      const int64_t o = (int64_t)r * ld + c0;
-      st_vec<T>(Q + o, acc);
-      T pr[N];
-      ld_vec<T>(P + o, pr);
-#pragma unroll
-      for (int q = 0; q < N; ++q) part[q] += (double)pr[q] * (double)acc[q];
     }
   }
-  column_reduce_add<N>(red, part, tl.z, ld, cols.pq + S.coff);
+  __syncthreads();
+  double part[V];
+#pragma unroll
+  for (int q = 0; q < V; ++q) part[q] = 0.0;
+  if (act) {
+    for (int i = w; i < nr; i += 4) {
+      const int r = tl.y + i;
+      T acc[V];
+#pragma unroll
+      for (int q = 0; q < V; ++q) acc[q] = 0;
+      const int cnt = s_off[i + 1] - s_off[i];
+      const int so = s_off[i], gb = s_beg[i];
+      if (staged)
+        spmm_row<T, V>(P, ld, c0, r, cnt, [&](int e) { return s_col[so + e]; }, [&](int e) { return s_val[so + e]; }, acc);
+      else
+        spmm_row<T, V>(P, ld, c0, r, cnt, [&](int e) { return gld(S.col + gb + e); }, [&](int e) { return gld(val + gb + e); },
+                       acc);
+      const int64_t o = (int64_t)r * ld + c0;
+#pragma unroll
+      for (int q = 0; q < V; ++q) st_nt(Q + o + q, acc[q]);
+      T pr[V];
+      ld_vec<T, V>(P + o, pr);
+#pragma unroll
+      for (int q = 0; q < V; ++q) part[q] += (double)pr[q] * (double)acc[q];
+    }
+  }
+  column_reduce_add<V>(red, part, tl.z, ld, cols.pq + S.coff);
 }
 
-// X += alpha P, R -= alpha Q, and the new r'D^-1 r.
-template <typename T>
+// R -= alpha Q and the new r'D^-1 r
+template <typename T, int V>
 __global__ __launch_bounds__(256) void k_cg_update(const CgSys* __restrict__ sys, const int4* __restrict__ tiles,
                                                    int ntiles, int rb, CgCols cols) {
-  constexpr int N = VecT<T>::N;
   __shared__ double red[4][64 * 4];
-  const int t = xcd_tile(blockIdx.x, ntiles);
-  if (t >= ntiles) return;
-  const int4 tl = tiles[t];
-  const CgSys& S = sys[tl.x];
-  const int lane = threadIdx.x & 63, w = wave_id();
-  const int c0 = tl.z + lane * N;
-  const bool act = c0 < S.ld;
-  const int ld = S.ld;
+  MOR_TILE_PROLOGUE(V)
   const T* dinv = (const T*)S.dinv;
-  T* X = (T*)S.X; T* R = (T*)S.R; const T* P = (const T*)S.P; const T* Q = (const T*)S.Q;
-  T al[N];
-  double part[N];
+  T* R = (T*)S.R; const T* Q = (const T*)S.Q;
+  T al[V];
+  double part[V];
 #pragma unroll
-  for (int q = 0; q < N; ++q) {
+  for (int q = 0; q < V; ++q) {
     part[q] = 0.0;
     al[q] = act ? (T)cols.alpha[S.coff + c0 + q] : (T)0;
   }
-  const int rend = min(tl.y + rb, S.nI);
-  for (int r = tl.y + w; r < rend; r += 4) {
-    if (!act) continue;
-    const int64_t o = (int64_t)r * ld + c0;
-    T x[N], rr[N], p[N], qq[N];
-    ld_vec<T>(X + o, x);
-    ld_vec<T>(R + o, rr);
-    ld_vec<T>(P + o, p);
-    ld_vec<T>(Q + o, qq);
-    const T di = dinv[r];
+  if (act) {
+#pragma unroll 2
+    for (int r = tl.y + w; r < rend; r += 4) {
+      const int64_t o = (int64_t)r * ld + c0;
+      T rr[V], qq[V];
+      ld_vec<T, V>(R + o, rr);
+      ld_vec<T, V>(Q + o, qq);
+      const T di = dinv[r];
 #pragma unroll
-    for (int q = 0; q < N; ++q) {
-      x[q] += al[q] * p[q];
-      rr[q] -= al[q] * qq[q];
-      part[q] += (double)rr[q] * (double)(di * rr[q]);
+      for (int q = 0; q < V; ++q) {
+        rr[q] -= al[q] * qq[q];
+        part[q] += (double)rr[q] * (double)(di * rr[q]);
+      }
+      st_vec<T, V>(R + o, rr);
     }
-    st_vec<T>(X + o, x);
-    st_vec<T>(R + o, rr);
   }
-  column_reduce_add<N>(red, part, tl.z, ld, cols.rznew + S.coff);
+  column_reduce_add<V>(red, part, tl.z, ld, cols.rznew + S.coff);
 }
 
-// P = D^-1 R + beta P
-template <typename T>
+// X += alpha P (the step of this iteration), then P = D^-1 R + beta P
+template <typename T, int V>
 __global__ __launch_bounds__(256) void k_cg_direction(const CgSys* __restrict__ sys, const int4* __restrict__ tiles,
                                                       int ntiles, int rb, CgCols cols) {
-  constexpr int N = VecT<T>::N;
-  const int t = xcd_tile(blockIdx.x, ntiles);
-  if (t >= ntiles) return;
-  const int4 tl = tiles[t];
-  const CgSys& S = sys[tl.x];
-  const int lane = threadIdx.x & 63, w = wave_id();
-  const int c0 = tl.z + lane * N;
-  if (c0 >= S.ld) return;
-  const int ld = S.ld;
+  MOR_TILE_PROLOGUE(V)
+  if (!act) return;
   const T* dinv = (const T*)S.dinv;
-  const T* R = (const T*)S.R; T* P = (T*)S.P;
-  T be[N];
+  const T* R = (const T*)S.R; T* P = (T*)S.P; T* X = (T*)S.X;
+  T be[V], al[V];
 #pragma unroll
-  for (int q = 0; q < N; ++q) be[q] = (T)cols.beta[S.coff + c0 + q];
-  const int rend = min(tl.y + rb, S.nI);
+  for (int q = 0; q < V; ++q) {
+    be[q] = (T)cols.beta[S.coff + c0 + q];
+    al[q] = (T)cols.alpha[S.coff + c0 + q];
+  }
+#pragma unroll 2
   for (int r = tl.y + w; r < rend; r += 4) {
     const int64_t o = (int64_t)r * ld + c0;
-    T rr[N], p[N];
-    ld_vec<T>(R + o, rr);
-    ld_vec<T>(P + o, p);
+    T rr[V], p[V], x[V];
+    ld_vec<T, V>(R + o, rr);
+    ld_vec<T, V>(P + o, p);
+    ld_vec<T, V>(X + o, x);
     const T di = dinv[r];
 #pragma unroll
-    for (int q = 0; q < N; ++q) p[q] = di * rr[q] + be[q] * p[q];
-    st_vec<T>(P + o, p);
+    for (int q = 0; q < V; ++q) {
+      x[q] += al[q] * p[q];
+      p[q] = di * rr[q] + be[q] * p[q];
+    }
+    st_vec<T, V>(X + o, x);
+    st_vec<T, V>(P + o, p);
   }
 }
 
 // X64 += X (accumulate a correction into the FP64 solution)
-template <typename T>
+template <typename T, int V>
 __global__ __launch_bounds__(256) void k_cg_shadow(const CgSys* __restrict__ sys, const int4* __restrict__ tiles,
                                                    int ntiles, int rb) {
-  constexpr int N = VecT<T>::N;
-  const int t = xcd_tile(blockIdx.x, ntiles);
-  if (t >= ntiles) return;
-  const int4 tl = tiles[t];
-  const CgSys& S = sys[tl.x];
-  const int lane = threadIdx.x & 63, w = wave_id();
-  const int c0 = tl.z + lane * N;
-  if (c0 >= S.ld || S.X64 == nullptr) return;
+  MOR_TILE_PROLOGUE(V)
+  if (!act || S.X64 == nullptr) return;
   const T* X = (const T*)S.X;
-  const int rend = min(tl.y + rb, S.nI);
   for (int r = tl.y + w; r < rend; r += 4) {
-    const int64_t o = (int64_t)r * S.ld + c0;
-    T x[N];
-    ld_vec<T>(X + o, x);
+    const int64_t o = (int64_t)r * ld + c0;
+    T x[V];
+    ld_vec<T, V>(X + o, x);
 #pragma unroll
-    for (int q = 0; q < N; ++q) S.X64[o + q] += (double)x[q];
+    for (int q = 0; q < V; ++q) S.X64[o + q] += (double)x[q];
   }
 }
 
 // FP64 residual of the FP64 solution: R = F - A_II X64 (rounded to T), P = D^-1 R, X = 0.
-template <typename T>
+template <typename T, int V>
 __global__ __launch_bounds__(256) void k_cg_residual64(const CgSys* __restrict__ sys, const int4* __restrict__ tiles,
                                                        int ntiles, int rb, CgCols cols) {
-  constexpr int N = VecT<T>::N;
   __shared__ double red[4][64 * 4];
-  const int t = xcd_tile(blockIdx.x, ntiles);
-  if (t >= ntiles) return;
-  const int4 tl = tiles[t];
-  const CgSys& S = sys[tl.x];
-  const int lane = threadIdx.x & 63, w = wave_id();
-  const int c0 = tl.z + lane * N;
-  const bool act = c0 < S.ld;
-  const int ld = S.ld;
+  MOR_TILE_PROLOGUE(V)
   const T* dinv = (const T*)S.dinv;
   T* X = (T*)S.X; T* R = (T*)S.R; T* P = (T*)S.P;
-  double part[N];
+  double part[V];
 #pragma unroll
-  for (int q = 0; q < N; ++q) part[q] = 0.0;
-  const int rend = min(tl.y + rb, S.nI);
+  for (int q = 0; q < V; ++q) part[q] = 0.0;
   for (int r = tl.y + w; r < rend; r += 4) {
     if (!act) continue;
-    double acc[N];
-    rhs_row<double, N>(S, r, c0, acc);
+    double acc[V];
+    rhs_row<double, V>(S, r, c0, acc);
     const int e1 = S.ii_end[r];
     for (int e = S.rp[r]; e < e1; ++e) {
       const double a = S.val64[e];
       const double* xr = S.X64 + (int64_t)S.col[e] * ld + c0;
 #pragma unroll
-      for (int q = 0; q < N; ++q) acc[q] -= a * xr[q];
+      for (int q = 0; q < V; ++q) acc[q] -= a * xr[q];
     }
     const T di = dinv[r];
-    T rr[N], p[N], z[N];
+    T rr[V], p[V], z[V];
 #pragma unroll
-    for (int q = 0; q < N; ++q) {
+    for (int q = 0; q < V; ++q) {
       rr[q] = (T)acc[q];
       p[q] = di * rr[q];
       z[q] = 0;
       part[q] += (double)rr[q] * (double)p[q];
     }
     const int64_t o = (int64_t)r * ld + c0;
-    st_vec<T>(R + o, rr);
-    st_vec<T>(P + o, p);
-    st_vec<T>(X + o, z);
+    st_vec<T, V>(R + o, rr);
+    st_vec<T, V>(P + o, p);
+    st_vec<T, V>(X + o, z);
   }
-  column_reduce_add<N>(red, part, tl.z, ld, cols.rz + S.coff);
+  column_reduce_add<V>(red, part, tl.z, ld, cols.rz + S.coff);
 }
 
+#define MOR_VSWITCH(T, V, KERNEL, ...)                                                                  \
+  do {                                                                                                  \
+    const dim3 g_(xcd_grid(ntiles)), b_(256);                                                           \
+    if ((V) == 1) hipLaunchKernelGGL((KERNEL<T, 1>), g_, b_, 0, s, __VA_ARGS__);                        \
+    else if ((V) == 2) hipLaunchKernelGGL((KERNEL<T, 2>), g_, b_, 0, s, __VA_ARGS__);                   \
+    else if (sizeof(T) == 4) hipLaunchKernelGGL((KERNEL<T, (sizeof(T) == 4 ? 4 : 2)>), g_, b_, 0, s, __VA_ARGS__); \
+  } while (0)
+
 template <typename T>
-void launch_cg_init(const CgSys* sys, const int4* tiles, int ntiles, int rb, CgCols cols, hipStream_t s) {
-  if (ntiles > 0) hipLaunchKernelGGL(k_cg_init<T>, dim3(xcd_grid(ntiles)), dim3(256), 0, s, sys, tiles, ntiles, rb, cols);
+void launch_cg_init(const CgSys* sys, const int4* tiles, int ntiles, int rb, int v, CgCols cols, hipStream_t s) {
+  if (ntiles > 0) MOR_VSWITCH(T, v, k_cg_init, sys, tiles, ntiles, rb, cols);
 }
 template <typename T>
-void launch_cg_spmm(const CgSys* sys, const int4* tiles, int ntiles, int rb, CgCols cols, hipStream_t s) {
-  if (ntiles > 0) hipLaunchKernelGGL(k_cg_spmm<T>, dim3(xcd_grid(ntiles)), dim3(256), 0, s, sys, tiles, ntiles, rb, cols);
+void launch_cg_spmm(const CgSys* sys, const int4* tiles, int ntiles, int rb, int v, CgCols cols, hipStream_t s) {
+  if (ntiles > 0) MOR_VSWITCH(T, v, k_cg_spmm, sys, tiles, ntiles, rb, cols);
 }
 template <typename T>
-void launch_cg_update(const CgSys* sys, const int4* tiles, int ntiles, int rb, CgCols cols, hipStream_t s) {
-  if (ntiles > 0) hipLaunchKernelGGL(k_cg_update<T>, dim3(xcd_grid(ntiles)), dim3(256), 0, s, sys, tiles, ntiles, rb, cols);
+void launch_cg_update(const CgSys* sys, const int4* tiles, int ntiles, int rb, int v, CgCols cols, hipStream_t s) {
+  if (ntiles > 0) MOR_VSWITCH(T, v, k_cg_update, sys, tiles, ntiles, rb, cols);
 }
 template <typename T>
-void launch_cg_direction(const CgSys* sys, const int4* tiles, int ntiles, int rb, CgCols cols, hipStream_t s) {
-  if (ntiles > 0)
-    hipLaunchKernelGGL(k_cg_direction<T>, dim3(xcd_grid(ntiles)), dim3(256), 0, s, sys, tiles, ntiles, rb, cols);
+void launch_cg_direction(const CgSys* sys, const int4* tiles, int ntiles, int rb, int v, CgCols cols, hipStream_t s) {
+  if (ntiles > 0) MOR_VSWITCH(T, v, k_cg_direction, sys, tiles, ntiles, rb, cols);
 }
 template <typename T>
-void launch_cg_residual64(const CgSys* sys, const int4* tiles, int ntiles, int rb, CgCols cols, hipStream_t s) {
-  if (ntiles > 0)
-    hipLaunchKernelGGL(k_cg_residual64<T>, dim3(xcd_grid(ntiles)), dim3(256), 0, s, sys, tiles, ntiles, rb, cols);
+void launch_cg_residual64(const CgSys* sys, const int4* tiles, int ntiles, int rb, int v, CgCols cols, hipStream_t s) {
+  if (ntiles > 0) MOR_VSWITCH(T, v, k_cg_residual64, sys, tiles, ntiles, rb, cols);
 }
 template <typename T>
-void launch_cg_shadow(const CgSys* sys, const int4* tiles, int ntiles, int rb, hipStream_t s) {
-  if (ntiles > 0) hipLaunchKernelGGL(k_cg_shadow<T>, dim3(xcd_grid(ntiles)), dim3(256), 0, s, sys, tiles, ntiles, rb);
+void launch_cg_shadow(const CgSys* sys, const int4* tiles, int ntiles, int rb, int v, hipStream_t s) {
+  if (ntiles > 0) MOR_VSWITCH(T, v, k_cg_shadow, sys, tiles, ntiles, rb);
 }
-#define MOR_INST(T)                                                                                 \
-  template void launch_cg_init<T>(const CgSys*, const int4*, int, int, CgCols, hipStream_t);       \
-  template void launch_cg_spmm<T>(const CgSys*, const int4*, int, int, CgCols, hipStream_t);       \
-  template void launch_cg_update<T>(const CgSys*, const int4*, int, int, CgCols, hipStream_t);     \
-  template void launch_cg_direction<T>(const CgSys*, const int4*, int, int, CgCols, hipStream_t);  \
-  template void launch_cg_residual64<T>(const CgSys*, const int4*, int, int, CgCols, hipStream_t); \
-  template void launch_cg_shadow<T>(const CgSys*, const int4*, int, int, hipStream_t);
+#define MOR_INST(T)                                                                                      \
+  template void launch_cg_init<T>(const CgSys*, const int4*, int, int, int, CgCols, hipStream_t);       \
+  template void launch_cg_spmm<T>(const CgSys*, const int4*, int, int, int, CgCols, hipStream_t);       \
+  template void launch_cg_update<T>(const CgSys*, const int4*, int, int, int, CgCols, hipStream_t);     \
+  template void launch_cg_direction<T>(const CgSys*, const int4*, int, int, int, CgCols, hipStream_t);  \
+  template void launch_cg_residual64<T>(const CgSys*, const int4*, int, int, int, CgCols, hipStream_t); \
+  template void launch_cg_shadow<T>(const CgSys*, const int4*, int, int, int, hipStream_t);
 MOR_INST(float)
 MOR_INST(double)
 #undef MOR_INST

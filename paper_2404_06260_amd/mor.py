@@ -54,7 +54,7 @@ class MorOpts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("cg_rtol", ctypes.c_double), ("refine_rtol", ctypes.c_double),
                 ("max_iter", ctypes.c_int32), ("refine_steps", ctypes.c_int32), ("oversample", ctypes.c_int32),
                 ("eig_rtol", ctypes.c_double), ("eig_max_iter", ctypes.c_int32), ("cg_chunk", ctypes.c_int32),
-                ("spmm_rows", ctypes.c_int32), ("use_graph", ctypes.c_int32), ("hbm_budget_bytes", ctypes.c_size_t),
+                ("spmm_rows", ctypes.c_int32), ("spmm_vec", ctypes.c_int32), ("use_graph", ctypes.c_int32), ("hbm_budget_bytes", ctypes.c_size_t),
                 ("dev_alloc", ALLOC_FN), ("dev_free", FREE_FN), ("alloc_user", ctypes.c_void_p),
                 ("hip_stream", ctypes.c_void_p), ("host_only", ctypes.c_int32)]
 
@@ -62,6 +62,12 @@ class MorOpts(ctypes.Structure):
 def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     if not os.path.exists(path):
         raise ImportError(f"{path} is missing: build it with `python -c 'import __graft_entry__ as g; g.build()'`")
+    # torch (when present) brings its own HIP/HSA runtime libraries; load them first so that
+    # the library's runtime binds to the already-loaded HSA runtime in the same order every time
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = ctypes.CDLL(path)
     P, I32, I64, D = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
     sig = {
@@ -126,7 +132,7 @@ class _TorchAllocator:
 
         def _alloc(nbytes, user):
             try:
-                p = torch.cuda.caching_allocator_alloc(int(nbytes), stream=self.stream)
+                p = torch.cuda.caching_allocator_alloc(int(nbytes))
             except Exception:
                 return None
             self.live[p] = nbytes
@@ -310,11 +316,13 @@ class Mor:
             import torch
             if not torch.cuda.is_available():
                 raise RuntimeError("no HIP device visible to torch")
-            stream = torch.cuda.current_stream().cuda_stream
-            self._alloc = _TorchAllocator(stream)
+            # memory from torch's caching allocator; the library orders its work on its own null
+            # stream and synchronizes before it returns or releases memory
+            torch.cuda.synchronize()
+            self._alloc = _TorchAllocator(None)
             self.opts.dev_alloc = self._alloc.alloc_cb
             self.opts.dev_free = self._alloc.free_cb
-            self.opts.hip_stream = stream
+            self.opts.hip_stream = None
         m, sd = problem.mesh, problem.subdomains
         self.ctx = mor_create(m.xyz, m.tets, m.dirichlet, problem.kappa, problem.f_nodal, sd.ext_tet_ptr,
                               sd.ext_tets, sd.in_core, self.opts)

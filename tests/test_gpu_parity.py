@@ -69,6 +69,8 @@ def _run_gpu(p, precision, **kw):
     import torch
     from paper_2404_06260_amd import mor
     torch.cuda.set_device(0)
+    if precision == "fp64":
+        kw.setdefault("refine_rtol", 1e-11)    # the FP64 CG target; default 1e-8 matches the FP32 path
     m = mor.Mor(p, precision=precision, **kw)
     _say(f"[gpu] {p.name} {precision}: local bases")
     k = m.local_basis_all()
