@@ -51,7 +51,7 @@ struct TimerRec {
 };
 
 struct SubDev {
-  int *rp = nullptr, *col = nullptr, *ii_end = nullptr, *rpV = nullptr, *colV = nullptr;
+  int *rp = nullptr, *col = nullptr, *ii_end = nullptr, *rpV = nullptr, *colV = nullptr, *bp = nullptr;
   int *ltet = nullptr, *tetg = nullptr, *nodes = nullptr;
   uint8_t* core = nullptr;
 };
@@ -288,6 +288,7 @@ extern "C" int mor_create(const mor_mesh* mesh, const mor_coeff* coeff, const mo
     r = r ? r : upload(c, &d.tetg, h.tetg.data(), h.tetg.size());
     r = r ? r : upload(c, &d.nodes, h.nodes.data(), h.nodes.size());
     r = r ? r : upload(c, &d.core, h.core.data(), h.core.size());
+    r = r ? r : upload(c, &d.bp, h.bp.data(), h.bp.size());
     return r;
   };
   c->sdev.resize(n);
@@ -444,13 +445,16 @@ struct CgState {
 
 // tiles of the active systems: (system, first row, first column), row blocks fastest so that
 // consecutive tiles (one XCD) sweep the rows of one column slab
-static void make_tiles(const CgState& cs, const std::vector<char>& act, const TileCfg& tc, std::vector<int4>& t) {
+// by_block: tiles over row aggregates (rb = aggregates per tile) instead of rows
+static void make_tiles(const CgState& cs, const std::vector<char>& act, const TileCfg& tc, std::vector<int4>& t,
+                       bool by_block) {
   const int W = 64 * tc.v;
   for (size_t s = 0; s < cs.hsys.size(); ++s) {
     if (!act[s]) continue;
     const CgSys& S = cs.hsys[s];
+    const int n = by_block ? S.nblk : S.nI;
     for (int c0 = 0; c0 < S.ld; c0 += W)
-      for (int r0 = 0; r0 < S.nI; r0 += tc.rb) t.push_back(make_int4((int)s, r0, c0, 0));
+      for (int r0 = 0; r0 < n; r0 += tc.rb) t.push_back(make_int4((int)s, r0, c0, 0));
   }
 }
 
@@ -458,9 +462,9 @@ static void make_tiles(const CgState& cs, const std::vector<char>& act, const Ti
 static int upload_tiles(mor_ctx* c, CgState& cs, const std::vector<char>& act, int4** sp, int* nsp, int4** st,
                         int* nst) {
   std::vector<int4> t;
-  make_tiles(cs, act, cs.sp, t);
+  make_tiles(cs, act, cs.sp, t, false);
   *nsp = (int)t.size();
-  make_tiles(cs, act, cs.stm, t);
+  make_tiles(cs, act, cs.stm, t, true);
   *nst = (int)t.size() - *nsp;
   if (t.size() > cs.tiles_cap) {
     dfree(c, cs.d_tiles_buf);
@@ -540,9 +544,9 @@ static int cg_solve(mor_ctx* c, CgState& cs, const std::vector<int>& sys_sub, co
   std::vector<char> all(nsys, 1), act(nsys, 1);
   // tile lists over every system (init, refinement passes) kept apart from the iteration lists
   std::vector<int4> ta;
-  make_tiles(cs, all, cs.sp, ta);
+  make_tiles(cs, all, cs.sp, ta, false);
   const int nta_sp = (int)ta.size();
-  make_tiles(cs, all, cs.stm, ta);
+  make_tiles(cs, all, cs.stm, ta, true);
   const int nta = (int)ta.size() - nta_sp;
   int4* dta_sp = (int4*)dalloc(c, sizeof(int4) * std::max<size_t>(1, ta.size()));
   if (!dta_sp) return fail(MOR_ENOMEM, "tile list allocation failed");
@@ -550,7 +554,8 @@ static int cg_solve(mor_ctx* c, CgState& cs, const std::vector<int>& sys_sub, co
   HIPCHK(hipMemcpyAsync(dta_sp, ta.data(), sizeof(int4) * ta.size(), hipMemcpyHostToDevice, c->st));
   HIPCHK(hipStreamSynchronize(c->st));
   launch_fill(cs.cols.rz, cs.cols.ncols_total, 0.0, c->st);
-  launch_cg_init<T>(cs.dsys, dta, nta, cs.stm.rb, cs.stm.v, cs.cols, c->st);
+  launch_cg_init<T>(cs.dsys, dta_sp, nta_sp, cs.sp.rb, cs.sp.v, cs.cols, c->st);
+  launch_cg_pstart<T>(cs.dsys, dta, nta, cs.stm.rb, cs.stm.v, cs.cols, c->st);
   launch_cg_start(cs.cols, 1, 0.0, c->st);
   HIPCHK(hipMemcpyAsync(cs.h_nactive, cs.cols.nactive, sizeof(int) * nsys, hipMemcpyDeviceToHost, c->st));
   HIPCHK(hipStreamSynchronize(c->st));
@@ -563,12 +568,13 @@ static int cg_solve(mor_ctx* c, CgState& cs, const std::vector<int>& sys_sub, co
   if (refine) {
     const double outer2 = c->opts.refine_rtol * c->opts.refine_rtol;
     for (int step = 0; step < c->opts.refine_steps; ++step) {
-      launch_cg_shadow<T>(cs.dsys, dta, nta, cs.stm.rb, cs.stm.v, c->st);
+      launch_cg_shadow<T>(cs.dsys, dta_sp, nta_sp, cs.sp.rb, cs.sp.v, c->st);
       launch_fill(cs.cols.rz, cs.cols.ncols_total, 0.0, c->st);
       {
         ScopedTimer tm(c, "residual64", 0);
         launch_cg_residual64<T>(cs.dsys, dta_sp, nta_sp, cs.sp.rb, cs.sp.v, cs.cols, c->st);
       }
+      launch_cg_pstart<T>(cs.dsys, dta, nta, cs.stm.rb, cs.stm.v, cs.cols, c->st);
       launch_cg_restart(cs.cols, outer2, c->st);
       HIPCHK(hipMemcpyAsync(cs.h_nactive, cs.cols.nactive, sizeof(int) * nsys, hipMemcpyDeviceToHost, c->st));
       HIPCHK(hipStreamSynchronize(c->st));
@@ -585,7 +591,7 @@ static int cg_solve(mor_ctx* c, CgState& cs, const std::vector<int>& sys_sub, co
         return rc;
       }
     }
-    launch_cg_shadow<T>(cs.dsys, dta, nta, cs.stm.rb, cs.stm.v, c->st);
+    launch_cg_shadow<T>(cs.dsys, dta_sp, nta_sp, cs.sp.rb, cs.sp.v, c->st);
   }
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(c->st));
@@ -667,7 +673,7 @@ static int slot_sizes(mor_ctx* c, Slot& q, Sizer& z, int elt) {
   const bool refine = c->opts.precision == MOR_FP32_REFINE;
   z.add(8 * nnz); z.add(8 * nnz); z.add(8 * nnzV); z.add(8 * (size_t)h.nL);
   if (fp32) { z.add(4 * nnz); z.add(4 * nnz); }
-  z.add((size_t)elt * h.nI); z.add((size_t)elt * h.nI);
+  z.add((size_t)elt * h.nI * 8); z.add((size_t)elt * h.nI * 8);
   for (int i = 0; i < 4; ++i) z.add((size_t)elt * h.nI * q.ldA);
   for (int i = 0; i < 4; ++i) z.add((size_t)elt * h.nI * q.ldK);
   if (refine) { z.add(8 * (size_t)h.nI * q.ldA); z.add(8 * (size_t)h.nI * q.ldK); }
@@ -693,7 +699,7 @@ static int slot_carve(mor_ctx* c, Slot& q, Arena& a, int elt) {
   q.A64 = (double*)tk(8 * nnz); q.K64 = (double*)tk(8 * nnz); q.Ki64 = (double*)tk(8 * nnzV); q.f = (double*)tk(8 * (size_t)h.nL);
   q.A32 = fp32 ? (float*)tk(4 * nnz) : nullptr;
   q.K32 = fp32 ? (float*)tk(4 * nnz) : nullptr;
-  q.dinvA = tk((size_t)elt * h.nI); q.dinvK = tk((size_t)elt * h.nI);
+  q.dinvA = tk((size_t)elt * h.nI * 8); q.dinvK = tk((size_t)elt * h.nI * 8);   // block inverses
   q.XA = tk((size_t)elt * h.nI * q.ldA); q.RA = tk((size_t)elt * h.nI * q.ldA);
   q.PA = tk((size_t)elt * h.nI * q.ldA); q.QA = tk((size_t)elt * h.nI * q.ldA);
   q.XK = tk((size_t)elt * h.nI * q.ldK); q.RK = tk((size_t)elt * h.nI * q.ldK);
@@ -780,8 +786,14 @@ static int local_batch_t(mor_ctx* c, std::vector<Slot>& slots) {
       launch_to_f32(q.A64, q.A32, h.rp[h.nL], st);
       launch_to_f32(q.K64, q.K32, h.rp[h.nL], st);
     }
-    launch_diag_inv(q.d->rp, q.d->col, q.A64, h.nI, q.dinvA, !fp32, st);
-    launch_diag_inv(q.d->rp, q.d->col, q.K64, h.nI, q.dinvK, !fp32, st);
+    const int nblk = (int)h.bp.size() - 1;
+    if (fp32) {
+      launch_block_inv<float>(q.d->rp, q.d->col, q.A64, q.d->bp, nblk, q.dinvA, st);
+      launch_block_inv<float>(q.d->rp, q.d->col, q.K64, q.d->bp, nblk, q.dinvK, st);
+    } else {
+      launch_block_inv<double>(q.d->rp, q.d->col, q.A64, q.d->bp, nblk, q.dinvA, st);
+      launch_block_inv<double>(q.d->rp, q.d->col, q.K64, q.d->bp, nblk, q.dinvK, st);
+    }
   }
 
   // ---- block CG on A_II (lifting + load) and K_II (H1 extension for S_B)
@@ -792,8 +804,8 @@ static int local_batch_t(mor_ctx* c, std::vector<Slot>& slots) {
   cs.sp.v = c->opts.spmm_vec > 0 ? c->opts.spmm_vec : 4;
   cs.sp.rb = c->opts.spmm_rows > 0 ? std::min(c->opts.spmm_rows, 64) : 8;
   if (!fp32 && cs.sp.v > 2) cs.sp.v = 2;
-  cs.stm.v = fp32 ? 4 : 2;
-  cs.stm.rb = 32;
+  cs.stm.v = 2;    // block kernels hold 8 rows per lane: 2 values per row keeps registers low
+  cs.stm.rb = 8;   // aggregates per tile (2 per wave)
   std::vector<int> sys_sub(nsys), sys_nnz(nsys);
   std::vector<int> sys_of_col(total_cols);
   int coff = 0;
@@ -816,6 +828,9 @@ static int local_batch_t(mor_ctx* c, std::vector<Slot>& slots) {
       S.P = w == 0 ? q.PA : q.PK; S.Q = w == 0 ? q.QA : q.QK;
       S.X64 = w == 0 ? q.XA64 : q.XK64;
       S.coff = coff;
+      S.bp = q.d->bp;
+      S.nblk = (int)h.bp.size() - 1;
+      S.minv = w == 0 ? q.dinvA : q.dinvK;
       const int sidx = 2 * i + w;
       for (int j = 0; j < S.ld; ++j) sys_of_col[coff + j] = sidx;
       coff += S.ld;

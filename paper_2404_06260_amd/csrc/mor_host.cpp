@@ -166,21 +166,57 @@ int build_sub(const HostMesh& m, const int32_t* ext, const uint8_t* in_core, int
   s.nodes.reserve(s.nL);
   for (auto* part : {&P, &VmP, &ImV, &B}) s.nodes.insert(s.nodes.end(), part->begin(), part->end());
   std::vector<int32_t>& lid = starE;   // reuse as global -> local map
-  for (int32_t v : touched) lid[v] = -1;
-  for (int i = 0; i < s.nL; ++i) lid[s.nodes[i]] = i;
   std::vector<int32_t> ltet(4 * n_ext), tetg(n_ext);
   std::vector<uint8_t> core(n_ext);
-  for (int64_t k = 0; k < n_ext; ++k) {
-    const int32_t t = ext[k];
-    tetg[k] = t;
-    core[k] = in_core[k] ? 1 : 0;
-    for (int a = 0; a < 4; ++a) {
-      const int32_t v = m.tets[4 * (int64_t)t + a];
-      ltet[4 * k + a] = m.dirichlet[v] ? -1 : lid[v];
+  auto local_tets = [&]() {
+    for (int32_t v : touched) lid[v] = -1;
+    for (int i = 0; i < s.nL; ++i) lid[s.nodes[i]] = i;
+    for (int64_t k = 0; k < n_ext; ++k) {
+      const int32_t t = ext[k];
+      tetg[k] = t;
+      core[k] = in_core[k] ? 1 : 0;
+      for (int a = 0; a < 4; ++a) {
+        const int32_t v = m.tets[4 * (int64_t)t + a];
+        ltet[4 * k + a] = m.dirichlet[v] ? -1 : lid[v];
+      }
     }
+    colour_sort(m, s, ltet, tetg, core);
+    tet_pattern(s.ltet, nullptr, s.nL, s.rp, s.col);
+  };
+  local_tets();
+  // Aggregates of at most 8 I rows for the block-Jacobi preconditioner of the CG: in id
+  // order, an unaggregated row takes its unaggregated higher-numbered neighbours of the same
+  // group (P, V\P, I\V).  On a Kuhn cube these are the 7 forward corners of a 2x2x2 cell
+  // block.  Rows are then renumbered aggregate by aggregate.
+  {
+    const int gb[4] = {0, s.nP, s.nV, s.nI};
+    std::vector<int32_t> agg(s.nI, -1), order;
+    std::vector<int32_t> bp{0};
+    order.reserve(s.nI);
+    for (int g = 0; g < 3; ++g)
+      for (int v = gb[g]; v < gb[g + 1]; ++v) {
+        if (agg[v] >= 0) continue;
+        const int b = (int)bp.size() - 1;
+        agg[v] = b;
+        order.push_back(v);
+        int n = 1;
+        for (int e = s.rp[v]; e < s.rp[v + 1] && n < 8; ++e) {
+          const int u = s.col[e];
+          if (u > v && u < gb[g + 1] && agg[u] < 0) {
+            agg[u] = b;
+            order.push_back(u);
+            ++n;
+          }
+        }
+        bp.push_back((int32_t)order.size());
+      }
+    std::vector<int32_t> nodes2(s.nL);
+    for (int i = 0; i < s.nI; ++i) nodes2[i] = s.nodes[order[i]];
+    for (int i = s.nI; i < s.nL; ++i) nodes2[i] = s.nodes[i];
+    s.nodes.swap(nodes2);
+    s.bp.swap(bp);
+    local_tets();
   }
-  colour_sort(m, s, ltet, tetg, core);
-  tet_pattern(s.ltet, nullptr, s.nL, s.rp, s.col);
   s.ii_end.resize(s.nI);
   for (int r = 0; r < s.nI; ++r) {
     const int32_t* b = s.col.data() + s.rp[r];

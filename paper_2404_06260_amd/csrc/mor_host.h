@@ -27,6 +27,7 @@ struct HostSub {
   std::vector<int32_t> tetg;               // global tet id per local tet
   std::vector<uint8_t> core;               // 1 if the local tet lies in omega_i
   std::vector<int32_t> colour_ptr;         // local tets of colour c: [colour_ptr[c], colour_ptr[c+1])
+  std::vector<int32_t> bp;                 // aggregates of I rows: block b = rows [bp[b], bp[b+1]), size <= 8
 };
 
 // omega_0: the elements in two or more subdomains, with A_0's pattern over their free nodes.

@@ -42,6 +42,9 @@ struct CgSys {
   void* X; void* R; void* P; void* Q;  // CG scalar type
   double* X64;         // FP64 solution shadow (refinement), or nullptr
   int coff;            // offset of this system's columns in the per-column arrays
+  const int* bp;       // aggregates of rows (block-Jacobi blocks): [bp[b], bp[b+1]), size <= 8
+  int nblk;
+  const void* minv;    // inverse of each diagonal block, 8 entries per row, CG scalar type
 };
 
 struct CgCols {        // per-column state, all systems concatenated
@@ -110,6 +113,12 @@ template <typename T>
 void launch_cg_residual64(const CgSys* sys, const int4* tiles, int ntiles, int rb, int v, CgCols cols, hipStream_t s);
 template <typename T>
 void launch_cg_shadow(const CgSys* sys, const int4* tiles, int ntiles, int rb, int v, hipStream_t s);
+// block tiles: (system, first block, first column); bpt blocks per tile
+template <typename T>
+void launch_cg_pstart(const CgSys* sys, const int4* tiles, int ntiles, int bpt, int v, CgCols cols, hipStream_t s);
+template <typename T>
+void launch_block_inv(const int* rp, const int* col, const double* v64, const int* bp, int nblk, void* minv,
+                      hipStream_t s);
 void launch_cg_alpha(CgCols cols, hipStream_t s);
 void launch_cg_beta(CgCols cols, double tol2, hipStream_t s);
 void launch_cg_start(CgCols cols, int first, double tol2_first, hipStream_t s);

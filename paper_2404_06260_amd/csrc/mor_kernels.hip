@@ -258,34 +258,22 @@ __device__ __forceinline__ void rhs_row(const CgSys& S, int r, int c0, TT (&v)[V
 template <typename T, int V>
 __global__ __launch_bounds__(256) void k_cg_init(const CgSys* __restrict__ sys, const int4* __restrict__ tiles, int ntiles,
                                                  int rb, CgCols cols) {
-  __shared__ double red[4][64 * 4];
   MOR_TILE_PROLOGUE(V)
-  const T* dinv = (const T*)S.dinv;
-  T* X = (T*)S.X; T* R = (T*)S.R; T* P = (T*)S.P;
-  double part[V];
-#pragma unroll
-  for (int q = 0; q < V; ++q) part[q] = 0.0;
+  if (!act) return;
+  T* X = (T*)S.X; T* R = (T*)S.R;
   for (int r = tl.y + w; r < rend; r += 4) {
-    if (!act) continue;
-    T v[V], z[V], p[V];
+    T v[V], z[V];
     rhs_row<T, V>(S, r, c0, v);
-    const T di = dinv[r];
 #pragma unroll
-    for (int q = 0; q < V; ++q) {
-      z[q] = 0;
-      p[q] = di * v[q];
-      part[q] += (double)v[q] * (double)p[q];
-    }
+    for (int q = 0; q < V; ++q) z[q] = 0;
     const int64_t o = (int64_t)r * ld + c0;
     st_vec<T, V>(R + o, v);
     st_vec<T, V>(X + o, z);
-    st_vec<T, V>(P + o, p);
     if (S.X64 != nullptr) {
 #pragma unroll
       for (int q = 0; q < V; ++q) S.X64[o + q] = 0.0;
     }
   }
-  column_reduce_add<V>(red, part, tl.z, ld, cols.rz + S.coff);
 }
 
 // Q = A_II P and the per-column p'Q: the dominant, HBM-bound kernel of the lifting.
@@ -391,13 +379,80 @@ __global__ __launch_bounds__(256) void k_cg_spmm(const CgSys* __restrict__ sys, 
   column_reduce_add<V>(red, part, tl.z, ld, cols.pq + S.coff);
 }
 
-// R -= alpha Q and the new r'D^-1 r
+// Block-Jacobi preconditioner: z = M^-1 r with M the diagonal blocks of A_II over the row
+// aggregates (at most 8 rows each).  A wave owns whole aggregates, so applying M^-1 needs no
+// data beyond the rows the kernel streams anyway.
+#define MOR_BLOCK_PROLOGUE(V)                                 \
+  const int t = xcd_tile(blockIdx.x, ntiles);                 \
+  if (t >= ntiles) return;                                    \
+  const int4 tl = tiles[t];                                   \
+  const CgSys& S = sys[tl.x];                                 \
+  const int lane = threadIdx.x & 63, w = wave_id();           \
+  const int c0 = tl.z + lane * (V);                           \
+  const bool act = c0 < S.ld;                                 \
+  const int ld = S.ld;                                        \
+  const int bend = min(tl.y + bpt, S.nblk);
+
+template <typename T, int V>
+__device__ __forceinline__ void block_apply(const T* __restrict__ minv, int r0, int nb, const T (&rr)[8][V], int j,
+                                            T (&z)[V]) {
+#pragma unroll
+  for (int q = 0; q < V; ++q) z[q] = 0;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    if (k < nb) {
+      const T m = gld(minv + (int64_t)(r0 + j) * 8 + k);
+#pragma unroll
+      for (int q = 0; q < V; ++q) z[q] += m * rr[k][q];
+    }
+  }
+}
+
+// P = M^-1 R and r'M^-1 r (start and restarts of the CG)
+template <typename T, int V>
+__global__ __launch_bounds__(256) void k_cg_pstart(const CgSys* __restrict__ sys, const int4* __restrict__ tiles,
+                                                   int ntiles, int bpt, CgCols cols) {
+  __shared__ double red[4][64 * 4];
+  MOR_BLOCK_PROLOGUE(V)
+  const T* minv = (const T*)S.minv;
+  const T* R = (const T*)S.R; T* P = (T*)S.P;
+  double part[V];
+#pragma unroll
+  for (int q = 0; q < V; ++q) part[q] = 0.0;
+  if (act) {
+    for (int b = tl.y + w; b < bend; b += 4) {
+      const int r0 = gld(S.bp + b), nb = gld(S.bp + b + 1) - r0;
+      T rr[8][V];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        if (j < nb) ld_vec<T, V>(R + (int64_t)(r0 + j) * ld + c0, rr[j]);
+        else {
+#pragma unroll
+          for (int q = 0; q < V; ++q) rr[j][q] = 0;
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        if (j < nb) {
+          T z[V];
+          block_apply<T, V>(minv, r0, nb, rr, j, z);
+#pragma unroll
+          for (int q = 0; q < V; ++q) part[q] += (double)rr[j][q] * (double)z[q];
+          st_vec<T, V>(P + (int64_t)(r0 + j) * ld + c0, z);
+        }
+      }
+    }
+  }
+  column_reduce_add<V>(red, part, tl.z, ld, cols.rz + S.coff);
+}
+
+// R -= alpha Q and the new r'M^-1 r
 template <typename T, int V>
 __global__ __launch_bounds__(256) void k_cg_update(const CgSys* __restrict__ sys, const int4* __restrict__ tiles,
-                                                   int ntiles, int rb, CgCols cols) {
+                                                   int ntiles, int bpt, CgCols cols) {
   __shared__ double red[4][64 * 4];
-  MOR_TILE_PROLOGUE(V)
-  const T* dinv = (const T*)S.dinv;
+  MOR_BLOCK_PROLOGUE(V)
+  const T* minv = (const T*)S.minv;
   T* R = (T*)S.R; const T* Q = (const T*)S.Q;
   T al[V];
   double part[V];
@@ -407,31 +462,45 @@ __global__ __launch_bounds__(256) void k_cg_update(const CgSys* __restrict__ sys
     al[q] = act ? (T)cols.alpha[S.coff + c0 + q] : (T)0;
   }
   if (act) {
-#pragma unroll 2
-    for (int r = tl.y + w; r < rend; r += 4) {
-      const int64_t o = (int64_t)r * ld + c0;
-      T rr[V], qq[V];
-      ld_vec<T, V>(R + o, rr);
-      ld_vec<T, V>(Q + o, qq);
-      const T di = dinv[r];
+    for (int b = tl.y + w; b < bend; b += 4) {
+      const int r0 = gld(S.bp + b), nb = gld(S.bp + b + 1) - r0;
+      T rr[8][V], qq[8][V];
 #pragma unroll
-      for (int q = 0; q < V; ++q) {
-        rr[q] -= al[q] * qq[q];
-        part[q] += (double)rr[q] * (double)(di * rr[q]);
+      for (int j = 0; j < 8; ++j) {
+        if (j < nb) {
+          ld_vec<T, V>(R + (int64_t)(r0 + j) * ld + c0, rr[j]);
+          ld_vec<T, V>(Q + (int64_t)(r0 + j) * ld + c0, qq[j]);
+        } else {
+#pragma unroll
+          for (int q = 0; q < V; ++q) rr[j][q] = qq[j][q] = 0;
+        }
       }
-      st_vec<T, V>(R + o, rr);
+#pragma unroll
+      for (int j = 0; j < 8; ++j)
+#pragma unroll
+        for (int q = 0; q < V; ++q) rr[j][q] -= al[q] * qq[j][q];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        if (j < nb) {
+          T z[V];
+          block_apply<T, V>(minv, r0, nb, rr, j, z);
+#pragma unroll
+          for (int q = 0; q < V; ++q) part[q] += (double)rr[j][q] * (double)z[q];
+          st_vec<T, V>(R + (int64_t)(r0 + j) * ld + c0, rr[j]);
+        }
+      }
     }
   }
   column_reduce_add<V>(red, part, tl.z, ld, cols.rznew + S.coff);
 }
 
-// X += alpha P (the step of this iteration), then P = D^-1 R + beta P
+// X += alpha P (the step of this iteration), then P = M^-1 R + beta P
 template <typename T, int V>
 __global__ __launch_bounds__(256) void k_cg_direction(const CgSys* __restrict__ sys, const int4* __restrict__ tiles,
-                                                      int ntiles, int rb, CgCols cols) {
-  MOR_TILE_PROLOGUE(V)
+                                                      int ntiles, int bpt, CgCols cols) {
+  MOR_BLOCK_PROLOGUE(V)
   if (!act) return;
-  const T* dinv = (const T*)S.dinv;
+  const T* minv = (const T*)S.minv;
   const T* R = (const T*)S.R; T* P = (T*)S.P; T* X = (T*)S.X;
   T be[V], al[V];
 #pragma unroll
@@ -439,21 +508,35 @@ __global__ __launch_bounds__(256) void k_cg_direction(const CgSys* __restrict__ 
     be[q] = (T)cols.beta[S.coff + c0 + q];
     al[q] = (T)cols.alpha[S.coff + c0 + q];
   }
-#pragma unroll 2
-  for (int r = tl.y + w; r < rend; r += 4) {
-    const int64_t o = (int64_t)r * ld + c0;
-    T rr[V], p[V], x[V];
-    ld_vec<T, V>(R + o, rr);
-    ld_vec<T, V>(P + o, p);
-    ld_vec<T, V>(X + o, x);
-    const T di = dinv[r];
+  for (int b = tl.y + w; b < bend; b += 4) {
+    const int r0 = gld(S.bp + b), nb = gld(S.bp + b + 1) - r0;
+    T rr[8][V], pp[8][V];
 #pragma unroll
-    for (int q = 0; q < V; ++q) {
-      x[q] += al[q] * p[q];
-      p[q] = di * rr[q] + be[q] * p[q];
+    for (int j = 0; j < 8; ++j) {
+      if (j < nb) {
+        ld_vec<T, V>(R + (int64_t)(r0 + j) * ld + c0, rr[j]);
+        ld_vec<T, V>(P + (int64_t)(r0 + j) * ld + c0, pp[j]);
+      } else {
+#pragma unroll
+        for (int q = 0; q < V; ++q) rr[j][q] = pp[j][q] = 0;
+      }
     }
-    st_vec<T, V>(X + o, x);
-    st_vec<T, V>(P + o, p);
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      if (j < nb) {
+        const int64_t o = (int64_t)(r0 + j) * ld + c0;
+        T x[V], z[V];
+        ld_vec<T, V>(X + o, x);
+        block_apply<T, V>(minv, r0, nb, rr, j, z);
+#pragma unroll
+        for (int q = 0; q < V; ++q) {
+          x[q] += al[q] * pp[j][q];
+          z[q] += be[q] * pp[j][q];
+        }
+        st_vec<T, V>(X + o, x);
+        st_vec<T, V>(P + o, z);
+      }
+    }
   }
 }
 
@@ -473,19 +556,14 @@ __global__ __launch_bounds__(256) void k_cg_shadow(const CgSys* __restrict__ sys
   }
 }
 
-// FP64 residual of the FP64 solution: R = F - A_II X64 (rounded to T), P = D^-1 R, X = 0.
+// FP64 residual of the FP64 solution: R = F - A_II X64 (rounded to T), X = 0.
 template <typename T, int V>
 __global__ __launch_bounds__(256) void k_cg_residual64(const CgSys* __restrict__ sys, const int4* __restrict__ tiles,
                                                        int ntiles, int rb, CgCols cols) {
-  __shared__ double red[4][64 * 4];
   MOR_TILE_PROLOGUE(V)
-  const T* dinv = (const T*)S.dinv;
-  T* X = (T*)S.X; T* R = (T*)S.R; T* P = (T*)S.P;
-  double part[V];
-#pragma unroll
-  for (int q = 0; q < V; ++q) part[q] = 0.0;
+  if (!act) return;
+  T* X = (T*)S.X; T* R = (T*)S.R;
   for (int r = tl.y + w; r < rend; r += 4) {
-    if (!act) continue;
     double acc[V];
     rhs_row<double, V>(S, r, c0, acc);
     const int e1 = S.ii_end[r];
@@ -495,22 +573,81 @@ __global__ __launch_bounds__(256) void k_cg_residual64(const CgSys* __restrict__
 #pragma unroll
       for (int q = 0; q < V; ++q) acc[q] -= a * xr[q];
     }
-    const T di = dinv[r];
-    T rr[V], p[V], z[V];
+    T rr[V], z[V];
 #pragma unroll
     for (int q = 0; q < V; ++q) {
       rr[q] = (T)acc[q];
-      p[q] = di * rr[q];
       z[q] = 0;
-      part[q] += (double)rr[q] * (double)p[q];
     }
     const int64_t o = (int64_t)r * ld + c0;
     st_vec<T, V>(R + o, rr);
-    st_vec<T, V>(P + o, p);
     st_vec<T, V>(X + o, z);
   }
-  column_reduce_add<V>(red, part, tl.z, ld, cols.rz + S.coff);
 }
+
+// Inverses of the diagonal blocks of A_II over the row aggregates (one thread per block,
+// Gauss-Jordan on the SPD block padded with the identity to 8 x 8, in FP64).
+template <typename T>
+__global__ void k_block_inv(const int* __restrict__ rp, const int* __restrict__ col, const double* __restrict__ v64,
+                            const int* __restrict__ bp, int nblk, T* __restrict__ minv) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= nblk) return;
+  const int r0 = bp[b], nb = bp[b + 1] - r0;
+  double a[8][8], inv[8][8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i)
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      a[i][j] = (i == j && i >= nb) ? 1.0 : 0.0;
+      inv[i][j] = (i == j) ? 1.0 : 0.0;
+    }
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    if (i < nb) {
+      const int r = r0 + i;
+      for (int e = rp[r]; e < rp[r + 1]; ++e) {
+        const int c = col[e] - r0;
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+          if (c == j && j < nb) a[i][j] = v64[e];
+      }
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const double d = 1.0 / a[k][k];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      a[k][j] *= d;
+      inv[k][j] *= d;
+    }
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      if (i != k) {
+        const double f = a[i][k];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          a[i][j] -= f * a[k][j];
+          inv[i][j] -= f * inv[k][j];
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < 8; ++i)
+    if (i < nb)
+#pragma unroll
+      for (int j = 0; j < 8; ++j) minv[(int64_t)(r0 + i) * 8 + j] = (j < nb) ? (T)inv[i][j] : (T)0;
+}
+
+template <typename T>
+void launch_block_inv(const int* rp, const int* col, const double* v64, const int* bp, int nblk, void* minv,
+                      hipStream_t s) {
+  if (nblk > 0)
+    hipLaunchKernelGGL(k_block_inv<T>, dim3((nblk + 127) / 128), dim3(128), 0, s, rp, col, v64, bp, nblk, (T*)minv);
+}
+template void launch_block_inv<float>(const int*, const int*, const double*, const int*, int, void*, hipStream_t);
+template void launch_block_inv<double>(const int*, const int*, const double*, const int*, int, void*, hipStream_t);
 
 #define MOR_VSWITCH(T, V, KERNEL, ...)                                                                  \
   do {                                                                                                  \
@@ -544,13 +681,18 @@ template <typename T>
 void launch_cg_shadow(const CgSys* sys, const int4* tiles, int ntiles, int rb, int v, hipStream_t s) {
   if (ntiles > 0) MOR_VSWITCH(T, v, k_cg_shadow, sys, tiles, ntiles, rb);
 }
+template <typename T>
+void launch_cg_pstart(const CgSys* sys, const int4* tiles, int ntiles, int bpt, int v, CgCols cols, hipStream_t s) {
+  if (ntiles > 0) MOR_VSWITCH(T, v, k_cg_pstart, sys, tiles, ntiles, bpt, cols);
+}
 #define MOR_INST(T)                                                                                      \
   template void launch_cg_init<T>(const CgSys*, const int4*, int, int, int, CgCols, hipStream_t);       \
   template void launch_cg_spmm<T>(const CgSys*, const int4*, int, int, int, CgCols, hipStream_t);       \
   template void launch_cg_update<T>(const CgSys*, const int4*, int, int, int, CgCols, hipStream_t);     \
   template void launch_cg_direction<T>(const CgSys*, const int4*, int, int, int, CgCols, hipStream_t);  \
   template void launch_cg_residual64<T>(const CgSys*, const int4*, int, int, int, CgCols, hipStream_t); \
-  template void launch_cg_shadow<T>(const CgSys*, const int4*, int, int, int, hipStream_t);
+  template void launch_cg_shadow<T>(const CgSys*, const int4*, int, int, int, hipStream_t);        \
+  template void launch_cg_pstart<T>(const CgSys*, const int4*, int, int, int, CgCols, hipStream_t);
 MOR_INST(float)
 MOR_INST(double)
 #undef MOR_INST

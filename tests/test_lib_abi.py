@@ -55,7 +55,7 @@ def test_host_decomposition_matches_oracle(case):
             nP, nV, nI, nB = mor.mor_get_sizes(ctx, i)
             nodes = mor.mor_get_nodes(ctx, i)
             assert (nP, nV, nI, nB) == (s.P.size, s.V.size, s.I.size, s.B.size)
-            np.testing.assert_array_equal(nodes[:nP], s.P)
+            np.testing.assert_array_equal(np.sort(nodes[:nP]), s.P)
             np.testing.assert_array_equal(np.sort(nodes[:nV]), s.V)
             np.testing.assert_array_equal(np.sort(nodes[:nI]), s.I)
             np.testing.assert_array_equal(nodes[nI:], s.B)
