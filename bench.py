@@ -85,14 +85,15 @@ def main():
     prec = args.precision or PRECISION_OF[args.config]
     p = w.make_config(args.config)
     print(f"[bench] {args.config}: {p.subdomains.n_sub} subdomains, precision {prec}", file=sys.stderr, flush=True)
-    spmm_vec, spmm_rows = 0, args.spmm_rows
-    if not spmm_rows:
+    tile = {}
+    if not args.spmm_rows:
         from paper_2404_06260_amd import autotune
-        tuned = autotune.best(p, prec)
-        if tuned:
-            spmm_vec, spmm_rows = tuned
-            print(f"[bench] autotuned SpMM tile: {64 * spmm_vec} columns x {spmm_rows} rows", file=sys.stderr, flush=True)
-    m = mor.Mor(p, precision=prec, spmm_rows=spmm_rows, spmm_vec=spmm_vec)
+        tile = autotune.best(p, prec) or {}
+        if tile:
+            print(f"[bench] autotuned tiles: {tile}", file=sys.stderr, flush=True)
+    else:
+        tile = dict(spmm_rows=args.spmm_rows)
+    m = mor.Mor(p, precision=prec, **tile)
     n_sub = p.subdomains.n_sub
 
     def step():
@@ -152,7 +153,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": WORKLOAD_OF[args.config], "name": args.config, "subdomains": n_sub,
                    "precision": prec, "reduced_dim": int(nred),
-                   "spmm_tile": [64 * (spmm_vec or 4), spmm_rows or 32]},
+                   "tiles": tile or "library defaults"},
         "roofline": {"bound": "hbm", "kernel": "k_cg_spmm (block-CG SpMM Q = A_II P)", "achieved": round(achieved, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": None, "avg_launch_ms": round(avg_ms, 4), "launches": n_launch,

@@ -97,6 +97,8 @@ typedef struct {
   int32_t cg_chunk;        /* CG iterations launched between two convergence polls */
   int32_t spmm_rows;       /* rows per SpMM workgroup tile (0 = automatic) */
   int32_t spmm_vec;        /* SpMM tile width in units of 64 columns: 1, 2 or 4 (0 = automatic) */
+  int32_t stream_vec;      /* width of the streaming CG kernels' tiles in units of 64 columns */
+  int32_t stream_blocks;   /* row aggregates per streaming tile (0 = automatic) */
   int32_t use_graph;       /* capture each CG chunk in a HIP graph and replay it */
   size_t hbm_budget_bytes; /* device bytes one batch of local reductions may use (0 = 75% free) */
   mor_alloc_fn dev_alloc;  /* NULL: hipMalloc */

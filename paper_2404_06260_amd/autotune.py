@@ -1,10 +1,12 @@
-"""Autotuner for the block-CG SpMM tile: width (64, 128 or 256 columns) and rows per tile.
+"""Autotuner for the block-CG tiles.
 
-Each candidate runs the batched local reduction of a workload with a loose CG tolerance (a
-few dozen iterations of the real kernels on the real matrices) and is timed with the
-library's HIP-event timer on its stream; the candidate with the highest algorithmic SpMM
-bandwidth wins.  Results are cached per device name and workload in a JSON file next to
-this module, and `best()` returns the cached choice (or None).
+Two sweeps on the real workload, each candidate running the batched local reduction with a
+loose CG tolerance (a few dozen iterations of the real kernels on the real matrices), timed
+with the library's HIP-event timers on its stream:
+  1. the SpMM tile: width (64, 128 or 256 columns) x rows per tile, best algorithmic GB/s;
+  2. the streaming (update / direction) tile: width x row aggregates per tile, least time.
+The winner is cached per device name and workload in a JSON file next to this module;
+`best()` returns the cached options (or None).
 """
 from __future__ import annotations
 
@@ -12,7 +14,8 @@ import json
 import os
 
 CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "autotune_cache.json")
-CANDIDATES = [(4, 4), (4, 8), (4, 16), (2, 8), (2, 16)]
+CANDIDATES = [(4, 4), (4, 8), (4, 16), (2, 8)]
+STREAM_CANDIDATES = [(2, 4), (2, 8), (2, 16), (1, 8), (4, 4), (4, 8)]
 
 
 def _key(problem, precision):
@@ -22,6 +25,7 @@ def _key(problem, precision):
 
 
 def best(problem, precision):
+    """Cached options dict (spmm_vec, spmm_rows, stream_vec, stream_blocks) or None."""
     if not os.path.exists(CACHE):
         return None
     try:
@@ -29,31 +33,55 @@ def best(problem, precision):
     except (OSError, ValueError):
         return None
     r = d.get(_key(problem, precision))
-    return None if r is None else (int(r["spmm_vec"]), int(r["spmm_rows"]))
+    if r is None:
+        return None
+    return {k: int(r[k]) for k in ("spmm_vec", "spmm_rows", "stream_vec", "stream_blocks") if k in r}
 
 
-def tune(problem, precision="fp32_refine", candidates=CANDIDATES, sub_ids=None, verbose=True, save=True):
+def _run(problem, ids, cg_prec, opts):
     import numpy as np
     from . import mor
+    m = mor.Mor(problem, precision=cg_prec, cg_rtol=1e-2, refine_rtol=1e-2, **opts)
+    try:
+        mor.mor_timing_enable(m.ctx, True)
+        ranks = np.full(ids.size, problem.rank, dtype=np.int32)
+        mor.mor_local_basis_batch(m.ctx, ids, ranks)
+        return {k: mor.mor_timing_get(m.ctx, k) for k in ("spmm", "cg_update", "cg_direction")}
+    finally:
+        m.close()
+
+
+def tune(problem, precision="fp32_refine", sub_ids=None, verbose=True, save=True):
+    import numpy as np
     cg_prec = "fp64" if precision == "fp64" else "fp32"
-    results = []
     ids = np.arange(problem.subdomains.n_sub) if sub_ids is None else np.asarray(sub_ids)
-    for v, rb in candidates:
+    sp_res = []
+    for v, rb in CANDIDATES:
         if cg_prec == "fp64" and v > 2:
             continue
-        m = mor.Mor(problem, precision=cg_prec, spmm_vec=v, spmm_rows=rb, cg_rtol=1e-2, refine_rtol=1e-2)
-        try:
-            mor.mor_timing_enable(m.ctx, True)
-            ranks = np.full(ids.size, problem.rank, dtype=np.int32)
-            mor.mor_local_basis_batch(m.ctx, ids, ranks)
-            n, ms, by = mor.mor_timing_get(m.ctx, "spmm")
-        finally:
-            m.close()
+        t = _run(problem, ids, cg_prec, dict(spmm_vec=v, spmm_rows=rb))
+        n, ms, by = t["spmm"]
         gbs = (by / n) / (ms / n * 1e-3) / 1e9 if n and ms > 0 else 0.0
-        results.append(dict(spmm_vec=v, spmm_rows=rb, launches=n, avg_ms=ms / max(n, 1), gbs=gbs))
+        sp_res.append(dict(spmm_vec=v, spmm_rows=rb, launches=n, avg_ms=ms / max(n, 1), gbs=gbs))
         if verbose:
-            print(f"[autotune] v={v} rows={rb}: {n} launches, {ms / max(n, 1):.3f} ms avg, {gbs:.0f} GB/s", flush=True)
-    win = max(results, key=lambda r: r["gbs"])
+            print(f"[autotune] spmm v={v} rows={rb}: {n} launches, {ms / max(n, 1):.3f} ms avg, {gbs:.0f} GB/s",
+                  flush=True)
+    sp = max(sp_res, key=lambda r: r["gbs"])
+    st_res = []
+    for v, nb in STREAM_CANDIDATES:
+        if cg_prec == "fp64" and v > 2:
+            continue
+        t = _run(problem, ids, cg_prec, dict(spmm_vec=sp["spmm_vec"], spmm_rows=sp["spmm_rows"], stream_vec=v,
+                                             stream_blocks=nb))
+        ms = t["cg_update"][1] + t["cg_direction"][1]
+        n = t["cg_update"][0]
+        st_res.append(dict(stream_vec=v, stream_blocks=nb, launches=n, ms=ms))
+        if verbose:
+            print(f"[autotune] stream v={v} blocks={nb}: {n} iterations, update+direction {ms / max(n, 1):.3f} ms/iter",
+                  flush=True)
+    st = min(st_res, key=lambda r: r["ms"] / max(r["launches"], 1))
+    win = dict(spmm_vec=sp["spmm_vec"], spmm_rows=sp["spmm_rows"], spmm_gbs=sp["gbs"], stream_vec=st["stream_vec"],
+               stream_blocks=st["stream_blocks"])
     if save:
         d = {}
         if os.path.exists(CACHE):
@@ -61,10 +89,10 @@ def tune(problem, precision="fp32_refine", candidates=CANDIDATES, sub_ids=None, 
                 d = json.load(open(CACHE))
             except (OSError, ValueError):
                 d = {}
-        d[_key(problem, precision)] = dict(win, all=results)
+        d[_key(problem, precision)] = dict(win, spmm_all=sp_res, stream_all=st_res)
         with open(CACHE, "w") as f:
             json.dump(d, f, indent=1)
-    return win, results
+    return win
 
 
 if __name__ == "__main__":
@@ -73,5 +101,4 @@ if __name__ == "__main__":
     import workloads as w
     name = sys.argv[1] if len(sys.argv) > 1 else "C2"
     prec = sys.argv[2] if len(sys.argv) > 2 else "fp32_refine"
-    win, _ = tune(w.make_config(name), prec)
-    print(json.dumps(win))
+    print(json.dumps(tune(w.make_config(name), prec)))

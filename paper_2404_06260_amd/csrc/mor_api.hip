@@ -804,8 +804,10 @@ static int local_batch_t(mor_ctx* c, std::vector<Slot>& slots) {
   cs.sp.v = c->opts.spmm_vec > 0 ? c->opts.spmm_vec : 4;
   cs.sp.rb = c->opts.spmm_rows > 0 ? std::min(c->opts.spmm_rows, 64) : 8;
   if (!fp32 && cs.sp.v > 2) cs.sp.v = 2;
-  cs.stm.v = 2;    // block kernels hold 8 rows per lane: 2 values per row keeps registers low
-  cs.stm.rb = 8;   // aggregates per tile (2 per wave)
+  // block kernels hold 8 rows per lane: 2 values per row keeps registers low
+  cs.stm.v = c->opts.stream_vec > 0 ? c->opts.stream_vec : 2;
+  if (!fp32 && cs.stm.v > 2) cs.stm.v = 2;
+  cs.stm.rb = c->opts.stream_blocks > 0 ? c->opts.stream_blocks : 8;   // aggregates per tile
   std::vector<int> sys_sub(nsys), sys_nnz(nsys);
   std::vector<int> sys_of_col(total_cols);
   int coff = 0;

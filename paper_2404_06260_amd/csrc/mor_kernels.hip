@@ -716,26 +716,41 @@ __global__ void k_cg_alpha(CgCols c) {
   c.pq[j] = 0.0;
 }
 
+// Count active columns per system with one atomic per wave when the wave's columns belong to
+// one system (the common case), instead of one atomic per column on a shared counter.
+__device__ __forceinline__ void count_active_wave(const CgCols& c, int j, bool active) {
+  const int sys = j < c.ncols_total ? c.sys_of_col[j] : -1;
+  const int s0 = __shfl(sys, 0);
+  const bool uniform = __all(sys == s0);
+  if (uniform) {
+    const unsigned long long m = __ballot(active);
+    if ((threadIdx.x & 63) == 0 && m != 0ull) atomicAdd(&c.nactive[s0], (int)__popcll(m));
+  } else if (active) {
+    atomicAdd(&c.nactive[sys], 1);
+  }
+}
+__device__ __forceinline__ void count_active(const CgCols&, int) {}
+
 __global__ void k_cg_beta(CgCols c, double tol2) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= c.ncols_total) return;
-  const double rn = c.rznew[j];
-  c.rznew[j] = 0.0;
-  if (!c.active[j]) {
-    c.beta[j] = 0.0;
-    return;
+  bool still = false;
+  if (j < c.ncols_total) {
+    const double rn = c.rznew[j];
+    c.rznew[j] = 0.0;
+    if (!c.active[j]) {
+      c.beta[j] = 0.0;
+    } else if (rn <= tol2 * c.rz0[j]) {
+      c.active[j] = 0;
+      c.beta[j] = 0.0;
+      c.rz[j] = rn;
+    } else {
+      c.beta[j] = rn / c.rz[j];
+      c.rz[j] = rn;
+      still = true;
+    }
   }
-  if (rn <= tol2 * c.rz0[j]) {
-    c.active[j] = 0;
-    c.beta[j] = 0.0;
-    c.rz[j] = rn;
-    return;
-  }
-  c.beta[j] = rn / c.rz[j];
-  c.rz[j] = rn;
-  atomicAdd(&c.nactive[c.sys_of_col[j]], 1);
+  count_active_wave(c, j, still);
 }
-
 // After the initial right-hand side: references, flags, zero accumulators.
 __global__ void k_cg_start(CgCols c) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
@@ -763,8 +778,7 @@ __global__ void k_cg_restart(CgCols c, double tol2_outer) {
 }
 __global__ void k_cg_count(CgCols c) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= c.ncols_total) return;
-  if (c.active[j]) atomicAdd(&c.nactive[c.sys_of_col[j]], 1);
+  count_active_wave(c, j, j < c.ncols_total && c.active[j] != 0);
 }
 __global__ void k_cg_zero_count(CgCols c) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
