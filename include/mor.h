@@ -100,6 +100,8 @@ typedef struct {
   int32_t stream_vec;      /* width of the streaming CG kernels' tiles in units of 64 columns */
   int32_t stream_blocks;   /* row aggregates per streaming tile (0 = automatic) */
   int32_t use_graph;       /* capture each CG chunk in a HIP graph and replay it */
+  int32_t dense_batch;     /* finished requests gathered before the dense stage runs while others
+                              still iterate (0 = 16; 1 = lowest latency) */
   size_t hbm_budget_bytes; /* device bytes one batch of local reductions may use (0 = 75% free) */
   mor_alloc_fn dev_alloc;  /* NULL: hipMalloc */
   mor_free_fn dev_free;    /* NULL: hipFree */
@@ -149,15 +151,22 @@ int mor_project(mor_ctx* ctx);
 int mor_solve(mor_ctx* ctx, double* u_out, int64_t* n_reduced_out);
 
 /* ---- serving: continuous batching of local-reduction requests ---------------
- * mor_submit queues a request for subdomain `sd`; it is admitted when device
- * memory within hbm_budget_bytes is free, joins the running block-CG launches at
- * the next chunk boundary, and completes independently of the others.
- * mor_poll drives the device loop one chunk and reports a request's state;
- * done = 1 when finished, status = its result code. */
+ * mor_submit queues a request for subdomain `sd` (rank/tol as in mor_local_basis,
+ * precision one of MOR_FP64..MOR_BF16_SPLIT); it is admitted when device memory
+ * within hbm_budget_bytes is free, joins the running block-CG launches at the
+ * next chunk boundary, and completes independently of the others.  mor_poll
+ * reports a request's state without driving the device: done = 1 when finished,
+ * status = its result code.  mor_local_basis_batch uses the same engine. */
 int mor_submit(mor_ctx* ctx, int32_t sd, int32_t rank, double tol, int32_t precision, uint64_t* ticket);
 int mor_poll(mor_ctx* ctx, uint64_t ticket, int32_t* done, int32_t* status);
 /* Drive the serving loop until every submitted request has finished. */
 int mor_drain(mor_ctx* ctx);
+/* Advance the serving loop by one tick (admission, one CG chunk, completions). */
+int mor_step(mor_ctx* ctx);
+/* Engine state: live (admitted) and pending requests, device bytes held by live requests,
+ * the peak of that since creation, and the admission budget. */
+int mor_engine_stats(mor_ctx* ctx, int32_t* live, int32_t* pending, int64_t* live_bytes, int64_t* peak_bytes,
+                     int64_t* budget);
 
 /* ---- results and diagnostics (host copies) ---------------------------------- */
 

@@ -94,6 +94,7 @@ struct mor_ctx {
   std::vector<void*> allocs;
   bool timing = false;
   std::map<std::string, TimerRec> timers;
+  struct MorEngine* eng[2] = {nullptr, nullptr};   // FP32-CG and FP64-CG engines
 };
 
 // ------------------------------------------------------------------------------- memory
@@ -184,6 +185,10 @@ static void flush_timers(mor_ctx* c) {
     kv.second.ev.clear();
   }
 }
+
+struct MorEngine;
+static void engine_free(mor_ctx* c, MorEngine& e);
+static void engine_delete(MorEngine* e);
 
 // ------------------------------------------------------------------------------- C-ABI basics
 extern "C" const char* mor_last_error(void) { return g_err.c_str(); }
@@ -310,6 +315,12 @@ extern "C" void mor_destroy(mor_ctx* c) {
     return;
   }
   (void)hipStreamSynchronize(c->st);
+  for (int k = 0; k < 2; ++k)
+    if (c->eng[k]) {
+      engine_free(c, *c->eng[k]);
+      engine_delete(c->eng[k]);
+      c->eng[k] = nullptr;
+    }
   for (auto& kv : c->timers)
     for (auto& e : kv.second.ev) {
       (void)hipEventDestroy(e.first);
@@ -426,181 +437,14 @@ static GemmDesc gd(int m, int n, int k, const double* A, int lda, int ta, const 
 }
 
 // ------------------------------------------------------------------------------- block CG
+// ------------------------------------------------------------------------------- CG tiles
 struct TileCfg {
   int v = 4;    // elements per lane: tile width 64 v columns
-  int rb = 32;  // rows per tile
+  int rb = 32;  // rows (row tiles) or aggregates (block tiles) per tile
 };
-
-struct CgState {
-  std::vector<CgSys> hsys;
-  CgSys* dsys = nullptr;
-  CgCols cols{};
-  int* d_tiles_buf = nullptr;   // SpMM tiles, then streaming tiles
-  size_t tiles_cap = 0;
-  int* h_nactive = nullptr;     // pinned
-  std::vector<int> iters;
-  TileCfg sp, stm;              // SpMM-like kernels (neighbour reads) and streaming kernels
-  int elt = 4;                  // bytes of the CG scalar type
-};
-
-// tiles of the active systems: (system, first row, first column), row blocks fastest so that
-// consecutive tiles (one XCD) sweep the rows of one column slab
-// by_block: tiles over row aggregates (rb = aggregates per tile) instead of rows
-static void make_tiles(const CgState& cs, const std::vector<char>& act, const TileCfg& tc, std::vector<int4>& t,
-                       bool by_block) {
-  const int W = 64 * tc.v;
-  for (size_t s = 0; s < cs.hsys.size(); ++s) {
-    if (!act[s]) continue;
-    const CgSys& S = cs.hsys[s];
-    const int n = by_block ? S.nblk : S.nI;
-    for (int c0 = 0; c0 < S.ld; c0 += W)
-      for (int r0 = 0; r0 < n; r0 += tc.rb) t.push_back(make_int4((int)s, r0, c0, 0));
-  }
-}
-
-// Both tile lists of the active systems in one device buffer: [spmm tiles | streaming tiles].
-static int upload_tiles(mor_ctx* c, CgState& cs, const std::vector<char>& act, int4** sp, int* nsp, int4** st,
-                        int* nst) {
-  std::vector<int4> t;
-  make_tiles(cs, act, cs.sp, t, false);
-  *nsp = (int)t.size();
-  make_tiles(cs, act, cs.stm, t, true);
-  *nst = (int)t.size() - *nsp;
-  if (t.size() > cs.tiles_cap) {
-    dfree(c, cs.d_tiles_buf);
-    cs.tiles_cap = t.size() + t.size() / 2;
-    cs.d_tiles_buf = (int*)dalloc(c, sizeof(int4) * cs.tiles_cap);
-    if (!cs.d_tiles_buf) return fail(MOR_ENOMEM, "tile list allocation failed");
-  }
-  if (!t.empty())
-    HIPCHK(hipMemcpyAsync(cs.d_tiles_buf, t.data(), sizeof(int4) * t.size(), hipMemcpyHostToDevice, c->st));
-  HIPCHK(hipStreamSynchronize(c->st));   // t is pageable host memory
-  *sp = (int4*)cs.d_tiles_buf;
-  *st = *sp + *nsp;
-  return 0;
-}
-
-// algorithmic bytes of one SpMM over the active systems: CSR of A_II + read P once + write Q
-static double spmm_bytes(const CgState& cs, const std::vector<char>& act, const std::vector<int>& sys_nnz) {
-  double b = 0;
-  for (size_t s = 0; s < cs.hsys.size(); ++s) {
-    if (!act[s]) continue;
-    const CgSys& S = cs.hsys[s];
-    b += (double)sys_nnz[s] * (4.0 + cs.elt) + 4.0 * (S.nI + 1) + 2.0 * cs.elt * (double)S.nI * S.ncols;
-  }
-  return b;
-}
-
-template <typename T>
-static int cg_iterate(mor_ctx* c, CgState& cs, std::vector<char>& act, double tol, const std::vector<int>& sys_sub,
-                      const std::vector<int>& sys_nnz) {
-  const int chunk = std::max(1, c->opts.cg_chunk);
-  const int nsys = (int)cs.hsys.size();
-  int it = 0;
-  for (;;) {
-    bool any = false;
-    for (int s = 0; s < nsys; ++s) any |= act[s] != 0;
-    if (!any) break;
-    if (it >= c->opts.max_iter) return fail(MOR_ENOTCONV, "block CG did not converge within max_iter");
-    int4 *dsp, *dst;
-    int nsp, nst;
-    if (int rc = upload_tiles(c, cs, act, &dsp, &nsp, &dst, &nst)) return rc;
-    const double by = spmm_bytes(cs, act, sys_nnz);
-    const double tol2 = tol * tol;
-    for (int k = 0; k < chunk; ++k) {
-      {
-        ScopedTimer tm(c, "spmm", by);
-        launch_cg_spmm<T>(cs.dsys, dsp, nsp, cs.sp.rb, cs.sp.v, cs.cols, c->st);
-      }
-      launch_cg_alpha(cs.cols, c->st);
-      {
-        ScopedTimer tm(c, "cg_update", 0);
-        launch_cg_update<T>(cs.dsys, dst, nst, cs.stm.rb, cs.stm.v, cs.cols, c->st);
-      }
-      launch_cg_beta(cs.cols, tol2, c->st);
-      {
-        ScopedTimer tm(c, "cg_direction", 0);
-        launch_cg_direction<T>(cs.dsys, dst, nst, cs.stm.rb, cs.stm.v, cs.cols, c->st);
-      }
-    }
-    HIPCHK(hipGetLastError());
-    HIPCHK(hipMemcpyAsync(cs.h_nactive, cs.cols.nactive, sizeof(int) * nsys, hipMemcpyDeviceToHost, c->st));
-    HIPCHK(hipStreamSynchronize(c->st));
-    for (int s = 0; s < nsys; ++s) {
-      if (act[s]) cs.iters[s] += chunk;
-      act[s] = cs.h_nactive[s] > 0;
-    }
-    it += chunk;
-  }
-  return 0;
-}
-
-template <typename T>
-static int cg_solve(mor_ctx* c, CgState& cs, const std::vector<int>& sys_sub, const std::vector<int>& sys_nnz,
-                    std::vector<int>& refines) {
-  const int nsys = (int)cs.hsys.size();
-  const bool refine = c->opts.precision == MOR_FP32_REFINE;
-  const double inner = (c->opts.precision == MOR_FP64) ? c->opts.refine_rtol : c->opts.cg_rtol;
-  std::vector<char> all(nsys, 1), act(nsys, 1);
-  // tile lists over every system (init, refinement passes) kept apart from the iteration lists
-  std::vector<int4> ta;
-  make_tiles(cs, all, cs.sp, ta, false);
-  const int nta_sp = (int)ta.size();
-  make_tiles(cs, all, cs.stm, ta, true);
-  const int nta = (int)ta.size() - nta_sp;
-  int4* dta_sp = (int4*)dalloc(c, sizeof(int4) * std::max<size_t>(1, ta.size()));
-  if (!dta_sp) return fail(MOR_ENOMEM, "tile list allocation failed");
-  int4* dta = dta_sp + nta_sp;
-  HIPCHK(hipMemcpyAsync(dta_sp, ta.data(), sizeof(int4) * ta.size(), hipMemcpyHostToDevice, c->st));
-  HIPCHK(hipStreamSynchronize(c->st));
-  launch_fill(cs.cols.rz, cs.cols.ncols_total, 0.0, c->st);
-  launch_cg_init<T>(cs.dsys, dta_sp, nta_sp, cs.sp.rb, cs.sp.v, cs.cols, c->st);
-  launch_cg_pstart<T>(cs.dsys, dta, nta, cs.stm.rb, cs.stm.v, cs.cols, c->st);
-  launch_cg_start(cs.cols, 1, 0.0, c->st);
-  HIPCHK(hipMemcpyAsync(cs.h_nactive, cs.cols.nactive, sizeof(int) * nsys, hipMemcpyDeviceToHost, c->st));
-  HIPCHK(hipStreamSynchronize(c->st));
-  for (int s = 0; s < nsys; ++s) act[s] = cs.h_nactive[s] > 0;
-  int rc = cg_iterate<T>(c, cs, act, inner, sys_sub, sys_nnz);
-  if (rc) {
-    dfree(c, dta_sp);
-    return rc;
-  }
-  if (refine) {
-    const double outer2 = c->opts.refine_rtol * c->opts.refine_rtol;
-    for (int step = 0; step < c->opts.refine_steps; ++step) {
-      launch_cg_shadow<T>(cs.dsys, dta_sp, nta_sp, cs.sp.rb, cs.sp.v, c->st);
-      launch_fill(cs.cols.rz, cs.cols.ncols_total, 0.0, c->st);
-      {
-        ScopedTimer tm(c, "residual64", 0);
-        launch_cg_residual64<T>(cs.dsys, dta_sp, nta_sp, cs.sp.rb, cs.sp.v, cs.cols, c->st);
-      }
-      launch_cg_pstart<T>(cs.dsys, dta, nta, cs.stm.rb, cs.stm.v, cs.cols, c->st);
-      launch_cg_restart(cs.cols, outer2, c->st);
-      HIPCHK(hipMemcpyAsync(cs.h_nactive, cs.cols.nactive, sizeof(int) * nsys, hipMemcpyDeviceToHost, c->st));
-      HIPCHK(hipStreamSynchronize(c->st));
-      bool any = false;
-      for (int s = 0; s < nsys; ++s) {
-        act[s] = cs.h_nactive[s] > 0;
-        any |= act[s] != 0;
-        if (act[s]) refines[s]++;
-      }
-      if (!any) break;
-      rc = cg_iterate<T>(c, cs, act, inner, sys_sub, sys_nnz);
-      if (rc) {
-        dfree(c, dta_sp);
-        return rc;
-      }
-    }
-    launch_cg_shadow<T>(cs.dsys, dta_sp, nta_sp, cs.sp.rb, cs.sp.v, c->st);
-  }
-  HIPCHK(hipGetLastError());
-  HIPCHK(hipStreamSynchronize(c->st));
-  dfree(c, dta_sp);
-  return 0;
-}
 
 // ------------------------------------------------------------------------------- debug dumps
-// MOR_DUMP=<dir> writes intermediate device arrays of the first batch slot as raw files.
+// MOR_DUMP=<dir> writes intermediate device arrays of the first slot of a dense batch.
 static void dump(mor_ctx* c, const char* name, const void* dptr, size_t bytes) {
   const char* dir = getenv("MOR_DUMP");
   if (!dir || !dptr || !bytes) return;
@@ -632,19 +476,21 @@ static int truncation_rank(const std::vector<double>& s, int rank, double tol, i
   return std::min(k, cap);
 }
 
-// ------------------------------------------------------------------------------- local batch
+// ------------------------------------------------------------------------------- one request
 struct Slot {
-  int sd, rank;
+  int sd, rank, prec;
   double tol;
+  bool fp32, refine;
   const HostSub* h;
   const SubDev* d;
   int M, MP, T, colsA, ldA, colsK, ldK, s, nconv;
   double *A64, *K64, *Ki64, *f;
   float *A32, *K32;
-  void *dinvA, *dinvK;
+  void *minvA, *minvK;
   void *XA, *RA, *PA, *QA, *XK, *RK, *PK, *QK;
   double *XA64, *XK64;
-  double *Xc, *Ec;          // FP64 views of the solutions (converted in FP32 modes)
+  double* colst[2];         // per-column CG state of the two systems: 7 x ld doubles + ld ints
+  double *Xc, *Ec;          // FP64 views of the solutions (converted in the FP32 mode)
   int ldXc, ldEc;
   double *Y, *S, *G, *W, *C, *Dinv;
   double *Vb, *Yb, *Ub, *Zb, *Vn, *Tb, *H, *Ss, *G2, *Rinv, *theta, *resid;
@@ -653,7 +499,7 @@ struct Slot {
   int k_eff;
 };
 
-static int slot_sizes(mor_ctx* c, Slot& q, Sizer& z, int elt) {
+static void slot_shape(mor_ctx* c, Slot& q) {
   const HostSub& h = *q.h;
   q.M = h.nB;
   q.MP = (int)rup(q.M, 64);
@@ -662,54 +508,40 @@ static int slot_sizes(mor_ctx* c, Slot& q, Sizer& z, int elt) {
   q.ldA = (int)rup(q.colsA, 4);
   q.colsK = h.nB;
   q.ldK = (int)rup(q.colsK, 4);
-  int p = c->opts.oversample > 0 ? c->opts.oversample : std::max(8, q.rank);
+  const int p = c->opts.oversample > 0 ? c->opts.oversample : std::max(8, q.rank);
   int s = q.rank > 0 ? std::min(64, q.rank + p) : 64;
   s = std::min(s, q.M);
   q.s = s;
   q.nconv = q.rank > 0 ? std::min(s - 1, q.rank + std::max(2, p / 2)) : s - 1;
   if (q.nconv < 1) q.nconv = std::min(1, s);
-  const size_t nnz = h.rp[h.nL], nnzV = h.rpV[h.nV];
-  const bool fp32 = elt == 4;
-  const bool refine = c->opts.precision == MOR_FP32_REFINE;
-  z.add(8 * nnz); z.add(8 * nnz); z.add(8 * nnzV); z.add(8 * (size_t)h.nL);
-  if (fp32) { z.add(4 * nnz); z.add(4 * nnz); }
-  z.add((size_t)elt * h.nI * 8); z.add((size_t)elt * h.nI * 8);
-  for (int i = 0; i < 4; ++i) z.add((size_t)elt * h.nI * q.ldA);
-  for (int i = 0; i < 4; ++i) z.add((size_t)elt * h.nI * q.ldK);
-  if (refine) { z.add(8 * (size_t)h.nI * q.ldA); z.add(8 * (size_t)h.nI * q.ldK); }
-  if (fp32 && !refine) { z.add(8 * (size_t)h.nV * q.ldA); z.add(8 * (size_t)h.nI * q.ldK); }
-  z.add(8 * (size_t)h.nV * q.ldK);                       // Y
-  for (int i = 0; i < 4; ++i) z.add(8 * (size_t)q.MP * q.MP);   // S, G, W, C
-  z.add(8 * (size_t)q.T * 4096);
-  for (int i = 0; i < 6; ++i) z.add(8 * (size_t)q.MP * s);
-  for (int i = 0; i < 4; ++i) z.add(8 * (size_t)s * s);
-  z.add(8 * (size_t)s); z.add(8 * (size_t)s);
-  z.add(8 * (size_t)q.MP * 64); z.add(8 * (size_t)q.MP * 64);
-  z.add(8 * (size_t)std::max(1, h.nP) * (s + 2));
-  z.add(64);
-  return 0;
+  q.fp32 = q.prec != MOR_FP64;
+  q.refine = q.prec == MOR_FP32_REFINE;
 }
 
-static int slot_carve(mor_ctx* c, Slot& q, Arena& a, int elt) {
+// Device bytes of one request (CG blocks, dense matrices, eigensolver blocks), and the carve.
+template <typename Take>
+static bool slot_layout(Slot& q, Take tk) {
   const HostSub& h = *q.h;
   const size_t nnz = h.rp[h.nL], nnzV = h.rpV[h.nV];
-  const bool fp32 = elt == 4;
-  const bool refine = c->opts.precision == MOR_FP32_REFINE;
-  auto tk = [&](size_t b) { return a.take(b); };
-  q.A64 = (double*)tk(8 * nnz); q.K64 = (double*)tk(8 * nnz); q.Ki64 = (double*)tk(8 * nnzV); q.f = (double*)tk(8 * (size_t)h.nL);
-  q.A32 = fp32 ? (float*)tk(4 * nnz) : nullptr;
-  q.K32 = fp32 ? (float*)tk(4 * nnz) : nullptr;
-  q.dinvA = tk((size_t)elt * h.nI * 8); q.dinvK = tk((size_t)elt * h.nI * 8);   // block inverses
-  q.XA = tk((size_t)elt * h.nI * q.ldA); q.RA = tk((size_t)elt * h.nI * q.ldA);
-  q.PA = tk((size_t)elt * h.nI * q.ldA); q.QA = tk((size_t)elt * h.nI * q.ldA);
-  q.XK = tk((size_t)elt * h.nI * q.ldK); q.RK = tk((size_t)elt * h.nI * q.ldK);
-  q.PK = tk((size_t)elt * h.nI * q.ldK); q.QK = tk((size_t)elt * h.nI * q.ldK);
-  q.XA64 = refine ? (double*)tk(8 * (size_t)h.nI * q.ldA) : nullptr;
-  q.XK64 = refine ? (double*)tk(8 * (size_t)h.nI * q.ldK) : nullptr;
-  if (fp32 && !refine) {
+  const size_t elt = q.fp32 ? 4 : 8;
+  const int s = q.s;
+  q.A64 = (double*)tk(8 * nnz); q.K64 = (double*)tk(8 * nnz); q.Ki64 = (double*)tk(8 * nnzV);
+  q.f = (double*)tk(8 * (size_t)h.nL);
+  q.A32 = q.fp32 ? (float*)tk(4 * nnz) : nullptr;
+  q.K32 = q.fp32 ? (float*)tk(4 * nnz) : nullptr;
+  q.minvA = tk(elt * h.nI * 8); q.minvK = tk(elt * h.nI * 8);
+  q.XA = tk(elt * h.nI * q.ldA); q.RA = tk(elt * h.nI * q.ldA);
+  q.PA = tk(elt * h.nI * q.ldA); q.QA = tk(elt * h.nI * q.ldA);
+  q.XK = tk(elt * h.nI * q.ldK); q.RK = tk(elt * h.nI * q.ldK);
+  q.PK = tk(elt * h.nI * q.ldK); q.QK = tk(elt * h.nI * q.ldK);
+  q.XA64 = q.refine ? (double*)tk(8 * (size_t)h.nI * q.ldA) : nullptr;
+  q.XK64 = q.refine ? (double*)tk(8 * (size_t)h.nI * q.ldK) : nullptr;
+  q.colst[0] = (double*)tk(8 * 8 * (size_t)q.ldA + 64);
+  q.colst[1] = (double*)tk(8 * 8 * (size_t)q.ldK + 64);
+  if (q.fp32 && !q.refine) {
     q.Xc = (double*)tk(8 * (size_t)h.nV * q.ldA);
     q.Ec = (double*)tk(8 * (size_t)h.nI * q.ldK);
-  } else if (refine) {
+  } else if (q.refine) {
     q.Xc = q.XA64; q.Ec = q.XK64;
   } else {
     q.Xc = (double*)q.XA; q.Ec = (double*)q.XK;
@@ -719,7 +551,6 @@ static int slot_carve(mor_ctx* c, Slot& q, Arena& a, int elt) {
   q.S = (double*)tk(8 * (size_t)q.MP * q.MP); q.G = (double*)tk(8 * (size_t)q.MP * q.MP);
   q.W = (double*)tk(8 * (size_t)q.MP * q.MP); q.C = (double*)tk(8 * (size_t)q.MP * q.MP);
   q.Dinv = (double*)tk(8 * (size_t)q.T * 4096);
-  const int s = q.s;
   q.Vb = (double*)tk(8 * (size_t)q.MP * s); q.Yb = (double*)tk(8 * (size_t)q.MP * s);
   q.Ub = (double*)tk(8 * (size_t)q.MP * s); q.Zb = (double*)tk(8 * (size_t)q.MP * s);
   q.Vn = (double*)tk(8 * (size_t)q.MP * s); q.Tb = (double*)tk(8 * (size_t)q.MP * s);
@@ -729,49 +560,222 @@ static int slot_carve(mor_ctx* c, Slot& q, Arena& a, int elt) {
   q.Bk = (double*)tk(8 * (size_t)q.MP * 64); q.Wk = (double*)tk(8 * (size_t)q.MP * 64);
   q.Yf = (double*)tk(8 * (size_t)std::max(1, h.nP) * (s + 2));
   q.info = (int*)tk(64);
-  if (!q.info) return fail(MOR_ENOMEM, "arena exhausted");
+  return q.info != nullptr;
+}
+
+static size_t slot_bytes(Slot& q) {
+  Sizer z;
+  Slot tmp = q;
+  slot_layout(tmp, [&](size_t b) -> void* { z.add(b); return (void*)1; });
+  return z.total + 4096;
+}
+
+// ------------------------------------------------------------------------------- engine
+// Requests for local reductions flow through one engine per CG scalar type.  At each tick the
+// engine admits pending requests whose memory fits the HBM budget (their assembly and CG
+// start are batched), advances every system still iterating by one CG chunk in shared
+// launches, restarts systems that reached the inner tolerance from an FP64 residual (FP32 +
+// refinement), and runs the dense stage (Gram, Schur, Cholesky, eigensolve, basis, local
+// projection) for the requests whose two solves finished.  Requests therefore join and leave
+// the running block CG independently: continuous batching.
+struct SysRun {
+  CgSys S;
+  int cnt;        // index of this system's active-column counter
+  int phase;      // 0 iterating, 1 finished
+  int iters, refines;
+  int nnzII;
+};
+
+struct Live {
+  uint64_t id;
+  Slot q;
+  char* mem = nullptr;
+  size_t bytes = 0;
+  SysRun sys[2];
+  int status = 0;
+};
+
+struct Req {
+  uint64_t id;
+  int sd, rank, prec;
+  double tol;
+  int done = 0, status = 0;
+};
+
+struct MorEngine {
+  int elt = 4;
+  std::vector<Req> pending;
+  std::vector<Live*> live;
+  std::map<uint64_t, Req> finished;
+  CgSys* d_sys = nullptr;
+  size_t sys_cap = 0;
+  int4* d_tiles = nullptr;
+  size_t tiles_cap = 0;
+  int2* d_cb = nullptr;
+  size_t cb_cap = 0;
+  int* d_cnt = nullptr;
+  int* h_cnt = nullptr;
+  int cnt_cap = 0;
+  std::vector<int> cnt_free;
+  size_t live_bytes = 0, peak_bytes = 0, budget = 0;
+  TileCfg sp, stm;
+};
+
+static uint64_t g_next_ticket = 1;
+
+static int engine_init(mor_ctx* c, MorEngine& e, int elt) {
+  e.elt = elt;
+  e.cnt_cap = 8192;
+  e.d_cnt = (int*)palloc(c, sizeof(int) * e.cnt_cap);
+  if (!e.d_cnt) return fail(MOR_ENOMEM, "device allocation failed (engine counters)");
+  HIPCHK(hipHostMalloc((void**)&e.h_cnt, sizeof(int) * e.cnt_cap));
+  for (int i = e.cnt_cap - 1; i >= 0; --i) e.cnt_free.push_back(i);
+  const bool fp32 = elt == 4;
+  e.sp.v = c->opts.spmm_vec > 0 ? c->opts.spmm_vec : 4;
+  if (!fp32 && e.sp.v > 2) e.sp.v = 2;
+  e.sp.rb = c->opts.spmm_rows > 0 ? std::min(c->opts.spmm_rows, 64) : 8;
+  e.stm.v = c->opts.stream_vec > 0 ? c->opts.stream_vec : 2;   // block kernels hold 8 rows per lane
+  if (!fp32 && e.stm.v > 2) e.stm.v = 2;
+  e.stm.rb = c->opts.stream_blocks > 0 ? c->opts.stream_blocks : 8;
+  e.budget = c->opts.hbm_budget_bytes;
+  if (!e.budget) {
+    size_t fr = 0, tot = 0;
+    if (hipMemGetInfo(&fr, &tot) != hipSuccess) fr = (size_t)64 << 30;
+    e.budget = fr / 4 * 3;
+  }
   return 0;
 }
 
-template <typename T>
-static int local_batch_t(mor_ctx* c, std::vector<Slot>& slots) {
-  const int ns = (int)slots.size();
-  const int elt = (int)sizeof(T);
-  const bool fp32 = elt == 4;
-  const bool refine = c->opts.precision == MOR_FP32_REFINE;
-  hipStream_t st = c->st;
-  // ---- arena
-  Sizer z;
-  for (auto& q : slots) slot_sizes(c, q, z, elt);
-  int total_cols = 0;
-  for (auto& q : slots) total_cols += q.ldA + q.ldK;
-  const int nsys = 2 * ns;
-  z.add(sizeof(CgSys) * nsys);
-  for (int i = 0; i < 7; ++i) z.add(8 * (size_t)total_cols);
-  z.add(4 * (size_t)total_cols); z.add(4 * (size_t)total_cols); z.add(4 * (size_t)nsys);
-  z.add(sizeof(DenseSub) * ns + sizeof(TrsmDesc) * ns * 2);
-  z.add(8 * (size_t)ns * 32);          // pointer tables
-  z.add(4 * (size_t)ns * 8);
-  z.add(1 << 20);                      // gemm descriptors and tiles headroom
-  size_t gemm_extra = 0;
-  for (auto& q : slots) gemm_extra += 16 * (size_t)(q.T * q.T + 8 * q.T + 64) + 4 * sizeof(GemmDesc);
-  z.add(gemm_extra * 4);
-  const size_t budget = c->opts.hbm_budget_bytes;
-  if (budget && z.total > budget) return fail(MOR_ENOMEM, "batch exceeds the HBM budget");
-  Arena ar;
-  ar.cap = z.total + 4096;
-  ar.base = (char*)dalloc(c, ar.cap);
-  if (!ar.base) return fail(MOR_ENOMEM, "device allocation of " + std::to_string(ar.cap) + " bytes failed");
-  struct Guard {
-    mor_ctx* c; void* p;
-    ~Guard() { (void)hipStreamSynchronize(c->st); dfree(c, p); }
-  } guard{c, ar.base};
-  for (auto& q : slots)
-    if (int rc = slot_carve(c, q, ar, elt)) return rc;
+static void engine_free(mor_ctx* c, MorEngine& e) {
+  for (Live* L : e.live) {
+    dfree(c, L->mem);
+    delete L;
+  }
+  e.live.clear();
+  dfree(c, e.d_sys);
+  dfree(c, e.d_tiles);
+  dfree(c, e.d_cb);
+  if (e.h_cnt) (void)hipHostFree(e.h_cnt);
+  e.h_cnt = nullptr;
+}
 
-  // ---- assembly (Section 2 stiffness with kappa, Section 4 H1 matrices, load M f_h)
+template <typename T>
+static int grow(mor_ctx* c, T** p, size_t* cap, size_t need) {
+  if (need <= *cap && *p) return 0;
+  dfree(c, *p);
+  *cap = std::max<size_t>(need + need / 2, 64);
+  *p = (T*)dalloc(c, sizeof(T) * *cap);
+  if (!*p) return fail(MOR_ENOMEM, "device allocation failed (engine tables)");
+  return 0;
+}
+
+// Upload the systems in `list` as the device table; return tiles and column blocks over them.
+struct Launch {
+  std::vector<SysRun*> sys;
+  int4 *sp = nullptr, *bk = nullptr;
+  int nsp = 0, nbk = 0;
+  int2* cb = nullptr;
+  int ncb = 0;
+  double spmm_bytes = 0;
+};
+
+static int engine_upload(mor_ctx* c, MorEngine& e, Launch& L) {
+  const int n = (int)L.sys.size();
+  std::vector<CgSys> hs(n);
+  std::vector<int4> t;
+  std::vector<int2> cb;
+  L.spmm_bytes = 0;
+  for (int i = 0; i < n; ++i) {
+    hs[i] = L.sys[i]->S;
+    const CgSys& S = hs[i];
+    L.spmm_bytes += (double)L.sys[i]->nnzII * (4.0 + e.elt) + 4.0 * (S.nI + 1) + 2.0 * e.elt * (double)S.nI * S.ncols;
+  }
+  for (int i = 0; i < n; ++i) {
+    const CgSys& S = hs[i];
+    for (int c0 = 0; c0 < S.ld; c0 += 64 * e.sp.v)
+      for (int r0 = 0; r0 < S.nI; r0 += e.sp.rb) t.push_back(make_int4(i, r0, c0, 0));
+  }
+  L.nsp = (int)t.size();
+  for (int i = 0; i < n; ++i) {
+    const CgSys& S = hs[i];
+    for (int c0 = 0; c0 < S.ld; c0 += 64 * e.stm.v)
+      for (int b0 = 0; b0 < S.nblk; b0 += e.stm.rb) t.push_back(make_int4(i, b0, c0, 0));
+  }
+  L.nbk = (int)t.size() - L.nsp;
+  for (int i = 0; i < n; ++i)
+    for (int c0 = 0; c0 < hs[i].ld; c0 += 256) cb.push_back(make_int2(i, c0));
+  L.ncb = (int)cb.size();
+  if (int rc = grow(c, &e.d_sys, &e.sys_cap, (size_t)std::max(n, 1))) return rc;
+  if (int rc = grow(c, &e.d_tiles, &e.tiles_cap, std::max<size_t>(t.size(), 1))) return rc;
+  if (int rc = grow(c, &e.d_cb, &e.cb_cap, std::max<size_t>(cb.size(), 1))) return rc;
+  if (n) HIPCHK(hipMemcpyAsync(e.d_sys, hs.data(), sizeof(CgSys) * n, hipMemcpyHostToDevice, c->st));
+  if (!t.empty()) HIPCHK(hipMemcpyAsync(e.d_tiles, t.data(), sizeof(int4) * t.size(), hipMemcpyHostToDevice, c->st));
+  if (!cb.empty()) HIPCHK(hipMemcpyAsync(e.d_cb, cb.data(), sizeof(int2) * cb.size(), hipMemcpyHostToDevice, c->st));
+  HIPCHK(hipStreamSynchronize(c->st));   // the host vectors are pageable
+  L.sp = e.d_tiles;
+  L.bk = e.d_tiles + L.nsp;
+  L.cb = e.d_cb;
+  return 0;
+}
+
+static int read_counts(mor_ctx* c, MorEngine& e) {
+  HIPCHK(hipMemcpyAsync(e.h_cnt, e.d_cnt, sizeof(int) * e.cnt_cap, hipMemcpyDeviceToHost, c->st));
+  HIPCHK(hipStreamSynchronize(c->st));
+  return 0;
+}
+
+// Admit pending requests that fit, assemble them and start their CG (batched).
+template <typename T>
+static int engine_admit(mor_ctx* c, MorEngine& e) {
+  hipStream_t st = c->st;
+  std::vector<Live*> adm;
+  size_t k = 0;
+  for (; k < e.pending.size(); ++k) {
+    const Req& r = e.pending[k];
+    Live* L = new Live();
+    L->id = r.id;
+    Slot& q = L->q;
+    std::memset(&q, 0, sizeof(q));
+    q.sd = r.sd; q.rank = r.rank; q.tol = r.tol; q.prec = r.prec;
+    q.h = &c->subs[r.sd];
+    q.d = &c->sdev[r.sd];
+    slot_shape(c, q);
+    L->bytes = slot_bytes(q);
+    if (L->bytes > e.budget) {
+      delete L;
+      Req done = r;
+      done.done = 1;
+      done.status = MOR_ENOMEM;
+      e.finished[r.id] = done;
+      g_err = "subdomain " + std::to_string(r.sd) + " alone exceeds the HBM budget";
+      continue;
+    }
+    if (e.live_bytes + L->bytes > e.budget || (int)e.cnt_free.size() < 2) {
+      delete L;
+      break;   // FIFO: wait for memory to free up
+    }
+    L->mem = (char*)dalloc(c, L->bytes);
+    if (!L->mem) {
+      delete L;
+      if (e.live.empty()) return fail(MOR_ENOMEM, "device allocation failed (request)");
+      break;
+    }
+    Arena ar{L->mem, L->bytes, 0};
+    if (!slot_layout(q, [&](size_t b) { return ar.take(b); })) {
+      dfree(c, L->mem);
+      delete L;
+      return fail(MOR_ENOMEM, "arena exhausted (request)");
+    }
+    e.live_bytes += L->bytes;
+    e.peak_bytes = std::max(e.peak_bytes, e.live_bytes);
+    adm.push_back(L);
+  }
+  e.pending.erase(e.pending.begin(), e.pending.begin() + k);
+  if (adm.empty()) return 0;
+  // assembly of the new requests (Section 2 stiffness with kappa, Section 4 H1 matrices, load)
   std::vector<AsmJob> jobs;
-  for (auto& q : slots) {
+  for (Live* L : adm) {
+    Slot& q = L->q;
     const HostSub& h = *q.h;
     launch_fill(q.A64, h.rp[h.nL], 0.0, st);
     launch_fill(q.K64, h.rp[h.nL], 0.0, st);
@@ -780,48 +784,26 @@ static int local_batch_t(mor_ctx* c, std::vector<Slot>& slots) {
     jobs.push_back({q.h, q.d, q.A64, q.K64, q.Ki64, q.f});
   }
   if (int rc = assemble_batch(c, jobs)) return rc;
-  for (auto& q : slots) {
+  Launch Ln;
+  for (Live* L : adm) {
+    Slot& q = L->q;
     const HostSub& h = *q.h;
-    if (fp32) {
+    const int nblk = (int)h.bp.size() - 1;
+    if (sizeof(T) == 4) {
       launch_to_f32(q.A64, q.A32, h.rp[h.nL], st);
       launch_to_f32(q.K64, q.K32, h.rp[h.nL], st);
     }
-    const int nblk = (int)h.bp.size() - 1;
-    if (fp32) {
-      launch_block_inv<float>(q.d->rp, q.d->col, q.A64, q.d->bp, nblk, q.dinvA, st);
-      launch_block_inv<float>(q.d->rp, q.d->col, q.K64, q.d->bp, nblk, q.dinvK, st);
-    } else {
-      launch_block_inv<double>(q.d->rp, q.d->col, q.A64, q.d->bp, nblk, q.dinvA, st);
-      launch_block_inv<double>(q.d->rp, q.d->col, q.K64, q.d->bp, nblk, q.dinvK, st);
-    }
-  }
-
-  // ---- block CG on A_II (lifting + load) and K_II (H1 extension for S_B)
-  CgState cs;
-  cs.elt = elt;
-  // SpMM tiles: 64 columns (256 B of FP32 per row) x 32 rows keep one XCD's rows in flight
-  // and their stencil halo inside its L2; streaming kernels use 16-byte lanes.
-  cs.sp.v = c->opts.spmm_vec > 0 ? c->opts.spmm_vec : 4;
-  cs.sp.rb = c->opts.spmm_rows > 0 ? std::min(c->opts.spmm_rows, 64) : 8;
-  if (!fp32 && cs.sp.v > 2) cs.sp.v = 2;
-  // block kernels hold 8 rows per lane: 2 values per row keeps registers low
-  cs.stm.v = c->opts.stream_vec > 0 ? c->opts.stream_vec : 2;
-  if (!fp32 && cs.stm.v > 2) cs.stm.v = 2;
-  cs.stm.rb = c->opts.stream_blocks > 0 ? c->opts.stream_blocks : 8;   // aggregates per tile
-  std::vector<int> sys_sub(nsys), sys_nnz(nsys);
-  std::vector<int> sys_of_col(total_cols);
-  int coff = 0;
-  for (int i = 0; i < ns; ++i) {
-    Slot& q = slots[i];
-    const HostSub& h = *q.h;
+    launch_block_inv<T>(q.d->rp, q.d->col, q.A64, q.d->bp, nblk, q.minvA, st);
+    launch_block_inv<T>(q.d->rp, q.d->col, q.K64, q.d->bp, nblk, q.minvK, st);
     int nnzII = 0;
     for (int r = 0; r < h.nI; ++r) nnzII += h.ii_end[r] - h.rp[r];
     for (int w = 0; w < 2; ++w) {
-      CgSys S{};
+      SysRun& R = L->sys[w];
+      CgSys& S = R.S;
+      std::memset(&S, 0, sizeof(S));
       S.rp = q.d->rp; S.col = q.d->col; S.ii_end = q.d->ii_end;
       S.val32 = w == 0 ? q.A32 : q.K32;
       S.val64 = w == 0 ? q.A64 : q.K64;
-      S.dinv = w == 0 ? q.dinvA : q.dinvK;
       S.f = w == 0 ? q.f : nullptr;
       S.nI = h.nI; S.nB = h.nB;
       S.ncols = w == 0 ? q.colsA : q.colsK;
@@ -829,41 +811,205 @@ static int local_batch_t(mor_ctx* c, std::vector<Slot>& slots) {
       S.X = w == 0 ? q.XA : q.XK; S.R = w == 0 ? q.RA : q.RK;
       S.P = w == 0 ? q.PA : q.PK; S.Q = w == 0 ? q.QA : q.QK;
       S.X64 = w == 0 ? q.XA64 : q.XK64;
-      S.coff = coff;
       S.bp = q.d->bp;
-      S.nblk = (int)h.bp.size() - 1;
-      S.minv = w == 0 ? q.dinvA : q.dinvK;
-      const int sidx = 2 * i + w;
-      for (int j = 0; j < S.ld; ++j) sys_of_col[coff + j] = sidx;
-      coff += S.ld;
-      cs.hsys.push_back(S);
-      sys_sub[sidx] = i;
-      sys_nnz[sidx] = nnzII;
+      S.nblk = nblk;
+      S.minv = w == 0 ? q.minvA : q.minvK;
+      double* cs = q.colst[w];
+      const int ld = S.ld;
+      S.pq = cs; S.rz = cs + ld; S.rznew = cs + 2 * ld; S.rz0 = cs + 3 * ld; S.rzF = cs + 4 * ld;
+      S.alpha = cs + 5 * ld; S.beta = cs + 6 * ld; S.active = (int*)(cs + 7 * ld);
+      R.cnt = e.cnt_free.back();
+      e.cnt_free.pop_back();
+      S.nactive = e.d_cnt + R.cnt;
+      R.phase = 0; R.iters = 0; R.refines = 0; R.nnzII = nnzII;
+      Ln.sys.push_back(&R);
     }
   }
-  cs.dsys = (CgSys*)ar.take(sizeof(CgSys) * nsys);
-  double* colbuf[7];
-  for (int i = 0; i < 7; ++i) colbuf[i] = (double*)ar.take(8 * (size_t)total_cols);
-  int* d_active = (int*)ar.take(4 * (size_t)total_cols);
-  int* d_soc = (int*)ar.take(4 * (size_t)total_cols);
-  int* d_nact = (int*)ar.take(4 * (size_t)nsys);
-  if (!d_nact) return fail(MOR_ENOMEM, "arena exhausted (cg)");
-  HIPCHK(hipMemcpyAsync(cs.dsys, cs.hsys.data(), sizeof(CgSys) * nsys, hipMemcpyHostToDevice, st));
-  HIPCHK(hipMemcpyAsync(d_soc, sys_of_col.data(), 4 * (size_t)total_cols, hipMemcpyHostToDevice, st));
-  cs.cols.pq = colbuf[0]; cs.cols.rz = colbuf[1]; cs.cols.rznew = colbuf[2]; cs.cols.rz0 = colbuf[3];
-  cs.cols.rzF = colbuf[4]; cs.cols.alpha = colbuf[5]; cs.cols.beta = colbuf[6];
-  cs.cols.active = d_active; cs.cols.sys_of_col = d_soc; cs.cols.nactive = d_nact;
-  cs.cols.ncols_total = total_cols;
-  HIPCHK(hipHostMalloc((void**)&cs.h_nactive, 4 * (size_t)nsys));
-  cs.iters.assign(nsys, 0);
-  std::vector<int> refines(nsys, 0);
-  int rc = cg_solve<T>(c, cs, sys_sub, sys_nnz, refines);
-  (void)hipHostFree(cs.h_nactive);
-  dfree(c, cs.d_tiles_buf);
-  if (rc) return rc;
+  if (int rc = engine_upload(c, e, Ln)) return rc;
+  launch_cg_zero(e.d_sys, Ln.cb, Ln.ncb, st);
+  launch_cg_init<T>(e.d_sys, Ln.sp, Ln.nsp, e.sp.rb, e.sp.v, st);
+  launch_cg_pstart<T>(e.d_sys, Ln.bk, Ln.nbk, e.stm.rb, e.stm.v, st);
+  launch_cg_start(e.d_sys, Ln.cb, Ln.ncb, 1, 0.0, st);
+  HIPCHK(hipGetLastError());
+  if (int rc = read_counts(c, e)) return rc;
+  for (SysRun* R : Ln.sys)
+    if (e.h_cnt[R->cnt] == 0) R->phase = 1;   // zero right-hand side
+  for (Live* L : adm) e.live.push_back(L);
+  return 0;
+}
 
+// One CG chunk over every system still iterating, then restarts and completions.
+template <typename T>
+static int engine_chunk(mor_ctx* c, MorEngine& e) {
+  hipStream_t st = c->st;
+  Launch La;
+  for (Live* L : e.live)
+    for (int w = 0; w < 2; ++w)
+      if (L->sys[w].phase == 0 && !L->status) La.sys.push_back(&L->sys[w]);
+  if (La.sys.empty()) return 0;
+  if (int rc = engine_upload(c, e, La)) return rc;
+  const bool fp64 = sizeof(T) == 8;
+  const double inner = fp64 ? c->opts.refine_rtol : c->opts.cg_rtol;
+  const double tol2 = inner * inner;
+  const int chunk = std::max(1, c->opts.cg_chunk);
+  for (int k = 0; k < chunk; ++k) {
+    {
+      ScopedTimer tm(c, "spmm", La.spmm_bytes);
+      launch_cg_spmm<T>(e.d_sys, La.sp, La.nsp, e.sp.rb, e.sp.v, st);
+    }
+    launch_cg_alpha(e.d_sys, La.cb, La.ncb, st);
+    {
+      ScopedTimer tm(c, "cg_update", 0);
+      launch_cg_update<T>(e.d_sys, La.bk, La.nbk, e.stm.rb, e.stm.v, st);
+    }
+    launch_cg_beta(e.d_sys, La.cb, La.ncb, tol2, st);
+    {
+      ScopedTimer tm(c, "cg_direction", 0);
+      launch_cg_direction<T>(e.d_sys, La.bk, La.nbk, e.stm.rb, e.stm.v, st);
+    }
+  }
+  HIPCHK(hipGetLastError());
+  if (int rc = read_counts(c, e)) return rc;
+  Launch Lr;   // systems restarting from an FP64 residual
+  std::vector<SysRun*> fin;
+  for (SysRun* R : La.sys) {
+    R->iters += chunk;
+    if (e.h_cnt[R->cnt] > 0) continue;
+    const bool refine = R->S.X64 != nullptr;
+    if (refine && R->refines < c->opts.refine_steps) Lr.sys.push_back(R);
+    else fin.push_back(R);
+  }
+  // iteration cap
+  for (Live* L : e.live)
+    for (int w = 0; w < 2; ++w)
+      if (L->sys[w].phase == 0 && L->sys[w].iters > c->opts.max_iter && !L->status) {
+        L->status = MOR_ENOTCONV;
+        g_err = "block CG did not converge within max_iter";
+      }
+  if (!Lr.sys.empty()) {
+    if (int rc = engine_upload(c, e, Lr)) return rc;
+    launch_cg_shadow<T>(e.d_sys, Lr.sp, Lr.nsp, e.sp.rb, e.sp.v, st);
+    launch_cg_zero(e.d_sys, Lr.cb, Lr.ncb, st);
+    {
+      ScopedTimer tm(c, "residual64", 0);
+      launch_cg_residual64<T>(e.d_sys, Lr.sp, Lr.nsp, e.sp.rb, e.sp.v, st);
+    }
+    launch_cg_pstart<T>(e.d_sys, Lr.bk, Lr.nbk, e.stm.rb, e.stm.v, st);
+    const double outer2 = c->opts.refine_rtol * c->opts.refine_rtol;
+    launch_cg_start(e.d_sys, Lr.cb, Lr.ncb, 0, outer2, st);
+    HIPCHK(hipGetLastError());
+    if (int rc = read_counts(c, e)) return rc;
+    for (SysRun* R : Lr.sys) {
+      R->refines++;
+      if (e.h_cnt[R->cnt] == 0) R->phase = 1;   // already at the outer target (X holds zeros)
+    }
+  }
+  if (!fin.empty()) {
+    Launch Lf;
+    for (SysRun* R : fin)
+      if (R->S.X64) Lf.sys.push_back(R);
+    if (!Lf.sys.empty()) {
+      if (int rc = engine_upload(c, e, Lf)) return rc;
+      launch_cg_shadow<T>(e.d_sys, Lf.sp, Lf.nsp, e.sp.rb, e.sp.v, st);
+    }
+    for (SysRun* R : fin) R->phase = 1;
+  }
+  return 0;
+}
+
+// Dense stage of the requests whose two solves finished.
+static int dense_stage(mor_ctx* c, std::vector<Live*>& done);
+
+template <typename T>
+static int engine_tick(mor_ctx* c, MorEngine& e) {
+  if (int rc = engine_admit<T>(c, e)) return rc;
+  if (int rc = engine_chunk<T>(c, e)) return rc;
+  std::vector<Live*> ready, keep;
+  bool iterating = false;
+  for (Live* L : e.live) {
+    if (L->status) ready.push_back(L);
+    else if (L->sys[0].phase == 1 && L->sys[1].phase == 1) ready.push_back(L);
+    else {
+      keep.push_back(L);
+      iterating = true;
+    }
+  }
+  if (ready.empty()) return 0;
+  // Batch the dense stage: wait for more finished requests while others still iterate,
+  // unless enough are ready or pending requests wait for the memory they hold.
+  const int want = c->opts.dense_batch > 0 ? c->opts.dense_batch : 16;
+  bool failed = false;
+  for (Live* L : ready) failed |= L->status != 0;
+  if (iterating && !failed && (int)ready.size() < want && e.pending.empty()) return 0;
+  std::vector<Live*> ok;
+  for (Live* L : ready)
+    if (!L->status) ok.push_back(L);
+  int rc = 0;
+  if (!ok.empty()) {
+    rc = dense_stage(c, ok);
+    if (rc)
+      for (Live* L : ok)
+        if (!L->status) L->status = rc;
+  }
+  for (Live* L : ready) {
+    Req r;
+    r.id = L->id;
+    r.sd = L->q.sd;
+    r.rank = L->q.rank;
+    r.prec = L->q.prec;
+    r.tol = L->q.tol;
+    r.done = 1;
+    r.status = L->status;
+    e.finished[r.id] = r;
+    for (int w = 0; w < 2; ++w) e.cnt_free.push_back(L->sys[w].cnt);
+    (void)hipStreamSynchronize(c->st);
+    dfree(c, L->mem);
+    e.live_bytes -= L->bytes;
+    delete L;
+  }
+  e.live = keep;
+  c->projected = 0;
+  c->solved = 0;
+  return 0;
+}
+
+static MorEngine& engine_for(mor_ctx* c, int prec);
+static int tick_all(mor_ctx* c) {
+  for (int k = 0; k < 2; ++k) {
+    MorEngine* e = c->eng[k];
+    if (!e || (e->pending.empty() && e->live.empty())) continue;
+    const int rc = k == 0 ? engine_tick<float>(c, *e) : engine_tick<double>(c, *e);
+    if (rc) return rc;
+  }
+  return 0;
+}
+static bool engines_idle(mor_ctx* c) {
+  for (int k = 0; k < 2; ++k)
+    if (c->eng[k] && (!c->eng[k]->pending.empty() || !c->eng[k]->live.empty())) return false;
+  return true;
+}
+
+// ------------------------------------------------------------------------------- dense stage
+static int dense_stage(mor_ctx* c, std::vector<Live*>& done) {
+  hipStream_t st = c->st;
+  const int ns = (int)done.size();
+  std::vector<Slot*> sl(ns);
+  for (int i = 0; i < ns; ++i) sl[i] = &done[i]->q;
+  // scratch for descriptors and pointer tables of this stage
+  size_t gemm_tiles = 0;
+  for (Slot* q : sl) gemm_tiles += (size_t)(q->T + 2) * (q->T + 2) + 16 * (size_t)(q->T + 2) + 256;
+  const size_t bytes = 2 * 8 * gemm_tiles * sizeof(int4) + 32 * ns * sizeof(GemmDesc) + ns * (sizeof(DenseSub) + 2 * sizeof(TrsmDesc)) +
+                       8 * (size_t)ns * 20 + 8 * (size_t)ns * 64 + 16 * 4096;
+  char* buf = (char*)dalloc(c, bytes);
+  if (!buf) return fail(MOR_ENOMEM, "device allocation failed (dense stage)");
+  struct Guard {
+    mor_ctx* c; void* p;
+    ~Guard() { (void)hipStreamSynchronize(c->st); dfree(c, p); }
+  } guard{c, buf};
+  Arena ar{buf, bytes, 0};
+  int rc = 0;
   {
-    Slot& q = slots[0];
+    Slot& q = *sl[0];
     const HostSub& h = *q.h;
     dump(c, "A64", q.A64, 8 * (size_t)h.rp[h.nL]);
     dump(c, "K64", q.K64, 8 * (size_t)h.rp[h.nL]);
@@ -871,37 +1017,36 @@ static int local_batch_t(mor_ctx* c, std::vector<Slot>& slots) {
     dump(c, "f", q.f, 8 * (size_t)h.nL);
   }
   // ---- FP64 views of the solutions
-  for (auto& q : slots) {
-    const HostSub& h = *q.h;
-    if (fp32 && !refine) {
-      launch_to_f64_block((const float*)q.XA, q.ldA, q.Xc, q.ldXc, h.nV, q.colsA, st);
-      launch_to_f64_block((const float*)q.XK, q.ldK, q.Ec, q.ldEc, h.nI, q.colsK, st);
+  for (Slot* q : sl) {
+    const HostSub& h = *q->h;
+    if (q->fp32 && !q->refine) {
+      launch_to_f64_block((const float*)q->XA, q->ldA, q->Xc, q->ldXc, h.nV, q->colsA, st);
+      launch_to_f64_block((const float*)q->XK, q->ldK, q->Ec, q->ldEc, h.nI, q->colsK, st);
     }
   }
   // ---- G1 = X_C^T K_i X_C (lifted interface functions in the H1(omega_i) inner product)
   GemmBatch gG;
-  for (auto& q : slots) {
-    const HostSub& h = *q.h;
-    launch_fill(q.G, (int64_t)q.MP * q.MP, 0.0, st);
-    launch_spmm64_rows(q.d->rpV, q.d->colV, q.Ki64, h.nV, h.nV, q.Xc, q.ldXc, q.M, q.Y, q.ldK, st);
-    gG.add(gd(q.M, q.M, h.nV, q.Xc, q.ldXc, 1, q.Y, q.ldK, 0, q.G, q.MP, 1.0, 0.0, 1));
+  for (Slot* q : sl) {
+    const HostSub& h = *q->h;
+    launch_fill(q->G, (int64_t)q->MP * q->MP, 0.0, st);
+    launch_spmm64_rows(q->d->rpV, q->d->colV, q->Ki64, h.nV, h.nV, q->Xc, q->ldXc, q->M, q->Y, q->ldK, st);
+    gG.add(gd(q->M, q->M, h.nV, q->Xc, q->ldXc, 1, q->Y, q->ldK, 0, q->G, q->MP, 1.0, 0.0, 1));
   }
   if ((rc = gemm_upload(c, gG, ar))) return rc;
   gemm_run(c, gG, "gram");
   // ---- S_B = K_BB + K_BI E (Lemma 4.1), padded with the identity
-  for (auto& q : slots) {
-    const HostSub& h = *q.h;
+  for (Slot* q : sl) {
+    const HostSub& h = *q->h;
     ScopedTimer tm(c, "schur", 0);
-    launch_schur(q.d->rp, q.d->col, q.K64, h.nI, h.nB, q.Ec, q.ldEc, q.S, q.MP, st);
-    launch_pad_identity(q.S, q.M, q.MP, st);
-    launch_symmetrize(q.S, q.MP, st);
+    launch_schur(q->d->rp, q->d->col, q->K64, h.nI, h.nB, q->Ec, q->ldEc, q->S, q->MP, st);
+    launch_pad_identity(q->S, q->M, q->MP, st);
+    launch_symmetrize(q->S, q->MP, st);
   }
   {
-    Slot& q = slots[0];
+    Slot& q = *sl[0];
     const HostSub& h = *q.h;
     dump(c, "Xc", q.Xc, 8 * (size_t)h.nV * q.ldXc);
     dump(c, "Ec", q.Ec, 8 * (size_t)h.nI * q.ldEc);
-    dump(c, "Y", q.Y, 8 * (size_t)h.nV * q.ldK);
     dump(c, "G", q.G, 8 * (size_t)q.MP * q.MP);
     dump(c, "S", q.S, 8 * (size_t)q.MP * q.MP);
   }
@@ -909,7 +1054,7 @@ static int local_batch_t(mor_ctx* c, std::vector<Slot>& slots) {
   std::vector<DenseSub> hds(ns);
   int tmax = 0;
   for (int i = 0; i < ns; ++i) {
-    Slot& q = slots[i];
+    Slot& q = *sl[i];
     hds[i] = DenseSub{q.M, q.MP, q.T, q.S, q.G, q.W, q.C, q.Dinv, q.info};
     tmax = std::max(tmax, q.T);
     launch_fill_i(q.info, 16, 0, st);
@@ -920,7 +1065,7 @@ static int local_batch_t(mor_ctx* c, std::vector<Slot>& slots) {
   HIPCHK(hipMemcpyAsync(dds, hds.data(), sizeof(DenseSub) * ns, hipMemcpyHostToDevice, st));
   {
     double fl = 0;
-    for (auto& q : slots) fl += (double)q.MP * q.MP * q.MP / 3.0;
+    for (Slot* q : sl) fl += (double)q->MP * q->MP * q->MP / 3.0;
     ScopedTimer tm(c, "potrf", fl);
     for (int p = 0; p < tmax; ++p) {
       launch_potrf_diag(dds, ns, p, st);
@@ -930,46 +1075,45 @@ static int local_batch_t(mor_ctx* c, std::vector<Slot>& slots) {
   }
   {
     std::vector<int> hinfo(ns * 16);
-    for (int i = 0; i < ns; ++i)
-      HIPCHK(hipMemcpyAsync(&hinfo[i * 16], slots[i].info, 64, hipMemcpyDeviceToHost, st));
+    for (int i = 0; i < ns; ++i) HIPCHK(hipMemcpyAsync(&hinfo[i * 16], sl[i]->info, 64, hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
     for (int i = 0; i < ns; ++i)
-      if (hinfo[i * 16] != 0)
-        return fail(MOR_EDEVICE, "subdomain " + std::to_string(slots[i].sd) + ": S_B is not positive definite (pivot " +
-                                     std::to_string(hinfo[i * 16]) + ")");
+      if (hinfo[i * 16] != 0) {
+        done[i]->status = MOR_EDEVICE;
+        g_err = "subdomain " + std::to_string(sl[i]->sd) + ": S_B is not positive definite (pivot " +
+                std::to_string(hinfo[i * 16]) + ")";
+      }
   }
   std::vector<TrsmDesc> htd(2 * ns);
   for (int i = 0; i < ns; ++i) {
-    Slot& q = slots[i];
+    Slot& q = *sl[i];
     htd[i] = TrsmDesc{q.G, q.MP, 0, q.W, q.MP, q.T};
     htd[ns + i] = TrsmDesc{q.W, q.MP, 1, q.C, q.MP, q.T};
   }
   HIPCHK(hipMemcpyAsync(dtd, htd.data(), sizeof(TrsmDesc) * 2 * ns, hipMemcpyHostToDevice, st));
   {
     double fl = 0;
-    for (auto& q : slots) fl += 2.0 * (double)q.MP * q.MP * q.MP;
+    for (Slot* q : sl) fl += 2.0 * (double)q->MP * q->MP * q->MP;
     ScopedTimer tm(c, "trsm", fl);
     launch_trsm_lt(dds, dtd, ns, tmax, st);
     launch_trsm_lt(dds, dtd + ns, ns, tmax, st);
   }
-  for (auto& q : slots) launch_symmetrize(q.C, q.MP, st);
+  for (Slot* q : sl) launch_symmetrize(q->C, q->MP, st);
   {
-    Slot& q = slots[0];
+    Slot& q = *sl[0];
     dump(c, "R", q.S, 8 * (size_t)q.MP * q.MP);
-    dump(c, "W", q.W, 8 * (size_t)q.MP * q.MP);
     dump(c, "C", q.C, 8 * (size_t)q.MP * q.MP);
-    dump(c, "Dinv", q.Dinv, 8 * (size_t)q.T * 4096);
   }
 
   // ---- top eigenpairs of C by subspace iteration with Rayleigh-Ritz
   int smax = 0, maxrows = 0;
   std::vector<int> s_of(ns), rows_of(ns), M_of(ns);
   for (int i = 0; i < ns; ++i) {
-    s_of[i] = slots[i].s;
-    rows_of[i] = slots[i].MP;
-    M_of[i] = slots[i].M;
-    smax = std::max(smax, slots[i].s);
-    maxrows = std::max(maxrows, slots[i].MP);
+    s_of[i] = sl[i]->s;
+    rows_of[i] = sl[i]->MP;
+    M_of[i] = sl[i]->M;
+    smax = std::max(smax, sl[i]->s);
+    maxrows = std::max(maxrows, sl[i]->MP);
   }
   int* d_s = (int*)ar.take(4 * ns);
   int* d_rows = (int*)ar.take(4 * ns);
@@ -981,7 +1125,7 @@ static int local_batch_t(mor_ctx* c, std::vector<Slot>& slots) {
   if (!dptr) return fail(MOR_ENOMEM, "arena exhausted (eig)");
   std::vector<double*> hptr((size_t)ns * NP);
   for (int i = 0; i < ns; ++i) {
-    Slot& q = slots[i];
+    Slot& q = *sl[i];
     double* v[NP] = {q.Vb, q.Yb, q.Ub, q.Zb, q.Vn, q.Tb, q.H, q.Ss, q.G2, q.Rinv, q.theta, q.resid, q.Bk, q.Wk};
     for (int k = 0; k < NP; ++k) hptr[(size_t)k * ns + i] = v[k];
   }
@@ -990,14 +1134,13 @@ static int local_batch_t(mor_ctx* c, std::vector<Slot>& slots) {
   HIPCHK(hipMemcpyAsync(d_rows, rows_of.data(), 4 * ns, hipMemcpyHostToDevice, st));
   HIPCHK(hipMemcpyAsync(d_M, M_of.data(), 4 * ns, hipMemcpyHostToDevice, st));
   launch_fill_i(d_info2, ns, 0, st);
-  double** P_Vb = dptr + 0 * ns; double** P_Yb = dptr + 1 * ns; double** P_Ub = dptr + 2 * ns;
-  double** P_Zb = dptr + 3 * ns; double** P_Vn = dptr + 4 * ns; double** P_Tb = dptr + 5 * ns;
+  double** P_Zb = dptr + 3 * ns; double** P_Vn = dptr + 4 * ns; double** P_Ub = dptr + 2 * ns;
   double** P_H = dptr + 6 * ns; double** P_Ss = dptr + 7 * ns; double** P_G2 = dptr + 8 * ns;
   double** P_Ri = dptr + 9 * ns; double** P_th = dptr + 10 * ns; double** P_res = dptr + 11 * ns;
   double** P_Bk = dptr + 12 * ns; double** P_Wk = dptr + 13 * ns;
-  (void)P_Ub; (void)P_Tb;
   GemmBatch gY, gH, gU, gZ, gO1a, gO1b, gO2a, gO2b;
-  for (auto& q : slots) {
+  for (Slot* qp : sl) {
+    Slot& q = *qp;
     const int s = q.s;
     gY.add(gd(q.MP, s, q.MP, q.C, q.MP, 0, q.Vb, s, 0, q.Yb, s));
     gH.add(gd(s, s, q.MP, q.Vb, s, 1, q.Yb, s, 0, q.H, s));
@@ -1029,29 +1172,18 @@ static int local_batch_t(mor_ctx* c, std::vector<Slot>& slots) {
     launch_jacobi(P_H, P_Ss, P_th, d_s, ns, smax, st);
     gemm_run(c, gU, "eig");
     gemm_run(c, gZ, "eig");
-    for (auto& q : slots) launch_fill(q.resid, q.s, 0.0, st);
+    for (Slot* q : sl) launch_fill(q->resid, q->s, 0.0, st);
     launch_ritz(P_Zb, P_Ub, P_Vn, P_th, P_res, d_rows, d_s, ns, maxrows, smax, st);
     for (int i = 0; i < ns; ++i) {
-      HIPCHK(hipMemcpyAsync(&hth[(size_t)i * 64], slots[i].theta, 8 * slots[i].s, hipMemcpyDeviceToHost, st));
-      HIPCHK(hipMemcpyAsync(&hres[(size_t)i * 64], slots[i].resid, 8 * slots[i].s, hipMemcpyDeviceToHost, st));
+      HIPCHK(hipMemcpyAsync(&hth[(size_t)i * 64], sl[i]->theta, 8 * sl[i]->s, hipMemcpyDeviceToHost, st));
+      HIPCHK(hipMemcpyAsync(&hres[(size_t)i * 64], sl[i]->resid, 8 * sl[i]->s, hipMemcpyDeviceToHost, st));
     }
     HIPCHK(hipStreamSynchronize(st));
-    if (getenv("MOR_DUMP") && (eig_it < 3 || eig_it % 50 == 0)) {
-      fprintf(stderr, "eig it %d theta0 %.6e th[1] %.6e res0 %.3e res_last %.3e\n", eig_it, hth[0], hth[1],
-              std::sqrt(std::max(hres[0], 0.0)), std::sqrt(std::max(hres[slots[0].nconv - 1], 0.0)));
-      if (eig_it == 0) {
-        Slot& q = slots[0];
-        dump(c, "Vb0", q.Vb, 8 * (size_t)q.MP * q.s);
-        dump(c, "Yb0", q.Yb, 8 * (size_t)q.MP * q.s);
-        dump(c, "H0", q.H, 8 * (size_t)q.s * q.s);
-        dump(c, "Ss0", q.Ss, 8 * (size_t)q.s * q.s);
-        dump(c, "th0", q.theta, 8 * (size_t)q.s);
-      }
-    }
     converged = true;
     for (int i = 0; i < ns && converged; ++i) {
+      if (done[i]->status) continue;
       const double t0 = std::max(hth[(size_t)i * 64], 1e-300);
-      for (int j = 0; j < slots[i].nconv; ++j)
+      for (int j = 0; j < sl[i]->nconv; ++j)
         if (!(std::sqrt(std::max(hres[(size_t)i * 64 + j], 0.0)) <= c->opts.eig_rtol * t0)) {
           converged = false;
           break;
@@ -1063,12 +1195,11 @@ static int local_batch_t(mor_ctx* c, std::vector<Slot>& slots) {
   if (!converged) return fail(MOR_ENOTCONV, "subspace iteration did not converge within eig_max_iter");
 
   // ---- truncation, basis Z R^-1 V_k Sigma_k^-1 (= R_i^-1 U_k), stitching, local projection
-  std::vector<double*> hB(ns), hX(ns);
   double* d_sig = (double*)ar.take(8 * (size_t)ns * 64);
   if (!d_sig) return fail(MOR_ENOMEM, "arena exhausted (basis)");
   std::vector<double> sig_all((size_t)ns * 64, 1.0);
   for (int i = 0; i < ns; ++i) {
-    Slot& q = slots[i];
+    Slot& q = *sl[i];
     std::vector<double> sg(q.s);
     for (int j = 0; j < q.s; ++j) sg[j] = std::sqrt(std::max(hth[(size_t)i * 64 + j], 0.0));
     q.k_eff = truncation_rank(sg, q.rank, q.tol, q.s - 1);
@@ -1079,13 +1210,13 @@ static int local_batch_t(mor_ctx* c, std::vector<Slot>& slots) {
   }
   HIPCHK(hipMemcpyAsync(d_sig, sig_all.data(), 8 * (size_t)ns * 64, hipMemcpyHostToDevice, st));
   for (int i = 0; i < ns; ++i) {
-    Slot& q = slots[i];
+    Slot& q = *sl[i];
     launch_scale_cols(q.Ub, q.s, d_sig + (size_t)i * 64, q.k_eff, q.MP, q.Bk, st);
   }
   launch_trsm_un(dds, ns, P_Bk, P_Wk, tmax, st);
   GemmBatch gV, gP;
   for (int i = 0; i < ns; ++i) {
-    Slot& q = slots[i];
+    Slot& q = *sl[i];
     const HostSub& h = *q.h;
     SubResult& R = c->res[q.sd];
     const int k1 = q.k_eff + 1;
@@ -1100,7 +1231,7 @@ static int local_batch_t(mor_ctx* c, std::vector<Slot>& slots) {
   if ((rc = gemm_upload(c, gV, ar))) return rc;
   gemm_run(c, gV, "basis");
   for (int i = 0; i < ns; ++i) {
-    Slot& q = slots[i];
+    Slot& q = *sl[i];
     const HostSub& h = *q.h;
     SubResult& R = c->res[q.sd];
     const int k1 = q.k_eff + 1;
@@ -1113,7 +1244,7 @@ static int local_batch_t(mor_ctx* c, std::vector<Slot>& slots) {
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(st));
   for (int i = 0; i < ns; ++i) {
-    Slot& q = slots[i];
+    Slot& q = *sl[i];
     SubResult& R = c->res[q.sd];
     const int k1 = q.k_eff + 1;
     std::vector<double> pm((size_t)k1 * (k1 + 1));
@@ -1121,28 +1252,68 @@ static int local_batch_t(mor_ctx* c, std::vector<Slot>& slots) {
     R.Aii.assign((size_t)k1 * k1, 0.0);
     R.bi.assign(k1, 0.0);
     for (int a = 0; a < k1; ++a) {
-      for (int b = 0; b < k1; ++b) R.Aii[(size_t)a * k1 + b] = 0.5 * (pm[(size_t)a * (k1 + 1) + b] + pm[(size_t)b * (k1 + 1) + a]);
+      for (int b = 0; b < k1; ++b)
+        R.Aii[(size_t)a * k1 + b] = 0.5 * (pm[(size_t)a * (k1 + 1) + b] + pm[(size_t)b * (k1 + 1) + a]);
       R.bi[a] = pm[(size_t)a * (k1 + 1) + k1];
     }
-    R.cg_a = cs.iters[2 * i];
-    R.cg_k = cs.iters[2 * i + 1];
-    R.refine = std::max(refines[2 * i], refines[2 * i + 1]);
+    R.cg_a = done[i]->sys[0].iters;
+    R.cg_k = done[i]->sys[1].iters;
+    R.refine = std::max(done[i]->sys[0].refines, done[i]->sys[1].refines);
     R.eig = eig_it + 1;
-    R.reduced = 1;
+    R.reduced = done[i]->status == 0;
   }
   return 0;
 }
 
-static int local_batch(mor_ctx* c, std::vector<Slot>& slots) {
-  if (c->opts.precision == MOR_FP64) return local_batch_t<double>(c, slots);
-  return local_batch_t<float>(c, slots);
+static void engine_delete(MorEngine* e) { delete e; }
+
+static MorEngine& engine_for(mor_ctx* c, int prec) {
+  const int k = prec == MOR_FP64 ? 1 : 0;
+  if (!c->eng[k]) {
+    c->eng[k] = new MorEngine();
+    if (engine_init(c, *c->eng[k], k == 0 ? 4 : 8)) {
+      // allocation failure is reported at the next tick (counters missing)
+    }
+  }
+  return *c->eng[k];
+}
+
+static uint64_t enqueue(mor_ctx* c, int sd, int rank, double tol, int prec) {
+  Req r;
+  r.id = g_next_ticket++;
+  r.sd = sd; r.rank = rank; r.tol = tol; r.prec = prec;
+  engine_for(c, prec).pending.push_back(r);
+  return r.id;
+}
+
+static const Req* find_req(mor_ctx* c, uint64_t id, bool* pending) {
+  for (int k = 0; k < 2; ++k) {
+    MorEngine* e = c->eng[k];
+    if (!e) continue;
+    auto it = e->finished.find(id);
+    if (it != e->finished.end()) {
+      *pending = false;
+      return &it->second;
+    }
+    for (const Req& r : e->pending)
+      if (r.id == id) {
+        *pending = true;
+        return &r;
+      }
+    for (Live* L : e->live)
+      if (L->id == id) {
+        *pending = true;
+        return nullptr;
+      }
+  }
+  *pending = false;
+  return nullptr;
 }
 
 extern "C" int mor_local_basis_batch(mor_ctx* c, int32_t n, const int32_t* sds, const int32_t* ranks, const double* tols,
                                      int32_t* k_eff_out) {
   if (!c || n <= 0 || !sds || !ranks) return fail(MOR_EINVAL, "bad arguments");
   if (c->opts.host_only) return fail(MOR_ESTATE, "context was created host_only");
-  std::vector<Slot> slots(n);
   std::vector<char> seen(c->subs.size(), 0);
   for (int i = 0; i < n; ++i) {
     const int sd = sds[i];
@@ -1151,47 +1322,24 @@ extern "C" int mor_local_basis_batch(mor_ctx* c, int32_t n, const int32_t* sds, 
     seen[sd] = 1;
     const double tol = tols ? tols[i] : 0.0;
     if (ranks[i] <= 0 && !(tol > 0.0)) return fail(MOR_EINVAL, "need rank > 0 or tol > 0");
-    Slot& q = slots[i];
-    std::memset(&q, 0, sizeof(q));
-    q.sd = sd;
-    q.rank = ranks[i];
-    q.tol = tol;
-    q.h = &c->subs[sd];
-    q.d = &c->sdev[sd];
   }
-  c->projected = 0;
-  c->solved = 0;
-  // waves under the HBM budget (default: 75% of the free device memory)
-  size_t budget = c->opts.hbm_budget_bytes;
-  if (!budget) {
-    size_t fr = 0, tot = 0;
-    if (hipMemGetInfo(&fr, &tot) != hipSuccess) fr = (size_t)64 << 30;
-    budget = fr / 4 * 3;
-  }
-  const int elt = c->opts.precision == MOR_FP64 ? 8 : 4;
-  std::vector<Slot> wave;
-  size_t used = 0;
-  auto flush = [&]() -> int {
-    if (wave.empty()) return 0;
-    const int rc = local_batch(c, wave);
-    wave.clear();
-    used = 0;
-    return rc;
-  };
+  std::vector<uint64_t> ids(n);
+  for (int i = 0; i < n; ++i) ids[i] = enqueue(c, sds[i], ranks[i], tols ? tols[i] : 0.0, c->opts.precision);
+  while (!engines_idle(c))
+    if (int rc = tick_all(c)) return rc;
+  int first_err = 0;
+  std::string msg = g_err;
   for (int i = 0; i < n; ++i) {
-    Sizer z;
-    Slot tmp = slots[i];
-    slot_sizes(c, tmp, z, elt);
-    const size_t need = z.total + (z.total >> 4);
-    if (need > budget) return fail(MOR_ENOMEM, "subdomain " + std::to_string(slots[i].sd) + " alone exceeds the HBM budget");
-    if (used + need > budget)
-      if (int rc = flush()) return rc;
-    wave.push_back(slots[i]);
-    used += need;
+    bool pend;
+    const Req* r = find_req(c, ids[i], &pend);
+    const int st = r ? r->status : MOR_ESTATE;
+    if (st && !first_err) first_err = st;
+    if (k_eff_out) k_eff_out[i] = c->res[sds[i]].k_eff;
   }
-  if (int rc = flush()) return rc;
-  if (k_eff_out)
-    for (int i = 0; i < n; ++i) k_eff_out[i] = c->res[sds[i]].k_eff;
+  for (int k = 0; k < 2; ++k)
+    if (c->eng[k])
+      for (uint64_t id : ids) c->eng[k]->finished.erase(id);
+  if (first_err) return fail(first_err, msg);
   return MOR_OK;
 }
 
@@ -1203,6 +1351,60 @@ extern "C" int mor_local_basis(mor_ctx* c, int32_t sd, int32_t rank, double tol,
     const auto& s = c->res[sd].sigma;
     for (int j = 0; j < sigma_cap && j < (int)s.size(); ++j) sigma_out[j] = s[j];
   }
+  return MOR_OK;
+}
+
+// ------------------------------------------------------------------------------- serving
+extern "C" int mor_submit(mor_ctx* c, int32_t sd, int32_t rank, double tol, int32_t precision, uint64_t* ticket) {
+  if (!c || !ticket) return fail(MOR_EINVAL, "null argument");
+  if (c->opts.host_only) return fail(MOR_ESTATE, "context was created host_only");
+  if (sd < 0 || sd >= (int)c->subs.size()) return fail(MOR_EINVAL, "subdomain id out of range");
+  if (rank <= 0 && !(tol > 0.0)) return fail(MOR_EINVAL, "need rank > 0 or tol > 0");
+  if (precision < MOR_FP64 || precision > MOR_BF16_SPLIT) return fail(MOR_EINVAL, "unknown precision");
+  *ticket = enqueue(c, sd, rank, tol, precision);
+  return MOR_OK;
+}
+
+extern "C" int mor_step(mor_ctx* c) {
+  if (!c) return fail(MOR_EINVAL, "null context");
+  return tick_all(c);
+}
+
+extern "C" int mor_poll(mor_ctx* c, uint64_t ticket, int32_t* done, int32_t* status) {
+  if (!c || !done || !status) return fail(MOR_EINVAL, "null argument");
+  bool pend = false;
+  const Req* r = find_req(c, ticket, &pend);
+  if (!r && !pend) return fail(MOR_EINVAL, "unknown ticket");
+  *done = (r && !pend) ? 1 : 0;
+  *status = (r && !pend) ? r->status : 0;
+  return MOR_OK;
+}
+
+extern "C" int mor_drain(mor_ctx* c) {
+  if (!c) return fail(MOR_EINVAL, "null context");
+  while (!engines_idle(c))
+    if (int rc = tick_all(c)) return rc;
+  return MOR_OK;
+}
+
+extern "C" int mor_engine_stats(mor_ctx* c, int32_t* live, int32_t* pending, int64_t* live_bytes, int64_t* peak_bytes,
+                                int64_t* budget) {
+  if (!c) return fail(MOR_EINVAL, "null context");
+  int32_t l = 0, p = 0;
+  int64_t lb = 0, pb = 0, bu = 0;
+  for (int k = 0; k < 2; ++k)
+    if (c->eng[k]) {
+      l += (int32_t)c->eng[k]->live.size();
+      p += (int32_t)c->eng[k]->pending.size();
+      lb += (int64_t)c->eng[k]->live_bytes;
+      pb = std::max<int64_t>(pb, (int64_t)c->eng[k]->peak_bytes);
+      bu = std::max<int64_t>(bu, (int64_t)c->eng[k]->budget);
+    }
+  if (live) *live = l;
+  if (pending) *pending = p;
+  if (live_bytes) *live_bytes = lb;
+  if (peak_bytes) *peak_bytes = pb;
+  if (budget) *budget = bu;
   return MOR_OK;
 }
 
@@ -1356,82 +1558,6 @@ extern "C" int mor_solve(mor_ctx* c, double* u_out, int64_t* n_reduced_out) {
   if (n_reduced_out) *n_reduced_out = c->n_red;
   c->solved = 1;
   return MOR_OK;
-}
-
-// ------------------------------------------------------------------------------- serving
-// Requests are queued and served in batches at every poll (continuous batching of requests
-// that arrive while others run is provided by mor_poll draining the queue chunk by chunk).
-namespace {
-struct Req {
-  uint64_t id;
-  int sd, rank, precision;
-  double tol;
-  int done = 0, status = 0;
-};
-}  // namespace
-static std::map<mor_ctx*, std::vector<Req>> g_queue;
-static uint64_t g_ticket = 1;
-
-extern "C" int mor_submit(mor_ctx* c, int32_t sd, int32_t rank, double tol, int32_t precision, uint64_t* ticket) {
-  if (!c || !ticket) return fail(MOR_EINVAL, "null argument");
-  if (sd < 0 || sd >= (int)c->subs.size()) return fail(MOR_EINVAL, "subdomain id out of range");
-  if (rank <= 0 && !(tol > 0.0)) return fail(MOR_EINVAL, "need rank > 0 or tol > 0");
-  if (precision < MOR_FP64 || precision > MOR_BF16_SPLIT) return fail(MOR_EINVAL, "unknown precision");
-  Req r;
-  r.id = g_ticket++;
-  r.sd = sd; r.rank = rank; r.tol = tol; r.precision = precision;
-  g_queue[c].push_back(r);
-  *ticket = r.id;
-  return MOR_OK;
-}
-
-static int serve_pending(mor_ctx* c) {
-  auto& q = g_queue[c];
-  // group pending requests by precision; a subdomain appears once per batch
-  for (int prec = MOR_FP64; prec <= MOR_BF16_SPLIT; ++prec) {
-    std::vector<int> idx;
-    std::vector<char> seen(c->subs.size(), 0);
-    for (size_t i = 0; i < q.size(); ++i)
-      if (!q[i].done && q[i].precision == prec && !seen[q[i].sd]) {
-        idx.push_back((int)i);
-        seen[q[i].sd] = 1;
-      }
-    if (idx.empty()) continue;
-    std::vector<int32_t> sds, ranks;
-    std::vector<double> tols;
-    for (int i : idx) {
-      sds.push_back(q[i].sd);
-      ranks.push_back(q[i].rank);
-      tols.push_back(q[i].tol);
-    }
-    const int saved = c->opts.precision;
-    c->opts.precision = prec;
-    const int rc = mor_local_basis_batch(c, (int)sds.size(), sds.data(), ranks.data(), tols.data(), nullptr);
-    c->opts.precision = saved;
-    for (int i : idx) {
-      q[i].done = 1;
-      q[i].status = rc;
-    }
-  }
-  return 0;
-}
-
-extern "C" int mor_poll(mor_ctx* c, uint64_t ticket, int32_t* done, int32_t* status) {
-  if (!c || !done || !status) return fail(MOR_EINVAL, "null argument");
-  auto& q = g_queue[c];
-  for (auto& r : q)
-    if (r.id == ticket) {
-      if (!r.done) serve_pending(c);
-      *done = r.done;
-      *status = r.status;
-      return MOR_OK;
-    }
-  return fail(MOR_EINVAL, "unknown ticket");
-}
-
-extern "C" int mor_drain(mor_ctx* c) {
-  if (!c) return fail(MOR_EINVAL, "null context");
-  return serve_pending(c);
 }
 
 // ------------------------------------------------------------------------------- getters

@@ -36,29 +36,23 @@ struct CgSys {
   const int* ii_end;   // end of the II part of each I row
   const float* val32;  // FP32 copy of the values
   const double* val64; // FP64 values
-  const void* dinv;    // 1 / diag(A_II), in the CG scalar type
   const double* f;     // load on [I, B] (dense RHS column nB) or nullptr
   int nI, nB, ncols, ld;
   void* X; void* R; void* P; void* Q;  // CG scalar type
   double* X64;         // FP64 solution shadow (refinement), or nullptr
-  int coff;            // offset of this system's columns in the per-column arrays
   const int* bp;       // aggregates of rows (block-Jacobi blocks): [bp[b], bp[b+1]), size <= 8
   int nblk;
   const void* minv;    // inverse of each diagonal block, 8 entries per row, CG scalar type
-};
-
-struct CgCols {        // per-column state, all systems concatenated
+  // per-column state (length ld each)
   double* pq;          // p'Ap accumulator
-  double* rz;          // r'D^-1 r of the current iterate
-  double* rznew;       // accumulator of the updated r'D^-1 r
+  double* rz;          // r'M^-1 r of the current iterate
+  double* rznew;       // accumulator of the updated r'M^-1 r
   double* rz0;         // reference of the current (re)start
   double* rzF;         // reference of the first right-hand side (refinement target)
   double* alpha;
   double* beta;
   int* active;         // 1 while the column iterates
-  const int* sys_of_col;
-  int* nactive;        // per system: active columns after the last iteration
-  int ncols_total;
+  int* nactive;        // active columns of this system after the last iteration
 };
 
 // ---------------------------------------------------------------------------------
@@ -97,32 +91,32 @@ void launch_assemble(const AsmSub* d_subs, const int* d_prefix, int nsub, int to
                      const double* xyz, const int* tets, const double* kappa, const double* fnodal,
                      hipStream_t s);
 void launch_to_f32(const double* in, float* out, int64_t n, hipStream_t s);
-void launch_diag_inv(const int* rp, const int* col, const double* v64, int nI, void* dinv, int is_double,
-                     hipStream_t s);
 
 // v = elements per lane (tile width 64 v columns): 1, 2 or 4 for float, 1 or 2 for double
+// v = elements per lane (tile width 64 v columns): 1, 2 or 4 for float, 1 or 2 for double
 template <typename T>
-void launch_cg_init(const CgSys* sys, const int4* tiles, int ntiles, int rb, int v, CgCols cols, hipStream_t s);
+void launch_cg_init(const CgSys* sys, const int4* tiles, int ntiles, int rb, int v, hipStream_t s);
 template <typename T>
-void launch_cg_spmm(const CgSys* sys, const int4* tiles, int ntiles, int rb, int v, CgCols cols, hipStream_t s);
+void launch_cg_spmm(const CgSys* sys, const int4* tiles, int ntiles, int rb, int v, hipStream_t s);
 template <typename T>
-void launch_cg_update(const CgSys* sys, const int4* tiles, int ntiles, int rb, int v, CgCols cols, hipStream_t s);
-template <typename T>
-void launch_cg_direction(const CgSys* sys, const int4* tiles, int ntiles, int rb, int v, CgCols cols, hipStream_t s);
-template <typename T>
-void launch_cg_residual64(const CgSys* sys, const int4* tiles, int ntiles, int rb, int v, CgCols cols, hipStream_t s);
+void launch_cg_residual64(const CgSys* sys, const int4* tiles, int ntiles, int rb, int v, hipStream_t s);
 template <typename T>
 void launch_cg_shadow(const CgSys* sys, const int4* tiles, int ntiles, int rb, int v, hipStream_t s);
-// block tiles: (system, first block, first column); bpt blocks per tile
+// block tiles: (system, first aggregate, first column); bpt aggregates per tile
 template <typename T>
-void launch_cg_pstart(const CgSys* sys, const int4* tiles, int ntiles, int bpt, int v, CgCols cols, hipStream_t s);
+void launch_cg_update(const CgSys* sys, const int4* tiles, int ntiles, int bpt, int v, hipStream_t s);
+template <typename T>
+void launch_cg_direction(const CgSys* sys, const int4* tiles, int ntiles, int bpt, int v, hipStream_t s);
+template <typename T>
+void launch_cg_pstart(const CgSys* sys, const int4* tiles, int ntiles, int bpt, int v, hipStream_t s);
 template <typename T>
 void launch_block_inv(const int* rp, const int* col, const double* v64, const int* bp, int nblk, void* minv,
                       hipStream_t s);
-void launch_cg_alpha(CgCols cols, hipStream_t s);
-void launch_cg_beta(CgCols cols, double tol2, hipStream_t s);
-void launch_cg_start(CgCols cols, int first, double tol2_first, hipStream_t s);
-void launch_cg_restart(CgCols cols, double tol2_outer, hipStream_t s);
+// column blocks: (system, first column) of 256 columns
+void launch_cg_alpha(const CgSys* sys, const int2* cb, int ncb, hipStream_t s);
+void launch_cg_beta(const CgSys* sys, const int2* cb, int ncb, double tol2, hipStream_t s);
+void launch_cg_zero(const CgSys* sys, const int2* cb, int ncb, hipStream_t s);
+void launch_cg_start(const CgSys* sys, const int2* cb, int ncb, int first, double tol2_outer, hipStream_t s);
 
 void launch_to_f64_block(const float* in, int ldi, double* out, int ldo, int rows, int cols, hipStream_t s);
 void launch_spmm64_rows(const int* rp, const int* col, const double* val, int nrows, int col_limit,

@@ -162,19 +162,6 @@ void launch_assemble(const AsmSub* d_subs, const int* d_prefix, int nsub, int to
                      tets, kappa, fnodal);
 }
 
-__global__ void k_diag_inv(const int* __restrict__ rp, const int* __restrict__ col, const double* __restrict__ v,
-                           int nI, void* dinv, int is_double) {
-  int r = blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= nI) return;
-  int slot = find_slot(rp, col, r, r);
-  double d = 1.0 / v[slot];
-  if (is_double) ((double*)dinv)[r] = d; else ((float*)dinv)[r] = (float)d;
-}
-void launch_diag_inv(const int* rp, const int* col, const double* v64, int nI, void* dinv, int is_double,
-                     hipStream_t s) {
-  if (nI > 0) hipLaunchKernelGGL(k_diag_inv, dim3((nI + 255) / 256), dim3(256), 0, s, rp, col, v64, nI, dinv, is_double);
-}
-
 // --------------------------------------------------------------------------------- block CG
 // A tile = (system, first row, first column).  A wave owns 64 * V consecutive columns (V
 // elements per lane) and rows wave, wave + 4, ... of the tile's row block.  The SpMM tile width
@@ -257,7 +244,7 @@ __device__ __forceinline__ void rhs_row(const CgSys& S, int r, int c0, TT (&v)[V
 
 template <typename T, int V>
 __global__ __launch_bounds__(256) void k_cg_init(const CgSys* __restrict__ sys, const int4* __restrict__ tiles, int ntiles,
-                                                 int rb, CgCols cols) {
+                                                 int rb) {
   MOR_TILE_PROLOGUE(V)
   if (!act) return;
   T* X = (T*)S.X; T* R = (T*)S.R;
@@ -319,7 +306,7 @@ __device__ __forceinline__ T ld_nt(const T* p) {
 
 template <typename T, int V>
 __global__ __launch_bounds__(256) void k_cg_spmm(const CgSys* __restrict__ sys, const int4* __restrict__ tiles, int ntiles,
-                                                 int rb, CgCols cols) {
+                                                 int rb) {
   __shared__ double red[4][64 * 4];
   __shared__ int s_beg[kSpmmMaxRows + 1], s_off[kSpmmMaxRows + 1];
   __shared__ int s_col[kSpmmNnzCap];
@@ -376,7 +363,7 @@ __global__ __launch_bounds__(256) void k_cg_spmm(const CgSys* __restrict__ sys, 
       for (int q = 0; q < V; ++q) part[q] += (double)pr[q] * (double)acc[q];
     }
   }
-  column_reduce_add<V>(red, part, tl.z, ld, cols.pq + S.coff);
+  column_reduce_add<V>(red, part, tl.z, ld, S.pq);
 }
 
 // Block-Jacobi preconditioner: z = M^-1 r with M the diagonal blocks of A_II over the row
@@ -411,7 +398,7 @@ __device__ __forceinline__ void block_apply(const T* __restrict__ minv, int r0, 
 // P = M^-1 R and r'M^-1 r (start and restarts of the CG)
 template <typename T, int V>
 __global__ __launch_bounds__(256) void k_cg_pstart(const CgSys* __restrict__ sys, const int4* __restrict__ tiles,
-                                                   int ntiles, int bpt, CgCols cols) {
+                                                   int ntiles, int bpt) {
   __shared__ double red[4][64 * 4];
   MOR_BLOCK_PROLOGUE(V)
   const T* minv = (const T*)S.minv;
@@ -443,13 +430,13 @@ __global__ __launch_bounds__(256) void k_cg_pstart(const CgSys* __restrict__ sys
       }
     }
   }
-  column_reduce_add<V>(red, part, tl.z, ld, cols.rz + S.coff);
+  column_reduce_add<V>(red, part, tl.z, ld, S.rz);
 }
 
 // R -= alpha Q and the new r'M^-1 r
 template <typename T, int V>
 __global__ __launch_bounds__(256) void k_cg_update(const CgSys* __restrict__ sys, const int4* __restrict__ tiles,
-                                                   int ntiles, int bpt, CgCols cols) {
+                                                   int ntiles, int bpt) {
   __shared__ double red[4][64 * 4];
   MOR_BLOCK_PROLOGUE(V)
   const T* minv = (const T*)S.minv;
@@ -459,7 +446,7 @@ __global__ __launch_bounds__(256) void k_cg_update(const CgSys* __restrict__ sys
 #pragma unroll
   for (int q = 0; q < V; ++q) {
     part[q] = 0.0;
-    al[q] = act ? (T)cols.alpha[S.coff + c0 + q] : (T)0;
+    al[q] = act ? (T)S.alpha[c0 + q] : (T)0;
   }
   if (act) {
     for (int b = tl.y + w; b < bend; b += 4) {
@@ -491,13 +478,13 @@ __global__ __launch_bounds__(256) void k_cg_update(const CgSys* __restrict__ sys
       }
     }
   }
-  column_reduce_add<V>(red, part, tl.z, ld, cols.rznew + S.coff);
+  column_reduce_add<V>(red, part, tl.z, ld, S.rznew);
 }
 
 // X += alpha P (the step of this iteration), then P = M^-1 R + beta P
 template <typename T, int V>
 __global__ __launch_bounds__(256) void k_cg_direction(const CgSys* __restrict__ sys, const int4* __restrict__ tiles,
-                                                      int ntiles, int bpt, CgCols cols) {
+                                                      int ntiles, int bpt) {
   MOR_BLOCK_PROLOGUE(V)
   if (!act) return;
   const T* minv = (const T*)S.minv;
@@ -505,8 +492,8 @@ __global__ __launch_bounds__(256) void k_cg_direction(const CgSys* __restrict__ 
   T be[V], al[V];
 #pragma unroll
   for (int q = 0; q < V; ++q) {
-    be[q] = (T)cols.beta[S.coff + c0 + q];
-    al[q] = (T)cols.alpha[S.coff + c0 + q];
+    be[q] = (T)S.beta[c0 + q];
+    al[q] = (T)S.alpha[c0 + q];
   }
   for (int b = tl.y + w; b < bend; b += 4) {
     const int r0 = gld(S.bp + b), nb = gld(S.bp + b + 1) - r0;
@@ -559,7 +546,7 @@ __global__ __launch_bounds__(256) void k_cg_shadow(const CgSys* __restrict__ sys
 // FP64 residual of the FP64 solution: R = F - A_II X64 (rounded to T), X = 0.
 template <typename T, int V>
 __global__ __launch_bounds__(256) void k_cg_residual64(const CgSys* __restrict__ sys, const int4* __restrict__ tiles,
-                                                       int ntiles, int rb, CgCols cols) {
+                                                       int ntiles, int rb) {
   MOR_TILE_PROLOGUE(V)
   if (!act) return;
   T* X = (T*)S.X; T* R = (T*)S.R;
@@ -658,148 +645,136 @@ template void launch_block_inv<double>(const int*, const int*, const double*, co
   } while (0)
 
 template <typename T>
-void launch_cg_init(const CgSys* sys, const int4* tiles, int ntiles, int rb, int v, CgCols cols, hipStream_t s) {
-  if (ntiles > 0) MOR_VSWITCH(T, v, k_cg_init, sys, tiles, ntiles, rb, cols);
+void launch_cg_init(const CgSys* sys, const int4* tiles, int ntiles, int rb, int v, hipStream_t s) {
+  if (ntiles > 0) MOR_VSWITCH(T, v, k_cg_init, sys, tiles, ntiles, rb);
 }
 template <typename T>
-void launch_cg_spmm(const CgSys* sys, const int4* tiles, int ntiles, int rb, int v, CgCols cols, hipStream_t s) {
-  if (ntiles > 0) MOR_VSWITCH(T, v, k_cg_spmm, sys, tiles, ntiles, rb, cols);
+void launch_cg_spmm(const CgSys* sys, const int4* tiles, int ntiles, int rb, int v, hipStream_t s) {
+  if (ntiles > 0) MOR_VSWITCH(T, v, k_cg_spmm, sys, tiles, ntiles, rb);
 }
 template <typename T>
-void launch_cg_update(const CgSys* sys, const int4* tiles, int ntiles, int rb, int v, CgCols cols, hipStream_t s) {
-  if (ntiles > 0) MOR_VSWITCH(T, v, k_cg_update, sys, tiles, ntiles, rb, cols);
+void launch_cg_update(const CgSys* sys, const int4* tiles, int ntiles, int rb, int v, hipStream_t s) {
+  if (ntiles > 0) MOR_VSWITCH(T, v, k_cg_update, sys, tiles, ntiles, rb);
 }
 template <typename T>
-void launch_cg_direction(const CgSys* sys, const int4* tiles, int ntiles, int rb, int v, CgCols cols, hipStream_t s) {
-  if (ntiles > 0) MOR_VSWITCH(T, v, k_cg_direction, sys, tiles, ntiles, rb, cols);
+void launch_cg_direction(const CgSys* sys, const int4* tiles, int ntiles, int rb, int v, hipStream_t s) {
+  if (ntiles > 0) MOR_VSWITCH(T, v, k_cg_direction, sys, tiles, ntiles, rb);
 }
 template <typename T>
-void launch_cg_residual64(const CgSys* sys, const int4* tiles, int ntiles, int rb, int v, CgCols cols, hipStream_t s) {
-  if (ntiles > 0) MOR_VSWITCH(T, v, k_cg_residual64, sys, tiles, ntiles, rb, cols);
+void launch_cg_residual64(const CgSys* sys, const int4* tiles, int ntiles, int rb, int v, hipStream_t s) {
+  if (ntiles > 0) MOR_VSWITCH(T, v, k_cg_residual64, sys, tiles, ntiles, rb);
 }
 template <typename T>
 void launch_cg_shadow(const CgSys* sys, const int4* tiles, int ntiles, int rb, int v, hipStream_t s) {
   if (ntiles > 0) MOR_VSWITCH(T, v, k_cg_shadow, sys, tiles, ntiles, rb);
 }
 template <typename T>
-void launch_cg_pstart(const CgSys* sys, const int4* tiles, int ntiles, int bpt, int v, CgCols cols, hipStream_t s) {
-  if (ntiles > 0) MOR_VSWITCH(T, v, k_cg_pstart, sys, tiles, ntiles, bpt, cols);
+void launch_cg_pstart(const CgSys* sys, const int4* tiles, int ntiles, int bpt, int v, hipStream_t s) {
+  if (ntiles > 0) MOR_VSWITCH(T, v, k_cg_pstart, sys, tiles, ntiles, bpt);
 }
 #define MOR_INST(T)                                                                                      \
-  template void launch_cg_init<T>(const CgSys*, const int4*, int, int, int, CgCols, hipStream_t);       \
-  template void launch_cg_spmm<T>(const CgSys*, const int4*, int, int, int, CgCols, hipStream_t);       \
-  template void launch_cg_update<T>(const CgSys*, const int4*, int, int, int, CgCols, hipStream_t);     \
-  template void launch_cg_direction<T>(const CgSys*, const int4*, int, int, int, CgCols, hipStream_t);  \
-  template void launch_cg_residual64<T>(const CgSys*, const int4*, int, int, int, CgCols, hipStream_t); \
+  template void launch_cg_init<T>(const CgSys*, const int4*, int, int, int, hipStream_t);       \
+  template void launch_cg_spmm<T>(const CgSys*, const int4*, int, int, int, hipStream_t);       \
+  template void launch_cg_update<T>(const CgSys*, const int4*, int, int, int, hipStream_t);     \
+  template void launch_cg_direction<T>(const CgSys*, const int4*, int, int, int, hipStream_t);  \
+  template void launch_cg_residual64<T>(const CgSys*, const int4*, int, int, int, hipStream_t); \
   template void launch_cg_shadow<T>(const CgSys*, const int4*, int, int, int, hipStream_t);        \
-  template void launch_cg_pstart<T>(const CgSys*, const int4*, int, int, int, CgCols, hipStream_t);
+  template void launch_cg_pstart<T>(const CgSys*, const int4*, int, int, int, hipStream_t);
 MOR_INST(float)
 MOR_INST(double)
 #undef MOR_INST
 
 // per-column scalars ------------------------------------------------------------------
-__device__ __forceinline__ bool first_col_of_sys(const CgCols& c, int j) {
-  return j == 0 || c.sys_of_col[j - 1] != c.sys_of_col[j];
+// Launched over column blocks (system, first column) of 256 columns; every wave's columns
+// belong to one system, so the active count takes one atomic per wave.
+__device__ __forceinline__ void count_active_wave(int* cnt, bool active) {
+  const unsigned long long m = __ballot(active);
+  if ((threadIdx.x & 63) == 0 && m != 0ull) atomicAdd(cnt, (int)__popcll(m));
 }
 
-__global__ void k_cg_alpha(CgCols c) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= c.ncols_total) return;
-  if (first_col_of_sys(c, j)) c.nactive[c.sys_of_col[j]] = 0;
-  const double pq = c.pq[j];
+__global__ void k_cg_alpha(const CgSys* __restrict__ sys, const int2* __restrict__ cb) {
+  const int2 b = cb[blockIdx.x];
+  const CgSys& S = sys[b.x];
+  const int j = b.y + threadIdx.x;
+  if (b.y == 0 && threadIdx.x == 0) *S.nactive = 0;
+  if (j >= S.ld) return;
+  const double pq = S.pq[j];
   double a = 0.0;
-  if (c.active[j]) {
-    if (pq > 0.0) a = c.rz[j] / pq;
-    else c.active[j] = 0;   // breakdown: p'Ap <= 0 cannot happen for SPD data
+  if (S.active[j]) {
+    if (pq > 0.0) a = S.rz[j] / pq;
+    else S.active[j] = 0;   // breakdown: p'Ap <= 0 cannot happen for SPD data
   }
-  c.alpha[j] = a;
-  c.pq[j] = 0.0;
+  S.alpha[j] = a;
+  S.pq[j] = 0.0;
 }
 
-// Count active columns per system with one atomic per wave when the wave's columns belong to
-// one system (the common case), instead of one atomic per column on a shared counter.
-__device__ __forceinline__ void count_active_wave(const CgCols& c, int j, bool active) {
-  const int sys = j < c.ncols_total ? c.sys_of_col[j] : -1;
-  const int s0 = __shfl(sys, 0);
-  const bool uniform = __all(sys == s0);
-  if (uniform) {
-    const unsigned long long m = __ballot(active);
-    if ((threadIdx.x & 63) == 0 && m != 0ull) atomicAdd(&c.nactive[s0], (int)__popcll(m));
-  } else if (active) {
-    atomicAdd(&c.nactive[sys], 1);
-  }
-}
-__device__ __forceinline__ void count_active(const CgCols&, int) {}
-
-__global__ void k_cg_beta(CgCols c, double tol2) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ void k_cg_beta(const CgSys* __restrict__ sys, const int2* __restrict__ cb, double tol2) {
+  const int2 b = cb[blockIdx.x];
+  const CgSys& S = sys[b.x];
+  const int j = b.y + threadIdx.x;
   bool still = false;
-  if (j < c.ncols_total) {
-    const double rn = c.rznew[j];
-    c.rznew[j] = 0.0;
-    if (!c.active[j]) {
-      c.beta[j] = 0.0;
-    } else if (rn <= tol2 * c.rz0[j]) {
-      c.active[j] = 0;
-      c.beta[j] = 0.0;
-      c.rz[j] = rn;
+  if (j < S.ld) {
+    const double rn = S.rznew[j];
+    S.rznew[j] = 0.0;
+    if (!S.active[j]) {
+      S.beta[j] = 0.0;
+    } else if (rn <= tol2 * S.rz0[j]) {
+      S.active[j] = 0;
+      S.beta[j] = 0.0;
+      S.rz[j] = rn;
     } else {
-      c.beta[j] = rn / c.rz[j];
-      c.rz[j] = rn;
+      S.beta[j] = rn / S.rz[j];
+      S.rz[j] = rn;
       still = true;
     }
   }
-  count_active_wave(c, j, still);
-}
-// After the initial right-hand side: references, flags, zero accumulators.
-__global__ void k_cg_start(CgCols c) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= c.ncols_total) return;
-  const double rz = c.rz[j];
-  c.rz0[j] = rz;
-  c.rzF[j] = rz;
-  c.alpha[j] = 0.0;
-  c.beta[j] = 0.0;
-  c.pq[j] = 0.0;
-  c.rznew[j] = 0.0;
-  c.active[j] = rz > 0.0 ? 1 : 0;
-}
-// After an FP64 residual: restart from it; columns already below the outer target stop.
-__global__ void k_cg_restart(CgCols c, double tol2_outer) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= c.ncols_total) return;
-  const double rz = c.rz[j];
-  c.rz0[j] = rz;
-  c.alpha[j] = 0.0;
-  c.beta[j] = 0.0;
-  c.pq[j] = 0.0;
-  c.rznew[j] = 0.0;
-  c.active[j] = (rz > tol2_outer * c.rzF[j]) ? 1 : 0;
-}
-__global__ void k_cg_count(CgCols c) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  count_active_wave(c, j, j < c.ncols_total && c.active[j] != 0);
-}
-__global__ void k_cg_zero_count(CgCols c) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= c.ncols_total) return;
-  if (first_col_of_sys(c, j)) c.nactive[c.sys_of_col[j]] = 0;
+  count_active_wave(S.nactive, still);
 }
 
-void launch_cg_alpha(CgCols c, hipStream_t s) {
-  hipLaunchKernelGGL(k_cg_alpha, dim3((c.ncols_total + 255) / 256), dim3(256), 0, s, c);
+// first = 1: references of a new right-hand side; first = 0: restart from an FP64 residual
+// (columns already below the outer target stay frozen).
+__global__ void k_cg_start(const CgSys* __restrict__ sys, const int2* __restrict__ cb, int first, double tol2_outer) {
+  const int2 b = cb[blockIdx.x];
+  const CgSys& S = sys[b.x];
+  const int j = b.y + threadIdx.x;
+  if (j >= S.ld) return;
+  const double rz = S.rz[j];
+  S.rz0[j] = rz;
+  if (first) S.rzF[j] = rz;
+  S.alpha[j] = 0.0;
+  S.beta[j] = 0.0;
+  S.pq[j] = 0.0;
+  S.rznew[j] = 0.0;
+  S.active[j] = first ? (rz > 0.0 ? 1 : 0) : ((rz > tol2_outer * S.rzF[j]) ? 1 : 0);
 }
-void launch_cg_beta(CgCols c, double tol2, hipStream_t s) {
-  hipLaunchKernelGGL(k_cg_beta, dim3((c.ncols_total + 255) / 256), dim3(256), 0, s, c, tol2);
+__global__ void k_cg_count(const CgSys* __restrict__ sys, const int2* __restrict__ cb) {
+  const int2 b = cb[blockIdx.x];
+  const CgSys& S = sys[b.x];
+  const int j = b.y + threadIdx.x;
+  count_active_wave(S.nactive, j < S.ld && S.active[j] != 0);
 }
-void launch_cg_start(CgCols c, int first, double tol2_outer, hipStream_t s) {
-  const dim3 g((c.ncols_total + 255) / 256);
-  hipLaunchKernelGGL(k_cg_zero_count, g, dim3(256), 0, s, c);
-  if (first) hipLaunchKernelGGL(k_cg_start, g, dim3(256), 0, s, c);
-  else hipLaunchKernelGGL(k_cg_restart, g, dim3(256), 0, s, c, tol2_outer);
-  hipLaunchKernelGGL(k_cg_count, g, dim3(256), 0, s, c);
+__global__ void k_cg_zero(const CgSys* __restrict__ sys, const int2* __restrict__ cb) {
+  const int2 b = cb[blockIdx.x];
+  const CgSys& S = sys[b.x];
+  const int j = b.y + threadIdx.x;
+  if (b.y == 0 && threadIdx.x == 0) *S.nactive = 0;
+  if (j < S.ld) S.rz[j] = 0.0;
 }
-void launch_cg_restart(CgCols c, double tol2_outer, hipStream_t s) { launch_cg_start(c, 0, tol2_outer, s); }
+
+void launch_cg_alpha(const CgSys* sys, const int2* cb, int ncb, hipStream_t s) {
+  if (ncb > 0) hipLaunchKernelGGL(k_cg_alpha, dim3(ncb), dim3(256), 0, s, sys, cb);
+}
+void launch_cg_beta(const CgSys* sys, const int2* cb, int ncb, double tol2, hipStream_t s) {
+  if (ncb > 0) hipLaunchKernelGGL(k_cg_beta, dim3(ncb), dim3(256), 0, s, sys, cb, tol2);
+}
+void launch_cg_zero(const CgSys* sys, const int2* cb, int ncb, hipStream_t s) {
+  if (ncb > 0) hipLaunchKernelGGL(k_cg_zero, dim3(ncb), dim3(256), 0, s, sys, cb);
+}
+void launch_cg_start(const CgSys* sys, const int2* cb, int ncb, int first, double tol2_outer, hipStream_t s) {
+  if (ncb <= 0) return;
+  hipLaunchKernelGGL(k_cg_start, dim3(ncb), dim3(256), 0, s, sys, cb, first, tol2_outer);
+  hipLaunchKernelGGL(k_cg_count, dim3(ncb), dim3(256), 0, s, sys, cb);
+}
 
 // --------------------------------------------------------------------------------- FP64 helpers
 __global__ void k_to_f64_block(const float* in, int ldi, double* out, int ldo, int rows, int cols) {

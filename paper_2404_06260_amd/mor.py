@@ -20,7 +20,7 @@ MOR_FP64, MOR_FP32_REFINE, MOR_FP32, MOR_BF16_SPLIT = 0, 1, 2, 3
 PRECISIONS = {"fp64": MOR_FP64, "fp32_refine": MOR_FP32_REFINE, "fp32": MOR_FP32, "bf16_split": MOR_BF16_SPLIT}
 
 EXPORTED = ("mor_default_opts", "mor_create", "mor_local_basis", "mor_local_basis_batch", "mor_project",
-            "mor_solve", "mor_submit", "mor_poll", "mor_drain", "mor_get_sizes", "mor_get_nodes",
+            "mor_solve", "mor_submit", "mor_poll", "mor_drain", "mor_step", "mor_engine_stats", "mor_get_sizes", "mor_get_nodes",
             "mor_get_pairs", "mor_get_basis", "mor_get_sigma", "mor_get_local_block", "mor_get_reduced",
             "mor_get_reduced_solution", "mor_get_stats", "mor_timing_enable", "mor_timing_get",
             "mor_timing_reset", "mor_destroy", "mor_last_error")
@@ -55,7 +55,8 @@ class MorOpts(ctypes.Structure):
                 ("max_iter", ctypes.c_int32), ("refine_steps", ctypes.c_int32), ("oversample", ctypes.c_int32),
                 ("eig_rtol", ctypes.c_double), ("eig_max_iter", ctypes.c_int32), ("cg_chunk", ctypes.c_int32),
                 ("spmm_rows", ctypes.c_int32), ("spmm_vec", ctypes.c_int32), ("stream_vec", ctypes.c_int32),
-                ("stream_blocks", ctypes.c_int32), ("use_graph", ctypes.c_int32), ("hbm_budget_bytes", ctypes.c_size_t),
+                ("stream_blocks", ctypes.c_int32), ("use_graph", ctypes.c_int32), ("dense_batch", ctypes.c_int32),
+                ("hbm_budget_bytes", ctypes.c_size_t),
                 ("dev_alloc", ALLOC_FN), ("dev_free", FREE_FN), ("alloc_user", ctypes.c_void_p),
                 ("hip_stream", ctypes.c_void_p), ("host_only", ctypes.c_int32)]
 
@@ -81,6 +82,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "mor_submit": (I32, [P, I32, I32, D, I32, P]),
         "mor_poll": (I32, [P, ctypes.c_uint64, P, P]),
         "mor_drain": (I32, [P]),
+        "mor_step": (I32, [P]),
+        "mor_engine_stats": (I32, [P, P, P, P, P, P]),
         "mor_get_sizes": (I32, [P, I32, P, P, P, P]),
         "mor_get_nodes": (I32, [P, I32, P, I64]),
         "mor_get_pairs": (I32, [P, P, I64, P]),
@@ -215,6 +218,18 @@ def mor_poll(ctx, ticket):
 
 def mor_drain(ctx):
     _check(lib().mor_drain(ctx))
+
+
+def mor_step(ctx):
+    _check(lib().mor_step(ctx))
+
+
+def mor_engine_stats(ctx):
+    l, p = ctypes.c_int32(), ctypes.c_int32()
+    lb, pb, bu = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+    _check(lib().mor_engine_stats(ctx, ctypes.byref(l), ctypes.byref(p), ctypes.byref(lb), ctypes.byref(pb),
+                                  ctypes.byref(bu)))
+    return dict(live=l.value, pending=p.value, live_bytes=lb.value, peak_bytes=pb.value, budget=bu.value)
 
 
 def mor_get_sizes(ctx, sd):
