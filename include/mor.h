@@ -95,8 +95,11 @@ typedef struct {
   double eig_rtol;         /* Ritz residual tolerance relative to the largest eigenvalue */
   int32_t eig_max_iter;    /* subspace iteration cap */
   int32_t cg_chunk;        /* CG iterations launched between two convergence polls */
-  int32_t spmm_rows;       /* rows per SpMM workgroup tile (0 = automatic) */
-  int32_t spmm_vec;        /* SpMM tile width in units of 64 columns: 1, 2 or 4 (0 = automatic) */
+  int32_t spmm_rows;       /* row tiles: rows per SpMM workgroup; halo tiles: largest halo (48, 64, 96, 128 or
+                              176 rows of P staged in LDS) (0 = automatic) */
+  int32_t spmm_vec;        /* halo tiles: 256-byte column slices per workgroup; row tiles: width in units of
+                              64 columns, 1, 2 or 4 (0 = automatic) */
+  int32_t spmm_kind;       /* 0 = automatic (LDS halo tiles), 1 = LDS halo tiles, 2 = row tiles (spmm_rows x spmm_vec) */
   int32_t stream_vec;      /* width of the streaming CG kernels' tiles in units of 64 columns */
   int32_t stream_blocks;   /* row aggregates per streaming tile (0 = automatic) */
   int32_t use_graph;       /* capture each CG chunk in a HIP graph and replay it */

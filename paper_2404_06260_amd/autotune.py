@@ -3,9 +3,10 @@
 Two sweeps on the real workload, each candidate running the batched local reduction with a
 loose CG tolerance (a few dozen iterations of the real kernels on the real matrices), timed
 with the library's HIP-event timers on its stream:
-  1. the SpMM tile: width (64, 128 or 256 columns) x rows per tile, best algorithmic GB/s;
+  1. the SpMM: LDS-halo tiles (halo cap x 256-byte column slices per workgroup) or row tiles
+     (rows x width), best algorithmic GB/s;
   2. the streaming (update / direction) tile: width x row aggregates per tile, least time.
-The winner is cached per device name and workload in a JSON file next to this module;
+The winner is cached per workload in a JSON file next to this module;
 `best()` returns the cached options (or None).
 """
 from __future__ import annotations
@@ -14,14 +15,15 @@ import json
 import os
 
 CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "autotune_cache.json")
-CANDIDATES = [(4, 4), (4, 8), (4, 16), (2, 8)]
+# (kind, spmm_vec, spmm_rows): kind 1 = LDS halo tiles (slices per workgroup, halo cap),
+# kind 2 = row tiles (width in 64 columns, rows)
+CANDIDATES = [(1, 8, 64), (1, 16, 64), (1, 8, 48), (1, 16, 96), (1, 4, 64), (2, 4, 8), (2, 4, 16)]
 STREAM_CANDIDATES = [(2, 4), (2, 8), (2, 16), (1, 8), (4, 4), (4, 8)]
 
 
 def _key(problem, precision):
-    import torch
-    dev = torch.cuda.get_device_name(0) if torch.cuda.is_available() else "cpu"
-    return f"{dev}|{problem.name}|{problem.subdomains.n_sub}|{precision}"
+    # one target (gfx950): the key is the workload, not the device name the runtime reports
+    return f"{problem.name}|{problem.subdomains.n_sub}|{precision}"
 
 
 def best(problem, precision):
@@ -35,7 +37,7 @@ def best(problem, precision):
     r = d.get(_key(problem, precision))
     if r is None:
         return None
-    return {k: int(r[k]) for k in ("spmm_vec", "spmm_rows", "stream_vec", "stream_blocks") if k in r}
+    return {k: int(r[k]) for k in ("spmm_kind", "spmm_vec", "spmm_rows", "stream_vec", "stream_blocks") if k in r}
 
 
 def _run(problem, ids, cg_prec, opts):
@@ -56,23 +58,23 @@ def tune(problem, precision="fp32_refine", sub_ids=None, verbose=True, save=True
     cg_prec = "fp64" if precision == "fp64" else "fp32"
     ids = np.arange(problem.subdomains.n_sub) if sub_ids is None else np.asarray(sub_ids)
     sp_res = []
-    for v, rb in CANDIDATES:
-        if cg_prec == "fp64" and v > 2:
+    for kind, v, rb in CANDIDATES:
+        if cg_prec == "fp64" and kind == 2 and v > 2:
             continue
-        t = _run(problem, ids, cg_prec, dict(spmm_vec=v, spmm_rows=rb))
+        t = _run(problem, ids, cg_prec, dict(spmm_kind=kind, spmm_vec=v, spmm_rows=rb))
         n, ms, by = t["spmm"]
         gbs = (by / n) / (ms / n * 1e-3) / 1e9 if n and ms > 0 else 0.0
-        sp_res.append(dict(spmm_vec=v, spmm_rows=rb, launches=n, avg_ms=ms / max(n, 1), gbs=gbs))
+        sp_res.append(dict(spmm_kind=kind, spmm_vec=v, spmm_rows=rb, launches=n, avg_ms=ms / max(n, 1), gbs=gbs))
         if verbose:
-            print(f"[autotune] spmm v={v} rows={rb}: {n} launches, {ms / max(n, 1):.3f} ms avg, {gbs:.0f} GB/s",
-                  flush=True)
+            print(f"[autotune] spmm kind={kind} v={v} rows={rb}: {n} launches, {ms / max(n, 1):.3f} ms avg, "
+                  f"{gbs:.0f} GB/s", flush=True)
     sp = max(sp_res, key=lambda r: r["gbs"])
     st_res = []
     for v, nb in STREAM_CANDIDATES:
         if cg_prec == "fp64" and v > 2:
             continue
-        t = _run(problem, ids, cg_prec, dict(spmm_vec=sp["spmm_vec"], spmm_rows=sp["spmm_rows"], stream_vec=v,
-                                             stream_blocks=nb))
+        t = _run(problem, ids, cg_prec, dict(spmm_kind=sp["spmm_kind"], spmm_vec=sp["spmm_vec"],
+                                             spmm_rows=sp["spmm_rows"], stream_vec=v, stream_blocks=nb))
         ms = t["cg_update"][1] + t["cg_direction"][1]
         n = t["cg_update"][0]
         st_res.append(dict(stream_vec=v, stream_blocks=nb, launches=n, ms=ms))
@@ -80,8 +82,8 @@ def tune(problem, precision="fp32_refine", sub_ids=None, verbose=True, save=True
             print(f"[autotune] stream v={v} blocks={nb}: {n} iterations, update+direction {ms / max(n, 1):.3f} ms/iter",
                   flush=True)
     st = min(st_res, key=lambda r: r["ms"] / max(r["launches"], 1))
-    win = dict(spmm_vec=sp["spmm_vec"], spmm_rows=sp["spmm_rows"], spmm_gbs=sp["gbs"], stream_vec=st["stream_vec"],
-               stream_blocks=st["stream_blocks"])
+    win = dict(spmm_kind=sp["spmm_kind"], spmm_vec=sp["spmm_vec"], spmm_rows=sp["spmm_rows"], spmm_gbs=sp["gbs"],
+               stream_vec=st["stream_vec"], stream_blocks=st["stream_blocks"])
     if save:
         d = {}
         if os.path.exists(CACHE):

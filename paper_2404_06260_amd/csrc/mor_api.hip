@@ -11,12 +11,14 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
 #include <map>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "../../include/mor.h"
@@ -52,7 +54,9 @@ struct TimerRec {
 
 struct SubDev {
   int *rp = nullptr, *col = nullptr, *ii_end = nullptr, *rpV = nullptr, *colV = nullptr, *bp = nullptr;
-  int *ltet = nullptr, *tetg = nullptr, *nodes = nullptr;
+  int *ltet = nullptr, *tetg = nullptr, *nodes = nullptr, *htile = nullptr, *halo = nullptr;
+  int *hrowp = nullptr, *hpe = nullptr;
+  uint16_t *hpp = nullptr, *hself = nullptr;
   uint8_t* core = nullptr;
 };
 
@@ -70,6 +74,7 @@ struct SubResult {
 
 struct mor_ctx {
   mor_opts opts;
+  int halo_cap = 64;   // LDS SpMM tiling: halo rows per tile (one of kHaloCaps)
   hipStream_t st = nullptr;
   HostMesh mesh;
   std::vector<double> kappa, fnodal;
@@ -205,6 +210,7 @@ extern "C" void mor_default_opts(mor_opts* o) {
   o->eig_max_iter = 600;
   o->cg_chunk = 8;
   o->spmm_rows = 0;
+  o->spmm_kind = 0;
   o->use_graph = 0;
   o->hbm_budget_bytes = 0;
 }
@@ -259,12 +265,31 @@ extern "C" int mor_create(const mor_mesh* mesh, const mor_coeff* coeff, const mo
   c->ext.assign(sub->ext_tets, sub->ext_tets + c->ext_ptr[n]);
   c->in_core.assign(sub->in_core, sub->in_core + c->ext_ptr[n]);
   c->subs.resize(n);
-  for (int i = 0; i < n; ++i) {
-    if (build_sub(m, c->ext.data() + c->ext_ptr[i], c->in_core.data() + c->ext_ptr[i], c->ext_ptr[i + 1] - c->ext_ptr[i],
-                  c->subs[i], err)) {
-      delete c;
-      return fail(MOR_EINVAL, "subdomain " + std::to_string(i) + ": " + err);
-    }
+  // halo size of the LDS SpMM tiles: spmm_rows picks one of kHaloCaps (0: 64 rows, which
+  // leaves room for 7 workgroups per CU)
+  c->halo_cap = 64;
+  if (c->opts.spmm_kind != 2 && c->opts.spmm_rows > 0)
+    for (int cap : kHaloCaps)
+      if (cap <= c->opts.spmm_rows) c->halo_cap = cap;
+  {
+    // the subdomains are independent: build them on the host cores
+    std::vector<std::string> errs(n);
+    std::vector<int> bad(n, 0);
+    const int nth = std::max(1, std::min<int>(n, (int)std::thread::hardware_concurrency()));
+    std::vector<std::thread> pool;
+    std::atomic<int> next{0};
+    for (int w = 0; w < nth; ++w)
+      pool.emplace_back([&]() {
+        for (int i = next++; i < n; i = next++)
+          bad[i] = build_sub(m, c->ext.data() + c->ext_ptr[i], c->in_core.data() + c->ext_ptr[i],
+                             c->ext_ptr[i + 1] - c->ext_ptr[i], c->subs[i], errs[i], c->halo_cap);
+      });
+    for (auto& th : pool) th.join();
+    for (int i = 0; i < n; ++i)
+      if (bad[i]) {
+        delete c;
+        return fail(MOR_EINVAL, "subdomain " + std::to_string(i) + ": " + errs[i]);
+      }
   }
   if (build_owner(m, c->subs, c->owner, c->ownpos, err) ||
       build_omega0(m, c->subs, c->ext_ptr.data(), c->ext.data(), c->in_core.data(), c->owner, c->ownpos, c->om0, err)) {
@@ -294,6 +319,12 @@ extern "C" int mor_create(const mor_mesh* mesh, const mor_coeff* coeff, const mo
     r = r ? r : upload(c, &d.nodes, h.nodes.data(), h.nodes.size());
     r = r ? r : upload(c, &d.core, h.core.data(), h.core.size());
     r = r ? r : upload(c, &d.bp, h.bp.data(), h.bp.size());
+    r = r ? r : upload(c, &d.htile, h.htile.data(), h.htile.size());
+    r = r ? r : upload(c, &d.halo, h.halo.data(), h.halo.size());
+    r = r ? r : upload(c, &d.hrowp, h.hrowp.data(), h.hrowp.size());
+    r = r ? r : upload(c, &d.hpe, h.hpe.data(), h.hpe.size());
+    r = r ? r : upload(c, &d.hpp, h.hpp.data(), h.hpp.size());
+    r = r ? r : upload(c, &d.hself, h.hself.data(), h.hself.size());
     return r;
   };
   c->sdev.resize(n);
@@ -441,6 +472,8 @@ static GemmDesc gd(int m, int n, int k, const double* A, int lda, int ta, const 
 struct TileCfg {
   int v = 4;    // elements per lane: tile width 64 v columns
   int rb = 32;  // rows (row tiles) or aggregates (block tiles) per tile
+  int halo = 1; // SpMM only: LDS halo tiles (1) or row tiles (0)
+  int g = 4;    // SpMM halo tiles: 256-byte column slices per workgroup
 };
 
 // ------------------------------------------------------------------------------- debug dumps
@@ -504,10 +537,12 @@ static void slot_shape(mor_ctx* c, Slot& q) {
   q.M = h.nB;
   q.MP = (int)rup(q.M, 64);
   q.T = q.MP / 64;
+  // rows of the block vectors start on 128-byte cache lines (32 FP32 / 16 FP64 columns), so
+  // the column slices of the CG kernels never straddle a line they only partly use
   q.colsA = h.nB + 1;
-  q.ldA = (int)rup(q.colsA, 4);
+  q.ldA = (int)rup(q.colsA, 32);
   q.colsK = h.nB;
-  q.ldK = (int)rup(q.colsK, 4);
+  q.ldK = (int)rup(q.colsK, 32);
   const int p = c->opts.oversample > 0 ? c->opts.oversample : std::max(8, q.rank);
   int s = q.rank > 0 ? std::min(64, q.rank + p) : 64;
   s = std::min(s, q.M);
@@ -584,6 +619,7 @@ struct SysRun {
   int phase;      // 0 iterating, 1 finished
   int iters, refines;
   int nnzII;
+  int nhtile;     // LDS-halo SpMM tiles of the subdomain
 };
 
 struct Live {
@@ -602,6 +638,15 @@ struct Req {
   int done = 0, status = 0;
 };
 
+struct Launch {
+  std::vector<SysRun*> sys;
+  int4 *sp = nullptr, *bk = nullptr, *hs = nullptr;
+  int nsp = 0, nbk = 0, nhs = 0;
+  int2* cb = nullptr;
+  int ncb = 0;
+  double spmm_bytes = 0;
+};
+
 struct MorEngine {
   int elt = 4;
   std::vector<Req> pending;
@@ -611,6 +656,9 @@ struct MorEngine {
   size_t sys_cap = 0;
   int4* d_tiles = nullptr;
   size_t tiles_cap = 0;
+  std::vector<CgSys> up_hs;   // the systems of the last upload (its device lists)
+  Launch up_L;
+  bool up_ok = false;
   int2* d_cb = nullptr;
   size_t cb_cap = 0;
   int* d_cnt = nullptr;
@@ -631,8 +679,14 @@ static int engine_init(mor_ctx* c, MorEngine& e, int elt) {
   HIPCHK(hipHostMalloc((void**)&e.h_cnt, sizeof(int) * e.cnt_cap));
   for (int i = e.cnt_cap - 1; i >= 0; --i) e.cnt_free.push_back(i);
   const bool fp32 = elt == 4;
-  e.sp.v = c->opts.spmm_vec > 0 ? c->opts.spmm_vec : 4;
-  if (!fp32 && e.sp.v > 2) e.sp.v = 2;
+  e.sp.halo = c->opts.spmm_kind != 2;
+  if (e.sp.halo) {
+    e.sp.g = c->opts.spmm_vec > 0 ? std::min(c->opts.spmm_vec, 64) : 8;   // slices per workgroup
+    e.sp.v = fp32 ? 4 : 2;   // the row kernels (init, residual, shadow)
+  } else {
+    e.sp.v = c->opts.spmm_vec > 0 ? c->opts.spmm_vec : 4;
+    if (!fp32 && e.sp.v > 2) e.sp.v = 2;
+  }
   e.sp.rb = c->opts.spmm_rows > 0 ? std::min(c->opts.spmm_rows, 64) : 8;
   e.stm.v = c->opts.stream_vec > 0 ? c->opts.stream_vec : 2;   // block kernels hold 8 rows per lane
   if (!fp32 && e.stm.v > 2) e.stm.v = 2;
@@ -670,23 +724,21 @@ static int grow(mor_ctx* c, T** p, size_t* cap, size_t need) {
 }
 
 // Upload the systems in `list` as the device table; return tiles and column blocks over them.
-struct Launch {
-  std::vector<SysRun*> sys;
-  int4 *sp = nullptr, *bk = nullptr;
-  int nsp = 0, nbk = 0;
-  int2* cb = nullptr;
-  int ncb = 0;
-  double spmm_bytes = 0;
-};
 
 static int engine_upload(mor_ctx* c, MorEngine& e, Launch& L) {
   const int n = (int)L.sys.size();
   std::vector<CgSys> hs(n);
   std::vector<int4> t;
   std::vector<int2> cb;
+  for (int i = 0; i < n; ++i) hs[i] = L.sys[i]->S;
+  // the same systems as the last upload: the device lists are still in place
+  if (e.up_ok && L.sys == e.up_L.sys && std::memcmp(hs.data(), e.up_hs.data(), sizeof(CgSys) * n) == 0) {
+    L = e.up_L;
+    return 0;
+  }
+  e.up_ok = false;
   L.spmm_bytes = 0;
   for (int i = 0; i < n; ++i) {
-    hs[i] = L.sys[i]->S;
     const CgSys& S = hs[i];
     L.spmm_bytes += (double)L.sys[i]->nnzII * (4.0 + e.elt) + 4.0 * (S.nI + 1) + 2.0 * e.elt * (double)S.nI * S.ncols;
   }
@@ -702,6 +754,15 @@ static int engine_upload(mor_ctx* c, MorEngine& e, Launch& L) {
       for (int b0 = 0; b0 < S.nblk; b0 += e.stm.rb) t.push_back(make_int4(i, b0, c0, 0));
   }
   L.nbk = (int)t.size() - L.nsp;
+  if (e.sp.halo) {
+    const int gw = (256 / e.elt) * e.sp.g;   // columns per slice group
+    for (int i = 0; i < n; ++i) {
+      const int nt = L.sys[i]->nhtile;
+      for (int c0 = 0; c0 < hs[i].ld; c0 += gw)
+        for (int h = 0; h < nt; ++h) t.push_back(make_int4(i, h, c0, c0 + gw));
+    }
+  }
+  L.nhs = (int)t.size() - L.nsp - L.nbk;
   for (int i = 0; i < n; ++i)
     for (int c0 = 0; c0 < hs[i].ld; c0 += 256) cb.push_back(make_int2(i, c0));
   L.ncb = (int)cb.size();
@@ -714,7 +775,11 @@ static int engine_upload(mor_ctx* c, MorEngine& e, Launch& L) {
   HIPCHK(hipStreamSynchronize(c->st));   // the host vectors are pageable
   L.sp = e.d_tiles;
   L.bk = e.d_tiles + L.nsp;
+  L.hs = e.d_tiles + L.nsp + L.nbk;
   L.cb = e.d_cb;
+  e.up_hs.swap(hs);
+  e.up_L = L;
+  e.up_ok = true;
   return 0;
 }
 
@@ -814,6 +879,13 @@ static int engine_admit(mor_ctx* c, MorEngine& e) {
       S.bp = q.d->bp;
       S.nblk = nblk;
       S.minv = w == 0 ? q.minvA : q.minvK;
+      S.htile = (const int4*)q.d->htile;
+      S.halo = q.d->halo;
+      S.hrowp = q.d->hrowp;
+      S.hpe = q.d->hpe;
+      S.hpp = q.d->hpp;
+      S.hself = q.d->hself;
+      R.nhtile = (int)h.htile.size() / 4;
       double* cs = q.colst[w];
       const int ld = S.ld;
       S.pq = cs; S.rz = cs + ld; S.rznew = cs + 2 * ld; S.rz0 = cs + 3 * ld; S.rzF = cs + 4 * ld;
@@ -855,7 +927,10 @@ static int engine_chunk(mor_ctx* c, MorEngine& e) {
   for (int k = 0; k < chunk; ++k) {
     {
       ScopedTimer tm(c, "spmm", La.spmm_bytes);
-      launch_cg_spmm<T>(e.d_sys, La.sp, La.nsp, e.sp.rb, e.sp.v, st);
+      if (e.sp.halo)
+        launch_cg_spmm_halo<T>(e.d_sys, La.hs, La.nhs, c->halo_cap, st);
+      else
+        launch_cg_spmm<T>(e.d_sys, La.sp, La.nsp, e.sp.rb, e.sp.v, st);
     }
     launch_cg_alpha(e.d_sys, La.cb, La.ncb, st);
     {

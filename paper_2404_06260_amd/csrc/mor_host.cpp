@@ -120,8 +120,110 @@ static void colour_sort(const HostMesh& m, HostSub& s, std::vector<int32_t>& lte
   }
 }
 
+// Greedy SpMM tiling over whole aggregates, in row order: a tile grows while it has at most
+// kHaloRows rows and halo_nnz_cap(cap) padded entries and its halo (the union of the II columns of its
+// rows) at most kHaloCap rows.  Each row's II entries are padded to a multiple of 8 (entry -1,
+// weight 0) so the kernel takes them in chunks of 8 without bounds tests.
+static int padded_ii(const HostSub& s, int r) { return (s.ii_end[r] - s.rp[r] + 7) / 8 * 8; }
+
+static int build_halo_tiles(HostSub& s, int cap, std::string& err) {
+  s.htile.clear();
+  s.halo.clear();
+  s.hpe.clear();
+  s.hpp.clear();
+  s.hrowp.assign(s.nI + 1, 0);
+  s.hself.assign(s.nI, 0);
+  std::vector<int32_t> stamp(s.nI, -1), cur, add;
+  const int nb = (int)s.bp.size() - 1;
+  int b = 0;
+  while (b < nb) {
+    const int tid = (int)s.htile.size() / 4;
+    const int row0 = s.bp[b];
+    cur.clear();
+    int b1 = b, npad = 0;
+    while (b1 < nb) {
+      const int r0 = s.bp[b1], r1 = s.bp[b1 + 1];
+      int addpad = 0;
+      for (int r = r0; r < r1; ++r) addpad += padded_ii(s, r);
+      if (b1 > b && (r1 - row0 > kHaloRows || npad + addpad > halo_nnz_cap(cap))) break;
+      add.clear();
+      for (int r = r0; r < r1; ++r)
+        for (int e = s.rp[r]; e < s.ii_end[r]; ++e) {
+          const int cc = s.col[e];
+          if (stamp[cc] != tid) {
+            stamp[cc] = tid;
+            add.push_back(cc);
+          }
+        }
+      if (b1 > b && (int)(cur.size() + add.size()) > cap) {
+        for (int cc : add) stamp[cc] = -1;
+        break;
+      }
+      cur.insert(cur.end(), add.begin(), add.end());
+      npad += addpad;
+      ++b1;
+    }
+    std::sort(cur.begin(), cur.end());
+    const int row1 = s.bp[b1];
+    s.htile.push_back(row0);
+    s.htile.push_back(row1 - row0);
+    s.htile.push_back((int32_t)s.halo.size());
+    s.htile.push_back((int32_t)cur.size());
+    auto pos = [&](int cc) { return (int)(std::lower_bound(cur.begin(), cur.end(), cc) - cur.begin()); };
+    for (int r = row0; r < row1; ++r) {
+      s.hrowp[r] = (int32_t)s.hpe.size();
+      const int pad = padded_ii(s, r);
+      for (int k = 0; k < pad; ++k) {
+        const int e = s.rp[r] + k;
+        const bool real = e < s.ii_end[r];
+        s.hpe.push_back(real ? e : -1);
+        s.hpp.push_back((uint16_t)(real ? pos(s.col[e]) : 0));
+      }
+      s.hself[r] = (uint16_t)pos(r);
+    }
+    s.halo.insert(s.halo.end(), cur.begin(), cur.end());
+    b = b1;
+  }
+  s.hrowp[s.nI] = (int32_t)s.hpe.size();
+  // the SpMM kernel indexes LDS with these: check every bound it relies on
+  int next = 0;
+  for (size_t t = 0; t < s.htile.size(); t += 4) {
+    const int r0 = s.htile[t], nr = s.htile[t + 1], h0 = s.htile[t + 2], nh = s.htile[t + 3];
+    if (r0 != next || nr < 1 || nr > kHaloRows || nh < 1 || nh > cap || cap > kHaloCap || h0 + nh > (int)s.halo.size() ||
+        s.hrowp[r0 + nr] - s.hrowp[r0] > halo_nnz_cap(cap)) {
+      err = "internal: SpMM tile out of bounds";
+      return -1;
+    }
+    next = r0 + nr;
+    for (int r = r0; r < r0 + nr; ++r) {
+      if (s.hself[r] >= nh || s.halo[h0 + s.hself[r]] != r || (s.hrowp[r + 1] - s.hrowp[r]) % 8 != 0) {
+        err = "internal: SpMM tile misses its own row";
+        return -1;
+      }
+      int real = 0;
+      for (int k = s.hrowp[r]; k < s.hrowp[r + 1]; ++k) {
+        const int e = s.hpe[k];
+        if (s.hpp[k] >= nh || (e >= 0 && (e < s.rp[r] || e >= s.ii_end[r] || s.halo[h0 + s.hpp[k]] != s.col[e]))) {
+          err = "internal: SpMM tile halo misses a column";
+          return -1;
+        }
+        real += e >= 0;
+      }
+      if (real != s.ii_end[r] - s.rp[r]) {
+        err = "internal: SpMM tile drops an entry";
+        return -1;
+      }
+    }
+  }
+  if (next != s.nI) {
+    err = "internal: SpMM tiles do not cover the interior rows";
+    return -1;
+  }
+  return 0;
+}
+
 int build_sub(const HostMesh& m, const int32_t* ext, const uint8_t* in_core, int64_t n_ext, HostSub& s,
-              std::string& err) {
+              std::string& err, int halo_cap) {
   std::vector<int32_t> starE(m.n_nodes, 0), starC(m.n_nodes, 0);
   std::vector<int32_t> touched;
   touched.reserve(n_ext);
@@ -223,6 +325,7 @@ int build_sub(const HostMesh& m, const int32_t* ext, const uint8_t* in_core, int
     const int32_t* e = s.col.data() + s.rp[r + 1];
     s.ii_end[r] = (int32_t)(std::lower_bound(b, e, s.nI) - s.col.data());
   }
+  if (build_halo_tiles(s, halo_cap, err)) return -1;
   tet_pattern(s.ltet, &s.core, s.nV, s.rpV, s.colV);
   for (int32_t c : s.colV)
     if (c >= s.nV) {

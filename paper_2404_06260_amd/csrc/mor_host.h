@@ -7,6 +7,16 @@
 
 namespace mor {
 
+// SpMM tiles of the block CG: runs of whole row aggregates of at most kHaloRows rows and
+// halo_nnz_cap(cap) padded CSR entries whose II columns (the tile's halo: every row of P the tile reads)
+// number at most cap, so that one 256-byte column slice of every halo row and the tile's
+// CSR fit in LDS.
+constexpr int kHaloRows = 64;
+constexpr int kHaloCap = 176;   // the largest halo; a context may choose a smaller one (kHaloCaps)
+constexpr int kHaloCaps[5] = {48, 64, 96, 128, 176};
+// padded CSR entries per tile for a halo cap (a Kuhn-cube row has 15 II entries, padded to 16)
+constexpr int halo_nnz_cap(int cap) { return cap * 8 < 1024 ? cap * 8 : 1024; }
+
 struct HostMesh {
   int64_t n_nodes = 0, n_tets = 0;
   std::vector<double> xyz;
@@ -28,6 +38,12 @@ struct HostSub {
   std::vector<uint8_t> core;               // 1 if the local tet lies in omega_i
   std::vector<int32_t> colour_ptr;         // local tets of colour c: [colour_ptr[c], colour_ptr[c+1])
   std::vector<int32_t> bp;                 // aggregates of I rows: block b = rows [bp[b], bp[b+1]), size <= 8
+  std::vector<int32_t> htile;              // SpMM tiles, 4 ints each: first row, rows, first halo entry, halo size
+  std::vector<int32_t> halo;               // each tile's halo rows (local ids < nI), ascending
+  std::vector<int32_t> hrowp;              // per I row (+1): start of its padded II entries in hpe / hpp
+  std::vector<int32_t> hpe;                // padded II entries: CSR entry id, or -1 (weight 0)
+  std::vector<uint16_t> hpp;               // padded II entries: the column's position in the tile halo
+  std::vector<uint16_t> hself;             // per I row: the row's own position in its tile halo
 };
 
 // omega_0: the elements in two or more subdomains, with A_0's pattern over their free nodes.
@@ -40,7 +56,7 @@ struct HostOmega0 {
 
 int build_mesh(HostMesh& m, std::string& err);
 int build_sub(const HostMesh& m, const int32_t* ext, const uint8_t* in_core, int64_t n_ext, HostSub& s,
-              std::string& err);
+              std::string& err, int halo_cap = kHaloCap);
 // owner / position of every free node in its P_i; error unless the P_i partition the free nodes
 int build_owner(const HostMesh& m, const std::vector<HostSub>& subs, std::vector<int32_t>& owner,
                 std::vector<int32_t>& ownpos, std::string& err);

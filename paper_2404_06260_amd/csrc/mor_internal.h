@@ -3,6 +3,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "mor_host.h"
+
 namespace mor {
 
 constexpr int kWave = 64;
@@ -53,6 +55,13 @@ struct CgSys {
   double* beta;
   int* active;         // 1 while the column iterates
   int* nactive;        // active columns of this system after the last iteration
+  // LDS-halo SpMM tiling (shared by the A and K systems of a subdomain)
+  const int4* htile;   // first row, rows, first halo entry, halo size
+  const int* halo;
+  const int* hrowp;    // per I row (+1): start of its padded II entries
+  const int* hpe;      // padded II entries: CSR entry id or -1
+  const uint16_t* hpp; // padded II entries: position in the tile halo
+  const uint16_t* hself;
 };
 
 // ---------------------------------------------------------------------------------
@@ -93,11 +102,12 @@ void launch_assemble(const AsmSub* d_subs, const int* d_prefix, int nsub, int to
 void launch_to_f32(const double* in, float* out, int64_t n, hipStream_t s);
 
 // v = elements per lane (tile width 64 v columns): 1, 2 or 4 for float, 1 or 2 for double
-// v = elements per lane (tile width 64 v columns): 1, 2 or 4 for float, 1 or 2 for double
 template <typename T>
 void launch_cg_init(const CgSys* sys, const int4* tiles, int ntiles, int rb, int v, hipStream_t s);
 template <typename T>
 void launch_cg_spmm(const CgSys* sys, const int4* tiles, int ntiles, int rb, int v, hipStream_t s);
+template <typename T>
+void launch_cg_spmm_halo(const CgSys* sys, const int4* tiles, int ntiles, int cap, hipStream_t s);
 template <typename T>
 void launch_cg_residual64(const CgSys* sys, const int4* tiles, int ntiles, int rb, int v, hipStream_t s);
 template <typename T>

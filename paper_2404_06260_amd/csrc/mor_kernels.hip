@@ -366,6 +366,118 @@ __global__ __launch_bounds__(256) void k_cg_spmm(const CgSys* __restrict__ sys, 
   column_reduce_add<V>(red, part, tl.z, ld, S.pq);
 }
 
+// Q = A_II P through LDS.  A workgroup owns one row tile (a host-built run of whole row
+// aggregates) of one system and sweeps a group of its 256-byte column slices; the launch lists
+// (system, slice group, tile) with the tile fastest, so the workgroups resident on one XCD
+// work on neighbouring tiles of the same slices at the same time.  Per slice, every P row
+// the tile reads (its halo) is loaded once into LDS, 16 bytes per lane, and each wave forms its
+// rows' Q entries from LDS alone: the L2/HBM reads per output row drop from one per matrix
+// entry (about 15) to halo/rows (about 4), and neighbouring tiles (consecutive workgroups on one
+// XCD) share the halo rows in L2.  The tile's CSR (halo offsets and values, padded to chunks of
+// 8) is staged once; the next slice's loads are in flight while the current slice computes.
+// FP32: one column per lane, one row per wave step; FP64: 32 columns, two rows per wave step.
+template <typename T, int CAP>
+__global__ __launch_bounds__(256) void k_cg_spmm_halo(const CgSys* __restrict__ sys, const int4* __restrict__ tiles,
+                                                      int ntiles) {
+  constexpr int CW = 256 / (int)sizeof(T);   // columns per slice
+  constexpr int RPW = 64 / CW;               // rows per wave step
+  constexpr int CPC = 16 / (int)sizeof(T);   // elements per 16-byte staging chunk
+  constexpr int NST = (CAP * 16 + 255) / 256;        // staging chunks per thread
+  constexpr int NZC = halo_nnz_cap(CAP);             // padded CSR entries per tile
+  constexpr int NNZ = (NZC + 255) / 256;             // padded CSR entries per thread
+  __shared__ __attribute__((aligned(16))) T hp[CAP * CW];
+  __shared__ __attribute__((aligned(16))) T s_val[NZC];
+  __shared__ __attribute__((aligned(16))) uint16_t s_off[NZC];   // halo position * CW
+  __shared__ int s_p[kHaloRows + 1], s_self[kHaloRows];
+  __shared__ double red[4 * 64];
+  const int t = xcd_tile(blockIdx.x, ntiles);
+  if (t >= ntiles) return;
+  const int4 tl = tiles[t];
+  const CgSys& S = sys[tl.x];
+  const int4 ht = S.htile[tl.y];   // first row, rows, first halo entry, halo size
+  const int ld = S.ld;
+  const int cbeg = tl.z, cend = min(tl.w, ld);
+  const T* __restrict__ P = (const T*)S.P;
+  T* __restrict__ Q = (T*)S.Q;
+  const T* __restrict__ val = (sizeof(T) == 4) ? (const T*)S.val32 : (const T*)S.val64;
+  const int tid = threadIdx.x;
+  const int nchunk = ht.w * 16;
+  const int pb = gld(S.hrowp + ht.x);
+  const int np = gld(S.hrowp + ht.x + ht.y) - pb;   // <= NZC (host-checked)
+  int64_t hoff[NST];   // element offset of each staged chunk's halo row (slice 0), -1: none
+#pragma unroll
+  for (int k = 0; k < NST; ++k) {
+    const int i = k * 256 + tid;
+    hoff[k] = i < nchunk ? (int64_t)gld(S.halo + ht.z + (i >> 4)) * ld + (i & 15) * CPC : -1;
+  }
+#pragma unroll
+  for (int k = 0; k < NNZ; ++k) {
+    const int i = k * 256 + tid;
+    if (i < np) {
+      const int e = gld(S.hpe + pb + i);
+      s_off[i] = (uint16_t)(gld(S.hpp + pb + i) * CW);
+      s_val[i] = e >= 0 ? gld(val + e) : (T)0;
+    }
+  }
+  if (tid <= ht.y) s_p[tid] = gld(S.hrowp + ht.x + tid) - pb;
+  if (tid < ht.y) s_self[tid] = (int)gld(S.hself + ht.x + tid) * CW;
+  u32x4 pv[NST];
+  auto issue = [&](int c0) {
+#pragma unroll
+    for (int k = 0; k < NST; ++k) {
+      pv[k] = (u32x4){0u, 0u, 0u, 0u};
+      if (hoff[k] >= 0 && c0 + (k * 256 + tid & 15) * CPC < ld)
+        pv[k] = *((const MOR_GLOBAL u32x4*)(P + hoff[k] + c0));
+    }
+  };
+  issue(cbeg);
+  const int lane = tid & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int sub = lane / CW, col = lane % CW;
+  // per-column p'Q of the previous slice: summed over the waves after the next barrier
+  auto flush = [&](int cp) {
+    if (tid < CW && cp + tid < ld) {
+      double sum = 0.0;
+#pragma unroll
+      for (int w = 0; w < 4; ++w)
+#pragma unroll
+        for (int sb = 0; sb < RPW; ++sb) sum += red[w * 64 + sb * CW + tid];
+      if (sum != 0.0) unsafeAtomicAdd(&S.pq[cp + tid], sum);
+    }
+  };
+  for (int c0 = cbeg; c0 < cend; c0 += CW) {
+    __syncthreads();   // the previous slice is done with hp; its red is complete
+    if (c0 > cbeg) flush(c0 - CW);
+#pragma unroll
+    for (int k = 0; k < NST; ++k) {
+      const int i = k * 256 + tid;
+      if (i < nchunk) *reinterpret_cast<u32x4*>(&hp[(i >> 4) * CW + (i & 15) * CPC]) = pv[k];
+    }
+    __syncthreads();
+    if (c0 + CW < cend) issue(c0 + CW);
+    const bool act = c0 + col < ld;
+    double part = 0.0;
+    for (int i0 = wv * RPW; i0 < ht.y; i0 += 4 * RPW) {
+      const int i = i0 + sub;
+      if (i < ht.y) {
+        const int e0 = s_p[i], e1 = s_p[i + 1];
+        T acc = 0;
+        for (int e = e0; e < e1; e += 8) {
+#pragma unroll
+          for (int k = 0; k < 8; ++k) acc += s_val[e + k] * hp[s_off[e + k] + col];
+        }
+        if (act) {
+          st_nt(Q + (int64_t)(ht.x + i) * ld + c0 + col, acc);
+          part += (double)hp[s_self[i] + col] * (double)acc;
+        }
+      }
+    }
+    red[wv * 64 + lane] = part;
+  }
+  __syncthreads();
+  flush(cbeg + (cend - cbeg - 1) / CW * CW);
+}
+
 // Block-Jacobi preconditioner: z = M^-1 r with M the diagonal blocks of A_II over the row
 // aggregates (at most 8 rows each).  A wave owns whole aggregates, so applying M^-1 needs no
 // data beyond the rows the kernel streams anyway.
@@ -653,6 +765,18 @@ void launch_cg_spmm(const CgSys* sys, const int4* tiles, int ntiles, int rb, int
   if (ntiles > 0) MOR_VSWITCH(T, v, k_cg_spmm, sys, tiles, ntiles, rb);
 }
 template <typename T>
+void launch_cg_spmm_halo(const CgSys* sys, const int4* tiles, int ntiles, int cap, hipStream_t s) {
+  if (ntiles <= 0) return;
+  const dim3 g(xcd_grid(ntiles)), b(256);
+  static_assert(kHaloCaps[0] == 48 && kHaloCaps[1] == 64 && kHaloCaps[2] == 96 && kHaloCaps[3] == 128 &&
+                kHaloCaps[4] == 176, "halo caps");
+  if (cap <= 48) hipLaunchKernelGGL((k_cg_spmm_halo<T, 48>), g, b, 0, s, sys, tiles, ntiles);
+  else if (cap <= 64) hipLaunchKernelGGL((k_cg_spmm_halo<T, 64>), g, b, 0, s, sys, tiles, ntiles);
+  else if (cap <= 96) hipLaunchKernelGGL((k_cg_spmm_halo<T, 96>), g, b, 0, s, sys, tiles, ntiles);
+  else if (cap <= 128) hipLaunchKernelGGL((k_cg_spmm_halo<T, 128>), g, b, 0, s, sys, tiles, ntiles);
+  else hipLaunchKernelGGL((k_cg_spmm_halo<T, 176>), g, b, 0, s, sys, tiles, ntiles);
+}
+template <typename T>
 void launch_cg_update(const CgSys* sys, const int4* tiles, int ntiles, int rb, int v, hipStream_t s) {
   if (ntiles > 0) MOR_VSWITCH(T, v, k_cg_update, sys, tiles, ntiles, rb);
 }
@@ -675,6 +799,7 @@ void launch_cg_pstart(const CgSys* sys, const int4* tiles, int ntiles, int bpt, 
 #define MOR_INST(T)                                                                                      \
   template void launch_cg_init<T>(const CgSys*, const int4*, int, int, int, hipStream_t);       \
   template void launch_cg_spmm<T>(const CgSys*, const int4*, int, int, int, hipStream_t);       \
+  template void launch_cg_spmm_halo<T>(const CgSys*, const int4*, int, int, hipStream_t);       \
   template void launch_cg_update<T>(const CgSys*, const int4*, int, int, int, hipStream_t);     \
   template void launch_cg_direction<T>(const CgSys*, const int4*, int, int, int, hipStream_t);  \
   template void launch_cg_residual64<T>(const CgSys*, const int4*, int, int, int, hipStream_t); \

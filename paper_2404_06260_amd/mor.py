@@ -54,7 +54,7 @@ class MorOpts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("cg_rtol", ctypes.c_double), ("refine_rtol", ctypes.c_double),
                 ("max_iter", ctypes.c_int32), ("refine_steps", ctypes.c_int32), ("oversample", ctypes.c_int32),
                 ("eig_rtol", ctypes.c_double), ("eig_max_iter", ctypes.c_int32), ("cg_chunk", ctypes.c_int32),
-                ("spmm_rows", ctypes.c_int32), ("spmm_vec", ctypes.c_int32), ("stream_vec", ctypes.c_int32),
+                ("spmm_rows", ctypes.c_int32), ("spmm_vec", ctypes.c_int32), ("spmm_kind", ctypes.c_int32), ("stream_vec", ctypes.c_int32),
                 ("stream_blocks", ctypes.c_int32), ("use_graph", ctypes.c_int32), ("dense_batch", ctypes.c_int32),
                 ("hbm_budget_bytes", ctypes.c_size_t),
                 ("dev_alloc", ALLOC_FN), ("dev_free", FREE_FN), ("alloc_user", ctypes.c_void_p),
