@@ -58,6 +58,24 @@ def cpu_baseline(problem, budget_s: float = 20.0):
                        f"full FP64 local reduction each, {el:.1f} s, scipy/LAPACK with {threads} threads")
 
 
+def serving_leg(m, problem, n_req: int, load: float):
+    """Continuous-batching serving on the same context: the saturation rate (all requests
+    queued at t = 0), then a Poisson stream at `load` times that rate; latency = completion
+    seen - arrival."""
+    from paper_2404_06260_amd import serve
+    sat = serve.run_stream(m.ctx, serve.make_stream(problem, n_req, float("inf"), seed_order=12))
+    rate = load * sat.throughput
+    print(f"[bench] serving: saturation {sat.throughput:.2f} req/s, stream at {rate:.2f} req/s", file=sys.stderr,
+          flush=True)
+    res = serve.run_stream(m.ctx, serve.make_stream(problem, n_req, rate, seed_arrivals=7, seed_order=11))
+    pc = res.percentiles((50, 99))
+    return {"requests": n_req, "arrivals": "poisson", "rate_per_s": round(rate, 3),
+            "load_vs_saturation": load, "saturation_per_s": round(sat.throughput, 3),
+            "throughput_per_s": round(res.throughput, 3), "p50_ms": round(pc["p50"] * 1e3, 1),
+            "p99_ms": round(pc["p99"] * 1e3, 1), "max_live": res.max_live, "peak_bytes": res.peak_bytes,
+            "budget_bytes": res.budget_bytes, "failed": int((res.status != 0).sum())}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -68,6 +86,10 @@ def main():
     ap.add_argument("--spmm-rows", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
+    ap.add_argument("--serve-requests", type=int, default=-1,
+                    help="requests in the serving leg (-1: one per subdomain, 0: no serving leg)")
+    ap.add_argument("--serve-load", type=float, default=0.9,
+                    help="Poisson arrival rate of the serving leg as a fraction of the measured saturation rate")
     ap.add_argument("--calibrate-copy", type=int, default=0,
                     help="MiB copied by one plain device copy before the steps (HBM counter calibration)")
     args = ap.parse_args()
@@ -133,6 +155,9 @@ def main():
         if n:
             kernels[name] = dict(launches=n, ms_per_step=round(ms / args.steps, 3))
     stats = [mor.mor_get_stats(m.ctx, i) for i in range(n_sub)]
+    serving = None
+    if args.serve_requests != 0:
+        serving = serving_leg(m, p, n_sub if args.serve_requests < 0 else args.serve_requests, args.serve_load)
     m.close()
     cpu = None
     if not args.no_cpu_baseline:
@@ -159,6 +184,7 @@ def main():
                      "traffic": None, "avg_launch_ms": round(avg_ms, 4), "launches": n_launch,
                      "algorithmic_bytes_per_launch": round(bytes_per_launch)},
         "cpu_baseline": cpu,
+        "serving": serving,
         "kernels": kernels,
         "cg_iters_max": [max(s["cg_iter_a"] for s in stats), max(s["cg_iter_k"] for s in stats)],
         "eig_iters_max": max(s["eig_iter"] for s in stats),
