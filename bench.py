@@ -58,6 +58,28 @@ def cpu_baseline(problem, budget_s: float = 20.0):
                        f"full FP64 local reduction each, {el:.1f} s, scipy/LAPACK with {threads} threads")
 
 
+PROFILE = os.path.join(ROOT, "profiles", "k_cg_spmm_halo_48cube_lognormal_fp32refine.md")
+
+
+def profiled_traffic(kernel: str, config: str):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 summary (calibrated
+    FETCH_SIZE + WRITE_SIZE), or None when the summary covers another workload or the kernel
+    source has changed since the counters were taken."""
+    import hashlib
+    import re
+    if config != "C2" or not os.path.exists(PROFILE):
+        return None
+    txt = open(PROFILE).read()
+    m = re.search(r"sha256 ([0-9a-f]{16})", txt)
+    src = os.path.join(ROOT, "paper_2404_06260_amd", "csrc", "mor_kernels.hip")
+    if not m or hashlib.sha256(open(src, "rb").read()).hexdigest()[:16] != m.group(1):
+        return None
+    row = re.search(r"\| `mor::" + re.escape(kernel) + r"` \|[^|]*\|[^|]*\|[^|]*\| ([0-9.]+) \| ([0-9.]+) \|", txt)
+    if not row:
+        return None
+    return round((float(row.group(1)) + float(row.group(2))) * 1e9)
+
+
 def serving_leg(m, problem, n_req: int, load: float):
     """Continuous-batching serving on the same context: the saturation rate (all requests
     queued at t = 0), then a Poisson stream at `load` times that rate; latency = completion
@@ -116,6 +138,11 @@ def main():
     else:
         tile = dict(spmm_rows=args.spmm_rows)
     m = mor.Mor(p, precision=prec, **tile)
+    halo = tile.get("spmm_kind", 0) != 2
+    spmm_cap = max([c for c in (48, 64, 96, 128, 176) if c <= tile.get("spmm_rows", 0)] or [64]) if halo else 0
+    elt = "double" if prec == "fp64" else "float"
+    spmm_kernel = (f"k_cg_spmm_halo<{elt}, {spmm_cap}>" if halo else
+                   f"k_cg_spmm<{elt}, {tile.get('spmm_vec', 4)}>")
     n_sub = p.subdomains.n_sub
 
     def step():
@@ -179,9 +206,12 @@ def main():
         "config": {"workload": WORKLOAD_OF[args.config], "name": args.config, "subdomains": n_sub,
                    "precision": prec, "reduced_dim": int(nred),
                    "tiles": tile or "library defaults"},
-        "roofline": {"bound": "hbm", "kernel": "k_cg_spmm (block-CG SpMM Q = A_II P)", "achieved": round(achieved, 1),
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": None, "avg_launch_ms": round(avg_ms, 4), "launches": n_launch,
+        "roofline": {"bound": "hbm", "kernel": f"{spmm_kernel} (block-CG SpMM Q = A_II P)",
+                     "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": profiled_traffic(spmm_kernel, args.config) if spmm_cap == 64 else None,
+                     "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, calibrated)",
+                     "avg_launch_ms": round(avg_ms, 4), "launches": n_launch,
                      "algorithmic_bytes_per_launch": round(bytes_per_launch)},
         "cpu_baseline": cpu,
         "serving": serving,
