@@ -44,7 +44,9 @@ extern "C" {
 #define MOR_FP64 0        /* FP64 block CG, FP64 everywhere (the plain comparator path) */
 #define MOR_FP32_REFINE 1 /* FP32 block CG + FP64 residual refinement; FP64 Gram and eigen */
 #define MOR_FP32 2        /* FP32 block CG; FP64 Gram and eigen on the FP32 solution */
-#define MOR_BF16_SPLIT 3  /* FP32 block CG; Gram contraction in BF16 MFMA hi/lo split, FP32 accumulate */
+#define MOR_BF16_SPLIT 3  /* FP32 block CG + FP64 residual refinement; Gram contraction X_C^T K_i X_C in
+                             BF16 MFMA on hi/lo splits of both operands (hi^T hi + hi^T lo + lo^T hi),
+                             FP32 accumulation; FP64 Cholesky, eigen and projections */
 
 typedef struct mor_ctx mor_ctx;
 

@@ -528,6 +528,8 @@ struct Slot {
   double *Y, *S, *G, *W, *C, *Dinv;
   double *Vb, *Yb, *Ub, *Zb, *Vn, *Tb, *H, *Ss, *G2, *Rinv, *theta, *resid;
   double *Bk, *Wk, *Yf;
+  uint16_t *Xh, *Xl, *Yh, *Yl;   // BF16 split (transposed) X_C and K_i X_C, MP x kpV
+  int kpV;
   int* info;
   int k_eff;
 };
@@ -550,7 +552,7 @@ static void slot_shape(mor_ctx* c, Slot& q) {
   q.nconv = q.rank > 0 ? std::min(s - 1, q.rank + std::max(2, p / 2)) : s - 1;
   if (q.nconv < 1) q.nconv = std::min(1, s);
   q.fp32 = q.prec != MOR_FP64;
-  q.refine = q.prec == MOR_FP32_REFINE;
+  q.refine = q.prec == MOR_FP32_REFINE || q.prec == MOR_BF16_SPLIT;
 }
 
 // Device bytes of one request (CG blocks, dense matrices, eigensolver blocks), and the carve.
@@ -583,6 +585,14 @@ static bool slot_layout(Slot& q, Take tk) {
   }
   q.ldXc = q.ldA; q.ldEc = q.ldK;
   q.Y = (double*)tk(8 * (size_t)h.nV * q.ldK);
+  q.kpV = (int)rup(std::max(h.nV, 1), 64);
+  if (q.prec == MOR_BF16_SPLIT) {
+    const size_t b = 2 * (size_t)q.MP * q.kpV;
+    q.Xh = (uint16_t*)tk(b); q.Xl = (uint16_t*)tk(b);
+    q.Yh = (uint16_t*)tk(b); q.Yl = (uint16_t*)tk(b);
+  } else {
+    q.Xh = q.Xl = q.Yh = q.Yl = nullptr;
+  }
   q.S = (double*)tk(8 * (size_t)q.MP * q.MP); q.G = (double*)tk(8 * (size_t)q.MP * q.MP);
   q.W = (double*)tk(8 * (size_t)q.MP * q.MP); q.C = (double*)tk(8 * (size_t)q.MP * q.MP);
   q.Dinv = (double*)tk(8 * (size_t)q.T * 4096);
@@ -1073,8 +1083,13 @@ static int dense_stage(mor_ctx* c, std::vector<Live*>& done) {
   // scratch for descriptors and pointer tables of this stage
   size_t gemm_tiles = 0;
   for (Slot* q : sl) gemm_tiles += (size_t)(q->T + 2) * (q->T + 2) + 16 * (size_t)(q->T + 2) + 256;
+  size_t bf_tiles = 0;   // split-precision Gram: split tiles of X_C and K_i X_C, symmetric C tiles
+  for (Slot* q : sl)
+    if (q->prec == MOR_BF16_SPLIT)
+      bf_tiles += 2 * (size_t)(q->MP / 64) * (q->kpV / 64) + (size_t)q->T * (q->T + 1) / 2;
   const size_t bytes = 2 * 8 * gemm_tiles * sizeof(int4) + 32 * ns * sizeof(GemmDesc) + ns * (sizeof(DenseSub) + 2 * sizeof(TrsmDesc)) +
-                       8 * (size_t)ns * 20 + 8 * (size_t)ns * 64 + 16 * 4096;
+                       8 * (size_t)ns * 20 + 8 * (size_t)ns * 64 + 16 * 4096 + bf_tiles * sizeof(int4) +
+                       ns * (2 * sizeof(SplitDesc) + sizeof(BfGramDesc)) + 4 * 256;
   char* buf = (char*)dalloc(c, bytes);
   if (!buf) return fail(MOR_ENOMEM, "device allocation failed (dense stage)");
   struct Guard {
@@ -1100,15 +1115,53 @@ static int dense_stage(mor_ctx* c, std::vector<Live*>& done) {
     }
   }
   // ---- G1 = X_C^T K_i X_C (lifted interface functions in the H1(omega_i) inner product)
+  // (FP64 MFMA, or BF16 MFMA on hi/lo splits of both operands for MOR_BF16_SPLIT)
   GemmBatch gG;
+  std::vector<SplitDesc> spd;
+  std::vector<BfGramDesc> bgd;
+  std::vector<int4> spt, bgt;
+  double bf_flops = 0;
   for (Slot* q : sl) {
     const HostSub& h = *q->h;
     launch_fill(q->G, (int64_t)q->MP * q->MP, 0.0, st);
     launch_spmm64_rows(q->d->rpV, q->d->colV, q->Ki64, h.nV, h.nV, q->Xc, q->ldXc, q->M, q->Y, q->ldK, st);
-    gG.add(gd(q->M, q->M, h.nV, q->Xc, q->ldXc, 1, q->Y, q->ldK, 0, q->G, q->MP, 1.0, 0.0, 1));
+    if (q->prec == MOR_BF16_SPLIT) {
+      const int id = (int)spd.size();
+      spd.push_back(SplitDesc{q->Xc, q->ldXc, h.nV, q->M, q->kpV, q->MP, q->Xh, q->Xl});
+      spd.push_back(SplitDesc{q->Y, q->ldK, h.nV, q->M, q->kpV, q->MP, q->Yh, q->Yl});
+      for (int t = 0; t < 2; ++t)
+        for (int a = 0; a < q->MP / 64; ++a)
+          for (int v = 0; v < q->kpV / 64; ++v) spt.push_back(make_int4(id + t, a, v, 0));
+      const int gid = (int)bgd.size();
+      bgd.push_back(BfGramDesc{q->M, q->kpV, q->Xh, q->Xl, q->Yh, q->Yl, q->G, q->MP});
+      for (int i = 0; i < q->T; ++i)
+        for (int j = i; j < q->T; ++j) bgt.push_back(make_int4(gid, i, j, 0));
+      bf_flops += (double)q->M * q->M * h.nV;   // the useful half of 2 M^2 nV
+    } else {
+      gG.add(gd(q->M, q->M, h.nV, q->Xc, q->ldXc, 1, q->Y, q->ldK, 0, q->G, q->MP, 1.0, 0.0, 1));
+    }
   }
   if ((rc = gemm_upload(c, gG, ar))) return rc;
   gemm_run(c, gG, "gram");
+  if (!bgd.empty()) {
+    SplitDesc* d_spd = (SplitDesc*)ar.take(sizeof(SplitDesc) * spd.size());
+    BfGramDesc* d_bgd = (BfGramDesc*)ar.take(sizeof(BfGramDesc) * bgd.size());
+    int4* d_spt = (int4*)ar.take(sizeof(int4) * spt.size());
+    int4* d_bgt = (int4*)ar.take(sizeof(int4) * bgt.size());
+    if (!d_spd || !d_bgd || !d_spt || !d_bgt) return fail(MOR_ENOMEM, "arena exhausted (bf16 gram)");
+    HIPCHK(hipMemcpyAsync(d_spd, spd.data(), sizeof(SplitDesc) * spd.size(), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(d_bgd, bgd.data(), sizeof(BfGramDesc) * bgd.size(), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(d_spt, spt.data(), sizeof(int4) * spt.size(), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(d_bgt, bgt.data(), sizeof(int4) * bgt.size(), hipMemcpyHostToDevice, st));
+    {
+      ScopedTimer tm(c, "gram_split", 0);
+      launch_split_bf16(d_spd, d_spt, (int)spt.size(), st);
+    }
+    {
+      ScopedTimer tm(c, "gram_bf16", bf_flops);
+      launch_gram_bf16(d_bgd, d_bgt, (int)bgt.size(), st);
+    }
+  }
   // ---- S_B = K_BB + K_BI E (Lemma 4.1), padded with the identity
   for (Slot* q : sl) {
     const HostSub& h = *q->h;

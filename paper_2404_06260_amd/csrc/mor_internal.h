@@ -76,6 +76,21 @@ struct DenseSub {
   int* info;           // non-SPD pivot report (0 = fine)
 };
 
+// Split-precision Gram: C = A^T B with A, B (k x m, row-major, FP64) carried as BF16 pairs
+// hi + lo, stored transposed (m_pad x kp, k contiguous, zero padded), so that
+// A^T B ~ Ahi^T Bhi + Ahi^T Blo + Alo^T Bhi on the BF16 matrix cores with FP32 accumulation.
+struct SplitDesc {      // FP64 k x m (row-major, ld) -> BF16 hi/lo transposed mp x kp
+  const double* X; int ldx;
+  int k, m;            // valid rows (contraction index) and columns
+  int kp, mp;          // padded sizes (multiples of 64)
+  uint16_t *hi, *lo;
+};
+struct BfGramDesc {     // symmetric C (m x m, FP64, ldc) = A^T B from split operands
+  int m, kp;
+  const uint16_t *Ahi, *Alo, *Bhi, *Blo;   // mp x kp each
+  double* C; int ldc;
+};
+
 struct TrsmDesc {       // right-hand side and solution of one subdomain's triangular solve
   const double* B; int ldb; int tb;   // tb: read B transposed
   double* X; int ldx;
@@ -129,6 +144,10 @@ void launch_cg_zero(const CgSys* sys, const int2* cb, int ncb, hipStream_t s);
 void launch_cg_start(const CgSys* sys, const int2* cb, int ncb, int first, double tol2_outer, hipStream_t s);
 
 void launch_to_f64_block(const float* in, int ldi, double* out, int ldo, int rows, int cols, hipStream_t s);
+// tiles: (descriptor, 64-row block of m_pad, 64-column block of kp)
+void launch_split_bf16(const SplitDesc* d, const int4* tiles, int ntiles, hipStream_t s);
+// tiles: (descriptor, ti, tj) with ti <= tj, 64 x 64 output blocks
+void launch_gram_bf16(const BfGramDesc* d, const int4* tiles, int ntiles, hipStream_t s);
 void launch_spmm64_rows(const int* rp, const int* col, const double* val, int nrows, int col_limit,
                         const double* X, int ldx, int ncols, double* Y, int ldy, hipStream_t s);
 void launch_gemm(const GemmDesc* d, const int4* tiles, int ntiles, hipStream_t s);

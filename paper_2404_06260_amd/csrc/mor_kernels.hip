@@ -1114,6 +1114,104 @@ void launch_gemm(const GemmDesc* d, const int4* tiles, int ntiles, hipStream_t s
   if (ntiles > 0) hipLaunchKernelGGL(k_gemm, dim3(ntiles), dim3(256), 0, s, d, tiles);
 }
 
+// ------------------------------------------------------------------------ split-precision Gram
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ uint16_t bf16_bits(float x) {
+  const __bf16 b = (__bf16)x;   // round to nearest even
+  return __builtin_bit_cast(uint16_t, b);
+}
+__device__ __forceinline__ float bf16_value(uint16_t u) {
+  return __builtin_bit_cast(float, (uint32_t)u << 16);
+}
+
+// x = hi + lo with hi = bf16(x), lo = bf16(x - hi): a 16-bit significand in two halves.  One
+// workgroup transposes a 64 x 64 block through LDS (reads along m, writes along k).
+__global__ __launch_bounds__(256) void k_split_bf16(const SplitDesc* __restrict__ ds, const int4* __restrict__ tiles) {
+  __shared__ uint16_t hs[64][66], ls[64][66];
+  const int4 tl = tiles[blockIdx.x];
+  const SplitDesc& d = ds[tl.x];
+  const int a0 = tl.y * 64, v0 = tl.z * 64;
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  for (int r = ty; r < 64; r += 4) {
+    const int v = v0 + r, a = a0 + tx;
+    const double x = (v < d.k && a < d.m) ? d.X[(int64_t)v * d.ldx + a] : 0.0;
+    const uint16_t h = bf16_bits((float)x);
+    hs[r][tx] = h;
+    ls[r][tx] = bf16_bits((float)(x - (double)bf16_value(h)));
+  }
+  __syncthreads();
+  for (int r = ty; r < 64; r += 4) {   // output row a0 + r, columns v0 + tx
+    const int64_t o = (int64_t)(a0 + r) * d.kp + v0 + tx;
+    d.hi[o] = hs[tx][r];
+    d.lo[o] = ls[tx][r];
+  }
+}
+void launch_split_bf16(const SplitDesc* d, const int4* tiles, int ntiles, hipStream_t s) {
+  if (ntiles > 0) hipLaunchKernelGGL(k_split_bf16, dim3(ntiles), dim3(256), 0, s, d, tiles);
+}
+
+// C = A^T B on v_mfma_f32_16x16x32_bf16: a workgroup owns a 64 x 64 block of C (ti <= tj),
+// each wave a 32 x 32 quarter (2 x 2 MFMA tiles); per 32-deep k step a lane loads 16 bytes
+// (8 consecutive k) of each operand row it feeds.  Three products per tile (the lo x lo term
+// is below the FP32 accumulation error).  Operand layout (gfx950): lane l feeds row l % 16
+// with k = 8 (l / 16) .. + 7; accumulator element r is row 4 (l / 16) + r, column l % 16.
+__global__ __launch_bounds__(256) void k_gram_bf16(const BfGramDesc* __restrict__ ds, const int4* __restrict__ tiles) {
+  const int4 tl = tiles[blockIdx.x];
+  const BfGramDesc& d = ds[tl.x];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, wr = w >> 1, wc = w & 1;
+  const int i0 = tl.y * 64 + wr * 32, j0 = tl.z * 64 + wc * 32;
+  const int kq = 8 * (lane >> 4), rl = lane & 15;
+  f4 acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = f4{0.f, 0.f, 0.f, 0.f};
+  const int64_t ra0 = (int64_t)(i0 + rl) * d.kp + kq, ra1 = ra0 + (int64_t)16 * d.kp;
+  const int64_t rb0 = (int64_t)(j0 + rl) * d.kp + kq, rb1 = rb0 + (int64_t)16 * d.kp;
+  for (int v0 = 0; v0 < d.kp; v0 += 32) {
+    const bf16x8 ah0 = *(const MOR_GLOBAL bf16x8*)(d.Ahi + ra0 + v0);
+    const bf16x8 ah1 = *(const MOR_GLOBAL bf16x8*)(d.Ahi + ra1 + v0);
+    const bf16x8 al0 = *(const MOR_GLOBAL bf16x8*)(d.Alo + ra0 + v0);
+    const bf16x8 al1 = *(const MOR_GLOBAL bf16x8*)(d.Alo + ra1 + v0);
+    const bf16x8 bh0 = *(const MOR_GLOBAL bf16x8*)(d.Bhi + rb0 + v0);
+    const bf16x8 bh1 = *(const MOR_GLOBAL bf16x8*)(d.Bhi + rb1 + v0);
+    const bf16x8 bl0 = *(const MOR_GLOBAL bf16x8*)(d.Blo + rb0 + v0);
+    const bf16x8 bl1 = *(const MOR_GLOBAL bf16x8*)(d.Blo + rb1 + v0);
+    acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah0, bh0, acc[0][0], 0, 0, 0);
+    acc[0][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah0, bh1, acc[0][1], 0, 0, 0);
+    acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah1, bh0, acc[1][0], 0, 0, 0);
+    acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah1, bh1, acc[1][1], 0, 0, 0);
+    acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah0, bl0, acc[0][0], 0, 0, 0);
+    acc[0][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah0, bl1, acc[0][1], 0, 0, 0);
+    acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah1, bl0, acc[1][0], 0, 0, 0);
+    acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah1, bl1, acc[1][1], 0, 0, 0);
+    acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al0, bh0, acc[0][0], 0, 0, 0);
+    acc[0][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al0, bh1, acc[0][1], 0, 0, 0);
+    acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al1, bh0, acc[1][0], 0, 0, 0);
+    acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al1, bh1, acc[1][1], 0, 0, 0);
+  }
+  const bool diag = tl.y == tl.z;
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = i0 + a * 16 + 4 * (lane >> 4) + r;
+        const int j = j0 + b * 16 + rl;
+        if (i < d.m && j < d.m && (!diag || i <= j)) {
+          const double v = (double)acc[a][b][r];
+          d.C[(int64_t)i * d.ldc + j] = v;
+          d.C[(int64_t)j * d.ldc + i] = v;
+        }
+      }
+}
+void launch_gram_bf16(const BfGramDesc* d, const int4* tiles, int ntiles, hipStream_t s) {
+  if (ntiles > 0) hipLaunchKernelGGL(k_gram_bf16, dim3(ntiles), dim3(256), 0, s, d, tiles);
+}
+
 // --------------------------------------------------------------------------------- Cholesky
 // Right-looking blocked Cholesky S = R^T R (R upper) of every subdomain's padded S_B.
 __global__ __launch_bounds__(256) void k_potrf_diag(const DenseSub* __restrict__ ds, int p) {

@@ -1,7 +1,10 @@
 """Write the FP64 oracle's results for a named workload to tests/golden/<name>_oracle.npz.
 
 Calls only `oracle/` (and the seeded input generators); the GPU tests compare the HIP path's
-full-size output with this file.  Usage: python tests/golden/make_oracle_reference.py C2 [workers]
+full-size output with this file.  Usage:
+    python tests/golden/make_oracle_reference.py C2 [workers] [--no-fe]
+--no-fe skips the full FE solve (a sparse direct factorisation of the global matrix, out of
+reach for the larger meshes); the file then holds the reduced solution only.
 """
 import os
 import sys
@@ -17,12 +20,14 @@ from oracle import solve  # noqa: E402
 
 
 def main():
-    name = sys.argv[1] if len(sys.argv) > 1 else "C2"
-    workers = int(sys.argv[2]) if len(sys.argv) > 2 else (os.cpu_count() or 1)
+    args = [a for a in sys.argv[1:] if not a.startswith("--")]
+    with_fe = "--no-fe" not in sys.argv
+    name = args[0] if args else "C2"
+    workers = int(args[1]) if len(args) > 1 else (os.cpu_count() or 1)
     os.environ.setdefault("OMP_NUM_THREADS", "1")
     p = w.make_config(name)
     t0 = time.time()
-    out = solve.run(p, workers=workers, with_fe=True)
+    out = solve.run(p, workers=workers, with_fe=with_fe)
     res = out["results"]
     kmax = max(r.k_eff for r in res) + 1
     sig = np.zeros((len(res), kmax + 8))
@@ -30,11 +35,11 @@ def main():
         n = min(sig.shape[1], r.sigma.size)
         sig[i, :n] = r.sigma[:n]
     path = os.path.join(os.path.dirname(os.path.abspath(__file__)), f"{name}_oracle.npz")
-    np.savez_compressed(path, u_tilde=out["u_tilde"], u_fe=out["u_fe"], x=out["x"], bt=out["bt"],
-                        k_eff=np.array([r.k_eff for r in res]), sigma=sig, red_err=out["red_err"],
-                        u_energy=out["u_energy"])
-    print(f"{name}: {len(res)} subdomains, reduced dim {out['x'].size}, relative reduction error "
-          f"{out['red_err'] / out['u_energy']:.3e}, {time.time() - t0:.0f} s -> {path}")
+    extra = dict(u_fe=out["u_fe"], red_err=out["red_err"], u_energy=out["u_energy"]) if with_fe else {}
+    np.savez_compressed(path, u_tilde=out["u_tilde"], x=out["x"], bt=out["bt"],
+                        k_eff=np.array([r.k_eff for r in res]), sigma=sig, **extra)
+    msg = f", relative reduction error {out['red_err'] / out['u_energy']:.3e}" if with_fe else ""
+    print(f"{name}: {len(res)} subdomains, reduced dim {out['x'].size}{msg}, {time.time() - t0:.0f} s -> {path}")
 
 
 if __name__ == "__main__":

@@ -7,7 +7,8 @@ and is compared with the oracle on the same seeded inputs:
   - leading singular values of the weighted lifting operator,
   - q_0 and the span of the lifting modes (largest principal angle in the K_i inner product),
   - the reduced solution: relative energy-norm difference ||u~_gpu - u~_orc||_A / ||u~_orc||_A,
-    within 1e-6 for the FP32 paths (the stated tolerance) and 1e-9 for FP64.
+    within 1e-6 for the refined FP32 path (the stated tolerance), 1e-9 for FP64, 1e-4 for FP32
+    without refinement, and 1e-3 (the stated bound for a BF16 Gram) for the BF16 split Gram.
 """
 import sys
 
@@ -21,9 +22,10 @@ from oracle import solve as osolve
 
 pytestmark = pytest.mark.gpu
 
-TOL_ENERGY = {"fp64": 1e-9, "fp32_refine": 1e-6, "fp32": 1e-4}   # fp32: CG to 1e-5, no FP64 refinement
-TOL_SIGMA = {"fp64": 1e-9, "fp32_refine": 1e-7, "fp32": 1e-4}
-TOL_ANGLE = {"fp64": 1e-7, "fp32_refine": 1e-5, "fp32": 1e-2}
+# fp32: CG to 1e-5, no FP64 refinement; bf16_split: the stated bound for a BF16 Gram (1e-3)
+TOL_ENERGY = {"fp64": 1e-9, "fp32_refine": 1e-6, "fp32": 1e-4, "bf16_split": 1e-3}
+TOL_SIGMA = {"fp64": 1e-9, "fp32_refine": 1e-7, "fp32": 1e-4, "bf16_split": 1e-5}
+TOL_ANGLE = {"fp64": 1e-7, "fp32_refine": 1e-5, "fp32": 1e-2, "bf16_split": 1e-4}
 
 _CACHE = {}
 
@@ -82,7 +84,7 @@ def _run_gpu(p, precision, **kw):
 
 
 @pytest.mark.parametrize("name", ["C1", "small-lognormal", "uneven-jitter"])
-@pytest.mark.parametrize("precision", ["fp64", "fp32_refine", "fp32"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32_refine", "fp32", "bf16_split"])
 def test_parity_whole_path(name, precision):
     from paper_2404_06260_amd import mor
     p = _problem(name)
