@@ -24,7 +24,7 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 
 CONFIG_DEFAULT = "C2"
-PRECISION_OF = {"C1": "fp64", "C2": "fp32_refine", "C3": "fp32_refine", "C4": "fp32_refine", "C5": "fp32_refine"}
+PRECISION_OF = {"C1": "fp64", "C2": "fp32_refine", "C3": "fp32_refine", "C4": "bf16_split", "C5": "fp32_refine"}
 WORKLOAD_OF = {
     "C1": "16^3 Kuhn cube, kappa=1, 2x2x2 boxes, r=1, k=8",
     "C2": "48^3 Kuhn cube (117,649 nodes), lognormal kappa sigma=1, 4x4x4 boxes, r=6, k=16",
@@ -61,23 +61,67 @@ def cpu_baseline(problem, budget_s: float = 20.0):
 PROFILE = os.path.join(ROOT, "profiles", "k_cg_spmm_halo_48cube_lognormal_fp32refine.md")
 
 
+def kernel_source_hash(name: str) -> str:
+    """sha256 (16 hex digits) of one kernel's source text in mor_kernels.hip: from its
+    `template` line to the closing brace at column 0."""
+    import hashlib
+    lines = open(os.path.join(ROOT, "paper_2404_06260_amd", "csrc", "mor_kernels.hip")).read().split("\n")
+    for i, ln in enumerate(lines):
+        if f"void {name}(" in ln and "__global__" in ln:
+            b = i - 1 if i > 0 and lines[i - 1].startswith("template") else i
+            e = next(j for j in range(i, len(lines)) if lines[j] == "}")
+            return hashlib.sha256("\n".join(lines[b:e + 1]).encode()).hexdigest()[:16]
+    return ""
+
+
 def profiled_traffic(kernel: str, config: str):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 summary (calibrated
-    FETCH_SIZE + WRITE_SIZE), or None when the summary covers another workload or the kernel
+    FETCH_SIZE + WRITE_SIZE), or None when the summary covers another workload or the kernel's
     source has changed since the counters were taken."""
-    import hashlib
     import re
     if config != "C2" or not os.path.exists(PROFILE):
         return None
     txt = open(PROFILE).read()
-    m = re.search(r"sha256 ([0-9a-f]{16})", txt)
-    src = os.path.join(ROOT, "paper_2404_06260_amd", "csrc", "mor_kernels.hip")
-    if not m or hashlib.sha256(open(src, "rb").read()).hexdigest()[:16] != m.group(1):
+    base = kernel.split("<")[0]
+    m = re.search(base + r" source sha256 ([0-9a-f]{16})", txt)
+    if not m or kernel_source_hash(base) != m.group(1):
         return None
     row = re.search(r"\| `mor::" + re.escape(kernel) + r"` \|[^|]*\|[^|]*\|[^|]*\| ([0-9.]+) \| ([0-9.]+) \|", txt)
     if not row:
         return None
     return round((float(row.group(1)) + float(row.group(2))) * 1e9)
+
+
+def comparator_leg(problem, steps: int):
+    """The plain FP64 per-subdomain GPU path: FP64 block CG (to the refined path's residual
+    target), FP64 Gram and eigensolve, one subdomain per call, no batching; same projection and
+    reduced solve.  Returns its reductions/s and the reduced energy x.b~ for comparison."""
+    import numpy as np
+    import torch
+    from paper_2404_06260_amd import mor
+    m = mor.Mor(problem, precision="fp64")
+    n = problem.subdomains.n_sub
+    ranks = problem.ranks if problem.ranks is not None else np.full(n, problem.rank)
+    try:
+        for i in range(n):                      # warm-up: one subdomain
+            mor.mor_local_basis(m.ctx, i, int(ranks[i]))
+            break
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            for i in range(n):
+                mor.mor_local_basis(m.ctx, i, int(ranks[i]))
+            m.project()
+            m.solve()
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        At, bt = mor.mor_get_reduced(m.ctx)
+        x = mor.mor_get_reduced_solution(m.ctx, At.shape[0])
+        return dict(value=round(n * steps / el, 4), unit="subdomain reductions/s", ms_per_step=round(1e3 * el / steps, 2),
+                    path="plain FP64 block CG (residual 1e-8) + FP64 Gram/eigen, one subdomain per call",
+                    energy=float(x @ bt))
+    finally:
+        m.close()
 
 
 def serving_leg(m, problem, n_req: int, load: float):
@@ -108,6 +152,8 @@ def main():
     ap.add_argument("--spmm-rows", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
+    ap.add_argument("--no-comparator", action="store_true",
+                    help="skip the plain FP64 one-subdomain-at-a-time comparator leg")
     ap.add_argument("--serve-requests", type=int, default=-1,
                     help="requests in the serving leg (-1: one per subdomain, 0: no serving leg)")
     ap.add_argument("--serve-load", type=float, default=0.9,
@@ -176,16 +222,35 @@ def main():
     bytes_per_launch = spmm_bytes / max(n_launch, 1)
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
     kernels = {}
-    for name in ("spmm", "cg_update", "cg_direction", "residual64", "assemble", "gram", "schur", "potrf", "trsm",
-                 "eig", "basis", "project_local", "project", "solve"):
+    for name in ("spmm", "cg_update", "cg_direction", "residual64", "assemble", "gram", "gram_split", "gram_bf16",
+                 "schur", "potrf", "trsm", "eig", "basis", "project_local", "project", "solve"):
         n, ms, wk = mor.mor_timing_get(m.ctx, name)
         if n:
             kernels[name] = dict(launches=n, ms_per_step=round(ms / args.steps, 3))
     stats = [mor.mor_get_stats(m.ctx, i) for i in range(n_sub)]
+    At_b, bt_b = mor.mor_get_reduced(m.ctx)
+    energy_b = float(mor.mor_get_reduced_solution(m.ctx, At_b.shape[0]) @ bt_b)
+    # the dense contraction of the Gram G1 = X_C^T K_i X_C on the matrix cores
+    mfma = None
+    n_g, ms_g, fl_g = mor.mor_timing_get(m.ctx, "gram_bf16")
+    peak, kname = 2500.0, "k_gram_bf16 (BF16 hi/lo split, 3 products)"
+    if not n_g:
+        n_g, ms_g, fl_g = mor.mor_timing_get(m.ctx, "gram")
+        peak, kname = 78.6, "k_gemm (FP64 MFMA)"
+    if n_g and ms_g > 0:
+        tf = fl_g / (ms_g * 1e-3) / 1e12
+        mfma = {"bound": "mfma", "kernel": kname, "achieved": round(tf, 2), "peak": peak, "unit": "TFLOP/s",
+                "frac": round(tf / peak, 4), "flops_per_step": fl_g / args.steps}
     serving = None
     if args.serve_requests != 0:
         serving = serving_leg(m, p, n_sub if args.serve_requests < 0 else args.serve_requests, args.serve_load)
     m.close()
+    comparator = None
+    if not args.no_comparator and prec != "fp64":
+        print("[bench] comparator: plain FP64 per-subdomain path", file=sys.stderr, flush=True)
+        comparator = comparator_leg(p, 1)
+        comparator["speedup_of_value"] = round(n_sub * args.steps / el / comparator["value"], 3)
+        comparator["energy_rel_diff"] = abs(comparator.pop("energy") - energy_b) / abs(energy_b)
     cpu = None
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
@@ -201,7 +266,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"fp64": "f64", "fp32_refine": "f32+f64", "fp32": "f32", "bf16_split": "bf16+f32"}[prec],
+        "dtype": {"fp64": "f64", "fp32_refine": "f32+f64", "fp32": "f32", "bf16_split": "f32+f64+bf16"}[prec],
         "data": "synthetic",
         "config": {"workload": WORKLOAD_OF[args.config], "name": args.config, "subdomains": n_sub,
                    "precision": prec, "reduced_dim": int(nred),
@@ -215,6 +280,8 @@ def main():
                      "algorithmic_bytes_per_launch": round(bytes_per_launch)},
         "cpu_baseline": cpu,
         "serving": serving,
+        "comparator": comparator,
+        "mfma": mfma,
         "kernels": kernels,
         "cg_iters_max": [max(s["cg_iter_a"] for s in stats), max(s["cg_iter_k"] for s in stats)],
         "eig_iters_max": max(s["eig_iter"] for s in stats),

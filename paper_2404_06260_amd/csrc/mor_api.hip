@@ -1136,7 +1136,7 @@ static int dense_stage(mor_ctx* c, std::vector<Live*>& done) {
       bgd.push_back(BfGramDesc{q->M, q->kpV, q->Xh, q->Xl, q->Yh, q->Yl, q->G, q->MP});
       for (int i = 0; i < q->T; ++i)
         for (int j = i; j < q->T; ++j) bgt.push_back(make_int4(gid, i, j, 0));
-      bf_flops += (double)q->M * q->M * h.nV;   // the useful half of 2 M^2 nV
+      bf_flops += 3.0 * q->M * q->M * h.nV;   // three BF16 products over the symmetric half
     } else {
       gG.add(gd(q->M, q->M, h.nV, q->Xc, q->ldXc, 1, q->Y, q->ldK, 0, q->G, q->MP, 1.0, 0.0, 1));
     }
