@@ -152,6 +152,8 @@ def main():
     ap.add_argument("--spmm-rows", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
+    ap.add_argument("--graph", type=int, default=-1,
+                    help="capture each CG chunk in a HIP graph (1) or launch eagerly (0); -1: graphs for C3")
     ap.add_argument("--no-comparator", action="store_true",
                     help="skip the plain FP64 one-subdomain-at-a-time comparator leg")
     ap.add_argument("--serve-requests", type=int, default=-1,
@@ -183,7 +185,8 @@ def main():
             print(f"[bench] autotuned tiles: {tile}", file=sys.stderr, flush=True)
     else:
         tile = dict(spmm_rows=args.spmm_rows)
-    m = mor.Mor(p, precision=prec, **tile)
+    use_graph = (args.config == "C3") if args.graph < 0 else bool(args.graph)
+    m = mor.Mor(p, precision=prec, use_graph=int(use_graph), **tile)
     halo = tile.get("spmm_kind", 0) != 2
     spmm_cap = max([c for c in (48, 64, 96, 128, 176) if c <= tile.get("spmm_rows", 0)] or [64]) if halo else 0
     elt = "double" if prec == "fp64" else "float"
@@ -218,11 +221,14 @@ def main():
     el = t1 - t0
     ms_per_step = 1e3 * el / args.steps
     n_launch, spmm_ms, spmm_bytes = mor.mor_timing_get(m.ctx, "spmm")
+    if use_graph:   # per-kernel events do not exist inside a graph: the whole chunk is the unit
+        n_launch, spmm_ms, spmm_bytes = mor.mor_timing_get(m.ctx, "cg_graph")
+        spmm_kernel = "CG chunk graph: SpMM + alpha + update + beta + direction"
     avg_ms = spmm_ms / max(n_launch, 1)
     bytes_per_launch = spmm_bytes / max(n_launch, 1)
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
     kernels = {}
-    for name in ("spmm", "cg_update", "cg_direction", "residual64", "assemble", "gram", "gram_split", "gram_bf16",
+    for name in ("spmm", "cg_update", "cg_direction", "cg_graph", "residual64", "assemble", "gram", "gram_split", "gram_bf16",
                  "schur", "potrf", "trsm", "eig", "basis", "project_local", "project", "solve"):
         n, ms, wk = mor.mor_timing_get(m.ctx, name)
         if n:
@@ -269,12 +275,14 @@ def main():
         "dtype": {"fp64": "f64", "fp32_refine": "f32+f64", "fp32": "f32", "bf16_split": "f32+f64+bf16"}[prec],
         "data": "synthetic",
         "config": {"workload": WORKLOAD_OF[args.config], "name": args.config, "subdomains": n_sub,
-                   "precision": prec, "reduced_dim": int(nred),
+                   "precision": prec, "reduced_dim": int(nred), "hip_graph": use_graph,
                    "tiles": tile or "library defaults"},
-        "roofline": {"bound": "hbm", "kernel": f"{spmm_kernel} (block-CG SpMM Q = A_II P)",
+        "roofline": {"bound": "hbm",
+                     "kernel": spmm_kernel if use_graph else f"{spmm_kernel} (block-CG SpMM Q = A_II P)",
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": profiled_traffic(spmm_kernel, args.config) if spmm_cap == 64 else None,
+                     "traffic": (profiled_traffic(spmm_kernel, args.config) if spmm_cap == 64 and not use_graph
+                                 else None),
                      "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, calibrated)",
                      "avg_launch_ms": round(avg_ms, 4), "launches": n_launch,
                      "algorithmic_bytes_per_launch": round(bytes_per_launch)},

@@ -58,6 +58,7 @@ def tune(problem, precision="fp32_refine", sub_ids=None, verbose=True, save=True
     cg_prec = "fp64" if precision == "fp64" else "fp32"
     ids = np.arange(problem.subdomains.n_sub) if sub_ids is None else np.asarray(sub_ids)
     sp_res = []
+    _run(problem, ids, cg_prec, {})   # warm-up: module load and first-touch allocations
     for kind, v, rb in CANDIDATES:
         if cg_prec == "fp64" and kind == 2 and v > 2:
             continue

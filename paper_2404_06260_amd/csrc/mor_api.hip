@@ -655,6 +655,7 @@ struct Launch {
   int2* cb = nullptr;
   int ncb = 0;
   double spmm_bytes = 0;
+  double stream_bytes = 0;   // update + direction: 8 block-vector elements per entry
 };
 
 struct MorEngine {
@@ -669,6 +670,11 @@ struct MorEngine {
   std::vector<CgSys> up_hs;   // the systems of the last upload (its device lists)
   Launch up_L;
   bool up_ok = false;
+  // graph mode: the CG chunk captured once per system set and replayed
+  hipStream_t cap_st = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  std::vector<SysRun*> g_sys;
+  std::vector<int64_t> g_key;
   int2* d_cb = nullptr;
   size_t cb_cap = 0;
   int* d_cnt = nullptr;
@@ -721,6 +727,10 @@ static void engine_free(mor_ctx* c, MorEngine& e) {
   dfree(c, e.d_cb);
   if (e.h_cnt) (void)hipHostFree(e.h_cnt);
   e.h_cnt = nullptr;
+  if (e.gexec) (void)hipGraphExecDestroy(e.gexec);
+  e.gexec = nullptr;
+  if (e.cap_st) (void)hipStreamDestroy(e.cap_st);
+  e.cap_st = nullptr;
 }
 
 template <typename T>
@@ -748,6 +758,8 @@ static int engine_upload(mor_ctx* c, MorEngine& e, Launch& L) {
   }
   e.up_ok = false;
   L.spmm_bytes = 0;
+  L.stream_bytes = 0;
+  for (int i = 0; i < n; ++i) L.stream_bytes += 8.0 * e.elt * (double)hs[i].nI * hs[i].ncols;
   for (int i = 0; i < n; ++i) {
     const CgSys& S = hs[i];
     L.spmm_bytes += (double)L.sys[i]->nnzII * (4.0 + e.elt) + 4.0 * (S.nI + 1) + 2.0 * e.elt * (double)S.nI * S.ncols;
@@ -934,7 +946,48 @@ static int engine_chunk(mor_ctx* c, MorEngine& e) {
   const double inner = fp64 ? c->opts.refine_rtol : c->opts.cg_rtol;
   const double tol2 = inner * inner;
   const int chunk = std::max(1, c->opts.cg_chunk);
-  for (int k = 0; k < chunk; ++k) {
+  // one CG iteration over every admitted system: Q = A P and p'Q, alpha, R -= alpha Q with
+  // r'M^-1 r, beta and convergence, X += alpha P and P = M^-1 R + beta P
+  auto iteration = [&](hipStream_t s) {
+    if (e.sp.halo)
+      launch_cg_spmm_halo<T>(e.d_sys, La.hs, La.nhs, c->halo_cap, s);
+    else
+      launch_cg_spmm<T>(e.d_sys, La.sp, La.nsp, e.sp.rb, e.sp.v, s);
+    launch_cg_alpha(e.d_sys, La.cb, La.ncb, s);
+    launch_cg_update<T>(e.d_sys, La.bk, La.nbk, e.stm.rb, e.stm.v, s);
+    launch_cg_beta(e.d_sys, La.cb, La.ncb, tol2, s);
+    launch_cg_direction<T>(e.d_sys, La.bk, La.nbk, e.stm.rb, e.stm.v, s);
+  };
+  if (c->opts.use_graph) {
+    // The chunk as one HIP graph, captured on a private stream and launched on the library's
+    // stream.  Its kernel arguments are the device lists of the last upload, which stay in
+    // place (and are re-uploaded identically) while the set of systems is unchanged; any
+    // change of systems, list addresses or sizes captures a new graph.
+    const std::vector<int64_t> key = {(int64_t)(intptr_t)e.d_sys, (int64_t)(intptr_t)e.d_tiles,
+                                      (int64_t)(intptr_t)e.d_cb, La.nsp, La.nbk, La.nhs, La.ncb, chunk,
+                                      (int64_t)(intptr_t)La.hs, (int64_t)(intptr_t)La.bk, (int64_t)(intptr_t)La.cb,
+                                      (int64_t)c->halo_cap};
+    if (!e.gexec || e.g_sys != La.sys || e.g_key != key) {
+      if (e.gexec) HIPCHK(hipGraphExecDestroy(e.gexec));
+      e.gexec = nullptr;
+      if (!e.cap_st) HIPCHK(hipStreamCreateWithFlags(&e.cap_st, hipStreamNonBlocking));
+      hipGraph_t g = nullptr;
+      HIPCHK(hipStreamBeginCapture(e.cap_st, hipStreamCaptureModeThreadLocal));
+      for (int k = 0; k < chunk; ++k) iteration(e.cap_st);
+      HIPCHK(hipStreamEndCapture(e.cap_st, &g));
+      const hipError_t ie = hipGraphInstantiate(&e.gexec, g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      if (ie != hipSuccess) {
+        e.gexec = nullptr;
+        return fail(MOR_EDEVICE, std::string("graph instantiation failed: ") + hipGetErrorString(ie));
+      }
+      e.g_sys = La.sys;
+      e.g_key = key;
+    }
+    ScopedTimer tm(c, "cg_graph", chunk * (La.spmm_bytes + La.stream_bytes));
+    HIPCHK(hipGraphLaunch(e.gexec, st));
+  }
+  for (int k = 0; k < (c->opts.use_graph ? 0 : chunk); ++k) {
     {
       ScopedTimer tm(c, "spmm", La.spmm_bytes);
       if (e.sp.halo)

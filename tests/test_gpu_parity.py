@@ -134,3 +134,28 @@ def test_reduced_system_invariants():
         np.testing.assert_allclose(x @ bt, ref["x"] @ ref["bt"], rtol=1e-9)
     finally:
         m.close()
+
+
+@pytest.mark.parametrize("name", ["uneven-jitter", "small-lognormal"])
+def test_graph_mode_matches_oracle_and_eager(name):
+    """Every CG chunk captured once in a HIP graph and replayed (with the engine's own host
+    work and synchronisations between replays): the result matches the oracle at the FP32
+    tolerance and the eager launch sequence to rounding."""
+    from paper_2404_06260_amd import mor
+    p = _problem(name)
+    ref = _oracle(name, p)
+    g = _run_gpu(p, "fp32_refine", use_graph=1, cg_chunk=4)
+    e = _run_gpu(p, "fp32_refine", use_graph=0, cg_chunk=4)
+    try:
+        np.testing.assert_array_equal(g["k"], e["k"])
+        for i in range(p.subdomains.n_sub):
+            np.testing.assert_allclose(mor.mor_get_sigma(g["ctx"].ctx, i), mor.mor_get_sigma(e["ctx"].ctx, i),
+                                       rtol=1e-9)
+        rel = _energy_rel(ref, g["u"])
+        _say(f"[gpu] {name} graph: energy rel {rel:.3e}")
+        assert rel < TOL_ENERGY["fp32_refine"], rel
+        d = g["u"] - e["u"]
+        assert np.abs(d).max() <= 1e-8 * np.abs(e["u"]).max()
+    finally:
+        g["ctx"].close()
+        e["ctx"].close()
