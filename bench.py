@@ -124,19 +124,28 @@ def comparator_leg(problem, steps: int):
         m.close()
 
 
-def serving_leg(m, problem, n_req: int, load: float):
+def serving_leg(m, problem, n_req: int, load: float, rate: float = 0.0, precisions=("fp32_refine",),
+                on_done=None):
     """Continuous-batching serving on the same context: the saturation rate (all requests
-    queued at t = 0), then a Poisson stream at `load` times that rate; latency = completion
-    seen - arrival."""
+    queued at t = 0), then a Poisson stream at `load` times that rate (or at `rate` req/s when
+    given, without the saturation run); latency = completion seen - arrival."""
     from paper_2404_06260_amd import serve
-    sat = serve.run_stream(m.ctx, serve.make_stream(problem, n_req, float("inf"), seed_order=12))
-    rate = load * sat.throughput
-    print(f"[bench] serving: saturation {sat.throughput:.2f} req/s, stream at {rate:.2f} req/s", file=sys.stderr,
-          flush=True)
-    res = serve.run_stream(m.ctx, serve.make_stream(problem, n_req, rate, seed_arrivals=7, seed_order=11))
+    pp = tuple(1.0 / len(precisions) for _ in precisions)
+    sat_tp = None
+    if rate <= 0:
+        sat = serve.run_stream(m.ctx, serve.make_stream(problem, n_req, float("inf"), seed_order=12,
+                                                       precisions=precisions, precision_p=pp), on_done=on_done)
+        sat_tp = sat.throughput
+        rate = load * sat_tp
+        print(f"[bench] serving: saturation {sat_tp:.2f} req/s, stream at {rate:.2f} req/s", file=sys.stderr,
+              flush=True)
+    res = serve.run_stream(m.ctx, serve.make_stream(problem, n_req, rate, seed_arrivals=7, seed_order=11,
+                                                    precisions=precisions, precision_p=pp), on_done=on_done)
     pc = res.percentiles((50, 99))
     return {"requests": n_req, "arrivals": "poisson", "rate_per_s": round(rate, 3),
-            "load_vs_saturation": load, "saturation_per_s": round(sat.throughput, 3),
+            "precisions": list(precisions),
+            "load_vs_saturation": load if sat_tp else None,
+            "saturation_per_s": round(sat_tp, 3) if sat_tp else None,
             "throughput_per_s": round(res.throughput, 3), "p50_ms": round(pc["p50"] * 1e3, 1),
             "p99_ms": round(pc["p99"] * 1e3, 1), "max_live": res.max_live, "peak_bytes": res.peak_bytes,
             "budget_bytes": res.budget_bytes, "failed": int((res.status != 0).sum())}
@@ -158,6 +167,8 @@ def main():
                     help="skip the plain FP64 one-subdomain-at-a-time comparator leg")
     ap.add_argument("--serve-requests", type=int, default=-1,
                     help="requests in the serving leg (-1: one per subdomain, 0: no serving leg)")
+    ap.add_argument("--serve-rate", type=float, default=0.0,
+                    help="absolute Poisson arrival rate (req/s) of the serving leg; 0: a fraction of saturation")
     ap.add_argument("--serve-load", type=float, default=0.9,
                     help="Poisson arrival rate of the serving leg as a fraction of the measured saturation rate")
     ap.add_argument("--calibrate-copy", type=int, default=0,
@@ -194,8 +205,22 @@ def main():
                    f"k_cg_spmm<{elt}, {tile.get('spmm_vec', 4)}>")
     n_sub = p.subdomains.n_sub
 
+    stream_step = args.config == "C5"   # minutes per step: drive it from the serving loop with progress
+    precs_c5 = ("fp32_refine", "bf16_split")
+
+    def progress(j, n_done, t):
+        print(f"[bench] {n_done}/{n_sub} subdomains reduced ({t:.0f} s)", file=sys.stderr, flush=True)
+
     def step():
-        m.local_basis_all()
+        if stream_step:
+            from paper_2404_06260_amd import serve
+            st = serve.make_stream(p, n_sub, float("inf"), seed_order=12, precisions=precs_c5,
+                                   precision_p=(0.5, 0.5))
+            res = serve.run_stream(m.ctx, st, on_done=progress)
+            if (res.status != 0).any():
+                raise RuntimeError(f"{int((res.status != 0).sum())} requests failed")
+        else:
+            m.local_basis_all()
         m.project()
         return m.solve()
 
@@ -249,7 +274,9 @@ def main():
                 "frac": round(tf / peak, 4), "flops_per_step": fl_g / args.steps}
     serving = None
     if args.serve_requests != 0:
-        serving = serving_leg(m, p, n_sub if args.serve_requests < 0 else args.serve_requests, args.serve_load)
+        serving = serving_leg(m, p, n_sub if args.serve_requests < 0 else args.serve_requests, args.serve_load,
+                              rate=args.serve_rate, precisions=precs_c5 if stream_step else ("fp32_refine",),
+                              on_done=progress if stream_step else None)
     m.close()
     comparator = None
     if not args.no_comparator and prec != "fp64":
@@ -272,10 +299,12 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"fp64": "f64", "fp32_refine": "f32+f64", "fp32": "f32", "bf16_split": "f32+f64+bf16"}[prec],
+        "dtype": "f32+f64+bf16" if stream_step else {"fp64": "f64", "fp32_refine": "f32+f64", "fp32": "f32",
+                                                      "bf16_split": "f32+f64+bf16"}[prec],
         "data": "synthetic",
         "config": {"workload": WORKLOAD_OF[args.config], "name": args.config, "subdomains": n_sub,
-                   "precision": prec, "reduced_dim": int(nred), "hip_graph": use_graph,
+                   "precision": "fp32_refine | bf16_split, p = 1/2 each" if stream_step else prec,
+                   "reduced_dim": int(nred), "hip_graph": use_graph,
                    "tiles": tile or "library defaults"},
         "roofline": {"bound": "hbm",
                      "kernel": spmm_kernel if use_graph else f"{spmm_kernel} (block-CG SpMM Q = A_II P)",

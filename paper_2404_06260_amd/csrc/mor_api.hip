@@ -549,8 +549,9 @@ static void slot_shape(mor_ctx* c, Slot& q) {
   int s = q.rank > 0 ? std::min(64, q.rank + p) : 64;
   s = std::min(s, q.M);
   q.s = s;
-  q.nconv = q.rank > 0 ? std::min(s - 1, q.rank + std::max(2, p / 2)) : s - 1;
-  if (q.nconv < 1) q.nconv = std::min(1, s);
+  // the fewest Ritz pairs that must converge; the eigensolver raises it to the truncation
+  // decision (kept pairs + the next + one) as the Ritz values settle
+  q.nconv = std::max(1, std::min(s - 1, q.rank > 0 ? q.rank + 2 : 1));
   q.fp32 = q.prec != MOR_FP64;
   q.refine = q.prec == MOR_FP32_REFINE || q.prec == MOR_BF16_SPLIT;
 }
@@ -1360,11 +1361,18 @@ static int dense_stage(mor_ctx* c, std::vector<Live*>& done) {
       HIPCHK(hipMemcpyAsync(&hres[(size_t)i * 64], sl[i]->resid, 8 * sl[i]->s, hipMemcpyDeviceToHost, st));
     }
     HIPCHK(hipStreamSynchronize(st));
+    // Converged when every Ritz pair the truncation decision reads is accurate: the kept
+    // ones and the next (the cluster/gap test), plus one, as judged on the current Ritz
+    // values; a cluster that grows the decision grows the requirement.
     converged = true;
     for (int i = 0; i < ns && converged; ++i) {
       if (done[i]->status) continue;
+      Slot& q = *sl[i];
       const double t0 = std::max(hth[(size_t)i * 64], 1e-300);
-      for (int j = 0; j < sl[i]->nconv; ++j)
+      std::vector<double> sg(q.s);
+      for (int j = 0; j < q.s; ++j) sg[j] = std::sqrt(std::max(hth[(size_t)i * 64 + j], 0.0));
+      const int need = std::min(q.s - 1, std::max(q.nconv, truncation_rank(sg, q.rank, q.tol, q.s - 1) + 2));
+      for (int j = 0; j < need; ++j)
         if (!(std::sqrt(std::max(hres[(size_t)i * 64 + j], 0.0)) <= c->opts.eig_rtol * t0)) {
           converged = false;
           break;

@@ -76,10 +76,11 @@ def make_stream(problem, n_requests: int, rate: float, seed_arrivals: int = 7, s
 
 
 def run_stream(ctx, stream: Stream, clock=time.perf_counter, sleep=time.sleep, api=None,
-               max_steps: int = 10_000_000) -> StreamResult:
+               max_steps: int = 10_000_000, on_done=None) -> StreamResult:
     """Replay `stream` against an engine context in real time (see the module docstring).
     `api` (default: the library binding) must provide mor_submit, mor_step, mor_poll and
-    mor_engine_stats with the binding's signatures."""
+    mor_engine_stats with the binding's signatures; `on_done(j, n_done, t)` is called for each
+    completion."""
     api = api or _mor
     n = len(stream)
     lat = np.full(n, np.nan)
@@ -117,6 +118,8 @@ def run_stream(ctx, stream: Stream, clock=time.perf_counter, sleep=time.sleep, a
                 fin[j] = now
                 status[j] = s
                 done += 1
+                if on_done is not None:
+                    on_done(j, done, now)
     st = api.mor_engine_stats(ctx)
     makespan = float(np.nanmax(fin) - stream.arrivals[0]) if n else 0.0
     return StreamResult(latency=lat, status=status, finish=fin, makespan=makespan, steps=steps,
