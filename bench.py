@@ -125,7 +125,7 @@ def comparator_leg(problem, steps: int):
 
 
 def serving_leg(m, problem, n_req: int, load: float, rate: float = 0.0, precisions=("fp32_refine",),
-                on_done=None):
+                on_done=None, saturation=None):
     """Continuous-batching serving on the same context: the saturation rate (all requests
     queued at t = 0), then a Poisson stream at `load` times that rate (or at `rate` req/s when
     given, without the saturation run); latency = completion seen - arrival."""
@@ -139,12 +139,14 @@ def serving_leg(m, problem, n_req: int, load: float, rate: float = 0.0, precisio
         rate = load * sat_tp
         print(f"[bench] serving: saturation {sat_tp:.2f} req/s, stream at {rate:.2f} req/s", file=sys.stderr,
               flush=True)
+    else:
+        sat_tp = saturation
     res = serve.run_stream(m.ctx, serve.make_stream(problem, n_req, rate, seed_arrivals=7, seed_order=11,
                                                     precisions=precisions, precision_p=pp), on_done=on_done)
     pc = res.percentiles((50, 99))
     return {"requests": n_req, "arrivals": "poisson", "rate_per_s": round(rate, 3),
             "precisions": list(precisions),
-            "load_vs_saturation": load if sat_tp else None,
+            "load_vs_saturation": round(rate / sat_tp, 3) if sat_tp else None,
             "saturation_per_s": round(sat_tp, 3) if sat_tp else None,
             "throughput_per_s": round(res.throughput, 3), "p50_ms": round(pc["p50"] * 1e3, 1),
             "p99_ms": round(pc["p99"] * 1e3, 1), "max_live": res.max_live, "peak_bytes": res.peak_bytes,
@@ -274,9 +276,13 @@ def main():
                 "frac": round(tf / peak, 4), "flops_per_step": fl_g / args.steps}
     serving = None
     if args.serve_requests != 0:
+        rate, sat = args.serve_rate, None
+        if stream_step and rate <= 0:   # the timed steps were saturation epochs already
+            sat = n_sub * args.steps / el
+            rate = args.serve_load * sat
         serving = serving_leg(m, p, n_sub if args.serve_requests < 0 else args.serve_requests, args.serve_load,
-                              rate=args.serve_rate, precisions=precs_c5 if stream_step else ("fp32_refine",),
-                              on_done=progress if stream_step else None)
+                              rate=rate, precisions=precs_c5 if stream_step else ("fp32_refine",),
+                              on_done=progress if stream_step else None, saturation=sat)
     m.close()
     comparator = None
     if not args.no_comparator and prec != "fp64":
