@@ -528,8 +528,8 @@ struct Slot {
   double *Y, *S, *G, *W, *C, *Dinv;
   double *Vb, *Yb, *Ub, *Zb, *Vn, *Tb, *H, *Ss, *G2, *Rinv, *theta, *resid;
   double *Bk, *Wk, *Yf;
-  uint16_t *Xh, *Xl, *Yh, *Yl;   // BF16 split (transposed) X_C and K_i X_C, MP x kpV
-  int kpV;
+  uint16_t *Xh, *Xl, *Yh, *Yl;   // BF16 split (transposed) X_C and K_i X_C, MB x kpV
+  int kpV, MB;                   // MB = roundup(M, 128): rows of the split operands
   int* info;
   int k_eff;
 };
@@ -587,8 +587,9 @@ static bool slot_layout(Slot& q, Take tk) {
   q.ldXc = q.ldA; q.ldEc = q.ldK;
   q.Y = (double*)tk(8 * (size_t)h.nV * q.ldK);
   q.kpV = (int)rup(std::max(h.nV, 1), 64);
+  q.MB = (int)rup(q.M, 128);
   if (q.prec == MOR_BF16_SPLIT) {
-    const size_t b = 2 * (size_t)q.MP * q.kpV;
+    const size_t b = 2 * (size_t)q.MB * q.kpV;
     q.Xh = (uint16_t*)tk(b); q.Xl = (uint16_t*)tk(b);
     q.Yh = (uint16_t*)tk(b); q.Yl = (uint16_t*)tk(b);
   } else {
@@ -1140,7 +1141,7 @@ static int dense_stage(mor_ctx* c, std::vector<Live*>& done) {
   size_t bf_tiles = 0;   // split-precision Gram: split tiles of X_C and K_i X_C, symmetric C tiles
   for (Slot* q : sl)
     if (q->prec == MOR_BF16_SPLIT)
-      bf_tiles += 2 * (size_t)(q->MP / 64) * (q->kpV / 64) + (size_t)q->T * (q->T + 1) / 2;
+      bf_tiles += 2 * (size_t)(q->MB / 64) * (q->kpV / 64) + (size_t)(q->MB / 128) * (q->MB / 128 + 1) / 2;
   const size_t bytes = 2 * 8 * gemm_tiles * sizeof(int4) + 32 * ns * sizeof(GemmDesc) + ns * (sizeof(DenseSub) + 2 * sizeof(TrsmDesc)) +
                        8 * (size_t)ns * 20 + 8 * (size_t)ns * 64 + 16 * 4096 + bf_tiles * sizeof(int4) +
                        ns * (2 * sizeof(SplitDesc) + sizeof(BfGramDesc)) + 4 * 256;
@@ -1181,15 +1182,15 @@ static int dense_stage(mor_ctx* c, std::vector<Live*>& done) {
     launch_spmm64_rows(q->d->rpV, q->d->colV, q->Ki64, h.nV, h.nV, q->Xc, q->ldXc, q->M, q->Y, q->ldK, st);
     if (q->prec == MOR_BF16_SPLIT) {
       const int id = (int)spd.size();
-      spd.push_back(SplitDesc{q->Xc, q->ldXc, h.nV, q->M, q->kpV, q->MP, q->Xh, q->Xl});
-      spd.push_back(SplitDesc{q->Y, q->ldK, h.nV, q->M, q->kpV, q->MP, q->Yh, q->Yl});
+      spd.push_back(SplitDesc{q->Xc, q->ldXc, h.nV, q->M, q->kpV, q->MB, q->Xh, q->Xl});
+      spd.push_back(SplitDesc{q->Y, q->ldK, h.nV, q->M, q->kpV, q->MB, q->Yh, q->Yl});
       for (int t = 0; t < 2; ++t)
-        for (int a = 0; a < q->MP / 64; ++a)
+        for (int a = 0; a < q->MB / 64; ++a)
           for (int v = 0; v < q->kpV / 64; ++v) spt.push_back(make_int4(id + t, a, v, 0));
       const int gid = (int)bgd.size();
       bgd.push_back(BfGramDesc{q->M, q->kpV, q->Xh, q->Xl, q->Yh, q->Yl, q->G, q->MP});
-      for (int i = 0; i < q->T; ++i)
-        for (int j = i; j < q->T; ++j) bgt.push_back(make_int4(gid, i, j, 0));
+      for (int i = 0; i < q->MB / 128; ++i)
+        for (int j = i; j < q->MB / 128; ++j) bgt.push_back(make_int4(gid, i, j, 0));
       bf_flops += 3.0 * q->M * q->M * h.nV;   // three BF16 products over the symmetric half
     } else {
       gG.add(gd(q->M, q->M, h.nV, q->Xc, q->ldXc, 1, q->Y, q->ldK, 0, q->G, q->MP, 1.0, 0.0, 1));

@@ -87,7 +87,7 @@ struct SplitDesc {      // FP64 k x m (row-major, ld) -> BF16 hi/lo transposed m
 };
 struct BfGramDesc {     // symmetric C (m x m, FP64, ldc) = A^T B from split operands
   int m, kp;
-  const uint16_t *Ahi, *Alo, *Bhi, *Blo;   // mp x kp each
+  const uint16_t *Ahi, *Alo, *Bhi, *Blo;   // mp x kp each, mp a multiple of 128
   double* C; int ldc;
 };
 
@@ -146,7 +146,7 @@ void launch_cg_start(const CgSys* sys, const int2* cb, int ncb, int first, doubl
 void launch_to_f64_block(const float* in, int ldi, double* out, int ldo, int rows, int cols, hipStream_t s);
 // tiles: (descriptor, 64-row block of m_pad, 64-column block of kp)
 void launch_split_bf16(const SplitDesc* d, const int4* tiles, int ntiles, hipStream_t s);
-// tiles: (descriptor, ti, tj) with ti <= tj, 64 x 64 output blocks
+// tiles: (descriptor, ti, tj) with ti <= tj, 128 x 128 output blocks
 void launch_gram_bf16(const BfGramDesc* d, const int4* tiles, int ntiles, hipStream_t s);
 void launch_spmm64_rows(const int* rp, const int* col, const double* val, int nrows, int col_limit,
                         const double* X, int ldx, int ncols, double* Y, int ldy, hipStream_t s);

@@ -1152,55 +1152,75 @@ void launch_split_bf16(const SplitDesc* d, const int4* tiles, int ntiles, hipStr
   if (ntiles > 0) hipLaunchKernelGGL(k_split_bf16, dim3(ntiles), dim3(256), 0, s, d, tiles);
 }
 
-// C = A^T B on v_mfma_f32_16x16x32_bf16: a workgroup owns a 64 x 64 block of C (ti <= tj),
-// each wave a 32 x 32 quarter (2 x 2 MFMA tiles); per 32-deep k step a lane loads 16 bytes
-// (8 consecutive k) of each operand row it feeds.  Three products per tile (the lo x lo term
-// is below the FP32 accumulation error).  Operand layout (gfx950): lane l feeds row l % 16
-// with k = 8 (l / 16) .. + 7; accumulator element r is row 4 (l / 16) + r, column l % 16.
+// C = A^T B on v_mfma_f32_16x16x32_bf16.  A workgroup owns a 128 x 128 block of C (ti <= tj)
+// and each wave a 64 x 64 quarter (4 x 4 MFMA tiles).  Per 32-deep k step the workgroup stages
+// the four operand tiles (A hi/lo, B hi/lo: 128 rows x 32 k each) in LDS, rows padded to 40
+// elements against bank conflicts, while the next step's tiles load into registers; each wave
+// then reads 16 fragments of 16 bytes and issues 48 MFMAs (three products per tile: hi x hi,
+// hi x lo, lo x hi; lo x lo is below the FP32 accumulation error).  Operand layout (gfx950):
+// lane l feeds row l % 16 with k = 8 (l / 16) .. + 7; accumulator element r is row
+// 4 (l / 16) + r, column l % 16.
+constexpr int kBfRow = 40;   // padded LDS row (bf16 elements) of a 32-deep operand tile
 __global__ __launch_bounds__(256) void k_gram_bf16(const BfGramDesc* __restrict__ ds, const int4* __restrict__ tiles) {
+  __shared__ __attribute__((aligned(16))) uint16_t sm[4][128 * kBfRow];   // A hi, A lo, B hi, B lo
   const int4 tl = tiles[blockIdx.x];
   const BfGramDesc& d = ds[tl.x];
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, wr = w >> 1, wc = w & 1;
-  const int i0 = tl.y * 64 + wr * 32, j0 = tl.z * 64 + wc * 32;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, wr = w >> 1, wc = w & 1;
+  const int I0 = tl.y * 128, J0 = tl.z * 128;
+  const uint16_t* src[4] = {d.Ahi + (int64_t)I0 * d.kp, d.Alo + (int64_t)I0 * d.kp, d.Bhi + (int64_t)J0 * d.kp,
+                            d.Blo + (int64_t)J0 * d.kp};
+  // staging: each operand tile is 128 rows x 64 bytes = 512 chunks of 16 bytes, 2 per thread
+  const int r0 = tid >> 2, q0 = (tid & 3) * 8;   // chunks (row r0, k q0) and (row r0 + 64, k q0)
+  u32x4 nx[4][2];
+  auto load = [&](int v0) {
+#pragma unroll
+    for (int o = 0; o < 4; ++o)
+#pragma unroll
+      for (int h = 0; h < 2; ++h)
+        nx[o][h] = *((const MOR_GLOBAL u32x4*)(src[o] + (int64_t)(r0 + 64 * h) * d.kp + v0 + q0));
+  };
+  f4 acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = f4{0.f, 0.f, 0.f, 0.f};
   const int kq = 8 * (lane >> 4), rl = lane & 15;
-  f4 acc[2][2];
-#pragma unroll
-  for (int a = 0; a < 2; ++a)
-#pragma unroll
-    for (int b = 0; b < 2; ++b) acc[a][b] = f4{0.f, 0.f, 0.f, 0.f};
-  const int64_t ra0 = (int64_t)(i0 + rl) * d.kp + kq, ra1 = ra0 + (int64_t)16 * d.kp;
-  const int64_t rb0 = (int64_t)(j0 + rl) * d.kp + kq, rb1 = rb0 + (int64_t)16 * d.kp;
+  load(0);
   for (int v0 = 0; v0 < d.kp; v0 += 32) {
-    const bf16x8 ah0 = *(const MOR_GLOBAL bf16x8*)(d.Ahi + ra0 + v0);
-    const bf16x8 ah1 = *(const MOR_GLOBAL bf16x8*)(d.Ahi + ra1 + v0);
-    const bf16x8 al0 = *(const MOR_GLOBAL bf16x8*)(d.Alo + ra0 + v0);
-    const bf16x8 al1 = *(const MOR_GLOBAL bf16x8*)(d.Alo + ra1 + v0);
-    const bf16x8 bh0 = *(const MOR_GLOBAL bf16x8*)(d.Bhi + rb0 + v0);
-    const bf16x8 bh1 = *(const MOR_GLOBAL bf16x8*)(d.Bhi + rb1 + v0);
-    const bf16x8 bl0 = *(const MOR_GLOBAL bf16x8*)(d.Blo + rb0 + v0);
-    const bf16x8 bl1 = *(const MOR_GLOBAL bf16x8*)(d.Blo + rb1 + v0);
-    acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah0, bh0, acc[0][0], 0, 0, 0);
-    acc[0][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah0, bh1, acc[0][1], 0, 0, 0);
-    acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah1, bh0, acc[1][0], 0, 0, 0);
-    acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah1, bh1, acc[1][1], 0, 0, 0);
-    acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah0, bl0, acc[0][0], 0, 0, 0);
-    acc[0][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah0, bl1, acc[0][1], 0, 0, 0);
-    acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah1, bl0, acc[1][0], 0, 0, 0);
-    acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah1, bl1, acc[1][1], 0, 0, 0);
-    acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al0, bh0, acc[0][0], 0, 0, 0);
-    acc[0][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al0, bh1, acc[0][1], 0, 0, 0);
-    acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al1, bh0, acc[1][0], 0, 0, 0);
-    acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al1, bh1, acc[1][1], 0, 0, 0);
+    __syncthreads();   // the previous step is done with the LDS tiles
+#pragma unroll
+    for (int o = 0; o < 4; ++o)
+#pragma unroll
+      for (int h = 0; h < 2; ++h) *reinterpret_cast<u32x4*>(&sm[o][(r0 + 64 * h) * kBfRow + q0]) = nx[o][h];
+    __syncthreads();
+    if (v0 + 32 < d.kp) load(v0 + 32);
+    bf16x8 ah[4], al[4], bh[4], bl[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int ra = (wr * 64 + t * 16 + rl) * kBfRow + kq, rb = (wc * 64 + t * 16 + rl) * kBfRow + kq;
+      ah[t] = *reinterpret_cast<const bf16x8*>(&sm[0][ra]);
+      al[t] = *reinterpret_cast<const bf16x8*>(&sm[1][ra]);
+      bh[t] = *reinterpret_cast<const bf16x8*>(&sm[2][rb]);
+      bl[t] = *reinterpret_cast<const bf16x8*>(&sm[3][rb]);
+    }
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[a], bh[b], acc[a][b], 0, 0, 0);
+        acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[a], bl[b], acc[a][b], 0, 0, 0);
+        acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[a], bh[b], acc[a][b], 0, 0, 0);
+      }
   }
   const bool diag = tl.y == tl.z;
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+  for (int a = 0; a < 4; ++a)
 #pragma unroll
-    for (int b = 0; b < 2; ++b)
+    for (int b = 0; b < 4; ++b)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int i = i0 + a * 16 + 4 * (lane >> 4) + r;
-        const int j = j0 + b * 16 + rl;
+        const int i = I0 + wr * 64 + a * 16 + 4 * (lane >> 4) + r;
+        const int j = J0 + wc * 64 + b * 16 + rl;
         if (i < d.m && j < d.m && (!diag || i <= j)) {
           const double v = (double)acc[a][b][r];
           d.C[(int64_t)i * d.ldc + j] = v;
