@@ -139,6 +139,14 @@ def reduce_local(mesh, kappa, f_nodal, sets: decomp.LocalSets, rank: int | None,
     U, s, _ = la.svd(Bw, full_matrices=False)
     k = truncation_rank(s, rank, tol)
     Phi = la.solve_triangular(R_i, U[:, :k], lower=False)
+    res = _stitch_and_project(lm, sets, s, k, q0, Phi)
+    if keep:
+        return res, dict(lm=lm, X=X, Z=Z, S_B=S_B, R_BB=R_BB, R_i=R_i, Bw=Bw, U=U)
+    return res
+
+
+def _stitch_and_project(lm: LocalMatrices, sets, sigma, k, q0, Phi) -> LocalResult:
+    """Steps 5-6: V_i = D_i [q0, Phi] and the local projected block and load."""
     Vfull = np.hstack([q0[:, None], Phi])
     Vloc = Vfull[lm.D_idx]
     # A restricted to P: P lies in I and every star of a P node lies in omega_i^+
@@ -147,9 +155,48 @@ def reduce_local(mesh, kappa, f_nodal, sets: decomp.LocalSets, rank: int | None,
     Aii = Vloc.T @ (A_PP @ Vloc)
     Aii = 0.5 * (Aii + Aii.T)
     bi = Vloc.T @ lm.f_plus[P_in_I]
-    res = LocalResult(sets=sets, sigma=s, k_eff=k, q0=q0, Phi=Phi, Vloc=Vloc, Aii=Aii, bi=bi)
+    return LocalResult(sets=sets, sigma=sigma, k_eff=k, q0=q0, Phi=Phi, Vloc=Vloc, Aii=Aii, bi=bi)
+
+
+def reduce_local_sketched(mesh, kappa, f_nodal, sets: decomp.LocalSets, rank: int | None, tol: float | None,
+                          omega: np.ndarray, keep: bool = False):
+    """The randomized variant of step 2 (Section 6, "Randomized numerical linear algebra").
+
+    omega is the random matrix S_i (M_i x l, rows in the order of B); the method's random
+    draws are an input here.  In the paper's order:
+      1. sketch: Qhat Rhat = R_i C_i A_II^{-1} A_IB R_BB^{-1} S_i (a QR factorisation; the
+         lifting carries the minus sign of the harmonic extension, as in the explicit path);
+      2. project the image of the weighted Z_i onto Qhat: B = Qhat^T R_i C_i A_II^{-1} A_IB
+         R_BB^{-1}, evaluated by the two left solves (transposes) so that the solves have l
+         right-hand sides instead of M_i;
+      3. the SVD B = Uhat Sigma V^T, truncated as in the explicit path;
+      4. the basis R_i^{-1} Qhat Uhat_k, stitched and projected as in the explicit path.
+    q_0 comes from the zero-boundary load problem as before.
+    """
+    lm = local_matrices(mesh, kappa, f_nodal, sets)
+    A_II, A_IB, _, _ = blocks(lm.A_plus, lm.nI)
+    lu = spla.splu(A_II)
+    S_B = schur_H1(lm)
+    R_BB = la.cholesky(S_B, lower=False)
+    R_i = la.cholesky(lm.K_i.toarray(), lower=False)
+    # 1. sketch and its QR
+    T = la.solve_triangular(R_BB, omega, lower=False)             # R_BB^{-1} S_i
+    Xs = lu.solve(-(A_IB @ T))                                    # A_II^{-1} (-A_IB) R_BB^{-1} S_i
+    Qh, _ = la.qr(R_i @ Xs[lm.C_idx], mode="economic")
+    # 2. B = Qhat^T R_i C (A_II^{-1} (-A_IB)) R_BB^{-1} by two left solves
+    L = np.zeros((lm.nI, Qh.shape[1]))
+    L[lm.C_idx] = R_i.T @ Qh                                      # (Qhat^T R_i C)^T
+    G = lu.solve(L, trans="T")                                    # A_II^{-T} (Qhat^T R_i C)^T
+    Bt = la.solve_triangular(R_BB, -(A_IB.T @ G), trans="T", lower=False)   # R_BB^{-T} (G^T (-A_IB))^T
+    # 3. SVD of the small matrix and truncation
+    Uh, s, _ = la.svd(Bt.T, full_matrices=False)
+    k = truncation_rank(s, rank, tol)
+    # 4. basis, stitching, projection
+    Phi = la.solve_triangular(R_i, Qh @ Uh[:, :k], lower=False)
+    q0 = lu.solve(lm.f_plus[:lm.nI])[lm.C_idx]
+    res = _stitch_and_project(lm, sets, s, k, q0, Phi)
     if keep:
-        return res, dict(lm=lm, X=X, Z=Z, S_B=S_B, R_BB=R_BB, R_i=R_i, Bw=Bw, U=U)
+        return res, dict(lm=lm, Qh=Qh, B=Bt.T, R_i=R_i, R_BB=R_BB)
     return res
 
 
@@ -162,16 +209,21 @@ _G = {}
 def _work(i):
     p, sets, rank, tol = _G["p"], _G["sets"], _G["rank"], _G["tol"]
     r = p.ranks[i] if (p.ranks is not None and rank is None) else rank
-    return reduce_local(p.mesh, p.kappa, p.f_nodal, sets[i], int(r) if r is not None else None, tol)
+    r = int(r) if r is not None else None
+    if _G.get("sketches") is not None:
+        return reduce_local_sketched(p.mesh, p.kappa, p.f_nodal, sets[i], r, tol, _G["sketches"][i])
+    return reduce_local(p.mesh, p.kappa, p.f_nodal, sets[i], r, tol)
 
 
 def reduce_all(problem, rank: int | None = None, tol: float | None = None, workers: int = 1,
-               subset=None) -> list[LocalResult]:
+               subset=None, sketches=None) -> list[LocalResult]:
+    """Every subdomain's local reduction (explicit; the randomized variant when `sketches`
+    holds one random matrix per subdomain)."""
     sets = decomp.all_local_sets(problem.mesh, problem.subdomains)
     if rank is None and tol is None and problem.ranks is None:
         rank = problem.rank
     idx = list(range(problem.subdomains.n_sub)) if subset is None else list(subset)
-    _G.update(p=problem, sets=sets, rank=rank, tol=tol)
+    _G.update(p=problem, sets=sets, rank=rank, tol=tol, sketches=sketches)
     if workers <= 1:
         return [_work(i) for i in idx]
     import multiprocessing as mp

@@ -167,3 +167,48 @@ def test_lemma_5_1_local_bound():
         den = np.sqrt(u[L] @ (lm.K_plus @ u[L]))
         eps = res.sigma[k]
         assert num / den < eps, (i, num / den, eps)
+
+
+# --------------------------------------------------------------------------------------
+# randomized variant (Section 6, "Randomized numerical linear algebra")
+
+def _sketch_case():
+    p = w.make_problem(10, (2, 2, 2), r=2, rank=5, kappa="lognormal", seed=3, name="sketch")
+    s = decomp.local_sets(p.mesh, p.subdomains, 0)
+    return p, s
+
+
+def test_sketched_variant_with_identity_sketch_is_the_explicit_svd():
+    """S_i = I: the sketch spans the whole image, so the projected SVD is the explicit one."""
+    p, s = _sketch_case()
+    ex = reduce.reduce_local(p.mesh, p.kappa, p.f_nodal, s, 5)
+    sk = reduce.reduce_local_sketched(p.mesh, p.kappa, p.f_nodal, s, 5, None, np.eye(s.B.size))
+    n = min(ex.sigma.size, sk.sigma.size)
+    np.testing.assert_allclose(sk.sigma[:n], ex.sigma[:n], rtol=1e-10, atol=1e-14 * ex.sigma[0])
+    assert sk.k_eff == ex.k_eff
+    np.testing.assert_allclose(sk.q0, ex.q0, rtol=0, atol=1e-12 * np.abs(ex.q0).max())
+    # same span (the singular vectors agree up to sign for distinct singular values)
+    P = sk.Phi @ np.linalg.lstsq(sk.Phi, ex.Phi, rcond=None)[0]
+    assert np.linalg.norm(P - ex.Phi) < 1e-9 * np.linalg.norm(ex.Phi)
+
+
+def test_full_width_gaussian_sketch_is_exact_and_narrow_sketches_interlace():
+    """A Gaussian S_i with M_i columns spans R^M almost surely, so the result is exact; with
+    fewer columns the singular values of Qhat^T (weighted Z) are lower bounds of the exact
+    ones (Qhat has orthonormal columns), and widening the sketch can only raise them."""
+    p, s = _sketch_case()
+    M = s.B.size
+    ex = reduce.reduce_local(p.mesh, p.kappa, p.f_nodal, s, 5)
+    full = reduce.reduce_local_sketched(p.mesh, p.kappa, p.f_nodal, s, 5, None,
+                                         w.sketch_rows(p.mesh.n_nodes, s.B, M, 0))
+    np.testing.assert_allclose(full.sigma[:20], ex.sigma[:20], rtol=1e-8)
+    prev = None
+    for l in (8, 24, 64):
+        om = w.sketch_rows(p.mesh.n_nodes, s.B, 64, 0)[:, :l]
+        sk = reduce.reduce_local_sketched(p.mesh, p.kappa, p.f_nodal, s, 5, None, om)
+        n = sk.sigma.size
+        assert n == l
+        assert np.all(sk.sigma <= ex.sigma[:n] * (1 + 1e-10))
+        if prev is not None:
+            assert np.all(sk.sigma[:prev.size] >= prev * (1 - 1e-10))
+        prev = sk.sigma

@@ -317,6 +317,16 @@ def make_config(name: str) -> Problem:
     raise ValueError(name)
 
 
+def sketch_rows(n_nodes: int, node_ids: np.ndarray, cols: int, sub: int, seed: int = 13) -> np.ndarray:
+    """Standard Gaussian random matrix for the randomized local reduction of subdomain `sub`:
+    one row per node id in `node_ids` (the subdomain's interface nodes, in the caller's
+    order), `cols` columns.  Row values depend only on (seed, sub, global node id), so every
+    consumer that lists the same nodes gets the same matrix."""
+    rng = np.random.default_rng([seed, sub])
+    table = rng.standard_normal((n_nodes, cols))
+    return np.ascontiguousarray(table[np.asarray(node_ids, dtype=np.int64)])
+
+
 def poisson_arrivals(n_requests: int, rate: float, seed: int = 7) -> np.ndarray:
     """Arrival times (seconds) of a Poisson stream with the given rate."""
     rng = np.random.default_rng(seed)
