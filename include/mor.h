@@ -144,6 +144,21 @@ int mor_local_basis(mor_ctx* ctx, int32_t sd, int32_t rank, double tol, int32_t*
 int mor_local_basis_batch(mor_ctx* ctx, int32_t n, const int32_t* sds, const int32_t* ranks,
                           const double* tols, int32_t* k_eff_out);
 
+/* The randomized local reduction of Section 6 ("Randomized numerical linear algebra"): the
+ * sketch Qhat Rhat = R_i C_i A_II^-1 A_IB R_BB^-1 S_i, then the SVD of Qhat^T (weighted Z_i)
+ * evaluated with two left solves, so that the A_II solves carry l + 1 and then l right-hand
+ * sides instead of M_i + 1.  The H1 solve for S_B keeps all M_i columns.
+ * sds, ranks, tols: n values each, host (tols may be NULL), as in mor_local_basis_batch.
+ * l: sketch columns, 1..64.  omega[i]: the random matrix S_i of subdomain sds[i], host, M_i x l
+ * row-major with rows in the order of the subdomain's interface nodes B (ascending global id;
+ * mor_get_nodes lists them after the interior nodes); read during the call only.
+ * The orthonormalisation of the sketch drops directions whose K_i-Gram eigenvalue is below
+ * 1e-10 of the largest; singular values are reported for the kept directions (at most l).
+ * Needs FP64 solutions: precision MOR_FP64, MOR_FP32_REFINE or MOR_BF16_SPLIT (else
+ * MOR_EINVAL).  k_eff_out: n, host, may be NULL. */
+int mor_local_basis_sketched(mor_ctx* ctx, int32_t n, const int32_t* sds, const int32_t* ranks, const double* tols,
+                             int32_t l, const double* const* omega, int32_t* k_eff_out);
+
 /* Galerkin projection Q^T A Q of the global system (eq. 6.1) without forming A
  * or Q: diagonal blocks from the local step, off-diagonal blocks from A_0
  * assembled on omega_0 and the interface rows of neighbouring bases.  Needs

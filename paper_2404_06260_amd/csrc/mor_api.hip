@@ -17,6 +17,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <memory>
 #include <string>
 #include <thread>
 #include <vector>
@@ -530,6 +531,11 @@ struct Slot {
   double *Bk, *Wk, *Yf;
   uint16_t *Xh, *Xl, *Yh, *Yl;   // BF16 split (transposed) X_C and K_i X_C, MB x kpV
   int kpV, MB;                   // MB = roundup(M, 128): rows of the split operands
+  // randomized variant (ls > 0 sketch columns, at most 64)
+  int ls, rk;                    // sketch columns; directions kept by the K_i-orthonormalisation
+  double *Fd;                    // dense FP64 right-hand sides of the A solves, nI x ldA
+  double *q0v;                   // zero-boundary load solution on V_i
+  double *Yk, *Wt, *KWt, *Vs;    // K_i Y, the K_i-orthonormal sketch basis W and K_i W (nV x 64); 64 x 64
   int* info;
   int k_eff;
 };
@@ -541,12 +547,12 @@ static void slot_shape(mor_ctx* c, Slot& q) {
   q.T = q.MP / 64;
   // rows of the block vectors start on 128-byte cache lines (32 FP32 / 16 FP64 columns), so
   // the column slices of the CG kernels never straddle a line they only partly use
-  q.colsA = h.nB + 1;
+  q.colsA = q.ls > 0 ? q.ls + 1 : h.nB + 1;   // sketch + load columns, or every interface column + load
   q.ldA = (int)rup(q.colsA, 32);
   q.colsK = h.nB;
   q.ldK = (int)rup(q.colsK, 32);
   const int p = c->opts.oversample > 0 ? c->opts.oversample : std::max(8, q.rank);
-  int s = q.rank > 0 ? std::min(64, q.rank + p) : 64;
+  int s = q.rank > 0 && q.ls == 0 ? std::min(64, q.rank + p) : 64;
   s = std::min(s, q.M);
   q.s = s;
   // the fewest Ritz pairs that must converge; the eigensolver raises it to the truncation
@@ -585,22 +591,35 @@ static bool slot_layout(Slot& q, Take tk) {
     q.Xc = (double*)q.XA; q.Ec = (double*)q.XK;
   }
   q.ldXc = q.ldA; q.ldEc = q.ldK;
-  q.Y = (double*)tk(8 * (size_t)h.nV * q.ldK);
+  const bool sk = q.ls > 0;
+  q.Y = sk ? nullptr : (double*)tk(8 * (size_t)h.nV * q.ldK);
   q.kpV = (int)rup(std::max(h.nV, 1), 64);
   q.MB = (int)rup(q.M, 128);
-  if (q.prec == MOR_BF16_SPLIT) {
+  if (sk) {
+    q.Fd = (double*)tk(8 * (size_t)h.nI * q.ldA);
+    q.q0v = (double*)tk(8 * (size_t)std::max(h.nV, 1));
+    q.Yk = (double*)tk(8 * (size_t)h.nV * 64); q.Wt = (double*)tk(8 * (size_t)h.nV * 64);
+    q.KWt = (double*)tk(8 * (size_t)h.nV * 64); q.Vs = (double*)tk(8 * 64 * 64);
+  } else {
+    q.Fd = q.q0v = q.Yk = q.Wt = q.KWt = q.Vs = nullptr;
+  }
+  if (q.prec == MOR_BF16_SPLIT && !sk) {
     const size_t b = 2 * (size_t)q.MB * q.kpV;
     q.Xh = (uint16_t*)tk(b); q.Xl = (uint16_t*)tk(b);
     q.Yh = (uint16_t*)tk(b); q.Yl = (uint16_t*)tk(b);
   } else {
     q.Xh = q.Xl = q.Yh = q.Yl = nullptr;
   }
-  q.S = (double*)tk(8 * (size_t)q.MP * q.MP); q.G = (double*)tk(8 * (size_t)q.MP * q.MP);
-  q.W = (double*)tk(8 * (size_t)q.MP * q.MP); q.C = (double*)tk(8 * (size_t)q.MP * q.MP);
+  q.S = (double*)tk(8 * (size_t)q.MP * q.MP);
+  q.G = sk ? nullptr : (double*)tk(8 * (size_t)q.MP * q.MP);
+  q.W = sk ? nullptr : (double*)tk(8 * (size_t)q.MP * q.MP);
+  q.C = sk ? nullptr : (double*)tk(8 * (size_t)q.MP * q.MP);
   q.Dinv = (double*)tk(8 * (size_t)q.T * 4096);
   q.Vb = (double*)tk(8 * (size_t)q.MP * s); q.Yb = (double*)tk(8 * (size_t)q.MP * s);
-  q.Ub = (double*)tk(8 * (size_t)q.MP * s); q.Zb = (double*)tk(8 * (size_t)q.MP * s);
-  q.Vn = (double*)tk(8 * (size_t)q.MP * s); q.Tb = (double*)tk(8 * (size_t)q.MP * s);
+  q.Ub = sk ? nullptr : (double*)tk(8 * (size_t)q.MP * s);
+  q.Zb = sk ? nullptr : (double*)tk(8 * (size_t)q.MP * s);
+  q.Vn = sk ? nullptr : (double*)tk(8 * (size_t)q.MP * s);
+  q.Tb = sk ? nullptr : (double*)tk(8 * (size_t)q.MP * s);
   q.H = (double*)tk(8 * (size_t)s * s); q.Ss = (double*)tk(8 * (size_t)s * s);
   q.G2 = (double*)tk(8 * (size_t)s * s); q.Rinv = (double*)tk(8 * (size_t)s * s);
   q.theta = (double*)tk(8 * (size_t)s); q.resid = (double*)tk(8 * (size_t)s);
@@ -641,6 +660,10 @@ struct Live {
   size_t bytes = 0;
   SysRun sys[2];
   int status = 0;
+  // randomized variant: 0 H1 solve, 1 sketch solve, 2 left solve (then the small SVD)
+  int stage = 0;
+  int iters_prev = 0;                            // A-system iterations of finished solves
+  std::shared_ptr<const std::vector<double>> om; // the random matrix S_i (M x l, host)
 };
 
 struct Req {
@@ -648,6 +671,8 @@ struct Req {
   int sd, rank, prec;
   double tol;
   int done = 0, status = 0;
+  int ls = 0;                                    // sketch columns (0: explicit SVD)
+  std::shared_ptr<const std::vector<double>> om;
 };
 
 struct Launch {
@@ -813,6 +838,27 @@ static int read_counts(mor_ctx* c, MorEngine& e) {
   return 0;
 }
 
+// Start the CG of the listed systems from their right-hand sides (zero state, R = F,
+// P = M^-1 R, per-column references); a system with a zero right-hand side is done at once.
+template <typename T>
+static int start_systems(mor_ctx* c, MorEngine& e, Launch& Ln) {
+  hipStream_t st = c->st;
+  if (Ln.sys.empty()) return 0;
+  if (int rc = engine_upload(c, e, Ln)) return rc;
+  launch_cg_zero(e.d_sys, Ln.cb, Ln.ncb, st);
+  launch_cg_init<T>(e.d_sys, Ln.sp, Ln.nsp, e.sp.rb, e.sp.v, st);
+  launch_cg_pstart<T>(e.d_sys, Ln.bk, Ln.nbk, e.stm.rb, e.stm.v, st);
+  launch_cg_start(e.d_sys, Ln.cb, Ln.ncb, 1, 0.0, st);
+  HIPCHK(hipGetLastError());
+  if (int rc = read_counts(c, e)) return rc;
+  for (SysRun* R : Ln.sys) {
+    R->phase = e.h_cnt[R->cnt] == 0 ? 1 : 0;
+    R->iters = 0;
+    R->refines = 0;
+  }
+  return 0;
+}
+
 // Admit pending requests that fit, assemble them and start their CG (batched).
 template <typename T>
 static int engine_admit(mor_ctx* c, MorEngine& e) {
@@ -826,6 +872,8 @@ static int engine_admit(mor_ctx* c, MorEngine& e) {
     Slot& q = L->q;
     std::memset(&q, 0, sizeof(q));
     q.sd = r.sd; q.rank = r.rank; q.tol = r.tol; q.prec = r.prec;
+    q.ls = r.ls;
+    L->om = r.om;
     q.h = &c->subs[r.sd];
     q.d = &c->sdev[r.sd];
     slot_shape(c, q);
@@ -893,7 +941,8 @@ static int engine_admit(mor_ctx* c, MorEngine& e) {
       S.rp = q.d->rp; S.col = q.d->col; S.ii_end = q.d->ii_end;
       S.val32 = w == 0 ? q.A32 : q.K32;
       S.val64 = w == 0 ? q.A64 : q.K64;
-      S.f = w == 0 ? q.f : nullptr;
+      S.f = w == 0 && q.ls == 0 ? q.f : nullptr;
+      S.Fd = w == 0 && q.ls > 0 ? q.Fd : nullptr;
       S.nI = h.nI; S.nB = h.nB;
       S.ncols = w == 0 ? q.colsA : q.colsK;
       S.ld = w == 0 ? q.ldA : q.ldK;
@@ -918,18 +967,19 @@ static int engine_admit(mor_ctx* c, MorEngine& e) {
       e.cnt_free.pop_back();
       S.nactive = e.d_cnt + R.cnt;
       R.phase = 0; R.iters = 0; R.refines = 0; R.nnzII = nnzII;
+      if (w == 0 && q.ls > 0) {
+        R.phase = 2;   // the sketch solve waits for R_BB (randomized variant)
+        continue;
+      }
       Ln.sys.push_back(&R);
     }
+    if (q.ls > 0) {   // the random matrix S_i, zero padded to MP x 64
+      launch_fill(q.Bk, (int64_t)q.MP * 64, 0.0, st);
+      HIPCHK(hipMemcpy2DAsync(q.Bk, 64 * sizeof(double), L->om->data(), q.ls * sizeof(double), q.ls * sizeof(double),
+                              q.M, hipMemcpyHostToDevice, st));
+    }
   }
-  if (int rc = engine_upload(c, e, Ln)) return rc;
-  launch_cg_zero(e.d_sys, Ln.cb, Ln.ncb, st);
-  launch_cg_init<T>(e.d_sys, Ln.sp, Ln.nsp, e.sp.rb, e.sp.v, st);
-  launch_cg_pstart<T>(e.d_sys, Ln.bk, Ln.nbk, e.stm.rb, e.stm.v, st);
-  launch_cg_start(e.d_sys, Ln.cb, Ln.ncb, 1, 0.0, st);
-  HIPCHK(hipGetLastError());
-  if (int rc = read_counts(c, e)) return rc;
-  for (SysRun* R : Ln.sys)
-    if (e.h_cnt[R->cnt] == 0) R->phase = 1;   // zero right-hand side
+  if (int rc = start_systems<T>(c, e, Ln)) return rc;
   for (Live* L : adm) e.live.push_back(L);
   return 0;
 }
@@ -1059,16 +1109,311 @@ static int engine_chunk(mor_ctx* c, MorEngine& e) {
 
 // Dense stage of the requests whose two solves finished.
 static int dense_stage(mor_ctx* c, std::vector<Live*>& done);
+static int project_local(mor_ctx* c, Arena& ar, const std::vector<Slot*>& sl, const std::vector<Live*>& done,
+                         int eig_iters);
+
+// ----------------------------------------------------------------- randomized variant (f1)
+// Section 6's randomized SVD with two left solves, for requests with a sketch S_i (l <= 64
+// columns).  Stages, each batched over the requests that reach it:
+//   after the H1 solve:  S_B, R_BB = chol(S_B), T = R_BB^-1 S_i and the sketch solve
+//                        A_II X = [-A_IB T | f_I];
+//   after that solve:    Y = C X[:, :l]; a K_i-orthonormal basis W of span(Y) from the
+//                        eigendecomposition of Y^T K_i Y (directions below 1e-10 of the largest
+//                        eigenvalue dropped), applied twice; the left solve A_II G = C^T K_i W;
+//   after the left solve: B^T = R_BB^-T A_BI G (= the transpose of W^T K_i Z R_BB^-1 up to the
+//                        sign of Z), the top eigenpairs of B B^T, the basis [q_0, W U_k] and the
+//                        local projection.
+struct StageBuf {
+  mor_ctx* c;
+  char* p = nullptr;
+  Arena ar;
+  StageBuf(mor_ctx* cc, size_t bytes) : c(cc) {
+    p = (char*)dalloc(c, bytes);
+    ar = Arena{p, p ? bytes : 0, 0};
+  }
+  ~StageBuf() {
+    (void)hipStreamSynchronize(c->st);
+    dfree(c, p);
+  }
+};
+
+// device pointer table of one field over the slots
+template <typename F>
+static double** ptr_table(mor_ctx* c, Arena& ar, const std::vector<Slot*>& sl, F get) {
+  std::vector<double*> h(sl.size());
+  for (size_t i = 0; i < sl.size(); ++i) h[i] = get(*sl[i]);
+  double** d = (double**)ar.take(sizeof(double*) * std::max<size_t>(1, h.size()));
+  if (d && !h.empty()) (void)hipMemcpyAsync(d, h.data(), sizeof(double*) * h.size(), hipMemcpyHostToDevice, c->st);
+  return d;
+}
+static int* int_table(mor_ctx* c, Arena& ar, const std::vector<int>& h) {
+  int* d = (int*)ar.take(sizeof(int) * std::max<size_t>(1, h.size()));
+  if (d && !h.empty()) (void)hipMemcpyAsync(d, h.data(), sizeof(int) * h.size(), hipMemcpyHostToDevice, c->st);
+  return d;
+}
+
+// eigenpairs (descending) of the symmetric s_i x s_i matrices in H, into Ss and theta
+static int small_eig(mor_ctx* c, Arena& ar, const std::vector<Slot*>& sl, const std::vector<int>& s_of,
+                     std::vector<std::vector<double>>& theta) {
+  hipStream_t st = c->st;
+  const int ns = (int)sl.size();
+  double** PH = ptr_table(c, ar, sl, [](Slot& q) { return q.H; });
+  double** PS = ptr_table(c, ar, sl, [](Slot& q) { return q.Ss; });
+  double** PT = ptr_table(c, ar, sl, [](Slot& q) { return q.theta; });
+  int* ds = int_table(c, ar, s_of);
+  if (!PH || !PS || !PT || !ds) return fail(MOR_ENOMEM, "arena exhausted (small eigen)");
+  launch_jacobi(PH, PS, PT, ds, ns, 64, st);
+  theta.assign(ns, {});
+  for (int i = 0; i < ns; ++i) {
+    theta[i].resize(std::max(s_of[i], 1));
+    HIPCHK(hipMemcpyAsync(theta[i].data(), sl[i]->theta, 8 * theta[i].size(), hipMemcpyDeviceToHost, st));
+  }
+  HIPCHK(hipStreamSynchronize(st));
+  return 0;
+}
+static int rank_of(const std::vector<double>& th, int s) {
+  int r = 0;
+  for (int j = 0; j < s; ++j) r += (th[j] > 0.0 && th[j] > 1e-10 * th[0]) ? 1 : 0;
+  return r;
+}
+
+template <typename T>
+static int rsvd_after_h1(mor_ctx* c, MorEngine& e, std::vector<Live*>& ls) {
+  hipStream_t st = c->st;
+  const int ns = (int)ls.size();
+  std::vector<Slot*> sl(ns);
+  for (int i = 0; i < ns; ++i) sl[i] = &ls[i]->q;
+  StageBuf buf(c, ns * (sizeof(DenseSub) + 4 * sizeof(double*)) + 8 * 256);
+  if (!buf.p) return fail(MOR_ENOMEM, "device allocation failed (sketch stage)");
+  std::vector<DenseSub> hds(ns);
+  int tmax = 0;
+  for (int i = 0; i < ns; ++i) {
+    Slot& q = *sl[i];
+    const HostSub& h = *q.h;
+    ScopedTimer tm(c, "schur", 0);
+    launch_schur(q.d->rp, q.d->col, q.K64, h.nI, h.nB, q.Ec, q.ldEc, q.S, q.MP, st);
+    launch_pad_identity(q.S, q.M, q.MP, st);
+    launch_symmetrize(q.S, q.MP, st);
+    hds[i] = DenseSub{q.M, q.MP, q.T, q.S, nullptr, nullptr, nullptr, q.Dinv, q.info};
+    tmax = std::max(tmax, q.T);
+    launch_fill_i(q.info, 16, 0, st);
+  }
+  DenseSub* dds = (DenseSub*)buf.ar.take(sizeof(DenseSub) * ns);
+  if (!dds) return fail(MOR_ENOMEM, "arena exhausted (sketch stage)");
+  HIPCHK(hipMemcpyAsync(dds, hds.data(), sizeof(DenseSub) * ns, hipMemcpyHostToDevice, st));
+  {
+    ScopedTimer tm(c, "potrf", 0);
+    for (int p = 0; p < tmax; ++p) {
+      launch_potrf_diag(dds, ns, p, st);
+      launch_chol_panel(dds, ns, p, tmax, st);
+      launch_chol_syrk(dds, ns, p, tmax, st);
+    }
+  }
+  std::vector<int> hinfo(ns * 16);
+  for (int i = 0; i < ns; ++i) HIPCHK(hipMemcpyAsync(&hinfo[i * 16], sl[i]->info, 64, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  for (int i = 0; i < ns; ++i)
+    if (hinfo[i * 16] != 0) {
+      ls[i]->status = MOR_EDEVICE;
+      g_err = "subdomain " + std::to_string(sl[i]->sd) + ": S_B is not positive definite";
+    }
+  double** PB = ptr_table(c, buf.ar, sl, [](Slot& q) { return q.Bk; });
+  double** PW = ptr_table(c, buf.ar, sl, [](Slot& q) { return q.Wk; });
+  if (!PB || !PW) return fail(MOR_ENOMEM, "arena exhausted (sketch stage)");
+  {
+    ScopedTimer tm(c, "trsm", 0);
+    launch_trsm_un(dds, ns, PB, PW, tmax, st);   // T = R_BB^-1 S_i
+  }
+  Launch Ln;
+  for (int i = 0; i < ns; ++i) {
+    Slot& q = *sl[i];
+    const HostSub& h = *q.h;
+    launch_rhs_sketch(q.d->rp, q.d->col, q.d->ii_end, q.A64, q.f, h.nI, q.Wk, q.ls, q.Fd, q.ldA, st);
+    if (ls[i]->status) continue;
+    SysRun& R = ls[i]->sys[0];
+    R.S.ncols = q.colsA;
+    ls[i]->stage = 1;
+    Ln.sys.push_back(&R);
+  }
+  return start_systems<T>(c, e, Ln);
+}
+
+template <typename T>
+static int rsvd_after_sketch(mor_ctx* c, MorEngine& e, std::vector<Live*>& ls) {
+  hipStream_t st = c->st;
+  const int ns = (int)ls.size();
+  std::vector<Slot*> sl(ns);
+  size_t tiles = 0;
+  for (int i = 0; i < ns; ++i) {
+    sl[i] = &ls[i]->q;
+    tiles += 4 * ((size_t)(sl[i]->h->nV + 63) / 64 + 2) + 8;
+  }
+  StageBuf buf(c, ns * (16 * sizeof(double*) + 4 * sizeof(int) + 4 * sizeof(GemmDesc)) + 4 * tiles * sizeof(int4) +
+                      64 * 256);
+  if (!buf.p) return fail(MOR_ENOMEM, "device allocation failed (sketch stage)");
+  // Y = C X[:, :l], K_i Y and the Gram Y^T K_i Y
+  GemmBatch g1;
+  for (Slot* q : sl) {
+    const HostSub& h = *q->h;
+    launch_copy_col(q->Xc + q->ls, q->ldXc, q->q0v, 1, h.nV, st);   // q_0 (load column)
+    launch_spmm64_rows(q->d->rpV, q->d->colV, q->Ki64, h.nV, h.nV, q->Xc, q->ldXc, q->ls, q->Yk, 64, st);
+    g1.add(gd(q->ls, q->ls, h.nV, q->Xc, q->ldXc, 1, q->Yk, 64, 0, q->H, q->ls));
+  }
+  if (int rc = gemm_upload(c, g1, buf.ar)) return rc;
+  gemm_run(c, g1, "sketch_gram");
+  std::vector<int> s_of(ns);
+  for (int i = 0; i < ns; ++i) s_of[i] = sl[i]->ls;
+  std::vector<std::vector<double>> th;
+  if (int rc = small_eig(c, buf.ar, sl, s_of, th)) return rc;
+  // first pass: W1 = Y V diag(th^-1/2), K_i W1 = (K_i Y) V diag(th^-1/2)
+  GemmBatch g2;
+  std::vector<int> r1(ns);
+  for (int i = 0; i < ns; ++i) {
+    Slot& q = *sl[i];
+    const HostSub& h = *q.h;
+    r1[i] = rank_of(th[i], q.ls);
+    launch_whiten(q.Ss, q.theta, q.ls, r1[i], q.Vs, st);
+    g2.add(gd(h.nV, 64, q.ls, q.Xc, q.ldXc, 0, q.Vs, 64, 0, q.Wt, 64));
+    g2.add(gd(h.nV, 64, q.ls, q.Yk, 64, 0, q.Vs, 64, 0, q.KWt, 64));
+  }
+  if (int rc = gemm_upload(c, g2, buf.ar)) return rc;
+  gemm_run(c, g2, "sketch_orth");
+  // second pass on W1 (its Gram is close to the identity): W = W1 V2 diag(th2^-1/2)
+  GemmBatch g3;
+  for (int i = 0; i < ns; ++i) {
+    Slot& q = *sl[i];
+    const HostSub& h = *q.h;
+    g3.add(gd(r1[i], r1[i], h.nV, q.Wt, 64, 1, q.KWt, 64, 0, q.H, r1[i]));
+  }
+  if (int rc = gemm_upload(c, g3, buf.ar)) return rc;
+  gemm_run(c, g3, "sketch_orth");
+  if (int rc = small_eig(c, buf.ar, sl, r1, th)) return rc;
+  GemmBatch g4;
+  for (int i = 0; i < ns; ++i) {
+    Slot& q = *sl[i];
+    const HostSub& h = *q.h;
+    q.rk = rank_of(th[i], r1[i]);
+    launch_whiten(q.Ss, q.theta, r1[i], q.rk, q.Vs, st);
+    g4.add(gd(h.nV, 64, r1[i], q.Wt, 64, 0, q.Vs, 64, 0, q.Yk, 64));   // W (into Yk)
+  }
+  if (int rc = gemm_upload(c, g4, buf.ar)) return rc;
+  gemm_run(c, g4, "sketch_orth");
+  Launch Ln;
+  for (int i = 0; i < ns; ++i) {
+    Slot& q = *sl[i];
+    const HostSub& h = *q.h;
+    launch_spmm64_rows(q.d->rpV, q.d->colV, q.Ki64, h.nV, h.nV, q.Yk, 64, q.rk, q.KWt, 64, st);   // K_i W
+    launch_rhs_rows(q.KWt, h.nV, q.rk, h.nI, q.Fd, q.ldA, st);   // C^T K_i W
+    SysRun& R = ls[i]->sys[0];
+    ls[i]->iters_prev += R.iters;
+    R.S.ncols = q.rk;
+    ls[i]->stage = 2;
+    if (q.rk < 1) {
+      ls[i]->status = MOR_EDEVICE;
+      g_err = "subdomain " + std::to_string(q.sd) + ": the sketch has no significant direction";
+      continue;
+    }
+    Ln.sys.push_back(&R);
+  }
+  return start_systems<T>(c, e, Ln);
+}
+
+static int rsvd_finish(mor_ctx* c, std::vector<Live*>& ls) {
+  hipStream_t st = c->st;
+  const int ns = (int)ls.size();
+  std::vector<Slot*> sl(ns);
+  size_t tiles = 0;
+  for (int i = 0; i < ns; ++i) {
+    sl[i] = &ls[i]->q;
+    tiles += 4 * ((size_t)(sl[i]->h->nV + 63) / 64 + (sl[i]->h->nP + 63) / 64 + 4) + 8;
+  }
+  StageBuf buf(c, ns * (sizeof(DenseSub) + sizeof(TrsmDesc) + 16 * sizeof(double*) + 4 * sizeof(GemmDesc)) +
+                      4 * tiles * sizeof(int4) + 64 * 256);
+  if (!buf.p) return fail(MOR_ENOMEM, "device allocation failed (sketch stage)");
+  // B^T = R_BB^-T (A_BI G)
+  std::vector<DenseSub> hds(ns);
+  std::vector<TrsmDesc> htd(ns);
+  for (int i = 0; i < ns; ++i) {
+    Slot& q = *sl[i];
+    const HostSub& h = *q.h;
+    launch_bi_product(q.d->rp, q.d->col, q.A64, h.nI, h.nB, q.MP, q.Xc, q.ldXc, q.rk, q.Vb, st);
+    hds[i] = DenseSub{q.M, q.MP, q.T, q.S, nullptr, nullptr, nullptr, q.Dinv, q.info};
+    htd[i] = TrsmDesc{q.Vb, 64, 0, q.Yb, 64, 1};
+  }
+  DenseSub* dds = (DenseSub*)buf.ar.take(sizeof(DenseSub) * ns);
+  TrsmDesc* dtd = (TrsmDesc*)buf.ar.take(sizeof(TrsmDesc) * ns);
+  if (!dds || !dtd) return fail(MOR_ENOMEM, "arena exhausted (sketch stage)");
+  HIPCHK(hipMemcpyAsync(dds, hds.data(), sizeof(DenseSub) * ns, hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(dtd, htd.data(), sizeof(TrsmDesc) * ns, hipMemcpyHostToDevice, st));
+  {
+    ScopedTimer tm(c, "trsm", 0);
+    launch_trsm_lt(dds, dtd, ns, 1, st);
+  }
+  // B B^T and its eigenpairs: sigma^2 and the left singular vectors U
+  GemmBatch g1;
+  std::vector<int> s_of(ns);
+  for (int i = 0; i < ns; ++i) {
+    Slot& q = *sl[i];
+    s_of[i] = q.rk;
+    g1.add(gd(q.rk, q.rk, q.MP, q.Yb, 64, 1, q.Yb, 64, 0, q.H, q.rk));
+  }
+  if (int rc = gemm_upload(c, g1, buf.ar)) return rc;
+  gemm_run(c, g1, "sketch_svd");
+  std::vector<std::vector<double>> th;
+  if (int rc = small_eig(c, buf.ar, sl, s_of, th)) return rc;
+  // truncation and the basis [q_0, W U_k]
+  GemmBatch gV;
+  for (int i = 0; i < ns; ++i) {
+    Slot& q = *sl[i];
+    const HostSub& h = *q.h;
+    std::vector<double> sg(q.rk);
+    for (int j = 0; j < q.rk; ++j) sg[j] = std::sqrt(std::max(th[i][j], 0.0));
+    q.k_eff = truncation_rank(sg, q.rank, q.tol, std::max(q.rk - 1, 1));
+    q.k_eff = std::min(q.k_eff, q.rk);
+    SubResult& R = c->res[q.sd];
+    R.sigma = sg;
+    R.k_eff = q.k_eff;
+    const int k1 = q.k_eff + 1;
+    if (R.d_V) pfree(c, R.d_V);
+    if (R.d_Pm) pfree(c, R.d_Pm);
+    R.d_V = (double*)palloc(c, 8 * (size_t)h.nV * k1);
+    R.d_Pm = (double*)palloc(c, 8 * (size_t)k1 * (k1 + 1));
+    if (!R.d_V || !R.d_Pm) return fail(MOR_ENOMEM, "device allocation failed (basis)");
+    launch_copy_col(q.q0v, 1, R.d_V, k1, h.nV, st);
+    if (q.k_eff > 0) gV.add(gd(h.nV, q.k_eff, q.rk, q.Yk, 64, 0, q.Ss, q.rk, 0, R.d_V + 1, k1));
+  }
+  if (int rc = gemm_upload(c, gV, buf.ar)) return rc;
+  gemm_run(c, gV, "basis");
+  for (Live* L : ls) L->stage = 3;
+  return project_local(c, buf.ar, sl, ls, 0);
+}
 
 template <typename T>
 static int engine_tick(mor_ctx* c, MorEngine& e) {
   if (int rc = engine_admit<T>(c, e)) return rc;
   if (int rc = engine_chunk<T>(c, e)) return rc;
+  {   // randomized variant: move the requests whose current solve finished to their next stage
+    std::vector<Live*> s1, s2, s3;
+    for (Live* L : e.live) {
+      if (L->status || L->q.ls == 0) continue;
+      if (L->stage == 0 && L->sys[1].phase == 1) s1.push_back(L);
+      else if (L->stage == 1 && L->sys[0].phase == 1) s2.push_back(L);
+      else if (L->stage == 2 && L->sys[0].phase == 1) s3.push_back(L);
+    }
+    auto run = [&](std::vector<Live*>& v, int rc) {
+      if (rc)
+        for (Live* L : v)
+          if (!L->status) L->status = rc;
+    };
+    if (!s3.empty()) run(s3, rsvd_finish(c, s3));
+    if (!s2.empty()) run(s2, rsvd_after_sketch<T>(c, e, s2));
+    if (!s1.empty()) run(s1, rsvd_after_h1<T>(c, e, s1));
+  }
   std::vector<Live*> ready, keep;
   bool iterating = false;
   for (Live* L : e.live) {
     if (L->status) ready.push_back(L);
-    else if (L->sys[0].phase == 1 && L->sys[1].phase == 1) ready.push_back(L);
+    else if (L->q.ls > 0 ? L->stage == 3 : (L->sys[0].phase == 1 && L->sys[1].phase == 1)) ready.push_back(L);
     else {
       keep.push_back(L);
       iterating = true;
@@ -1078,12 +1423,15 @@ static int engine_tick(mor_ctx* c, MorEngine& e) {
   // Batch the dense stage: wait for more finished requests while others still iterate,
   // unless enough are ready or pending requests wait for the memory they hold.
   const int want = c->opts.dense_batch > 0 ? c->opts.dense_batch : 16;
-  bool failed = false;
-  for (Live* L : ready) failed |= L->status != 0;
-  if (iterating && !failed && (int)ready.size() < want && e.pending.empty()) return 0;
+  bool failed = false, dense = false;
+  for (Live* L : ready) {
+    failed |= L->status != 0;
+    dense |= L->status == 0 && L->q.ls == 0;
+  }
+  if (iterating && dense && !failed && (int)ready.size() < want && e.pending.empty()) return 0;
   std::vector<Live*> ok;
   for (Live* L : ready)
-    if (!L->status) ok.push_back(L);
+    if (!L->status && L->q.ls == 0) ok.push_back(L);
   int rc = 0;
   if (!ok.empty()) {
     rc = dense_stage(c, ok);
@@ -1130,6 +1478,49 @@ static bool engines_idle(mor_ctx* c) {
 }
 
 // ------------------------------------------------------------------------------- dense stage
+// Local projection of finished bases (Section 6, step 2): with R.d_V = V_i (|V_i| x (k+1))
+// filled, [Q^T A_PP Q | Q^T f_P] over the leading |P_i| rows, then the host copies of the
+// local block and load, and the request's statistics.
+static int project_local(mor_ctx* c, Arena& ar, const std::vector<Slot*>& sl, const std::vector<Live*>& done,
+                         int eig_iters) {
+  hipStream_t st = c->st;
+  const int ns = (int)sl.size();
+  GemmBatch gP;
+  for (int i = 0; i < ns; ++i) {
+    Slot& q = *sl[i];
+    const HostSub& h = *q.h;
+    SubResult& R = c->res[q.sd];
+    const int k1 = q.k_eff + 1;
+    launch_spmm64_rows(q.d->rp, q.d->col, q.A64, h.nP, h.nP, R.d_V, k1, k1, q.Yf, k1 + 1, st);
+    launch_copy_col(q.f, 1, q.Yf + k1, k1 + 1, h.nP, st);
+    gP.add(gd(k1, k1 + 1, h.nP, R.d_V, k1, 1, q.Yf, k1 + 1, 0, R.d_Pm, k1 + 1));
+  }
+  if (int rc = gemm_upload(c, gP, ar)) return rc;
+  gemm_run(c, gP, "project_local");
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(st));
+  for (int i = 0; i < ns; ++i) {
+    Slot& q = *sl[i];
+    SubResult& R = c->res[q.sd];
+    const int k1 = q.k_eff + 1;
+    std::vector<double> pm((size_t)k1 * (k1 + 1));
+    HIPCHK(hipMemcpy(pm.data(), R.d_Pm, 8 * pm.size(), hipMemcpyDeviceToHost));
+    R.Aii.assign((size_t)k1 * k1, 0.0);
+    R.bi.assign(k1, 0.0);
+    for (int a = 0; a < k1; ++a) {
+      for (int b = 0; b < k1; ++b)
+        R.Aii[(size_t)a * k1 + b] = 0.5 * (pm[(size_t)a * (k1 + 1) + b] + pm[(size_t)b * (k1 + 1) + a]);
+      R.bi[a] = pm[(size_t)a * (k1 + 1) + k1];
+    }
+    R.cg_a = done[i]->sys[0].iters + done[i]->iters_prev;
+    R.cg_k = done[i]->sys[1].iters;
+    R.refine = std::max(done[i]->sys[0].refines, done[i]->sys[1].refines);
+    R.eig = eig_iters;
+    R.reduced = done[i]->status == 0;
+  }
+  return 0;
+}
+
 static int dense_stage(mor_ctx* c, std::vector<Live*>& done) {
   hipStream_t st = c->st;
   const int ns = (int)done.size();
@@ -1404,7 +1795,7 @@ static int dense_stage(mor_ctx* c, std::vector<Live*>& done) {
     launch_scale_cols(q.Ub, q.s, d_sig + (size_t)i * 64, q.k_eff, q.MP, q.Bk, st);
   }
   launch_trsm_un(dds, ns, P_Bk, P_Wk, tmax, st);
-  GemmBatch gV, gP;
+  GemmBatch gV;
   for (int i = 0; i < ns; ++i) {
     Slot& q = *sl[i];
     const HostSub& h = *q.h;
@@ -1420,39 +1811,7 @@ static int dense_stage(mor_ctx* c, std::vector<Live*>& done) {
   }
   if ((rc = gemm_upload(c, gV, ar))) return rc;
   gemm_run(c, gV, "basis");
-  for (int i = 0; i < ns; ++i) {
-    Slot& q = *sl[i];
-    const HostSub& h = *q.h;
-    SubResult& R = c->res[q.sd];
-    const int k1 = q.k_eff + 1;
-    launch_spmm64_rows(q.d->rp, q.d->col, q.A64, h.nP, h.nP, R.d_V, k1, k1, q.Yf, k1 + 1, st);
-    launch_copy_col(q.f, 1, q.Yf + k1, k1 + 1, h.nP, st);
-    gP.add(gd(k1, k1 + 1, h.nP, R.d_V, k1, 1, q.Yf, k1 + 1, 0, R.d_Pm, k1 + 1));
-  }
-  if ((rc = gemm_upload(c, gP, ar))) return rc;
-  gemm_run(c, gP, "project_local");
-  HIPCHK(hipGetLastError());
-  HIPCHK(hipStreamSynchronize(st));
-  for (int i = 0; i < ns; ++i) {
-    Slot& q = *sl[i];
-    SubResult& R = c->res[q.sd];
-    const int k1 = q.k_eff + 1;
-    std::vector<double> pm((size_t)k1 * (k1 + 1));
-    HIPCHK(hipMemcpy(pm.data(), R.d_Pm, 8 * pm.size(), hipMemcpyDeviceToHost));
-    R.Aii.assign((size_t)k1 * k1, 0.0);
-    R.bi.assign(k1, 0.0);
-    for (int a = 0; a < k1; ++a) {
-      for (int b = 0; b < k1; ++b)
-        R.Aii[(size_t)a * k1 + b] = 0.5 * (pm[(size_t)a * (k1 + 1) + b] + pm[(size_t)b * (k1 + 1) + a]);
-      R.bi[a] = pm[(size_t)a * (k1 + 1) + k1];
-    }
-    R.cg_a = done[i]->sys[0].iters;
-    R.cg_k = done[i]->sys[1].iters;
-    R.refine = std::max(done[i]->sys[0].refines, done[i]->sys[1].refines);
-    R.eig = eig_it + 1;
-    R.reduced = done[i]->status == 0;
-  }
-  return 0;
+  return project_local(c, ar, sl, done, eig_it + 1);
 }
 
 static void engine_delete(MorEngine* e) { delete e; }
@@ -1468,10 +1827,13 @@ static MorEngine& engine_for(mor_ctx* c, int prec) {
   return *c->eng[k];
 }
 
-static uint64_t enqueue(mor_ctx* c, int sd, int rank, double tol, int prec) {
+static uint64_t enqueue(mor_ctx* c, int sd, int rank, double tol, int prec, int ls = 0,
+                        std::shared_ptr<const std::vector<double>> om = nullptr) {
   Req r;
   r.id = g_next_ticket++;
   r.sd = sd; r.rank = rank; r.tol = tol; r.prec = prec;
+  r.ls = ls;
+  r.om = std::move(om);
   engine_for(c, prec).pending.push_back(r);
   return r.id;
 }
@@ -1515,6 +1877,49 @@ extern "C" int mor_local_basis_batch(mor_ctx* c, int32_t n, const int32_t* sds, 
   }
   std::vector<uint64_t> ids(n);
   for (int i = 0; i < n; ++i) ids[i] = enqueue(c, sds[i], ranks[i], tols ? tols[i] : 0.0, c->opts.precision);
+  while (!engines_idle(c))
+    if (int rc = tick_all(c)) return rc;
+  int first_err = 0;
+  std::string msg = g_err;
+  for (int i = 0; i < n; ++i) {
+    bool pend;
+    const Req* r = find_req(c, ids[i], &pend);
+    const int st = r ? r->status : MOR_ESTATE;
+    if (st && !first_err) first_err = st;
+    if (k_eff_out) k_eff_out[i] = c->res[sds[i]].k_eff;
+  }
+  for (int k = 0; k < 2; ++k)
+    if (c->eng[k])
+      for (uint64_t id : ids) c->eng[k]->finished.erase(id);
+  if (first_err) return fail(first_err, msg);
+  return MOR_OK;
+}
+
+extern "C" int mor_local_basis_sketched(mor_ctx* c, int32_t n, const int32_t* sds, const int32_t* ranks,
+                                        const double* tols, int32_t l, const double* const* omega,
+                                        int32_t* k_eff_out) {
+  if (!c || n <= 0 || !sds || !ranks || !omega) return fail(MOR_EINVAL, "bad arguments");
+  if (c->opts.host_only) return fail(MOR_ESTATE, "context was created host_only");
+  if (l < 1 || l > 64) return fail(MOR_EINVAL, "sketch columns must be in 1..64");
+  if (c->opts.precision == MOR_FP32)
+    return fail(MOR_EINVAL, "the sketched variant needs FP64 solutions (MOR_FP64, MOR_FP32_REFINE or MOR_BF16_SPLIT)");
+  std::vector<char> seen(c->subs.size(), 0);
+  for (int i = 0; i < n; ++i) {
+    const int sd = sds[i];
+    if (sd < 0 || sd >= (int)c->subs.size()) return fail(MOR_EINVAL, "subdomain id out of range");
+    if (seen[sd]) return fail(MOR_EINVAL, "subdomain listed twice in one batch");
+    seen[sd] = 1;
+    const double tol = tols ? tols[i] : 0.0;
+    if (ranks[i] <= 0 && !(tol > 0.0)) return fail(MOR_EINVAL, "need rank > 0 or tol > 0");
+    if (!omega[i]) return fail(MOR_EINVAL, "null sketch");
+    if (c->subs[sd].nB < 1) return fail(MOR_EINVAL, "subdomain without interface nodes");
+  }
+  std::vector<uint64_t> ids(n);
+  for (int i = 0; i < n; ++i) {
+    const size_t M = (size_t)c->subs[sds[i]].nB;
+    auto om = std::make_shared<const std::vector<double>>(omega[i], omega[i] + M * l);
+    ids[i] = enqueue(c, sds[i], ranks[i], tols ? tols[i] : 0.0, c->opts.precision, l, std::move(om));
+  }
   while (!engines_idle(c))
     if (int rc = tick_all(c)) return rc;
   int first_err = 0;

@@ -62,6 +62,7 @@ struct CgSys {
   const int* hpe;      // padded II entries: CSR entry id or -1
   const uint16_t* hpp; // padded II entries: position in the tile halo
   const uint16_t* hself;
+  const double* Fd;    // dense FP64 right-hand sides (nI x ld) in place of -A_IB and f, or nullptr
 };
 
 // ---------------------------------------------------------------------------------
@@ -144,6 +145,14 @@ void launch_cg_zero(const CgSys* sys, const int2* cb, int ncb, hipStream_t s);
 void launch_cg_start(const CgSys* sys, const int2* cb, int ncb, int first, double tol2_outer, hipStream_t s);
 
 void launch_to_f64_block(const float* in, int ldi, double* out, int ldo, int rows, int cols, hipStream_t s);
+// randomized variant: sketch right-hand sides [-A_IB T | f | 0], [KW ; 0], P = A_BI X, and the
+// whitening V diag(th^-1/2) of a small eigendecomposition
+void launch_rhs_sketch(const int* rp, const int* col, const int* ii_end, const double* A, const double* f, int nI,
+                       const double* T, int l, double* F, int ld, hipStream_t s);
+void launch_rhs_rows(const double* KW, int nV, int c, int nI, double* F, int ld, hipStream_t s);
+void launch_bi_product(const int* rp, const int* col, const double* A, int nI, int nB, int MP, const double* X, int ldx,
+                       int c, double* P, hipStream_t s);
+void launch_whiten(const double* V, const double* th, int s, int r, double* out, hipStream_t st);
 // tiles: (descriptor, 64-row block of m_pad, 64-column block of kp)
 void launch_split_bf16(const SplitDesc* d, const int4* tiles, int ntiles, hipStream_t s);
 // tiles: (descriptor, ti, tj) with ti <= tj, 128 x 128 output blocks

@@ -207,9 +207,16 @@ __device__ __forceinline__ void column_reduce_add(double (*red)[64 * 4], const d
   }
 }
 
-// sparse right-hand side entries of row r: -A_IB[r, :] and the load column
+// right-hand side entries of row r: a dense FP64 block when given, else the sparse columns
+// -A_IB[r, :] and the load column
 template <typename TT, int V>
 __device__ __forceinline__ void rhs_row(const CgSys& S, int r, int c0, TT (&v)[V]) {
+  if (S.Fd != nullptr) {
+    const double* fr = S.Fd + (int64_t)r * S.ld + c0;
+#pragma unroll
+    for (int q = 0; q < V; ++q) v[q] = (TT)fr[q];
+    return;
+  }
 #pragma unroll
   for (int q = 0; q < V; ++q) v[q] = 0;
   const int e1 = S.rp[r + 1];
@@ -1112,6 +1119,82 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmDesc* __restrict__ descs
 }
 void launch_gemm(const GemmDesc* d, const int4* tiles, int ntiles, hipStream_t s) {
   if (ntiles > 0) hipLaunchKernelGGL(k_gemm, dim3(ntiles), dim3(256), 0, s, d, tiles);
+}
+
+// ------------------------------------------------------------------------ randomized variant
+// Right-hand sides of the sketch solve: F[r, j] = -(A_IB T)[r, j] for j < l (T = R_BB^-1 S, MP x
+// 64, ld 64), F[r, l] = f[r] (the zero-boundary load problem), zero up to ld.  One thread per
+// entry of the I x ld block.
+__global__ void k_rhs_sketch(const int* __restrict__ rp, const int* __restrict__ col, const int* __restrict__ ii_end,
+                             const double* __restrict__ A, const double* __restrict__ f, int nI, const double* __restrict__ T,
+                             int l, double* __restrict__ F, int ld) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (int64_t)nI * ld) return;
+  const int r = (int)(i / ld), j = (int)(i % ld);
+  double v = 0.0;
+  if (j < l) {
+    for (int e = ii_end[r]; e < rp[r + 1]; ++e) v -= A[e] * T[(int64_t)(col[e] - nI) * 64 + j];
+  } else if (j == l) {
+    v = f[r];
+  }
+  F[i] = v;
+}
+void launch_rhs_sketch(const int* rp, const int* col, const int* ii_end, const double* A, const double* f, int nI,
+                       const double* T, int l, double* F, int ld, hipStream_t s) {
+  const int64_t n = (int64_t)nI * ld;
+  if (n > 0)
+    hipLaunchKernelGGL(k_rhs_sketch, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, rp, col, ii_end, A, f, nI, T,
+                       l, F, ld);
+}
+
+// F (nI x ld) = [KW ; 0]: the first nV rows take KW's first c columns (KW: nV x 64), the
+// rest is zero.
+__global__ void k_rhs_rows(const double* __restrict__ KW, int nV, int c, int nI, double* __restrict__ F, int ld) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (int64_t)nI * ld) return;
+  const int r = (int)(i / ld), j = (int)(i % ld);
+  F[i] = (r < nV && j < c) ? KW[(int64_t)r * 64 + j] : 0.0;
+}
+void launch_rhs_rows(const double* KW, int nV, int c, int nI, double* F, int ld, hipStream_t s) {
+  const int64_t n = (int64_t)nI * ld;
+  if (n > 0) hipLaunchKernelGGL(k_rhs_rows, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, KW, nV, c, nI, F, ld);
+}
+
+// P (MP x 64) = A_BI X: row b of P is the B row nI + b of the local CSR times the I rows of X
+// (nI x ldx), columns j < c; rows b >= nB and columns j >= c are zero.
+__global__ void k_bi_product(const int* __restrict__ rp, const int* __restrict__ col, const double* __restrict__ A,
+                             int nI, int nB, int MP, const double* __restrict__ X, int ldx, int c, double* __restrict__ P) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (int64_t)MP * 64) return;
+  const int b = (int)(i >> 6), j = (int)(i & 63);
+  double v = 0.0;
+  if (b < nB && j < c) {
+    const int r = nI + b;
+    for (int e = rp[r]; e < rp[r + 1]; ++e) {
+      const int cc = col[e];
+      if (cc < nI) v += A[e] * X[(int64_t)cc * ldx + j];
+    }
+  }
+  P[i] = v;
+}
+void launch_bi_product(const int* rp, const int* col, const double* A, int nI, int nB, int MP, const double* X, int ldx,
+                       int c, double* P, hipStream_t s) {
+  const int64_t n = (int64_t)MP * 64;
+  hipLaunchKernelGGL(k_bi_product, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, rp, col, A, nI, nB, MP, X, ldx,
+                     c, P);
+}
+
+// Whitening of an eigendecomposition (V: s x s row-major, eigenvalues th descending):
+// out (s x 64, ld 64) = V[:, :r] diag(th^-1/2), zero columns from r on.
+__global__ void k_whiten(const double* __restrict__ V, const double* __restrict__ th, int s, int r,
+                         double* __restrict__ out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= s * 64) return;
+  const int a = i >> 6, j = i & 63;
+  out[i] = (j < r) ? V[a * s + j] / sqrt(th[j]) : 0.0;
+}
+void launch_whiten(const double* V, const double* th, int s, int r, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_whiten, dim3((s * 64 + 255) / 256), dim3(256), 0, st, V, th, s, r, out);
 }
 
 // ------------------------------------------------------------------------ split-precision Gram

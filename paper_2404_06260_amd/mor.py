@@ -19,7 +19,8 @@ MOR_OK, MOR_EINVAL, MOR_ENOMEM, MOR_ENOTCONV, MOR_ESTATE, MOR_EDEVICE = 0, -1, -
 MOR_FP64, MOR_FP32_REFINE, MOR_FP32, MOR_BF16_SPLIT = 0, 1, 2, 3
 PRECISIONS = {"fp64": MOR_FP64, "fp32_refine": MOR_FP32_REFINE, "fp32": MOR_FP32, "bf16_split": MOR_BF16_SPLIT}
 
-EXPORTED = ("mor_default_opts", "mor_create", "mor_local_basis", "mor_local_basis_batch", "mor_project",
+EXPORTED = ("mor_default_opts", "mor_create", "mor_local_basis", "mor_local_basis_batch", "mor_local_basis_sketched",
+            "mor_project",
             "mor_solve", "mor_submit", "mor_poll", "mor_drain", "mor_step", "mor_engine_stats", "mor_get_sizes", "mor_get_nodes",
             "mor_get_pairs", "mor_get_basis", "mor_get_sigma", "mor_get_local_block", "mor_get_reduced",
             "mor_get_reduced_solution", "mor_get_stats", "mor_timing_enable", "mor_timing_get",
@@ -77,6 +78,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "mor_create": (I32, [P, P, P, P, P]),
         "mor_local_basis": (I32, [P, I32, I32, D, P, P, I32]),
         "mor_local_basis_batch": (I32, [P, I32, P, P, P, P]),
+        "mor_local_basis_sketched": (I32, [P, I32, P, P, P, I32, P, P]),
         "mor_project": (I32, [P]),
         "mor_solve": (I32, [P, P, P]),
         "mor_submit": (I32, [P, I32, I32, D, I32, P]),
@@ -190,6 +192,23 @@ def mor_local_basis_batch(ctx, sds, ranks, tols=None):
     tl = None if tols is None else np.ascontiguousarray(tols, dtype=np.float64)
     k = np.zeros(sds.size, dtype=np.int32)
     _check(lib().mor_local_basis_batch(ctx, sds.size, _ptr(sds), _ptr(ranks), _ptr(tl), _ptr(k)))
+    return k
+
+
+def mor_local_basis_sketched(ctx, sds, ranks, omegas, tols=None):
+    """Randomized local reduction (the C entry point of the same name).  omegas[i]: the
+    random matrix of subdomain sds[i], (M_i, l) float64, rows in the subdomain's interface
+    node order; the same l for every subdomain."""
+    sds = np.ascontiguousarray(sds, dtype=np.int32)
+    ranks = np.ascontiguousarray(ranks, dtype=np.int32)
+    tl = None if tols is None else np.ascontiguousarray(tols, dtype=np.float64)
+    oms = [np.ascontiguousarray(o, dtype=np.float64) for o in omegas]
+    if len(oms) != sds.size or len({o.shape[1] for o in oms}) != 1:
+        raise ValueError("one (M_i, l) sketch per subdomain, same l")
+    ptrs = (ctypes.c_void_p * len(oms))(*[o.ctypes.data for o in oms])
+    k = np.zeros(sds.size, dtype=np.int32)
+    _check(lib().mor_local_basis_sketched(ctx, sds.size, _ptr(sds), _ptr(ranks), _ptr(tl), oms[0].shape[1],
+                                          ctypes.cast(ptrs, ctypes.c_void_p), _ptr(k)))
     return k
 
 
