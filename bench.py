@@ -163,6 +163,8 @@ def main():
     ap.add_argument("--spmm-rows", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
+    ap.add_argument("--sketch", type=int, default=0,
+                    help="randomized local reduction with this many sketch columns (1..64); 0: explicit SVD")
     ap.add_argument("--graph", type=int, default=-1,
                     help="capture each CG chunk in a HIP graph (1) or launch eagerly (0); -1: graphs for C3")
     ap.add_argument("--no-comparator", action="store_true",
@@ -213,7 +215,19 @@ def main():
     def progress(j, n_done, t):
         print(f"[bench] {n_done}/{n_sub} subdomains reduced ({t:.0f} s)", file=sys.stderr, flush=True)
 
+    sketches = None
+    if args.sketch > 0:   # seeded Gaussian S_i per subdomain, rows in the library's interface order
+        sketches = []
+        for i in range(n_sub):
+            nP, nV, nI, nB = mor.mor_get_sizes(m.ctx, i)
+            sketches.append(w.sketch_rows(p.mesh.n_nodes, mor.mor_get_nodes(m.ctx, i)[nI:nI + nB], args.sketch, i))
+        sk_ranks = p.ranks if p.ranks is not None else np.full(n_sub, p.rank)
+
     def step():
+        if sketches is not None:
+            mor.mor_local_basis_sketched(m.ctx, np.arange(n_sub), sk_ranks, sketches)
+            m.project()
+            return m.solve()
         if stream_step:
             from paper_2404_06260_amd import serve
             st = serve.make_stream(p, n_sub, float("inf"), seed_order=12, precisions=precs_c5,
@@ -311,6 +325,7 @@ def main():
         "config": {"workload": WORKLOAD_OF[args.config], "name": args.config, "subdomains": n_sub,
                    "precision": "fp32_refine | bf16_split, p = 1/2 each" if stream_step else prec,
                    "reduced_dim": int(nred), "hip_graph": use_graph,
+                   "local_svd": f"randomized, {args.sketch} sketch columns" if sketches is not None else "explicit",
                    "tiles": tile or "library defaults"},
         "roofline": {"bound": "hbm",
                      "kernel": spmm_kernel if use_graph else f"{spmm_kernel} (block-CG SpMM Q = A_II P)",
@@ -326,6 +341,7 @@ def main():
         "comparator": comparator,
         "mfma": mfma,
         "kernels": kernels,
+        "reduced_energy": energy_b,   # x^T b~ = ||u~||_A^2 (larger = closer to the FE solution)
         "cg_iters_max": [max(s["cg_iter_a"] for s in stats), max(s["cg_iter_k"] for s in stats)],
         "eig_iters_max": max(s["eig_iter"] for s in stats),
     }
