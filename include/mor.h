@@ -101,7 +101,9 @@ typedef struct {
                               176 rows of P staged in LDS) (0 = automatic) */
   int32_t spmm_vec;        /* halo tiles: 256-byte column slices per workgroup; row tiles: width in units of
                               64 columns, 1, 2 or 4 (0 = automatic) */
-  int32_t spmm_kind;       /* 0 = automatic (LDS halo tiles), 1 = LDS halo tiles, 2 = row tiles (spmm_rows x spmm_vec) */
+  int32_t spmm_kind;       /* 0 = automatic (LDS halo tiles, 128-byte slices), 1 = LDS halo tiles with 256-byte
+                              column slices, 3 = LDS halo tiles with 128-byte slices, 2 = row tiles
+                              (spmm_rows x spmm_vec) */
   int32_t stream_vec;      /* width of the streaming CG kernels' tiles in units of 64 columns */
   int32_t stream_blocks;   /* row aggregates per streaming tile (0 = automatic) */
   int32_t use_graph;       /* capture each CG chunk in a HIP graph and replay it */

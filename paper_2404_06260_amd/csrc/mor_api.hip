@@ -75,7 +75,7 @@ struct SubResult {
 
 struct mor_ctx {
   mor_opts opts;
-  int halo_cap = 64;   // LDS SpMM tiling: halo rows per tile (one of kHaloCaps)
+  int halo_cap = 96;   // LDS SpMM tiling: halo rows per tile (one of kHaloCaps)
   hipStream_t st = nullptr;
   HostMesh mesh;
   std::vector<double> kappa, fnodal;
@@ -266,9 +266,9 @@ extern "C" int mor_create(const mor_mesh* mesh, const mor_coeff* coeff, const mo
   c->ext.assign(sub->ext_tets, sub->ext_tets + c->ext_ptr[n]);
   c->in_core.assign(sub->in_core, sub->in_core + c->ext_ptr[n]);
   c->subs.resize(n);
-  // halo size of the LDS SpMM tiles: spmm_rows picks one of kHaloCaps (0: 64 rows, which
-  // leaves room for 7 workgroups per CU)
-  c->halo_cap = 64;
+  // halo size of the LDS SpMM tiles: spmm_rows picks one of kHaloCaps (0: 96 rows, with
+  // 128-byte slices 19 KB of LDS per workgroup)
+  c->halo_cap = 96;
   if (c->opts.spmm_kind != 2 && c->opts.spmm_rows > 0)
     for (int cap : kHaloCaps)
       if (cap <= c->opts.spmm_rows) c->halo_cap = cap;
@@ -474,7 +474,8 @@ struct TileCfg {
   int v = 4;    // elements per lane: tile width 64 v columns
   int rb = 32;  // rows (row tiles) or aggregates (block tiles) per tile
   int halo = 1; // SpMM only: LDS halo tiles (1) or row tiles (0)
-  int g = 4;    // SpMM halo tiles: 256-byte column slices per workgroup
+  int g = 4;    // SpMM halo tiles: column slices per workgroup
+  int cwb = 256;  // SpMM halo tiles: bytes of a row per column slice (128 or 256)
 };
 
 // ------------------------------------------------------------------------------- debug dumps
@@ -723,8 +724,9 @@ static int engine_init(mor_ctx* c, MorEngine& e, int elt) {
   for (int i = e.cnt_cap - 1; i >= 0; --i) e.cnt_free.push_back(i);
   const bool fp32 = elt == 4;
   e.sp.halo = c->opts.spmm_kind != 2;
+  e.sp.cwb = c->opts.spmm_kind == 1 ? 256 : 128;
   if (e.sp.halo) {
-    e.sp.g = c->opts.spmm_vec > 0 ? std::min(c->opts.spmm_vec, 64) : 8;   // slices per workgroup
+    e.sp.g = c->opts.spmm_vec > 0 ? std::min(c->opts.spmm_vec, 64) : 16;   // slices per workgroup
     e.sp.v = fp32 ? 4 : 2;   // the row kernels (init, residual, shadow)
   } else {
     e.sp.v = c->opts.spmm_vec > 0 ? c->opts.spmm_vec : 4;
@@ -804,7 +806,7 @@ static int engine_upload(mor_ctx* c, MorEngine& e, Launch& L) {
   }
   L.nbk = (int)t.size() - L.nsp;
   if (e.sp.halo) {
-    const int gw = (256 / e.elt) * e.sp.g;   // columns per slice group
+    const int gw = (e.sp.cwb / e.elt) * e.sp.g;   // columns per slice group
     for (int i = 0; i < n; ++i) {
       const int nt = L.sys[i]->nhtile;
       for (int c0 = 0; c0 < hs[i].ld; c0 += gw)
@@ -1002,7 +1004,7 @@ static int engine_chunk(mor_ctx* c, MorEngine& e) {
   // r'M^-1 r, beta and convergence, X += alpha P and P = M^-1 R + beta P
   auto iteration = [&](hipStream_t s) {
     if (e.sp.halo)
-      launch_cg_spmm_halo<T>(e.d_sys, La.hs, La.nhs, c->halo_cap, s);
+      launch_cg_spmm_halo<T>(e.d_sys, La.hs, La.nhs, c->halo_cap, e.sp.cwb, s);
     else
       launch_cg_spmm<T>(e.d_sys, La.sp, La.nsp, e.sp.rb, e.sp.v, s);
     launch_cg_alpha(e.d_sys, La.cb, La.ncb, s);
@@ -1015,7 +1017,7 @@ static int engine_chunk(mor_ctx* c, MorEngine& e) {
     // stream.  Its kernel arguments are the device lists of the last upload, which stay in
     // place (and are re-uploaded identically) while the set of systems is unchanged; any
     // change of systems, list addresses or sizes captures a new graph.
-    const std::vector<int64_t> key = {(int64_t)(intptr_t)e.d_sys, (int64_t)(intptr_t)e.d_tiles,
+    const std::vector<int64_t> key = {(int64_t)e.sp.cwb, (int64_t)(intptr_t)e.d_sys, (int64_t)(intptr_t)e.d_tiles,
                                       (int64_t)(intptr_t)e.d_cb, La.nsp, La.nbk, La.nhs, La.ncb, chunk,
                                       (int64_t)(intptr_t)La.hs, (int64_t)(intptr_t)La.bk, (int64_t)(intptr_t)La.cb,
                                       (int64_t)c->halo_cap};
@@ -1043,7 +1045,7 @@ static int engine_chunk(mor_ctx* c, MorEngine& e) {
     {
       ScopedTimer tm(c, "spmm", La.spmm_bytes);
       if (e.sp.halo)
-        launch_cg_spmm_halo<T>(e.d_sys, La.hs, La.nhs, c->halo_cap, st);
+        launch_cg_spmm_halo<T>(e.d_sys, La.hs, La.nhs, c->halo_cap, e.sp.cwb, st);
       else
         launch_cg_spmm<T>(e.d_sys, La.sp, La.nsp, e.sp.rb, e.sp.v, st);
     }

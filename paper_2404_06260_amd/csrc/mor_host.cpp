@@ -289,13 +289,17 @@ int build_sub(const HostMesh& m, const int32_t* ext, const uint8_t* in_core, int
   // Aggregates of at most 8 I rows for the block-Jacobi preconditioner of the CG: in id
   // order, an unaggregated row takes its unaggregated higher-numbered neighbours of the same
   // group (P, V\P, I\V).  On a Kuhn cube these are the 7 forward corners of a 2x2x2 cell
-  // block.  Rows are then renumbered aggregate by aggregate.
+  // block.  Rows are then renumbered aggregate by aggregate, the aggregates of each group in
+  // Morton (Z-curve) order of their first node, so that runs of consecutive aggregates (the
+  // SpMM tiles) are compact bricks rather than strips.
   {
     const int gb[4] = {0, s.nP, s.nV, s.nI};
     std::vector<int32_t> agg(s.nI, -1), order;
     std::vector<int32_t> bp{0};
+    int gfirst[4] = {0, 0, 0, 0};   // first aggregate of each group
     order.reserve(s.nI);
-    for (int g = 0; g < 3; ++g)
+    for (int g = 0; g < 3; ++g) {
+      gfirst[g] = (int)bp.size() - 1;
       for (int v = gb[g]; v < gb[g + 1]; ++v) {
         if (agg[v] >= 0) continue;
         const int b = (int)bp.size() - 1;
@@ -312,6 +316,44 @@ int build_sub(const HostMesh& m, const int32_t* ext, const uint8_t* in_core, int
         }
         bp.push_back((int32_t)order.size());
       }
+    }
+    gfirst[3] = (int)bp.size() - 1;
+    {
+      double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+      for (int i = 0; i < s.nI; ++i)
+        for (int a = 0; a < 3; ++a) {
+          const double x = m.xyz[3 * (int64_t)s.nodes[i] + a];
+          lo[a] = std::min(lo[a], x);
+          hi[a] = std::max(hi[a], x);
+        }
+      auto morton = [&](int node) {
+        uint64_t key = 0;
+        uint32_t qv[3];
+        for (int a = 0; a < 3; ++a) {
+          const double w = hi[a] > lo[a] ? (m.xyz[3 * (int64_t)node + a] - lo[a]) / (hi[a] - lo[a]) : 0.0;
+          qv[a] = (uint32_t)std::min(1023.0, std::max(0.0, w * 1023.0 + 0.5));
+        }
+        for (int bit = 9; bit >= 0; --bit)
+          for (int a = 0; a < 3; ++a) key = (key << 1) | ((qv[a] >> bit) & 1u);
+        return key;
+      };
+      const int na = (int)bp.size() - 1;
+      std::vector<uint64_t> key(na);
+      for (int b = 0; b < na; ++b) key[b] = morton(s.nodes[order[bp[b]]]);
+      std::vector<int32_t> ord2, bp2{0};
+      ord2.reserve(s.nI);
+      for (int g = 0; g < 3; ++g) {
+        std::vector<int32_t> ids(gfirst[g + 1] - gfirst[g]);
+        std::iota(ids.begin(), ids.end(), gfirst[g]);
+        std::stable_sort(ids.begin(), ids.end(), [&](int a, int b) { return key[a] < key[b]; });
+        for (int b : ids) {
+          for (int k = bp[b]; k < bp[b + 1]; ++k) ord2.push_back(order[k]);
+          bp2.push_back((int32_t)ord2.size());
+        }
+      }
+      order.swap(ord2);
+      bp.swap(bp2);
+    }
     std::vector<int32_t> nodes2(s.nL);
     for (int i = 0; i < s.nI; ++i) nodes2[i] = s.nodes[order[i]];
     for (int i = s.nI; i < s.nL; ++i) nodes2[i] = s.nodes[i];

@@ -123,7 +123,7 @@ void launch_cg_init(const CgSys* sys, const int4* tiles, int ntiles, int rb, int
 template <typename T>
 void launch_cg_spmm(const CgSys* sys, const int4* tiles, int ntiles, int rb, int v, hipStream_t s);
 template <typename T>
-void launch_cg_spmm_halo(const CgSys* sys, const int4* tiles, int ntiles, int cap, hipStream_t s);
+void launch_cg_spmm_halo(const CgSys* sys, const int4* tiles, int ntiles, int cap, int cwb, hipStream_t s);
 template <typename T>
 void launch_cg_residual64(const CgSys* sys, const int4* tiles, int ntiles, int rb, int v, hipStream_t s);
 template <typename T>

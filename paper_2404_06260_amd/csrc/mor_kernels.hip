@@ -383,13 +383,14 @@ __global__ __launch_bounds__(256) void k_cg_spmm(const CgSys* __restrict__ sys, 
 // XCD) share the halo rows in L2.  The tile's CSR (halo offsets and values, padded to chunks of
 // 8) is staged once; the next slice's loads are in flight while the current slice computes.
 // FP32: one column per lane, one row per wave step; FP64: 32 columns, two rows per wave step.
-template <typename T, int CAP>
+template <typename T, int CAP, int CWB>
 __global__ __launch_bounds__(256) void k_cg_spmm_halo(const CgSys* __restrict__ sys, const int4* __restrict__ tiles,
                                                       int ntiles) {
-  constexpr int CW = 256 / (int)sizeof(T);   // columns per slice
+  constexpr int CW = CWB / (int)sizeof(T);   // columns per slice (a slice is CWB bytes of a row)
   constexpr int RPW = 64 / CW;               // rows per wave step
   constexpr int CPC = 16 / (int)sizeof(T);   // elements per 16-byte staging chunk
-  constexpr int NST = (CAP * 16 + 255) / 256;        // staging chunks per thread
+  constexpr int CPR = CWB / 16;              // staging chunks per halo row
+  constexpr int NST = (CAP * CPR + 255) / 256;       // staging chunks per thread
   constexpr int NZC = halo_nnz_cap(CAP);             // padded CSR entries per tile
   constexpr int NNZ = (NZC + 255) / 256;             // padded CSR entries per thread
   __shared__ __attribute__((aligned(16))) T hp[CAP * CW];
@@ -408,14 +409,14 @@ __global__ __launch_bounds__(256) void k_cg_spmm_halo(const CgSys* __restrict__ 
   T* __restrict__ Q = (T*)S.Q;
   const T* __restrict__ val = (sizeof(T) == 4) ? (const T*)S.val32 : (const T*)S.val64;
   const int tid = threadIdx.x;
-  const int nchunk = ht.w * 16;
+  const int nchunk = ht.w * CPR;
   const int pb = gld(S.hrowp + ht.x);
   const int np = gld(S.hrowp + ht.x + ht.y) - pb;   // <= NZC (host-checked)
   int64_t hoff[NST];   // element offset of each staged chunk's halo row (slice 0), -1: none
 #pragma unroll
   for (int k = 0; k < NST; ++k) {
     const int i = k * 256 + tid;
-    hoff[k] = i < nchunk ? (int64_t)gld(S.halo + ht.z + (i >> 4)) * ld + (i & 15) * CPC : -1;
+    hoff[k] = i < nchunk ? (int64_t)gld(S.halo + ht.z + i / CPR) * ld + (i % CPR) * CPC : -1;
   }
 #pragma unroll
   for (int k = 0; k < NNZ; ++k) {
@@ -433,7 +434,7 @@ __global__ __launch_bounds__(256) void k_cg_spmm_halo(const CgSys* __restrict__ 
 #pragma unroll
     for (int k = 0; k < NST; ++k) {
       pv[k] = (u32x4){0u, 0u, 0u, 0u};
-      if (hoff[k] >= 0 && c0 + (k * 256 + tid & 15) * CPC < ld)
+      if (hoff[k] >= 0 && c0 + ((k * 256 + tid) % CPR) * CPC < ld)
         pv[k] = *((const MOR_GLOBAL u32x4*)(P + hoff[k] + c0));
     }
   };
@@ -458,7 +459,7 @@ __global__ __launch_bounds__(256) void k_cg_spmm_halo(const CgSys* __restrict__ 
 #pragma unroll
     for (int k = 0; k < NST; ++k) {
       const int i = k * 256 + tid;
-      if (i < nchunk) *reinterpret_cast<u32x4*>(&hp[(i >> 4) * CW + (i & 15) * CPC]) = pv[k];
+      if (i < nchunk) *reinterpret_cast<u32x4*>(&hp[(i / CPR) * CW + (i % CPR) * CPC]) = pv[k];
     }
     __syncthreads();
     if (c0 + CW < cend) issue(c0 + CW);
@@ -771,17 +772,22 @@ template <typename T>
 void launch_cg_spmm(const CgSys* sys, const int4* tiles, int ntiles, int rb, int v, hipStream_t s) {
   if (ntiles > 0) MOR_VSWITCH(T, v, k_cg_spmm, sys, tiles, ntiles, rb);
 }
-template <typename T>
-void launch_cg_spmm_halo(const CgSys* sys, const int4* tiles, int ntiles, int cap, hipStream_t s) {
-  if (ntiles <= 0) return;
+template <typename T, int CWB>
+static void launch_halo_cap(const CgSys* sys, const int4* tiles, int ntiles, int cap, hipStream_t s) {
   const dim3 g(xcd_grid(ntiles)), b(256);
   static_assert(kHaloCaps[0] == 48 && kHaloCaps[1] == 64 && kHaloCaps[2] == 96 && kHaloCaps[3] == 128 &&
                 kHaloCaps[4] == 176, "halo caps");
-  if (cap <= 48) hipLaunchKernelGGL((k_cg_spmm_halo<T, 48>), g, b, 0, s, sys, tiles, ntiles);
-  else if (cap <= 64) hipLaunchKernelGGL((k_cg_spmm_halo<T, 64>), g, b, 0, s, sys, tiles, ntiles);
-  else if (cap <= 96) hipLaunchKernelGGL((k_cg_spmm_halo<T, 96>), g, b, 0, s, sys, tiles, ntiles);
-  else if (cap <= 128) hipLaunchKernelGGL((k_cg_spmm_halo<T, 128>), g, b, 0, s, sys, tiles, ntiles);
-  else hipLaunchKernelGGL((k_cg_spmm_halo<T, 176>), g, b, 0, s, sys, tiles, ntiles);
+  if (cap <= 48) hipLaunchKernelGGL((k_cg_spmm_halo<T, 48, CWB>), g, b, 0, s, sys, tiles, ntiles);
+  else if (cap <= 64) hipLaunchKernelGGL((k_cg_spmm_halo<T, 64, CWB>), g, b, 0, s, sys, tiles, ntiles);
+  else if (cap <= 96) hipLaunchKernelGGL((k_cg_spmm_halo<T, 96, CWB>), g, b, 0, s, sys, tiles, ntiles);
+  else if (cap <= 128) hipLaunchKernelGGL((k_cg_spmm_halo<T, 128, CWB>), g, b, 0, s, sys, tiles, ntiles);
+  else hipLaunchKernelGGL((k_cg_spmm_halo<T, 176, CWB>), g, b, 0, s, sys, tiles, ntiles);
+}
+template <typename T>
+void launch_cg_spmm_halo(const CgSys* sys, const int4* tiles, int ntiles, int cap, int cwb, hipStream_t s) {
+  if (ntiles <= 0) return;
+  if (cwb == 128) launch_halo_cap<T, 128>(sys, tiles, ntiles, cap, s);
+  else launch_halo_cap<T, 256>(sys, tiles, ntiles, cap, s);
 }
 template <typename T>
 void launch_cg_update(const CgSys* sys, const int4* tiles, int ntiles, int rb, int v, hipStream_t s) {
@@ -806,7 +812,7 @@ void launch_cg_pstart(const CgSys* sys, const int4* tiles, int ntiles, int bpt, 
 #define MOR_INST(T)                                                                                      \
   template void launch_cg_init<T>(const CgSys*, const int4*, int, int, int, hipStream_t);       \
   template void launch_cg_spmm<T>(const CgSys*, const int4*, int, int, int, hipStream_t);       \
-  template void launch_cg_spmm_halo<T>(const CgSys*, const int4*, int, int, hipStream_t);       \
+  template void launch_cg_spmm_halo<T>(const CgSys*, const int4*, int, int, int, hipStream_t);  \
   template void launch_cg_update<T>(const CgSys*, const int4*, int, int, int, hipStream_t);     \
   template void launch_cg_direction<T>(const CgSys*, const int4*, int, int, int, hipStream_t);  \
   template void launch_cg_residual64<T>(const CgSys*, const int4*, int, int, int, hipStream_t); \
