@@ -116,6 +116,11 @@ typedef struct {
   void* hip_stream;        /* hipStream_t all work is ordered on; NULL = null stream */
   int32_t host_only;       /* 1: derive the decomposition on the host only (no device memory);
                               only mor_get_sizes / mor_get_nodes / mor_get_pairs may follow */
+  int32_t basis_update;    /* 1: the basis update of Section 6 step 2 after each local reduction:
+                              eigendecomposition of the stitched block Q^T A_ii Q, eigenvalues below
+                              update_drop * lambda_max removed, basis rescaled so the block is the
+                              identity (the basis then has dim <= k_eff + 1 columns) */
+  double update_drop;      /* relative drop tolerance of the basis update (0 = 1e-10) */
 } mor_opts;
 
 /* Fill `opts` with defaults (FP32_REFINE, cg_rtol 1e-5, refine_rtol 1e-8, ...). */
@@ -199,12 +204,14 @@ int mor_get_nodes(mor_ctx* ctx, int32_t sd, int32_t* out, int64_t cap);
 /* Neighbour pairs (i < j) coupled through A_0 on omega_0: pairs_out receives 2 ints per pair
  * (up to cap pairs); n_pairs the total count.  Works in host_only mode. */
 int mor_get_pairs(mor_ctx* ctx, int32_t* pairs_out, int64_t cap, int64_t* n_pairs);
-/* Basis on V_i: (nV x (k_eff+1)) row-major doubles, column 0 = q_0, then the
- * H1(omega_i)-orthonormal lifting modes; the stitched basis is its first nP rows. */
+/* Basis on V_i: (nV x dim) row-major doubles, dim = k_eff + 1: column 0 = q_0, then the
+ * H1(omega_i)-orthonormal lifting modes; after the basis update (mor_opts.basis_update) the
+ * dim columns of the updated basis instead.  The stitched basis is its first nP rows.
+ * The last argument receives dim - 1. */
 int mor_get_basis(mor_ctx* ctx, int32_t sd, double* out, int64_t cap, int32_t* k_eff);
 /* Leading singular values of the weighted lifting operator (up to cap). */
 int mor_get_sigma(mor_ctx* ctx, int32_t sd, double* out, int32_t cap, int32_t* n);
-/* Q_i^T A_ii Q_i ((k+1)^2, row-major) and Q_i^T f_i (k+1). */
+/* Q_i^T A_ii Q_i (dim^2, row-major) and Q_i^T f_i (dim). */
 int mor_get_local_block(mor_ctx* ctx, int32_t sd, double* Aii, double* bi, int64_t cap);
 /* After mor_project: the dense reduced matrix (n x n) and load (n). */
 int mor_get_reduced(mor_ctx* ctx, double* At, double* bt, int64_t cap, int64_t* n);

@@ -19,7 +19,9 @@ from . import decomp, fem
 
 
 def offsets(results) -> np.ndarray:
-    return np.concatenate([[0], np.cumsum([r.k_eff + 1 for r in results])]).astype(np.int64)
+    """Block offsets of the reduced system: each subdomain contributes its basis columns
+    (k_eff + 1, or fewer after the basis update)."""
+    return np.concatenate([[0], np.cumsum([r.Vloc.shape[1] for r in results])]).astype(np.int64)
 
 
 def omega0_stiffness(mesh, kappa, subdomains) -> sp.csr_matrix:
@@ -102,7 +104,7 @@ def dense_QtAQ(mesh, kappa, results):
     off = offsets(results)
     rows, cols, vals = [], [], []
     for i, r in enumerate(results):
-        k1 = r.k_eff + 1
+        k1 = r.Vloc.shape[1]
         rr = np.repeat(gmap[r.sets.P], k1)
         cc = np.tile(np.arange(off[i], off[i] + k1), r.sets.P.size)
         rows.append(rr)

@@ -158,6 +158,22 @@ def _stitch_and_project(lm: LocalMatrices, sets, sigma, k, q0, Phi) -> LocalResu
     return LocalResult(sets=sets, sigma=sigma, k_eff=k, q0=q0, Phi=Phi, Vloc=Vloc, Aii=Aii, bi=bi)
 
 
+def basis_update(res: LocalResult, drop: float = 1e-10) -> LocalResult:
+    """Section 6, step 2's update that diagonalises the diagonal block Q_i^T A_ii Q_i of the
+    reduced system.  The paper leaves the details to its source code; the reading taken here:
+    the eigendecomposition Q_i^T A_ii Q_i = U Lambda U^T of the stitched block, eigenvalues
+    below drop * lambda_max removed (numerically dependent stitched columns), and the basis
+    Q_i U_r Lambda_r^{-1/2}, whose diagonal block is the identity.  The load becomes
+    Lambda_r^{-1/2} U_r^T Q_i^T f.  The span changes only by the dropped directions."""
+    lam, U = la.eigh(res.Aii)
+    order = np.argsort(lam)[::-1]
+    lam, U = lam[order], U[:, order]
+    keep = lam > drop * lam[0]
+    T = U[:, keep] / np.sqrt(lam[keep])
+    return LocalResult(sets=res.sets, sigma=res.sigma, k_eff=res.k_eff, q0=res.q0, Phi=res.Phi,
+                       Vloc=res.Vloc @ T, Aii=np.eye(T.shape[1]), bi=T.T @ res.bi)
+
+
 def reduce_local_sketched(mesh, kappa, f_nodal, sets: decomp.LocalSets, rank: int | None, tol: float | None,
                           omega: np.ndarray, keep: bool = False):
     """The randomized variant of step 2 (Section 6, "Randomized numerical linear algebra").

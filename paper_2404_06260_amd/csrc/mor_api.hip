@@ -66,7 +66,8 @@ struct SubResult {
   int k_eff = 0;
   std::vector<double> sigma;
   std::vector<double> Aii, bi;
-  double* d_V = nullptr;   // nV x (k+1)
+  int dim = 0;             // basis columns: k_eff + 1, or fewer after the basis update
+  double* d_V = nullptr;   // nV x dim
   double* d_Pm = nullptr;  // (k+1) x (k+2): [Q^T A Q | Q^T f]
   int cg_a = 0, cg_k = 0, refine = 0, eig = 0;
 };
@@ -1480,6 +1481,81 @@ static bool engines_idle(mor_ctx* c) {
 }
 
 // ------------------------------------------------------------------------------- dense stage
+template <typename F>
+static double** ptr_table(mor_ctx* c, Arena& ar, const std::vector<Slot*>& sl, F get);
+static int small_eig(mor_ctx* c, Arena& ar, const std::vector<Slot*>& sl, const std::vector<int>& s_of,
+                     std::vector<std::vector<double>>& theta);
+
+// The basis update of Section 6, step 2, which diagonalises the diagonal blocks of the reduced
+// system.  Reading (the paper defers the details to its source code): eigendecomposition
+// Q^T A_ii Q = U Lambda U^T of each stitched block, eigenvalues below update_drop * lambda_max
+// removed, basis Q U_r Lambda_r^-1/2 (its block is the identity) and load Lambda_r^-1/2 U_r^T
+// Q^T f.  Runs on the blocks project_local left in R.Aii / R.d_Pm.
+static int basis_update(mor_ctx* c, const std::vector<Slot*>& sl) {
+  hipStream_t st = c->st;
+  const int ns = (int)sl.size();
+  size_t tiles = 0;
+  for (Slot* q : sl) tiles += (size_t)(q->h->nV + 63) / 64 + 4;
+  StageBuf buf(c, ns * (8 * sizeof(double*) + sizeof(int) + 8 * 64 + 4 * sizeof(GemmDesc)) + 2 * tiles * sizeof(int4) +
+                      32 * 256);
+  if (!buf.p) return fail(MOR_ENOMEM, "device allocation failed (basis update)");
+  Arena& ar = buf.ar;
+  const double drop = c->opts.update_drop > 0 ? c->opts.update_drop : 1e-10;
+  std::vector<int> s_of(ns);
+  for (int i = 0; i < ns; ++i) {
+    Slot& q = *sl[i];
+    SubResult& R = c->res[q.sd];
+    s_of[i] = R.dim;
+    HIPCHK(hipMemcpyAsync(q.H, R.Aii.data(), 8 * R.Aii.size(), hipMemcpyHostToDevice, st));
+  }
+  std::vector<std::vector<double>> th;
+  if (int rc = small_eig(c, ar, sl, s_of, th)) return rc;
+  GemmBatch gV, gB;
+  std::vector<double*> newV(ns), newb(ns);
+  std::vector<int> r(ns);
+  for (int i = 0; i < ns; ++i) {
+    Slot& q = *sl[i];
+    const HostSub& h = *q.h;
+    SubResult& R = c->res[q.sd];
+    r[i] = 0;
+    for (int j = 0; j < R.dim; ++j) r[i] += (th[i][j] > drop * th[i][0]) ? 1 : 0;
+    r[i] = std::max(r[i], 1);
+    launch_whiten(q.Ss, q.theta, R.dim, r[i], q.Bk, st);   // U_r Lambda_r^-1/2 (dim x 64)
+    newV[i] = (double*)palloc(c, 8 * (size_t)h.nV * r[i]);
+    newb[i] = (double*)ar.take(8 * 64);
+    if (!newV[i] || !newb[i]) return fail(MOR_ENOMEM, "device allocation failed (basis update)");
+    gV.add(gd(h.nV, r[i], R.dim, R.d_V, R.dim, 0, q.Bk, 64, 0, newV[i], r[i]));
+    gB.add(gd(r[i], 1, R.dim, q.Bk, 64, 1, R.d_Pm + R.dim, R.dim + 1, 0, newb[i], 1));
+  }
+  if (int rc = gemm_upload(c, gV, ar)) return rc;
+  if (int rc = gemm_upload(c, gB, ar)) return rc;
+  gemm_run(c, gV, "basis_update");
+  gemm_run(c, gB, "basis_update");
+  HIPCHK(hipStreamSynchronize(st));
+  for (int i = 0; i < ns; ++i) {
+    Slot& q = *sl[i];
+    SubResult& R = c->res[q.sd];
+    pfree(c, R.d_V);
+    R.d_V = newV[i];
+    R.dim = r[i];
+    R.Aii.assign((size_t)r[i] * r[i], 0.0);
+    for (int a = 0; a < r[i]; ++a) R.Aii[(size_t)a * r[i] + a] = 1.0;
+    R.bi.assign(r[i], 0.0);
+    HIPCHK(hipMemcpy(R.bi.data(), newb[i], 8 * r[i], hipMemcpyDeviceToHost));
+    // [I | b~] for the reduced assembly
+    std::vector<double> pm((size_t)r[i] * (r[i] + 1), 0.0);
+    for (int a = 0; a < r[i]; ++a) {
+      pm[(size_t)a * (r[i] + 1) + a] = 1.0;
+      pm[(size_t)a * (r[i] + 1) + r[i]] = R.bi[a];
+    }
+    pfree(c, R.d_Pm);
+    R.d_Pm = (double*)palloc(c, 8 * pm.size());
+    if (!R.d_Pm) return fail(MOR_ENOMEM, "device allocation failed (basis update)");
+    HIPCHK(hipMemcpy(R.d_Pm, pm.data(), 8 * pm.size(), hipMemcpyHostToDevice));
+  }
+  return 0;
+}
+
 // Local projection of finished bases (Section 6, step 2): with R.d_V = V_i (|V_i| x (k+1))
 // filled, [Q^T A_PP Q | Q^T f_P] over the leading |P_i| rows, then the host copies of the
 // local block and load, and the request's statistics.
@@ -1514,12 +1590,14 @@ static int project_local(mor_ctx* c, Arena& ar, const std::vector<Slot*>& sl, co
         R.Aii[(size_t)a * k1 + b] = 0.5 * (pm[(size_t)a * (k1 + 1) + b] + pm[(size_t)b * (k1 + 1) + a]);
       R.bi[a] = pm[(size_t)a * (k1 + 1) + k1];
     }
+    R.dim = k1;
     R.cg_a = done[i]->sys[0].iters + done[i]->iters_prev;
     R.cg_k = done[i]->sys[1].iters;
     R.refine = std::max(done[i]->sys[0].refines, done[i]->sys[1].refines);
     R.eig = eig_iters;
     R.reduced = done[i]->status == 0;
   }
+  if (c->opts.basis_update) return basis_update(c, sl);
   return 0;
 }
 
@@ -2014,7 +2092,7 @@ extern "C" int mor_project(mor_ctx* c) {
     if (!c->res[i].reduced) return fail(MOR_ESTATE, "subdomain " + std::to_string(i) + " has no basis yet");
   hipStream_t st = c->st;
   c->off.assign(n + 1, 0);
-  for (int i = 0; i < n; ++i) c->off[i + 1] = c->off[i] + c->res[i].k_eff + 1;
+  for (int i = 0; i < n; ++i) c->off[i + 1] = c->off[i] + c->res[i].dim;
   c->n_red = c->off[n];
   c->MPr = rup(c->n_red, 64);
   pfree(c, c->d_At);
@@ -2029,7 +2107,7 @@ extern "C" int mor_project(mor_ctx* c) {
   launch_pad_identity(c->d_At, (int)c->n_red, (int)c->MPr, st);
   launch_fill(c->d_bt, (int64_t)c->MPr * 64, 0.0, st);
   for (int i = 0; i < n; ++i) {
-    const int k1 = c->res[i].k_eff + 1;
+    const int k1 = c->res[i].dim;
     launch_scatter_block(c->res[i].d_Pm, k1, k1 + 1, c->d_At, c->MPr, c->off[i], st);
     launch_copy_col(c->res[i].d_Pm + k1, k1 + 1, c->d_bt + (size_t)c->off[i] * 64, 64, k1, st);
   }
@@ -2052,7 +2130,7 @@ extern "C" int mor_project(mor_ctx* c) {
     std::vector<int> ldv(n), k1(n);
     for (int i = 0; i < n; ++i) {
       vp[i] = c->res[i].d_V;
-      ldv[i] = k1[i] = c->res[i].k_eff + 1;
+      ldv[i] = k1[i] = c->res[i].dim;
     }
     const size_t bytes = sizeof(int4) * npairs + 4 * c->om0.trip.size() + sizeof(double*) * n + 4 * 3 * (size_t)n + 8 * 256;
     char* buf = (char*)dalloc(c, bytes);
@@ -2145,7 +2223,7 @@ extern "C" int mor_solve(mor_ctx* c, double* u_out, int64_t* n_reduced_out) {
   HIPCHK(hipMemcpyAsync(dx, c->x_host.data(), 8 * c->n_red, hipMemcpyHostToDevice, st));
   launch_fill(du, c->mesh.n_nodes, 0.0, st);
   for (size_t i = 0; i < c->subs.size(); ++i) {
-    const int k1 = c->res[i].k_eff + 1;
+    const int k1 = c->res[i].dim;
     launch_reconstruct(c->res[i].d_V, c->subs[i].nP, k1, dx + c->off[i], c->sdev[i].nodes, du, st);
   }
   HIPCHK(hipGetLastError());
@@ -2189,8 +2267,8 @@ extern "C" int mor_get_basis(mor_ctx* c, int32_t sd, double* out, int64_t cap, i
   if (!c || sd < 0 || sd >= (int)c->subs.size()) return fail(MOR_EINVAL, "bad subdomain");
   const SubResult& R = c->res[sd];
   if (!R.reduced) return fail(MOR_ESTATE, "subdomain not reduced");
-  if (k_eff) *k_eff = R.k_eff;
-  const size_t n = (size_t)c->subs[sd].nV * (R.k_eff + 1);
+  if (k_eff) *k_eff = R.dim - 1;
+  const size_t n = (size_t)c->subs[sd].nV * R.dim;
   if (out) {
     if ((size_t)cap < n) return fail(MOR_EINVAL, "output too small");
     HIPCHK(hipMemcpy(out, R.d_V, 8 * n, hipMemcpyDeviceToHost));

@@ -59,7 +59,7 @@ class MorOpts(ctypes.Structure):
                 ("stream_blocks", ctypes.c_int32), ("use_graph", ctypes.c_int32), ("dense_batch", ctypes.c_int32),
                 ("hbm_budget_bytes", ctypes.c_size_t),
                 ("dev_alloc", ALLOC_FN), ("dev_free", FREE_FN), ("alloc_user", ctypes.c_void_p),
-                ("hip_stream", ctypes.c_void_p), ("host_only", ctypes.c_int32)]
+                ("hip_stream", ctypes.c_void_p), ("host_only", ctypes.c_int32), ("basis_update", ctypes.c_int32), ("update_drop", ctypes.c_double)]
 
 
 def load_library(path: str = LIB_PATH) -> ctypes.CDLL:

@@ -10,7 +10,7 @@ import numpy as np
 import pytest
 
 import workloads as w
-from oracle import decomp, project, reduce, solve
+from oracle import decomp, fem, project, reduce, solve
 
 
 def test_partition_of_unity_and_ownership():
@@ -81,3 +81,52 @@ def test_galerkin_error_identity():
     lhs = out["red_err"] ** 2
     rhs = u @ out["b"] - out["x"] @ out["bt"]
     assert abs(lhs - rhs) < 1e-10 * (u @ out["b"])
+
+
+# --------------------------------------------------------------------------------------
+# the basis update of Section 6, step 2 (reading: whitening of the stitched diagonal block)
+
+def _results(p, **kw):
+    from oracle import reduce as oreduce
+    return oreduce.reduce_all(p, workers=1, **kw)
+
+
+def test_basis_update_without_drops_keeps_the_galerkin_solution():
+    """With nothing dropped the updated basis spans the same space, so the Galerkin solution
+    u~ is unchanged, while every diagonal block Q_i^T A_ii Q_i (recomputed here from the
+    updated stitched basis and A) is the identity."""
+    from oracle import reduce as oreduce
+    p = w.make_problem(10, (2, 2, 1), r=2, rank=4, kappa="lognormal", seed=3, name="upd")
+    res = _results(p)
+    upd = [oreduce.basis_update(r, drop=0.0) for r in res]
+    A, b, free, gmap = fem.global_system(p.mesh, p.kappa, p.f_nodal)
+    for r in upd:
+        P = gmap[r.sets.P]
+        Aii = r.Vloc.T @ (A[P][:, P] @ r.Vloc)
+        np.testing.assert_allclose(Aii, np.eye(Aii.shape[0]), atol=1e-10)
+        np.testing.assert_allclose(r.bi, r.Vloc.T @ b[P], rtol=1e-10, atol=1e-14)
+    outs = []
+    for rr in (res, upd):
+        At, bt, _ = project.reduced_system(p.mesh, p.kappa, p.subdomains, rr)
+        outs.append(project.reconstruct(p.mesh, rr, project.solve_reduced(At, bt)))
+    np.testing.assert_allclose(outs[1], outs[0], rtol=0, atol=1e-10 * np.abs(outs[0]).max())
+
+
+def test_basis_update_removes_dependent_columns_of_many_mode_bases():
+    """Keeping many modes (tolerance far below the spectrum) makes stitched columns nearly
+    dependent: the plain reduced matrix is then numerically singular.  After the update (drop
+    1e-10) it is the identity on the diagonal blocks and positive definite, and its solution
+    matches the eigenvalue-truncated (pseudo-inverse) solution of the plain system."""
+    from oracle import reduce as oreduce
+    p = w.make_problem(10, (2, 2, 1), r=2, rank=4, kappa="lognormal", seed=3, name="upd")
+    res = _results(p, rank=None, tol=1e-6)
+    upd = [oreduce.basis_update(r, drop=1e-10) for r in res]
+    assert sum(r.Vloc.shape[1] for r in upd) < sum(r.Vloc.shape[1] for r in res)
+    At0, bt0, _ = project.reduced_system(p.mesh, p.kappa, p.subdomains, res)
+    At1, bt1, _ = project.reduced_system(p.mesh, p.kappa, p.subdomains, upd)
+    np.linalg.cholesky(At1)
+    u1 = project.reconstruct(p.mesh, upd, project.solve_reduced(At1, bt1))
+    u0 = project.reconstruct(p.mesh, res, project.solve_reduced(At0, bt0, pinv_rtol=1e-12))
+    A, _, free, _ = fem.global_system(p.mesh, p.kappa, p.f_nodal)
+    d = (u1 - u0)[free]
+    assert np.sqrt(d @ (A @ d)) <= 1e-4 * np.sqrt(u0[free] @ (A @ u0[free]))
