@@ -204,3 +204,75 @@ def test_tolerance_mode_matches_oracle():
         assert rel < TOL_ENERGY["fp32_refine"], rel
     finally:
         m.close()
+
+
+def test_basis_update_keeps_the_solution_and_whitens_the_blocks():
+    """The basis update (Section 6, step 2; reading in the oracle's basis_update): in rank
+    mode nothing is dropped, so u~ equals the plain oracle's and every diagonal block of the
+    reduced matrix is the identity."""
+    from paper_2404_06260_amd import mor
+    p = _problem("small-lognormal")
+    ref = _oracle("small-lognormal", p)
+    g = _run_gpu(p, "fp64", basis_update=1)
+    m = g["ctx"]
+    try:
+        At, bt = mor.mor_get_reduced(m.ctx)
+        off = 0
+        for i in range(p.subdomains.n_sub):
+            A_i, b_i = mor.mor_get_local_block(m.ctx, i)
+            d = A_i.shape[0]
+            np.testing.assert_allclose(A_i, np.eye(d), atol=1e-12)
+            np.testing.assert_allclose(At[off:off + d, off:off + d], np.eye(d), atol=1e-9)
+            off += d
+        rel = _energy_rel(ref, g["u"])
+        _say(f"[gpu] basis update, rank mode: energy rel {rel:.3e}")
+        assert rel < TOL_ENERGY["fp64"], rel
+    finally:
+        m.close()
+
+
+def test_basis_update_with_many_modes_matches_oracle():
+    """Many modes (rank 45 on boxes with about 100 interface nodes): the stitched blocks become
+    ill-conditioned and the update drops their weakest directions.  The drop threshold is put
+    in a gap of the oracle's block eigenvalues (FP64 on both sides) so that both drop the same
+    ones; the reduced solutions then agree."""
+    import scipy.linalg as la
+    from oracle import project as oproj
+    from oracle import reduce as ored
+    from paper_2404_06260_amd import mor
+    p = w.make_problem(10, (2, 2, 1), r=2, rank=45, kappa="lognormal", seed=3, name="upd")
+    res = ored.reduce_all(p, rank=45, workers=4)
+    rel_ev = np.concatenate([np.sort(la.eigvalsh(r.Aii))[::-1] / la.eigvalsh(r.Aii).max() for r in res])
+    rel_ev = np.maximum(rel_ev, 1e-30)   # rounding can leave null directions slightly negative
+    cands = np.geomspace(1e-4, 1e-2, 81)
+    margin = [np.min(np.abs(np.log10(rel_ev) - np.log10(t))) for t in cands]
+    drop = float(cands[int(np.argmax(margin))])
+    assert max(margin) > 0.05
+    upd = [ored.basis_update(r, drop=drop) for r in res]
+    assert sum(r.Vloc.shape[1] for r in upd) < sum(r.Vloc.shape[1] for r in res)
+    At, bt, _ = oproj.reduced_system(p.mesh, p.kappa, p.subdomains, upd)
+    x = oproj.solve_reduced(At, bt)
+    ut = oproj.reconstruct(p.mesh, upd, x)
+    ref = dict(_oracle_fe(p))
+    ref["u_tilde"] = ut
+    import torch
+    torch.cuda.set_device(0)
+    m = mor.Mor(p, precision="fp64", refine_rtol=1e-11, basis_update=1, update_drop=drop)
+    try:
+        n = p.subdomains.n_sub
+        mor.mor_local_basis_batch(m.ctx, np.arange(n), np.full(n, 45, np.int32))
+        dims = [mor.mor_get_local_block(m.ctx, i)[0].shape[0] for i in range(n)]
+        assert dims == [r.Vloc.shape[1] for r in upd], (dims, [r.Vloc.shape[1] for r in upd])
+        m.project()
+        u, nred = m.solve()
+        rel = _energy_rel(ref, u)
+        _say(f"[gpu] basis update, rank 45 (drop {drop:.1e}): dims {dims}, energy rel {rel:.3e}")
+        assert rel < 1e-8, rel
+    finally:
+        m.close()
+
+
+def _oracle_fe(p):
+    from oracle import solve as osolve
+    u, A, b, free = osolve.fe_solution(p.mesh, p.kappa, p.f_nodal)
+    return dict(A=A, free=free)
