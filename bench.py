@@ -58,7 +58,7 @@ def cpu_baseline(problem, budget_s: float = 20.0):
                        f"full FP64 local reduction each, {el:.1f} s, scipy/LAPACK with {threads} threads")
 
 
-PROFILE = os.path.join(ROOT, "profiles", "k_cg_spmm_halo_48cube_lognormal_fp32refine.md")
+PROFILE = os.path.join(ROOT, "profiles", "k_cg_spmm_halo_cap96_slice128_48cube_lognormal_fp32refine.md")
 
 
 def kernel_source_hash(name: str) -> str:
@@ -203,9 +203,10 @@ def main():
     use_graph = (args.config == "C3") if args.graph < 0 else bool(args.graph)
     m = mor.Mor(p, precision=prec, use_graph=int(use_graph), **tile)
     halo = tile.get("spmm_kind", 0) != 2
-    spmm_cap = max([c for c in (48, 64, 96, 128, 176) if c <= tile.get("spmm_rows", 0)] or [64]) if halo else 0
+    spmm_cap = max([c for c in (48, 64, 96, 128, 176) if c <= tile.get("spmm_rows", 0)] or [96]) if halo else 0
+    spmm_cwb = 256 if tile.get("spmm_kind", 0) == 1 else 128   # bytes of a row per column slice
     elt = "double" if prec == "fp64" else "float"
-    spmm_kernel = (f"k_cg_spmm_halo<{elt}, {spmm_cap}>" if halo else
+    spmm_kernel = (f"k_cg_spmm_halo<{elt}, {spmm_cap}, {spmm_cwb}>" if halo else
                    f"k_cg_spmm<{elt}, {tile.get('spmm_vec', 4)}>")
     n_sub = p.subdomains.n_sub
 
@@ -331,8 +332,7 @@ def main():
                      "kernel": spmm_kernel if use_graph else f"{spmm_kernel} (block-CG SpMM Q = A_II P)",
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": (profiled_traffic(spmm_kernel, args.config) if spmm_cap == 64 and not use_graph
-                                 else None),
+                     "traffic": profiled_traffic(spmm_kernel, args.config) if not use_graph else None,
                      "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, calibrated)",
                      "avg_launch_ms": round(avg_ms, 4), "launches": n_launch,
                      "algorithmic_bytes_per_launch": round(bytes_per_launch)},
