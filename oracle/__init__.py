@@ -16,7 +16,9 @@ Modules
   project  memory-efficient Galerkin projection and reduced solve (Section 6, step 3)
   solve    the full FE solution and error measures (Sections 2 and 7.1)
 
-Parity unpinned: the generalized-eigenvalue basis update of Section 6, step 2
-(its details are only in the authors' code) is not implemented here.
+Parity unpinned against the paper: the basis update of Section 6, step 2 (its
+details are only in the authors' code).  `reduce.basis_update` implements one
+reading of it (whitening of the stitched diagonal block with a drop tolerance);
+it is pinned by identities, not by the paper.
 """
 from . import fem, decomp, reduce, project, solve  # noqa: F401

@@ -5,9 +5,10 @@ or Q.  Diagonal blocks come from the local step.  An off-diagonal block
 Q_i^T A_ij Q_j is non-zero only for neighbouring subdomains; its entries depend
 only on the elements of omega_0 (elements in two or more subdomains), so it is
 computed from a stiffness matrix A_0 assembled on omega_0 and the rows of Q_i
-and Q_j on the shared nodes.  The reduced system is then solved; the paper uses
-PCG with a diagonal preconditioner, here a dense Cholesky factorization gives
-the same solution.
+and Q_j on the shared nodes.  The reduced system is then solved: the paper uses
+conjugate gradients with a diagonal preconditioner (end of Section 6, step 3, and
+the scaling runs of Section 7), given here by `pcg_diag`; a dense Cholesky
+factorization (`solve_reduced`) gives the same solution.
 """
 from __future__ import annotations
 
@@ -87,6 +88,50 @@ def solve_reduced(At: np.ndarray, bt: np.ndarray, pinv_rtol: float | None = None
     w, U = la.eigh(At)
     keep = w > pinv_rtol * w.max()
     return U[:, keep] @ ((U[:, keep].T @ bt) / w[keep])
+
+
+def pcg_diag(At: np.ndarray, bt: np.ndarray, rtol: float = 1e-12, max_iter: int = 20000, on_iter=None):
+    """The paper's reduced solver (Section 6, step 3; Section 7): conjugate gradients on
+    A~ x = b~ preconditioned by the diagonal D of A~, from x = 0, in the textbook order
+    (Hestenes and Stiefel):
+
+        r = b, z = D^-1 r, p = z
+        repeat:  q = A p;  alpha = r.z / p.q;  x += alpha p;  r -= alpha q
+                 stop if ||r|| <= rtol ||b||
+                 z = D^-1 r;  beta = r.z(new) / r.z(old);  p = z + beta p
+
+    r is the recurrence residual.  Returns (x, iterations, ||r|| / ||b|| at the stop).
+    on_iter(k, x, r), if given, sees every iterate.  Raises if p.q <= 0 (A~ not SPD) or
+    when max_iter is reached."""
+    A = np.asarray(At, dtype=np.float64)
+    b = np.asarray(bt, dtype=np.float64)
+    dinv = 1.0 / np.diag(A)
+    x = np.zeros_like(b)
+    nb = np.linalg.norm(b)
+    if nb == 0.0:
+        return x, 0, 0.0
+    r = b.copy()
+    z = dinv * r
+    p = z.copy()
+    rz = r @ z
+    for k in range(1, max_iter + 1):
+        q = A @ p
+        pq = p @ q
+        if not pq > 0.0:
+            raise np.linalg.LinAlgError("p'Ap <= 0: the reduced matrix is not positive definite")
+        alpha = rz / pq
+        x = x + alpha * p
+        r = r - alpha * q
+        if on_iter is not None:
+            on_iter(k, x, r)
+        res = np.linalg.norm(r) / nb
+        if res <= rtol:
+            return x, k, res
+        z = dinv * r
+        rz_new = r @ z
+        p = z + (rz_new / rz) * p
+        rz = rz_new
+    raise RuntimeError(f"reduced PCG did not reach {rtol} in {max_iter} iterations")
 
 
 def reconstruct(mesh, results, x: np.ndarray) -> np.ndarray:

@@ -5,6 +5,10 @@
   nested spaces         the energy error does not increase with the rank
   projection            the memory-efficient Q^T A Q equals the directly formed product
   Galerkin identity     ||u - u~||_A^2 = u^T b - x^T Q^T b (Section 7.1)
+  reduced PCG           the diagonal-preconditioned CG of Section 6 step 3 against exact
+                        statements: one step on a diagonal matrix, LAPACK's solution, a
+                        monotone A-norm error, recurrence = true residual, invariance under
+                        diagonal scaling, and the Cholesky route on a real reduced system
 """
 import numpy as np
 import pytest
@@ -130,3 +134,76 @@ def test_basis_update_removes_dependent_columns_of_many_mode_bases():
     A, _, free, _ = fem.global_system(p.mesh, p.kappa, p.f_nodal)
     d = (u1 - u0)[free]
     assert np.sqrt(d @ (A @ d)) <= 1e-4 * np.sqrt(u0[free] @ (A @ u0[free]))
+
+
+# --------------------------------------------------------------------------------------
+# the reduced solver of Section 6, step 3: conjugate gradients with a diagonal preconditioner
+
+def _spd(n, cond, seed):
+    rng = np.random.default_rng(seed)
+    U, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    lam = np.geomspace(1.0, cond, n)
+    return (U * lam) @ U.T
+
+
+def test_pcg_solves_a_diagonal_system_in_one_step():
+    d = np.array([3.0, 0.5, 7.0, 2.0, 11.0])
+    b = np.array([1.0, -2.0, 0.25, 4.0, 3.0])
+    x, it, res = project.pcg_diag(np.diag(d), b, rtol=1e-14)
+    assert it == 1 and res < 1e-15
+    np.testing.assert_allclose(x, b / d, rtol=1e-15)
+
+
+def test_pcg_matches_lapack_with_monotone_energy_error():
+    n = 30
+    S = np.diag(np.geomspace(0.1, 10.0, n))           # row scaling: the diagonal matters
+    A = S @ _spd(n, 1e3, 5) @ S
+    b = np.random.default_rng(6).standard_normal(n)
+    xs = np.linalg.solve(A, b)
+    errs, gaps = [], []
+
+    def seen(k, x, r):
+        e = x - xs
+        errs.append(float(e @ A @ e))
+        gaps.append(float(np.linalg.norm(r - (b - A @ x)) / np.linalg.norm(b)))
+
+    x, it, res = project.pcg_diag(A, b, rtol=1e-12, on_iter=seen)
+    assert res <= 1e-12 and it <= 3 * n
+    np.testing.assert_allclose(x, xs, rtol=0, atol=1e-8 * np.abs(xs).max())
+    assert all(e2 <= e1 * (1 + 1e-9) for e1, e2 in zip(errs, errs[1:])), errs
+    assert max(gaps) < 1e-10, max(gaps)
+
+
+def test_pcg_is_invariant_under_diagonal_scaling():
+    """Diagonal preconditioning makes CG on A = S B S (B with unit diagonal) the same
+    iteration as plain CG on B: the A-norm errors of the iterates agree step by step."""
+    n = 24
+    B = _spd(n, 50.0, 7)
+    dB = np.sqrt(np.diag(B))
+    B = B / np.outer(dB, dB)                            # unit diagonal: its own preconditioner is I
+    S = np.diag(np.random.default_rng(8).uniform(0.2, 5.0, n))
+    A = S @ B @ S
+    c = np.random.default_rng(9).standard_normal(n)
+    b = S @ c                                           # A x = b  <=>  B (S x) = c
+    xa, xb = np.linalg.solve(A, b), np.linalg.solve(B, c)
+    ea, eb = [], []
+    project.pcg_diag(A, b, rtol=1e-10, on_iter=lambda k, x, r: ea.append(float((x - xa) @ A @ (x - xa))))
+    project.pcg_diag(B, c, rtol=1e-10, on_iter=lambda k, x, r: eb.append(float((x - xb) @ B @ (x - xb))))
+    m = min(len(ea), len(eb), 12)
+    np.testing.assert_allclose(ea[:m], eb[:m], rtol=1e-6)
+
+
+def test_pcg_on_a_reduced_system_matches_cholesky():
+    p = w.make_problem(10, (2, 2, 2), r=2, rank=6, kappa="lognormal", seed=12)
+    res = reduce.reduce_all(p, workers=1)
+    At, bt, _ = project.reduced_system(p.mesh, p.kappa, p.subdomains, res)
+    xc = project.solve_reduced(At, bt)
+    x, it, rel = project.pcg_diag(At, bt, rtol=1e-13)
+    assert rel <= 1e-13 and 0 < it < At.shape[0] + 50
+    np.testing.assert_allclose(x, xc, rtol=0, atol=1e-9 * np.abs(xc).max())
+    np.testing.assert_allclose(x @ bt, xc @ bt, rtol=1e-12)
+
+
+def test_pcg_rejects_an_indefinite_matrix():
+    with pytest.raises(np.linalg.LinAlgError):
+        project.pcg_diag(np.diag([2.0, -1.0]), np.array([1.0, 1.0]))
