@@ -121,6 +121,15 @@ typedef struct {
                               update_drop * lambda_max removed, basis rescaled so the block is the
                               identity (the basis then has dim <= k_eff + 1 columns) */
   double update_drop;      /* relative drop tolerance of the basis update (0 = 1e-10) */
+  int32_t reduced_solver;  /* solver of the reduced system Q^T A Q x = Q^T b:
+                              0 = dense FP64 Cholesky (mor_project stores the n x n matrix);
+                              1 = FP64 conjugate gradients with the diagonal preconditioner, the
+                                  paper's choice (end of Section 6 step 3, Section 7), on the
+                                  block-sparse matrix (one dense row slab per subdomain over itself
+                                  and its neighbours; no n x n storage) */
+  double reduced_rtol;     /* reduced_solver 1: stop when ||b~ - A~ x|| <= reduced_rtol ||b~|| for the
+                              recurrence residual (0 = 1e-12) */
+  int32_t reduced_max_iter;/* reduced_solver 1: iteration cap (0 = 20000); MOR_ENOTCONV beyond it */
 } mor_opts;
 
 /* Fill `opts` with defaults (FP32_REFINE, cg_rtol 1e-5, refine_rtol 1e-8, ...). */
@@ -169,12 +178,17 @@ int mor_local_basis_sketched(mor_ctx* ctx, int32_t n, const int32_t* sds, const 
 /* Galerkin projection Q^T A Q of the global system (eq. 6.1) without forming A
  * or Q: diagonal blocks from the local step, off-diagonal blocks from A_0
  * assembled on omega_0 and the interface rows of neighbouring bases.  Needs
- * every subdomain reduced (MOR_ESTATE otherwise). */
+ * every subdomain reduced (MOR_ESTATE otherwise).  Stored dense (reduced_solver 0)
+ * or as block-row slabs over the neighbour pairs (reduced_solver 1). */
 int mor_project(mor_ctx* ctx);
 
-/* Solve the reduced system (FP64 Cholesky) and write u~ = sum_i S_i Q_i x_i at
- * every mesh node into u_out (n_nodes doubles, host; zero at Dirichlet nodes).
- * n_reduced_out (may be NULL) receives dim of the reduced space. */
+/* Solve the reduced system (reduced_solver: FP64 Cholesky, or FP64 conjugate
+ * gradients with the diagonal preconditioner from x = 0) and write
+ * u~ = sum_i S_i Q_i x_i at every mesh node into u_out (n_nodes doubles, host;
+ * zero at Dirichlet nodes).  n_reduced_out (may be NULL) receives dim of the
+ * reduced space.  MOR_EDEVICE if the reduced matrix is not positive definite
+ * (a Cholesky pivot, p'A~p or a diagonal entry <= 0); MOR_ENOTCONV if the
+ * conjugate gradients reach reduced_max_iter first. */
 int mor_solve(mor_ctx* ctx, double* u_out, int64_t* n_reduced_out);
 
 /* ---- serving: continuous batching of local-reduction requests ---------------
@@ -213,10 +227,15 @@ int mor_get_basis(mor_ctx* ctx, int32_t sd, double* out, int64_t cap, int32_t* k
 int mor_get_sigma(mor_ctx* ctx, int32_t sd, double* out, int32_t cap, int32_t* n);
 /* Q_i^T A_ii Q_i (dim^2, row-major) and Q_i^T f_i (dim). */
 int mor_get_local_block(mor_ctx* ctx, int32_t sd, double* Aii, double* bi, int64_t cap);
-/* After mor_project: the dense reduced matrix (n x n) and load (n). */
+/* After mor_project: the dense reduced matrix (n x n, cap >= n*n; with reduced_solver 1
+ * it is expanded from the block-row slabs on the host) and load (n). */
 int mor_get_reduced(mor_ctx* ctx, double* At, double* bt, int64_t cap, int64_t* n);
 /* After mor_solve: the reduced coefficient vector x (n). */
 int mor_get_reduced_solution(mor_ctx* ctx, double* x, int64_t cap);
+/* After mor_solve: the solver used (0 Cholesky, 1 conjugate gradients), its iterations
+ * (0 for Cholesky) and ||r|| / ||b~|| of the recurrence residual it stopped at (conjugate
+ * gradients; 0 for Cholesky).  Any pointer may be NULL. */
+int mor_get_solve_info(mor_ctx* ctx, int32_t* solver, int32_t* iters, double* rel_residual);
 /* Per-solve statistics of the last local reduction of sd: CG iterations of the
  * A- and H1-systems, refinement passes, subspace iterations. */
 int mor_get_stats(mor_ctx* ctx, int32_t sd, int32_t* cg_iter_a, int32_t* cg_iter_k, int32_t* refine,
@@ -224,7 +243,8 @@ int mor_get_stats(mor_ctx* ctx, int32_t sd, int32_t* cg_iter_a, int32_t* cg_iter
 
 /* Per-kernel device timing with HIP events on the library's stream.
  * name: "spmm" (the block-CG sparse product), "cg_update", "cg_direction",
- * "gram", "schur", "potrf", "trsm", "eig", "assemble", "project", "solve".
+ * "gram", "schur", "potrf", "trsm", "eig", "assemble", "project", "solve"
+ * (the reduced solve; for conjugate gradients its work is 2 nnz(A~) flops per iteration).
  * Reports launches, total milliseconds and algorithmic bytes (spmm) or flops. */
 int mor_timing_enable(mor_ctx* ctx, int32_t on);
 int mor_timing_get(mor_ctx* ctx, const char* name, int64_t* launches, double* total_ms, double* work);

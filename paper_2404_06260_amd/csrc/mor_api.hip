@@ -96,8 +96,20 @@ struct mor_ctx {
   int64_t n_red = 0, MPr = 0;
   std::vector<int> off;
   double *d_At = nullptr, *d_bt = nullptr, *d_x = nullptr;
+  // block-sparse form (reduced_solver 1): row r of A~ is the slab entries val[rs[r] ..+ rwc[r].x)
+  // at the global columns ccol[rwc[r].y ..]; rdiag[r] = position of its diagonal entry
+  double* d_slab = nullptr;
+  int *d_ccol = nullptr, *d_rdiag = nullptr;
+  int64_t* d_rs = nullptr;
+  int2* d_rwc = nullptr;
+  std::vector<int> h_ccol;
+  std::vector<int64_t> h_rs;
+  std::vector<int2> h_rwc;
+  int64_t slab_len = 0;
   std::vector<double> x_host;
   int projected = 0, solved = 0;
+  int solve_iters = 0;
+  double solve_relres = 0.0;
   std::vector<void*> allocs;
   bool timing = false;
   std::map<std::string, TimerRec> timers;
@@ -215,6 +227,9 @@ extern "C" void mor_default_opts(mor_opts* o) {
   o->spmm_kind = 0;
   o->use_graph = 0;
   o->hbm_budget_bytes = 0;
+  o->reduced_solver = 0;
+  o->reduced_rtol = 1e-12;
+  o->reduced_max_iter = 20000;
 }
 
 extern "C" int mor_create(const mor_mesh* mesh, const mor_coeff* coeff, const mor_subdomains* sub,
@@ -233,6 +248,13 @@ extern "C" int mor_create(const mor_mesh* mesh, const mor_coeff* coeff, const mo
     delete c;
     return fail(MOR_EINVAL, "unknown precision mode");
   }
+  if (c->opts.reduced_solver < 0 || c->opts.reduced_solver > 1 || c->opts.reduced_rtol < 0 ||
+      c->opts.reduced_max_iter < 0) {
+    delete c;
+    return fail(MOR_EINVAL, "reduced_solver must be 0 or 1, reduced_rtol and reduced_max_iter >= 0");
+  }
+  if (c->opts.reduced_rtol == 0) c->opts.reduced_rtol = 1e-12;
+  if (c->opts.reduced_max_iter == 0) c->opts.reduced_max_iter = 20000;
   c->st = (hipStream_t)c->opts.hip_stream;
   HostMesh& m = c->mesh;
   m.n_nodes = mesh->n_nodes;
@@ -2091,29 +2113,104 @@ extern "C" int mor_project(mor_ctx* c) {
   for (int i = 0; i < n; ++i)
     if (!c->res[i].reduced) return fail(MOR_ESTATE, "subdomain " + std::to_string(i) + " has no basis yet");
   hipStream_t st = c->st;
+  const bool sparse = c->opts.reduced_solver == 1;
+  c->projected = c->solved = 0;
   c->off.assign(n + 1, 0);
   for (int i = 0; i < n; ++i) c->off[i + 1] = c->off[i] + c->res[i].dim;
   c->n_red = c->off[n];
   c->MPr = rup(c->n_red, 64);
-  pfree(c, c->d_At);
-  pfree(c, c->d_bt);
-  pfree(c, c->d_x);
-  c->d_At = (double*)palloc(c, 8 * (size_t)c->MPr * c->MPr);
+  const int npairs = (int)c->om0.pair_i.size();
+  for (void* p : {(void*)c->d_At, (void*)c->d_bt, (void*)c->d_x, (void*)c->d_slab, (void*)c->d_ccol,
+                  (void*)c->d_rdiag, (void*)c->d_rs, (void*)c->d_rwc})
+    pfree(c, p);
+  c->d_At = c->d_bt = c->d_x = c->d_slab = nullptr;
+  c->d_ccol = c->d_rdiag = nullptr;
+  c->d_rs = nullptr;
+  c->d_rwc = nullptr;
+  // where each block goes: dense rows of length MPr, or per-subdomain slabs over the neighbours
+  std::vector<int64_t> dbase(n);   // element offset of block (i, i)
+  std::vector<int64_t> dld(n);     // row length of subdomain i's rows
+  std::vector<PairOut> pout(npairs);
+  if (sparse) {
+    std::vector<std::vector<int>> nb(n);
+    for (int i = 0; i < n; ++i) nb[i].push_back(i);
+    for (int p = 0; p < npairs; ++p) {
+      nb[c->om0.pair_i[p]].push_back(c->om0.pair_j[p]);
+      nb[c->om0.pair_j[p]].push_back(c->om0.pair_i[p]);
+    }
+    std::vector<std::map<int, int>> coff(n);   // column offset of neighbour j within subdomain i's slab
+    std::vector<int64_t> sbase(n);
+    c->h_ccol.clear();
+    c->h_rs.assign(c->n_red, 0);
+    c->h_rwc.assign(c->n_red, make_int2(0, 0));
+    std::vector<int> rdiag(c->n_red);
+    int64_t len = 0;
+    for (int i = 0; i < n; ++i) {
+      std::sort(nb[i].begin(), nb[i].end());
+      nb[i].erase(std::unique(nb[i].begin(), nb[i].end()), nb[i].end());
+      const int cbase = (int)c->h_ccol.size();
+      int W = 0;
+      for (int j : nb[i]) {
+        coff[i][j] = W;
+        for (int b = 0; b < c->res[j].dim; ++b) c->h_ccol.push_back(c->off[j] + b);
+        W += c->res[j].dim;
+      }
+      sbase[i] = len;
+      dld[i] = W;
+      dbase[i] = len + coff[i][i];
+      for (int a = 0; a < c->res[i].dim; ++a) {
+        const int64_t r = c->off[i] + a;
+        c->h_rs[r] = len + (int64_t)a * W;
+        c->h_rwc[r] = make_int2(W, cbase);
+        rdiag[r] = coff[i][i] + a;
+      }
+      len += (int64_t)c->res[i].dim * W;
+    }
+    if (c->h_ccol.size() > (size_t)INT32_MAX) return fail(MOR_EINVAL, "reduced system too large for int32 columns");
+    c->slab_len = len;
+    for (int p = 0; p < npairs; ++p) {
+      const int i = c->om0.pair_i[p], j = c->om0.pair_j[p];
+      pout[p] = PairOut{sbase[i] + coff[i][j], sbase[j] + coff[j][i], (int)dld[i], (int)dld[j]};
+    }
+    c->d_slab = (double*)palloc(c, 8 * (size_t)std::max<int64_t>(1, len));
+    if (!c->d_slab) return fail(MOR_ENOMEM, "device allocation failed (reduced slabs)");
+    if (upload(c, &c->d_ccol, c->h_ccol.data(), c->h_ccol.size()) ||
+        upload(c, &c->d_rs, c->h_rs.data(), c->h_rs.size()) ||
+        upload(c, &c->d_rwc, c->h_rwc.data(), c->h_rwc.size()) || upload(c, &c->d_rdiag, rdiag.data(), rdiag.size()))
+      return fail(MOR_ENOMEM, "device allocation failed (reduced pattern)");
+    HIPCHK(hipStreamSynchronize(st));   // rdiag is read by the copy
+  } else {
+    c->d_At = (double*)palloc(c, 8 * (size_t)c->MPr * c->MPr);
+    if (!c->d_At) return fail(MOR_ENOMEM, "device allocation failed (reduced system)");
+    for (int i = 0; i < n; ++i) {
+      dbase[i] = (int64_t)c->off[i] * c->MPr + c->off[i];
+      dld[i] = c->MPr;
+    }
+    for (int p = 0; p < npairs; ++p) {
+      const int i = c->om0.pair_i[p], j = c->om0.pair_j[p];
+      pout[p] = PairOut{(int64_t)c->off[i] * c->MPr + c->off[j], (int64_t)c->off[j] * c->MPr + c->off[i],
+                        (int)c->MPr, (int)c->MPr};
+    }
+  }
   c->d_bt = (double*)palloc(c, 8 * (size_t)c->MPr * 64);
   c->d_x = (double*)palloc(c, 8 * (size_t)c->MPr * 64);
-  if (!c->d_At || !c->d_bt || !c->d_x) return fail(MOR_ENOMEM, "device allocation failed (reduced system)");
+  if (!c->d_bt || !c->d_x) return fail(MOR_ENOMEM, "device allocation failed (reduced system)");
   ScopedTimer tm(c, "project", 0);
-  launch_fill(c->d_At, (int64_t)c->MPr * c->MPr, 0.0, st);
-  launch_pad_identity(c->d_At, (int)c->n_red, (int)c->MPr, st);
+  double* out = sparse ? c->d_slab : c->d_At;
+  if (sparse) {
+    launch_fill(c->d_slab, c->slab_len, 0.0, st);
+  } else {
+    launch_fill(c->d_At, (int64_t)c->MPr * c->MPr, 0.0, st);
+    launch_pad_identity(c->d_At, (int)c->n_red, (int)c->MPr, st);
+  }
   launch_fill(c->d_bt, (int64_t)c->MPr * 64, 0.0, st);
   for (int i = 0; i < n; ++i) {
     const int k1 = c->res[i].dim;
-    launch_scatter_block(c->res[i].d_Pm, k1, k1 + 1, c->d_At, c->MPr, c->off[i], st);
+    launch_scatter_block(c->res[i].d_Pm, k1, k1 + 1, out, dbase[i], dld[i], st);
     launch_copy_col(c->res[i].d_Pm + k1, k1 + 1, c->d_bt + (size_t)c->off[i] * 64, 64, k1, st);
   }
   // A_0 on omega_0, then every neighbour pair
   const HostSub& h0 = c->om0.sub;
-  const int npairs = (int)c->om0.pair_i.size();
   if (npairs > 0) {
     double* A0 = (double*)dalloc(c, 8 * (size_t)std::max(1, h0.rp[h0.nL]));
     if (!A0) return fail(MOR_ENOMEM, "device allocation failed (A_0)");
@@ -2132,7 +2229,8 @@ extern "C" int mor_project(mor_ctx* c) {
       vp[i] = c->res[i].d_V;
       ldv[i] = k1[i] = c->res[i].dim;
     }
-    const size_t bytes = sizeof(int4) * npairs + 4 * c->om0.trip.size() + sizeof(double*) * n + 4 * 3 * (size_t)n + 8 * 256;
+    const size_t bytes = sizeof(int4) * npairs + 4 * c->om0.trip.size() + sizeof(double*) * n + 4 * 2 * (size_t)n +
+                         sizeof(PairOut) * npairs + 8 * 256;
     char* buf = (char*)dalloc(c, bytes);
     if (!buf) {
       dfree(c, A0);
@@ -2144,8 +2242,8 @@ extern "C" int mor_project(mor_ctx* c) {
     double** d_vp = (double**)ar.take(sizeof(double*) * n);
     int* d_ldv = (int*)ar.take(4 * n);
     int* d_k1 = (int*)ar.take(4 * n);
-    int* d_off = (int*)ar.take(4 * n);
-    if (!d_off) {
+    PairOut* d_out = (PairOut*)ar.take(sizeof(PairOut) * npairs);
+    if (!d_out) {
       dfree(c, buf);
       dfree(c, A0);
       return fail(MOR_ENOMEM, "arena exhausted (pairs)");
@@ -2155,8 +2253,8 @@ extern "C" int mor_project(mor_ctx* c) {
     HIPCHK(hipMemcpyAsync(d_vp, vp.data(), sizeof(double*) * n, hipMemcpyHostToDevice, st));
     HIPCHK(hipMemcpyAsync(d_ldv, ldv.data(), 4 * n, hipMemcpyHostToDevice, st));
     HIPCHK(hipMemcpyAsync(d_k1, k1.data(), 4 * n, hipMemcpyHostToDevice, st));
-    HIPCHK(hipMemcpyAsync(d_off, c->off.data(), 4 * n, hipMemcpyHostToDevice, st));
-    launch_pair_project(d_range, d_trip, A0, d_vp, d_ldv, d_k1, d_off, c->d_At, c->MPr, npairs, st);
+    HIPCHK(hipMemcpyAsync(d_out, pout.data(), sizeof(PairOut) * npairs, hipMemcpyHostToDevice, st));
+    launch_pair_project(d_range, d_trip, A0, d_vp, d_ldv, d_k1, d_out, out, npairs, st);
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(st));
     dfree(c, buf);
@@ -2167,15 +2265,108 @@ extern "C" int mor_project(mor_ctx* c) {
   return MOR_OK;
 }
 
+// u~ = sum_i S_i Q_i x_i at every mesh node from c->x_host
+static int reconstruct_solution(mor_ctx* c, double* u_out) {
+  hipStream_t st = c->st;
+  double* du = (double*)dalloc(c, 8 * (size_t)c->mesh.n_nodes);
+  double* dx = (double*)dalloc(c, 8 * (size_t)std::max<int64_t>(1, c->n_red));
+  if (!du || !dx) {
+    dfree(c, du);
+    dfree(c, dx);
+    return fail(MOR_ENOMEM, "device allocation failed (reconstruction)");
+  }
+  HIPCHK(hipMemcpyAsync(dx, c->x_host.data(), 8 * c->n_red, hipMemcpyHostToDevice, st));
+  launch_fill(du, c->mesh.n_nodes, 0.0, st);
+  for (size_t i = 0; i < c->subs.size(); ++i) {
+    const int k1 = c->res[i].dim;
+    launch_reconstruct(c->res[i].d_V, c->subs[i].nP, k1, dx + c->off[i], c->sdev[i].nodes, du, st);
+  }
+  HIPCHK(hipGetLastError());
+  if (u_out) HIPCHK(hipMemcpyAsync(u_out, du, 8 * (size_t)c->mesh.n_nodes, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  dfree(c, dx);
+  dfree(c, du);
+  return MOR_OK;
+}
+
+// The reduced system by conjugate gradients with the diagonal preconditioner on the
+// block-row slabs (end of Section 6 step 3; Section 7), from x = 0.  The iterations run in
+// chunks of launches; between chunks the host reads the stop flag.
+static int solve_pcg(mor_ctx* c, double* u_out, int64_t* n_reduced_out) {
+  hipStream_t st = c->st;
+  const int n = (int)c->n_red;
+  c->x_host.assign(n, 0.0);
+  c->solve_iters = 0;
+  c->solve_relres = 0.0;
+  if (n > 0) {
+    const size_t bytes = 8 * 6 * (size_t)rup(n, 64) + 8 * 16 + 4 * 16 + 1024;
+    char* buf = (char*)dalloc(c, bytes);
+    if (!buf) return fail(MOR_ENOMEM, "device allocation failed (reduced solve)");
+    struct G { mor_ctx* c; void* p; ~G() { (void)hipStreamSynchronize(c->st); dfree(c, p); } } guard{c, buf};
+    Arena ar{buf, bytes, 0};
+    RpcgDev d{};
+    d.val = c->d_slab;
+    d.ccol = c->d_ccol;
+    d.rs = c->d_rs;
+    d.rwc = c->d_rwc;
+    d.rdiag = c->d_rdiag;
+    d.b = c->d_bt;
+    d.bstride = 64;
+    double* v[6];
+    for (auto& p : v) p = (double*)ar.take(8 * (size_t)rup(n, 64));
+    d.x = v[0]; d.r = v[1]; d.z = v[2]; d.p = v[3]; d.q = v[4]; d.dinv = v[5];
+    d.sc = (double*)ar.take(8 * 16);
+    d.state = (int*)ar.take(4 * 16);
+    if (!d.state) return fail(MOR_ENOMEM, "arena exhausted (reduced solve)");
+    const double nnz = (double)c->slab_len;
+    ScopedTimer tm(c, "solve", 0.0);
+    const double tol2 = c->opts.reduced_rtol * c->opts.reduced_rtol;
+    const int chunk = 32, cap = c->opts.reduced_max_iter;
+    launch_rpcg_setup(d, n, st);
+    int hs[4] = {0, 0, 0, 0};
+    for (int it = 0; it < cap;) {
+      const int m = std::min(chunk, cap - it);
+      for (int k = 0; k < m; ++k) launch_rpcg_iteration(d, n, it + k, tol2, st);
+      it += m;
+      HIPCHK(hipGetLastError());
+      HIPCHK(hipMemcpyAsync(hs, d.state, sizeof(hs), hipMemcpyDeviceToHost, st));
+      HIPCHK(hipStreamSynchronize(st));
+      if (hs[0] || hs[2]) break;
+    }
+    tm.work = 2.0 * nnz * hs[1];
+    if (hs[2] == 2) return fail(MOR_EDEVICE, "reduced matrix has a diagonal entry <= 0");
+    if (hs[2] == 1)
+      return fail(MOR_EDEVICE, "reduced matrix is not positive definite (p'Ap <= 0 at iteration " +
+                                   std::to_string(hs[1] + 1) + ")");
+    double sc[10];
+    HIPCHK(hipMemcpy(sc, d.sc, sizeof(sc), hipMemcpyDeviceToHost));
+    c->solve_iters = hs[1];
+    const int last = hs[1] > 0 ? (hs[1] - 1) % 3 : 2;
+    c->solve_relres = sc[9] > 0 ? std::sqrt(std::max(0.0, sc[6 + last]) / sc[9]) : 0.0;
+    if (!hs[0])
+      return fail(MOR_ENOTCONV, "reduced conjugate gradients: ||r||/||b|| = " + std::to_string(c->solve_relres) +
+                                    " after " + std::to_string(hs[1]) + " iterations");
+    HIPCHK(hipMemcpy(c->x_host.data(), d.x, 8 * (size_t)n, hipMemcpyDeviceToHost));
+  }
+  if (int rc = reconstruct_solution(c, u_out)) return rc;
+  if (n_reduced_out) *n_reduced_out = c->n_red;
+  c->solved = 1;
+  return MOR_OK;
+}
+
 extern "C" int mor_solve(mor_ctx* c, double* u_out, int64_t* n_reduced_out) {
   if (!c) return fail(MOR_EINVAL, "null context");
   if (c->opts.host_only) return fail(MOR_ESTATE, "context was created host_only");
   if (!c->projected) return fail(MOR_ESTATE, "mor_project must run first");
+  c->solved = 0;
+  if (c->opts.reduced_solver == 1) return solve_pcg(c, u_out, n_reduced_out);
+  c->solve_iters = 0;
+  c->solve_relres = 0.0;
   hipStream_t st = c->st;
   const int64_t MP = c->MPr;
   const int T = (int)(MP / 64);
   const size_t bytes = 8 * (size_t)MP * MP + 8 * (size_t)T * 4096 + 64 + sizeof(DenseSub) + 2 * sizeof(TrsmDesc) +
-                       2 * sizeof(double*) + 8 * (size_t)c->mesh.n_nodes + 8 * (size_t)MP * 64 + 8192;
+                       2 * sizeof(double*) + 8 * (size_t)MP * 64 + 8192;
   char* buf = (char*)dalloc(c, bytes);
   if (!buf) return fail(MOR_ENOMEM, "device allocation failed (reduced solve)");
   struct G { mor_ctx* c; void* p; ~G() { (void)hipStreamSynchronize(c->st); dfree(c, p); } } guard{c, buf};
@@ -2186,8 +2377,7 @@ extern "C" int mor_solve(mor_ctx* c, double* u_out, int64_t* n_reduced_out) {
   DenseSub* dd = (DenseSub*)ar.take(sizeof(DenseSub));
   TrsmDesc* td = (TrsmDesc*)ar.take(2 * sizeof(TrsmDesc));
   double** pb = (double**)ar.take(2 * sizeof(double*));
-  double* du = (double*)ar.take(8 * (size_t)c->mesh.n_nodes);
-  if (!du) return fail(MOR_ENOMEM, "arena exhausted (reduced solve)");
+  if (!pb) return fail(MOR_ENOMEM, "arena exhausted (reduced solve)");
   ScopedTimer tm(c, "solve", (double)MP * MP * MP / 3.0);
   HIPCHK(hipMemcpyAsync(F, c->d_At, 8 * (size_t)MP * MP, hipMemcpyDeviceToDevice, st));
   launch_fill_i(info, 16, 0, st);
@@ -2217,19 +2407,7 @@ extern "C" int mor_solve(mor_ctx* c, double* u_out, int64_t* n_reduced_out) {
   HIPCHK(hipStreamSynchronize(st));
   c->x_host.assign(c->n_red, 0.0);
   for (int64_t i = 0; i < c->n_red; ++i) c->x_host[i] = xs[(size_t)i * 64];
-  // u~ = sum_i S_i Q_i x_i
-  double* dx = (double*)dalloc(c, 8 * (size_t)std::max<int64_t>(1, c->n_red));
-  if (!dx) return fail(MOR_ENOMEM, "device allocation failed (x)");
-  HIPCHK(hipMemcpyAsync(dx, c->x_host.data(), 8 * c->n_red, hipMemcpyHostToDevice, st));
-  launch_fill(du, c->mesh.n_nodes, 0.0, st);
-  for (size_t i = 0; i < c->subs.size(); ++i) {
-    const int k1 = c->res[i].dim;
-    launch_reconstruct(c->res[i].d_V, c->subs[i].nP, k1, dx + c->off[i], c->sdev[i].nodes, du, st);
-  }
-  HIPCHK(hipGetLastError());
-  if (u_out) HIPCHK(hipMemcpyAsync(u_out, du, 8 * (size_t)c->mesh.n_nodes, hipMemcpyDeviceToHost, st));
-  HIPCHK(hipStreamSynchronize(st));
-  dfree(c, dx);
+  if (int rc = reconstruct_solution(c, u_out)) return rc;
   if (n_reduced_out) *n_reduced_out = c->n_red;
   c->solved = 1;
   return MOR_OK;
@@ -2300,13 +2478,31 @@ extern "C" int mor_get_reduced(mor_ctx* c, double* At, double* bt, int64_t cap, 
   if (n) *n = nr;
   if (At) {
     if (cap < nr * nr) return fail(MOR_EINVAL, "output too small");
-    HIPCHK(hipMemcpy2D(At, 8 * nr, c->d_At, 8 * c->MPr, 8 * nr, nr, hipMemcpyDeviceToHost));
+    if (c->d_slab) {   // expand the block-row slabs
+      std::vector<double> sl((size_t)c->slab_len);
+      HIPCHK(hipMemcpy(sl.data(), c->d_slab, 8 * sl.size(), hipMemcpyDeviceToHost));
+      std::fill(At, At + nr * nr, 0.0);
+      for (int64_t r = 0; r < nr; ++r) {
+        const int2 wc = c->h_rwc[r];
+        for (int k = 0; k < wc.x; ++k) At[r * nr + c->h_ccol[wc.y + k]] = sl[c->h_rs[r] + k];
+      }
+    } else {
+      HIPCHK(hipMemcpy2D(At, 8 * nr, c->d_At, 8 * c->MPr, 8 * nr, nr, hipMemcpyDeviceToHost));
+    }
   }
   if (bt) {
     std::vector<double> b((size_t)c->MPr * 64);
     HIPCHK(hipMemcpy(b.data(), c->d_bt, 8 * b.size(), hipMemcpyDeviceToHost));
     for (int64_t i = 0; i < nr; ++i) bt[i] = b[(size_t)i * 64];
   }
+  return MOR_OK;
+}
+extern "C" int mor_get_solve_info(mor_ctx* c, int32_t* solver, int32_t* iters, double* rel_residual) {
+  if (!c) return fail(MOR_EINVAL, "null context");
+  if (!c->solved) return fail(MOR_ESTATE, "mor_solve must run first");
+  if (solver) *solver = c->opts.reduced_solver;
+  if (iters) *iters = c->solve_iters;
+  if (rel_residual) *rel_residual = c->solve_relres;
   return MOR_OK;
 }
 extern "C" int mor_get_reduced_solution(mor_ctx* c, double* x, int64_t cap) {

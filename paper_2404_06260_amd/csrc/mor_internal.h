@@ -185,10 +185,35 @@ void launch_random_init(double* const* V, const int* rows, const int* M_of, cons
                         int maxrows, int smax, uint32_t seed, hipStream_t s);
 
 void launch_copy_col(const double* src, int lds, double* dst, int ldd, int rows, hipStream_t s);
+// Where a neighbour pair's block Q_i^T A_0 Q_j and its transpose go: entry (a, b) of the block
+// at out[base_ij + a ld_i + b], entry (b, a) of the transpose at out[base_ji + b ld_j + a].
+// The dense reduced matrix and the block-row slabs of the sparse one are both such layouts.
+struct PairOut {
+  int64_t base_ij, base_ji;
+  int ld_i, ld_j;
+};
 void launch_pair_project(const int4* trip_range, const int* trip, const double* A0, double* const* Vi,
-                         const int* ldv, const int* k1, const int* off, double* At, int64_t ldat, int npairs,
-                         hipStream_t s);
-void launch_scatter_block(const double* B, int k1, int ld, double* At, int64_t ldat, int off, hipStream_t s);
+                         const int* ldv, const int* k1, const PairOut* outs, double* out, int npairs, hipStream_t s);
+// symmetrised A_ii of a [A_ii | b_i] block (k1 x (k1+1), ld) to out[base + a ldo + b]
+void launch_scatter_block(const double* B, int k1, int ld, double* out, int64_t base, int64_t ldo, hipStream_t s);
+
+// Block-sparse reduced system for the conjugate-gradient solve: the rows of subdomain i form a
+// dense slab of dim_i rows over the columns of i and its neighbours.  Row r of the reduced system
+// starts at val[rs[r]], has rwc[r].x entries whose global columns are ccol[rwc[r].y + k], and
+// its diagonal entry at val[rs[r] + rdiag[r]].
+struct RpcgDev {
+  const double* val;
+  const int* ccol;
+  const int64_t* rs;
+  const int2* rwc;
+  const int* rdiag;
+  const double* b; int bstride;   // load b~ (entry r at b[r * bstride])
+  double *x, *r, *z, *p, *q, *dinv;
+  double* sc;    // pq[3], rz[3], rr[3], rr0: ring of three per-iteration slots
+  int* state;    // [0] stop flag, [1] iterations done, [2] failure (1 p'Ap <= 0, 2 diagonal <= 0)
+};
+void launch_rpcg_setup(const RpcgDev& d, int n, hipStream_t s);
+void launch_rpcg_iteration(const RpcgDev& d, int n, int it, double tol2, hipStream_t s);
 void launch_reconstruct(const double* V, int nP, int k1, const double* x, const int* nodes, double* u,
                         hipStream_t s);
 

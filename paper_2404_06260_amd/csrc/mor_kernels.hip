@@ -374,7 +374,7 @@ __global__ __launch_bounds__(256) void k_cg_spmm(const CgSys* __restrict__ sys, 
 }
 
 // Q = A_II P through LDS.  A workgroup owns one row tile (a host-built run of whole row
-// aggregates) of one system and sweeps a group of its 256-byte column slices; the launch lists
+// aggregates) of one system and sweeps a group of its column slices (CWB bytes of a row each); the launch lists
 // (system, slice group, tile) with the tile fastest, so the workgroups resident on one XCD
 // work on neighbouring tiles of the same slices at the same time.  Per slice, every P row
 // the tile reads (its halo) is loaded once into LDS, 16 bytes per lane, and each wave forms its
@@ -1735,13 +1735,14 @@ void launch_copy_col(const double* src, int lds, double* dst, int ldd, int rows,
 __global__ __launch_bounds__(256) void k_pair_project(const int4* __restrict__ range, const int* __restrict__ trip,
                                                       const double* __restrict__ A0, double* const* Vs,
                                                       const int* __restrict__ ldv, const int* __restrict__ k1,
-                                                      const int* __restrict__ off, double* At, int64_t ldat) {
+                                                      const PairOut* __restrict__ outs, double* out) {
   const int4 pr = range[blockIdx.x];   // (i, j, first triplet, count)
   const int i = pr.x, j = pr.y;
   const int ki = k1[i], kj = k1[j];
   const double* Vi = Vs[i];
   const double* Vj = Vs[j];
   const int li = ldv[i], lj = ldv[j];
+  const PairOut po = outs[blockIdx.x];
   for (int o = threadIdx.x; o < ki * kj; o += 256) {
     const int a = o / kj, b = o % kj;
     double acc = 0.0;
@@ -1749,25 +1750,153 @@ __global__ __launch_bounds__(256) void k_pair_project(const int4* __restrict__ r
       const int p = trip[3 * t], q = trip[3 * t + 1], sl = trip[3 * t + 2];
       acc += A0[sl] * Vi[(int64_t)p * li + a] * Vj[(int64_t)q * lj + b];
     }
-    At[(int64_t)(off[i] + a) * ldat + off[j] + b] = acc;
-    At[(int64_t)(off[j] + b) * ldat + off[i] + a] = acc;
+    out[po.base_ij + (int64_t)a * po.ld_i + b] = acc;
+    out[po.base_ji + (int64_t)b * po.ld_j + a] = acc;
   }
 }
 void launch_pair_project(const int4* trip_range, const int* trip, const double* A0, double* const* Vi, const int* ldv,
-                         const int* k1, const int* off, double* At, int64_t ldat, int npairs, hipStream_t s) {
+                         const int* k1, const PairOut* outs, double* out, int npairs, hipStream_t s) {
   if (npairs > 0)
-    hipLaunchKernelGGL(k_pair_project, dim3(npairs), dim3(256), 0, s, trip_range, trip, A0, Vi, ldv, k1, off, At, ldat);
+    hipLaunchKernelGGL(k_pair_project, dim3(npairs), dim3(256), 0, s, trip_range, trip, A0, Vi, ldv, k1, outs, out);
 }
 
-// [A_ii | b_i] (k1 x (k1+1), ld) into the dense reduced system, symmetrising A_ii
-__global__ void k_scatter_block(const double* B, int k1, int ld, double* At, int64_t ldat, int off) {
+// A_ii of a [A_ii | b_i] block (k1 x (k1+1), ld) into the reduced system, symmetrised
+__global__ void k_scatter_block(const double* B, int k1, int ld, double* out, int64_t base, int64_t ldo) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= k1 * k1) return;
   const int a = i / k1, b = i % k1;
-  At[(int64_t)(off + a) * ldat + off + b] = 0.5 * (B[a * ld + b] + B[b * ld + a]);
+  out[base + a * ldo + b] = 0.5 * (B[a * ld + b] + B[b * ld + a]);
 }
-void launch_scatter_block(const double* B, int k1, int ld, double* At, int64_t ldat, int off, hipStream_t s) {
-  hipLaunchKernelGGL(k_scatter_block, dim3((k1 * k1 + 255) / 256), dim3(256), 0, s, B, k1, ld, At, ldat, off);
+void launch_scatter_block(const double* B, int k1, int ld, double* out, int64_t base, int64_t ldo, hipStream_t s) {
+  hipLaunchKernelGGL(k_scatter_block, dim3((k1 * k1 + 255) / 256), dim3(256), 0, s, B, k1, ld, out, base, ldo);
+}
+
+// ---- the reduced solve by conjugate gradients with the diagonal preconditioner (Section 6,
+// step 3).  One iteration is three launches: q = A~ p with p'q; the x, r, z updates with r'z
+// and r'r; the new direction.  The scalars of iteration `it` live in slot it % 3 of each ring, so
+// a slot is cleared two launches before it is summed into and is never cleared while read.
+// Every launch first reads the stop flag: once converged (or failed) the remaining launches of
+// a chunk return at once, and x keeps the converged iterate.
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+__device__ __forceinline__ bool rpcg_stopped(const RpcgDev& d) {
+  return __atomic_load_n(d.state, __ATOMIC_RELAXED) != 0;
+}
+// sum of one value per thread over the workgroup (256 threads), added to *dst by thread 0
+__device__ __forceinline__ void block_add(double v, double* dst, double* red) {
+  v = wave_sum(v);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) unsafeAtomicAdd(dst, red[0] + red[1] + red[2] + red[3]);
+}
+
+// x = 0, r = b, z = D^-1 b, p = z, r'z into rz[2] (the slot "before iteration 0"), b'b into rr0
+__global__ __launch_bounds__(256) void k_rpcg_init(const RpcgDev d, int n) {
+  __shared__ double red[2][4];
+  double rz = 0.0, rr = 0.0;
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
+    const double a = d.val[d.rs[i] + d.rdiag[i]];
+    if (!(a > 0.0)) atomicMax(d.state + 2, 2);
+    const double di = a > 0.0 ? 1.0 / a : 0.0;
+    const double bi = d.b[(int64_t)i * d.bstride];
+    d.dinv[i] = di;
+    d.x[i] = 0.0;
+    d.r[i] = bi;
+    d.z[i] = di * bi;
+    d.p[i] = di * bi;
+    rz += bi * di * bi;
+    rr += bi * bi;
+  }
+  block_add(rz, d.sc + 3 + 2, red[0]);
+  block_add(rr, d.sc + 9, red[1]);
+}
+
+__global__ __launch_bounds__(256) void k_rpcg_matvec(const RpcgDev d, int n, int it) {
+  __shared__ double red[4];
+  if (rpcg_stopped(d)) return;
+  const int c = it % 3;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {   // this iteration's r'z and r'r slots
+    d.sc[3 + c] = 0.0;
+    d.sc[6 + c] = 0.0;
+  }
+  const int lane = threadIdx.x & 63;
+  const int row = blockIdx.x * 4 + (threadIdx.x >> 6);   // one wave per reduced row
+  double part = 0.0;
+  if (row < n) {
+    const double* a = d.val + d.rs[row];
+    const int2 wc = d.rwc[row];
+    const int* cc = d.ccol + wc.y;
+    double acc = 0.0;
+    for (int k = lane; k < wc.x; k += 64) acc += a[k] * d.p[cc[k]];
+    acc = wave_sum(acc);
+    if (lane == 0) {
+      d.q[row] = acc;
+      part = acc * d.p[row];
+    }
+  }
+  if (lane == 0) red[threadIdx.x >> 6] = part;
+  __syncthreads();
+  if (threadIdx.x == 0) unsafeAtomicAdd(d.sc + c, red[0] + red[1] + red[2] + red[3]);
+}
+
+__global__ __launch_bounds__(256) void k_rpcg_update(const RpcgDev d, int n, int it) {
+  __shared__ double red[2][4];
+  if (rpcg_stopped(d)) return;
+  const int c = it % 3, pv = (it + 2) % 3;
+  const double pq = d.sc[c];
+  if (!(pq > 0.0)) {   // the same decision in every workgroup: A~ is not positive definite
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      d.state[2] = 1;
+      __atomic_store_n(d.state, 1, __ATOMIC_RELAXED);
+    }
+    return;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) d.sc[(it + 1) % 3] = 0.0;   // next iteration's p'q slot
+  const double al = d.sc[3 + pv] / pq;
+  double rz = 0.0, rr = 0.0;
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
+    d.x[i] += al * d.p[i];
+    const double ri = d.r[i] - al * d.q[i];
+    const double zi = d.dinv[i] * ri;
+    d.r[i] = ri;
+    d.z[i] = zi;
+    rz += ri * zi;
+    rr += ri * ri;
+  }
+  block_add(rz, d.sc + 3 + c, red[0]);
+  block_add(rr, d.sc + 6 + c, red[1]);
+}
+
+__global__ __launch_bounds__(256) void k_rpcg_direction(const RpcgDev d, int n, int it, double tol2) {
+  if (rpcg_stopped(d)) return;
+  const int c = it % 3, pv = (it + 2) % 3;
+  const bool first = blockIdx.x == 0 && threadIdx.x == 0;
+  if (d.sc[6 + c] <= tol2 * d.sc[9]) {   // converged: x is final
+    if (first) {
+      d.state[1] = it + 1;
+      __atomic_store_n(d.state, 1, __ATOMIC_RELAXED);
+    }
+    return;
+  }
+  const double be = d.sc[3 + c] / d.sc[3 + pv];
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) d.p[i] = d.z[i] + be * d.p[i];
+  if (first) d.state[1] = it + 1;
+}
+
+static int rpcg_grid(int n) { return std::max(1, std::min((n + 255) / 256, 1024)); }
+
+void launch_rpcg_setup(const RpcgDev& d, int n, hipStream_t s) {
+  hipLaunchKernelGGL(k_fill, dim3(1), dim3(256), 0, s, d.sc, (int64_t)10, 0.0);
+  hipLaunchKernelGGL(k_fill_i, dim3(1), dim3(256), 0, s, d.state, (int64_t)4, 0);
+  hipLaunchKernelGGL(k_rpcg_init, dim3(rpcg_grid(n)), dim3(256), 0, s, d, n);
+}
+void launch_rpcg_iteration(const RpcgDev& d, int n, int it, double tol2, hipStream_t s) {
+  hipLaunchKernelGGL(k_rpcg_matvec, dim3((n + 3) / 4), dim3(256), 0, s, d, n, it);
+  hipLaunchKernelGGL(k_rpcg_update, dim3(rpcg_grid(n)), dim3(256), 0, s, d, n, it);
+  hipLaunchKernelGGL(k_rpcg_direction, dim3(rpcg_grid(n)), dim3(256), 0, s, d, n, it, tol2);
 }
 
 // u~ at the owned nodes of one subdomain: u[node(p)] = V[p, :] . x_i

@@ -23,7 +23,7 @@ EXPORTED = ("mor_default_opts", "mor_create", "mor_local_basis", "mor_local_basi
             "mor_project",
             "mor_solve", "mor_submit", "mor_poll", "mor_drain", "mor_step", "mor_engine_stats", "mor_get_sizes", "mor_get_nodes",
             "mor_get_pairs", "mor_get_basis", "mor_get_sigma", "mor_get_local_block", "mor_get_reduced",
-            "mor_get_reduced_solution", "mor_get_stats", "mor_timing_enable", "mor_timing_get",
+            "mor_get_reduced_solution", "mor_get_solve_info", "mor_get_stats", "mor_timing_enable", "mor_timing_get",
             "mor_timing_reset", "mor_destroy", "mor_last_error")
 
 
@@ -59,7 +59,9 @@ class MorOpts(ctypes.Structure):
                 ("stream_blocks", ctypes.c_int32), ("use_graph", ctypes.c_int32), ("dense_batch", ctypes.c_int32),
                 ("hbm_budget_bytes", ctypes.c_size_t),
                 ("dev_alloc", ALLOC_FN), ("dev_free", FREE_FN), ("alloc_user", ctypes.c_void_p),
-                ("hip_stream", ctypes.c_void_p), ("host_only", ctypes.c_int32), ("basis_update", ctypes.c_int32), ("update_drop", ctypes.c_double)]
+                ("hip_stream", ctypes.c_void_p), ("host_only", ctypes.c_int32), ("basis_update", ctypes.c_int32), ("update_drop", ctypes.c_double),
+                ("reduced_solver", ctypes.c_int32), ("reduced_rtol", ctypes.c_double),
+                ("reduced_max_iter", ctypes.c_int32)]
 
 
 def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
@@ -94,6 +96,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "mor_get_local_block": (I32, [P, I32, P, P, I64]),
         "mor_get_reduced": (I32, [P, P, P, I64, P]),
         "mor_get_reduced_solution": (I32, [P, P, I64]),
+        "mor_get_solve_info": (I32, [P, P, P, P]),
         "mor_get_stats": (I32, [P, I32, P, P, P, P]),
         "mor_timing_enable": (I32, [P, I32]),
         "mor_timing_get": (I32, [P, ctypes.c_char_p, P, P, P]),
@@ -311,6 +314,13 @@ def mor_get_reduced_solution(ctx, n):
     x = np.zeros(n)
     _check(lib().mor_get_reduced_solution(ctx, _ptr(x), n))
     return x
+
+
+def mor_get_solve_info(ctx):
+    """(solver, iterations, relative recurrence residual) of the last reduced solve."""
+    s, it, rr = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_double()
+    _check(lib().mor_get_solve_info(ctx, ctypes.byref(s), ctypes.byref(it), ctypes.byref(rr)))
+    return s.value, it.value, rr.value
 
 
 def mor_get_stats(ctx, sd):

@@ -1,6 +1,6 @@
 """Failure handling on the GPU, every condition forced from the host so that every kernel
-exits normally: an iteration cap the block CG cannot meet, an eigensolver cap, a request larger
-than the HBM budget, and calls out of order.  Each failure comes back as its error code with a
+exits normally: an iteration cap the block CG cannot meet, an eigensolver cap, an iteration cap
+of the reduced conjugate gradients, a request larger than the HBM budget, and calls out of order.  Each failure comes back as its error code with a
 message, the engine is left idle with its memory released, and the context keeps working."""
 import sys
 
@@ -92,5 +92,23 @@ def test_calls_out_of_order_report_estate():
         m.project()
         u, n = m.solve()
         assert np.isfinite(u).all() and n == (p.rank + 1) * p.subdomains.n_sub
+    finally:
+        m.close()
+
+
+def test_reduced_pcg_iteration_cap_reports_enotconv():
+    from paper_2404_06260_amd import mor
+    p = _problem()
+    m = mor.Mor(p, precision="fp64", reduced_solver=1, reduced_max_iter=2)
+    try:
+        m.local_basis_all()
+        m.project()
+        with pytest.raises(mor.MorError) as ei:
+            m.solve()
+        _say(f"[gpu] {ei.value}")
+        assert ei.value.code == mor.MOR_ENOTCONV
+        with pytest.raises(mor.MorError) as ei:
+            mor.mor_get_reduced_solution(m.ctx, 1)
+        assert ei.value.code == mor.MOR_ESTATE
     finally:
         m.close()
