@@ -92,14 +92,14 @@ def profiled_traffic(kernel: str, config: str):
     return round((float(row.group(1)) + float(row.group(2))) * 1e9)
 
 
-def comparator_leg(problem, steps: int):
+def comparator_leg(problem, steps: int, reduced_solver: int = 0):
     """The plain FP64 per-subdomain GPU path: FP64 block CG (to the refined path's residual
     target), FP64 Gram and eigensolve, one subdomain per call, no batching; same projection and
     reduced solve.  Returns its reductions/s and the reduced energy x.b~ for comparison."""
     import numpy as np
     import torch
     from paper_2404_06260_amd import mor
-    m = mor.Mor(problem, precision="fp64")
+    m = mor.Mor(problem, precision="fp64", reduced_solver=reduced_solver)
     n = problem.subdomains.n_sub
     ranks = problem.ranks if problem.ranks is not None else np.full(n, problem.rank)
     try:
@@ -175,6 +175,9 @@ def main():
                     help="absolute Poisson arrival rate (req/s) of the serving leg; 0: a fraction of saturation")
     ap.add_argument("--serve-load", type=float, default=0.9,
                     help="Poisson arrival rate of the serving leg as a fraction of the measured saturation rate")
+    ap.add_argument("--reduced-solver", choices=("pcg", "cholesky"), default="pcg",
+                    help="reduced system: the paper's diagonal-preconditioned conjugate gradients on the "
+                         "block-sparse matrix, or a dense FP64 Cholesky factorization")
     ap.add_argument("--calibrate-copy", type=int, default=0,
                     help="MiB copied by one plain device copy before the steps (HBM counter calibration)")
     args = ap.parse_args()
@@ -201,7 +204,8 @@ def main():
     else:
         tile = dict(spmm_rows=args.spmm_rows)
     use_graph = (args.config == "C3") if args.graph < 0 else bool(args.graph)
-    m = mor.Mor(p, precision=prec, use_graph=int(use_graph), **tile)
+    red_solver = 1 if args.reduced_solver == "pcg" else 0
+    m = mor.Mor(p, precision=prec, use_graph=int(use_graph), reduced_solver=red_solver, **tile)
     halo = tile.get("spmm_kind", 0) != 2
     spmm_cap = max([c for c in (48, 64, 96, 128, 176) if c <= tile.get("spmm_rows", 0)] or [96]) if halo else 0
     spmm_cwb = 256 if tile.get("spmm_kind", 0) == 1 else 128   # bytes of a row per column slice
@@ -276,6 +280,11 @@ def main():
         if n:
             kernels[name] = dict(launches=n, ms_per_step=round(ms / args.steps, 3))
     stats = [mor.mor_get_stats(m.ctx, i) for i in range(n_sub)]
+    _, red_iters, red_rel = mor.mor_get_solve_info(m.ctx)
+    n_s, ms_s, _ = mor.mor_timing_get(m.ctx, "solve")
+    reduced_solve = {"solver": "diagonal-preconditioned CG, block-sparse" if red_solver else "dense FP64 Cholesky",
+                     "iterations": red_iters, "rel_residual": red_rel,
+                     "ms": round(ms_s / max(n_s, 1), 3)}
     At_b, bt_b = mor.mor_get_reduced(m.ctx)
     energy_b = float(mor.mor_get_reduced_solution(m.ctx, At_b.shape[0]) @ bt_b)
     # the dense contraction of the Gram G1 = X_C^T K_i X_C on the matrix cores
@@ -302,7 +311,7 @@ def main():
     comparator = None
     if not args.no_comparator and prec != "fp64":
         print("[bench] comparator: plain FP64 per-subdomain path", file=sys.stderr, flush=True)
-        comparator = comparator_leg(p, 1)
+        comparator = comparator_leg(p, 1, red_solver)
         comparator["speedup_of_value"] = round(n_sub * args.steps / el / comparator["value"], 3)
         comparator["energy_rel_diff"] = abs(comparator.pop("energy") - energy_b) / abs(energy_b)
     cpu = None
@@ -342,6 +351,7 @@ def main():
         "mfma": mfma,
         "kernels": kernels,
         "reduced_energy": energy_b,   # x^T b~ = ||u~||_A^2 (larger = closer to the FE solution)
+        "reduced_solve": reduced_solve,
         "cg_iters_max": [max(s["cg_iter_a"] for s in stats), max(s["cg_iter_k"] for s in stats)],
         "eig_iters_max": max(s["eig_iter"] for s in stats),
     }

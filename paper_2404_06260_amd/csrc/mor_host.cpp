@@ -289,12 +289,25 @@ int build_sub(const HostMesh& m, const int32_t* ext, const uint8_t* in_core, int
   // Aggregates of at most 8 I rows for the block-Jacobi preconditioner of the CG: in id
   // order, an unaggregated row takes its unaggregated higher-numbered neighbours of the same
   // group (P, V\P, I\V).  On a Kuhn cube these are the 7 forward corners of a 2x2x2 cell
-  // block.  Rows are then renumbered aggregate by aggregate, the aggregates of each group in
+  // block.  A row joins only while the aggregate's halo (the I rows its rows couple to) stays
+  // within the LDS tile capacity, so every aggregate fits one SpMM tile on any mesh (on a Kuhn
+  // mesh the halo is at most 65 rows).  Rows are then renumbered aggregate by aggregate, the aggregates of each group in
   // Morton (Z-curve) order of their first node, so that runs of consecutive aggregates (the
   // SpMM tiles) are compact bricks rather than strips.
   {
     const int gb[4] = {0, s.nP, s.nV, s.nI};
-    std::vector<int32_t> agg(s.nI, -1), order;
+    std::vector<int32_t> agg(s.nI, -1), order, hstamp(s.nI, -1);
+    auto halo_add = [&](int v, int tag, bool commit) {   // I columns of row v new to aggregate `tag`
+      int k = 0;
+      for (int e = s.rp[v]; e < s.rp[v + 1]; ++e) {
+        const int cc = s.col[e];
+        if (cc < s.nI && hstamp[cc] != tag) {
+          ++k;
+          if (commit) hstamp[cc] = tag;
+        }
+      }
+      return k;
+    };
     std::vector<int32_t> bp{0};
     int gfirst[4] = {0, 0, 0, 0};   // first aggregate of each group
     order.reserve(s.nI);
@@ -306,9 +319,18 @@ int build_sub(const HostMesh& m, const int32_t* ext, const uint8_t* in_core, int
         agg[v] = b;
         order.push_back(v);
         int n = 1;
+        int hsize = halo_add(v, b, true);
+        if (hsize > halo_cap) {
+          err = "a row couples to " + std::to_string(hsize) + " interior rows, more than the SpMM halo capacity " +
+                std::to_string(halo_cap) + " (choose a larger spmm_rows, up to 176)";
+          return -1;
+        }
         for (int e = s.rp[v]; e < s.rp[v + 1] && n < 8; ++e) {
           const int u = s.col[e];
           if (u > v && u < gb[g + 1] && agg[u] < 0) {
+            const int k = halo_add(u, b, false);
+            if (hsize + k > halo_cap) continue;
+            hsize += halo_add(u, b, true);
             agg[u] = b;
             order.push_back(u);
             ++n;

@@ -1,5 +1,9 @@
 """GPU parity of the HIP path against the FP64 oracle, through the C-ABI.
 
+Problems: the 16^3 cube (C1), a lognormal 12^3 cube, an uneven jittered box decomposition, and a
+general mesh (an L-shaped region with a cavity, jittered, nodes and tets in random order, split
+by a breadth-first graph partition with the paper's touching-element subdomains).
+
 For each precision mode the library runs the whole hot path (assembly, block-CG lifting,
 Gram/Schur, Cholesky, eigensolve, stitching, local and pairwise projection, reduced solve)
 and is compared with the oracle on the same seeded inputs:
@@ -50,6 +54,8 @@ def _problem(name):
         rng = np.random.default_rng(5)
         cuts = tuple(w.cuts_random(14, k, 3, rng) for k in (3, 2, 2))
         return w.make_problem(14, cuts=cuts, r=2, rank=5, jitter=0.2, seed=6, name=name)
+    if name == "general":   # L-shape with a cavity, jittered, shuffled numbering, BFS graph partition
+        return w.make_general_problem(name=name)
     raise KeyError(name)
 
 
@@ -83,7 +89,7 @@ def _run_gpu(p, precision, **kw):
     return out
 
 
-@pytest.mark.parametrize("name", ["C1", "small-lognormal", "uneven-jitter"])
+@pytest.mark.parametrize("name", ["C1", "small-lognormal", "uneven-jitter", "general"])
 @pytest.mark.parametrize("precision", ["fp64", "fp32_refine", "fp32", "bf16_split"])
 def test_parity_whole_path(name, precision):
     from paper_2404_06260_amd import mor
@@ -282,7 +288,7 @@ def _oracle_fe(p):
 # the paper's reduced solver: conjugate gradients with the diagonal preconditioner on the
 # block-sparse reduced matrix (end of Section 6 step 3; Section 7)
 
-@pytest.mark.parametrize("name", ["small-lognormal", "uneven-jitter"])
+@pytest.mark.parametrize("name", ["small-lognormal", "uneven-jitter", "general"])
 def test_reduced_pcg_matches_oracle(name):
     """GPU conjugate gradients on the block-row slabs against the oracle's PCG on its own
     reduced system: the same u~ (energy norm, the FP64 tolerance) and x^T b~, iteration

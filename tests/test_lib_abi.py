@@ -37,10 +37,12 @@ def _host_ctx(p):
     return mor.mor_create(m.xyz, m.tets, m.dirichlet, p.kappa, p.f_nodal, sd.ext_tet_ptr, sd.ext_tets, sd.in_core, o)
 
 
-@pytest.mark.parametrize("case", ["C1", "uneven", "jitter"])
+@pytest.mark.parametrize("case", ["C1", "uneven", "jitter", "general"])
 def test_host_decomposition_matches_oracle(case):
     from paper_2404_06260_amd import mor
-    if case == "C1":
+    if case == "general":          # L-shape with a cavity, shuffled numbering, BFS graph partition
+        p = w.make_general_problem()
+    elif case == "C1":
         p = w.make_config("C1")
     elif case == "uneven":
         rng = np.random.default_rng(3)

@@ -245,6 +245,184 @@ def box_subdomains(n: int, cuts: tuple, r: int) -> Subdomains:
 
 
 # ----------------------------------------------------------------------------------
+# general meshes and graph partitions
+
+def kuhn_region(n: int, keep_cell, jitter: float = 0.0, seed: int = 0, shuffle: bool = True) -> Mesh:
+    """A tetrahedral mesh of a non-box region: the Kuhn tets of the cells (i, j, k) of the
+    n^3 grid with keep_cell(ci, cj, ck) true (arrays in, bool array out), Dirichlet data on
+    the whole boundary of the region (nodes of faces used by one tet only), every node off
+    that boundary moved by U(-jitter h, +jitter h) per coordinate.  With shuffle, nodes and
+    tets are renumbered by seeded random permutations and each tet's vertex list is rotated
+    by a seeded even permutation (orientation kept), so that no structured numbering
+    survives."""
+    full = kuhn_cube(n)
+    c = np.arange(n)
+    ck, cj, ci = np.meshgrid(c, c, c, indexing="ij")
+    keep = np.asarray(keep_cell(ci.ravel(), cj.ravel(), ck.ravel()), dtype=bool)
+    tets = full.tets.reshape(-1, 6, 4)[keep].reshape(-1, 4).astype(np.int64)
+    used = np.unique(tets)
+    new_id = -np.ones(full.n_nodes, dtype=np.int64)
+    new_id[used] = np.arange(used.size)
+    tets = new_id[tets]
+    xyz = full.xyz[used].copy()
+    faces = np.sort(tets[:, [[1, 2, 3], [0, 2, 3], [0, 1, 3], [0, 1, 2]]].reshape(-1, 3), axis=1)
+    uniq, counts = np.unique(faces, axis=0, return_counts=True)
+    dirichlet = np.zeros(used.size, dtype=np.uint8)
+    dirichlet[np.unique(uniq[counts == 1])] = 1
+    rng = np.random.default_rng(seed)
+    if jitter > 0.0:
+        d = rng.uniform(-jitter / n, jitter / n, size=xyz.shape)
+        xyz = xyz + np.where(dirichlet[:, None] == 0, d, 0.0)
+    if shuffle:
+        perm = rng.permutation(used.size)            # old id -> new id
+        xyz_new = np.empty_like(xyz)
+        xyz_new[perm] = xyz
+        dir_new = np.empty_like(dirichlet)
+        dir_new[perm] = dirichlet
+        tets = perm[tets][rng.permutation(tets.shape[0])]
+        even = np.array([[0, 1, 2, 3], [1, 2, 0, 3], [2, 0, 1, 3], [0, 2, 3, 1], [0, 3, 1, 2], [1, 0, 3, 2],
+                         [2, 3, 0, 1], [3, 2, 1, 0], [3, 0, 2, 1], [1, 3, 2, 0], [2, 1, 3, 0], [3, 1, 0, 2]])
+        rot = even[rng.integers(0, 12, size=tets.shape[0])]
+        tets = np.take_along_axis(tets, rot, axis=1)
+        xyz, dirichlet = xyz_new, dir_new
+    e = xyz[tets[:, 1:]] - xyz[tets[:, :1]]
+    det = np.einsum("ti,ti->t", e[:, 0], np.cross(e[:, 1], e[:, 2]))
+    if not np.all(det > 0):
+        raise ValueError("region mesh has a degenerate or inverted tet")
+    return Mesh(n=n, xyz=xyz, tets=tets.astype(np.int32), dirichlet=dirichlet)
+
+
+def _node_graph(mesh: Mesh):
+    """CSR node adjacency (mesh edges) and node -> tets incidence."""
+    t = mesh.tets.astype(np.int64)
+    nn = mesh.n_nodes
+    a = np.concatenate([t[:, i] for i in range(4) for j in range(4) if i != j])
+    b = np.concatenate([t[:, j] for i in range(4) for j in range(4) if i != j])
+    key = np.unique(a * nn + b)
+    a, b = key // nn, key % nn
+    ptr = np.concatenate([[0], np.cumsum(np.bincount(a, minlength=nn))])
+    tn = t.ravel()
+    order = np.argsort(tn, kind="stable")
+    tptr = np.concatenate([[0], np.cumsum(np.bincount(tn, minlength=nn))])
+    return ptr, b, tptr, order // 4
+
+
+def graph_parts(mesh: Mesh, n_parts: int, seed: int) -> np.ndarray:
+    """Part id per node: parts grown at once by breadth-first search over the mesh edges from
+    n_parts start nodes (each round, every part claims the unclaimed neighbours of its last
+    claimed layer), a simple graph partition with connected, compact parts.  The first start
+    is a seeded random node; each further start is a node farthest (in edge hops) from the
+    starts so far."""
+    ptr, adj, _, _ = _node_graph(mesh)
+    rng = np.random.default_rng(seed)
+
+    def hops(src):
+        d = -np.ones(mesh.n_nodes, dtype=np.int64)
+        d[src] = 0
+        f = np.asarray(src)
+        k = 0
+        while f.size:
+            k += 1
+            nb = np.unique(np.concatenate([adj[ptr[v]:ptr[v + 1]] for v in f]))
+            nb = nb[d[nb] < 0]
+            d[nb] = k
+            f = nb
+        return d
+
+    starts = [int(rng.integers(mesh.n_nodes))]
+    while len(starts) < n_parts:
+        d = hops(starts)
+        far = np.flatnonzero(d == d.max())
+        starts.append(int(far[rng.integers(far.size)]))
+    part = -np.ones(mesh.n_nodes, dtype=np.int64)
+    part[starts] = np.arange(n_parts)
+    fronts = [np.array([s]) for s in starts]
+    while any(f.size for f in fronts):
+        for p in range(n_parts):
+            f = fronts[p]
+            if not f.size:
+                continue
+            nb = np.unique(np.concatenate([adj[ptr[v]:ptr[v + 1]] for v in f]))
+            nb = nb[part[nb] < 0]
+            part[nb] = p
+            fronts[p] = nb
+    return part
+
+
+def graph_subdomains(mesh: Mesh, part: np.ndarray, r: int, max_rounds: int = 50) -> Subdomains:
+    """Subdomains from a node partition (Section 3, the construction next to its decomposition
+    figure): omega_i = the tets with at least one node in part i, so neighbouring subdomains share
+    one element layer; omega_i^+ = omega_i grown by r element layers (tets sharing a node with the
+    previous layer).  A free node interior to two subdomains (every tet around it touches
+    both parts) moves to the part whose subdomain surrounds it, until the interiors of the
+    omega_i partition the free nodes; raises if max_rounds do not settle it."""
+    ptr, adj, tptr, tet_of = _node_graph(mesh)
+    t = mesh.tets.astype(np.int64)
+    nn, nt = mesh.n_nodes, mesh.n_tets
+    n_parts = int(part.max()) + 1
+    part = part.copy()
+    free = mesh.dirichlet == 0
+    star = np.bincount(t.ravel(), minlength=nn)
+    for _ in range(max_rounds):
+        cores = []
+        moved = False
+        inner = np.zeros(nn, dtype=np.int64)
+        for p in range(n_parts):
+            core = np.zeros(nt, dtype=bool)
+            core[np.unique(tet_of[np.concatenate([np.arange(tptr[v], tptr[v + 1]) for v in np.flatnonzero(part == p)])])] = True
+            cnt = np.bincount(t[core].ravel(), minlength=nn)
+            interior = free & (cnt == star)
+            inner += interior
+            cores.append(core)
+            intruders = np.flatnonzero(interior & (part != p))
+            if intruders.size:
+                part[intruders] = p
+                moved = True
+                break
+        if not moved:
+            if np.any(inner[free] != 1):
+                raise ValueError("graph decomposition: free nodes not covered exactly once")
+            break
+    else:
+        raise ValueError("graph decomposition did not settle")
+    ptr_out = [0]
+    ext_all, core_all = [], []
+    for p in range(n_parts):
+        ext = cores[p].copy()
+        for _ in range(r):
+            nodes = np.unique(t[ext].ravel())
+            grow = np.unique(tet_of[np.concatenate([np.arange(tptr[v], tptr[v + 1]) for v in nodes])])
+            ext[grow] = True
+        ids = np.flatnonzero(ext)
+        ext_all.append(ids.astype(np.int32))
+        core_all.append(cores[p][ids].astype(np.uint8))
+        ptr_out.append(ptr_out[-1] + ids.size)
+    return Subdomains(ext_tet_ptr=np.asarray(ptr_out, dtype=np.int64), ext_tets=np.concatenate(ext_all),
+                      in_core=np.concatenate(core_all))
+
+
+def make_general_problem(n: int = 14, n_parts: int = 6, r: int = 2, rank: int = 6, kappa_sigma: float = 1.0,
+                         jitter: float = 0.2, seed: int = 31, name: str = "general") -> Problem:
+    """A general mesh and partition: the L-shaped region [0,1]^3 minus the quarter
+    x, y > 1/2 with a cubic cavity of n/7 cells near its corner removed, jittered and
+    renumbered at random (kuhn_region), lognormal kappa per tet, f = 1, a BFS graph partition
+    into n_parts parts and r element layers of extension."""
+    h = max(1, n // 7)
+    a0 = n // 4
+
+    def keep(ci, cj, ck):
+        lshape = ~((ci >= n // 2) & (cj >= n // 2))
+        cavity = (ci >= a0) & (ci < a0 + h) & (cj >= a0) & (cj < a0 + h) & (ck >= a0) & (ck < a0 + h)
+        return lshape & ~cavity
+
+    mesh = kuhn_region(n, keep, jitter=jitter, seed=seed)
+    kap = np.exp(kappa_sigma * np.random.default_rng(seed + 1).standard_normal(mesh.n_tets))
+    sd = graph_subdomains(mesh, graph_parts(mesh, n_parts, seed + 2), r)
+    return Problem(name=name, mesh=mesh, kappa=kap, f_nodal=None, subdomains=sd, rank=rank, precision="fp64",
+                   meta=dict(n=n, r=r, parts=n_parts, region="L-shape with cavity"))
+
+
+# ----------------------------------------------------------------------------------
 # named workloads
 
 def make_problem(n: int, parts=(2, 2, 2), r: int = 1, rank: int = 8, kappa: str = "one",
