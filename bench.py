@@ -24,13 +24,15 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 
 CONFIG_DEFAULT = "C2"
-PRECISION_OF = {"C1": "fp64", "C2": "fp32_refine", "C3": "fp32_refine", "C4": "bf16_split", "C5": "fp32_refine"}
+PRECISION_OF = {"C1": "fp64", "C2": "fp32_refine", "C3": "fp32_refine", "C4": "bf16_split", "C5": "fp32_refine",
+                "C6": "fp32_refine"}
 WORKLOAD_OF = {
     "C1": "16^3 Kuhn cube, kappa=1, 2x2x2 boxes, r=1, k=8",
     "C2": "48^3 Kuhn cube (117,649 nodes), lognormal kappa sigma=1, 4x4x4 boxes, r=6, k=16",
     "C3": "64^3 jittered Kuhn cube, 6x5x4 random boxes, r=6, k=24",
     "C4": "96^3 Kuhn cube, lognormal kappa sigma=2, 8x8x8 boxes, r=6, k=32",
     "C5": "128^3 Kuhn cube, kappa inclusions, boxes of widths 10-40, r=6, k in 8-48",
+    "C6": "216^3 Kuhn cube (10,218,313 nodes, 9.9M free DOFs), lognormal kappa sigma=1, 18x18x18 boxes, r=6, k=16",
 }
 
 
@@ -115,8 +117,8 @@ def comparator_leg(problem, steps: int, reduced_solver: int = 0):
             m.solve()
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
-        At, bt = mor.mor_get_reduced(m.ctx)
-        x = mor.mor_get_reduced_solution(m.ctx, At.shape[0])
+        bt = mor.mor_get_reduced_load(m.ctx)
+        x = mor.mor_get_reduced_solution(m.ctx, bt.size)
         return dict(value=round(n * steps / el, 4), unit="subdomain reductions/s", ms_per_step=round(1e3 * el / steps, 2),
                     path="plain FP64 block CG (residual 1e-8) + FP64 Gram/eigen, one subdomain per call",
                     energy=float(x @ bt))
@@ -205,7 +207,9 @@ def main():
         tile = dict(spmm_rows=args.spmm_rows)
     use_graph = (args.config == "C3") if args.graph < 0 else bool(args.graph)
     red_solver = 1 if args.reduced_solver == "pcg" else 0
+    t_create = time.perf_counter()
     m = mor.Mor(p, precision=prec, use_graph=int(use_graph), reduced_solver=red_solver, **tile)
+    print(f"[bench] context created ({time.perf_counter() - t_create:.0f} s)", file=sys.stderr, flush=True)
     halo = tile.get("spmm_kind", 0) != 2
     spmm_cap = max([c for c in (48, 64, 96, 128, 176) if c <= tile.get("spmm_rows", 0)] or [96]) if halo else 0
     spmm_cwb = 256 if tile.get("spmm_kind", 0) == 1 else 128   # bytes of a row per column slice
@@ -240,6 +244,13 @@ def main():
             res = serve.run_stream(m.ctx, st, on_done=progress)
             if (res.status != 0).any():
                 raise RuntimeError(f"{int((res.status != 0).sum())} requests failed")
+        elif n_sub > 1000:   # thousands of subdomains: batches of 729 with a progress line after each
+            ranks = p.ranks if p.ranks is not None else np.full(n_sub, p.rank)
+            t0s = time.perf_counter()
+            for a in range(0, n_sub, 729):
+                ids = np.arange(a, min(a + 729, n_sub))
+                mor.mor_local_basis_batch(m.ctx, ids, ranks[ids].astype(np.int32))
+                progress(None, int(ids[-1]) + 1, time.perf_counter() - t0s)
         else:
             m.local_basis_all()
         m.project()
@@ -285,8 +296,8 @@ def main():
     reduced_solve = {"solver": "diagonal-preconditioned CG, block-sparse" if red_solver else "dense FP64 Cholesky",
                      "iterations": red_iters, "rel_residual": red_rel,
                      "ms": round(ms_s / max(n_s, 1), 3)}
-    At_b, bt_b = mor.mor_get_reduced(m.ctx)
-    energy_b = float(mor.mor_get_reduced_solution(m.ctx, At_b.shape[0]) @ bt_b)
+    bt_b = mor.mor_get_reduced_load(m.ctx)
+    energy_b = float(mor.mor_get_reduced_solution(m.ctx, bt_b.size) @ bt_b)
     # the dense contraction of the Gram G1 = X_C^T K_i X_C on the matrix cores
     mfma = None
     n_g, ms_g, fl_g = mor.mor_timing_get(m.ctx, "gram_bf16")

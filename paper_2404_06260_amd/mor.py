@@ -310,6 +310,15 @@ def mor_get_reduced(ctx):
     return A, b
 
 
+def mor_get_reduced_load(ctx):
+    """The reduced load b~ alone (no n x n matrix)."""
+    n = ctypes.c_int64()
+    _check(lib().mor_get_reduced(ctx, None, None, 0, ctypes.byref(n)))
+    b = np.zeros(n.value)
+    _check(lib().mor_get_reduced(ctx, None, _ptr(b), 0, ctypes.byref(n)))
+    return b
+
+
 def mor_get_reduced_solution(ctx, n):
     x = np.zeros(n)
     _check(lib().mor_get_reduced_solution(ctx, _ptr(x), n))

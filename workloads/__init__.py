@@ -452,7 +452,7 @@ def make_problem(n: int, parts=(2, 2, 2), r: int = 1, rank: int = 8, kappa: str 
                    precision=precision, meta=dict(n=n, r=r, cuts=[c.tolist() for c in cuts]))
 
 
-CONFIG_NAMES = ("C1", "C2", "C3", "C4", "C5")
+CONFIG_NAMES = ("C1", "C2", "C3", "C4", "C5", "C6")
 
 
 def make_config(name: str) -> Problem:
@@ -466,6 +466,9 @@ def make_config(name: str) -> Problem:
     C4  96^3, kappa = exp(2 N(0,1)) (seed 4), 8^3 boxes, r = 6, k = 32, BF16 Gram.
     C5  128^3, kappa = 1 with 20 spheres of kappa = 1e4 (seed 5), boxes with widths
         U{10..40} per axis (seed 6), r = 6, ranks U{8..48} per request (seed 8).
+    C6  216^3 (10.2 million nodes, 9.9 million free DOFs), kappa = exp(N(0,1)) (seed 10),
+        18x18x18 boxes of 12 cells (5 832 subdomains), r = 6, k = 16: the scale of the
+        paper's larger scaling cases (Table 2) on one device.
     """
     if name == "C1":
         return make_problem(16, (2, 2, 2), r=1, rank=8, name="C1", precision="fp64")
@@ -483,6 +486,9 @@ def make_config(name: str) -> Problem:
     if name == "C4":
         return make_problem(96, (8, 8, 8), r=6, rank=32, kappa="lognormal", kappa_sigma=2.0, seed=4,
                             name="C4", precision="bf16_split")
+    if name == "C6":
+        return make_problem(216, (18, 18, 18), r=6, rank=16, kappa="lognormal", kappa_sigma=1.0, seed=10,
+                            name="C6", precision="fp32_refine")
     if name == "C5":
         mesh = kuhn_cube(128)
         kap = kappa_inclusions(mesh, seed=5)
