@@ -2,14 +2,18 @@
 launch configuration the benchmark times (FP32 block CG with FP64 refinement, autotuned tiles).
 
 The FP64 oracle's whole-path result for this workload is stored in tests/golden/C2_oracle.npz,
-written by tests/golden/make_oracle_reference.py (which calls only the oracle; about 9 CPU
-minutes).  Compared here:
+written by tests/golden/make_oracle_reference.py (which calls only the oracle; about an hour on
+8 cores).  Compared here:
   - k_eff of every subdomain (exact) and the reduced dimension,
   - the leading singular values of every subdomain (rtol 1e-7),
   - the reduced solution in the global energy norm (relative, 1e-6),
   - the Galerkin identity A~ x = b~ on the GPU's reduced system, and x.b~ against the oracle,
   - two sampled subdomains (a corner and an interior box) recomputed by the oracle one by one:
-    q_0 and the span of the lifting modes in the K_i inner product.
+    q_0 and the span of the lifting modes in the K_i inner product;
+  - with the benchmark's reduced solver (conjugate gradients with the diagonal preconditioner
+    on the block-sparse reduced matrix): the requested residual 1e-12, an iteration count
+    within 10% of the oracle's on its own reduced system (stored beside its result), and the
+    oracle's u~ (energy norm, 1e-6) and x.b~.
 """
 import os
 import sys
@@ -92,5 +96,37 @@ def test_c2_full_size_parity():
             ang = _sin_angle(Vs[:, 1:], r.Phi, lm.K_i.tocsr())
             _say(f"[gpu] C2 subdomain {i}: span angle {ang:.2e}")
             assert ang < TOL_ANGLE, (i, ang)
+    finally:
+        m.close()
+
+
+def test_c2_full_size_reduced_pcg():
+    import torch
+    from paper_2404_06260_amd import autotune, mor
+    ref = np.load(GOLDEN)
+    p = w.make_config("C2")
+    torch.cuda.set_device(0)
+    tile = autotune.best(p, "fp32_refine") or {}
+    _say("[gpu] C2 fp32_refine, reduced CG: local bases")
+    m = mor.Mor(p, precision="fp32_refine", reduced_solver=1, reduced_rtol=float(ref["pcg_rtol"]), **tile)
+    try:
+        m.local_basis_all()
+        m.project()
+        u, nred = m.solve()
+        solver, it, rel = mor.mor_get_solve_info(m.ctx)
+        it_o = int(ref["pcg_iters"])
+        _say(f"[gpu] C2 reduced CG: {it} iterations (oracle {it_o}), ||r||/||b|| {rel:.2e}")
+        assert solver == 1 and 0 < rel <= float(ref["pcg_rtol"])
+        assert abs(it - it_o) <= max(3, 0.1 * it_o), (it, it_o)
+        At, bt = mor.mor_get_reduced(m.ctx)
+        x = mor.mor_get_reduced_solution(m.ctx, nred)
+        assert np.linalg.norm(bt - At @ x) <= 1e-10 * np.linalg.norm(bt)
+        np.testing.assert_allclose(x @ bt, ref["x"] @ ref["bt"], rtol=1e-7)
+        A, _, free, _ = ofem.global_system(p.mesh, p.kappa, p.f_nodal)
+        d = (u - ref["u_tilde"])[free]
+        uo = ref["u_tilde"][free]
+        e = np.sqrt(max(d @ (A @ d), 0.0)) / np.sqrt(uo @ (A @ uo))
+        _say(f"[gpu] C2 reduced CG: energy rel {e:.3e}")
+        assert e < TOL_ENERGY, e
     finally:
         m.close()
