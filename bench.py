@@ -177,6 +177,8 @@ def main():
                     help="absolute Poisson arrival rate (req/s) of the serving leg; 0: a fraction of saturation")
     ap.add_argument("--serve-load", type=float, default=0.9,
                     help="Poisson arrival rate of the serving leg as a fraction of the measured saturation rate")
+    ap.add_argument("--cg-rtol", type=float, default=0.0,
+                    help="inner block-CG tolerance (0: the library default); FP32 paths refine to the same FP64 target")
     ap.add_argument("--reduced-solver", choices=("pcg", "cholesky"), default="pcg",
                     help="reduced system: the paper's diagonal-preconditioned conjugate gradients on the "
                          "block-sparse matrix, or a dense FP64 Cholesky factorization")
@@ -208,7 +210,8 @@ def main():
     use_graph = (args.config == "C3") if args.graph < 0 else bool(args.graph)
     red_solver = 1 if args.reduced_solver == "pcg" else 0
     t_create = time.perf_counter()
-    m = mor.Mor(p, precision=prec, use_graph=int(use_graph), reduced_solver=red_solver, **tile)
+    extra = {"cg_rtol": args.cg_rtol} if args.cg_rtol > 0 else {}
+    m = mor.Mor(p, precision=prec, use_graph=int(use_graph), reduced_solver=red_solver, **tile, **extra)
     print(f"[bench] context created ({time.perf_counter() - t_create:.0f} s)", file=sys.stderr, flush=True)
     halo = tile.get("spmm_kind", 0) != 2
     spmm_cap = max([c for c in (48, 64, 96, 128, 176) if c <= tile.get("spmm_rows", 0)] or [96]) if halo else 0

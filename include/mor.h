@@ -89,7 +89,10 @@ typedef void (*mor_free_fn)(void* ptr, void* user);
 
 typedef struct {
   int32_t precision;       /* MOR_FP64 | MOR_FP32_REFINE | MOR_FP32 | MOR_BF16_SPLIT */
-  double cg_rtol;          /* inner CG stop: sqrt(r'D^-1 r / r0'D^-1 r0) <= cg_rtol per column */
+  double cg_rtol;          /* inner FP32 CG stop: sqrt(r'M^-1 r / r0'M^-1 r0) <= cg_rtol per column
+                              (0 = 1e-5).  With FP64 refinement a looser value (1e-4) needs fewer
+                              iterations for the same refine_rtol target, at lower accuracy of the
+                              singular values (up to 1.2e-7 relative instead of below 1e-7) */
   double refine_rtol;      /* FP32_REFINE: stop refinement when the FP64 residual reaches this */
   int32_t max_iter;        /* CG iteration cap per solve (MOR_ENOTCONV beyond it) */
   int32_t refine_steps;    /* FP32_REFINE: maximum number of FP64 residual corrections */

@@ -709,6 +709,14 @@ struct Launch {
   double stream_bytes = 0;   // update + direction: 8 block-vector elements per entry
 };
 
+// Inner stop of a block-CG system: FP64 systems iterate to the outer target refine_rtol; FP32
+// systems (refined in FP64 or not) stop at cg_rtol.
+template <typename T>
+static double inner_tol2(const mor_ctx* c) {
+  const double t = sizeof(T) == 8 ? c->opts.refine_rtol : (c->opts.cg_rtol > 0 ? c->opts.cg_rtol : 1e-5);
+  return t * t;
+}
+
 struct MorEngine {
   int elt = 4;
   std::vector<Req> pending;
@@ -974,6 +982,7 @@ static int engine_admit(mor_ctx* c, MorEngine& e) {
       S.X = w == 0 ? q.XA : q.XK; S.R = w == 0 ? q.RA : q.RK;
       S.P = w == 0 ? q.PA : q.PK; S.Q = w == 0 ? q.QA : q.QK;
       S.X64 = w == 0 ? q.XA64 : q.XK64;
+      S.tol2 = inner_tol2<T>(c);
       S.bp = q.d->bp;
       S.nblk = nblk;
       S.minv = w == 0 ? q.minvA : q.minvK;
@@ -1019,9 +1028,6 @@ static int engine_chunk(mor_ctx* c, MorEngine& e) {
       if (L->sys[w].phase == 0 && !L->status) La.sys.push_back(&L->sys[w]);
   if (La.sys.empty()) return 0;
   if (int rc = engine_upload(c, e, La)) return rc;
-  const bool fp64 = sizeof(T) == 8;
-  const double inner = fp64 ? c->opts.refine_rtol : c->opts.cg_rtol;
-  const double tol2 = inner * inner;
   const int chunk = std::max(1, c->opts.cg_chunk);
   // one CG iteration over every admitted system: Q = A P and p'Q, alpha, R -= alpha Q with
   // r'M^-1 r, beta and convergence, X += alpha P and P = M^-1 R + beta P
@@ -1032,7 +1038,7 @@ static int engine_chunk(mor_ctx* c, MorEngine& e) {
       launch_cg_spmm<T>(e.d_sys, La.sp, La.nsp, e.sp.rb, e.sp.v, s);
     launch_cg_alpha(e.d_sys, La.cb, La.ncb, s);
     launch_cg_update<T>(e.d_sys, La.bk, La.nbk, e.stm.rb, e.stm.v, s);
-    launch_cg_beta(e.d_sys, La.cb, La.ncb, tol2, s);
+    launch_cg_beta(e.d_sys, La.cb, La.ncb, s);
     launch_cg_direction<T>(e.d_sys, La.bk, La.nbk, e.stm.rb, e.stm.v, s);
   };
   if (c->opts.use_graph) {
@@ -1077,7 +1083,7 @@ static int engine_chunk(mor_ctx* c, MorEngine& e) {
       ScopedTimer tm(c, "cg_update", 0);
       launch_cg_update<T>(e.d_sys, La.bk, La.nbk, e.stm.rb, e.stm.v, st);
     }
-    launch_cg_beta(e.d_sys, La.cb, La.ncb, tol2, st);
+    launch_cg_beta(e.d_sys, La.cb, La.ncb, st);
     {
       ScopedTimer tm(c, "cg_direction", 0);
       launch_cg_direction<T>(e.d_sys, La.bk, La.nbk, e.stm.rb, e.stm.v, st);

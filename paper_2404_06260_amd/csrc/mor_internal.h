@@ -63,6 +63,7 @@ struct CgSys {
   const uint16_t* hpp; // padded II entries: position in the tile halo
   const uint16_t* hself;
   const double* Fd;    // dense FP64 right-hand sides (nI x ld) in place of -A_IB and f, or nullptr
+  double tol2;         // inner stop of this system: r'M^-1 r <= tol2 * (its value at the (re)start)
 };
 
 // ---------------------------------------------------------------------------------
@@ -140,7 +141,7 @@ void launch_block_inv(const int* rp, const int* col, const double* v64, const in
                       hipStream_t s);
 // column blocks: (system, first column) of 256 columns
 void launch_cg_alpha(const CgSys* sys, const int2* cb, int ncb, hipStream_t s);
-void launch_cg_beta(const CgSys* sys, const int2* cb, int ncb, double tol2, hipStream_t s);
+void launch_cg_beta(const CgSys* sys, const int2* cb, int ncb, hipStream_t s);
 void launch_cg_zero(const CgSys* sys, const int2* cb, int ncb, hipStream_t s);
 void launch_cg_start(const CgSys* sys, const int2* cb, int ncb, int first, double tol2_outer, hipStream_t s);
 

@@ -846,7 +846,7 @@ __global__ void k_cg_alpha(const CgSys* __restrict__ sys, const int2* __restrict
   S.pq[j] = 0.0;
 }
 
-__global__ void k_cg_beta(const CgSys* __restrict__ sys, const int2* __restrict__ cb, double tol2) {
+__global__ void k_cg_beta(const CgSys* __restrict__ sys, const int2* __restrict__ cb) {
   const int2 b = cb[blockIdx.x];
   const CgSys& S = sys[b.x];
   const int j = b.y + threadIdx.x;
@@ -856,7 +856,7 @@ __global__ void k_cg_beta(const CgSys* __restrict__ sys, const int2* __restrict_
     S.rznew[j] = 0.0;
     if (!S.active[j]) {
       S.beta[j] = 0.0;
-    } else if (rn <= tol2 * S.rz0[j]) {
+    } else if (rn <= S.tol2 * S.rz0[j]) {
       S.active[j] = 0;
       S.beta[j] = 0.0;
       S.rz[j] = rn;
@@ -902,8 +902,8 @@ __global__ void k_cg_zero(const CgSys* __restrict__ sys, const int2* __restrict_
 void launch_cg_alpha(const CgSys* sys, const int2* cb, int ncb, hipStream_t s) {
   if (ncb > 0) hipLaunchKernelGGL(k_cg_alpha, dim3(ncb), dim3(256), 0, s, sys, cb);
 }
-void launch_cg_beta(const CgSys* sys, const int2* cb, int ncb, double tol2, hipStream_t s) {
-  if (ncb > 0) hipLaunchKernelGGL(k_cg_beta, dim3(ncb), dim3(256), 0, s, sys, cb, tol2);
+void launch_cg_beta(const CgSys* sys, const int2* cb, int ncb, hipStream_t s) {
+  if (ncb > 0) hipLaunchKernelGGL(k_cg_beta, dim3(ncb), dim3(256), 0, s, sys, cb);
 }
 void launch_cg_zero(const CgSys* sys, const int2* cb, int ncb, hipStream_t s) {
   if (ncb > 0) hipLaunchKernelGGL(k_cg_zero, dim3(ncb), dim3(256), 0, s, sys, cb);
