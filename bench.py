@@ -179,6 +179,8 @@ def main():
                     help="Poisson arrival rate of the serving leg as a fraction of the measured saturation rate")
     ap.add_argument("--cg-rtol", type=float, default=0.0,
                     help="inner block-CG tolerance (0: the library default); FP32 paths refine to the same FP64 target")
+    ap.add_argument("--coarse", type=int, default=1,
+                    help="block-CG preconditioner: 1 two-level (block Jacobi + coarse correction), 0 block Jacobi")
     ap.add_argument("--reduced-solver", choices=("pcg", "cholesky"), default="pcg",
                     help="reduced system: the paper's diagonal-preconditioned conjugate gradients on the "
                          "block-sparse matrix, or a dense FP64 Cholesky factorization")
@@ -211,6 +213,7 @@ def main():
     red_solver = 1 if args.reduced_solver == "pcg" else 0
     t_create = time.perf_counter()
     extra = {"cg_rtol": args.cg_rtol} if args.cg_rtol > 0 else {}
+    extra["coarse"] = args.coarse
     m = mor.Mor(p, precision=prec, use_graph=int(use_graph), reduced_solver=red_solver, **tile, **extra)
     print(f"[bench] context created ({time.perf_counter() - t_create:.0f} s)", file=sys.stderr, flush=True)
     halo = tile.get("spmm_kind", 0) != 2
@@ -288,7 +291,7 @@ def main():
     bytes_per_launch = spmm_bytes / max(n_launch, 1)
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
     kernels = {}
-    for name in ("spmm", "cg_update", "cg_direction", "cg_graph", "residual64", "assemble", "gram", "gram_split", "gram_bf16",
+    for name in ("spmm", "cg_update", "cg_direction", "cg_coarse", "coarse_setup", "cg_graph", "residual64", "assemble", "gram", "gram_split", "gram_bf16",
                  "schur", "potrf", "trsm", "eig", "basis", "project_local", "project", "solve"):
         n, ms, wk = mor.mor_timing_get(m.ctx, name)
         if n:
@@ -349,6 +352,7 @@ def main():
         "config": {"workload": WORKLOAD_OF[args.config], "name": args.config, "subdomains": n_sub,
                    "precision": "fp32_refine | bf16_split, p = 1/2 each" if stream_step else prec,
                    "reduced_dim": int(nred), "hip_graph": use_graph,
+                   "cg_preconditioner": "block Jacobi + coarse correction" if args.coarse else "block Jacobi",
                    "local_svd": f"randomized, {args.sketch} sketch columns" if sketches is not None else "explicit",
                    "tiles": tile or "library defaults"},
         "roofline": {"bound": "hbm",

@@ -133,6 +133,11 @@ typedef struct {
   double reduced_rtol;     /* reduced_solver 1: stop when ||b~ - A~ x|| <= reduced_rtol ||b~|| for the
                               recurrence residual (0 = 1e-12) */
   int32_t reduced_max_iter;/* reduced_solver 1: iteration cap (0 = 20000); MOR_ENOTCONV beyond it */
+  int32_t coarse;          /* 1 (default): two-level preconditioner for the block CG, the block Jacobi
+                              plus an additive coarse correction, piecewise constant on runs of 8 row
+                              aggregates, with the coarse matrix P^T A_II P inverted in FP64 (on the
+                              48^3 workload 25-30% fewer iterations for a small dense product per
+                              iteration); 0: block Jacobi only */
 } mor_opts;
 
 /* Fill `opts` with defaults (FP32_REFINE, cg_rtol 1e-5, refine_rtol 1e-8, ...). */

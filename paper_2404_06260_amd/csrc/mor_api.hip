@@ -59,6 +59,7 @@ struct SubDev {
   int *hrowp = nullptr, *hpe = nullptr;
   uint16_t *hpp = nullptr, *hself = nullptr;
   uint8_t* core = nullptr;
+  int* rcb = nullptr;
 };
 
 struct SubResult {
@@ -230,6 +231,7 @@ extern "C" void mor_default_opts(mor_opts* o) {
   o->reduced_solver = 0;
   o->reduced_rtol = 1e-12;
   o->reduced_max_iter = 20000;
+  o->coarse = 1;
 }
 
 extern "C" int mor_create(const mor_mesh* mesh, const mor_coeff* coeff, const mor_subdomains* sub,
@@ -349,6 +351,7 @@ extern "C" int mor_create(const mor_mesh* mesh, const mor_coeff* coeff, const mo
     r = r ? r : upload(c, &d.hpe, h.hpe.data(), h.hpe.size());
     r = r ? r : upload(c, &d.hpp, h.hpp.data(), h.hpp.size());
     r = r ? r : upload(c, &d.hself, h.hself.data(), h.hself.size());
+    r = r ? r : upload(c, &d.rcb, h.rcb.data(), h.rcb.size());
     return r;
   };
   c->sdev.resize(n);
@@ -562,6 +565,11 @@ struct Slot {
   double *Yk, *Wt, *KWt, *Vs;    // K_i Y, the K_i-orthonormal sketch basis W and K_i W (nV x 64); 64 x 64
   int* info;
   int k_eff;
+  // two-level preconditioner (nc > 0): per system P^T r and A_c^-1 P^T r (nc x ld), A_c and then
+  // A_c^-1 (MPc x MPc), R^-T (MPc x MPc), the Cholesky diagonal-block inverses, pivot reports
+  int nc, MPc, Tc;
+  double *crc[2], *cec[2], *cA[2], *cY[2], *cD[2];
+  int* cinfo;
 };
 
 static void slot_shape(mor_ctx* c, Slot& q) {
@@ -584,6 +592,10 @@ static void slot_shape(mor_ctx* c, Slot& q) {
   q.nconv = std::max(1, std::min(s - 1, q.rank > 0 ? q.rank + 2 : 1));
   q.fp32 = q.prec != MOR_FP64;
   q.refine = q.prec == MOR_FP32_REFINE || q.prec == MOR_BF16_SPLIT;
+  const int nblk = (int)h.bp.size() - 1;
+  q.nc = c->opts.coarse ? (nblk + kCoarseAgg - 1) / kCoarseAgg : 0;
+  q.MPc = (int)rup(std::max(q.nc, 1), 64);
+  q.Tc = q.MPc / 64;
 }
 
 // Device bytes of one request (CG blocks, dense matrices, eigensolver blocks), and the carve.
@@ -649,6 +661,16 @@ static bool slot_layout(Slot& q, Take tk) {
   q.theta = (double*)tk(8 * (size_t)s); q.resid = (double*)tk(8 * (size_t)s);
   q.Bk = (double*)tk(8 * (size_t)q.MP * 64); q.Wk = (double*)tk(8 * (size_t)q.MP * 64);
   q.Yf = (double*)tk(8 * (size_t)std::max(1, h.nP) * (s + 2));
+  for (int w = 0; w < 2; ++w) {
+    const int ld = w == 0 ? q.ldA : q.ldK;
+    const bool on = q.nc > 0;
+    q.crc[w] = on ? (double*)tk(8 * (size_t)q.nc * ld) : nullptr;
+    q.cec[w] = on ? (double*)tk(8 * (size_t)q.nc * ld) : nullptr;
+    q.cA[w] = on ? (double*)tk(8 * (size_t)q.MPc * q.MPc) : nullptr;
+    q.cY[w] = on ? (double*)tk(8 * (size_t)q.MPc * q.MPc) : nullptr;
+    q.cD[w] = on ? (double*)tk(8 * (size_t)q.Tc * 4096) : nullptr;
+  }
+  q.cinfo = q.nc > 0 ? (int*)tk(128) : nullptr;
   q.info = (int*)tk(64);
   return q.info != nullptr;
 }
@@ -675,6 +697,8 @@ struct SysRun {
   int iters, refines;
   int nnzII;
   int nhtile;     // LDS-halo SpMM tiles of the subdomain
+  const double* Ainv = nullptr;   // two-level preconditioner: A_c^-1 (ldac x ldac), or nullptr
+  int ldac = 0;
 };
 
 struct Live {
@@ -707,6 +731,10 @@ struct Launch {
   int ncb = 0;
   double spmm_bytes = 0;
   double stream_bytes = 0;   // update + direction: 8 block-vector elements per entry
+  GemmDesc* gd = nullptr;    // two-level preconditioner: A_c^-1 (P^T r) of every coarse system
+  int4* gt = nullptr;
+  int ngt = 0;
+  double coarse_flops = 0;
 };
 
 // Inner stop of a block-CG system: FP64 systems iterate to the outer target refine_rtol; FP32
@@ -736,6 +764,10 @@ struct MorEngine {
   std::vector<int64_t> g_key;
   int2* d_cb = nullptr;
   size_t cb_cap = 0;
+  GemmDesc* d_gd = nullptr;
+  size_t gd_cap = 0;
+  int4* d_gt = nullptr;
+  size_t gt_cap = 0;
   int* d_cnt = nullptr;
   int* h_cnt = nullptr;
   int cnt_cap = 0;
@@ -785,6 +817,8 @@ static void engine_free(mor_ctx* c, MorEngine& e) {
   dfree(c, e.d_sys);
   dfree(c, e.d_tiles);
   dfree(c, e.d_cb);
+  dfree(c, e.d_gd);
+  dfree(c, e.d_gt);
   if (e.h_cnt) (void)hipHostFree(e.h_cnt);
   e.h_cnt = nullptr;
   if (e.gexec) (void)hipGraphExecDestroy(e.gexec);
@@ -848,9 +882,22 @@ static int engine_upload(mor_ctx* c, MorEngine& e, Launch& L) {
   for (int i = 0; i < n; ++i)
     for (int c0 = 0; c0 < hs[i].ld; c0 += 256) cb.push_back(make_int2(i, c0));
   L.ncb = (int)cb.size();
+  GemmBatch gb;
+  for (int i = 0; i < n; ++i) {
+    const CgSys& S = hs[i];
+    if (S.rc != nullptr)
+      gb.add(gd(S.nc, S.ld, S.nc, L.sys[i]->Ainv, L.sys[i]->ldac, 0, S.rc, S.ld, 0, S.ec, S.ld));
+  }
+  L.ngt = (int)gb.tiles.size();
+  L.coarse_flops = gb.flops();
   if (int rc = grow(c, &e.d_sys, &e.sys_cap, (size_t)std::max(n, 1))) return rc;
   if (int rc = grow(c, &e.d_tiles, &e.tiles_cap, std::max<size_t>(t.size(), 1))) return rc;
   if (int rc = grow(c, &e.d_cb, &e.cb_cap, std::max<size_t>(cb.size(), 1))) return rc;
+  if (int rc = grow(c, &e.d_gd, &e.gd_cap, std::max<size_t>(gb.d.size(), 1))) return rc;
+  if (int rc = grow(c, &e.d_gt, &e.gt_cap, std::max<size_t>(gb.tiles.size(), 1))) return rc;
+  if (!gb.d.empty()) HIPCHK(hipMemcpyAsync(e.d_gd, gb.d.data(), sizeof(GemmDesc) * gb.d.size(), hipMemcpyHostToDevice, c->st));
+  if (!gb.tiles.empty())
+    HIPCHK(hipMemcpyAsync(e.d_gt, gb.tiles.data(), sizeof(int4) * gb.tiles.size(), hipMemcpyHostToDevice, c->st));
   if (n) HIPCHK(hipMemcpyAsync(e.d_sys, hs.data(), sizeof(CgSys) * n, hipMemcpyHostToDevice, c->st));
   if (!t.empty()) HIPCHK(hipMemcpyAsync(e.d_tiles, t.data(), sizeof(int4) * t.size(), hipMemcpyHostToDevice, c->st));
   if (!cb.empty()) HIPCHK(hipMemcpyAsync(e.d_cb, cb.data(), sizeof(int2) * cb.size(), hipMemcpyHostToDevice, c->st));
@@ -859,6 +906,8 @@ static int engine_upload(mor_ctx* c, MorEngine& e, Launch& L) {
   L.bk = e.d_tiles + L.nsp;
   L.hs = e.d_tiles + L.nsp + L.nbk;
   L.cb = e.d_cb;
+  L.gd = e.d_gd;
+  L.gt = e.d_gt;
   e.up_hs.swap(hs);
   e.up_L = L;
   e.up_ok = true;
@@ -871,6 +920,17 @@ static int read_counts(mor_ctx* c, MorEngine& e) {
   return 0;
 }
 
+// Two-level preconditioner at a (re)start, after the block-Jacobi start direction: the coarse
+// solve of the restricted residual, its part of r'M^-1 r, and its correction of P.
+template <typename T>
+static void coarse_start(mor_ctx* c, MorEngine& e, const Launch& L) {
+  if (L.ngt == 0) return;
+  hipStream_t st = c->st;
+  launch_gemm(L.gd, L.gt, L.ngt, st);
+  launch_cg_coarse_dot(e.d_sys, L.cb, L.ncb, 1, st);
+  launch_cg_prolong<T>(e.d_sys, L.bk, L.nbk, e.stm.rb, e.stm.v, st);
+}
+
 // Start the CG of the listed systems from their right-hand sides (zero state, R = F,
 // P = M^-1 R, per-column references); a system with a zero right-hand side is done at once.
 template <typename T>
@@ -881,6 +941,7 @@ static int start_systems(mor_ctx* c, MorEngine& e, Launch& Ln) {
   launch_cg_zero(e.d_sys, Ln.cb, Ln.ncb, st);
   launch_cg_init<T>(e.d_sys, Ln.sp, Ln.nsp, e.sp.rb, e.sp.v, st);
   launch_cg_pstart<T>(e.d_sys, Ln.bk, Ln.nbk, e.stm.rb, e.stm.v, st);
+  coarse_start<T>(c, e, Ln);
   launch_cg_start(e.d_sys, Ln.cb, Ln.ncb, 1, 0.0, st);
   HIPCHK(hipGetLastError());
   if (int rc = read_counts(c, e)) return rc;
@@ -889,6 +950,82 @@ static int start_systems(mor_ctx* c, MorEngine& e, Launch& Ln) {
     R->iters = 0;
     R->refines = 0;
   }
+  return 0;
+}
+
+// Two-level preconditioner set-up of newly admitted requests: for both systems of each,
+// A_c = P^T A_II P (FP64), its Cholesky factor R, R^-T from a triangular solve against the
+// identity, and A_c^-1 = (R^-T)^T R^-T, batched over the systems.  A request whose A_c is not
+// positive definite fails with MOR_EDEVICE.
+static int coarse_setup(mor_ctx* c, const std::vector<Live*>& adm) {
+  hipStream_t st = c->st;
+  std::vector<Live*> ls;
+  for (Live* L : adm)
+    if (L->q.nc > 0) ls.push_back(L);
+  if (ls.empty()) return 0;
+  const int ns = 2 * (int)ls.size();
+  int tmax = 0, mpmax = 0;
+  for (Live* L : ls) {
+    tmax = std::max(tmax, L->q.Tc);
+    mpmax = std::max(mpmax, L->q.MPc);
+  }
+  std::vector<DenseSub> hds(ns);
+  std::vector<TrsmDesc> htd(ns);
+  GemmBatch gb;
+  Sizer z;
+  z.add(8 * (size_t)mpmax * mpmax);
+  z.add(sizeof(DenseSub) * ns);
+  z.add(sizeof(TrsmDesc) * ns);
+  z.add(sizeof(GemmDesc) * ns);
+  size_t tiles = 0;
+  for (Live* L : ls) tiles += 2 * (size_t)L->q.Tc * L->q.Tc;
+  z.add(sizeof(int4) * tiles);
+  char* buf = (char*)dalloc(c, z.total + 4096);
+  if (!buf) return fail(MOR_ENOMEM, "device allocation failed (coarse set-up)");
+  struct G { mor_ctx* c; void* p; ~G() { (void)hipStreamSynchronize(c->st); dfree(c, p); } } guard{c, buf};
+  Arena ar{buf, z.total + 4096, 0};
+  double* ident = (double*)ar.take(8 * (size_t)mpmax * mpmax);
+  DenseSub* dds = (DenseSub*)ar.take(sizeof(DenseSub) * ns);
+  TrsmDesc* dtd = (TrsmDesc*)ar.take(sizeof(TrsmDesc) * ns);
+  if (!dtd) return fail(MOR_ENOMEM, "arena exhausted (coarse set-up)");
+  launch_pad_identity(ident, 0, mpmax, st);
+  for (size_t i = 0; i < ls.size(); ++i) {
+    Slot& q = ls[i]->q;
+    const HostSub& h = *q.h;
+    launch_fill_i(q.cinfo, 32, 0, st);
+    for (int w = 0; w < 2; ++w) {
+      const int ld = w == 0 ? q.ldA : q.ldK;
+      launch_fill(q.cA[w], (int64_t)q.MPc * q.MPc, 0.0, st);
+      launch_coarse_assemble(q.d->rp, q.d->col, q.d->ii_end, w == 0 ? q.A64 : q.K64, q.d->rcb, h.nI, q.cA[w], q.MPc,
+                             st);
+      launch_pad_identity(q.cA[w], q.nc, q.MPc, st);
+      launch_fill(q.crc[w], (int64_t)q.nc * ld, 0.0, st);
+      launch_fill(q.cec[w], (int64_t)q.nc * ld, 0.0, st);
+      hds[2 * i + w] = DenseSub{q.nc, q.MPc, q.Tc, q.cA[w], nullptr, nullptr, nullptr, q.cD[w], q.cinfo + 16 * w};
+      htd[2 * i + w] = TrsmDesc{ident, mpmax, 0, q.cY[w], q.MPc, q.Tc};
+      gb.add(gd(q.nc, q.nc, q.nc, q.cY[w], q.MPc, 1, q.cY[w], q.MPc, 0, q.cA[w], q.MPc, 1.0, 0.0, 1));
+    }
+  }
+  if (int rc = gemm_upload(c, gb, ar)) return rc;
+  HIPCHK(hipMemcpyAsync(dds, hds.data(), sizeof(DenseSub) * ns, hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(dtd, htd.data(), sizeof(TrsmDesc) * ns, hipMemcpyHostToDevice, st));
+  for (int p = 0; p < tmax; ++p) {
+    launch_potrf_diag(dds, ns, p, st);
+    launch_chol_panel(dds, ns, p, tmax, st);
+    launch_chol_syrk(dds, ns, p, tmax, st);
+  }
+  launch_trsm_lt(dds, dtd, ns, tmax, st);
+  gemm_run(c, gb, "coarse_setup");
+  HIPCHK(hipGetLastError());
+  std::vector<int> hinfo(32 * ls.size());
+  for (size_t i = 0; i < ls.size(); ++i)
+    HIPCHK(hipMemcpyAsync(&hinfo[32 * i], ls[i]->q.cinfo, 128, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  for (size_t i = 0; i < ls.size(); ++i)
+    if (hinfo[32 * i] != 0 || hinfo[32 * i + 16] != 0) {
+      ls[i]->status = MOR_EDEVICE;
+      g_err = "subdomain " + std::to_string(ls[i]->q.sd) + ": coarse matrix is not positive definite";
+    }
   return 0;
 }
 
@@ -983,6 +1120,11 @@ static int engine_admit(mor_ctx* c, MorEngine& e) {
       S.P = w == 0 ? q.PA : q.PK; S.Q = w == 0 ? q.QA : q.QK;
       S.X64 = w == 0 ? q.XA64 : q.XK64;
       S.tol2 = inner_tol2<T>(c);
+      S.rc = q.nc > 0 ? q.crc[w] : nullptr;
+      S.ec = q.nc > 0 ? q.cec[w] : nullptr;
+      S.nc = q.nc;
+      R.Ainv = q.nc > 0 ? q.cA[w] : nullptr;
+      R.ldac = q.MPc;
       S.bp = q.d->bp;
       S.nblk = nblk;
       S.minv = w == 0 ? q.minvA : q.minvK;
@@ -1013,6 +1155,7 @@ static int engine_admit(mor_ctx* c, MorEngine& e) {
                               q.M, hipMemcpyHostToDevice, st));
     }
   }
+  if (int rc = coarse_setup(c, adm)) return rc;
   if (int rc = start_systems<T>(c, e, Ln)) return rc;
   for (Live* L : adm) e.live.push_back(L);
   return 0;
@@ -1038,6 +1181,10 @@ static int engine_chunk(mor_ctx* c, MorEngine& e) {
       launch_cg_spmm<T>(e.d_sys, La.sp, La.nsp, e.sp.rb, e.sp.v, s);
     launch_cg_alpha(e.d_sys, La.cb, La.ncb, s);
     launch_cg_update<T>(e.d_sys, La.bk, La.nbk, e.stm.rb, e.stm.v, s);
+    if (La.ngt) {   // two-level preconditioner: coarse solve and its part of r'M^-1 r
+      launch_gemm(La.gd, La.gt, La.ngt, s);
+      launch_cg_coarse_dot(e.d_sys, La.cb, La.ncb, 0, s);
+    }
     launch_cg_beta(e.d_sys, La.cb, La.ncb, s);
     launch_cg_direction<T>(e.d_sys, La.bk, La.nbk, e.stm.rb, e.stm.v, s);
   };
@@ -1049,7 +1196,8 @@ static int engine_chunk(mor_ctx* c, MorEngine& e) {
     const std::vector<int64_t> key = {(int64_t)e.sp.cwb, (int64_t)(intptr_t)e.d_sys, (int64_t)(intptr_t)e.d_tiles,
                                       (int64_t)(intptr_t)e.d_cb, La.nsp, La.nbk, La.nhs, La.ncb, chunk,
                                       (int64_t)(intptr_t)La.hs, (int64_t)(intptr_t)La.bk, (int64_t)(intptr_t)La.cb,
-                                      (int64_t)c->halo_cap};
+                                      (int64_t)c->halo_cap, (int64_t)(intptr_t)La.gd, (int64_t)(intptr_t)La.gt,
+                                      La.ngt};
     if (!e.gexec || e.g_sys != La.sys || e.g_key != key) {
       if (e.gexec) HIPCHK(hipGraphExecDestroy(e.gexec));
       e.gexec = nullptr;
@@ -1082,6 +1230,11 @@ static int engine_chunk(mor_ctx* c, MorEngine& e) {
     {
       ScopedTimer tm(c, "cg_update", 0);
       launch_cg_update<T>(e.d_sys, La.bk, La.nbk, e.stm.rb, e.stm.v, st);
+    }
+    if (La.ngt) {   // two-level preconditioner: coarse solve and its part of r'M^-1 r
+      ScopedTimer tm(c, "cg_coarse", La.coarse_flops);
+      launch_gemm(La.gd, La.gt, La.ngt, st);
+      launch_cg_coarse_dot(e.d_sys, La.cb, La.ncb, 0, st);
     }
     launch_cg_beta(e.d_sys, La.cb, La.ncb, st);
     {
@@ -1116,6 +1269,7 @@ static int engine_chunk(mor_ctx* c, MorEngine& e) {
       launch_cg_residual64<T>(e.d_sys, Lr.sp, Lr.nsp, e.sp.rb, e.sp.v, st);
     }
     launch_cg_pstart<T>(e.d_sys, Lr.bk, Lr.nbk, e.stm.rb, e.stm.v, st);
+    coarse_start<T>(c, e, Lr);
     const double outer2 = c->opts.refine_rtol * c->opts.refine_rtol;
     launch_cg_start(e.d_sys, Lr.cb, Lr.ncb, 0, outer2, st);
     HIPCHK(hipGetLastError());

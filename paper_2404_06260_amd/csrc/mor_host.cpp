@@ -383,6 +383,9 @@ int build_sub(const HostMesh& m, const int32_t* ext, const uint8_t* in_core, int
     s.bp.swap(bp);
     local_tets();
   }
+  s.rcb.assign(s.nI, 0);
+  for (int b = 0; b + 1 < (int)s.bp.size(); ++b)
+    for (int r = s.bp[b]; r < s.bp[b + 1]; ++r) s.rcb[r] = b / kCoarseAgg;
   s.ii_end.resize(s.nI);
   for (int r = 0; r < s.nI; ++r) {
     const int32_t* b = s.col.data() + s.rp[r];

@@ -14,6 +14,8 @@ namespace mor {
 constexpr int kHaloRows = 64;
 constexpr int kHaloCap = 176;   // the largest halo; a context may choose a smaller one (kHaloCaps)
 constexpr int kHaloCaps[5] = {48, 64, 96, 128, 176};
+// two-level preconditioner: a coarse block is a run of this many consecutive row aggregates
+constexpr int kCoarseAgg = 8;
 // padded CSR entries per tile for a halo cap (a Kuhn-cube row has 15 II entries, padded to 16)
 constexpr int halo_nnz_cap(int cap) { return cap * 8 < 1024 ? cap * 8 : 1024; }
 
@@ -44,6 +46,7 @@ struct HostSub {
   std::vector<int32_t> hpe;                // padded II entries: CSR entry id, or -1 (weight 0)
   std::vector<uint16_t> hpp;               // padded II entries: the column's position in the tile halo
   std::vector<uint16_t> hself;             // per I row: the row's own position in its tile halo
+  std::vector<int32_t> rcb;                // per I row: its coarse block (aggregate / kCoarseAgg)
 };
 
 // omega_0: the elements in two or more subdomains, with A_0's pattern over their free nodes.

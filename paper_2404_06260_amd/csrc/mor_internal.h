@@ -64,6 +64,11 @@ struct CgSys {
   const uint16_t* hself;
   const double* Fd;    // dense FP64 right-hand sides (nI x ld) in place of -A_IB and f, or nullptr
   double tol2;         // inner stop of this system: r'M^-1 r <= tol2 * (its value at the (re)start)
+  // two-level preconditioner (rc == nullptr: block Jacobi only).  Coarse block c = aggregates
+  // [8c, 8c+8); M^-1 r = (block Jacobi) r + P A_c^-1 P^T r with P piecewise constant on the blocks
+  double* rc;          // P^T r: nc x ld (FP64), summed by the update / start kernels, cleared after use
+  double* ec;          // A_c^-1 P^T r: nc x ld (FP64)
+  int nc;
 };
 
 // ---------------------------------------------------------------------------------
@@ -136,6 +141,11 @@ template <typename T>
 void launch_cg_direction(const CgSys* sys, const int4* tiles, int ntiles, int bpt, int v, hipStream_t s);
 template <typename T>
 void launch_cg_pstart(const CgSys* sys, const int4* tiles, int ntiles, int bpt, int v, hipStream_t s);
+template <typename T>
+void launch_cg_prolong(const CgSys* sys, const int4* tiles, int ntiles, int bpt, int v, hipStream_t s);
+void launch_cg_coarse_dot(const CgSys* sys, const int2* cb, int ncb, int at_start, hipStream_t s);
+void launch_coarse_assemble(const int* rp, const int* col, const int* ii_end, const double* v64, const int* rcb, int nI,
+                            double* Ac, int ldac, hipStream_t s);
 template <typename T>
 void launch_block_inv(const int* rp, const int* col, const double* v64, const int* bp, int nblk, void* minv,
                       hipStream_t s);

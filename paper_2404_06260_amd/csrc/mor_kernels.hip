@@ -515,6 +515,40 @@ __device__ __forceinline__ void block_apply(const T* __restrict__ minv, int r0, 
   }
 }
 
+// Two-level preconditioner, restriction: add the column sums of aggregate b's rows (rr) to the
+// running sums of its coarse block.  A tile whose aggregates all lie in one coarse block sums
+// in registers and across the workgroup (coarse_flush); otherwise each aggregate adds its own.
+template <typename T, int V>
+__device__ __forceinline__ void coarse_gather(const CgSys& S, bool one_block, int b, int nb, int c0,
+                                              const T (&rr)[8][V], double (&cs)[V]) {
+  double s[V];
+#pragma unroll
+  for (int q = 0; q < V; ++q) s[q] = 0.0;
+#pragma unroll
+  for (int j = 0; j < 8; ++j)
+    if (j < nb) {
+#pragma unroll
+      for (int q = 0; q < V; ++q) s[q] += (double)rr[j][q];
+    }
+  if (one_block) {
+#pragma unroll
+    for (int q = 0; q < V; ++q) cs[q] += s[q];
+  } else {
+    double* dst = S.rc + (int64_t)(b / kCoarseAgg) * S.ld + c0;
+#pragma unroll
+    for (int q = 0; q < V; ++q)
+      if (c0 + q < S.ld && s[q] != 0.0) unsafeAtomicAdd(dst + q, s[q]);
+  }
+}
+// every thread of the workgroup calls this (it synchronises)
+template <int V>
+__device__ __forceinline__ void coarse_flush(const CgSys& S, bool one_block, int b0, int c0tile,
+                                             double (*red)[64 * 4], const double (&cs)[V]) {
+  if (S.rc == nullptr || !one_block) return;
+  __syncthreads();   // red may still be read by an earlier reduction
+  column_reduce_add<V>(red, cs, c0tile, S.ld, S.rc + (int64_t)(b0 / kCoarseAgg) * S.ld);
+}
+
 // P = M^-1 R and r'M^-1 r (start and restarts of the CG)
 template <typename T, int V>
 __global__ __launch_bounds__(256) void k_cg_pstart(const CgSys* __restrict__ sys, const int4* __restrict__ tiles,
@@ -523,9 +557,10 @@ __global__ __launch_bounds__(256) void k_cg_pstart(const CgSys* __restrict__ sys
   MOR_BLOCK_PROLOGUE(V)
   const T* minv = (const T*)S.minv;
   const T* R = (const T*)S.R; T* P = (T*)S.P;
-  double part[V];
+  const bool one_block = tl.y / kCoarseAgg == (bend - 1) / kCoarseAgg;
+  double part[V], cs[V];
 #pragma unroll
-  for (int q = 0; q < V; ++q) part[q] = 0.0;
+  for (int q = 0; q < V; ++q) part[q] = cs[q] = 0.0;
   if (act) {
     for (int b = tl.y + w; b < bend; b += 4) {
       const int r0 = gld(S.bp + b), nb = gld(S.bp + b + 1) - r0;
@@ -538,6 +573,7 @@ __global__ __launch_bounds__(256) void k_cg_pstart(const CgSys* __restrict__ sys
           for (int q = 0; q < V; ++q) rr[j][q] = 0;
         }
       }
+      if (S.rc != nullptr) coarse_gather<T, V>(S, one_block, b, nb, c0, rr, cs);
 #pragma unroll
       for (int j = 0; j < 8; ++j) {
         if (j < nb) {
@@ -551,6 +587,7 @@ __global__ __launch_bounds__(256) void k_cg_pstart(const CgSys* __restrict__ sys
     }
   }
   column_reduce_add<V>(red, part, tl.z, ld, S.rz);
+  coarse_flush<V>(S, one_block, tl.y, tl.z, red, cs);
 }
 
 // R -= alpha Q and the new r'M^-1 r
@@ -561,11 +598,12 @@ __global__ __launch_bounds__(256) void k_cg_update(const CgSys* __restrict__ sys
   MOR_BLOCK_PROLOGUE(V)
   const T* minv = (const T*)S.minv;
   T* R = (T*)S.R; const T* Q = (const T*)S.Q;
+  const bool one_block = tl.y / kCoarseAgg == (bend - 1) / kCoarseAgg;
   T al[V];
-  double part[V];
+  double part[V], cs[V];
 #pragma unroll
   for (int q = 0; q < V; ++q) {
-    part[q] = 0.0;
+    part[q] = cs[q] = 0.0;
     al[q] = act ? (T)S.alpha[c0 + q] : (T)0;
   }
   if (act) {
@@ -586,6 +624,7 @@ __global__ __launch_bounds__(256) void k_cg_update(const CgSys* __restrict__ sys
       for (int j = 0; j < 8; ++j)
 #pragma unroll
         for (int q = 0; q < V; ++q) rr[j][q] -= al[q] * qq[j][q];
+      if (S.rc != nullptr) coarse_gather<T, V>(S, one_block, b, nb, c0, rr, cs);
 #pragma unroll
       for (int j = 0; j < 8; ++j) {
         if (j < nb) {
@@ -599,6 +638,7 @@ __global__ __launch_bounds__(256) void k_cg_update(const CgSys* __restrict__ sys
     }
   }
   column_reduce_add<V>(red, part, tl.z, ld, S.rznew);
+  coarse_flush<V>(S, one_block, tl.y, tl.z, red, cs);
 }
 
 // X += alpha P (the step of this iteration), then P = M^-1 R + beta P
@@ -617,6 +657,14 @@ __global__ __launch_bounds__(256) void k_cg_direction(const CgSys* __restrict__ 
   }
   for (int b = tl.y + w; b < bend; b += 4) {
     const int r0 = gld(S.bp + b), nb = gld(S.bp + b + 1) - r0;
+    T ec[V];   // coarse correction of this aggregate's block (two-level preconditioner)
+#pragma unroll
+    for (int q = 0; q < V; ++q) ec[q] = 0;
+    if (S.ec != nullptr) {
+      const double* e = S.ec + (int64_t)(b / kCoarseAgg) * ld + c0;
+#pragma unroll
+      for (int q = 0; q < V; ++q) ec[q] = (T)e[q];
+    }
     T rr[8][V], pp[8][V];
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
@@ -638,11 +686,35 @@ __global__ __launch_bounds__(256) void k_cg_direction(const CgSys* __restrict__ 
 #pragma unroll
         for (int q = 0; q < V; ++q) {
           x[q] += al[q] * pp[j][q];
-          z[q] += be[q] * pp[j][q];
+          z[q] += ec[q] + be[q] * pp[j][q];
         }
         st_vec<T, V>(X + o, x);
         st_vec<T, V>(P + o, z);
       }
+    }
+  }
+}
+
+// P += P_c A_c^-1 P_c^T R at a (re)start of the two-level preconditioned CG: the coarse
+// correction of each aggregate's block, added to the block-Jacobi start direction
+template <typename T, int V>
+__global__ __launch_bounds__(256) void k_cg_prolong(const CgSys* __restrict__ sys, const int4* __restrict__ tiles,
+                                                    int ntiles, int bpt) {
+  MOR_BLOCK_PROLOGUE(V)
+  if (!act || S.ec == nullptr) return;
+  T* P = (T*)S.P;
+  for (int b = tl.y + w; b < bend; b += 4) {
+    const int r0 = gld(S.bp + b), nb = gld(S.bp + b + 1) - r0;
+    const double* e = S.ec + (int64_t)(b / kCoarseAgg) * ld + c0;
+    T ec[V];
+#pragma unroll
+    for (int q = 0; q < V; ++q) ec[q] = (T)e[q];
+    for (int j = 0; j < nb; ++j) {
+      T p[V];
+      ld_vec<T, V>(P + (int64_t)(r0 + j) * ld + c0, p);
+#pragma unroll
+      for (int q = 0; q < V; ++q) p[q] += ec[q];
+      st_vec<T, V>(P + (int64_t)(r0 + j) * ld + c0, p);
     }
   }
 }
@@ -809,6 +881,10 @@ template <typename T>
 void launch_cg_pstart(const CgSys* sys, const int4* tiles, int ntiles, int bpt, int v, hipStream_t s) {
   if (ntiles > 0) MOR_VSWITCH(T, v, k_cg_pstart, sys, tiles, ntiles, bpt);
 }
+template <typename T>
+void launch_cg_prolong(const CgSys* sys, const int4* tiles, int ntiles, int bpt, int v, hipStream_t s) {
+  if (ntiles > 0) MOR_VSWITCH(T, v, k_cg_prolong, sys, tiles, ntiles, bpt);
+}
 #define MOR_INST(T)                                                                                      \
   template void launch_cg_init<T>(const CgSys*, const int4*, int, int, int, hipStream_t);       \
   template void launch_cg_spmm<T>(const CgSys*, const int4*, int, int, int, hipStream_t);       \
@@ -817,7 +893,8 @@ void launch_cg_pstart(const CgSys* sys, const int4* tiles, int ntiles, int bpt, 
   template void launch_cg_direction<T>(const CgSys*, const int4*, int, int, int, hipStream_t);  \
   template void launch_cg_residual64<T>(const CgSys*, const int4*, int, int, int, hipStream_t); \
   template void launch_cg_shadow<T>(const CgSys*, const int4*, int, int, int, hipStream_t);        \
-  template void launch_cg_pstart<T>(const CgSys*, const int4*, int, int, int, hipStream_t);
+  template void launch_cg_pstart<T>(const CgSys*, const int4*, int, int, int, hipStream_t);       \
+  template void launch_cg_prolong<T>(const CgSys*, const int4*, int, int, int, hipStream_t);
 MOR_INST(float)
 MOR_INST(double)
 #undef MOR_INST
@@ -885,6 +962,43 @@ __global__ void k_cg_start(const CgSys* __restrict__ sys, const int2* __restrict
   S.rznew[j] = 0.0;
   S.active[j] = first ? (rz > 0.0 ? 1 : 0) : ((rz > tol2_outer * S.rzF[j]) ? 1 : 0);
 }
+// r'M^-1 r of the two-level preconditioner, coarse part: (P^T r)' A_c^-1 (P^T r) per column,
+// added to the fine part (rznew during the iteration, rz at a start); P^T r is cleared for the
+// next restriction.
+__global__ void k_cg_coarse_dot(const CgSys* __restrict__ sys, const int2* __restrict__ cb, int at_start) {
+  const int2 b = cb[blockIdx.x];
+  const CgSys& S = sys[b.x];
+  const int j = b.y + threadIdx.x;
+  if (S.rc == nullptr || j >= S.ld) return;
+  double s = 0.0;
+  for (int c = 0; c < S.nc; ++c) {
+    const int64_t o = (int64_t)c * S.ld + j;
+    s += S.rc[o] * S.ec[o];
+    S.rc[o] = 0.0;
+  }
+  if (at_start) S.rz[j] += s;
+  else S.rznew[j] += s;
+}
+void launch_cg_coarse_dot(const CgSys* sys, const int2* cb, int ncb, int at_start, hipStream_t s) {
+  if (ncb > 0) hipLaunchKernelGGL(k_cg_coarse_dot, dim3(ncb), dim3(256), 0, s, sys, cb, at_start);
+}
+
+// A_c = P^T A_II P for the piecewise-constant coarse space: entry (rcb[r], rcb[c]) sums A_II[r, c]
+__global__ void k_coarse_assemble(const int* __restrict__ rp, const int* __restrict__ col,
+                                  const int* __restrict__ ii_end, const double* __restrict__ v64,
+                                  const int* __restrict__ rcb, int nI, double* Ac, int ldac) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= nI) return;
+  const int cr = rcb[r];
+  for (int e = rp[r]; e < ii_end[r]; ++e) unsafeAtomicAdd(&Ac[(int64_t)cr * ldac + rcb[col[e]]], v64[e]);
+}
+void launch_coarse_assemble(const int* rp, const int* col, const int* ii_end, const double* v64, const int* rcb, int nI,
+                            double* Ac, int ldac, hipStream_t s) {
+  if (nI > 0)
+    hipLaunchKernelGGL(k_coarse_assemble, dim3((nI + 255) / 256), dim3(256), 0, s, rp, col, ii_end, v64, rcb, nI, Ac,
+                       ldac);
+}
+
 __global__ void k_cg_count(const CgSys* __restrict__ sys, const int2* __restrict__ cb) {
   const int2 b = cb[blockIdx.x];
   const CgSys& S = sys[b.x];

@@ -324,3 +324,78 @@ def test_reduced_pcg_matches_oracle(name):
         np.testing.assert_allclose(bt, bd, rtol=0, atol=1e-10 * np.abs(bd).max())
     finally:
         d["ctx"].close()
+
+
+# --------------------------------------------------------------------------------------
+# the two-level preconditioner of the block CG (option `coarse`): block Jacobi plus an additive
+# piecewise-constant coarse correction.  It changes only how fast the CG converges, so the
+# results must meet the same bars against the oracle.  (Iteration counts are printed; on these
+# small subdomains the coarse space has about ten blocks and saves little.)
+
+def _whole_path_checks(p, ref, m, k, u, precision):
+    from paper_2404_06260_amd import mor
+    kref = np.array([r.k_eff for r in ref["results"]])
+    np.testing.assert_array_equal(k, kref)
+    for i, r in enumerate(ref["results"]):
+        sig = mor.mor_get_sigma(m.ctx, i)
+        ns = min(sig.size, r.k_eff + 1)
+        np.testing.assert_allclose(sig[:ns], r.sigma[:ns], rtol=TOL_SIGMA[precision])
+        nP, nV, nI, nB = mor.mor_get_sizes(m.ctx, i)
+        nodes = mor.mor_get_nodes(m.ctx, i)[:nV]
+        Vs = mor.mor_get_basis(m.ctx, i)[np.argsort(nodes)]
+        lm = oreduce.local_matrices(p.mesh, p.kappa, p.f_nodal, r.sets)
+        s = _sin_angle(Vs[:, 1:], r.Phi, lm.K_i.toarray())
+        assert s < TOL_ANGLE[precision], (i, s)
+    rel = _energy_rel(ref, u)
+    assert rel < TOL_ENERGY[precision], rel
+    return rel
+
+
+@pytest.mark.parametrize("name", ["small-lognormal", "general"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32_refine", "bf16_split", "fp32"])
+def test_two_level_preconditioner_matches_oracle(name, precision):
+    from paper_2404_06260_amd import mor
+    p = _problem(name)
+    ref = _oracle(name, p)
+    base = _run_gpu(p, precision, coarse=0)
+    try:
+        it0 = [mor.mor_get_stats(base["ctx"].ctx, i) for i in range(p.subdomains.n_sub)]
+    finally:
+        base["ctx"].close()
+    g = _run_gpu(p, precision, coarse=1)
+    m = g["ctx"]
+    try:
+        rel = _whole_path_checks(p, ref, m, g["k"], g["u"], precision)
+        it1 = [mor.mor_get_stats(m.ctx, i) for i in range(p.subdomains.n_sub)]
+        a0 = sum(s["cg_iter_a"] for s in it0)
+        a1 = sum(s["cg_iter_a"] for s in it1)
+        k0 = sum(s["cg_iter_k"] for s in it0)
+        k1 = sum(s["cg_iter_k"] for s in it1)
+        _say(f"[gpu] {name} {precision} two-level: energy rel {rel:.2e}, CG iterations A {a0} -> {a1}, K {k0} -> {k1}")
+    finally:
+        m.close()
+
+
+def test_two_level_preconditioner_in_graph_mode_and_serving():
+    """The coarse GEMM and coarse dot inside a captured CG chunk, and requests joining and
+    leaving the batch, give the oracle's solution."""
+    from paper_2404_06260_amd import mor, serve
+    p = _problem("uneven-jitter")
+    ref = _oracle("uneven-jitter", p)
+    g = _run_gpu(p, "fp32_refine", coarse=1, use_graph=1)
+    try:
+        _whole_path_checks(p, ref, g["ctx"], g["k"], g["u"], "fp32_refine")
+    finally:
+        g["ctx"].close()
+    m = mor.Mor(p, precision="fp32_refine", coarse=1, cg_chunk=4)
+    try:
+        st = serve.make_stream(p, p.subdomains.n_sub, rate=400.0, seed_arrivals=61, seed_order=62)
+        res = serve.run_stream(m.ctx, st)
+        assert (res.status == 0).all() and res.max_live >= 2
+        m.project()
+        u, _ = m.solve()
+        rel = _energy_rel(ref, u)
+        _say(f"[gpu] two-level serving: max live {res.max_live}, energy rel {rel:.2e}")
+        assert rel < TOL_ENERGY["fp32_refine"], rel
+    finally:
+        m.close()
