@@ -799,6 +799,8 @@ static int engine_init(mor_ctx* c, MorEngine& e, int elt) {
   e.stm.v = c->opts.stream_vec > 0 ? c->opts.stream_vec : 2;   // block kernels hold 8 rows per lane
   if (!fp32 && e.stm.v > 2) e.stm.v = 2;
   e.stm.rb = c->opts.stream_blocks > 0 ? c->opts.stream_blocks : 8;
+  // two-level preconditioner: every streaming tile lies inside one coarse block
+  if (c->opts.coarse && kCoarseAgg % e.stm.rb != 0) e.stm.rb = kCoarseAgg;
   e.budget = c->opts.hbm_budget_bytes;
   if (!e.budget) {
     size_t fr = 0, tot = 0;

@@ -515,38 +515,66 @@ __device__ __forceinline__ void block_apply(const T* __restrict__ minv, int r0, 
   }
 }
 
-// Two-level preconditioner, restriction: add the column sums of aggregate b's rows (rr) to the
-// running sums of its coarse block.  A tile whose aggregates all lie in one coarse block sums
-// in registers and across the workgroup (coarse_flush); otherwise each aggregate adds its own.
+// Two-level preconditioner, restriction: add the column sums of an aggregate's rows (rr) to this
+// thread's running sums.  The host makes the streaming tiles divide the coarse blocks, so all
+// aggregates of a workgroup lie in one block; the sums leave the kernel once, after the loop
+// (stores inside the loop would keep the uniform block-inverse loads off the scalar cache).
 template <typename T, int V>
-__device__ __forceinline__ void coarse_gather(const CgSys& S, bool one_block, int b, int nb, int c0,
-                                              const T (&rr)[8][V], double (&cs)[V]) {
-  double s[V];
-#pragma unroll
-  for (int q = 0; q < V; ++q) s[q] = 0.0;
+__device__ __forceinline__ void coarse_gather(int nb, const T (&rr)[8][V], double (&cs)[V]) {
 #pragma unroll
   for (int j = 0; j < 8; ++j)
     if (j < nb) {
 #pragma unroll
-      for (int q = 0; q < V; ++q) s[q] += (double)rr[j][q];
+      for (int q = 0; q < V; ++q) cs[q] += (double)rr[j][q];
     }
-  if (one_block) {
-#pragma unroll
-    for (int q = 0; q < V; ++q) cs[q] += s[q];
-  } else {
-    double* dst = S.rc + (int64_t)(b / kCoarseAgg) * S.ld + c0;
-#pragma unroll
-    for (int q = 0; q < V; ++q)
-      if (c0 + q < S.ld && s[q] != 0.0) unsafeAtomicAdd(dst + q, s[q]);
-  }
 }
-// every thread of the workgroup calls this (it synchronises)
+
+// The per-column r'M^-1 r partial sums (added to acc) and, with the two-level preconditioner,
+// the coarse block's column sums, reduced over the 4 waves (in one LDS pass when both fit).  A
+// tile that covers its whole coarse block (the default tiles of 8 aggregates) stores the block's
+// sums; tiles that share a block add theirs.  Every thread of the workgroup calls this.
 template <int V>
-__device__ __forceinline__ void coarse_flush(const CgSys& S, bool one_block, int b0, int c0tile,
-                                             double (*red)[64 * 4], const double (&cs)[V]) {
-  if (S.rc == nullptr || !one_block) return;
-  __syncthreads();   // red may still be read by an earlier reduction
-  column_reduce_add<V>(red, cs, c0tile, S.ld, S.rc + (int64_t)(b0 / kCoarseAgg) * S.ld);
+__device__ __forceinline__ void reduce_rz_coarse(double (*red)[64 * 4], const double (&part)[V], const double (&cs)[V],
+                                                 const CgSys& S, bool whole, int b0, int c0tile,
+                                                 double* __restrict__ acc) {
+  if (S.rc == nullptr) {
+    column_reduce_add<V>(red, part, c0tile, S.ld, acc);
+    return;
+  }
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  double* rc = S.rc + (int64_t)(b0 / kCoarseAgg) * S.ld;
+  auto emit = [&](int i, bool rz, int c) {
+    const double s = red[0][i] + red[1][i] + red[2][i] + red[3][i];
+    if (rz) {
+      if (s != 0.0) unsafeAtomicAdd(&acc[c], s);
+    } else if (whole) {
+      rc[c] = s;
+    } else if (s != 0.0) {
+      unsafeAtomicAdd(&rc[c], s);
+    }
+  };
+  if (2 * 64 * V <= 64 * 4) {
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      red[w][lane * V + v] = part[v];
+      red[w][64 * V + lane * V + v] = cs[v];
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < 2 * 64 * V; i += 256) {
+      const bool rz = i < 64 * V;
+      const int c = c0tile + (rz ? i : i - 64 * V);
+      if (c < S.ld) emit(i, rz, c);
+    }
+    return;
+  }
+  for (int pass = 0; pass < 2; ++pass) {
+    if (pass) __syncthreads();   // the first pass has finished reading red
+#pragma unroll
+    for (int v = 0; v < V; ++v) red[w][lane * V + v] = pass ? cs[v] : part[v];
+    __syncthreads();
+    for (int i = threadIdx.x; i < 64 * V; i += 256)
+      if (c0tile + i < S.ld) emit(i, pass == 0, c0tile + i);
+  }
 }
 
 // P = M^-1 R and r'M^-1 r (start and restarts of the CG)
@@ -557,7 +585,6 @@ __global__ __launch_bounds__(256) void k_cg_pstart(const CgSys* __restrict__ sys
   MOR_BLOCK_PROLOGUE(V)
   const T* minv = (const T*)S.minv;
   const T* R = (const T*)S.R; T* P = (T*)S.P;
-  const bool one_block = tl.y / kCoarseAgg == (bend - 1) / kCoarseAgg;
   double part[V], cs[V];
 #pragma unroll
   for (int q = 0; q < V; ++q) part[q] = cs[q] = 0.0;
@@ -573,7 +600,7 @@ __global__ __launch_bounds__(256) void k_cg_pstart(const CgSys* __restrict__ sys
           for (int q = 0; q < V; ++q) rr[j][q] = 0;
         }
       }
-      if (S.rc != nullptr) coarse_gather<T, V>(S, one_block, b, nb, c0, rr, cs);
+      if (S.rc != nullptr) coarse_gather<T, V>(nb, rr, cs);
 #pragma unroll
       for (int j = 0; j < 8; ++j) {
         if (j < nb) {
@@ -586,8 +613,8 @@ __global__ __launch_bounds__(256) void k_cg_pstart(const CgSys* __restrict__ sys
       }
     }
   }
-  column_reduce_add<V>(red, part, tl.z, ld, S.rz);
-  coarse_flush<V>(S, one_block, tl.y, tl.z, red, cs);
+  const bool whole = tl.y % kCoarseAgg == 0 && (bend - tl.y >= kCoarseAgg || bend == S.nblk);
+  reduce_rz_coarse<V>(red, part, cs, S, whole, tl.y, tl.z, S.rz);
 }
 
 // R -= alpha Q and the new r'M^-1 r
@@ -598,7 +625,6 @@ __global__ __launch_bounds__(256) void k_cg_update(const CgSys* __restrict__ sys
   MOR_BLOCK_PROLOGUE(V)
   const T* minv = (const T*)S.minv;
   T* R = (T*)S.R; const T* Q = (const T*)S.Q;
-  const bool one_block = tl.y / kCoarseAgg == (bend - 1) / kCoarseAgg;
   T al[V];
   double part[V], cs[V];
 #pragma unroll
@@ -624,7 +650,7 @@ __global__ __launch_bounds__(256) void k_cg_update(const CgSys* __restrict__ sys
       for (int j = 0; j < 8; ++j)
 #pragma unroll
         for (int q = 0; q < V; ++q) rr[j][q] -= al[q] * qq[j][q];
-      if (S.rc != nullptr) coarse_gather<T, V>(S, one_block, b, nb, c0, rr, cs);
+      if (S.rc != nullptr) coarse_gather<T, V>(nb, rr, cs);
 #pragma unroll
       for (int j = 0; j < 8; ++j) {
         if (j < nb) {
@@ -637,8 +663,8 @@ __global__ __launch_bounds__(256) void k_cg_update(const CgSys* __restrict__ sys
       }
     }
   }
-  column_reduce_add<V>(red, part, tl.z, ld, S.rznew);
-  coarse_flush<V>(S, one_block, tl.y, tl.z, red, cs);
+  const bool whole = tl.y % kCoarseAgg == 0 && (bend - tl.y >= kCoarseAgg || bend == S.nblk);
+  reduce_rz_coarse<V>(red, part, cs, S, whole, tl.y, tl.z, S.rznew);
 }
 
 // X += alpha P (the step of this iteration), then P = M^-1 R + beta P
