@@ -251,6 +251,8 @@ int mor_get_stats(mor_ctx* ctx, int32_t sd, int32_t* cg_iter_a, int32_t* cg_iter
 
 /* Per-kernel device timing with HIP events on the library's stream.
  * name: "spmm" (the block-CG sparse product), "cg_update", "cg_direction",
+ * "cg_coarse" (the coarse solve of the two-level preconditioner, flops), "coarse_setup",
+ * "cg_graph" (a whole CG chunk in graph mode), "residual64",
  * "gram", "schur", "potrf", "trsm", "eig", "assemble", "project", "solve"
  * (the reduced solve; for conjugate gradients its work is 2 nnz(A~) flops per iteration).
  * Reports launches, total milliseconds and algorithmic bytes (spmm) or flops. */
