@@ -134,6 +134,58 @@ def pcg_diag(At: np.ndarray, bt: np.ndarray, rtol: float = 1e-12, max_iter: int 
     raise RuntimeError(f"reduced PCG did not reach {rtol} in {max_iter} iterations")
 
 
+def block_pinv(At: np.ndarray, off, drop: float = 1e-10) -> np.ndarray:
+    """The block-diagonal preconditioner of the reduced system: for each subdomain's diagonal
+    block A~_ii = U Lambda U^T, the pseudo-inverse U_r Lambda_r^-1 U_r^T over the eigenvalues
+    above drop * lambda_max (the directions the basis update of Section 6, step 2 keeps)."""
+    n = At.shape[0]
+    M = np.zeros((n, n))
+    for i in range(len(off) - 1):
+        a, b = int(off[i]), int(off[i + 1])
+        lam, U = np.linalg.eigh(0.5 * (At[a:b, a:b] + At[a:b, a:b].T))
+        keep = lam > drop * lam.max()
+        M[a:b, a:b] = (U[:, keep] / lam[keep]) @ U[:, keep].T
+    return M
+
+
+def pcg_block(At: np.ndarray, bt: np.ndarray, off, drop: float = 1e-10, rtol: float = 1e-12, max_iter: int = 20000,
+              on_iter=None):
+    """Conjugate gradients on A~ x = b~ preconditioned by `block_pinv` (reading of Section 6:
+    after the basis update the diagonal blocks are the identity and the paper's diagonal
+    preconditioner leaves plain CG on the updated system, which is this iteration on the
+    un-updated one).  Same steps and stopping test as `pcg_diag`; the preconditioner may be
+    singular (dropped directions), so x stays in its range."""
+    A = np.asarray(At, dtype=np.float64)
+    b = np.asarray(bt, dtype=np.float64)
+    Minv = block_pinv(A, off, drop)
+    x = np.zeros_like(b)
+    nb = np.linalg.norm(b)
+    if nb == 0.0:
+        return x, 0, 0.0
+    r = b.copy()
+    z = Minv @ r
+    p = z.copy()
+    rz = r @ z
+    for k in range(1, max_iter + 1):
+        q = A @ p
+        pq = p @ q
+        if not pq > 0.0:
+            raise np.linalg.LinAlgError("p'Ap <= 0: the reduced matrix is not positive definite")
+        alpha = rz / pq
+        x = x + alpha * p
+        r = r - alpha * q
+        if on_iter is not None:
+            on_iter(k, x, r)
+        res = np.linalg.norm(r) / nb
+        if res <= rtol:
+            return x, k, res
+        z = Minv @ r
+        rz_new = r @ z
+        p = z + (rz_new / rz) * p
+        rz = rz_new
+    raise RuntimeError(f"reduced block PCG did not reach {rtol} in {max_iter} iterations")
+
+
 def reconstruct(mesh, results, x: np.ndarray) -> np.ndarray:
     """u~ = sum_i S_i (Q_i x_i): on P_i the value is Vloc_i x_i; zero on the Dirichlet nodes."""
     off = offsets(results)

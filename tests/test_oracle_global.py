@@ -8,7 +8,8 @@
   reduced PCG           the diagonal-preconditioned CG of Section 6 step 3 against exact
                         statements: one step on a diagonal matrix, LAPACK's solution, a
                         monotone A-norm error, recurrence = true residual, invariance under
-                        diagonal scaling, and the Cholesky route on a real reduced system
+                        diagonal scaling, and the Cholesky route on a real reduced system;
+                        the block-preconditioned variant equals plain CG after the basis update
 """
 import numpy as np
 import pytest
@@ -219,3 +220,34 @@ def test_pcg_on_a_reduced_system_matches_cholesky():
 def test_pcg_rejects_an_indefinite_matrix():
     with pytest.raises(np.linalg.LinAlgError):
         project.pcg_diag(np.diag([2.0, -1.0]), np.array([1.0, 1.0]))
+
+
+def test_block_pcg_solves_a_block_diagonal_system_in_one_step():
+    rng = np.random.default_rng(3)
+    blocks = [_spd(k, 30.0, 10 + k) for k in (3, 5, 2)]
+    A = np.zeros((10, 10))
+    off = [0, 3, 8, 10]
+    for (a, b), B in zip(zip(off[:-1], off[1:]), blocks):
+        A[a:b, a:b] = B
+    bvec = rng.standard_normal(10)
+    x, it, res = project.pcg_block(A, bvec, off, rtol=1e-13)
+    assert it == 1 and res < 1e-13
+    np.testing.assert_allclose(x, np.linalg.solve(A, bvec), rtol=1e-12)
+
+
+def test_block_pcg_equals_plain_cg_after_the_basis_update():
+    """Block-pseudo-inverse PCG on Q^T A Q and plain CG on the reduced system of the updated bases
+    (diagonal blocks = I, so the diagonal preconditioner is the identity) are one iteration in
+    exact arithmetic: same iteration count (to one) and the same energy x^T b~."""
+    p = w.make_problem(10, (2, 2, 2), r=2, rank=6, kappa="lognormal", seed=12)
+    res = reduce.reduce_all(p, workers=1)
+    At, bt, off = project.reduced_system(p.mesh, p.kappa, p.subdomains, res)
+    upd = [reduce.basis_update(r, drop=1e-10) for r in res]
+    Au, bu, _ = project.reduced_system(p.mesh, p.kappa, p.subdomains, upd)
+    np.testing.assert_allclose(np.diag(Au), 1.0, rtol=1e-9)
+    xb, itb, _ = project.pcg_block(At, bt, off, drop=1e-10, rtol=1e-12)
+    xu, itu, _ = project.pcg_diag(Au, bu, rtol=1e-12)
+    assert abs(itb - itu) <= 1, (itb, itu)
+    np.testing.assert_allclose(xb @ bt, xu @ bu, rtol=1e-10)
+    xc = project.solve_reduced(At, bt)
+    np.testing.assert_allclose(xb, xc, rtol=0, atol=1e-9 * np.abs(xc).max())
