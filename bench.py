@@ -181,9 +181,14 @@ def main():
                     help="inner block-CG tolerance (0: the library default); FP32 paths refine to the same FP64 target")
     ap.add_argument("--coarse", type=int, default=1,
                     help="block-CG preconditioner: 1 two-level (block Jacobi + coarse correction), 0 block Jacobi")
-    ap.add_argument("--reduced-solver", choices=("pcg", "cholesky"), default="pcg",
+    ap.add_argument("--reduced-solver", choices=("pcg", "pcg-block", "cholesky"), default="pcg",
                     help="reduced system: the paper's diagonal-preconditioned conjugate gradients on the "
-                         "block-sparse matrix, or a dense FP64 Cholesky factorization")
+                         "block-sparse matrix, the same with block-Jacobi preconditioning, or a dense FP64 "
+                         "Cholesky factorization")
+    ap.add_argument("--basis-update", type=int, default=-1,
+                    help="1: the basis update of Section 6 step 2 (whitened diagonal blocks, dependent directions "
+                         "dropped); -1: on for the inclusions stream (high-contrast coefficient, ranks up to 48, "
+                         "whose stitched columns are nearly dependent), off otherwise")
     ap.add_argument("--calibrate-copy", type=int, default=0,
                     help="MiB copied by one plain device copy before the steps (HBM counter calibration)")
     args = ap.parse_args()
@@ -210,10 +215,13 @@ def main():
     else:
         tile = dict(spmm_rows=args.spmm_rows)
     use_graph = (args.config == "C3") if args.graph < 0 else bool(args.graph)
-    red_solver = 1 if args.reduced_solver == "pcg" else 0
+    red_solver = {"cholesky": 0, "pcg": 1, "pcg-block": 2}[args.reduced_solver]
     t_create = time.perf_counter()
     extra = {"cg_rtol": args.cg_rtol} if args.cg_rtol > 0 else {}
     extra["coarse"] = args.coarse
+    basis_update = (args.config == "C5") if args.basis_update < 0 else bool(args.basis_update)
+    if basis_update:
+        extra["basis_update"] = 1
     m = mor.Mor(p, precision=prec, use_graph=int(use_graph), reduced_solver=red_solver, **tile, **extra)
     print(f"[bench] context created ({time.perf_counter() - t_create:.0f} s)", file=sys.stderr, flush=True)
     halo = tile.get("spmm_kind", 0) != 2
@@ -299,7 +307,8 @@ def main():
     stats = [mor.mor_get_stats(m.ctx, i) for i in range(n_sub)]
     _, red_iters, red_rel = mor.mor_get_solve_info(m.ctx)
     n_s, ms_s, _ = mor.mor_timing_get(m.ctx, "solve")
-    reduced_solve = {"solver": "diagonal-preconditioned CG, block-sparse" if red_solver else "dense FP64 Cholesky",
+    reduced_solve = {"solver": {0: "dense FP64 Cholesky", 1: "diagonal-preconditioned CG, block-sparse",
+                                2: "CG with block-inverse preconditioner, block-sparse"}[red_solver],
                      "iterations": red_iters, "rel_residual": red_rel,
                      "ms": round(ms_s / max(n_s, 1), 3)}
     bt_b = mor.mor_get_reduced_load(m.ctx)
@@ -353,6 +362,7 @@ def main():
                    "precision": "fp32_refine | bf16_split, p = 1/2 each" if stream_step else prec,
                    "reduced_dim": int(nred), "hip_graph": use_graph,
                    "cg_preconditioner": "block Jacobi + coarse correction" if args.coarse else "block Jacobi",
+                   "basis_update": basis_update,
                    "local_svd": f"randomized, {args.sketch} sketch columns" if sketches is not None else "explicit",
                    "tiles": tile or "library defaults"},
         "roofline": {"bound": "hbm",

@@ -123,16 +123,26 @@ typedef struct {
                               eigendecomposition of the stitched block Q^T A_ii Q, eigenvalues below
                               update_drop * lambda_max removed, basis rescaled so the block is the
                               identity (the basis then has dim <= k_eff + 1 columns) */
-  double update_drop;      /* relative drop tolerance of the basis update (0 = 1e-10) */
+  double update_drop;      /* relative eigenvalue drop of the basis update and of the block preconditioner
+                              (0 = automatic per subdomain, the accuracy of its basis: max(1e-10,
+                              refine_rtol) for MOR_FP64 and MOR_FP32_REFINE bases, 1e-6 for
+                              MOR_FP32 and MOR_BF16_SPLIT bases) */
   int32_t reduced_solver;  /* solver of the reduced system Q^T A Q x = Q^T b:
                               0 = dense FP64 Cholesky (mor_project stores the n x n matrix);
                               1 = FP64 conjugate gradients with the diagonal preconditioner, the
                                   paper's choice (end of Section 6 step 3, Section 7), on the
                                   block-sparse matrix (one dense row slab per subdomain over itself
-                                  and its neighbours; no n x n storage) */
-  double reduced_rtol;     /* reduced_solver 1: stop when ||b~ - A~ x|| <= reduced_rtol ||b~|| for the
-                              recurrence residual (0 = 1e-12) */
-  int32_t reduced_max_iter;/* reduced_solver 1: iteration cap (0 = 20000); MOR_ENOTCONV beyond it */
+                                  and its neighbours; no n x n storage);
+                              2 = the same with each subdomain block's inverse as preconditioner
+                                  (block Jacobi; blocks of at most 64 columns).  In exact arithmetic
+                                  this is the paper's diagonal-preconditioned CG after its basis
+                                  update (which makes the blocks the identity).  Where stitched
+                                  columns are nearly dependent, use basis_update = 1, which drops
+                                  those directions from the system, with reduced_solver 1 */
+  double reduced_rtol;     /* reduced_solver 1, 2: stop when ||b~ - A~ x|| <= reduced_rtol ||b~|| for the
+                              recurrence residual (1), or r'M^-1 r <= reduced_rtol^2 b~'M^-1 b~ (2)
+                              (0 = 1e-12) */
+  int32_t reduced_max_iter;/* reduced_solver 1, 2: iteration cap (0 = 20000); MOR_ENOTCONV beyond it */
   int32_t coarse;          /* 1 (default): two-level preconditioner for the block CG, the block Jacobi
                               plus an additive coarse correction, piecewise constant on runs of 8 row
                               aggregates, with the coarse matrix P^T A_II P inverted in FP64 (on the
@@ -240,9 +250,10 @@ int mor_get_local_block(mor_ctx* ctx, int32_t sd, double* Aii, double* bi, int64
 int mor_get_reduced(mor_ctx* ctx, double* At, double* bt, int64_t cap, int64_t* n);
 /* After mor_solve: the reduced coefficient vector x (n). */
 int mor_get_reduced_solution(mor_ctx* ctx, double* x, int64_t cap);
-/* After mor_solve: the solver used (0 Cholesky, 1 conjugate gradients), its iterations
- * (0 for Cholesky) and ||r|| / ||b~|| of the recurrence residual it stopped at (conjugate
- * gradients; 0 for Cholesky).  Any pointer may be NULL. */
+/* After mor_solve: the solver used (0 Cholesky, 1 and 2 conjugate gradients), its iterations
+ * (0 for Cholesky) and the stopping quantity it reached: ||r|| / ||b~|| of the recurrence
+ * residual (1), sqrt(r'M^-1 r / b~'M^-1 b~), the residual of the basis-updated system (2), or 0
+ * (Cholesky).  Any pointer may be NULL. */
 int mor_get_solve_info(mor_ctx* ctx, int32_t* solver, int32_t* iters, double* rel_residual);
 /* Per-solve statistics of the last local reduction of sd: CG iterations of the
  * A- and H1-systems, refinement passes, subspace iterations. */

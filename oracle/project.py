@@ -134,7 +134,7 @@ def pcg_diag(At: np.ndarray, bt: np.ndarray, rtol: float = 1e-12, max_iter: int 
     raise RuntimeError(f"reduced PCG did not reach {rtol} in {max_iter} iterations")
 
 
-def block_pinv(At: np.ndarray, off, drop: float = 1e-10) -> np.ndarray:
+def block_pinv(At: np.ndarray, off, drop: float = 0.0) -> np.ndarray:
     """The block-diagonal preconditioner of the reduced system: for each subdomain's diagonal
     block A~_ii = U Lambda U^T, the pseudo-inverse U_r Lambda_r^-1 U_r^T over the eigenvalues
     above drop * lambda_max (the directions the basis update of Section 6, step 2 keeps)."""
@@ -148,13 +148,17 @@ def block_pinv(At: np.ndarray, off, drop: float = 1e-10) -> np.ndarray:
     return M
 
 
-def pcg_block(At: np.ndarray, bt: np.ndarray, off, drop: float = 1e-10, rtol: float = 1e-12, max_iter: int = 20000,
+def pcg_block(At: np.ndarray, bt: np.ndarray, off, drop: float = 0.0, rtol: float = 1e-12, max_iter: int = 20000,
               on_iter=None):
     """Conjugate gradients on A~ x = b~ preconditioned by `block_pinv` (reading of Section 6:
     after the basis update the diagonal blocks are the identity and the paper's diagonal
     preconditioner leaves plain CG on the updated system, which is this iteration on the
-    un-updated one).  Same steps and stopping test as `pcg_diag`; the preconditioner may be
-    singular (dropped directions), so x stays in its range."""
+    un-updated one).  Same steps as `pcg_diag`.  The stopping test is the updated system's:
+    with M^-1 = T T^T its residual is T^T r, so stop when sqrt(r'M^-1 r / b'M^-1 b) <= rtol.
+    With drop > 0 the preconditioner is singular: the dropped part of r never shrinks and, once
+    the kept part is near rounding relative to it, the recurrence loses conjugacy (the basis
+    update, which removes those directions from the system, has no such part).  drop = 0 keeps
+    every positive eigenvalue.  Returns (x, iterations, that ratio)."""
     A = np.asarray(At, dtype=np.float64)
     b = np.asarray(bt, dtype=np.float64)
     Minv = block_pinv(A, off, drop)
@@ -166,6 +170,7 @@ def pcg_block(At: np.ndarray, bt: np.ndarray, off, drop: float = 1e-10, rtol: fl
     z = Minv @ r
     p = z.copy()
     rz = r @ z
+    rz0 = rz
     for k in range(1, max_iter + 1):
         q = A @ p
         pq = p @ q
@@ -176,11 +181,11 @@ def pcg_block(At: np.ndarray, bt: np.ndarray, off, drop: float = 1e-10, rtol: fl
         r = r - alpha * q
         if on_iter is not None:
             on_iter(k, x, r)
-        res = np.linalg.norm(r) / nb
-        if res <= rtol:
-            return x, k, res
         z = Minv @ r
         rz_new = r @ z
+        res = np.sqrt(max(rz_new, 0.0) / rz0)
+        if res <= rtol:
+            return x, k, res
         p = z + (rz_new / rz) * p
         rz = rz_new
     raise RuntimeError(f"reduced block PCG did not reach {rtol} in {max_iter} iterations")

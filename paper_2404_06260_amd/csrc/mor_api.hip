@@ -68,6 +68,7 @@ struct SubResult {
   std::vector<double> sigma;
   std::vector<double> Aii, bi;
   int dim = 0;             // basis columns: k_eff + 1, or fewer after the basis update
+  int prec = MOR_FP64;     // precision mode the basis was computed in
   double* d_V = nullptr;   // nV x dim
   double* d_Pm = nullptr;  // (k+1) x (k+2): [Q^T A Q | Q^T f]
   int cg_a = 0, cg_k = 0, refine = 0, eig = 0;
@@ -104,6 +105,10 @@ struct mor_ctx {
   int64_t* d_rs = nullptr;
   int2* d_rwc = nullptr;
   std::vector<int> h_ccol;
+  // block preconditioner (reduced_solver 2): pseudo-inverses of the subdomain blocks, per-row maps
+  double* d_bmv = nullptr;
+  int64_t* d_rbm = nullptr;
+  int2* d_rbd = nullptr;
   std::vector<int64_t> h_rs;
   std::vector<int2> h_rwc;
   int64_t slab_len = 0;
@@ -250,10 +255,10 @@ extern "C" int mor_create(const mor_mesh* mesh, const mor_coeff* coeff, const mo
     delete c;
     return fail(MOR_EINVAL, "unknown precision mode");
   }
-  if (c->opts.reduced_solver < 0 || c->opts.reduced_solver > 1 || c->opts.reduced_rtol < 0 ||
+  if (c->opts.reduced_solver < 0 || c->opts.reduced_solver > 2 || c->opts.reduced_rtol < 0 ||
       c->opts.reduced_max_iter < 0) {
     delete c;
-    return fail(MOR_EINVAL, "reduced_solver must be 0 or 1, reduced_rtol and reduced_max_iter >= 0");
+    return fail(MOR_EINVAL, "reduced_solver must be 0, 1 or 2, reduced_rtol and reduced_max_iter >= 0");
   }
   if (c->opts.reduced_rtol == 0) c->opts.reduced_rtol = 1e-12;
   if (c->opts.reduced_max_iter == 0) c->opts.reduced_max_iter = 20000;
@@ -1670,6 +1675,15 @@ static double** ptr_table(mor_ctx* c, Arena& ar, const std::vector<Slot*>& sl, F
 static int small_eig(mor_ctx* c, Arena& ar, const std::vector<Slot*>& sl, const std::vector<int>& s_of,
                      std::vector<std::vector<double>>& theta);
 
+// Relative eigenvalue drop of a subdomain block (basis update, block preconditioner): update_drop
+// if set, else the accuracy the basis was computed to, below which a block's directions are
+// noise: the solves' target refine_rtol (at least 1e-10) for FP64 and FP64-refined bases, 1e-6
+// where FP32 solves or the BF16 Gram set it.
+static double drop_of(const mor_ctx* c, int prec) {
+  if (c->opts.update_drop > 0) return c->opts.update_drop;
+  return (prec == MOR_FP32 || prec == MOR_BF16_SPLIT) ? 1e-6 : std::max(1e-10, c->opts.refine_rtol);
+}
+
 // The basis update of Section 6, step 2, which diagonalises the diagonal blocks of the reduced
 // system.  Reading (the paper defers the details to its source code): eigendecomposition
 // Q^T A_ii Q = U Lambda U^T of each stitched block, eigenvalues below update_drop * lambda_max
@@ -1684,7 +1698,6 @@ static int basis_update(mor_ctx* c, const std::vector<Slot*>& sl) {
                       32 * 256);
   if (!buf.p) return fail(MOR_ENOMEM, "device allocation failed (basis update)");
   Arena& ar = buf.ar;
-  const double drop = c->opts.update_drop > 0 ? c->opts.update_drop : 1e-10;
   std::vector<int> s_of(ns);
   for (int i = 0; i < ns; ++i) {
     Slot& q = *sl[i];
@@ -1702,6 +1715,7 @@ static int basis_update(mor_ctx* c, const std::vector<Slot*>& sl) {
     const HostSub& h = *q.h;
     SubResult& R = c->res[q.sd];
     r[i] = 0;
+    const double drop = drop_of(c, q.prec);
     for (int j = 0; j < R.dim; ++j) r[i] += (th[i][j] > drop * th[i][0]) ? 1 : 0;
     r[i] = std::max(r[i], 1);
     launch_whiten(q.Ss, q.theta, R.dim, r[i], q.Bk, st);   // U_r Lambda_r^-1/2 (dim x 64)
@@ -1779,6 +1793,7 @@ static int project_local(mor_ctx* c, Arena& ar, const std::vector<Slot*>& sl, co
     R.cg_k = done[i]->sys[1].iters;
     R.refine = std::max(done[i]->sys[0].refines, done[i]->sys[1].refines);
     R.eig = eig_iters;
+    R.prec = q.prec;
     R.reduced = done[i]->status == 0;
   }
   if (c->opts.basis_update) return basis_update(c, sl);
@@ -2268,6 +2283,79 @@ extern "C" int mor_engine_stats(mor_ctx* c, int32_t* live, int32_t* pending, int
 }
 
 // ------------------------------------------------------------------------------- projection
+// The block preconditioner of the reduced CG (reduced_solver 2): the inverse of each subdomain's
+// diagonal block Q_i^T A_ii Q_i from its eigendecomposition.  With the updated bases of Section 6
+// step 2 the blocks are the identity and this CG is the paper's diagonal-preconditioned CG; on
+// the un-updated system it is the same iteration in exact arithmetic, as long as nothing is dropped.
+static int block_preconditioner(mor_ctx* c) {
+  hipStream_t st = c->st;
+  const int n = (int)c->subs.size();
+  std::vector<int64_t> bo(n + 1, 0);
+  std::vector<int> s_of(n);
+  for (int i = 0; i < n; ++i) {
+    s_of[i] = c->res[i].dim;
+    if (s_of[i] > 64) return fail(MOR_EINVAL, "block preconditioner: a subdomain block has more than 64 columns");
+    bo[i + 1] = bo[i] + (int64_t)s_of[i] * s_of[i];
+  }
+  c->d_bmv = (double*)palloc(c, 8 * (size_t)std::max<int64_t>(1, bo[n]));
+  std::vector<int64_t> rbm(c->n_red);
+  std::vector<int2> rbd(c->n_red);
+  for (int i = 0; i < n; ++i)
+    for (int a = 0; a < s_of[i]; ++a) {
+      rbm[c->off[i] + a] = bo[i] + (int64_t)a * s_of[i];
+      rbd[c->off[i] + a] = make_int2(c->off[i], s_of[i]);
+    }
+  if (!c->d_bmv || upload(c, &c->d_rbm, rbm.data(), rbm.size()) || upload(c, &c->d_rbd, rbd.data(), rbd.size()))
+    return fail(MOR_ENOMEM, "device allocation failed (block preconditioner)");
+  const int64_t nth = c->off[n];
+  const size_t bytes = 16 * (size_t)std::max<int64_t>(1, bo[n]) + 8 * (size_t)std::max<int64_t>(1, nth) +
+                       4 * sizeof(double*) * n + 12 * (size_t)n + 8 * 256;
+  char* buf = (char*)dalloc(c, bytes);
+  if (!buf) return fail(MOR_ENOMEM, "device allocation failed (block preconditioner)");
+  struct G { mor_ctx* c; void* p; ~G() { (void)hipStreamSynchronize(c->st); dfree(c, p); } } guard{c, buf};
+  Arena ar{buf, bytes, 0};
+  double* H = (double*)ar.take(8 * (size_t)std::max<int64_t>(1, bo[n]));
+  double* S = (double*)ar.take(8 * (size_t)std::max<int64_t>(1, bo[n]));
+  double* th = (double*)ar.take(8 * (size_t)std::max<int64_t>(1, nth));
+  double** PH = (double**)ar.take(sizeof(double*) * n);
+  double** PS = (double**)ar.take(sizeof(double*) * n);
+  double** PT = (double**)ar.take(sizeof(double*) * n);
+  double** PO = (double**)ar.take(sizeof(double*) * n);
+  int* ds = (int*)ar.take(4 * (size_t)n);
+  double* dd = (double*)ar.take(8 * (size_t)n);
+  if (!dd) return fail(MOR_ENOMEM, "arena exhausted (block preconditioner)");
+  // every positive eigenvalue is kept (an exact block inverse for SPD blocks): with directions
+  // dropped, the full-space recurrence keeps their residual part and loses conjugacy at tight
+  // tolerances; dropping belongs to the basis update, which removes them from the system
+  std::vector<double> drops(n, 0.0);
+  HIPCHK(hipMemcpyAsync(dd, drops.data(), 8 * (size_t)n, hipMemcpyHostToDevice, st));
+  std::vector<double> hH((size_t)std::max<int64_t>(1, bo[n]));
+  std::vector<double*> ph(n), ps(n), pt(n), po(n);
+  for (int i = 0; i < n; ++i) {
+    std::copy(c->res[i].Aii.begin(), c->res[i].Aii.end(), hH.begin() + bo[i]);
+    ph[i] = H + bo[i];
+    ps[i] = S + bo[i];
+    pt[i] = th + c->off[i];
+    po[i] = c->d_bmv + bo[i];
+  }
+  HIPCHK(hipMemcpyAsync(H, hH.data(), 8 * hH.size(), hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(PH, ph.data(), sizeof(double*) * n, hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(PS, ps.data(), sizeof(double*) * n, hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(PT, pt.data(), sizeof(double*) * n, hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(PO, po.data(), sizeof(double*) * n, hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(ds, s_of.data(), 4 * (size_t)n, hipMemcpyHostToDevice, st));
+  launch_jacobi(PH, PS, PT, ds, n, 64, st);
+  launch_block_pinv(PS, PT, ds, n, dd, PO, st);
+  HIPCHK(hipGetLastError());
+  std::vector<double> hth((size_t)std::max<int64_t>(1, nth));
+  HIPCHK(hipMemcpyAsync(hth.data(), th, 8 * hth.size(), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  for (int i = 0; i < n; ++i)
+    if (s_of[i] > 0 && !(hth[c->off[i]] > 0.0))
+      return fail(MOR_EDEVICE, "subdomain " + std::to_string(i) + ": reduced diagonal block is not positive definite");
+  return MOR_OK;
+}
+
 extern "C" int mor_project(mor_ctx* c) {
   if (!c) return fail(MOR_EINVAL, "null context");
   if (c->opts.host_only) return fail(MOR_ESTATE, "context was created host_only");
@@ -2275,7 +2363,7 @@ extern "C" int mor_project(mor_ctx* c) {
   for (int i = 0; i < n; ++i)
     if (!c->res[i].reduced) return fail(MOR_ESTATE, "subdomain " + std::to_string(i) + " has no basis yet");
   hipStream_t st = c->st;
-  const bool sparse = c->opts.reduced_solver == 1;
+  const bool sparse = c->opts.reduced_solver >= 1;
   c->projected = c->solved = 0;
   c->off.assign(n + 1, 0);
   for (int i = 0; i < n; ++i) c->off[i + 1] = c->off[i] + c->res[i].dim;
@@ -2283,8 +2371,12 @@ extern "C" int mor_project(mor_ctx* c) {
   c->MPr = rup(c->n_red, 64);
   const int npairs = (int)c->om0.pair_i.size();
   for (void* p : {(void*)c->d_At, (void*)c->d_bt, (void*)c->d_x, (void*)c->d_slab, (void*)c->d_ccol,
-                  (void*)c->d_rdiag, (void*)c->d_rs, (void*)c->d_rwc})
+                  (void*)c->d_rdiag, (void*)c->d_rs, (void*)c->d_rwc, (void*)c->d_bmv, (void*)c->d_rbm,
+                  (void*)c->d_rbd})
     pfree(c, p);
+  c->d_bmv = nullptr;
+  c->d_rbm = nullptr;
+  c->d_rbd = nullptr;
   c->d_At = c->d_bt = c->d_x = c->d_slab = nullptr;
   c->d_ccol = c->d_rdiag = nullptr;
   c->d_rs = nullptr;
@@ -2341,6 +2433,8 @@ extern "C" int mor_project(mor_ctx* c) {
         upload(c, &c->d_rwc, c->h_rwc.data(), c->h_rwc.size()) || upload(c, &c->d_rdiag, rdiag.data(), rdiag.size()))
       return fail(MOR_ENOMEM, "device allocation failed (reduced pattern)");
     HIPCHK(hipStreamSynchronize(st));   // rdiag is read by the copy
+    if (c->opts.reduced_solver == 2)
+      if (int rc = block_preconditioner(c)) return rc;
   } else {
     c->d_At = (double*)palloc(c, 8 * (size_t)c->MPr * c->MPr);
     if (!c->d_At) return fail(MOR_ENOMEM, "device allocation failed (reduced system)");
@@ -2474,6 +2568,10 @@ static int solve_pcg(mor_ctx* c, double* u_out, int64_t* n_reduced_out) {
     d.rdiag = c->d_rdiag;
     d.b = c->d_bt;
     d.bstride = 64;
+    d.block = c->opts.reduced_solver == 2;
+    d.bmv = c->d_bmv;
+    d.rbm = c->d_rbm;
+    d.rbd = c->d_rbd;
     double* v[6];
     for (auto& p : v) p = (double*)ar.take(8 * (size_t)rup(n, 64));
     d.x = v[0]; d.r = v[1]; d.z = v[2]; d.p = v[3]; d.q = v[4]; d.dinv = v[5];
@@ -2500,11 +2598,14 @@ static int solve_pcg(mor_ctx* c, double* u_out, int64_t* n_reduced_out) {
     if (hs[2] == 1)
       return fail(MOR_EDEVICE, "reduced matrix is not positive definite (p'Ap <= 0 at iteration " +
                                    std::to_string(hs[1] + 1) + ")");
-    double sc[10];
+    double sc[11];
     HIPCHK(hipMemcpy(sc, d.sc, sizeof(sc), hipMemcpyDeviceToHost));
     c->solve_iters = hs[1];
     const int last = hs[1] > 0 ? (hs[1] - 1) % 3 : 2;
-    c->solve_relres = sc[9] > 0 ? std::sqrt(std::max(0.0, sc[6 + last]) / sc[9]) : 0.0;
+    if (d.block)
+      c->solve_relres = sc[10] > 0 ? std::sqrt(std::max(0.0, sc[3 + last]) / sc[10]) : 0.0;
+    else
+      c->solve_relres = sc[9] > 0 ? std::sqrt(std::max(0.0, sc[6 + last]) / sc[9]) : 0.0;
     if (!hs[0])
       return fail(MOR_ENOTCONV, "reduced conjugate gradients: ||r||/||b|| = " + std::to_string(c->solve_relres) +
                                     " after " + std::to_string(hs[1]) + " iterations");
@@ -2521,7 +2622,7 @@ extern "C" int mor_solve(mor_ctx* c, double* u_out, int64_t* n_reduced_out) {
   if (c->opts.host_only) return fail(MOR_ESTATE, "context was created host_only");
   if (!c->projected) return fail(MOR_ESTATE, "mor_project must run first");
   c->solved = 0;
-  if (c->opts.reduced_solver == 1) return solve_pcg(c, u_out, n_reduced_out);
+  if (c->opts.reduced_solver >= 1) return solve_pcg(c, u_out, n_reduced_out);
   c->solve_iters = 0;
   c->solve_relres = 0.0;
   hipStream_t st = c->st;

@@ -220,11 +220,21 @@ struct RpcgDev {
   const int* rdiag;
   const double* b; int bstride;   // load b~ (entry r at b[r * bstride])
   double *x, *r, *z, *p, *q, *dinv;
-  double* sc;    // pq[3], rz[3], rr[3], rr0: ring of three per-iteration slots
+  double* sc;    // pq[3], rz[3], rr[3], rr0, rz0 (block preconditioner): ring of three per-iteration slots
   int* state;    // [0] stop flag, [1] iterations done, [2] failure (1 p'Ap <= 0, 2 diagonal <= 0)
+  // block preconditioner (block = 1): row r's row of its subdomain block's pseudo-inverse starts at
+  // bmv[rbm[r]]; rbd[r] = (first reduced row, size) of that block.  block = 0: the diagonal.
+  const double* bmv;
+  const int64_t* rbm;
+  const int2* rbd;
+  int block;
 };
 void launch_rpcg_setup(const RpcgDev& d, int n, hipStream_t s);
 void launch_rpcg_iteration(const RpcgDev& d, int n, int it, double tol2, hipStream_t s);
+// pseudo-inverse of each symmetric block from its eigendecomposition (vectors S: s x s row-major,
+// values th descending): out = sum over th_j > drops[b] * th_0 of u_j u_j^T / th_j (s x s row-major)
+void launch_block_pinv(double* const* S, double* const* th, const int* s_of, int n, const double* drops,
+                       double* const* out, hipStream_t s);
 void launch_reconstruct(const double* V, int nP, int k1, const double* x, const int* nodes, double* u,
                         hipStream_t s);
 

@@ -1945,9 +1945,11 @@ __global__ __launch_bounds__(256) void k_rpcg_init(const RpcgDev d, int n) {
     d.dinv[i] = di;
     d.x[i] = 0.0;
     d.r[i] = bi;
-    d.z[i] = di * bi;
-    d.p[i] = di * bi;
-    rz += bi * di * bi;
+    if (!d.block) {   // the block preconditioner's z, p and r'z come from k_rpcg_prec
+      d.z[i] = di * bi;
+      d.p[i] = di * bi;
+      rz += bi * di * bi;
+    }
     rr += bi * bi;
   }
   block_add(rz, d.sc + 3 + 2, red[0]);
@@ -2000,10 +2002,12 @@ __global__ __launch_bounds__(256) void k_rpcg_update(const RpcgDev d, int n, int
   for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
     d.x[i] += al * d.p[i];
     const double ri = d.r[i] - al * d.q[i];
-    const double zi = d.dinv[i] * ri;
     d.r[i] = ri;
-    d.z[i] = zi;
-    rz += ri * zi;
+    if (!d.block) {   // block preconditioner: z and r'z in k_rpcg_prec
+      const double zi = d.dinv[i] * ri;
+      d.z[i] = zi;
+      rz += ri * zi;
+    }
     rr += ri * ri;
   }
   block_add(rz, d.sc + 3 + c, red[0]);
@@ -2014,7 +2018,10 @@ __global__ __launch_bounds__(256) void k_rpcg_direction(const RpcgDev d, int n, 
   if (rpcg_stopped(d)) return;
   const int c = it % 3, pv = (it + 2) % 3;
   const bool first = blockIdx.x == 0 && threadIdx.x == 0;
-  if (d.sc[6 + c] <= tol2 * d.sc[9]) {   // converged: x is final
+  // converged: x is final.  Diagonal preconditioner: ||r|| <= rtol ||b||; block preconditioner:
+  // the updated system's residual, r'M^-1 r <= rtol^2 b'M^-1 b
+  const bool done = d.block ? d.sc[3 + c] <= tol2 * d.sc[10] : d.sc[6 + c] <= tol2 * d.sc[9];
+  if (done) {
     if (first) {
       d.state[1] = it + 1;
       __atomic_store_n(d.state, 1, __ATOMIC_RELAXED);
@@ -2026,16 +2033,60 @@ __global__ __launch_bounds__(256) void k_rpcg_direction(const RpcgDev d, int n, 
   if (first) d.state[1] = it + 1;
 }
 
+// z = M^-1 r with the block pseudo-inverses (each row: its block row times r over the block),
+// r'z into sc[slot]; at the start also p = z
+__global__ __launch_bounds__(256) void k_rpcg_prec(const RpcgDev d, int n, int slot, int set_p) {
+  __shared__ double red[2][4];
+  if (rpcg_stopped(d)) return;
+  double part = 0.0;
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
+    const int2 bd = d.rbd[i];
+    const double* m = d.bmv + d.rbm[i];
+    const double* rb = d.r + bd.x;
+    double z = 0.0;
+    for (int b = 0; b < bd.y; ++b) z += m[b] * rb[b];
+    d.z[i] = z;
+    if (set_p) d.p[i] = z;
+    part += d.r[i] * z;
+  }
+  block_add(part, d.sc + slot, red[0]);
+  if (set_p) block_add(part, d.sc + 10, red[1]);   // b'M^-1 b: the reference of the stopping test
+}
+
+// pseudo-inverse of each block from its eigendecomposition, one workgroup per block
+__global__ __launch_bounds__(256) void k_block_pinv(double* const* Ss, double* const* Ths, const int* s_of,
+                                                    const double* drops, double* const* Outs) {
+  const int blk = blockIdx.x;
+  const int s = s_of[blk];
+  const double* S = Ss[blk];
+  const double* th = Ths[blk];
+  double* out = Outs[blk];
+  const double thr = drops[blk] * th[0];
+  for (int idx = threadIdx.x; idx < s * s; idx += 256) {
+    const int a = idx / s, b = idx % s;
+    double acc = 0.0;
+    for (int j = 0; j < s; ++j)
+      if (th[j] > thr && th[j] > 0.0) acc += S[a * s + j] * S[b * s + j] / th[j];
+    out[idx] = acc;
+  }
+}
+void launch_block_pinv(double* const* S, double* const* th, const int* s_of, int n, const double* drops,
+                       double* const* out, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(k_block_pinv, dim3(n), dim3(256), 0, s, S, th, s_of, drops, out);
+}
+
 static int rpcg_grid(int n) { return std::max(1, std::min((n + 255) / 256, 1024)); }
 
 void launch_rpcg_setup(const RpcgDev& d, int n, hipStream_t s) {
-  hipLaunchKernelGGL(k_fill, dim3(1), dim3(256), 0, s, d.sc, (int64_t)10, 0.0);
+  hipLaunchKernelGGL(k_fill, dim3(1), dim3(256), 0, s, d.sc, (int64_t)16, 0.0);
   hipLaunchKernelGGL(k_fill_i, dim3(1), dim3(256), 0, s, d.state, (int64_t)4, 0);
   hipLaunchKernelGGL(k_rpcg_init, dim3(rpcg_grid(n)), dim3(256), 0, s, d, n);
+  if (d.block) hipLaunchKernelGGL(k_rpcg_prec, dim3(rpcg_grid(n)), dim3(256), 0, s, d, n, 3 + 2, 1);
 }
 void launch_rpcg_iteration(const RpcgDev& d, int n, int it, double tol2, hipStream_t s) {
   hipLaunchKernelGGL(k_rpcg_matvec, dim3((n + 3) / 4), dim3(256), 0, s, d, n, it);
   hipLaunchKernelGGL(k_rpcg_update, dim3(rpcg_grid(n)), dim3(256), 0, s, d, n, it);
+  if (d.block) hipLaunchKernelGGL(k_rpcg_prec, dim3(rpcg_grid(n)), dim3(256), 0, s, d, n, 3 + it % 3, 0);
   hipLaunchKernelGGL(k_rpcg_direction, dim3(rpcg_grid(n)), dim3(256), 0, s, d, n, it, tol2);
 }
 

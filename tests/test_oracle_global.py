@@ -236,18 +236,37 @@ def test_block_pcg_solves_a_block_diagonal_system_in_one_step():
 
 
 def test_block_pcg_equals_plain_cg_after_the_basis_update():
-    """Block-pseudo-inverse PCG on Q^T A Q and plain CG on the reduced system of the updated bases
+    """Block-inverse PCG on Q^T A Q and plain CG on the reduced system of the updated bases
     (diagonal blocks = I, so the diagonal preconditioner is the identity) are one iteration in
     exact arithmetic: same iteration count (to one) and the same energy x^T b~."""
+    drop = 1e-10
     p = w.make_problem(10, (2, 2, 2), r=2, rank=6, kappa="lognormal", seed=12)
     res = reduce.reduce_all(p, workers=1)
     At, bt, off = project.reduced_system(p.mesh, p.kappa, p.subdomains, res)
-    upd = [reduce.basis_update(r, drop=1e-10) for r in res]
+    upd = [reduce.basis_update(r, drop=drop) for r in res]
     Au, bu, _ = project.reduced_system(p.mesh, p.kappa, p.subdomains, upd)
     np.testing.assert_allclose(np.diag(Au), 1.0, rtol=1e-9)
-    xb, itb, _ = project.pcg_block(At, bt, off, drop=1e-10, rtol=1e-12)
+    xb, itb, _ = project.pcg_block(At, bt, off, drop=drop, rtol=1e-12)
     xu, itu, _ = project.pcg_diag(Au, bu, rtol=1e-12)
     assert abs(itb - itu) <= 1, (itb, itu)
     np.testing.assert_allclose(xb @ bt, xu @ bu, rtol=1e-10)
     xc = project.solve_reduced(At, bt)
     np.testing.assert_allclose(xb, xc, rtol=0, atol=1e-9 * np.abs(xc).max())
+
+
+def test_block_pcg_with_dropped_directions_tracks_the_update_then_loses_conjugacy():
+    """With directions dropped (singular block pseudo-inverse) the full-space iteration follows
+    plain CG on the updated system step by step while the kept residual is well above rounding
+    relative to the dropped part, and then loses conjugacy: why the library's block preconditioner
+    keeps every positive eigenvalue and dropping is left to the basis update."""
+    p = w.make_problem(10, (2, 2, 2), r=2, rank=6, kappa="lognormal", seed=12)
+    res = reduce.reduce_all(p, workers=1)
+    At, bt, off = project.reduced_system(p.mesh, p.kappa, p.subdomains, res)
+    upd = [reduce.basis_update(r, drop=1e-3) for r in res]
+    Au, bu, _ = project.reduced_system(p.mesh, p.kappa, p.subdomains, upd)
+    assert Au.shape[0] < At.shape[0]                 # directions were dropped
+    hb, hu = [], []
+    project.pcg_block(At, bt, off, drop=1e-3, rtol=1e-9, on_iter=lambda k, x, r: hb.append(x @ bt))
+    project.pcg_diag(Au, bu, rtol=1e-9, on_iter=lambda k, x, r: hu.append(x @ bu))
+    m = min(len(hb), len(hu))
+    np.testing.assert_allclose(hb[:m], hu[:m], rtol=1e-9)
