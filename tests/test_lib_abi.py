@@ -97,3 +97,29 @@ def test_invalid_inputs_are_rejected():
     with pytest.raises(mor.MorError):
         mor.mor_create(p3.mesh.xyz, p3.mesh.tets, p3.mesh.dirichlet, p3.kappa, None, p3.subdomains.ext_tet_ptr,
                        p3.subdomains.ext_tets, p3.subdomains.in_core, o)
+
+
+def test_default_options_and_option_checks():
+    """mor_default_opts fills the defaults include/mor.h documents, the binding's struct has the
+    header's size (a field added on one side only would shift every later field), and
+    mor_create rejects out-of-range reduced-solver options before touching a device."""
+    from paper_2404_06260_amd import mor
+    o = mor.mor_default_opts()
+    assert o.precision == mor.PRECISIONS["fp32_refine"]
+    assert (o.cg_rtol, o.refine_rtol, o.max_iter, o.refine_steps) == (1e-5, 1e-8, 4000, 3)
+    assert (o.reduced_solver, o.reduced_rtol, o.reduced_max_iter) == (0, 1e-12, 20000)
+    assert o.coarse == 1 and o.basis_update == 0 and o.update_drop == 0.0
+    h = open(os.path.join(ROOT, "include", "mor.h")).read()
+    body = h[h.index("typedef struct {\n  int32_t precision;"):h.index("} mor_opts;")]
+    fields = re.findall(r"^\s*(?:int32_t|double|size_t|mor_alloc_fn|mor_free_fn|void\*)\s+(\w+);", body, re.M)
+    assert fields == [f[0] for f in mor.MorOpts._fields_]
+    p = w.make_config("C1")
+    m, sd = p.mesh, p.subdomains
+    for bad in (dict(reduced_solver=3), dict(reduced_solver=-1), dict(reduced_rtol=-1.0), dict(reduced_max_iter=-2)):
+        o = mor.mor_default_opts()
+        o.host_only = 1
+        for k, v in bad.items():
+            setattr(o, k, v)
+        with pytest.raises(mor.MorError) as e:
+            mor.mor_create(m.xyz, m.tets, m.dirichlet, p.kappa, None, sd.ext_tet_ptr, sd.ext_tets, sd.in_core, o)
+        assert e.value.code == mor.MOR_EINVAL, bad
