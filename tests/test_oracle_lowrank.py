@@ -212,3 +212,20 @@ def test_full_width_gaussian_sketch_is_exact_and_narrow_sketches_interlace():
         if prev is not None:
             assert np.all(sk.sigma[:prev.size] >= prev * (1 - 1e-10))
         prev = sk.sigma
+
+
+@pytest.mark.parametrize("kappa", ["one", "lognormal"])
+def test_rank_of_the_lifting_equals_the_boundary_dofs_of_omega_i(kappa):
+    """The spectrum of the weighted lifting operator reaches rounding at the number of interface
+    degrees of freedom of omega_i: a discrete harmonic function on omega_i is fixed by its
+    values on the free nodes of the boundary of omega_i (V_i minus P_i), so rank Z <= |V_i \\ P_i|,
+    and the traces of the liftings reach every such value, so the bound is attained.  The
+    gap is clean: the same count above 1e-10 and above 1e-13 of sigma_1."""
+    p = w.make_problem(10, (2, 2, 2), r=2, kappa=kappa, seed=5)
+    for i in (0, 7):
+        s = decomp.local_sets(p.mesh, p.subdomains, i)
+        r = reduce.reduce_local(p.mesh, p.kappa, p.f_nodal, s, 10 ** 6)
+        sg = r.sigma / r.sigma[0]
+        nb = s.V.size - s.P.size
+        assert s.B.size > nb
+        assert (sg > 1e-10).sum() == (sg > 1e-13).sum() == nb, (i, nb)
