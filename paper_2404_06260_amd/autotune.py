@@ -18,7 +18,9 @@ CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "autotune_cache
 # (kind, spmm_vec, spmm_rows): kind 1 / 3 = LDS halo tiles with 256- / 128-byte column slices
 # (slices per workgroup, halo cap), kind 2 = row tiles (width in 64 columns, rows)
 CANDIDATES = [(3, 16, 96), (3, 16, 64), (3, 32, 96), (3, 16, 128), (3, 8, 96), (1, 16, 64), (1, 8, 64), (2, 4, 8)]
-STREAM_CANDIDATES = [(2, 4), (2, 8), (2, 16), (1, 8), (4, 4), (4, 8)]
+# (stream_vec, stream_blocks); the block counts divide the 8-aggregate coarse blocks of the
+# two-level preconditioner (a tile never straddles two blocks), so none is overridden
+STREAM_CANDIDATES = [(2, 4), (2, 8), (1, 4), (1, 8), (4, 4), (4, 8)]
 
 
 def _key(problem, precision):
