@@ -14,7 +14,10 @@
  *
  * Conventions for every entry point
  *   - Return 0 on success or a negative MOR_E* code; mor_last_error() then holds
- *     a message (per thread).  No C++ exception crosses this boundary.
+ *     a message (per thread).  No C++ exception crosses this boundary: every
+ *     entry point catches what it throws; a failed host allocation returns
+ *     MOR_ENOMEM, anything else MOR_EDEVICE.  After such a failure inside the
+ *     serving engine the context should only be destroyed.
  *   - Pointers documented "host" are caller-owned, read (or written) only during
  *     the call; the library copies what it keeps.  Device memory is owned by the
  *     context and released by mor_destroy.
@@ -35,8 +38,9 @@ extern "C" {
 
 #define MOR_OK 0
 #define MOR_EINVAL (-1)   /* bad argument, invalid mesh (det J <= 0), not a partition, bad rank/tol */
-#define MOR_ENOMEM (-2)   /* device allocation failed or a subdomain exceeds the HBM budget */
-#define MOR_ENOTCONV (-3) /* block CG or the eigensolver did not converge within its limits */
+#define MOR_ENOMEM (-2)   /* device or host allocation failed, or a subdomain exceeds the HBM budget */
+#define MOR_ENOTCONV (-3) /* block CG, its FP64 refinement or the eigensolver did not converge within
+                             its limits */
 #define MOR_ESTATE (-4)   /* call order: e.g. mor_project before every subdomain has a basis */
 #define MOR_EDEVICE (-5)  /* HIP runtime error or a failed device-side check (non-SPD pivot) */
 
@@ -95,7 +99,9 @@ typedef struct {
                               singular values (up to 1.2e-7 relative instead of below 1e-7) */
   double refine_rtol;      /* FP32_REFINE: stop refinement when the FP64 residual reaches this */
   int32_t max_iter;        /* CG iteration cap per solve (MOR_ENOTCONV beyond it) */
-  int32_t refine_steps;    /* FP32_REFINE: maximum number of FP64 residual corrections */
+  int32_t refine_steps;    /* FP32_REFINE, BF16_SPLIT: maximum number of FP64 residual corrections; a
+                              system whose FP64 residual is still above refine_rtol after the last one
+                              fails its request with MOR_ENOTCONV */
   int32_t oversample;      /* extra subspace vectors of the top-k eigensolve (0 = automatic) */
   double eig_rtol;         /* Ritz residual tolerance relative to the largest eigenvalue */
   int32_t eig_max_iter;    /* subspace iteration cap */
@@ -116,17 +122,22 @@ typedef struct {
   mor_alloc_fn dev_alloc;  /* NULL: hipMalloc */
   mor_free_fn dev_free;    /* NULL: hipFree */
   void* alloc_user;
-  void* hip_stream;        /* hipStream_t all work is ordered on; NULL = null stream */
+  void* hip_stream;        /* hipStream_t all work is ordered on; NULL = null stream.  It must come from
+                              the HIP runtime this library is linked against (a handle made by another
+                              runtime instance in the same process, such as one bundled with a Python
+                              framework, is not valid here); the library synchronizes this stream
+                              before it returns results to the host or releases memory */
   int32_t host_only;       /* 1: derive the decomposition on the host only (no device memory);
                               only mor_get_sizes / mor_get_nodes / mor_get_pairs may follow */
   int32_t basis_update;    /* 1: the basis update of Section 6 step 2 after each local reduction:
                               eigendecomposition of the stitched block Q^T A_ii Q, eigenvalues below
                               update_drop * lambda_max removed, basis rescaled so the block is the
                               identity (the basis then has dim <= k_eff + 1 columns) */
-  double update_drop;      /* relative eigenvalue drop of the basis update and of the block preconditioner
+  double update_drop;      /* relative eigenvalue drop of the basis update (basis_update = 1) only
                               (0 = automatic per subdomain, the accuracy of its basis: max(1e-10,
                               refine_rtol) for MOR_FP64 and MOR_FP32_REFINE bases, 1e-6 for
-                              MOR_FP32 and MOR_BF16_SPLIT bases) */
+                              MOR_FP32 and MOR_BF16_SPLIT bases).  The block preconditioner of
+                              reduced_solver 2 keeps every positive eigenvalue of each block */
   int32_t reduced_solver;  /* solver of the reduced system Q^T A Q x = Q^T b:
                               0 = dense FP64 Cholesky (mor_project stores the n x n matrix);
                               1 = FP64 conjugate gradients with the diagonal preconditioner, the
@@ -256,7 +267,8 @@ int mor_get_reduced_solution(mor_ctx* ctx, double* x, int64_t cap);
  * (Cholesky).  Any pointer may be NULL. */
 int mor_get_solve_info(mor_ctx* ctx, int32_t* solver, int32_t* iters, double* rel_residual);
 /* Per-solve statistics of the last local reduction of sd: CG iterations of the
- * A- and H1-systems, refinement passes, subspace iterations. */
+ * A- and H1-systems, FP64 refinement restarts (the larger of the two systems), subspace
+ * iterations. */
 int mor_get_stats(mor_ctx* ctx, int32_t sd, int32_t* cg_iter_a, int32_t* cg_iter_k, int32_t* refine,
                   int32_t* eig_iter);
 

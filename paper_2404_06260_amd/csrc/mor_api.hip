@@ -18,7 +18,10 @@
 #include <cstring>
 #include <map>
 #include <memory>
+#include <new>
+#include <stdexcept>
 #include <string>
+#include <system_error>
 #include <thread>
 #include <vector>
 
@@ -30,10 +33,47 @@ using namespace mor;
 
 static thread_local std::string g_err;
 
-static int fail(int code, const std::string& msg) {
-  g_err = msg;
+// Error reporting never throws: the message is dropped if it cannot be stored.
+static int fail(int code, const std::string& msg) noexcept {
+  try {
+    g_err = msg;
+  } catch (...) {
+    g_err.clear();
+  }
   return code;
 }
+static int fail(int code, const char* msg) noexcept {
+  try {
+    g_err.assign(msg);
+  } catch (...) {
+    g_err.clear();
+  }
+  return code;
+}
+
+// The C-ABI boundary: an exception thrown inside an entry point (a host allocation failure from
+// a container, or any other) becomes an error code with a message and never crosses into C.
+static int exception_code() noexcept {
+  try {
+    throw;
+  } catch (const std::bad_alloc&) {
+    return fail(MOR_ENOMEM, "host memory allocation failed");
+  } catch (const std::exception& e) {
+    int rc = MOR_EDEVICE;
+    try {
+      g_err = std::string("internal error: ") + e.what();
+    } catch (...) {
+      rc = fail(MOR_EDEVICE, "internal error");
+    }
+    return rc;
+  } catch (...) {
+    return fail(MOR_EDEVICE, "internal error (unknown exception)");
+  }
+}
+#define MOR_TRY try {
+#define MOR_CATCH \
+  }               \
+  catch (...) { return exception_code(); }
 
 #define HIPCHK(expr)                                                                                     \
   do {                                                                                                   \
@@ -239,8 +279,10 @@ extern "C" void mor_default_opts(mor_opts* o) {
   o->coarse = 1;
 }
 
-extern "C" int mor_create(const mor_mesh* mesh, const mor_coeff* coeff, const mor_subdomains* sub,
-                          const mor_opts* opts, mor_ctx** out) {
+// mor_create's body; `c` is the caller's handle of the context under construction, so that an
+// exception can release it (every normal return has released it or handed it out already).
+static int create_impl(const mor_mesh* mesh, const mor_coeff* coeff, const mor_subdomains* sub,
+                       const mor_opts* opts, mor_ctx** out, mor_ctx*& c) {
   if (!mesh || !coeff || !sub || !out) return fail(MOR_EINVAL, "null argument");
   if (mesh->n_nodes <= 0 || mesh->n_tets <= 0 || !mesh->xyz || !mesh->tets || !mesh->dirichlet)
     return fail(MOR_EINVAL, "empty or incomplete mesh");
@@ -248,16 +290,18 @@ extern "C" int mor_create(const mor_mesh* mesh, const mor_coeff* coeff, const mo
   if (sub->n_sub <= 0 || !sub->ext_tet_ptr || !sub->ext_tets || !sub->in_core)
     return fail(MOR_EINVAL, "empty decomposition");
   if (mesh->n_nodes > INT32_MAX || mesh->n_tets > INT32_MAX) return fail(MOR_EINVAL, "mesh too large for int32 ids");
-  mor_ctx* c = new mor_ctx();
+  c = new mor_ctx();
   if (opts) c->opts = *opts;
   else mor_default_opts(&c->opts);
   if (c->opts.precision < MOR_FP64 || c->opts.precision > MOR_BF16_SPLIT) {
     delete c;
+    c = nullptr;
     return fail(MOR_EINVAL, "unknown precision mode");
   }
   if (c->opts.reduced_solver < 0 || c->opts.reduced_solver > 2 || c->opts.reduced_rtol < 0 ||
       c->opts.reduced_max_iter < 0) {
     delete c;
+    c = nullptr;
     return fail(MOR_EINVAL, "reduced_solver must be 0, 1 or 2, reduced_rtol and reduced_max_iter >= 0");
   }
   if (c->opts.reduced_rtol == 0) c->opts.reduced_rtol = 1e-12;
@@ -272,6 +316,7 @@ extern "C" int mor_create(const mor_mesh* mesh, const mor_coeff* coeff, const mo
   for (int64_t t = 0; t < m.n_tets; ++t)
     if (!(coeff->kappa[t] > 0.0)) {
       delete c;
+      c = nullptr;
       return fail(MOR_EINVAL, "kappa must be positive");
     }
   c->kappa.assign(coeff->kappa, coeff->kappa + m.n_tets);
@@ -280,17 +325,20 @@ extern "C" int mor_create(const mor_mesh* mesh, const mor_coeff* coeff, const mo
   std::string err;
   if (build_mesh(m, err)) {
     delete c;
+    c = nullptr;
     return fail(MOR_EINVAL, err);
   }
   const int n = sub->n_sub;
   c->ext_ptr.assign(sub->ext_tet_ptr, sub->ext_tet_ptr + n + 1);
   if (c->ext_ptr[0] != 0) {
     delete c;
+    c = nullptr;
     return fail(MOR_EINVAL, "ext_tet_ptr[0] must be 0");
   }
   for (int i = 0; i < n; ++i)
     if (c->ext_ptr[i + 1] < c->ext_ptr[i]) {
       delete c;
+      c = nullptr;
       return fail(MOR_EINVAL, "ext_tet_ptr must be non-decreasing");
     }
   c->ext.assign(sub->ext_tets, sub->ext_tets + c->ext_ptr[n]);
@@ -304,32 +352,54 @@ extern "C" int mor_create(const mor_mesh* mesh, const mor_coeff* coeff, const mo
       if (cap <= c->opts.spmm_rows) c->halo_cap = cap;
   {
     // the subdomains are independent: build them on the host cores
+    // (a worker catches what its subdomain throws: 2 = host allocation failure, 3 = other)
     std::vector<std::string> errs(n);
     std::vector<int> bad(n, 0);
     const int nth = std::max(1, std::min<int>(n, (int)std::thread::hardware_concurrency()));
-    std::vector<std::thread> pool;
     std::atomic<int> next{0};
-    for (int w = 0; w < nth; ++w)
-      pool.emplace_back([&]() {
-        for (int i = next++; i < n; i = next++)
+    auto work = [&]() {
+      for (int i = next++; i < n; i = next++) {
+        try {
           bad[i] = build_sub(m, c->ext.data() + c->ext_ptr[i], c->in_core.data() + c->ext_ptr[i],
                              c->ext_ptr[i + 1] - c->ext_ptr[i], c->subs[i], errs[i], c->halo_cap);
-      });
+        } catch (const std::bad_alloc&) {
+          bad[i] = 2;
+        } catch (...) {
+          bad[i] = 3;
+        }
+      }
+    };
+    std::vector<std::thread> pool;
+    pool.reserve(nth);
+    for (int w = 0; w < nth; ++w) {
+      try {
+        pool.emplace_back(work);
+      } catch (const std::system_error&) {
+        break;   // no more threads: the ones started (or this thread, below) take the rest
+      }
+    }
     for (auto& th : pool) th.join();
+    work();
     for (int i = 0; i < n; ++i)
       if (bad[i]) {
+        const int b = bad[i];
         delete c;
+        c = nullptr;
+        if (b == 2) return fail(MOR_ENOMEM, "host memory allocation failed");
+        if (b == 3) return fail(MOR_EDEVICE, "internal error while building subdomain " + std::to_string(i));
         return fail(MOR_EINVAL, "subdomain " + std::to_string(i) + ": " + errs[i]);
       }
   }
   if (build_owner(m, c->subs, c->owner, c->ownpos, err) ||
       build_omega0(m, c->subs, c->ext_ptr.data(), c->ext.data(), c->in_core.data(), c->owner, c->ownpos, c->om0, err)) {
     delete c;
+    c = nullptr;
     return fail(MOR_EINVAL, err);
   }
   c->res.resize(n);
   if (c->opts.host_only) {
     *out = c;
+    c = nullptr;
     return MOR_OK;
   }
   // device uploads: geometry, coefficients, patterns
@@ -365,14 +435,32 @@ extern "C" int mor_create(const mor_mesh* mesh, const mor_coeff* coeff, const mo
   if (!rc && hipStreamSynchronize(c->st) != hipSuccess) rc = fail(MOR_EDEVICE, "upload failed");
   if (rc) {
     mor_destroy(c);
+    c = nullptr;
     return rc;
   }
   *out = c;
+  c = nullptr;
   return MOR_OK;
 }
 
-extern "C" void mor_destroy(mor_ctx* c) {
-  if (!c) return;
+extern "C" int mor_create(const mor_mesh* mesh, const mor_coeff* coeff, const mor_subdomains* sub,
+                          const mor_opts* opts, mor_ctx** out) {
+  mor_ctx* c = nullptr;
+  try {
+    return create_impl(mesh, coeff, sub, opts, out, c);
+  } catch (...) {
+    const int rc = exception_code();
+    if (c) {
+      try {
+        mor_destroy(c);
+      } catch (...) {
+      }
+    }
+    return rc;
+  }
+}
+
+static void destroy_impl(mor_ctx* c) {
   if (c->opts.host_only) {
     delete c;
     return;
@@ -391,6 +479,15 @@ extern "C" void mor_destroy(mor_ctx* c) {
     }
   for (void* p : c->allocs) dfree(c, p);
   delete c;
+}
+
+extern "C" void mor_destroy(mor_ctx* c) {
+  if (!c) return;
+  try {
+    destroy_impl(c);
+  } catch (...) {
+    (void)exception_code();   // nothing to return; the message stays in mor_last_error
+  }
 }
 
 // ------------------------------------------------------------------------------- assembly
@@ -1251,13 +1348,15 @@ static int engine_chunk(mor_ctx* c, MorEngine& e) {
   }
   HIPCHK(hipGetLastError());
   if (int rc = read_counts(c, e)) return rc;
-  Launch Lr;   // systems restarting from an FP64 residual
+  // Systems whose inner CG converged: refined systems fold X into the FP64 shadow and test the
+  // FP64 residual against the outer target; those above it restart while refinement steps are
+  // left, and fail with MOR_ENOTCONV after the last one.  Unrefined systems are done.
+  Launch Lr;
   std::vector<SysRun*> fin;
   for (SysRun* R : La.sys) {
     R->iters += chunk;
     if (e.h_cnt[R->cnt] > 0) continue;
-    const bool refine = R->S.X64 != nullptr;
-    if (refine && R->refines < c->opts.refine_steps) Lr.sys.push_back(R);
+    if (R->S.X64 != nullptr) Lr.sys.push_back(R);
     else fin.push_back(R);
   }
   // iteration cap
@@ -1282,20 +1381,23 @@ static int engine_chunk(mor_ctx* c, MorEngine& e) {
     HIPCHK(hipGetLastError());
     if (int rc = read_counts(c, e)) return rc;
     for (SysRun* R : Lr.sys) {
+      if (e.h_cnt[R->cnt] == 0) {   // at the outer target (X holds zeros)
+        R->phase = 1;
+        continue;
+      }
+      if (R->refines >= c->opts.refine_steps) {   // corrections used up, residual still above it
+        R->phase = 1;
+        for (Live* L : e.live)
+          if ((&L->sys[0] == R || &L->sys[1] == R) && !L->status) {
+            L->status = MOR_ENOTCONV;
+            g_err = "FP64 residual refinement did not reach refine_rtol within refine_steps corrections";
+          }
+        continue;
+      }
       R->refines++;
-      if (e.h_cnt[R->cnt] == 0) R->phase = 1;   // already at the outer target (X holds zeros)
     }
   }
-  if (!fin.empty()) {
-    Launch Lf;
-    for (SysRun* R : fin)
-      if (R->S.X64) Lf.sys.push_back(R);
-    if (!Lf.sys.empty()) {
-      if (int rc = engine_upload(c, e, Lf)) return rc;
-      launch_cg_shadow<T>(e.d_sys, Lf.sp, Lf.nsp, e.sp.rb, e.sp.v, st);
-    }
-    for (SysRun* R : fin) R->phase = 1;
-  }
+  for (SysRun* R : fin) R->phase = 1;
   return 0;
 }
 
@@ -2143,6 +2245,7 @@ static const Req* find_req(mor_ctx* c, uint64_t id, bool* pending) {
 
 extern "C" int mor_local_basis_batch(mor_ctx* c, int32_t n, const int32_t* sds, const int32_t* ranks, const double* tols,
                                      int32_t* k_eff_out) {
+  MOR_TRY
   if (!c || n <= 0 || !sds || !ranks) return fail(MOR_EINVAL, "bad arguments");
   if (c->opts.host_only) return fail(MOR_ESTATE, "context was created host_only");
   std::vector<char> seen(c->subs.size(), 0);
@@ -2172,11 +2275,13 @@ extern "C" int mor_local_basis_batch(mor_ctx* c, int32_t n, const int32_t* sds, 
       for (uint64_t id : ids) c->eng[k]->finished.erase(id);
   if (first_err) return fail(first_err, msg);
   return MOR_OK;
+  MOR_CATCH
 }
 
 extern "C" int mor_local_basis_sketched(mor_ctx* c, int32_t n, const int32_t* sds, const int32_t* ranks,
                                         const double* tols, int32_t l, const double* const* omega,
                                         int32_t* k_eff_out) {
+  MOR_TRY
   if (!c || n <= 0 || !sds || !ranks || !omega) return fail(MOR_EINVAL, "bad arguments");
   if (c->opts.host_only) return fail(MOR_ESTATE, "context was created host_only");
   if (l < 1 || l > 64) return fail(MOR_EINVAL, "sketch columns must be in 1..64");
@@ -2215,10 +2320,12 @@ extern "C" int mor_local_basis_sketched(mor_ctx* c, int32_t n, const int32_t* sd
       for (uint64_t id : ids) c->eng[k]->finished.erase(id);
   if (first_err) return fail(first_err, msg);
   return MOR_OK;
+  MOR_CATCH
 }
 
 extern "C" int mor_local_basis(mor_ctx* c, int32_t sd, int32_t rank, double tol, int32_t* k_eff_out, double* sigma_out,
                                int32_t sigma_cap) {
+  MOR_TRY
   const int rc = mor_local_basis_batch(c, 1, &sd, &rank, &tol, k_eff_out);
   if (rc) return rc;
   if (sigma_out) {
@@ -2226,10 +2333,12 @@ extern "C" int mor_local_basis(mor_ctx* c, int32_t sd, int32_t rank, double tol,
     for (int j = 0; j < sigma_cap && j < (int)s.size(); ++j) sigma_out[j] = s[j];
   }
   return MOR_OK;
+  MOR_CATCH
 }
 
 // ------------------------------------------------------------------------------- serving
 extern "C" int mor_submit(mor_ctx* c, int32_t sd, int32_t rank, double tol, int32_t precision, uint64_t* ticket) {
+  MOR_TRY
   if (!c || !ticket) return fail(MOR_EINVAL, "null argument");
   if (c->opts.host_only) return fail(MOR_ESTATE, "context was created host_only");
   if (sd < 0 || sd >= (int)c->subs.size()) return fail(MOR_EINVAL, "subdomain id out of range");
@@ -2237,14 +2346,18 @@ extern "C" int mor_submit(mor_ctx* c, int32_t sd, int32_t rank, double tol, int3
   if (precision < MOR_FP64 || precision > MOR_BF16_SPLIT) return fail(MOR_EINVAL, "unknown precision");
   *ticket = enqueue(c, sd, rank, tol, precision);
   return MOR_OK;
+  MOR_CATCH
 }
 
 extern "C" int mor_step(mor_ctx* c) {
+  MOR_TRY
   if (!c) return fail(MOR_EINVAL, "null context");
   return tick_all(c);
+  MOR_CATCH
 }
 
 extern "C" int mor_poll(mor_ctx* c, uint64_t ticket, int32_t* done, int32_t* status) {
+  MOR_TRY
   if (!c || !done || !status) return fail(MOR_EINVAL, "null argument");
   bool pend = false;
   const Req* r = find_req(c, ticket, &pend);
@@ -2252,17 +2365,21 @@ extern "C" int mor_poll(mor_ctx* c, uint64_t ticket, int32_t* done, int32_t* sta
   *done = (r && !pend) ? 1 : 0;
   *status = (r && !pend) ? r->status : 0;
   return MOR_OK;
+  MOR_CATCH
 }
 
 extern "C" int mor_drain(mor_ctx* c) {
+  MOR_TRY
   if (!c) return fail(MOR_EINVAL, "null context");
   while (!engines_idle(c))
     if (int rc = tick_all(c)) return rc;
   return MOR_OK;
+  MOR_CATCH
 }
 
 extern "C" int mor_engine_stats(mor_ctx* c, int32_t* live, int32_t* pending, int64_t* live_bytes, int64_t* peak_bytes,
                                 int64_t* budget) {
+  MOR_TRY
   if (!c) return fail(MOR_EINVAL, "null context");
   int32_t l = 0, p = 0;
   int64_t lb = 0, pb = 0, bu = 0;
@@ -2280,6 +2397,7 @@ extern "C" int mor_engine_stats(mor_ctx* c, int32_t* live, int32_t* pending, int
   if (peak_bytes) *peak_bytes = pb;
   if (budget) *budget = bu;
   return MOR_OK;
+  MOR_CATCH
 }
 
 // ------------------------------------------------------------------------------- projection
@@ -2357,6 +2475,7 @@ static int block_preconditioner(mor_ctx* c) {
 }
 
 extern "C" int mor_project(mor_ctx* c) {
+  MOR_TRY
   if (!c) return fail(MOR_EINVAL, "null context");
   if (c->opts.host_only) return fail(MOR_ESTATE, "context was created host_only");
   const int n = (int)c->subs.size();
@@ -2519,6 +2638,7 @@ extern "C" int mor_project(mor_ctx* c) {
   HIPCHK(hipStreamSynchronize(st));
   c->projected = 1;
   return MOR_OK;
+  MOR_CATCH
 }
 
 // u~ = sum_i S_i Q_i x_i at every mesh node from c->x_host
@@ -2618,6 +2738,7 @@ static int solve_pcg(mor_ctx* c, double* u_out, int64_t* n_reduced_out) {
 }
 
 extern "C" int mor_solve(mor_ctx* c, double* u_out, int64_t* n_reduced_out) {
+  MOR_TRY
   if (!c) return fail(MOR_EINVAL, "null context");
   if (c->opts.host_only) return fail(MOR_ESTATE, "context was created host_only");
   if (!c->projected) return fail(MOR_ESTATE, "mor_project must run first");
@@ -2674,10 +2795,12 @@ extern "C" int mor_solve(mor_ctx* c, double* u_out, int64_t* n_reduced_out) {
   if (n_reduced_out) *n_reduced_out = c->n_red;
   c->solved = 1;
   return MOR_OK;
+  MOR_CATCH
 }
 
 // ------------------------------------------------------------------------------- getters
 extern "C" int mor_get_sizes(mor_ctx* c, int32_t sd, int32_t* nP, int32_t* nV, int32_t* nI, int32_t* nB) {
+  MOR_TRY
   if (!c || sd < 0 || sd >= (int)c->subs.size()) return fail(MOR_EINVAL, "bad subdomain");
   const HostSub& h = c->subs[sd];
   if (nP) *nP = h.nP;
@@ -2685,15 +2808,19 @@ extern "C" int mor_get_sizes(mor_ctx* c, int32_t sd, int32_t* nP, int32_t* nV, i
   if (nI) *nI = h.nI;
   if (nB) *nB = h.nB;
   return MOR_OK;
+  MOR_CATCH
 }
 extern "C" int mor_get_nodes(mor_ctx* c, int32_t sd, int32_t* out, int64_t cap) {
+  MOR_TRY
   if (!c || sd < 0 || sd >= (int)c->subs.size() || !out) return fail(MOR_EINVAL, "bad arguments");
   const HostSub& h = c->subs[sd];
   if (cap < h.nL) return fail(MOR_EINVAL, "output too small");
   std::memcpy(out, h.nodes.data(), 4 * (size_t)h.nL);
   return MOR_OK;
+  MOR_CATCH
 }
 extern "C" int mor_get_pairs(mor_ctx* c, int32_t* out, int64_t cap, int64_t* n) {
+  MOR_TRY
   if (!c) return fail(MOR_EINVAL, "null context");
   const int64_t np = (int64_t)c->om0.pair_i.size();
   if (n) *n = np;
@@ -2703,8 +2830,10 @@ extern "C" int mor_get_pairs(mor_ctx* c, int32_t* out, int64_t cap, int64_t* n) 
       out[2 * p + 1] = c->om0.pair_j[p];
     }
   return MOR_OK;
+  MOR_CATCH
 }
 extern "C" int mor_get_basis(mor_ctx* c, int32_t sd, double* out, int64_t cap, int32_t* k_eff) {
+  MOR_TRY
   if (!c || sd < 0 || sd >= (int)c->subs.size()) return fail(MOR_EINVAL, "bad subdomain");
   const SubResult& R = c->res[sd];
   if (!R.reduced) return fail(MOR_ESTATE, "subdomain not reduced");
@@ -2715,8 +2844,10 @@ extern "C" int mor_get_basis(mor_ctx* c, int32_t sd, double* out, int64_t cap, i
     HIPCHK(hipMemcpy(out, R.d_V, 8 * n, hipMemcpyDeviceToHost));
   }
   return MOR_OK;
+  MOR_CATCH
 }
 extern "C" int mor_get_sigma(mor_ctx* c, int32_t sd, double* out, int32_t cap, int32_t* n) {
+  MOR_TRY
   if (!c || sd < 0 || sd >= (int)c->subs.size()) return fail(MOR_EINVAL, "bad subdomain");
   const SubResult& R = c->res[sd];
   if (!R.reduced) return fail(MOR_ESTATE, "subdomain not reduced");
@@ -2724,8 +2855,10 @@ extern "C" int mor_get_sigma(mor_ctx* c, int32_t sd, double* out, int32_t cap, i
   if (out)
     for (int j = 0; j < cap && j < (int)R.sigma.size(); ++j) out[j] = R.sigma[j];
   return MOR_OK;
+  MOR_CATCH
 }
 extern "C" int mor_get_local_block(mor_ctx* c, int32_t sd, double* Aii, double* bi, int64_t cap) {
+  MOR_TRY
   if (!c || sd < 0 || sd >= (int)c->subs.size()) return fail(MOR_EINVAL, "bad subdomain");
   const SubResult& R = c->res[sd];
   if (!R.reduced) return fail(MOR_ESTATE, "subdomain not reduced");
@@ -2733,8 +2866,10 @@ extern "C" int mor_get_local_block(mor_ctx* c, int32_t sd, double* Aii, double* 
   if (Aii) std::memcpy(Aii, R.Aii.data(), 8 * R.Aii.size());
   if (bi) std::memcpy(bi, R.bi.data(), 8 * R.bi.size());
   return MOR_OK;
+  MOR_CATCH
 }
 extern "C" int mor_get_reduced(mor_ctx* c, double* At, double* bt, int64_t cap, int64_t* n) {
+  MOR_TRY
   if (!c) return fail(MOR_EINVAL, "null context");
   if (!c->projected) return fail(MOR_ESTATE, "mor_project must run first");
   const int64_t nr = c->n_red;
@@ -2759,23 +2894,29 @@ extern "C" int mor_get_reduced(mor_ctx* c, double* At, double* bt, int64_t cap, 
     for (int64_t i = 0; i < nr; ++i) bt[i] = b[(size_t)i * 64];
   }
   return MOR_OK;
+  MOR_CATCH
 }
 extern "C" int mor_get_solve_info(mor_ctx* c, int32_t* solver, int32_t* iters, double* rel_residual) {
+  MOR_TRY
   if (!c) return fail(MOR_EINVAL, "null context");
   if (!c->solved) return fail(MOR_ESTATE, "mor_solve must run first");
   if (solver) *solver = c->opts.reduced_solver;
   if (iters) *iters = c->solve_iters;
   if (rel_residual) *rel_residual = c->solve_relres;
   return MOR_OK;
+  MOR_CATCH
 }
 extern "C" int mor_get_reduced_solution(mor_ctx* c, double* x, int64_t cap) {
+  MOR_TRY
   if (!c || !x) return fail(MOR_EINVAL, "null argument");
   if (!c->solved) return fail(MOR_ESTATE, "mor_solve must run first");
   if (cap < c->n_red) return fail(MOR_EINVAL, "output too small");
   std::memcpy(x, c->x_host.data(), 8 * (size_t)c->n_red);
   return MOR_OK;
+  MOR_CATCH
 }
 extern "C" int mor_get_stats(mor_ctx* c, int32_t sd, int32_t* a, int32_t* k, int32_t* refine, int32_t* eig) {
+  MOR_TRY
   if (!c || sd < 0 || sd >= (int)c->subs.size()) return fail(MOR_EINVAL, "bad subdomain");
   const SubResult& R = c->res[sd];
   if (a) *a = R.cg_a;
@@ -2783,14 +2924,18 @@ extern "C" int mor_get_stats(mor_ctx* c, int32_t sd, int32_t* a, int32_t* k, int
   if (refine) *refine = R.refine;
   if (eig) *eig = R.eig;
   return MOR_OK;
+  MOR_CATCH
 }
 
 extern "C" int mor_timing_enable(mor_ctx* c, int32_t on) {
+  MOR_TRY
   if (!c) return fail(MOR_EINVAL, "null context");
   c->timing = on != 0;
   return MOR_OK;
+  MOR_CATCH
 }
 extern "C" int mor_timing_get(mor_ctx* c, const char* name, int64_t* launches, double* total_ms, double* work) {
+  MOR_TRY
   if (!c || !name) return fail(MOR_EINVAL, "null argument");
   flush_timers(c);
   auto it = c->timers.find(name);
@@ -2804,10 +2949,13 @@ extern "C" int mor_timing_get(mor_ctx* c, const char* name, int64_t* launches, d
   if (total_ms) *total_ms = it->second.ms;
   if (work) *work = it->second.work;
   return MOR_OK;
+  MOR_CATCH
 }
 extern "C" int mor_timing_reset(mor_ctx* c) {
+  MOR_TRY
   if (!c) return fail(MOR_EINVAL, "null context");
   flush_timers(c);
   c->timers.clear();
   return MOR_OK;
+  MOR_CATCH
 }

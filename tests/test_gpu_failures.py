@@ -1,7 +1,9 @@
 """Failure handling on the GPU, every condition forced from the host so that every kernel
-exits normally: an iteration cap the block CG cannot meet, an eigensolver cap, an iteration cap
-of the reduced conjugate gradients, a request larger than the HBM budget, and calls out of order.  Each failure comes back as its error code with a
-message, the engine is left idle with its memory released, and the context keeps working."""
+exits normally: an iteration cap the block CG cannot meet, an FP64 refinement target the allowed
+corrections cannot reach, an eigensolver cap, an iteration cap of the reduced conjugate
+gradients, a request larger than the HBM budget, and calls out of order.  Each failure comes
+back as its error code with a message, the engine is left idle with its memory released, and the
+context keeps working."""
 import sys
 
 import numpy as np
@@ -36,6 +38,33 @@ def test_cg_iteration_cap_reports_enotconv():
         _say(f"[gpu] {ei.value}")
         assert ei.value.code == mor.MOR_ENOTCONV
         _idle(mor, m.ctx)
+    finally:
+        m.close()
+
+
+def test_refinement_target_out_of_reach_reports_enotconv():
+    """FP32 block CG with FP64 residual refinement: with no correction allowed (refine_steps = 0),
+    a refinement target far below what one FP32 solve to cg_rtol reaches must fail the request
+    instead of returning the unrefined solution; the same context with corrections allowed
+    reaches it."""
+    from paper_2404_06260_amd import mor
+    p = _problem()
+    for prec in ("fp32_refine", "bf16_split"):
+        m = mor.Mor(p, precision=prec, refine_steps=0, refine_rtol=1e-12)
+        try:
+            with pytest.raises(mor.MorError) as ei:
+                mor.mor_local_basis(m.ctx, 0, p.rank)
+            _say(f"[gpu] {prec}: {ei.value}")
+            assert ei.value.code == mor.MOR_ENOTCONV
+            assert "refine" in str(ei.value)
+            _idle(mor, m.ctx)
+        finally:
+            m.close()
+    m = mor.Mor(p, precision="fp32_refine", refine_steps=4, refine_rtol=1e-12)
+    try:
+        k, _ = mor.mor_local_basis(m.ctx, 0, p.rank)
+        assert k >= p.rank
+        assert 1 <= mor.mor_get_stats(m.ctx, 0)["refine"] <= 4
     finally:
         m.close()
 

@@ -404,9 +404,12 @@ def test_two_level_preconditioner_in_graph_mode_and_serving():
 @pytest.mark.parametrize("name", ["small-lognormal", "general"])
 def test_reduced_block_pcg_matches_oracle(name):
     """reduced_solver 2 (the subdomain blocks' inverses as preconditioner) against the
-    oracle's block PCG on its own reduced system: the same u~ and x^T b~, iteration counts within
-    a few, the requested residual; and with the basis update on (blocks = identity) the same
-    iteration as reduced_solver 1."""
+    oracle's block PCG on its own reduced system: the same u~ and x^T b~ and the requested
+    residual.  The two runs are not the same iteration step for step: the GPU's reduced system
+    differs from the oracle's by the rounding of the local bases, and CG on a system this
+    ill-conditioned amplifies that, so the iteration counts must agree within max(3, 10%) of the
+    oracle's.  With the basis update on (blocks = identity) reduced_solver 2 and 1 are the same
+    iteration in exact arithmetic, and their counts agree within one."""
     from oracle import project as oproject
     from paper_2404_06260_amd import mor
     p = _problem(name)

@@ -123,3 +123,38 @@ def test_default_options_and_option_checks():
         with pytest.raises(mor.MorError) as e:
             mor.mor_create(m.xyz, m.tets, m.dirichlet, p.kappa, None, sd.ext_tet_ptr, sd.ext_tets, sd.in_core, o)
         assert e.value.code == mor.MOR_EINVAL, bad
+
+
+_ENOMEM_CHILD = r"""
+import resource, sys
+sys.path.insert(0, sys.argv[1])
+import workloads as w
+from paper_2404_06260_amd import mor
+p = w.make_problem(40, (2, 2, 2), r=2)
+o = mor.mor_default_opts()
+o.host_only = 1
+m, sd = p.mesh, p.subdomains
+mor.lib()
+vm = int([l.split()[1] for l in open("/proc/self/status") if l.startswith("VmSize:")][0]) * 1024
+resource.setrlimit(resource.RLIMIT_AS, (vm + (1 << 20), resource.RLIM_INFINITY))
+try:
+    ctx = mor.mor_create(m.xyz, m.tets, m.dirichlet, p.kappa, None, sd.ext_tet_ptr, sd.ext_tets, sd.in_core, o)
+    print("CODE 0")
+except mor.MorError as e:
+    print("CODE", e.code, str(e))
+"""
+
+
+def test_host_allocation_failure_is_an_error_code():
+    """A host allocation that fails inside an entry point comes back as MOR_ENOMEM with a message,
+    not as a C++ exception through the C-ABI (which would abort the process): a child process
+    caps its address space just above its current size, then builds a context (host-only, no
+    device) for a 40^3 mesh whose copies alone exceed the cap."""
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, "-c", _ENOMEM_CHILD, ROOT], capture_output=True, text=True, timeout=300)
+    assert r.returncode == 0, r.stderr[-2000:]
+    line = [ln for ln in r.stdout.splitlines() if ln.startswith("CODE")][-1]
+    from paper_2404_06260_amd import mor
+    assert int(line.split()[1]) == mor.MOR_ENOMEM, line
+    assert "host memory allocation failed" in line
