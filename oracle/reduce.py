@@ -145,6 +145,83 @@ def reduce_local(mesh, kappa, f_nodal, sets: decomp.LocalSets, rank: int | None,
     return res
 
 
+def reduce_local_implicit(mesh, kappa, f_nodal, sets: decomp.LocalSets, rank: int | None, tol: float | None = None,
+                          eig_tol: float = 1e-13, keep: bool = False):
+    """The same local reduction as `reduce_local`, for subdomains whose dense matrices do not fit
+    (tens of thousands of interior and thousands of interface nodes): nothing of size
+    |I| x M_i or |V_i| x |V_i| is formed.
+
+    The leading singular triplets of R_i Z_i R_BB^{-1} (eq. 4.4) are the leading eigenpairs of
+    the pencil
+
+        (Z_i^T K_i Z_i) beta = sigma^2 S_B beta,   S_B = R_BB^T R_BB (Lemma 4.1),
+
+    because R_i^T R_i = K_i: with v = R_BB beta, (R_i Z_i R_BB^{-1})^T (R_i Z_i R_BB^{-1}) v =
+    sigma^2 v.  For beta normalised to beta^T S_B beta = 1 the basis function is
+    q = R_i^{-1} u = Z_i beta / sigma (eq. 4.5 and the end of Section 4).  ARPACK's Lanczos
+    iteration (scipy's eigsh, generalised mode) finds the leading eigenpairs from products
+    with the pencil's matrices, each made of sparse solves with SuperLU factors:
+      Z_i x   = -C_i A_II^{-1} A_IB x                       (the lifting, Problem 3.3)
+      Z_i^T y = -A_BI A_II^{-1} C_i^T y                     (A_II is symmetric)
+      S_B x   = K_BB x - K_BI K_II^{-1} K_IB x              (the Schur complement)
+      S_B^{-1} y = [(K^+)^{-1} (0, y)]_B                    (the inverse of a Schur complement is
+                                                             the B block of the inverse)
+    More eigenpairs than the truncation reads are computed, doubling until the truncation rule
+    (top-`rank` widened over a cluster, or sigma > tol) ends strictly inside the computed set.
+    sigma holds the computed leading singular values only."""
+    lm = local_matrices(mesh, kappa, f_nodal, sets)
+    M = lm.nB
+    A_II, A_IB, A_BI, _ = blocks(lm.A_plus, lm.nI)
+    K_II, K_IB, K_BI, K_BB = blocks(lm.K_plus, lm.nI)
+    luA = spla.splu(A_II)
+    luK = spla.splu(K_II)
+    luKp = spla.splu(lm.K_plus.tocsc())
+    C = lm.C_idx
+    K_i = lm.K_i.tocsr()
+
+    def Z(x):                                 # V x (..) from B x (..)
+        return -luA.solve(np.asarray(A_IB @ x))[C]
+
+    def Zt(y):
+        w = np.zeros((lm.nI,) + y.shape[1:])
+        w[C] = y
+        return -(A_BI @ luA.solve(w))
+
+    def G(x):                                 # Z^T K_i Z
+        return Zt(K_i @ Z(x))
+
+    def SB(x):
+        return K_BB @ x - K_BI @ luK.solve(np.asarray(K_IB @ x))
+
+    def SBinv(y):
+        w = np.zeros((lm.nI + M,) + y.shape[1:])
+        w[lm.nI:] = y
+        return luKp.solve(w)[lm.nI:]
+
+    def op(f):
+        return spla.LinearOperator((M, M), matvec=lambda x: f(x.reshape(M)), matmat=f, dtype=np.float64)
+
+    want = rank if (rank is not None and rank > 0) else 8
+    nev = min(M - 1, want + 8)
+    while True:
+        lam, beta = spla.eigsh(op(G), k=nev, M=op(SB), Minv=op(SBinv), which="LA", tol=eig_tol,
+                               v0=np.ones(M))
+        order = np.argsort(lam)[::-1]
+        lam, beta = lam[order], beta[:, order]
+        s = np.sqrt(np.maximum(lam, 0.0))
+        k = truncation_rank(s, rank, tol)
+        if k < nev or nev >= M - 1:
+            break
+        nev = min(M - 1, 2 * nev)
+    beta = beta[:, :k] / np.sqrt(np.einsum("ij,ij->j", beta[:, :k], SB(beta[:, :k])))
+    Phi = Z(beta) / s[:k]
+    q0 = luA.solve(lm.f_plus[:lm.nI])[C]
+    res = _stitch_and_project(lm, sets, s, k, q0, Phi)
+    if keep:
+        return res, dict(lm=lm, beta=beta, lam=lam)
+    return res
+
+
 def _stitch_and_project(lm: LocalMatrices, sets, sigma, k, q0, Phi) -> LocalResult:
     """Steps 5-6: V_i = D_i [q0, Phi] and the local projected block and load."""
     Vfull = np.hstack([q0[:, None], Phi])
@@ -228,21 +305,28 @@ def _work(i):
     r = int(r) if r is not None else None
     if _G.get("sketches") is not None:
         return reduce_local_sketched(p.mesh, p.kappa, p.f_nodal, sets[i], r, tol, _G["sketches"][i])
+    if _G.get("implicit"):
+        return reduce_local_implicit(p.mesh, p.kappa, p.f_nodal, sets[i], r, tol)
     return reduce_local(p.mesh, p.kappa, p.f_nodal, sets[i], r, tol)
 
 
 def reduce_all(problem, rank: int | None = None, tol: float | None = None, workers: int = 1,
-               subset=None, sketches=None) -> list[LocalResult]:
-    """Every subdomain's local reduction (explicit; the randomized variant when `sketches`
-    holds one random matrix per subdomain)."""
+               subset=None, sketches=None, implicit: bool = False, order=None) -> list[LocalResult]:
+    """Every subdomain's local reduction (explicit; through the pencil's sparse factors when
+    `implicit`, for subdomains too large for the dense matrices; the randomized variant when
+    `sketches` holds one random matrix per subdomain).  `order`, if given, is the order in which
+    a process pool takes the subdomains up (largest first keeps the pool busy to the end); the
+    results are always returned in subdomain order."""
     sets = decomp.all_local_sets(problem.mesh, problem.subdomains)
     if rank is None and tol is None and problem.ranks is None:
         rank = problem.rank
     idx = list(range(problem.subdomains.n_sub)) if subset is None else list(subset)
-    _G.update(p=problem, sets=sets, rank=rank, tol=tol, sketches=sketches)
+    _G.update(p=problem, sets=sets, rank=rank, tol=tol, sketches=sketches, implicit=implicit)
     if workers <= 1:
         return [_work(i) for i in idx]
     import multiprocessing as mp
+    run = idx if order is None else [i for i in order if i in set(idx)]
     ctx = mp.get_context("fork")
     with ctx.Pool(workers) as pool:
-        return pool.map(_work, idx, chunksize=1)
+        out = dict(zip(run, pool.imap(_work, run, chunksize=1)))
+    return [out[i] for i in idx]

@@ -229,3 +229,41 @@ def test_rank_of_the_lifting_equals_the_boundary_dofs_of_omega_i(kappa):
         nb = s.V.size - s.P.size
         assert s.B.size > nb
         assert (sg > 1e-10).sum() == (sg > 1e-13).sum() == nb, (i, nb)
+
+
+def _kspan_sin(A, B, K):
+    """Largest principal angle (sine) between the spans of two K-orthonormal bases."""
+    D = B - A @ (A.T @ (K @ B))
+    return float(np.sqrt(max(np.linalg.eigvalsh(D.T @ (K @ D)).max(), 0.0)))
+
+
+@pytest.mark.parametrize("case", ["lognormal-rank", "lognormal-tol", "inclusions-rank"])
+def test_implicit_route_equals_the_dense_svd(case):
+    """The large-subdomain route (Lanczos on the pencil (Z^T K_i Z, S_B) through sparse factors,
+    S_B^-1 as the B block of (K^+)^-1) against the dense SVD of R_i Z R_BB^-1 (eq. 4.4), which the
+    other pins of this file fix: the same k_eff, the leading singular values to 1e-9, the same
+    q_0, K_i-orthonormal modes spanning the same space (sine of the largest principal angle below
+    1e-8), and the same projected block.  The tolerance case keeps more modes than the first
+    Lanczos call computes, so the route has to widen its eigenpair count."""
+    if case.startswith("inclusions"):
+        p = w.make_problem(16, (2, 2, 2), r=3, rank=24, kappa="inclusions", seed=5)
+    else:
+        p = w.make_problem(16, (2, 2, 2), r=3, rank=10, kappa="lognormal", kappa_sigma=1.0, seed=5)
+    for i in (0, 6):
+        sets = decomp.local_sets(p.mesh, p.subdomains, i)
+        rank, tol = p.rank, None
+        if case.endswith("tol"):     # a tolerance between the 22nd and 23rd singular values
+            s = reduce.reduce_local(p.mesh, p.kappa, p.f_nodal, sets, 40).sigma
+            rank, tol = None, 0.5 * (s[21] + s[22])
+        rd = reduce.reduce_local(p.mesh, p.kappa, p.f_nodal, sets, rank, tol)
+        ri = reduce.reduce_local_implicit(p.mesh, p.kappa, p.f_nodal, sets, rank, tol)
+        k = rd.k_eff
+        assert ri.k_eff == k and (tol is None or k >= 22)
+        np.testing.assert_allclose(ri.sigma[:k + 1], rd.sigma[:k + 1], rtol=1e-9)
+        np.testing.assert_allclose(ri.q0, rd.q0, rtol=0, atol=1e-12 * np.abs(rd.q0).max())
+        K = reduce.local_matrices(p.mesh, p.kappa, p.f_nodal, sets).K_i.tocsr()
+        np.testing.assert_allclose(ri.Phi.T @ (K @ ri.Phi), np.eye(k), atol=1e-9)
+        assert _kspan_sin(rd.Phi, ri.Phi, K) < 1e-8
+        np.testing.assert_allclose(ri.Aii[0, 0], rd.Aii[0, 0], rtol=1e-12)
+        np.testing.assert_allclose(np.linalg.eigvalsh(ri.Aii), np.linalg.eigvalsh(rd.Aii), rtol=1e-8,
+                                   atol=1e-12 * np.abs(rd.Aii).max())
