@@ -1,14 +1,25 @@
 """Benchmark of the local model-order-reduction hot path on one MI355X.
 
-One step = the whole path over the 48^3 lognormal workload (64 box subdomains, r = 6 cell
-layers, rank 16): batched local reductions of every subdomain (assembly, FP32 block CG with
-FP64 refinement lifting all interface data, Gram/Schur, Cholesky, top-k eigensolve, stitching,
-local projection), the neighbour-pair projection and the reduced FP64 Cholesky solve.
+Default workload (the serving configuration the metric is quoted on): the 128^3 Kuhn cube with
+kappa = 1 and twenty spherical inclusions of kappa = 1e4, cut into 100 boxes of widths 10-40
+cells (r = 6), each local reduction one request with a rank in 8..48 and FP32 (+ FP64
+refinement) or BF16-split Gram precision drawn with p = 1/2 each.
+
+Setup (untimed): one full epoch of the request stream, so that every subdomain has a basis and
+the global projection is defined.  One step = a fixed slice of the request stream (default 4
+requests, cycling through a seeded order of the subdomains) submitted at once to the
+continuous-batching engine and served to completion (assembly, FP32 block CG with FP64
+refinement lifting every interface hat function, Gram/Schur, Cholesky, top-k eigensolve,
+stitching, local projection, the basis update), then the memory-efficient projection over all
+neighbour pairs and the reduced solve (diagonal-preconditioned CG) with the new bases.
 Inputs (mesh, coefficients, decomposition) are resident on the device before timing starts.
 
+The other workloads (--config C1..C4, C6) time the whole batched path per step.
+
 Prints one JSON line: subdomain reductions/s, the SpMM roofline (algorithmic HBM bytes per
-launch / average launch time from HIP events on the library's stream) and the FP64 CPU oracle
-timed on a bounded sample on the host cores.
+launch / average launch time from HIP events on the library's stream), p50/p99 latency of a
+Poisson stream, the MFMA roofline of the Gram contraction, the plain FP64 one-at-a-time
+comparator on a sample, and the FP64 CPU oracle timed on a bounded sample on the host cores.
 """
 from __future__ import annotations
 
@@ -23,7 +34,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 
-CONFIG_DEFAULT = "C2"
+CONFIG_DEFAULT = "C5"
 PRECISION_OF = {"C1": "fp64", "C2": "fp32_refine", "C3": "fp32_refine", "C4": "bf16_split", "C5": "fp32_refine",
                 "C6": "fp32_refine"}
 WORKLOAD_OF = {
@@ -31,36 +42,60 @@ WORKLOAD_OF = {
     "C2": "48^3 Kuhn cube (117,649 nodes), lognormal kappa sigma=1, 4x4x4 boxes, r=6, k=16",
     "C3": "64^3 jittered Kuhn cube, 6x5x4 random boxes, r=6, k=24",
     "C4": "96^3 Kuhn cube, lognormal kappa sigma=2, 8x8x8 boxes, r=6, k=32",
-    "C5": "128^3 Kuhn cube, kappa inclusions, boxes of widths 10-40, r=6, k in 8-48",
+    "C5": "128^3 Kuhn cube (2,146,689 nodes), kappa=1 with 20 spheres of kappa=1e4, 100 boxes of widths "
+          "10-40 cells, r=6, request stream with ranks 8-48, FP32+refinement / BF16-split Gram mixed",
     "C6": "216^3 Kuhn cube (10,218,313 nodes, 9.9M free DOFs), lognormal kappa sigma=1, 18x18x18 boxes, r=6, k=16",
 }
+STREAM_PRECISIONS = ("fp32_refine", "bf16_split")
 
 
-def cpu_baseline(problem, budget_s: float = 20.0):
-    """The FP64 oracle's local reduction, one subdomain after another in id order, until the
-    time budget is spent (at least one subdomain)."""
+def _oracle_box(i):
+    """One local reduction by the FP64 oracle (a process-pool task, one BLAS thread)."""
+    from threadpoolctl import threadpool_limits
+
     from oracle import decomp, reduce
-    import numpy as np  # noqa: F401
-    done = 0
+    threadpool_limits(1)
+    p = _POOL["p"]
+    s = decomp.local_sets(p.mesh, p.subdomains, i)
+    r = int(p.ranks[i]) if p.ranks is not None else p.rank
     t0 = time.perf_counter()
-    ids = []
-    star = None
-    for i in range(problem.subdomains.n_sub):
-        s = decomp.local_sets(problem.mesh, problem.subdomains, i, star)
-        r = int(problem.ranks[i]) if problem.ranks is not None else problem.rank
-        reduce.reduce_local(problem.mesh, problem.kappa, problem.f_nodal, s, r)
-        done += 1
-        ids.append(i)
-        if time.perf_counter() - t0 > budget_s:
-            break
+    if _POOL["implicit"]:
+        reduce.reduce_local_implicit(p.mesh, p.kappa, p.f_nodal, s, r)
+    else:
+        reduce.reduce_local(p.mesh, p.kappa, p.f_nodal, s, r)
+    return time.perf_counter() - t0
+
+
+_POOL = {}
+
+
+def cpu_baseline(problem, workers: int, implicit: bool):
+    """The FP64 oracle's local reduction as a process pool on the host cores, one BLAS thread per
+    process, one subdomain per process: the `workers` smallest subdomains (their extended boxes
+    by tet count), all started at once.  Must run before the process touches the GPU (the pool
+    forks it).  Rate = subdomains / wall time."""
+    import multiprocessing as mp
+
+    import numpy as np
+    sizes = np.diff(problem.subdomains.ext_tet_ptr)
+    ids = [int(i) for i in np.argsort(sizes, kind="stable")[:workers]]
+    _POOL.update(p=problem, implicit=implicit)
+    t0 = time.perf_counter()
+    with mp.get_context("fork").Pool(len(ids)) as pool:
+        per = pool.map(_oracle_box, ids, chunksize=1)
     el = time.perf_counter() - t0
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return dict(value=done / el, unit="subdomain reductions/s", cores=threads, kind="oracle",
-                sample=f"subdomains {ids} of {problem.name} (the smallest, boundary-touching ones first), "
-                       f"full FP64 local reduction each, {el:.1f} s, scipy/LAPACK with {threads} threads")
+    route = "sparse-factor pencil route (Lanczos)" if implicit else "dense SVD route"
+    return dict(value=round(len(ids) / el, 5), unit="subdomain reductions/s", cores=len(ids), kind="oracle",
+                sample=f"process pool of {len(ids)} processes x 1 BLAS thread, one subdomain each: the {len(ids)} "
+                       f"smallest subdomains {ids} of {problem.name} (extended-box tets "
+                       f"{int(sizes[ids].min())}-{int(sizes[ids].max())}), full FP64 local reduction each "
+                       f"({route}), {el:.1f} s wall, per-subdomain {min(per):.1f}-{max(per):.1f} s")
 
 
-PROFILE = os.path.join(ROOT, "profiles", "k_cg_spmm_halo_cap96_slice128_48cube_lognormal_fp32refine.md")
+PROFILE_OF = {
+    "C2": os.path.join(ROOT, "profiles", "k_cg_spmm_halo_cap96_slice128_48cube_lognormal_fp32refine.md"),
+    "C5": os.path.join(ROOT, "profiles", "k_cg_spmm_halo_128cube_inclusions_stream.md"),
+}
 
 
 def kernel_source_hash(name: str) -> str:
@@ -77,13 +112,14 @@ def kernel_source_hash(name: str) -> str:
 
 
 def profiled_traffic(kernel: str, config: str):
-    """HBM bytes per launch of `kernel` from the committed rocprofv3 summary (calibrated
-    FETCH_SIZE + WRITE_SIZE), or None when the summary covers another workload or the kernel's
-    source has changed since the counters were taken."""
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 summary of this workload
+    (calibrated FETCH_SIZE + WRITE_SIZE), or None when there is none or the kernel's source has
+    changed since the counters were taken."""
     import re
-    if config != "C2" or not os.path.exists(PROFILE):
+    path = PROFILE_OF.get(config)
+    if path is None or not os.path.exists(path):
         return None
-    txt = open(PROFILE).read()
+    txt = open(path).read()
     base = kernel.split("<")[0]
     m = re.search(base + r" source sha256 ([0-9a-f]{16})", txt)
     if not m or kernel_source_hash(base) != m.group(1):
@@ -126,6 +162,38 @@ def comparator_leg(problem, steps: int, reduced_solver: int = 0):
         m.close()
 
 
+def comparator_sample(problem, sds, ranks, batched_s: float, batched_sigma: dict):
+    """The plain FP64 per-subdomain path on a sample of requests (the first timed step's): each
+    subdomain alone, FP64 block CG to the refined path's residual target, FP64 Gram and eigensolve.
+    Compared with the batched mixed-precision time of the same requests, at equal accuracy: the
+    largest relative difference of the kept singular values."""
+    import numpy as np
+    import torch
+    from paper_2404_06260_amd import mor
+    m = mor.Mor(problem, precision="fp64")
+    try:
+        mor.mor_local_basis(m.ctx, int(sds[0]), int(ranks[0]))     # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for sd, r in zip(sds, ranks):
+            mor.mor_local_basis(m.ctx, int(sd), int(r))
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        dev = 0.0
+        for sd in sds:
+            s64 = mor.mor_get_sigma(m.ctx, int(sd))
+            sb = batched_sigma[int(sd)]
+            k = min(s64.size, sb.size)
+            dev = max(dev, float(np.max(np.abs(sb[:k] - s64[:k]) / s64[:k])))
+    finally:
+        m.close()
+    return dict(value=round(len(sds) / el, 4), unit="subdomain reductions/s",
+                path="plain FP64 block CG (residual 1e-8) + FP64 Gram/eigen, one subdomain per call",
+                sample=f"the first timed step's requests, subdomains {list(map(int, sds))}",
+                batched_value=round(len(sds) / batched_s, 4), speedup_of_batched=round(el / batched_s, 3),
+                sigma_max_rel_diff=dev)
+
+
 def serving_leg(m, problem, n_req: int, load: float, rate: float = 0.0, precisions=("fp32_refine",),
                 on_done=None, saturation=None):
     """Continuous-batching serving on the same context: the saturation rate (all requests
@@ -164,15 +232,19 @@ def main():
     ap.add_argument("--precision", default=None)
     ap.add_argument("--spmm-rows", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-budget", type=float, default=20.0)
+    ap.add_argument("--cpu-workers", type=int, default=0,
+                    help="processes of the CPU-baseline pool (0: min(8, host cores))")
     ap.add_argument("--sketch", type=int, default=0,
                     help="randomized local reduction with this many sketch columns (1..64); 0: explicit SVD")
     ap.add_argument("--graph", type=int, default=-1,
                     help="capture each CG chunk in a HIP graph (1) or launch eagerly (0); -1: graphs for C3")
     ap.add_argument("--no-comparator", action="store_true",
                     help="skip the plain FP64 one-subdomain-at-a-time comparator leg")
+    ap.add_argument("--step-requests", type=int, default=4,
+                    help="request-stream workload: requests per timed step")
     ap.add_argument("--serve-requests", type=int, default=-1,
-                    help="requests in the serving leg (-1: one per subdomain, 0: no serving leg)")
+                    help="requests in the Poisson serving leg (-1: 40 on the request-stream workload, one per "
+                         "subdomain otherwise; 0: no serving leg)")
     ap.add_argument("--serve-rate", type=float, default=0.0,
                     help="absolute Poisson arrival rate (req/s) of the serving leg; 0: a fraction of saturation")
     ap.add_argument("--serve-load", type=float, default=0.9,
@@ -197,15 +269,25 @@ def main():
                                    "design note only", "n_gpus": args.gpus}))
         sys.exit(2)
     import numpy as np
-    import torch
 
     import workloads as w
-    from paper_2404_06260_amd import mor
 
-    torch.cuda.set_device(0)
+    stream_wl = args.config == "C5"    # the request-stream workload
     prec = args.precision or PRECISION_OF[args.config]
     p = w.make_config(args.config)
-    print(f"[bench] {args.config}: {p.subdomains.n_sub} subdomains, precision {prec}", file=sys.stderr, flush=True)
+    n_sub = p.subdomains.n_sub
+    print(f"[bench] {args.config}: {n_sub} subdomains, precision {prec}", file=sys.stderr, flush=True)
+    # the CPU baseline forks a process pool: run it before this process touches the GPU
+    cpu = None
+    if not args.no_cpu_baseline:
+        workers = args.cpu_workers or min(8, os.cpu_count() or 1)
+        print(f"[bench] cpu baseline (oracle, {workers} processes)", file=sys.stderr, flush=True)
+        cpu = cpu_baseline(p, workers, implicit=stream_wl)
+        print(f"[bench] cpu baseline done: {cpu['value']} /s", file=sys.stderr, flush=True)
+
+    import torch
+    from paper_2404_06260_amd import mor, serve
+    torch.cuda.set_device(0)
     tile = {}
     if not args.spmm_rows:
         from paper_2404_06260_amd import autotune
@@ -219,7 +301,7 @@ def main():
     t_create = time.perf_counter()
     extra = {"cg_rtol": args.cg_rtol} if args.cg_rtol > 0 else {}
     extra["coarse"] = args.coarse
-    basis_update = (args.config == "C5") if args.basis_update < 0 else bool(args.basis_update)
+    basis_update = stream_wl if args.basis_update < 0 else bool(args.basis_update)
     if basis_update:
         extra["basis_update"] = 1
     m = mor.Mor(p, precision=prec, use_graph=int(use_graph), reduced_solver=red_solver, **tile, **extra)
@@ -230,13 +312,9 @@ def main():
     elt = "double" if prec == "fp64" else "float"
     spmm_kernel = (f"k_cg_spmm_halo<{elt}, {spmm_cap}, {spmm_cwb}>" if halo else
                    f"k_cg_spmm<{elt}, {tile.get('spmm_vec', 4)}>")
-    n_sub = p.subdomains.n_sub
-
-    stream_step = args.config == "C5"   # minutes per step: drive it from the serving loop with progress
-    precs_c5 = ("fp32_refine", "bf16_split")
 
     def progress(j, n_done, t):
-        print(f"[bench] {n_done}/{n_sub} subdomains reduced ({t:.0f} s)", file=sys.stderr, flush=True)
+        print(f"[bench] {n_done} requests served ({t:.0f} s)", file=sys.stderr, flush=True)
 
     sketches = None
     if args.sketch > 0:   # seeded Gaussian S_i per subdomain, rows in the library's interface order
@@ -246,16 +324,36 @@ def main():
             sketches.append(w.sketch_rows(p.mesh.n_nodes, mor.mor_get_nodes(m.ctx, i)[nI:nI + nB], args.sketch, i))
         sk_ranks = p.ranks if p.ranks is not None else np.full(n_sub, p.rank)
 
+    setup = None
+    slices = None
+    if stream_wl:
+        # setup: one full epoch of the stream (every subdomain reduced once), untimed
+        t0 = time.perf_counter()
+        ep = serve.run_stream(m.ctx, serve.make_stream(p, n_sub, float("inf"), seed_order=12,
+                                                       precisions=STREAM_PRECISIONS, precision_p=(0.5, 0.5)),
+                              on_done=lambda j, n, t: n % 10 == 0 and progress(j, n, t))
+        if (ep.status != 0).any():
+            raise RuntimeError(f"{int((ep.status != 0).sum())} requests of the setup epoch failed")
+        m.project()
+        m.solve()
+        torch.cuda.synchronize()
+        setup = {"epoch_requests": n_sub, "epoch_s": round(time.perf_counter() - t0, 2),
+                 "epoch_throughput_per_s": round(ep.throughput, 4)}
+        print(f"[bench] setup epoch {setup['epoch_s']} s", file=sys.stderr, flush=True)
+        # the steps' request slices: a second seeded order of the subdomains, cycling
+        S = args.step_requests
+        n_req = S * (args.warmup + args.steps)
+        full = serve.make_stream(p, n_req, float("inf"), seed_order=13, seed_precision=14,
+                                 precisions=STREAM_PRECISIONS, precision_p=(0.5, 0.5))
+        slices = [serve.Stream(arrivals=full.arrivals[a:a + S], sds=full.sds[a:a + S], ranks=full.ranks[a:a + S],
+                               precisions=full.precisions[a:a + S]) for a in range(0, n_req, S)]
+    step_no = [0]
+
     def step():
         if sketches is not None:
             mor.mor_local_basis_sketched(m.ctx, np.arange(n_sub), sk_ranks, sketches)
-            m.project()
-            return m.solve()
-        if stream_step:
-            from paper_2404_06260_amd import serve
-            st = serve.make_stream(p, n_sub, float("inf"), seed_order=12, precisions=precs_c5,
-                                   precision_p=(0.5, 0.5))
-            res = serve.run_stream(m.ctx, st, on_done=progress)
+        elif stream_wl:
+            res = serve.run_stream(m.ctx, slices[step_no[0]])
             if (res.status != 0).any():
                 raise RuntimeError(f"{int((res.status != 0).sum())} requests failed")
         elif n_sub > 1000:   # thousands of subdomains: batches of 729 with a progress line after each
@@ -267,6 +365,7 @@ def main():
                 progress(None, int(ids[-1]) + 1, time.perf_counter() - t0s)
         else:
             m.local_basis_all()
+        step_no[0] += 1
         m.project()
         return m.solve()
 
@@ -282,15 +381,20 @@ def main():
     mor.mor_timing_reset(m.ctx)
     mor.mor_timing_enable(m.ctx, True)
     torch.cuda.synchronize()
+    step_s = []
     t0 = time.perf_counter()
     for i in range(args.steps):
+        ts = time.perf_counter()
         u, nred = step()
-        print(f"[bench] step {i} done", file=sys.stderr, flush=True)
+        step_s.append(time.perf_counter() - ts)
+        print(f"[bench] step {i} done ({step_s[-1]:.2f} s)", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     mor.mor_timing_enable(m.ctx, False)
     el = t1 - t0
     ms_per_step = 1e3 * el / args.steps
+    per_step = args.step_requests if stream_wl else n_sub
+    value = per_step * args.steps / el
     n_launch, spmm_ms, spmm_bytes = mor.mor_timing_get(m.ctx, "spmm")
     if use_graph:   # per-kernel events do not exist inside a graph: the whole chunk is the unit
         n_launch, spmm_ms, spmm_bytes = mor.mor_timing_get(m.ctx, "cg_graph")
@@ -304,7 +408,8 @@ def main():
         n, ms, wk = mor.mor_timing_get(m.ctx, name)
         if n:
             kernels[name] = dict(launches=n, ms_per_step=round(ms / args.steps, 3))
-    stats = [mor.mor_get_stats(m.ctx, i) for i in range(n_sub)]
+    timed_sds = sorted({int(s) for sl in slices[args.warmup:] for s in sl.sds}) if stream_wl else range(n_sub)
+    stats = [mor.mor_get_stats(m.ctx, i) for i in timed_sds]
     _, red_iters, red_rel = mor.mor_get_solve_info(m.ctx)
     n_s, ms_s, _ = mor.mor_timing_get(m.ctx, "solve")
     reduced_solve = {"solver": {0: "dense FP64 Cholesky", 1: "diagonal-preconditioned CG, block-sparse",
@@ -324,29 +429,47 @@ def main():
         tf = fl_g / (ms_g * 1e-3) / 1e12
         mfma = {"bound": "mfma", "kernel": kname, "achieved": round(tf, 2), "peak": peak, "unit": "TFLOP/s",
                 "frac": round(tf / peak, 4), "flops_per_step": fl_g / args.steps}
+    # the comparator sample (request-stream workload): the first timed step's requests
+    cmp_sample = None
+    if stream_wl and not args.no_comparator:
+        sl = slices[args.warmup]
+        cmp_sample = (sl.sds, sl.ranks, step_s[0], {int(s): mor.mor_get_sigma(m.ctx, int(s)) for s in sl.sds})
     serving = None
     if args.serve_requests != 0:
+        n_serve = args.serve_requests if args.serve_requests > 0 else (40 if stream_wl else n_sub)
         rate, sat = args.serve_rate, None
-        if stream_step and rate <= 0:   # the timed steps were saturation epochs already
-            sat = n_sub * args.steps / el
+        if stream_wl and rate <= 0:   # the timed steps measured the saturated rate already
+            sat = value
             rate = args.serve_load * sat
-        serving = serving_leg(m, p, n_sub if args.serve_requests < 0 else args.serve_requests, args.serve_load,
-                              rate=rate, precisions=precs_c5 if stream_step else ("fp32_refine",),
-                              on_done=progress if stream_step else None, saturation=sat)
+        serving = serving_leg(m, p, n_serve, args.serve_load, rate=rate,
+                              precisions=STREAM_PRECISIONS if stream_wl else ("fp32_refine",),
+                              on_done=(lambda j, n, t: n % 10 == 0 and progress(j, n, t)) if stream_wl else None,
+                              saturation=sat)
     m.close()
+    torch.cuda.empty_cache()   # the context's memory back to the device for the comparator's budget
     comparator = None
     if not args.no_comparator and prec != "fp64":
         print("[bench] comparator: plain FP64 per-subdomain path", file=sys.stderr, flush=True)
-        comparator = comparator_leg(p, 1, red_solver)
-        comparator["speedup_of_value"] = round(n_sub * args.steps / el / comparator["value"], 3)
-        comparator["energy_rel_diff"] = abs(comparator.pop("energy") - energy_b) / abs(energy_b)
-    cpu = None
-    if not args.no_cpu_baseline:
-        print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
-        cpu = cpu_baseline(p, args.cpu_budget)
+        if stream_wl:
+            comparator = comparator_sample(p, *cmp_sample)
+        else:
+            comparator = comparator_leg(p, 1, red_solver)
+            comparator["speedup_of_value"] = round(value / comparator["value"], 3)
+            comparator["energy_rel_diff"] = abs(comparator.pop("energy") - energy_b) / abs(energy_b)
+    cfg = {"workload": WORKLOAD_OF[args.config], "name": args.config, "subdomains": n_sub,
+           "precision": "fp32_refine | bf16_split, p = 1/2 each" if stream_wl else prec,
+           "reduced_dim": int(nred), "hip_graph": use_graph,
+           "cg_preconditioner": "block Jacobi + coarse correction" if args.coarse else "block Jacobi",
+           "basis_update": basis_update,
+           "local_svd": f"randomized, {args.sketch} sketch columns" if sketches is not None else "explicit",
+           "tiles": tile or "library defaults"}
+    if stream_wl:
+        cfg["step"] = (f"{args.step_requests} requests of the stream served to completion by the continuous-batching "
+                       f"engine, then projection over all {n_sub} subdomains and the reduced solve")
+        cfg["setup"] = setup
     out = {
         "metric": "subdomain reductions/s",
-        "value": round(n_sub * args.steps / el, 4),
+        "value": round(value, 4),
         "unit": "subdomain reductions/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -355,16 +478,10 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32+f64+bf16" if stream_step else {"fp64": "f64", "fp32_refine": "f32+f64", "fp32": "f32",
-                                                      "bf16_split": "f32+f64+bf16"}[prec],
+        "dtype": "f32+f64+bf16" if stream_wl else {"fp64": "f64", "fp32_refine": "f32+f64", "fp32": "f32",
+                                                   "bf16_split": "f32+f64+bf16"}[prec],
         "data": "synthetic",
-        "config": {"workload": WORKLOAD_OF[args.config], "name": args.config, "subdomains": n_sub,
-                   "precision": "fp32_refine | bf16_split, p = 1/2 each" if stream_step else prec,
-                   "reduced_dim": int(nred), "hip_graph": use_graph,
-                   "cg_preconditioner": "block Jacobi + coarse correction" if args.coarse else "block Jacobi",
-                   "basis_update": basis_update,
-                   "local_svd": f"randomized, {args.sketch} sketch columns" if sketches is not None else "explicit",
-                   "tiles": tile or "library defaults"},
+        "config": cfg,
         "roofline": {"bound": "hbm",
                      "kernel": spmm_kernel if use_graph else f"{spmm_kernel} (block-CG SpMM Q = A_II P)",
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",

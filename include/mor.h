@@ -252,6 +252,11 @@ int mor_get_pairs(mor_ctx* ctx, int32_t* pairs_out, int64_t cap, int64_t* n_pair
  * dim columns of the updated basis instead.  The stitched basis is its first nP rows.
  * The last argument receives dim - 1. */
 int mor_get_basis(mor_ctx* ctx, int32_t sd, double* out, int64_t cap, int32_t* k_eff);
+/* The truncation of the last local reduction of sd (eq. 4.5): k_eff = lifting modes kept by the
+ * rank or tolerance rule (widened over a cluster), dim = basis columns of the subdomain (k_eff + 1,
+ * or fewer after the basis update of Section 6 step 2).  MOR_ESTATE before sd is reduced.  Either
+ * pointer may be NULL. */
+int mor_get_rank(mor_ctx* ctx, int32_t sd, int32_t* k_eff, int32_t* dim);
 /* Leading singular values of the weighted lifting operator (up to cap). */
 int mor_get_sigma(mor_ctx* ctx, int32_t sd, double* out, int32_t cap, int32_t* n);
 /* Q_i^T A_ii Q_i (dim^2, row-major) and Q_i^T f_i (dim). */

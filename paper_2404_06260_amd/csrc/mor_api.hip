@@ -2927,6 +2927,17 @@ extern "C" int mor_get_stats(mor_ctx* c, int32_t sd, int32_t* a, int32_t* k, int
   MOR_CATCH
 }
 
+extern "C" int mor_get_rank(mor_ctx* c, int32_t sd, int32_t* k_eff, int32_t* dim) {
+  MOR_TRY
+  if (!c || sd < 0 || sd >= (int)c->subs.size()) return fail(MOR_EINVAL, "bad subdomain");
+  const SubResult& R = c->res[sd];
+  if (!R.reduced) return fail(MOR_ESTATE, "subdomain not reduced");
+  if (k_eff) *k_eff = R.k_eff;
+  if (dim) *dim = R.dim;
+  return MOR_OK;
+  MOR_CATCH
+}
+
 extern "C" int mor_timing_enable(mor_ctx* c, int32_t on) {
   MOR_TRY
   if (!c) return fail(MOR_EINVAL, "null context");

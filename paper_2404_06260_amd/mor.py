@@ -22,7 +22,7 @@ PRECISIONS = {"fp64": MOR_FP64, "fp32_refine": MOR_FP32_REFINE, "fp32": MOR_FP32
 EXPORTED = ("mor_default_opts", "mor_create", "mor_local_basis", "mor_local_basis_batch", "mor_local_basis_sketched",
             "mor_project",
             "mor_solve", "mor_submit", "mor_poll", "mor_drain", "mor_step", "mor_engine_stats", "mor_get_sizes", "mor_get_nodes",
-            "mor_get_pairs", "mor_get_basis", "mor_get_sigma", "mor_get_local_block", "mor_get_reduced",
+            "mor_get_pairs", "mor_get_basis", "mor_get_rank", "mor_get_sigma", "mor_get_local_block", "mor_get_reduced",
             "mor_get_reduced_solution", "mor_get_solve_info", "mor_get_stats", "mor_timing_enable", "mor_timing_get",
             "mor_timing_reset", "mor_destroy", "mor_last_error")
 
@@ -92,6 +92,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "mor_get_nodes": (I32, [P, I32, P, I64]),
         "mor_get_pairs": (I32, [P, P, I64, P]),
         "mor_get_basis": (I32, [P, I32, P, I64, P]),
+        "mor_get_rank": (I32, [P, I32, P, P]),
         "mor_get_sigma": (I32, [P, I32, P, I32, P]),
         "mor_get_local_block": (I32, [P, I32, P, P, I64]),
         "mor_get_reduced": (I32, [P, P, P, I64, P]),
@@ -282,6 +283,13 @@ def mor_get_basis(ctx, sd):
     out = np.zeros((nV, k.value + 1))
     _check(lib().mor_get_basis(ctx, sd, _ptr(out), out.size, ctypes.byref(k)))
     return out
+
+
+def mor_get_rank(ctx, sd):
+    """(k_eff, dim): lifting modes kept and basis columns after the optional basis update."""
+    k, d = ctypes.c_int32(), ctypes.c_int32()
+    _check(lib().mor_get_rank(ctx, sd, ctypes.byref(k), ctypes.byref(d)))
+    return k.value, d.value
 
 
 def mor_get_sigma(ctx, sd, cap=64):

@@ -3,17 +3,21 @@ seeded random positions (120 subdomains of uneven size, r = 6, rank 24), in the 
 configuration the benchmark times (every CG chunk over all admitted subdomains replayed as one
 HIP graph, autotuned tiles, FP32 block CG with FP64 refinement).
 
-The FP64 oracle cannot redo the whole workload inside a test, so it is compared on sampled
-outputs it computes one by one, and the rest is checked through properties that hold at any
-size:
-  - sampled subdomains (the smallest and one from the lower quartile of sizes) against the
-    oracle: k_eff exact, singular values (rtol 1e-7), q_0 and the span of the lifting modes
-    (largest principal angle in the K_i inner product below 1e-5);
+Against the FP64 oracle's whole-path result stored in tests/golden/C3_oracle.npz (written by
+tests/golden/make_oracle_reference.py `C3 4 --implicit`: every box reduced through the sparse
+factors of the pencil (Z^T K_i Z, S_B), the reduced system by Cholesky, and the FE solution):
+  - k_eff of every box (exact) and its leading k_eff + 1 singular values (rtol 1e-7);
+  - the reduced solution in the global energy norm (the FP32-refined path's bound, 1e-6) and
+    x^T b~;
+and on sampled outputs the oracle recomputes one by one: the smallest box and the largest (box
+80, 21 060 interior and 4 924 interface nodes): q_0 and the span of the lifting modes (largest
+principal angle in the K_i inner product below 1e-5).  Properties that hold at any size:
   - the reduced system is SPD and the reduced solution satisfies A~ x = b~;
   - with A and b assembled independently by the oracle, the reconstruction u~ = Q x satisfies
     u~^T A u~ = x^T A~ x and u~^T b = x^T b~ (so Q^T A Q and Q^T b from the memory-efficient
     projection agree with the global matrix), and the energy ||u~||_A^2 = x^T b~.
 """
+import os
 import sys
 
 import numpy as np
@@ -29,7 +33,9 @@ pytestmark = pytest.mark.gpu
 
 TOL_SIGMA = 1e-7
 TOL_ANGLE = 1e-5
-SAMPLED = (0, 115)
+TOL_ENERGY = 1e-6
+SAMPLED = (0, 80)
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "C3_oracle.npz")
 
 
 def _say(msg):
@@ -72,9 +78,26 @@ def test_c3_full_size_graph_mode():
         np.testing.assert_allclose(e_u, x @ (At @ x), rtol=1e-9)
         np.testing.assert_allclose(uf @ b, x @ bt, rtol=1e-9)
         np.testing.assert_allclose(e_u, x @ bt, rtol=1e-9)
+        if os.path.exists(GOLDEN):
+            ref = np.load(GOLDEN)
+            np.testing.assert_array_equal(k, ref["k_eff"])
+            worst = 0.0
+            for i in range(p.subdomains.n_sub):
+                sig = mor.mor_get_sigma(m.ctx, i)
+                ns = min(sig.size, int(k[i]) + 1)
+                d = float(np.max(np.abs(sig[:ns] - ref["sigma"][i, :ns]) / ref["sigma"][i, :ns]))
+                worst = max(worst, d)
+                assert d < TOL_SIGMA, (i, d)
+            np.testing.assert_allclose(x @ bt, ref["x"] @ ref["bt"], rtol=1e-8)
+            uo = ref["u_tilde"][free]
+            dv = uf - uo
+            erel = np.sqrt(max(dv @ (A @ dv), 0.0)) / np.sqrt(uo @ (A @ uo))
+            _say(f"[gpu] C3: against the stored oracle result: singular values {worst:.2e}, energy rel {erel:.3e}, "
+                 f"oracle reduction error {float(ref['red_err'] / ref['u_energy']):.3e}")
+            assert erel < TOL_ENERGY, erel
         for i in SAMPLED:
             s = odecomp.local_sets(p.mesh, p.subdomains, i)
-            r = oreduce.reduce_local(p.mesh, p.kappa, p.f_nodal, s, p.rank)
+            r = oreduce.reduce_local_implicit(p.mesh, p.kappa, p.f_nodal, s, p.rank)
             assert k[i] == r.k_eff, (i, k[i], r.k_eff)
             sig = mor.mor_get_sigma(m.ctx, i)
             ns = min(sig.size, r.k_eff + 1)

@@ -4,7 +4,16 @@ precisions in one stream each match their own solo run.
 
 "Same" is judged at the FP32 paths' tolerance: singular values within 1e-7 relative, k_eff
 exact, and the largest principal angle between the two bases below 1e-5 (the batched CG sums
-p'Ap with atomics in a different order, so results agree to rounding, not bit for bit).
+p'Ap with atomics in a different order, so results agree to rounding, not bit for bit).  A
+request with the BF16 split Gram is judged at that path's tolerance (singular values 1e-4,
+angle 1e-3): the hi/lo BF16 pair represents the lifting to about 16 bits, so a rounding-level
+change of the CG solution can move the Gram by that much.
+
+The high-contrast case is the serving workload's input class at a size the oracle reduces in
+seconds: kappa = 1e4 in spherical inclusions, uneven boxes, ranks 8..48, a Poisson stream of
+FP32-refined and BF16-Gram requests, the basis update of Section 6 step 2 and the paper's
+diagonal-preconditioned reduced CG.  Each result matches its solo run, and the reduced solution
+matches the FP64 oracle's (same readings) in the global energy norm within the BF16 bound.
 """
 import sys
 
@@ -17,6 +26,7 @@ pytestmark = pytest.mark.gpu
 
 TOL_SIGMA = 1e-7
 TOL_ANGLE = 1e-5
+TOL_BF16 = dict(sigma=1e-4, angle=1e-3)
 
 
 def _say(msg):
@@ -43,9 +53,9 @@ def _result(mor, ctx, sd):
     return dict(sigma=mor.mor_get_sigma(ctx, sd), V=mor.mor_get_basis(ctx, sd))
 
 
-def _solo(p, sd, rank, precision):
+def _solo(p, sd, rank, precision, **opts):
     from paper_2404_06260_amd import mor
-    m = mor.Mor(p, precision=precision)
+    m = mor.Mor(p, precision=precision, **opts)
     try:
         k, _ = mor.mor_local_basis(m.ctx, sd, int(rank))
         r = _result(mor, m.ctx, sd)
@@ -55,14 +65,20 @@ def _solo(p, sd, rank, precision):
         m.close()
 
 
-def _compare(a, b, k, tag):
+def _compare(a, b, k, tag, precision="fp32_refine", whole_basis=False):
+    """Solo result a against mix result b.  whole_basis: compare the span of every basis column
+    (after the basis update the columns are whitened combinations of q_0 and the modes)."""
+    tol_s, tol_a = (TOL_BF16["sigma"], TOL_BF16["angle"]) if precision == "bf16_split" else (TOL_SIGMA, TOL_ANGLE)
     ns = min(a["sigma"].size, b["sigma"].size, k + 1)
-    np.testing.assert_allclose(b["sigma"][:ns], a["sigma"][:ns], rtol=TOL_SIGMA, err_msg=tag)
+    np.testing.assert_allclose(b["sigma"][:ns], a["sigma"][:ns], rtol=tol_s, err_msg=tag)
     assert a["V"].shape == b["V"].shape, tag
-    np.testing.assert_allclose(b["V"][:, 0], a["V"][:, 0], rtol=0, atol=1e-6 * np.abs(a["V"][:, 0]).max(),
-                               err_msg=tag)
-    s = _sin_angle(a["V"][:, 1:], b["V"][:, 1:])
-    assert s < TOL_ANGLE, (tag, s)
+    if whole_basis:
+        s = _sin_angle(a["V"], b["V"])
+    else:
+        np.testing.assert_allclose(b["V"][:, 0], a["V"][:, 0], rtol=0, atol=10 * tol_a * np.abs(a["V"][:, 0]).max(),
+                                   err_msg=tag)
+        s = _sin_angle(a["V"][:, 1:], b["V"][:, 1:])
+    assert s < tol_a, (tag, s)
 
 
 def _run_mix(p, stream, **opts):
@@ -129,11 +145,67 @@ def test_mixed_precisions_each_match_their_solo_run():
     p = _problem()
     n = p.subdomains.n_sub
     stream = serve.make_stream(p, n, rate=400.0, seed_arrivals=51, seed_order=52,
-                               precisions=("fp32_refine", "fp64"), precision_p=(0.5, 0.5))
-    assert len(set(stream.precisions)) == 2
+                               precisions=("fp32_refine", "fp64", "bf16_split"), precision_p=(0.4, 0.3, 0.3))
+    assert len(set(stream.precisions)) == 3
     res, mix = _run_mix(p, stream, cg_chunk=4)
     assert (res.status == 0).all()
     for j in range(n):
         sd = int(stream.sds[j])
         solo = _solo(p, sd, stream.ranks[j], stream.precisions[j])
-        _compare(solo, mix[j], solo["k"], f"subdomain {sd} {stream.precisions[j]}")
+        _compare(solo, mix[j], solo["k"], f"subdomain {sd} {stream.precisions[j]}", stream.precisions[j])
+
+
+def _inclusions_problem():
+    rng = np.random.default_rng(61)
+    cuts = tuple(w.cuts_random(20, k, 4, rng) for k in (3, 2, 2))
+    p = w.make_problem(20, cuts=cuts, r=3, rank=48, kappa="inclusions", seed=62, name="inclusions-small")
+    p.ranks = np.random.default_rng(63).integers(8, 49, size=p.subdomains.n_sub)
+    return p
+
+
+def test_inclusions_stream_mixed_precisions_match_solo_and_oracle():
+    import torch
+    from oracle import solve as osolve
+    from paper_2404_06260_amd import mor, serve
+    p = _inclusions_problem()
+    n = p.subdomains.n_sub
+    assert float(p.kappa.max()) == 1e4 and float(p.kappa.min()) == 1.0
+    _say(f"[oracle] inclusions-small: {n} subdomains, ranks {p.ranks.tolist()}")
+    ref = osolve.run(p, workers=4, update_drop=1e-10, pcg_rtol=1e-12)
+    stream = serve.make_stream(p, n, rate=300.0, seed_arrivals=64, seed_order=65,
+                               precisions=("fp32_refine", "bf16_split"), precision_p=(0.5, 0.5))
+    assert len(set(stream.precisions)) == 2
+    opts = dict(basis_update=1, reduced_solver=1)
+    torch.cuda.set_device(0)
+    m = mor.Mor(p, precision="fp32_refine", cg_chunk=4, **opts)
+    try:
+        res = serve.run_stream(m.ctx, stream)
+        assert (res.status == 0).all(), res.status
+        assert res.max_live >= 2, "requests never overlapped on the device"
+        mix = {j: _result(mor, m.ctx, int(stream.sds[j])) for j in range(n)}
+        m.project()
+        u, nred = m.solve()
+        _, it, rel = mor.mor_get_solve_info(m.ctx)
+        A, free = ref["A"], ref["free"]
+        d = (u - ref["u_tilde"])[free]
+        uo = ref["u_tilde"][free]
+        erel = np.sqrt(max(d @ (A @ d), 0.0)) / np.sqrt(uo @ (A @ uo))
+        _say(f"[serve] inclusions: reduced dim {nred} (oracle {ref['x'].size}), reduced CG {it} iterations "
+             f"(oracle {ref['pcg_iters']}), energy rel {erel:.3e}")
+        assert 0 < rel <= 1e-12
+        assert erel < 1e-3, erel
+        for j in range(n):
+            sd, prec = int(stream.sds[j]), stream.precisions[j]
+            r = ref["local"][sd]
+            k = mor.mor_get_stats(m.ctx, sd)
+            sig = mix[j]["sigma"]
+            ns = min(sig.size, r.k_eff + 1)
+            np.testing.assert_allclose(sig[:ns], r.sigma[:ns], rtol=TOL_BF16["sigma"] if prec == "bf16_split" else 1e-6,
+                                       err_msg=f"subdomain {sd} {prec} vs oracle")
+            assert k["cg_iter_a"] > 0
+    finally:
+        m.close()
+    for j in range(n):
+        sd, prec = int(stream.sds[j]), stream.precisions[j]
+        solo = _solo(p, sd, stream.ranks[j], prec, **opts)
+        _compare(solo, mix[j], solo["k"], f"subdomain {sd} {prec}", prec, whole_basis=True)
