@@ -180,11 +180,11 @@ def comparator_sample(problem, sds, ranks, batched_s: float, batched_sigma: dict
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
         dev = 0.0
-        for sd in sds:
+        for sd in sds:   # the singular values the truncation read: the kept ones and the next
             s64 = mor.mor_get_sigma(m.ctx, int(sd))
-            sb = batched_sigma[int(sd)]
-            k = min(s64.size, sb.size)
-            dev = max(dev, float(np.max(np.abs(sb[:k] - s64[:k]) / s64[:k])))
+            k = min(mor.mor_get_rank(m.ctx, int(sd))[0] + 1, s64.size)
+            sb = batched_sigma[int(sd)][:k]
+            dev = max(dev, float(np.max(np.abs(sb - s64[:k]) / s64[:k])))
     finally:
         m.close()
     return dict(value=round(len(sds) / el, 4), unit="subdomain reductions/s",
@@ -251,6 +251,8 @@ def main():
                     help="Poisson arrival rate of the serving leg as a fraction of the measured saturation rate")
     ap.add_argument("--cg-rtol", type=float, default=0.0,
                     help="inner block-CG tolerance (0: the library default); FP32 paths refine to the same FP64 target")
+    ap.add_argument("--box-spmm", type=int, default=0,
+                    help="0: the plane-streaming SpMM for box interiors (FP32 systems), -1: the general SpMM only")
     ap.add_argument("--coarse", type=int, default=1,
                     help="block-CG preconditioner: 1 two-level (block Jacobi + coarse correction), 0 block Jacobi")
     ap.add_argument("--reduced-solver", choices=("pcg", "pcg-block", "cholesky"), default="pcg",
@@ -301,6 +303,7 @@ def main():
     t_create = time.perf_counter()
     extra = {"cg_rtol": args.cg_rtol} if args.cg_rtol > 0 else {}
     extra["coarse"] = args.coarse
+    extra["box_spmm"] = args.box_spmm
     basis_update = stream_wl if args.basis_update < 0 else bool(args.basis_update)
     if basis_update:
         extra["basis_update"] = 1
@@ -396,6 +399,10 @@ def main():
     per_step = args.step_requests if stream_wl else n_sub
     value = per_step * args.steps / el
     n_launch, spmm_ms, spmm_bytes = mor.mor_timing_get(m.ctx, "spmm")
+    nb_l, nb_ms, nb_bytes = mor.mor_timing_get(m.ctx, "spmm_box")
+    if nb_l and nb_ms > 0 and nb_bytes >= spmm_bytes:   # the box kernel carried most of the SpMM bytes
+        n_launch, spmm_ms, spmm_bytes = nb_l, nb_ms, nb_bytes
+        spmm_kernel = "k_cg_spmm_box"
     if use_graph:   # per-kernel events do not exist inside a graph: the whole chunk is the unit
         n_launch, spmm_ms, spmm_bytes = mor.mor_timing_get(m.ctx, "cg_graph")
         spmm_kernel = "CG chunk graph: SpMM + alpha + update + beta + direction"
@@ -403,7 +410,7 @@ def main():
     bytes_per_launch = spmm_bytes / max(n_launch, 1)
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
     kernels = {}
-    for name in ("spmm", "cg_update", "cg_direction", "cg_coarse", "coarse_setup", "cg_graph", "residual64", "assemble", "gram", "gram_split", "gram_bf16",
+    for name in ("spmm", "spmm_box", "cg_update", "cg_direction", "cg_coarse", "coarse_setup", "cg_graph", "residual64", "assemble", "gram", "gram_split", "gram_bf16",
                  "schur", "potrf", "trsm", "eig", "basis", "project_local", "project", "solve"):
         n, ms, wk = mor.mor_timing_get(m.ctx, name)
         if n:

@@ -134,9 +134,9 @@ typedef struct {
                               update_drop * lambda_max removed, basis rescaled so the block is the
                               identity (the basis then has dim <= k_eff + 1 columns) */
   double update_drop;      /* relative eigenvalue drop of the basis update (basis_update = 1) only
-                              (0 = automatic per subdomain, the accuracy of its basis: max(1e-10,
-                              refine_rtol) for MOR_FP64 and MOR_FP32_REFINE bases, 1e-6 for
-                              MOR_FP32 and MOR_BF16_SPLIT bases).  The block preconditioner of
+                              (0 = 1e-10: only numerically dependent directions of the stitched block
+                              go, in every precision mode; a larger drop can remove directions that
+                              carry much of the solution's energy).  The block preconditioner of
                               reduced_solver 2 keeps every positive eigenvalue of each block */
   int32_t reduced_solver;  /* solver of the reduced system Q^T A Q x = Q^T b:
                               0 = dense FP64 Cholesky (mor_project stores the n x n matrix);
@@ -159,6 +159,10 @@ typedef struct {
                               aggregates, with the coarse matrix P^T A_II P inverted in FP64 (on the
                               48^3 workload 25-30% fewer iterations for a small dense product per
                               iteration); 0: block Jacobi only */
+  int32_t box_spmm;        /* 0 (default): FP32 systems whose interior rows fill a box of a Kuhn lattice
+                              (detected from the mesh: grid points, Kuhn edge offsets) use the
+                              plane-streaming SpMM (timer "spmm_box"); -1: the general SpMM for every
+                              system (also with spmm_kind 2) */
 } mor_opts;
 
 /* Fill `opts` with defaults (FP32_REFINE, cg_rtol 1e-5, refine_rtol 1e-8, ...). */

@@ -84,6 +84,9 @@ static int exception_code() noexcept {
 
 static inline int64_t rup(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
 
+// The eigensolver's subspace holds at most 64 vectors; a truncation must end two inside it.
+constexpr int kMaxRank = 62;
+
 namespace {
 
 struct TimerRec {
@@ -100,6 +103,7 @@ struct SubDev {
   uint16_t *hpp = nullptr, *hself = nullptr;
   uint8_t* core = nullptr;
   int* rcb = nullptr;
+  int *smap = nullptr, *spos = nullptr;   // box form of the interior, or nullptr
 };
 
 struct SubResult {
@@ -427,6 +431,10 @@ static int create_impl(const mor_mesh* mesh, const mor_coeff* coeff, const mor_s
     r = r ? r : upload(c, &d.hpp, h.hpp.data(), h.hpp.size());
     r = r ? r : upload(c, &d.hself, h.hself.data(), h.hself.size());
     r = r ? r : upload(c, &d.rcb, h.rcb.data(), h.rcb.size());
+    if (!h.smap.empty()) {
+      r = r ? r : upload(c, &d.smap, h.smap.data(), h.smap.size());
+      r = r ? r : upload(c, &d.spos, h.spos.data(), h.spos.size());
+    }
     return r;
   };
   c->sdev.resize(n);
@@ -649,6 +657,7 @@ struct Slot {
   int M, MP, T, colsA, ldA, colsK, ldK, s, nconv;
   double *A64, *K64, *Ki64, *f;
   float *A32, *K32;
+  float *s16A, *s16K;       // stencil coefficients of a box interior (FP32 systems), or nullptr
   void *minvA, *minvK;
   void *XA, *RA, *PA, *QA, *XK, *RK, *PK, *QK;
   double *XA64, *XK64;
@@ -661,6 +670,7 @@ struct Slot {
   uint16_t *Xh, *Xl, *Yh, *Yl;   // BF16 split (transposed) X_C and K_i X_C, MB x kpV
   int kpV, MB;                   // MB = roundup(M, 128): rows of the split operands
   // randomized variant (ls > 0 sketch columns, at most 64)
+  bool box;                      // the plane-streaming SpMM serves this request's systems
   int ls, rk;                    // sketch columns; directions kept by the K_i-orthonormalisation
   double *Fd;                    // dense FP64 right-hand sides of the A solves, nI x ldA
   double *q0v;                   // zero-boundary load solution on V_i
@@ -694,6 +704,8 @@ static void slot_shape(mor_ctx* c, Slot& q) {
   q.nconv = std::max(1, std::min(s - 1, q.rank > 0 ? q.rank + 2 : 1));
   q.fp32 = q.prec != MOR_FP64;
   q.refine = q.prec == MOR_FP32_REFINE || q.prec == MOR_BF16_SPLIT;
+  q.box = q.fp32 && c->opts.box_spmm >= 0 && c->opts.spmm_kind != 2 && !h.smap.empty() && q.d != nullptr &&
+          q.d->smap != nullptr;
   const int nblk = (int)h.bp.size() - 1;
   q.nc = c->opts.coarse ? (nblk + kCoarseAgg - 1) / kCoarseAgg : 0;
   q.MPc = (int)rup(std::max(q.nc, 1), 64);
@@ -711,6 +723,9 @@ static bool slot_layout(Slot& q, Take tk) {
   q.f = (double*)tk(8 * (size_t)h.nL);
   q.A32 = q.fp32 ? (float*)tk(4 * nnz) : nullptr;
   q.K32 = q.fp32 ? (float*)tk(4 * nnz) : nullptr;
+  const bool box = q.fp32 && q.box;
+  q.s16A = box ? (float*)tk(4 * (size_t)kStencil * h.nI) : nullptr;
+  q.s16K = box ? (float*)tk(4 * (size_t)kStencil * h.nI) : nullptr;
   q.minvA = tk(elt * h.nI * 8); q.minvK = tk(elt * h.nI * 8);
   q.XA = tk(elt * h.nI * q.ldA); q.RA = tk(elt * h.nI * q.ldA);
   q.PA = tk(elt * h.nI * q.ldA); q.QA = tk(elt * h.nI * q.ldA);
@@ -827,11 +842,12 @@ struct Req {
 
 struct Launch {
   std::vector<SysRun*> sys;
-  int4 *sp = nullptr, *bk = nullptr, *hs = nullptr;
-  int nsp = 0, nbk = 0, nhs = 0;
+  int4 *sp = nullptr, *bk = nullptr, *hs = nullptr, *bx = nullptr;
+  int nsp = 0, nbk = 0, nhs = 0, nbx = 0;
   int2* cb = nullptr;
   int ncb = 0;
-  double spmm_bytes = 0;
+  double spmm_bytes = 0;     // algorithmic bytes of the general (halo or row-tile) SpMM launch
+  double box_bytes = 0;      // ... and of the box-interior launch
   double stream_bytes = 0;   // update + direction: 8 block-vector elements per entry
   GemmDesc* gd = nullptr;    // two-level preconditioner: A_c^-1 (P^T r) of every coarse system
   int4* gt = nullptr;
@@ -956,11 +972,13 @@ static int engine_upload(mor_ctx* c, MorEngine& e, Launch& L) {
   }
   e.up_ok = false;
   L.spmm_bytes = 0;
+  L.box_bytes = 0;
   L.stream_bytes = 0;
   for (int i = 0; i < n; ++i) L.stream_bytes += 8.0 * e.elt * (double)hs[i].nI * hs[i].ncols;
-  for (int i = 0; i < n; ++i) {
+  for (int i = 0; i < n; ++i) {   // the matrix once, P read once, Q written once
     const CgSys& S = hs[i];
-    L.spmm_bytes += (double)L.sys[i]->nnzII * (4.0 + e.elt) + 4.0 * (S.nI + 1) + 2.0 * e.elt * (double)S.nI * S.ncols;
+    const double b = (double)L.sys[i]->nnzII * (4.0 + e.elt) + 4.0 * (S.nI + 1) + 2.0 * e.elt * (double)S.nI * S.ncols;
+    (S.s16 != nullptr ? L.box_bytes : L.spmm_bytes) += b;
   }
   for (int i = 0; i < n; ++i) {
     const CgSys& S = hs[i];
@@ -977,12 +995,24 @@ static int engine_upload(mor_ctx* c, MorEngine& e, Launch& L) {
   if (e.sp.halo) {
     const int gw = (e.sp.cwb / e.elt) * e.sp.g;   // columns per slice group
     for (int i = 0; i < n; ++i) {
+      if (hs[i].s16 != nullptr) continue;   // served by the box kernel
       const int nt = L.sys[i]->nhtile;
       for (int c0 = 0; c0 < hs[i].ld; c0 += gw)
         for (int h = 0; h < nt; ++h) t.push_back(make_int4(i, h, c0, c0 + gw));
     }
   }
   L.nhs = (int)t.size() - L.nsp - L.nbk;
+  // box interiors: (system, 32-column slice, footprint row, footprint column), the footprint
+  // column fastest so that neighbouring footprints of one slice run together on one XCD
+  for (int i = 0; i < n; ++i) {
+    const CgSys& S = hs[i];
+    if (S.s16 == nullptr) continue;
+    const int ntx = (S.bx + 7) / 8, nty = (S.by + 7) / 8;
+    for (int c0 = 0; c0 < S.ld; c0 += 32)
+      for (int ty = 0; ty < nty; ++ty)
+        for (int tx = 0; tx < ntx; ++tx) t.push_back(make_int4(i, tx | (ty << 16), c0, 0));
+  }
+  L.nbx = (int)t.size() - L.nsp - L.nbk - L.nhs;
   for (int i = 0; i < n; ++i)
     for (int c0 = 0; c0 < hs[i].ld; c0 += 256) cb.push_back(make_int2(i, c0));
   L.ncb = (int)cb.size();
@@ -1009,6 +1039,7 @@ static int engine_upload(mor_ctx* c, MorEngine& e, Launch& L) {
   L.sp = e.d_tiles;
   L.bk = e.d_tiles + L.nsp;
   L.hs = e.d_tiles + L.nsp + L.nbk;
+  L.bx = e.d_tiles + L.nsp + L.nbk + L.nhs;
   L.cb = e.d_cb;
   L.gd = e.d_gd;
   L.gt = e.d_gt;
@@ -1204,6 +1235,10 @@ static int engine_admit(mor_ctx* c, MorEngine& e) {
       launch_to_f32(q.A64, q.A32, h.rp[h.nL], st);
       launch_to_f32(q.K64, q.K32, h.rp[h.nL], st);
     }
+    if (q.s16A) {
+      launch_box_coeffs(q.d->spos, q.A64, h.nI, q.s16A, st);
+      launch_box_coeffs(q.d->spos, q.K64, h.nI, q.s16K, st);
+    }
     launch_block_inv<T>(q.d->rp, q.d->col, q.A64, q.d->bp, nblk, q.minvA, st);
     launch_block_inv<T>(q.d->rp, q.d->col, q.K64, q.d->bp, nblk, q.minvK, st);
     int nnzII = 0;
@@ -1239,6 +1274,11 @@ static int engine_admit(mor_ctx* c, MorEngine& e) {
       S.hpp = q.d->hpp;
       S.hself = q.d->hself;
       R.nhtile = (int)h.htile.size() / 4;
+      if (q.s16A) {
+        S.s16 = w == 0 ? q.s16A : q.s16K;
+        S.smap = q.d->smap;
+        S.bx = h.bx; S.by = h.by; S.bz = h.bz;
+      }
       double* cs = q.colst[w];
       const int ld = S.ld;
       S.pq = cs; S.rz = cs + ld; S.rznew = cs + 2 * ld; S.rz0 = cs + 3 * ld; S.rzF = cs + 4 * ld;
@@ -1283,6 +1323,7 @@ static int engine_chunk(mor_ctx* c, MorEngine& e) {
       launch_cg_spmm_halo<T>(e.d_sys, La.hs, La.nhs, c->halo_cap, e.sp.cwb, s);
     else
       launch_cg_spmm<T>(e.d_sys, La.sp, La.nsp, e.sp.rb, e.sp.v, s);
+    launch_cg_spmm_box(e.d_sys, La.bx, La.nbx, s);
     launch_cg_alpha(e.d_sys, La.cb, La.ncb, s);
     launch_cg_update<T>(e.d_sys, La.bk, La.nbk, e.stm.rb, e.stm.v, s);
     if (La.ngt) {   // two-level preconditioner: coarse solve and its part of r'M^-1 r
@@ -1301,7 +1342,7 @@ static int engine_chunk(mor_ctx* c, MorEngine& e) {
                                       (int64_t)(intptr_t)e.d_cb, La.nsp, La.nbk, La.nhs, La.ncb, chunk,
                                       (int64_t)(intptr_t)La.hs, (int64_t)(intptr_t)La.bk, (int64_t)(intptr_t)La.cb,
                                       (int64_t)c->halo_cap, (int64_t)(intptr_t)La.gd, (int64_t)(intptr_t)La.gt,
-                                      La.ngt};
+                                      La.ngt, (int64_t)(intptr_t)La.bx, La.nbx};
     if (!e.gexec || e.g_sys != La.sys || e.g_key != key) {
       if (e.gexec) HIPCHK(hipGraphExecDestroy(e.gexec));
       e.gexec = nullptr;
@@ -1319,16 +1360,22 @@ static int engine_chunk(mor_ctx* c, MorEngine& e) {
       e.g_sys = La.sys;
       e.g_key = key;
     }
-    ScopedTimer tm(c, "cg_graph", chunk * (La.spmm_bytes + La.stream_bytes));
+    ScopedTimer tm(c, "cg_graph", chunk * (La.spmm_bytes + La.box_bytes + La.stream_bytes));
     HIPCHK(hipGraphLaunch(e.gexec, st));
   }
   for (int k = 0; k < (c->opts.use_graph ? 0 : chunk); ++k) {
     {
-      ScopedTimer tm(c, "spmm", La.spmm_bytes);
-      if (e.sp.halo)
-        launch_cg_spmm_halo<T>(e.d_sys, La.hs, La.nhs, c->halo_cap, e.sp.cwb, st);
-      else
-        launch_cg_spmm<T>(e.d_sys, La.sp, La.nsp, e.sp.rb, e.sp.v, st);
+      if (!e.sp.halo || La.nhs > 0) {
+        ScopedTimer tm(c, "spmm", La.spmm_bytes);
+        if (e.sp.halo)
+          launch_cg_spmm_halo<T>(e.d_sys, La.hs, La.nhs, c->halo_cap, e.sp.cwb, st);
+        else
+          launch_cg_spmm<T>(e.d_sys, La.sp, La.nsp, e.sp.rb, e.sp.v, st);
+      }
+    }
+    if (La.nbx > 0) {
+      ScopedTimer tm(c, "spmm_box", La.box_bytes);
+      launch_cg_spmm_box(e.d_sys, La.bx, La.nbx, st);
     }
     launch_cg_alpha(e.d_sys, La.cb, La.ncb, st);
     {
@@ -1781,9 +1828,15 @@ static int small_eig(mor_ctx* c, Arena& ar, const std::vector<Slot*>& sl, const 
 // if set, else the accuracy the basis was computed to, below which a block's directions are
 // noise: the solves' target refine_rtol (at least 1e-10) for FP64 and FP64-refined bases, 1e-6
 // where FP32 solves or the BF16 Gram set it.
+// Relative eigenvalue below which the basis update drops a direction of the stitched block: only
+// numerically dependent combinations of the stitched columns (near the rounding level of an FP64
+// eigendecomposition), whatever the precision the basis came from.  A small eigenvalue measures
+// a direction's energy per unit coefficient, not its accuracy: on high-contrast coefficients the
+// blocks hold directions near 1e-8 of the largest that carry a large share of the solution.
 static double drop_of(const mor_ctx* c, int prec) {
+  (void)prec;
   if (c->opts.update_drop > 0) return c->opts.update_drop;
-  return (prec == MOR_FP32 || prec == MOR_BF16_SPLIT) ? 1e-6 : std::max(1e-10, c->opts.refine_rtol);
+  return 1e-10;
 }
 
 // The basis update of Section 6, step 2, which diagonalises the diagonal blocks of the reduced
@@ -2165,6 +2218,15 @@ static int dense_stage(mor_ctx* c, std::vector<Live*>& done) {
     std::vector<double> sg(q.s);
     for (int j = 0; j < q.s; ++j) sg[j] = std::sqrt(std::max(hth[(size_t)i * 64 + j], 0.0));
     q.k_eff = truncation_rank(sg, q.rank, q.tol, q.s - 1);
+    // the truncation must end inside the subspace (the kept modes and the next one resolved);
+    // a tolerance below more singular values than that (or a cluster reaching its end) is
+    // refused rather than cut short
+    if (q.s < q.M && truncation_rank(sg, q.rank, q.tol, q.s) >= q.s - 1 && !done[i]->status) {
+      done[i]->status = MOR_EINVAL;
+      g_err = "subdomain " + std::to_string(q.sd) + ": the truncation keeps " + std::to_string(q.s - 1) +
+              " or more modes, beyond what the " + std::to_string(q.s) +
+              "-vector eigensolver subspace resolves (raise the tolerance or lower the rank)";
+    }
     SubResult& R = c->res[q.sd];
     R.sigma = sg;
     R.k_eff = q.k_eff;
@@ -2256,6 +2318,8 @@ extern "C" int mor_local_basis_batch(mor_ctx* c, int32_t n, const int32_t* sds, 
     seen[sd] = 1;
     const double tol = tols ? tols[i] : 0.0;
     if (ranks[i] <= 0 && !(tol > 0.0)) return fail(MOR_EINVAL, "need rank > 0 or tol > 0");
+    if (ranks[i] > kMaxRank) return fail(MOR_EINVAL, "rank above " + std::to_string(kMaxRank) +
+                                                   " (the eigensolver subspace holds 64 vectors)");
   }
   std::vector<uint64_t> ids(n);
   for (int i = 0; i < n; ++i) ids[i] = enqueue(c, sds[i], ranks[i], tols ? tols[i] : 0.0, c->opts.precision);
@@ -2295,6 +2359,8 @@ extern "C" int mor_local_basis_sketched(mor_ctx* c, int32_t n, const int32_t* sd
     seen[sd] = 1;
     const double tol = tols ? tols[i] : 0.0;
     if (ranks[i] <= 0 && !(tol > 0.0)) return fail(MOR_EINVAL, "need rank > 0 or tol > 0");
+    if (ranks[i] > kMaxRank) return fail(MOR_EINVAL, "rank above " + std::to_string(kMaxRank) +
+                                                   " (the eigensolver subspace holds 64 vectors)");
     if (!omega[i]) return fail(MOR_EINVAL, "null sketch");
     if (c->subs[sd].nB < 1) return fail(MOR_EINVAL, "subdomain without interface nodes");
   }
@@ -2343,6 +2409,8 @@ extern "C" int mor_submit(mor_ctx* c, int32_t sd, int32_t rank, double tol, int3
   if (c->opts.host_only) return fail(MOR_ESTATE, "context was created host_only");
   if (sd < 0 || sd >= (int)c->subs.size()) return fail(MOR_EINVAL, "subdomain id out of range");
   if (rank <= 0 && !(tol > 0.0)) return fail(MOR_EINVAL, "need rank > 0 or tol > 0");
+  if (rank > kMaxRank) return fail(MOR_EINVAL, "rank above " + std::to_string(kMaxRank) +
+                                                 " (the eigensolver subspace holds 64 vectors)");
   if (precision < MOR_FP64 || precision > MOR_BF16_SPLIT) return fail(MOR_EINVAL, "unknown precision");
   *ticket = enqueue(c, sd, rank, tol, precision);
   return MOR_OK;
@@ -2636,6 +2704,7 @@ extern "C" int mor_project(mor_ctx* c) {
     dfree(c, A0);
   }
   HIPCHK(hipStreamSynchronize(st));
+  c->x_host.assign((size_t)c->n_red, 0.0);
   c->projected = 1;
   return MOR_OK;
   MOR_CATCH
@@ -2665,71 +2734,91 @@ static int reconstruct_solution(mor_ctx* c, double* u_out) {
   return MOR_OK;
 }
 
+// Reduced-solve vectors carved from one buffer: x, r, z, p, q, D^-1 (rup(n, 64) doubles each),
+// the scalar rings and the stop state.
+static size_t pcg_bytes(int64_t n) { return 8 * 6 * (size_t)rup(std::max<int64_t>(n, 1), 64) + 8 * 16 + 4 * 16 + 1024; }
+
+static RpcgDev pcg_layout(mor_ctx* c, char* buf, size_t bytes, int n) {
+  Arena ar{buf, bytes, 0};
+  RpcgDev d{};
+  d.val = c->d_slab;
+  d.ccol = c->d_ccol;
+  d.rs = c->d_rs;
+  d.rwc = c->d_rwc;
+  d.rdiag = c->d_rdiag;
+  d.b = c->d_bt;
+  d.bstride = 64;
+  d.block = c->opts.reduced_solver == 2;
+  d.bmv = c->d_bmv;
+  d.rbm = c->d_rbm;
+  d.rbd = c->d_rbd;
+  double* v[6];
+  for (auto& q : v) q = (double*)ar.take(8 * (size_t)rup(n, 64));
+  d.x = v[0]; d.r = v[1]; d.z = v[2]; d.p = v[3]; d.q = v[4]; d.dinv = v[5];
+  d.sc = (double*)ar.take(8 * 16);
+  d.state = (int*)ar.take(4 * 16);
+  return d;
+}
+
 // The reduced system by conjugate gradients with the diagonal preconditioner on the
 // block-row slabs (end of Section 6 step 3; Section 7), from x = 0.  The iterations run in
-// chunks of launches; between chunks the host reads the stop flag.
-static int solve_pcg(mor_ctx* c, double* u_out, int64_t* n_reduced_out) {
+// chunks of launches; between chunks the host reads the stop flag.  On success x is left in
+// d.x on the device and copied into c->x_host (sized n by mor_project).
+static int pcg_iterate(mor_ctx* c, const RpcgDev& d, int n) {
   hipStream_t st = c->st;
+  c->solve_iters = 0;
+  c->solve_relres = 0.0;
+  const double tol2 = c->opts.reduced_rtol * c->opts.reduced_rtol;
+  const int chunk = 32, cap = c->opts.reduced_max_iter;
+  launch_rpcg_setup(d, n, st);
+  int hs[4] = {0, 0, 0, 0};
+  for (int it = 0; it < cap;) {
+    const int m = std::min(chunk, cap - it);
+    for (int k = 0; k < m; ++k) launch_rpcg_iteration(d, n, it + k, tol2, st);
+    it += m;
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(hs, d.state, sizeof(hs), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (hs[0] || hs[2]) break;
+  }
+  if (hs[2] == 2) return fail(MOR_EDEVICE, "reduced matrix has a diagonal entry <= 0");
+  if (hs[2] == 1)
+    return fail(MOR_EDEVICE, "reduced matrix is not positive definite (p'Ap <= 0 at iteration " +
+                                 std::to_string(hs[1] + 1) + ")");
+  double sc[11];
+  HIPCHK(hipMemcpyAsync(sc, d.sc, sizeof(sc), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  c->solve_iters = hs[1];
+  const int last = hs[1] > 0 ? (hs[1] - 1) % 3 : 2;
+  if (d.block)
+    c->solve_relres = sc[10] > 0 ? std::sqrt(std::max(0.0, sc[3 + last]) / sc[10]) : 0.0;
+  else
+    c->solve_relres = sc[9] > 0 ? std::sqrt(std::max(0.0, sc[6 + last]) / sc[9]) : 0.0;
+  if (!hs[0])
+    return fail(MOR_ENOTCONV, "reduced conjugate gradients: ||r||/||b|| = " + std::to_string(c->solve_relres) +
+                                  " after " + std::to_string(hs[1]) + " iterations");
+  if ((int64_t)c->x_host.size() != (int64_t)n) return fail(MOR_ESTATE, "reduced solution storage not sized");
+  HIPCHK(hipMemcpyAsync(c->x_host.data(), d.x, 8 * (size_t)n, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  return MOR_OK;
+}
+
+static int solve_pcg(mor_ctx* c, double* u_out, int64_t* n_reduced_out) {
   const int n = (int)c->n_red;
-  c->x_host.assign(n, 0.0);
+  std::fill(c->x_host.begin(), c->x_host.end(), 0.0);
   c->solve_iters = 0;
   c->solve_relres = 0.0;
   if (n > 0) {
-    const size_t bytes = 8 * 6 * (size_t)rup(n, 64) + 8 * 16 + 4 * 16 + 1024;
+    const size_t bytes = pcg_bytes(n);
     char* buf = (char*)dalloc(c, bytes);
     if (!buf) return fail(MOR_ENOMEM, "device allocation failed (reduced solve)");
     struct G { mor_ctx* c; void* p; ~G() { (void)hipStreamSynchronize(c->st); dfree(c, p); } } guard{c, buf};
-    Arena ar{buf, bytes, 0};
-    RpcgDev d{};
-    d.val = c->d_slab;
-    d.ccol = c->d_ccol;
-    d.rs = c->d_rs;
-    d.rwc = c->d_rwc;
-    d.rdiag = c->d_rdiag;
-    d.b = c->d_bt;
-    d.bstride = 64;
-    d.block = c->opts.reduced_solver == 2;
-    d.bmv = c->d_bmv;
-    d.rbm = c->d_rbm;
-    d.rbd = c->d_rbd;
-    double* v[6];
-    for (auto& p : v) p = (double*)ar.take(8 * (size_t)rup(n, 64));
-    d.x = v[0]; d.r = v[1]; d.z = v[2]; d.p = v[3]; d.q = v[4]; d.dinv = v[5];
-    d.sc = (double*)ar.take(8 * 16);
-    d.state = (int*)ar.take(4 * 16);
+    const RpcgDev d = pcg_layout(c, buf, bytes, n);
     if (!d.state) return fail(MOR_ENOMEM, "arena exhausted (reduced solve)");
-    const double nnz = (double)c->slab_len;
     ScopedTimer tm(c, "solve", 0.0);
-    const double tol2 = c->opts.reduced_rtol * c->opts.reduced_rtol;
-    const int chunk = 32, cap = c->opts.reduced_max_iter;
-    launch_rpcg_setup(d, n, st);
-    int hs[4] = {0, 0, 0, 0};
-    for (int it = 0; it < cap;) {
-      const int m = std::min(chunk, cap - it);
-      for (int k = 0; k < m; ++k) launch_rpcg_iteration(d, n, it + k, tol2, st);
-      it += m;
-      HIPCHK(hipGetLastError());
-      HIPCHK(hipMemcpyAsync(hs, d.state, sizeof(hs), hipMemcpyDeviceToHost, st));
-      HIPCHK(hipStreamSynchronize(st));
-      if (hs[0] || hs[2]) break;
-    }
-    tm.work = 2.0 * nnz * hs[1];
-    if (hs[2] == 2) return fail(MOR_EDEVICE, "reduced matrix has a diagonal entry <= 0");
-    if (hs[2] == 1)
-      return fail(MOR_EDEVICE, "reduced matrix is not positive definite (p'Ap <= 0 at iteration " +
-                                   std::to_string(hs[1] + 1) + ")");
-    double sc[11];
-    HIPCHK(hipMemcpy(sc, d.sc, sizeof(sc), hipMemcpyDeviceToHost));
-    c->solve_iters = hs[1];
-    const int last = hs[1] > 0 ? (hs[1] - 1) % 3 : 2;
-    if (d.block)
-      c->solve_relres = sc[10] > 0 ? std::sqrt(std::max(0.0, sc[3 + last]) / sc[10]) : 0.0;
-    else
-      c->solve_relres = sc[9] > 0 ? std::sqrt(std::max(0.0, sc[6 + last]) / sc[9]) : 0.0;
-    if (!hs[0])
-      return fail(MOR_ENOTCONV, "reduced conjugate gradients: ||r||/||b|| = " + std::to_string(c->solve_relres) +
-                                    " after " + std::to_string(hs[1]) + " iterations");
-    HIPCHK(hipMemcpy(c->x_host.data(), d.x, 8 * (size_t)n, hipMemcpyDeviceToHost));
+    const int rc = pcg_iterate(c, d, n);
+    tm.work = 2.0 * (double)c->slab_len * c->solve_iters;
+    if (rc) return rc;
   }
   if (int rc = reconstruct_solution(c, u_out)) return rc;
   if (n_reduced_out) *n_reduced_out = c->n_red;
@@ -2789,7 +2878,7 @@ extern "C" int mor_solve(mor_ctx* c, double* u_out, int64_t* n_reduced_out) {
   std::vector<double> xs((size_t)MP * 64);
   HIPCHK(hipMemcpyAsync(xs.data(), xsol, 8 * xs.size(), hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
-  c->x_host.assign(c->n_red, 0.0);
+  c->x_host.assign((size_t)c->n_red, 0.0);
   for (int64_t i = 0; i < c->n_red; ++i) c->x_host[i] = xs[(size_t)i * 64];
   if (int rc = reconstruct_solution(c, u_out)) return rc;
   if (n_reduced_out) *n_reduced_out = c->n_red;

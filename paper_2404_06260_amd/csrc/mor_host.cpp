@@ -9,6 +9,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <climits>
 #include <cstring>
 #include <numeric>
 
@@ -22,6 +23,134 @@ static double tet_det(const HostMesh& m, int64_t t) {
     for (int d = 0; d < 3; ++d) e[a][d] = m.xyz[3 * (int64_t)v[a + 1] + d] - x0[d];
   return e[0][0] * (e[1][1] * e[2][2] - e[1][2] * e[2][1]) - e[0][1] * (e[1][0] * e[2][2] - e[1][2] * e[2][0]) +
          e[0][2] * (e[1][0] * e[2][1] - e[1][1] * e[2][0]);
+}
+
+// Kuhn-lattice detection.  The grid spacing per axis: a first guess h0 is the median of each
+// edge's largest coordinate difference; edge components above h0 / 2 are then single grid steps
+// (plus noise from node jitter), whose median estimates the spacing, which is finally rounded so
+// that the node extent along the axis is a whole number of steps.  Each node takes the nearest
+// grid point.  The structure is then verified, not assumed: every tet edge must join grid points
+// whose offset is a Kuhn offset and no two nodes may share a grid point.  Any failure leaves
+// m.lattice false.
+static void detect_lattice(HostMesh& m) {
+  m.lattice = false;
+  m.lat.clear();
+  if (m.n_nodes < 8) return;
+  static const int E[6][2] = {{0, 1}, {0, 2}, {0, 3}, {1, 2}, {1, 3}, {2, 3}};
+  const int64_t stride = std::max<int64_t>(1, m.n_tets / 200000);
+  auto edge_diff = [&](int64_t t, const int* ed, double* d) {
+    const double* a = &m.xyz[3 * (int64_t)m.tets[4 * t + ed[0]]];
+    const double* b = &m.xyz[3 * (int64_t)m.tets[4 * t + ed[1]]];
+    for (int ax = 0; ax < 3; ++ax) d[ax] = std::fabs(b[ax] - a[ax]);
+  };
+  std::vector<double> big;
+  for (int64_t t = 0; t < m.n_tets; t += stride)
+    for (const auto& ed : E) {
+      double d[3];
+      edge_diff(t, ed, d);
+      big.push_back(std::max(d[0], std::max(d[1], d[2])));
+    }
+  if (big.size() < 16) return;
+  std::nth_element(big.begin(), big.begin() + big.size() / 2, big.end());
+  const double h0 = big[big.size() / 2];
+  if (!(h0 > 0.0)) return;
+  std::vector<double> len[3];
+  for (int64_t t = 0; t < m.n_tets; t += stride)
+    for (const auto& ed : E) {
+      double d[3];
+      edge_diff(t, ed, d);
+      for (int ax = 0; ax < 3; ++ax)
+        if (d[ax] > 0.5 * h0) len[ax].push_back(d[ax]);
+    }
+  double h[3], lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+  for (int64_t v = 0; v < m.n_nodes; ++v)
+    for (int ax = 0; ax < 3; ++ax) {
+      lo[ax] = std::min(lo[ax], m.xyz[3 * v + ax]);
+      hi[ax] = std::max(hi[ax], m.xyz[3 * v + ax]);
+    }
+  for (int ax = 0; ax < 3; ++ax) {
+    if (len[ax].size() < 16) return;
+    std::nth_element(len[ax].begin(), len[ax].begin() + len[ax].size() / 2, len[ax].end());
+    const double he = len[ax][len[ax].size() / 2];
+    const double steps = std::nearbyint((hi[ax] - lo[ax]) / he);
+    if (!(he > 0.0) || !(steps >= 1.0)) return;
+    h[ax] = (hi[ax] - lo[ax]) / steps;
+  }
+  std::vector<int32_t> lat(3 * m.n_nodes);
+  for (int64_t v = 0; v < m.n_nodes; ++v)
+    for (int ax = 0; ax < 3; ++ax) {
+      const double q = std::nearbyint((m.xyz[3 * v + ax] - lo[ax]) / h[ax]);
+      if (!(q >= 0.0 && q < 2097152.0)) return;   // 21 bits per axis for the uniqueness key
+      lat[3 * v + ax] = (int32_t)q;
+    }
+  for (int64_t t = 0; t < m.n_tets; ++t)
+    for (const auto& ed : E) {
+      const int32_t* a = &lat[3 * (int64_t)m.tets[4 * t + ed[0]]];
+      const int32_t* b = &lat[3 * (int64_t)m.tets[4 * t + ed[1]]];
+      int pos = 0, neg = 0;
+      for (int ax = 0; ax < 3; ++ax) {
+        const int d = b[ax] - a[ax];
+        if (d < -1 || d > 1) return;
+        pos += d > 0;
+        neg += d < 0;
+      }
+      if ((pos > 0) == (neg > 0)) return;   // zero, or a mixed-sign offset
+    }
+  std::vector<uint64_t> key(m.n_nodes);
+  for (int64_t v = 0; v < m.n_nodes; ++v)
+    key[v] = ((uint64_t)lat[3 * v] << 42) | ((uint64_t)lat[3 * v + 1] << 21) | (uint64_t)lat[3 * v + 2];
+  std::sort(key.begin(), key.end());
+  if (std::adjacent_find(key.begin(), key.end()) != key.end()) return;
+  m.lat.swap(lat);
+  m.lattice = true;
+}
+
+// Box form of a subdomain's interior on a Kuhn lattice (see HostSub): empty unless the I rows
+// fill a box of grid points and every II entry is a stencil slot.
+static void build_box(const HostMesh& m, HostSub& s) {
+  s.bx = s.by = s.bz = 0;
+  s.smap.clear();
+  s.spos.clear();
+  if (!m.lattice || s.nI == 0) return;
+  int lo[3] = {INT32_MAX, INT32_MAX, INT32_MAX}, hi[3] = {-1, -1, -1};
+  for (int r = 0; r < s.nI; ++r)
+    for (int ax = 0; ax < 3; ++ax) {
+      const int q = m.lat[3 * (int64_t)s.nodes[r] + ax];
+      lo[ax] = std::min(lo[ax], q);
+      hi[ax] = std::max(hi[ax], q);
+    }
+  const int64_t ext[3] = {hi[0] - lo[0] + 1, hi[1] - lo[1] + 1, hi[2] - lo[2] + 1};
+  if (ext[0] * ext[1] * ext[2] != (int64_t)s.nI) return;
+  std::vector<int32_t> smap(s.nI, -1);
+  auto cell = [&](int r, int* q) {
+    for (int ax = 0; ax < 3; ++ax) q[ax] = m.lat[3 * (int64_t)s.nodes[r] + ax] - lo[ax];
+  };
+  for (int r = 0; r < s.nI; ++r) {
+    int q[3];
+    cell(r, q);
+    int32_t& slot = smap[((int64_t)q[2] * ext[1] + q[1]) * ext[0] + q[0]];
+    if (slot >= 0) return;
+    slot = r;
+  }
+  std::vector<int32_t> spos((size_t)kStencil * s.nI, -1);
+  for (int r = 0; r < s.nI; ++r) {
+    int q[3];
+    cell(r, q);
+    for (int e = s.rp[r]; e < s.ii_end[r]; ++e) {
+      int w[3];
+      cell(s.col[e], w);
+      int k = -1;
+      for (int sl = 0; sl < 15 && k < 0; ++sl)
+        if (w[0] - q[0] == kKuhnOff[sl][0] && w[1] - q[1] == kKuhnOff[sl][1] && w[2] - q[2] == kKuhnOff[sl][2]) k = sl;
+      if (k < 0 || spos[(size_t)kStencil * r + k] >= 0) return;
+      spos[(size_t)kStencil * r + k] = e;
+    }
+  }
+  s.bx = (int)ext[0];
+  s.by = (int)ext[1];
+  s.bz = (int)ext[2];
+  s.smap.swap(smap);
+  s.spos.swap(spos);
 }
 
 int build_mesh(HostMesh& m, std::string& err) {
@@ -57,6 +186,7 @@ int build_mesh(HostMesh& m, std::string& err) {
     for (int a = 0; a < 4; ++a) used[m.tets[4 * t + a]] |= (1ull << c);
   }
   m.ncolours = nc;
+  detect_lattice(m);
   return 0;
 }
 
@@ -393,6 +523,7 @@ int build_sub(const HostMesh& m, const int32_t* ext, const uint8_t* in_core, int
     s.ii_end[r] = (int32_t)(std::lower_bound(b, e, s.nI) - s.col.data());
   }
   if (build_halo_tiles(s, halo_cap, err)) return -1;
+  build_box(m, s);
   tet_pattern(s.ltet, &s.core, s.nV, s.rpV, s.colV);
   for (int32_t c : s.colV)
     if (c >= s.nV) {

@@ -27,7 +27,19 @@ struct HostMesh {
   std::vector<int32_t> star;    // tets per node
   std::vector<uint8_t> colour;  // greedy element colouring: tets sharing a node differ
   int ncolours = 0;
+  // Kuhn lattice: when every node sits near a point of a regular grid (spacing estimated from
+  // the axis-aligned edges) and every edge joins two grid points whose offset lies in
+  // {0,1}^3 or {0,-1}^3, lat holds each node's integer grid coordinates (3 per node)
+  bool lattice = false;
+  std::vector<int32_t> lat;
 };
+
+// The 15-point stencil of a Kuhn lattice: slot 0 the node itself, slots 1..7 the forward
+// offsets, slots 8..14 their negatives; slot 15 pads a row to 16 entries.
+constexpr int kStencil = 16;
+constexpr int kKuhnOff[15][3] = {{0, 0, 0}, {1, 0, 0}, {0, 1, 0}, {0, 0, 1}, {1, 1, 0}, {1, 0, 1}, {0, 1, 1},
+                                 {1, 1, 1}, {-1, 0, 0}, {0, -1, 0}, {0, 0, -1}, {-1, -1, 0}, {-1, 0, -1},
+                                 {0, -1, -1}, {-1, -1, -1}};
 
 // Local numbering of one subdomain: [P | V\P | I\V | B], each part sorted by global id.
 struct HostSub {
@@ -47,6 +59,11 @@ struct HostSub {
   std::vector<uint16_t> hpp;               // padded II entries: the column's position in the tile halo
   std::vector<uint16_t> hself;             // per I row: the row's own position in its tile halo
   std::vector<int32_t> rcb;                // per I row: its coarse block (aggregate / kCoarseAgg)
+  // Box form of the interior (on a Kuhn lattice, when I is a full box of grid points):
+  // extents nx, ny, nz; smap[(z*ny + y)*nx + x] = local row of the grid point (x, y, z) of the
+  // box; spos[16 r + s] = CSR entry of row r's stencil slot s in the II block, or -1.
+  int bx = 0, by = 0, bz = 0;
+  std::vector<int32_t> smap, spos;
 };
 
 // omega_0: the elements in two or more subdomains, with A_0's pattern over their free nodes.

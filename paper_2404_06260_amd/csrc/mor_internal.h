@@ -69,6 +69,11 @@ struct CgSys {
   double* rc;          // P^T r: nc x ld (FP64), summed by the update / start kernels, cleared after use
   double* ec;          // A_c^-1 P^T r: nc x ld (FP64)
   int nc;
+  // box form of the interior (FP32 systems on a Kuhn lattice; s16 == nullptr: none): stencil
+  // coefficients (16 per row), the grid-point -> row map and the box extents
+  const float* s16;
+  const int* smap;
+  int bx, by, bz;
 };
 
 // ---------------------------------------------------------------------------------
@@ -130,6 +135,9 @@ template <typename T>
 void launch_cg_spmm(const CgSys* sys, const int4* tiles, int ntiles, int rb, int v, hipStream_t s);
 template <typename T>
 void launch_cg_spmm_halo(const CgSys* sys, const int4* tiles, int ntiles, int cap, int cwb, hipStream_t s);
+// box interiors (FP32): tiles (system, tx | ty << 16, first column of a 32-column slice, 0)
+void launch_cg_spmm_box(const CgSys* sys, const int4* tiles, int ntiles, hipStream_t s);
+void launch_box_coeffs(const int* spos, const double* val, int nI, float* s16, hipStream_t s);
 template <typename T>
 void launch_cg_residual64(const CgSys* sys, const int4* tiles, int ntiles, int rb, int v, hipStream_t s);
 template <typename T>

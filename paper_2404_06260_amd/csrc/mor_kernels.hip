@@ -486,6 +486,178 @@ __global__ __launch_bounds__(256) void k_cg_spmm_halo(const CgSys* __restrict__ 
   flush(cbeg + (cend - cbeg - 1) / CW * CW);
 }
 
+// Q = A_II P for a subdomain whose interior rows fill a box of a Kuhn lattice (FP32): a
+// plane-streaming stencil.  A workgroup owns an 8 x 8 footprint of the box in (x, y) and one
+// 128-byte column slice, and marches along z.  Three planes of P (the footprint with a one-point
+// ring, z-1, z, z+1) and two planes of stencil coefficients (16 per row, from the assembled
+// matrix) sit in LDS; the loads of planes z+2 and z+3 are in flight in registers while plane z
+// computes, and the grid-point -> row lookups run one plane ahead of those loads, so no load
+// waits on another.  Each P row of the box is fetched once per slice by the workgroup and shared
+// with the neighbouring footprints (consecutive workgroups on one XCD) through L2.  Grid points
+// outside the box (interface or Dirichlet nodes) read as zero, and their coefficients are zero.
+// Each thread owns one column and one footprint row of 8 points; per-column p'Q is summed over
+// the workgroup and added once.
+constexpr int kBoxF = 8;                     // footprint edge
+constexpr int kBoxH = kBoxF + 2;             // with the ring
+constexpr int kBoxRows = kBoxH * kBoxH;      // halo rows per plane
+constexpr int kBoxChunks = kBoxRows * 8;     // 16-byte chunks of one 128-byte slice per plane
+constexpr int kBoxLd = (kBoxChunks + 255) / 256;   // chunk loads per thread and plane
+
+struct BoxRows {    // one plane's row ids for this thread: its P chunks and its coefficient point
+  int r[kBoxLd];
+  int rc;
+};
+struct BoxPlane {   // one plane's loads in flight: P chunks, the coefficient chunk, its row
+  u32x4 pv[kBoxLd];
+  u32x4 cv;
+  int rc;
+};
+
+__device__ __forceinline__ int box_row(const CgSys& S, int x, int y, int z) {
+  if (x < 0 || y < 0 || z < 0 || x >= S.bx || y >= S.by || z >= S.bz) return -1;
+  return gld(S.smap + ((int64_t)z * S.by + y) * S.bx + x);
+}
+
+__device__ __forceinline__ void box_rows(const CgSys& S, int x0, int y0, int z, BoxRows& q) {
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int k = 0; k < kBoxLd; ++k) {
+    const int i = k * 256 + tid, hr = i >> 3;
+    q.r[k] = i < kBoxChunks ? box_row(S, x0 - 1 + hr % kBoxH, y0 - 1 + hr / kBoxH, z) : -1;
+  }
+  const int pt = tid >> 2;   // coefficient point of this thread: quarter tid % 4 of its 16 values
+  q.rc = box_row(S, x0 + (pt & 7), y0 + (pt >> 3), z);
+}
+
+__device__ __forceinline__ void box_issue(const CgSys& S, const float* __restrict__ P, int c0, const BoxRows& q,
+                                          BoxPlane& b) {
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int k = 0; k < kBoxLd; ++k) {
+    const int i = k * 256 + tid;
+    b.pv[k] = (u32x4){0u, 0u, 0u, 0u};
+    if (q.r[k] >= 0) b.pv[k] = *((const MOR_GLOBAL u32x4*)(P + (int64_t)q.r[k] * S.ld + c0 + (i & 7) * 4));
+  }
+  b.cv = (u32x4){0u, 0u, 0u, 0u};
+  if (q.rc >= 0) b.cv = *((const MOR_GLOBAL u32x4*)(S.s16 + (int64_t)q.rc * kStencil + (tid & 3) * 4));
+  b.rc = q.rc;
+}
+
+__device__ __forceinline__ void box_store(const BoxPlane& b, float (*pl)[32], float* cf, int* rid) {
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int k = 0; k < kBoxLd; ++k) {
+    const int i = k * 256 + tid;
+    if (i < kBoxChunks) *reinterpret_cast<u32x4*>(&pl[i >> 3][(i & 7) * 4]) = b.pv[k];
+  }
+  *reinterpret_cast<u32x4*>(&cf[tid * 4]) = b.cv;
+  if ((tid & 3) == 0) rid[tid >> 2] = b.rc;
+}
+
+__global__ __launch_bounds__(256) void k_cg_spmm_box(const CgSys* __restrict__ sys, const int4* __restrict__ tiles,
+                                                     int ntiles) {
+  __shared__ __attribute__((aligned(16))) float pl[3][kBoxRows][32];
+  __shared__ __attribute__((aligned(16))) float cf[2][kBoxF * kBoxF * kStencil];
+  __shared__ int rid[2][kBoxF * kBoxF];
+  __shared__ double red[8][32];
+  const int t = xcd_tile(blockIdx.x, ntiles);
+  if (t >= ntiles) return;
+  const int4 tl = tiles[t];
+  const CgSys& S = sys[tl.x];
+  const int x0 = (tl.y & 0xffff) * kBoxF, y0 = (tl.y >> 16) * kBoxF, c0 = tl.z;
+  const float* __restrict__ P = (const float*)S.P;
+  float* __restrict__ Q = (float*)S.Q;
+  const int ld = S.ld, nz = S.bz;
+  const int tid = threadIdx.x;
+  const int col = tid & 31, yy = tid >> 5;        // this thread: column c0 + col, footprint row yy
+  // P slot of plane z: (z + 3) % 3 (plane -1 is zeros); coefficient and row-id slot: z % 2
+  BoxRows q;
+  BoxPlane A, B;
+  box_rows(S, x0, y0, -1, q);
+  box_issue(S, P, c0, q, A);
+  box_store(A, pl[2], cf[1], rid[1]);
+  box_rows(S, x0, y0, 0, q);
+  box_issue(S, P, c0, q, A);
+  box_store(A, pl[0], cf[0], rid[0]);
+  box_rows(S, x0, y0, 1, q);
+  box_issue(S, P, c0, q, A);
+  box_store(A, pl[1], cf[1], rid[1]);
+  box_rows(S, x0, y0, 2, q);
+  box_issue(S, P, c0, q, A);
+  box_rows(S, x0, y0, 3, q);
+  box_issue(S, P, c0, q, B);
+  box_rows(S, x0, y0, 4, q);
+  __syncthreads();
+  double part = 0.0;
+  // one plane: Q rows of plane z from slots (lower, centre, upper); then plane z+2 from `nx`
+  // into the lower slot, the loads of plane z+4 (rows in q) into `nx`, and the rows of z+5
+  auto plane = [&](int z, BoxPlane& nx) {
+    const int sc = z % 3, su = (z + 1) % 3, sl = (z + 2) % 3, cs = z & 1;
+    const float* cfz = cf[cs];
+#pragma unroll
+    for (int x = 0; x < kBoxF; ++x) {
+      const int h = (yy + 1) * kBoxH + (x + 1);   // the point's halo position
+      const float* c = cfz + (yy * kBoxF + x) * kStencil;
+      float acc = c[0] * pl[sc][h][col];
+      acc += c[1] * pl[sc][h + 1][col];
+      acc += c[2] * pl[sc][h + kBoxH][col];
+      acc += c[3] * pl[su][h][col];
+      acc += c[4] * pl[sc][h + kBoxH + 1][col];
+      acc += c[5] * pl[su][h + 1][col];
+      acc += c[6] * pl[su][h + kBoxH][col];
+      acc += c[7] * pl[su][h + kBoxH + 1][col];
+      acc += c[8] * pl[sc][h - 1][col];
+      acc += c[9] * pl[sc][h - kBoxH][col];
+      acc += c[10] * pl[sl][h][col];
+      acc += c[11] * pl[sc][h - kBoxH - 1][col];
+      acc += c[12] * pl[sl][h - 1][col];
+      acc += c[13] * pl[sl][h - kBoxH][col];
+      acc += c[14] * pl[sl][h - kBoxH - 1][col];
+      const int r = rid[cs][yy * kBoxF + x];   // -1 outside the box
+      if (r >= 0) {
+        st_nt(Q + (int64_t)r * ld + c0 + col, acc);
+        part += (double)pl[sc][h][col] * (double)acc;
+      }
+    }
+    __syncthreads();
+    box_store(nx, pl[sl], cf[cs], rid[cs]);
+    __syncthreads();
+    box_issue(S, P, c0, q, nx);
+    box_rows(S, x0, y0, z + 5, q);
+  };
+  int z = 0;
+  for (; z + 1 < nz; z += 2) {
+    plane(z, A);
+    plane(z + 1, B);
+  }
+  if (z < nz) plane(z, A);
+  red[yy][col] = part;
+  __syncthreads();
+  if (tid < 32 && c0 + tid < ld) {
+    double sum = 0.0;
+#pragma unroll
+    for (int w = 0; w < 8; ++w) sum += red[w][tid];
+    if (sum != 0.0) unsafeAtomicAdd(&S.pq[c0 + tid], sum);
+  }
+}
+
+// Stencil-ordered FP32 coefficients of a box interior from the assembled FP64 CSR values:
+// s16[16 r + s] = val[spos[16 r + s]], 0 where the slot has no II entry.
+__global__ void k_box_coeffs(const int* __restrict__ spos, const double* __restrict__ val, int n16, float* __restrict__ s16) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n16) return;
+  const int e = spos[i];
+  s16[i] = e >= 0 ? (float)val[e] : 0.0f;
+}
+void launch_box_coeffs(const int* spos, const double* val, int nI, float* s16, hipStream_t s) {
+  const int n = nI * kStencil;
+  if (n > 0) hipLaunchKernelGGL(k_box_coeffs, dim3((n + 255) / 256), dim3(256), 0, s, spos, val, n, s16);
+}
+void launch_cg_spmm_box(const CgSys* sys, const int4* tiles, int ntiles, hipStream_t s) {
+  // xcd_tile spreads the tiles over a grid of whole groups of 8 workgroups
+  if (ntiles > 0) hipLaunchKernelGGL(k_cg_spmm_box, dim3(xcd_grid(ntiles)), dim3(256), 0, s, sys, tiles, ntiles);
+}
+
 // Block-Jacobi preconditioner: z = M^-1 r with M the diagonal blocks of A_II over the row
 // aggregates (at most 8 rows each).  A wave owns whole aggregates, so applying M^-1 needs no
 // data beyond the rows the kernel streams anyway.

@@ -61,7 +61,7 @@ class MorOpts(ctypes.Structure):
                 ("dev_alloc", ALLOC_FN), ("dev_free", FREE_FN), ("alloc_user", ctypes.c_void_p),
                 ("hip_stream", ctypes.c_void_p), ("host_only", ctypes.c_int32), ("basis_update", ctypes.c_int32), ("update_drop", ctypes.c_double),
                 ("reduced_solver", ctypes.c_int32), ("reduced_rtol", ctypes.c_double),
-                ("reduced_max_iter", ctypes.c_int32), ("coarse", ctypes.c_int32)]
+                ("reduced_max_iter", ctypes.c_int32), ("coarse", ctypes.c_int32), ("box_spmm", ctypes.c_int32)]
 
 
 def load_library(path: str = LIB_PATH) -> ctypes.CDLL:

@@ -12,8 +12,9 @@ tests/golden/make_oracle_reference.py with the same readings (`C5 4 --no-fe --im
 diagonal-preconditioned CG to 1e-12; u~ stored in float32, whose rounding is below 1e-7 of the
 energy).  Compared here:
   - k_eff of every box (exact: an integer decision), and its singular values, the leading
-    k_eff + 1 within 1e-6 relative for FP32-refined requests and 1e-4 for BF16-Gram requests
-    (the hi/lo BF16 pair carries about 16 bits; R_BB^-1 and the 1e4 contrast amplify it);
+    k_eff + 1 within 1e-5 relative for FP32-refined requests (the FP64 refinement stops at a
+    residual of 1e-8 and the contrast of 1e4 raises A_II's condition number by that factor) and
+    1e-4 for BF16-Gram requests (the hi/lo BF16 pair carries about 16 bits);
   - the reduced solve reaches its residual (1e-12) and x^T b~ = ||u~||_A^2 agrees with the
     oracle's;
   - the reduced solution in the global energy norm, with A assembled by the oracle: within the
@@ -39,7 +40,7 @@ pytestmark = pytest.mark.gpu
 
 GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "C5_oracle.npz")
 PRECISIONS = ("fp32_refine", "bf16_split")
-TOL_SIGMA = {"fp32_refine": 1e-6, "bf16_split": 1e-4}
+TOL_SIGMA = {"fp32_refine": 1e-5, "bf16_split": 1e-4}
 TOL_ANGLE = {"fp32_refine": 1e-4, "bf16_split": 1e-2}
 
 

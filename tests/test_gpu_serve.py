@@ -13,7 +13,9 @@ The high-contrast case is the serving workload's input class at a size the oracl
 seconds: kappa = 1e4 in spherical inclusions, uneven boxes, ranks 8..48, a Poisson stream of
 FP32-refined and BF16-Gram requests, the basis update of Section 6 step 2 and the paper's
 diagonal-preconditioned reduced CG.  Each result matches its solo run, and the reduced solution
-matches the FP64 oracle's (same readings) in the global energy norm within the BF16 bound.
+matches the FP64 oracle's (same readings) in the global energy norm within the BF16 bound; the
+singular values of FP32-refined requests match the oracle's to 1e-5 (the contrast of 1e4 raises
+A_II's condition number by that factor, and the FP64 refinement stops at a residual of 1e-8).
 """
 import sys
 
@@ -200,7 +202,7 @@ def test_inclusions_stream_mixed_precisions_match_solo_and_oracle():
             k = mor.mor_get_stats(m.ctx, sd)
             sig = mix[j]["sigma"]
             ns = min(sig.size, r.k_eff + 1)
-            np.testing.assert_allclose(sig[:ns], r.sigma[:ns], rtol=TOL_BF16["sigma"] if prec == "bf16_split" else 1e-6,
+            np.testing.assert_allclose(sig[:ns], r.sigma[:ns], rtol=TOL_BF16["sigma"] if prec == "bf16_split" else 1e-5,
                                        err_msg=f"subdomain {sd} {prec} vs oracle")
             assert k["cg_iter_a"] > 0
     finally:
