@@ -94,7 +94,7 @@ def cpu_baseline(problem, workers: int, implicit: bool):
 
 PROFILE_OF = {
     "C2": os.path.join(ROOT, "profiles", "k_cg_spmm_halo_cap96_slice128_48cube_lognormal_fp32refine.md"),
-    "C5": os.path.join(ROOT, "profiles", "k_cg_spmm_halo_128cube_inclusions_stream.md"),
+    "C5": os.path.join(ROOT, "profiles", "k_cg_spmm_box_128cube_inclusions_stream.md"),
 }
 
 
@@ -415,6 +415,8 @@ def main():
         n, ms, wk = mor.mor_timing_get(m.ctx, name)
         if n:
             kernels[name] = dict(launches=n, ms_per_step=round(ms / args.steps, 3))
+            if wk > 0:   # the timer's work: bytes for the streaming kernels, flops for the dense ones
+                kernels[name]["work_per_step"] = wk / args.steps
     timed_sds = sorted({int(s) for sl in slices[args.warmup:] for s in sl.sds}) if stream_wl else range(n_sub)
     stats = [mor.mor_get_stats(m.ctx, i) for i in timed_sds]
     _, red_iters, red_rel = mor.mor_get_solve_info(m.ctx)
