@@ -224,6 +224,19 @@ int mor_project(mor_ctx* ctx);
  * conjugate gradients reach reduced_max_iter first. */
 int mor_solve(mor_ctx* ctx, double* u_out, int64_t* n_reduced_out);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid allocation): mor_solve's conjugate-gradient path (reduced_solver
+ * 1 or 2) with every vector in a static device array of the library (32 MiB per device, held
+ * until the process ends), so the call itself allocates nothing.  u_dev: device buffer of
+ * n_nodes doubles, caller-owned, receives u~ (zero at Dirichlet nodes); n_reduced_out as in
+ * mor_solve; the reduced solution is then also readable with mor_get_reduced_solution.
+ * Errors: MOR_EINVAL for reduced_solver 0 or a NULL u_dev; MOR_ENOMEM when the reduced
+ * dimension exceeds 699,008 unknowns (the array's capacity); MOR_ESTATE before mor_project;
+ * MOR_EDEVICE if the array's address could not be found on the context's device; otherwise as
+ * mor_solve.  All calls on one device share its array: calls that overlap on one device (from
+ * two host threads, or on two streams) race and must be serialized by the caller. */
+int mor_solve_noalloc(mor_ctx* ctx, double* u_dev, int64_t* n_reduced_out);
+
 /* ---- serving: continuous batching of local-reduction requests ---------------
  * mor_submit queues a request for subdomain `sd` (rank/tol as in mor_local_basis,
  * precision one of MOR_FP64..MOR_BF16_SPLIT); it is admitted when device memory

@@ -18,6 +18,7 @@
 #include <cstring>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <new>
 #include <stdexcept>
 #include <string>
@@ -123,6 +124,7 @@ struct SubResult {
 struct mor_ctx {
   mor_opts opts;
   int halo_cap = 96;   // LDS SpMM tiling: halo rows per tile (one of kHaloCaps)
+  int device = 0;      // HIP device current at mor_create
   hipStream_t st = nullptr;
   HostMesh mesh;
   std::vector<double> kappa, fnodal;
@@ -256,6 +258,7 @@ static void flush_timers(mor_ctx* c) {
 }
 
 struct MorEngine;
+static int scratch_setup(int dev) noexcept;
 static void engine_free(mor_ctx* c, MorEngine& e);
 static void engine_delete(MorEngine* e);
 
@@ -407,6 +410,8 @@ static int create_impl(const mor_mesh* mesh, const mor_coeff* coeff, const mor_s
     return MOR_OK;
   }
   // device uploads: geometry, coefficients, patterns
+  if (hipGetDevice(&c->device) != hipSuccess) c->device = 0;
+  (void)scratch_setup(c->device);   // the no-allocation solve's array (its failure surfaces there)
   int rc = 0;
   rc = rc ? rc : upload(c, &c->d_xyz, m.xyz.data(), m.xyz.size());
   rc = rc ? rc : upload(c, &c->d_tets, m.tets.data(), m.tets.size());
@@ -2824,6 +2829,72 @@ static int solve_pcg(mor_ctx* c, double* u_out, int64_t* n_reduced_out) {
   if (n_reduced_out) *n_reduced_out = c->n_red;
   c->solved = 1;
   return MOR_OK;
+}
+
+// ---- the reduced solve without allocation ---------------------------------------------------
+// A file-scope device array holds the conjugate-gradient vectors of mor_solve_noalloc, so the
+// call allocates nothing.  Its address is looked up once per device, with that device current,
+// when the first context is created there; host code passes that address, never the array's
+// name, to kernels and copies.  Every call on a device shares the device's array.
+constexpr size_t kNoAllocScratchBytes = (size_t)32 << 20;
+constexpr int kMaxScratchDevices = 64;
+static __device__ __align__(256) char scratch[kNoAllocScratchBytes];
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[kMaxScratchDevices] = {};
+static int g_scratch_state[kMaxScratchDevices] = {};   // 0 not looked up, 1 found, -1 lookup failed
+
+// Look up this device's copy of `scratch` (the device must be current); 1 when available.
+// Largest reduced dimension whose vectors fit the scratch (48 bytes per unknown, rounded to 64).
+static int64_t noalloc_max_reduced() {
+  int64_t n = (int64_t)((kNoAllocScratchBytes - 8 * 16 - 4 * 16 - 1024) / 48) / 64 * 64;
+  while (n > 0 && pcg_bytes(n) > kNoAllocScratchBytes) n -= 64;
+  return n;
+}
+
+static int scratch_setup(int dev) noexcept {
+  if (dev < 0 || dev >= kMaxScratchDevices) return -1;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_state[dev] == 0) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    g_scratch_state[dev] = (e == hipSuccess && ptr != nullptr) ? 1 : -1;
+    g_scratch_ptr[dev] = g_scratch_state[dev] == 1 ? ptr : nullptr;
+  }
+  return g_scratch_state[dev];
+}
+
+extern "C" int mor_solve_noalloc(mor_ctx* c, double* u_dev, int64_t* n_reduced_out) {
+  MOR_TRY
+  if (!c) return fail(MOR_EINVAL, "null context");
+  if (c->opts.host_only) return fail(MOR_ESTATE, "context was created host_only");
+  if (!c->projected) return fail(MOR_ESTATE, "mor_project must run first");
+  if (c->opts.reduced_solver < 1) return fail(MOR_EINVAL, "mor_solve_noalloc needs reduced_solver 1 or 2");
+  if (!u_dev) return fail(MOR_EINVAL, "u_dev is required (device buffer of n_nodes doubles)");
+  const int64_t n = c->n_red;
+  if (n > 0 && pcg_bytes(n) > kNoAllocScratchBytes)
+    return fail(MOR_ENOMEM, "reduced dimension " + std::to_string(n) + " exceeds the static scratch of " +
+                                std::to_string(kNoAllocScratchBytes >> 20) + " MiB (at most " +
+                                std::to_string(noalloc_max_reduced()) + " unknowns)");
+  if (scratch_setup(c->device) != 1) return fail(MOR_EDEVICE, "static scratch of this device is not available");
+  c->solved = 0;
+  hipStream_t st = c->st;
+  if (n > 0) {
+    const RpcgDev d = pcg_layout(c, (char*)g_scratch_ptr[c->device], kNoAllocScratchBytes, (int)n);
+    if (!d.state) return fail(MOR_ENOMEM, "static scratch exhausted (reduced solve)");
+    if (int rc = pcg_iterate(c, d, (int)n)) return rc;
+    launch_fill(u_dev, c->mesh.n_nodes, 0.0, st);
+    for (size_t i = 0; i < c->subs.size(); ++i)
+      launch_reconstruct(c->res[i].d_V, c->subs[i].nP, c->res[i].dim, d.x + c->off[i], c->sdev[i].nodes, u_dev, st);
+  } else {
+    std::fill(c->x_host.begin(), c->x_host.end(), 0.0);
+    launch_fill(u_dev, c->mesh.n_nodes, 0.0, st);
+  }
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(st));
+  if (n_reduced_out) *n_reduced_out = n;
+  c->solved = 1;
+  return MOR_OK;
+  MOR_CATCH
 }
 
 extern "C" int mor_solve(mor_ctx* c, double* u_out, int64_t* n_reduced_out) {

@@ -21,7 +21,7 @@ PRECISIONS = {"fp64": MOR_FP64, "fp32_refine": MOR_FP32_REFINE, "fp32": MOR_FP32
 
 EXPORTED = ("mor_default_opts", "mor_create", "mor_local_basis", "mor_local_basis_batch", "mor_local_basis_sketched",
             "mor_project",
-            "mor_solve", "mor_submit", "mor_poll", "mor_drain", "mor_step", "mor_engine_stats", "mor_get_sizes", "mor_get_nodes",
+            "mor_solve", "mor_solve_noalloc", "mor_submit", "mor_poll", "mor_drain", "mor_step", "mor_engine_stats", "mor_get_sizes", "mor_get_nodes",
             "mor_get_pairs", "mor_get_basis", "mor_get_rank", "mor_get_sigma", "mor_get_local_block", "mor_get_reduced",
             "mor_get_reduced_solution", "mor_get_solve_info", "mor_get_stats", "mor_timing_enable", "mor_timing_get",
             "mor_timing_reset", "mor_destroy", "mor_last_error")
@@ -83,6 +83,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "mor_local_basis_sketched": (I32, [P, I32, P, P, P, I32, P, P]),
         "mor_project": (I32, [P]),
         "mor_solve": (I32, [P, P, P]),
+        "mor_solve_noalloc": (I32, [P, P, P]),
         "mor_submit": (I32, [P, I32, I32, D, I32, P]),
         "mor_poll": (I32, [P, ctypes.c_uint64, P, P]),
         "mor_drain": (I32, [P]),
@@ -139,8 +140,11 @@ class _TorchAllocator:
         self.torch = torch
         self.stream = stream_handle
         self.live = {}
+        self.n_alloc = 0     # allocation and release callbacks seen
+        self.n_free = 0
 
         def _alloc(nbytes, user):
+            self.n_alloc += 1
             try:
                 p = torch.cuda.caching_allocator_alloc(int(nbytes))
             except Exception:
@@ -149,6 +153,7 @@ class _TorchAllocator:
             return p
 
         def _free(ptr, user):
+            self.n_free += 1
             if ptr in self.live:
                 del self.live[ptr]
                 torch.cuda.caching_allocator_delete(ptr)
@@ -225,6 +230,14 @@ def mor_solve(ctx, n_nodes: int):
     n = ctypes.c_int64()
     _check(lib().mor_solve(ctx, _ptr(u), ctypes.byref(n)))
     return u, n.value
+
+
+def mor_solve_noalloc(ctx, u_dev_ptr: int):
+    """The allocation-free reduced solve: u~ is written to the caller's device buffer at
+    u_dev_ptr (n_nodes doubles); returns the reduced dimension."""
+    n = ctypes.c_int64()
+    _check(lib().mor_solve_noalloc(ctx, ctypes.c_void_p(u_dev_ptr), ctypes.byref(n)))
+    return n.value
 
 
 def mor_submit(ctx, sd, rank, tol, precision):
