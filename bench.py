@@ -111,10 +111,11 @@ def kernel_source_hash(name: str) -> str:
     return ""
 
 
-def profiled_traffic(kernel: str, config: str):
-    """HBM bytes per launch of `kernel` from the committed rocprofv3 summary of this workload
-    (calibrated FETCH_SIZE + WRITE_SIZE), or None when there is none or the kernel's source has
-    changed since the counters were taken."""
+def profiled_traffic(kernel: str, config: str, algorithmic_bytes: float):
+    """HBM bytes per launch of `kernel`: the committed rocprofv3 summary of this workload gives its
+    calibrated FETCH_SIZE + WRITE_SIZE per algorithmic byte over the launches it profiled, applied
+    here to this run's algorithmic bytes per launch.  None when there is no summary or the
+    kernel's source has changed since the counters were taken."""
     import re
     path = PROFILE_OF.get(config)
     if path is None or not os.path.exists(path):
@@ -124,10 +125,10 @@ def profiled_traffic(kernel: str, config: str):
     m = re.search(base + r" source sha256 ([0-9a-f]{16})", txt)
     if not m or kernel_source_hash(base) != m.group(1):
         return None
-    row = re.search(r"\| `mor::" + re.escape(kernel) + r"` \|[^|]*\|[^|]*\|[^|]*\| ([0-9.]+) \| ([0-9.]+) \|", txt)
+    row = re.search(base + r" traffic per algorithmic byte ([0-9.]+)", txt)
     if not row:
         return None
-    return round((float(row.group(1)) + float(row.group(2))) * 1e9)
+    return round(float(row.group(1)) * algorithmic_bytes)
 
 
 def comparator_leg(problem, steps: int, reduced_solver: int = 0):
@@ -495,8 +496,9 @@ def main():
                      "kernel": spmm_kernel if use_graph else f"{spmm_kernel} (block-CG SpMM Q = A_II P)",
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": profiled_traffic(spmm_kernel, args.config) if not use_graph else None,
-                     "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, calibrated)",
+                     "traffic": profiled_traffic(spmm_kernel, args.config, bytes_per_launch) if not use_graph else None,
+                     "traffic_unit": "bytes per launch: rocprofv3 FETCH_SIZE + WRITE_SIZE (calibrated) per algorithmic "
+                                     "byte of the profiled launches, times this run's algorithmic bytes per launch",
                      "avg_launch_ms": round(avg_ms, 4), "launches": n_launch,
                      "algorithmic_bytes_per_launch": round(bytes_per_launch)},
         "cpu_baseline": cpu,
