@@ -609,6 +609,114 @@ static GemmDesc gd(int m, int n, int k, const double* A, int lda, int ta, const 
   return g;
 }
 
+// ------------------------------------------------------------------------------- blocked TRSM
+// Triangular solves with a Cholesky factor R (upper, T panels of 64 rows, in DenseSub) over a
+// batch.  The panel kernels solve one diagonal block of kTrsmBlk panels at a time, in place in X
+// (B is copied there first), and the coupling to the other blocks is one k_gemm update per block
+// (the rows below it for R^T X = B, the rows above it for R X = B): most of the flops then run
+// on XCD-grouped GEMM tiles over the whole chip instead of inside the panel loop, which keeps
+// one workgroup per 64-column tile busy for all T panels.
+constexpr int kTrsmBlk = 8;
+
+struct DevBuf {   // one device allocation for descriptors and tile lists, freed once the stream drains
+  mor_ctx* c;
+  char* p;
+  Arena ar;
+  DevBuf(mor_ctx* cc, size_t bytes) : c(cc), p((char*)dalloc(cc, bytes)) { ar = Arena{p, p ? bytes : 0, 0}; }
+  ~DevBuf() {
+    if (!p) return;
+    (void)hipStreamSynchronize(c->st);
+    dfree(c, p);
+  }
+};
+
+static int gemm_now(mor_ctx* c, const GemmBatch& g, GemmDesc* dg, int4* dt) {
+  if (g.d.empty()) return 0;
+  HIPCHK(hipMemcpyAsync(dg, g.d.data(), sizeof(GemmDesc) * g.d.size(), hipMemcpyHostToDevice, c->st));
+  HIPCHK(hipMemcpyAsync(dt, g.tiles.data(), sizeof(int4) * g.tiles.size(), hipMemcpyHostToDevice, c->st));
+  launch_gemm(dg, dt, (int)g.tiles.size(), c->st);
+  return 0;
+}
+
+// R^T X = B for every slot i (hds[i], htd[i]; dds: the DenseSub table on the device)
+static int trsm_lt_blocked(mor_ctx* c, const std::vector<DenseSub>& hds, const DenseSub* dds,
+                           const std::vector<TrsmDesc>& htd) {
+  hipStream_t st = c->st;
+  const int ns = (int)hds.size();
+  if (ns == 0) return 0;
+  int tmax = 0, ctmax = 0;
+  size_t tiles = 1;
+  for (int i = 0; i < ns; ++i) {
+    tmax = std::max(tmax, hds[i].T);
+    ctmax = std::max(ctmax, htd[i].ncol_tiles);
+    tiles += (size_t)std::max(hds[i].T - kTrsmBlk, 0) * htd[i].ncol_tiles;
+  }
+  DevBuf buf(c, sizeof(TrsmDesc) * ns + sizeof(GemmDesc) * ns + sizeof(int4) * tiles + 3 * 256);
+  TrsmDesc* dip = (TrsmDesc*)buf.ar.take(sizeof(TrsmDesc) * ns);
+  GemmDesc* dg = (GemmDesc*)buf.ar.take(sizeof(GemmDesc) * ns);
+  int4* dt = (int4*)buf.ar.take(sizeof(int4) * tiles);
+  if (!dip || !dg || !dt) return fail(MOR_ENOMEM, "device allocation failed (triangular solve)");
+  std::vector<TrsmDesc> ip(ns);
+  for (int i = 0; i < ns; ++i) {
+    const TrsmDesc& t = htd[i];
+    launch_copy_rect(t.B, t.ldb, t.tb, t.X, t.ldx, hds[i].MP, t.ncol_tiles * 64, st);
+    ip[i] = TrsmDesc{t.X, t.ldx, 0, t.X, t.ldx, t.ncol_tiles};
+  }
+  HIPCHK(hipMemcpyAsync(dip, ip.data(), sizeof(TrsmDesc) * ns, hipMemcpyHostToDevice, st));
+  for (int p0 = 0; p0 < tmax; p0 += kTrsmBlk) {
+    const int p1 = p0 + kTrsmBlk;
+    launch_trsm_lt(dds, dip, ns, ctmax, st, p0, p1);
+    GemmBatch g;   // X[p1:, :] -= R[p0:p1, p1:]^T X[p0:p1, :]
+    for (int i = 0; i < ns; ++i) {
+      const DenseSub& d = hds[i];
+      if (d.T <= p1) continue;
+      const int ld = ip[i].ldx;
+      double* X = ip[i].X;
+      g.add(gd((d.T - p1) * 64, ip[i].ncol_tiles * 64, kTrsmBlk * 64, d.S + (size_t)p0 * 64 * d.MP + (size_t)p1 * 64,
+               d.MP, 1, X + (size_t)p0 * 64 * ld, ld, 0, X + (size_t)p1 * 64 * ld, ld, -1.0, 1.0));
+    }
+    if (int rc = gemm_now(c, g, dg, dt)) return rc;
+  }
+  return 0;
+}
+
+// R X = B for one 64-column tile per slot (B, X: MP x 64, ld 64; host arrays of device pointers)
+static int trsm_un_blocked(mor_ctx* c, const std::vector<DenseSub>& hds, const DenseSub* dds,
+                           const std::vector<double*>& hB, const std::vector<double*>& hX) {
+  hipStream_t st = c->st;
+  const int ns = (int)hds.size();
+  if (ns == 0) return 0;
+  int tmax = 0;
+  size_t tiles = 1;
+  for (int i = 0; i < ns; ++i) {
+    tmax = std::max(tmax, hds[i].T);
+    tiles += (size_t)hds[i].T;
+  }
+  DevBuf buf(c, sizeof(double*) * ns + sizeof(GemmDesc) * ns + sizeof(int4) * tiles + 3 * 256);
+  double** dX = (double**)buf.ar.take(sizeof(double*) * ns);
+  GemmDesc* dg = (GemmDesc*)buf.ar.take(sizeof(GemmDesc) * ns);
+  int4* dt = (int4*)buf.ar.take(sizeof(int4) * tiles);
+  if (!dX || !dg || !dt) return fail(MOR_ENOMEM, "device allocation failed (triangular solve)");
+  for (int i = 0; i < ns; ++i)
+    if (hB[i] != hX[i]) launch_copy_rect(hB[i], 64, 0, hX[i], 64, hds[i].MP, 64, st);
+  HIPCHK(hipMemcpyAsync(dX, hX.data(), sizeof(double*) * ns, hipMemcpyHostToDevice, st));
+  for (int p0 = (tmax - 1) / kTrsmBlk * kTrsmBlk; p0 >= 0; p0 -= kTrsmBlk) {
+    const int p1 = p0 + kTrsmBlk;
+    launch_trsm_un(dds, ns, dX, dX, st, p0, p1);
+    if (p0 == 0) break;
+    GemmBatch g;   // X[:p0, :] -= R[:p0, p0:pe] X[p0:pe, :]
+    for (int i = 0; i < ns; ++i) {
+      const DenseSub& d = hds[i];
+      if (d.T <= p0) continue;
+      const int pe = std::min(p1, d.T);
+      g.add(gd(p0 * 64, 64, (pe - p0) * 64, d.S + (size_t)p0 * 64, d.MP, 0, hX[i] + (size_t)p0 * 64 * 64, 64, 0, hX[i],
+               64, -1.0, 1.0));
+    }
+    if (int rc = gemm_now(c, g, dg, dt)) return rc;
+  }
+  return 0;
+}
+
 // ------------------------------------------------------------------------------- block CG
 // ------------------------------------------------------------------------------- CG tiles
 struct TileCfg {
@@ -1154,7 +1262,7 @@ static int coarse_setup(mor_ctx* c, const std::vector<Live*>& adm) {
     launch_chol_panel(dds, ns, p, tmax, st);
     launch_chol_syrk(dds, ns, p, tmax, st);
   }
-  launch_trsm_lt(dds, dtd, ns, tmax, st);
+  if (int rc = trsm_lt_blocked(c, hds, dds, htd)) return rc;
   gemm_run(c, gb, "coarse_setup");
   HIPCHK(hipGetLastError());
   std::vector<int> hinfo(32 * ls.size());
@@ -1568,7 +1676,12 @@ static int rsvd_after_h1(mor_ctx* c, MorEngine& e, std::vector<Live*>& ls) {
   if (!PB || !PW) return fail(MOR_ENOMEM, "arena exhausted (sketch stage)");
   {
     ScopedTimer tm(c, "trsm", 0);
-    launch_trsm_un(dds, ns, PB, PW, tmax, st);   // T = R_BB^-1 S_i
+    std::vector<double*> hB(ns), hW(ns);
+    for (int i = 0; i < ns; ++i) {
+      hB[i] = sl[i]->Bk;
+      hW[i] = sl[i]->Wk;
+    }
+    if (int rc = trsm_un_blocked(c, hds, dds, hB, hW)) return rc;   // T = R_BB^-1 S_i
   }
   Launch Ln;
   for (int i = 0; i < ns; ++i) {
@@ -1693,7 +1806,7 @@ static int rsvd_finish(mor_ctx* c, std::vector<Live*>& ls) {
   HIPCHK(hipMemcpyAsync(dtd, htd.data(), sizeof(TrsmDesc) * ns, hipMemcpyHostToDevice, st));
   {
     ScopedTimer tm(c, "trsm", 0);
-    launch_trsm_lt(dds, dtd, ns, 1, st);
+    if (int rc = trsm_lt_blocked(c, hds, dds, htd)) return rc;
   }
   // B B^T and its eigenpairs: sigma^2 and the left singular vectors U
   GemmBatch g1;
@@ -2108,8 +2221,8 @@ static int dense_stage(mor_ctx* c, std::vector<Live*>& done) {
     double fl = 0;
     for (Slot* q : sl) fl += 2.0 * (double)q->MP * q->MP * q->MP;
     ScopedTimer tm(c, "trsm", fl);
-    launch_trsm_lt(dds, dtd, ns, tmax, st);
-    launch_trsm_lt(dds, dtd + ns, ns, tmax, st);
+    if ((rc = trsm_lt_blocked(c, hds, dds, std::vector<TrsmDesc>(htd.begin(), htd.begin() + ns)))) return rc;
+    if ((rc = trsm_lt_blocked(c, hds, dds, std::vector<TrsmDesc>(htd.begin() + ns, htd.end())))) return rc;
   }
   for (Slot* q : sl) launch_symmetrize(q->C, q->MP, st);
   {
@@ -2242,7 +2355,15 @@ static int dense_stage(mor_ctx* c, std::vector<Live*>& done) {
     Slot& q = *sl[i];
     launch_scale_cols(q.Ub, q.s, d_sig + (size_t)i * 64, q.k_eff, q.MP, q.Bk, st);
   }
-  launch_trsm_un(dds, ns, P_Bk, P_Wk, tmax, st);
+  {
+    std::vector<double*> hB(ns), hW(ns);
+    for (int i = 0; i < ns; ++i) {
+      hB[i] = sl[i]->Bk;
+      hW[i] = sl[i]->Wk;
+    }
+    ScopedTimer tm(c, "trsm_basis", 0);
+    if ((rc = trsm_un_blocked(c, hds, dds, hB, hW))) return rc;
+  }
   GemmBatch gV;
   for (int i = 0; i < ns; ++i) {
     Slot& q = *sl[i];
@@ -2919,9 +3040,7 @@ extern "C" int mor_solve(mor_ctx* c, double* u_out, int64_t* n_reduced_out) {
   double* Di = (double*)ar.take(8 * (size_t)T * 4096);
   int* info = (int*)ar.take(64);
   DenseSub* dd = (DenseSub*)ar.take(sizeof(DenseSub));
-  TrsmDesc* td = (TrsmDesc*)ar.take(2 * sizeof(TrsmDesc));
-  double** pb = (double**)ar.take(2 * sizeof(double*));
-  if (!pb) return fail(MOR_ENOMEM, "arena exhausted (reduced solve)");
+  if (!dd) return fail(MOR_ENOMEM, "arena exhausted (reduced solve)");
   ScopedTimer tm(c, "solve", (double)MP * MP * MP / 3.0);
   HIPCHK(hipMemcpyAsync(F, c->d_At, 8 * (size_t)MP * MP, hipMemcpyDeviceToDevice, st));
   launch_fill_i(info, 16, 0, st);
@@ -2937,14 +3056,11 @@ extern "C" int mor_solve(mor_ctx* c, double* u_out, int64_t* n_reduced_out) {
   HIPCHK(hipStreamSynchronize(st));
   if (hinfo) return fail(MOR_EDEVICE, "reduced matrix is not positive definite (pivot " + std::to_string(hinfo) + ")");
   // R^T y = b (y in d_x), then R x = y
-  TrsmDesc ht{c->d_bt, 64, 0, c->d_x, 64, 1};
-  HIPCHK(hipMemcpyAsync(td, &ht, sizeof(ht), hipMemcpyHostToDevice, st));
-  launch_trsm_lt(dd, td, 1, 1, st);
+  const TrsmDesc ht{c->d_bt, 64, 0, c->d_x, 64, 1};
+  if (int rc = trsm_lt_blocked(c, {hd}, dd, {ht})) return rc;
   double* xsol = (double*)ar.take(8 * (size_t)MP * 64);
   if (!xsol) return fail(MOR_ENOMEM, "arena exhausted (reduced solve)");
-  double* hp[2] = {c->d_x, xsol};
-  HIPCHK(hipMemcpyAsync(pb, hp, sizeof(hp), hipMemcpyHostToDevice, st));
-  launch_trsm_un(dd, 1, pb, pb + 1, T, st);
+  if (int rc = trsm_un_blocked(c, {hd}, dd, {c->d_x}, {xsol})) return rc;
   // x = column 0 of xsol
   std::vector<double> xs((size_t)MP * 64);
   HIPCHK(hipMemcpyAsync(xs.data(), xsol, 8 * xs.size(), hipMemcpyDeviceToHost, st));

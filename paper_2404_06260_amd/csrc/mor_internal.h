@@ -188,10 +188,13 @@ void launch_potrf_diag(const DenseSub* d, int nsub, int p, hipStream_t s);
 void launch_chol_panel(const DenseSub* d, int nsub, int p, int tmax, hipStream_t s);
 void launch_chol_syrk(const DenseSub* d, int nsub, int p, int tmax, hipStream_t s);
 // solve R^T X = B for every 64-column tile of every subdomain
-void launch_trsm_lt(const DenseSub* d, const TrsmDesc* td, int nsub, int max_col_tiles, hipStream_t s);
+void launch_trsm_lt(const DenseSub* d, const TrsmDesc* td, int nsub, int max_col_tiles, hipStream_t s, int p0 = 0,
+                    int p1 = 1 << 30);
 void launch_scale_cols(const double* U, int ldu, const double* sigma, int k, int rows, double* B, hipStream_t s);
 // solve R X = B for one column tile (<= 64 columns): B, X are MP x 64 (ld 64)
-void launch_trsm_un(const DenseSub* d, int nsub, double* const* Bs, double* const* Xs, int tmax, hipStream_t s);
+void launch_trsm_un(const DenseSub* d, int nsub, double* const* Bs, double* const* Xs, hipStream_t s, int p0 = 0,
+                    int p1 = 1 << 30);
+void launch_copy_rect(const double* src, int lds, int trans, double* dst, int ldd, int rows, int cols, hipStream_t s);
 
 void launch_jacobi(double* const* H, double* const* Svec, double* const* theta, const int* s_of, int nsub,
                    int smax, hipStream_t s);

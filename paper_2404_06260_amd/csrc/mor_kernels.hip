@@ -1321,39 +1321,77 @@ void launch_symmetrize(double* S, int MP, hipStream_t s) {
 // lane%16, k lane/16; D: lane -> col lane%16, register r -> row lane/16 + 4r).
 constexpr int kLdsPad = 68;
 
+// One thread's share of a 16-deep k-step of the A and B tiles (4 + 4 doubles, zero outside
+// the matrix), loaded into registers one step ahead so that the loads are in flight while the
+// matrix cores work on the current step.
+template <bool TA, bool TB>
+__device__ __forceinline__ void tile_fetch(const double* __restrict__ A, int lda, const double* __restrict__ B, int ldb,
+                                           int m, int n, int i0, int j0, int k0, int ke, double (&ra)[4],
+                                           double (&rb)[4]) {
+  const int tid = threadIdx.x;
+  if (!TA) {
+    const int i = tid >> 2, kk = (tid & 3) * 4;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int k = k0 + kk + q;
+      ra[q] = (i0 + i < m && k < ke) ? A[(int64_t)(i0 + i) * lda + k] : 0.0;
+    }
+  } else {
+    const int kk = tid >> 4, i = (tid & 15) * 4;
+    const int k = k0 + kk;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) ra[q] = (i0 + i + q < m && k < ke) ? A[(int64_t)k * lda + i0 + i + q] : 0.0;
+  }
+  if (!TB) {
+    const int kk = tid >> 4, j = (tid & 15) * 4;
+    const int k = k0 + kk;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) rb[q] = (k < ke && j0 + j + q < n) ? B[(int64_t)k * ldb + j0 + j + q] : 0.0;
+  } else {
+    const int j = tid >> 2, kk = (tid & 3) * 4;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int k = k0 + kk + q;
+      rb[q] = (k < ke && j0 + j < n) ? B[(int64_t)(j0 + j) * ldb + k] : 0.0;
+    }
+  }
+}
+
+template <bool TA, bool TB>
+__device__ __forceinline__ void tile_put(const double (&ra)[4], const double (&rb)[4], double (*As)[kLdsPad],
+                                         double (*Bs)[kLdsPad]) {
+  const int tid = threadIdx.x;
+  if (!TA) {
+    const int i = tid >> 2, kk = (tid & 3) * 4;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) As[kk + q][i] = ra[q];
+  } else {
+    const int kk = tid >> 4, i = (tid & 15) * 4;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) As[kk][i + q] = ra[q];
+  }
+  if (!TB) {
+    const int kk = tid >> 4, j = (tid & 15) * 4;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) Bs[kk][j + q] = rb[q];
+  } else {
+    const int j = tid >> 2, kk = (tid & 3) * 4;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) Bs[kk + q][j] = rb[q];
+  }
+}
+
 template <bool TA, bool TB>
 __device__ __forceinline__ void tile_mma(const double* __restrict__ A, int lda, const double* __restrict__ B, int ldb,
                                          int m, int n, int i0, int j0, int kb, int ke, double (*As)[kLdsPad],
                                          double (*Bs)[kLdsPad], d4 (&acc)[2][2]) {
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, wr = w >> 1, wc = w & 1;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, wr = w >> 1, wc = w & 1;
+  double ra[4], rb[4];
+  if (kb < ke) tile_fetch<TA, TB>(A, lda, B, ldb, m, n, i0, j0, kb, ke, ra, rb);
   for (int k0 = kb; k0 < ke; k0 += 16) {
-    if (!TA) {
-      const int i = tid >> 2, kk = (tid & 3) * 4;
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int k = k0 + kk + q;
-        As[kk + q][i] = (i0 + i < m && k < ke) ? A[(int64_t)(i0 + i) * lda + k] : 0.0;
-      }
-    } else {
-      const int kk = tid >> 4, i = (tid & 15) * 4;
-      const int k = k0 + kk;
-#pragma unroll
-      for (int q = 0; q < 4; ++q) As[kk][i + q] = (i0 + i + q < m && k < ke) ? A[(int64_t)k * lda + i0 + i + q] : 0.0;
-    }
-    if (!TB) {
-      const int kk = tid >> 4, j = (tid & 15) * 4;
-      const int k = k0 + kk;
-#pragma unroll
-      for (int q = 0; q < 4; ++q) Bs[kk][j + q] = (k < ke && j0 + j + q < n) ? B[(int64_t)k * ldb + j0 + j + q] : 0.0;
-    } else {
-      const int j = tid >> 2, kk = (tid & 3) * 4;
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int k = k0 + kk + q;
-        Bs[kk + q][j] = (k < ke && j0 + j < n) ? B[(int64_t)(j0 + j) * ldb + k] : 0.0;
-      }
-    }
+    tile_put<TA, TB>(ra, rb, As, Bs);
     __syncthreads();
+    if (k0 + 16 < ke) tile_fetch<TA, TB>(A, lda, B, ldb, m, n, i0, j0, k0 + 16, ke, ra, rb);
 #pragma unroll
     for (int s4 = 0; s4 < 4; ++s4) {
       const int kr = s4 * 4 + (lane >> 4);
@@ -1426,6 +1464,9 @@ __device__ void gemm_tile_body(const GemmDesc& g, int ti, int tj, double (*As)[k
   else tile_store(g.C, g.ldc, g.m, g.n, ti * 64, tj * 64, g.alpha, g.beta, acc);
 }
 
+// Tiles are listed column tile fastest and dealt round-robin over the XCDs, so that the tiles an
+// XCD runs together share their A row panel in its L2 (grouping consecutive tiles on one XCD
+// instead measured slower on the coarse products, whose panels do not fit in L2 either way).
 __global__ __launch_bounds__(256) void k_gemm(const GemmDesc* __restrict__ descs, const int4* __restrict__ tiles) {
   __shared__ double As[16][kLdsPad], Bs[16][kLdsPad];
   const int4 tl = tiles[blockIdx.x];
@@ -1732,9 +1773,12 @@ void launch_chol_syrk(const DenseSub* d, int nsub, int p, int tmax, hipStream_t 
   if (nt > 0) hipLaunchKernelGGL(k_chol_syrk, dim3(nt * nt, nsub), dim3(256), 0, s, d, p, nt);
 }
 
-// Forward substitution R^T X = B, left-looking per 64-column tile (workgroup = column tile):
-// for each 64-row panel p, X_p = R_pp^{-T} (B_p - sum_{q<p} R_{q,p}^T X_q).
-__global__ __launch_bounds__(256) void k_trsm_lt(const DenseSub* __restrict__ ds, const TrsmDesc* __restrict__ tds) {
+// Forward substitution R^T X = B, left-looking per 64-column tile (workgroup = column tile),
+// over the panels [p0, min(p1, T)): X_p = R_pp^{-T} (B_p - sum_{p0<=q<p} R_{q,p}^T X_q).  With
+// p0 = 0 and p1 >= T this is the whole solve; a blocked solve passes one diagonal block at a time
+// (B = X, in place) and applies the panels before it as a GEMM update.
+__global__ __launch_bounds__(256) void k_trsm_lt(const DenseSub* __restrict__ ds, const TrsmDesc* __restrict__ tds,
+                                                 int p0, int p1) {
   __shared__ double As[16][kLdsPad], Bs[16][kLdsPad];
   const DenseSub& d = ds[blockIdx.y];
   const TrsmDesc& td = tds[blockIdx.y];
@@ -1745,11 +1789,12 @@ __global__ __launch_bounds__(256) void k_trsm_lt(const DenseSub* __restrict__ ds
   double* X = td.X;
   const int ldb = td.ldb, ldx = td.ldx;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, wr = w >> 1, wc = w & 1;
-  for (int p = 0; p < d.T; ++p) {
+  const int pe = min(p1, d.T);
+  for (int p = p0; p < pe; ++p) {
     d4 acc[2][2];
     tile_zero(acc);
-    // sum_{q<p} R_{q,p}^T X_{q,c}: A(i,k) = R[k][p*64+i], B(k,j) = X[k][c*64+j], k < 64p
-    tile_mma<true, false>(d.S + p * 64, MP, X + c * 64, ldx, 64, 64, 0, 0, 0, p * 64, As, Bs, acc);
+    // sum_{p0<=q<p} R_{q,p}^T X_{q,c}: A(i,k) = R[k][p*64+i], B(k,j) = X[k][c*64+j], 64 p0 <= k < 64p
+    tile_mma<true, false>(d.S + p * 64, MP, X + c * 64, ldx, 64, 64, 0, 0, p0 * 64, p * 64, As, Bs, acc);
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
@@ -1769,8 +1814,8 @@ __global__ __launch_bounds__(256) void k_trsm_lt(const DenseSub* __restrict__ ds
     __syncthreads();
   }
 }
-void launch_trsm_lt(const DenseSub* d, const TrsmDesc* td, int nsub, int max_col_tiles, hipStream_t s) {
-  hipLaunchKernelGGL(k_trsm_lt, dim3(max_col_tiles, nsub), dim3(256), 0, s, d, td);
+void launch_trsm_lt(const DenseSub* d, const TrsmDesc* td, int nsub, int max_col_tiles, hipStream_t s, int p0, int p1) {
+  hipLaunchKernelGGL(k_trsm_lt, dim3(max_col_tiles, nsub), dim3(256), 0, s, d, td, p0, p1);
 }
 
 // B[r][j] = U[r][j] / sigma_j for j < k, 0 for k <= j < 64 (B: rows x 64)
@@ -1785,8 +1830,11 @@ void launch_scale_cols(const double* U, int ldu, const double* sigma, int k, int
   hipLaunchKernelGGL(k_scale_cols, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, U, ldu, sigma, k, rows, B);
 }
 
-// Back substitution R X = B for one 64-column tile; B, X: MP x 64 (ld 64).
-__global__ __launch_bounds__(256) void k_trsm_un(const DenseSub* __restrict__ ds, double* const* Bs_, double* const* Xs_) {
+// Back substitution R X = B for one 64-column tile over the panels [p0, min(p1, T)), last
+// first: X_p = R_pp^-1 (B_p - sum_{p<q<min(p1,T)} R_{p,q} X_q); B, X: MP x 64 (ld 64).  The
+// blocked solve passes one diagonal block at a time, in place.
+__global__ __launch_bounds__(256) void k_trsm_un(const DenseSub* __restrict__ ds, double* const* Bs_, double* const* Xs_,
+                                                 int p0, int p1) {
   __shared__ double As[16][kLdsPad], Bs[16][kLdsPad];
   const int slot = blockIdx.x;
   const DenseSub& d = ds[slot];
@@ -1794,11 +1842,12 @@ __global__ __launch_bounds__(256) void k_trsm_un(const DenseSub* __restrict__ ds
   double* X = Xs_[slot];
   const int MP = d.MP;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, wr = w >> 1, wc = w & 1;
-  for (int p = d.T - 1; p >= 0; --p) {
+  const int pe = min(p1, d.T);
+  for (int p = pe - 1; p >= p0; --p) {
     d4 acc[2][2];
     tile_zero(acc);
-    // sum_{q>p} R_{p,q} X_q : A(i,k) = R[p*64+i][k], k in [(p+1)*64, MP)
-    tile_mma<false, false>(d.S + (int64_t)(p * 64) * MP, MP, X, 64, 64, 64, 0, 0, (p + 1) * 64, MP, As, Bs, acc);
+    // sum_{p<q<pe} R_{p,q} X_q : A(i,k) = R[p*64+i][k], k in [(p+1)*64, 64 pe)
+    tile_mma<false, false>(d.S + (int64_t)(p * 64) * MP, MP, X, 64, 64, 64, 0, 0, (p + 1) * 64, pe * 64, As, Bs, acc);
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
@@ -1817,9 +1866,24 @@ __global__ __launch_bounds__(256) void k_trsm_un(const DenseSub* __restrict__ ds
     __syncthreads();
   }
 }
-void launch_trsm_un(const DenseSub* d, int nsub, double* const* Bs, double* const* Xs, int tmax, hipStream_t s) {
-  (void)tmax;
-  hipLaunchKernelGGL(k_trsm_un, dim3(nsub), dim3(256), 0, s, d, Bs, Xs);
+void launch_trsm_un(const DenseSub* d, int nsub, double* const* Bs, double* const* Xs, hipStream_t s, int p0, int p1) {
+  hipLaunchKernelGGL(k_trsm_un, dim3(nsub), dim3(256), 0, s, d, Bs, Xs, p0, p1);
+}
+
+// dst[r][c] = src[r][c] (trans = 0) or src[c][r] (trans = 1) for r < rows, c < cols
+__global__ void k_copy_rect(const double* __restrict__ src, int lds, int trans, double* __restrict__ dst, int ldd,
+                            int rows, int cols) {
+  const int64_t n = (int64_t)rows * cols;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const int r = (int)(i / cols), c = (int)(i % cols);
+    dst[(int64_t)r * ldd + c] = trans ? src[(int64_t)c * lds + r] : src[(int64_t)r * lds + c];
+  }
+}
+void launch_copy_rect(const double* src, int lds, int trans, double* dst, int ldd, int rows, int cols, hipStream_t s) {
+  const int64_t n = (int64_t)rows * cols;
+  if (n <= 0) return;
+  const int blocks = (int)std::min<int64_t>((n + 255) / 256, 65536);
+  hipLaunchKernelGGL(k_copy_rect, dim3(blocks), dim3(256), 0, s, src, lds, trans, dst, ldd, rows, cols);
 }
 
 // --------------------------------------------------------------------------------- small eigen
