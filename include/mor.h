@@ -113,7 +113,7 @@ typedef struct {
   int32_t spmm_kind;       /* 0 = automatic (LDS halo tiles, 128-byte slices), 1 = LDS halo tiles with 256-byte
                               column slices, 3 = LDS halo tiles with 128-byte slices, 2 = row tiles
                               (spmm_rows x spmm_vec) */
-  int32_t stream_vec;      /* width of the streaming CG kernels' tiles in units of 64 columns */
+  int32_t stream_vec;      /* width of the streaming CG kernels' tiles in units of 64 columns (0 = 1) */
   int32_t stream_blocks;   /* row aggregates per streaming tile (0 = automatic) */
   int32_t use_graph;       /* capture each CG chunk in a HIP graph and replay it */
   int32_t dense_batch;     /* finished requests gathered before the dense stage runs while others

@@ -6,8 +6,9 @@ with the library's HIP-event timers on its stream:
   1. the SpMM: LDS-halo tiles (halo cap x 256-byte column slices per workgroup) or row tiles
      (rows x width), best algorithmic GB/s;
   2. the streaming (update / direction) tile: width x row aggregates per tile, least time.
-The winner is cached per workload in a JSON file next to this module;
-`best()` returns the cached options (or None).
+The winner is cached per workload in a JSON file next to this module, with a hash of the
+source text of the kernels it tuned; `best()` returns the cached options, or None when there is
+no entry or those kernels have changed since it was measured.
 """
 from __future__ import annotations
 
@@ -21,6 +22,27 @@ CANDIDATES = [(3, 16, 96), (3, 16, 64), (3, 32, 96), (3, 16, 128), (3, 8, 96), (
 # (stream_vec, stream_blocks); the block counts divide the 8-aggregate coarse blocks of the
 # two-level preconditioner (a tile never straddles two blocks), so none is overridden
 STREAM_CANDIDATES = [(2, 4), (2, 8), (1, 4), (1, 8), (4, 4), (4, 8)]
+
+
+# the kernels whose launch shapes the cached options choose
+TUNED_KERNELS = ("k_cg_spmm_halo", "k_cg_spmm", "k_cg_update", "k_cg_direction")
+
+
+def kernel_hash() -> str:
+    """sha256 (16 hex digits) of the tuned kernels' source text in csrc/mor_kernels.hip, each
+    from its `template` line (if any) to the closing brace at column 0."""
+    import hashlib
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc", "mor_kernels.hip")
+    lines = open(path).read().split("\n")
+    h = hashlib.sha256()
+    for name in TUNED_KERNELS:
+        for i, ln in enumerate(lines):
+            if "__global__" in ln and f"void {name}(" in ln:
+                b = i - 1 if i > 0 and lines[i - 1].startswith("template") else i
+                e = next(j for j in range(i, len(lines)) if lines[j] == "}")
+                h.update("\n".join(lines[b:e + 1]).encode())
+                break
+    return h.hexdigest()[:16]
 
 
 def _key(problem, precision):
@@ -37,7 +59,7 @@ def best(problem, precision):
     except (OSError, ValueError):
         return None
     r = d.get(_key(problem, precision))
-    if r is None:
+    if r is None or r.get("src") != kernel_hash():
         return None
     return {k: int(r[k]) for k in ("spmm_kind", "spmm_vec", "spmm_rows", "stream_vec", "stream_blocks") if k in r}
 
@@ -94,7 +116,7 @@ def tune(problem, precision="fp32_refine", sub_ids=None, verbose=True, save=True
                 d = json.load(open(CACHE))
             except (OSError, ValueError):
                 d = {}
-        d[_key(problem, precision)] = dict(win, spmm_all=sp_res, stream_all=st_res)
+        d[_key(problem, precision)] = dict(win, src=kernel_hash(), spmm_all=sp_res, stream_all=st_res)
         with open(CACHE, "w") as f:
             json.dump(d, f, indent=1)
     return win

@@ -19,6 +19,7 @@
 #include <map>
 #include <memory>
 #include <mutex>
+#include <type_traits>
 #include <new>
 #include <stdexcept>
 #include <string>
@@ -1027,7 +1028,8 @@ static int engine_init(mor_ctx* c, MorEngine& e, int elt) {
     if (!fp32 && e.sp.v > 2) e.sp.v = 2;
   }
   e.sp.rb = c->opts.spmm_rows > 0 ? std::min(c->opts.spmm_rows, 64) : 8;
-  e.stm.v = c->opts.stream_vec > 0 ? c->opts.stream_vec : 2;   // block kernels hold 8 rows per lane
+  // block kernels hold 8 rows per lane; 64-column tiles measured fastest (C2, C3, C4 tuner sweeps)
+  e.stm.v = c->opts.stream_vec > 0 ? c->opts.stream_vec : 1;
   if (!fp32 && e.stm.v > 2) e.stm.v = 2;
   e.stm.rb = c->opts.stream_blocks > 0 ? c->opts.stream_blocks : 8;
   // two-level preconditioner: every streaming tile lies inside one coarse block
@@ -1168,13 +1170,21 @@ static int read_counts(mor_ctx* c, MorEngine& e) {
   return 0;
 }
 
+// The coarse products A_c^-1 (P^T r): on the FP32 matrix cores for the FP32 block CG (whose
+// vectors carry FP32 anyway), on the FP64 ones for the FP64 CG.
+template <typename T>
+static void launch_coarse_gemm(const GemmDesc* d, const int4* tiles, int ntiles, hipStream_t s) {
+  if (std::is_same<T, float>::value) launch_gemm32(d, tiles, ntiles, s);
+  else launch_gemm(d, tiles, ntiles, s);
+}
+
 // Two-level preconditioner at a (re)start, after the block-Jacobi start direction: the coarse
 // solve of the restricted residual, its part of r'M^-1 r, and its correction of P.
 template <typename T>
 static void coarse_start(mor_ctx* c, MorEngine& e, const Launch& L) {
   if (L.ngt == 0) return;
   hipStream_t st = c->st;
-  launch_gemm(L.gd, L.gt, L.ngt, st);
+  launch_coarse_gemm<T>(L.gd, L.gt, L.ngt, st);
   launch_cg_coarse_dot(e.d_sys, L.cb, L.ncb, 1, st);
   launch_cg_prolong<T>(e.d_sys, L.bk, L.nbk, e.stm.rb, e.stm.v, st);
 }
@@ -1440,7 +1450,7 @@ static int engine_chunk(mor_ctx* c, MorEngine& e) {
     launch_cg_alpha(e.d_sys, La.cb, La.ncb, s);
     launch_cg_update<T>(e.d_sys, La.bk, La.nbk, e.stm.rb, e.stm.v, s);
     if (La.ngt) {   // two-level preconditioner: coarse solve and its part of r'M^-1 r
-      launch_gemm(La.gd, La.gt, La.ngt, s);
+      launch_coarse_gemm<T>(La.gd, La.gt, La.ngt, s);
       launch_cg_coarse_dot(e.d_sys, La.cb, La.ncb, 0, s);
     }
     launch_cg_beta(e.d_sys, La.cb, La.ncb, s);
@@ -1497,7 +1507,7 @@ static int engine_chunk(mor_ctx* c, MorEngine& e) {
     }
     if (La.ngt) {   // two-level preconditioner: coarse solve and its part of r'M^-1 r
       ScopedTimer tm(c, "cg_coarse", La.coarse_flops);
-      launch_gemm(La.gd, La.gt, La.ngt, st);
+      launch_coarse_gemm<T>(La.gd, La.gt, La.ngt, st);
       launch_cg_coarse_dot(e.d_sys, La.cb, La.ncb, 0, st);
     }
     launch_cg_beta(e.d_sys, La.cb, La.ncb, st);

@@ -1674,6 +1674,89 @@ void launch_gram_bf16(const BfGramDesc* d, const int4* tiles, int ntiles, hipStr
   if (ntiles > 0) hipLaunchKernelGGL(k_gram_bf16, dim3(ntiles), dim3(256), 0, s, d, tiles);
 }
 
+// --------------------------------------------------------------------------------- FP32 MFMA GEMM
+// k_gemm's contract (FP64 operands and result, the same descriptors and tile lists) computed on
+// the FP32 matrix cores: operands rounded to FP32 as they are staged in LDS, FP32 accumulation,
+// C = alpha acc + beta C in FP64.  For the coarse correction of the FP32 block CG, whose vectors
+// are FP32 anyway.  v_mfma_f32_16x16x4f32 takes A and B with k-major lanes as the FP64 tile
+// does, but returns D with lane -> col lane%16, register r -> row 4 (lane/16) + r.
+constexpr int kLdsPad32 = 68;
+
+template <bool TA, bool TB>
+__device__ void gemm32_tile_body(const GemmDesc& g, int ti, int tj, float (*As)[kLdsPad32], float (*Bs)[kLdsPad32]) {
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, wr = w >> 1, wc = w & 1;
+  const int i0 = ti * 64, j0 = tj * 64;
+  f4 acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+  double ra[4], rb[4];
+  if (g.k > 0) tile_fetch<TA, TB>(g.A, g.lda, g.B, g.ldb, g.m, g.n, i0, j0, 0, g.k, ra, rb);
+  for (int k0 = 0; k0 < g.k; k0 += 16) {
+    if (!TA) {
+      const int i = tid >> 2, kk = (tid & 3) * 4;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) As[kk + q][i] = (float)ra[q];
+    } else {
+      const int kk = tid >> 4, i = (tid & 15) * 4;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) As[kk][i + q] = (float)ra[q];
+    }
+    if (!TB) {
+      const int kk = tid >> 4, j = (tid & 15) * 4;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) Bs[kk][j + q] = (float)rb[q];
+    } else {
+      const int j = tid >> 2, kk = (tid & 3) * 4;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) Bs[kk + q][j] = (float)rb[q];
+    }
+    __syncthreads();
+    if (k0 + 16 < g.k) tile_fetch<TA, TB>(g.A, g.lda, g.B, g.ldb, g.m, g.n, i0, j0, k0 + 16, g.k, ra, rb);
+#pragma unroll
+    for (int s4 = 0; s4 < 4; ++s4) {
+      const int kr = s4 * 4 + (lane >> 4);
+      const float a0 = As[kr][wr * 32 + (lane & 15)];
+      const float a1 = As[kr][wr * 32 + 16 + (lane & 15)];
+      const float b0 = Bs[kr][wc * 32 + (lane & 15)];
+      const float b1 = Bs[kr][wc * 32 + 16 + (lane & 15)];
+      acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b0, acc[0][0], 0, 0, 0);
+      acc[0][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b1, acc[0][1], 0, 0, 0);
+      acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b0, acc[1][0], 0, 0, 0);
+      acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b1, acc[1][1], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = i0 + wr * 32 + a * 16 + 4 * (lane >> 4) + r;
+        const int j = j0 + wc * 32 + b * 16 + (lane & 15);
+        if (i < g.m && j < g.n) {
+          double* p = g.C + (int64_t)i * g.ldc + j;
+          const double v = g.alpha * (double)acc[a][b][r];
+          *p = (g.beta == 0.0) ? v : v + g.beta * *p;
+        }
+      }
+}
+
+__global__ __launch_bounds__(256) void k_gemm32(const GemmDesc* __restrict__ descs, const int4* __restrict__ tiles) {
+  __shared__ float As[16][kLdsPad32], Bs[16][kLdsPad32];
+  const int4 tl = tiles[blockIdx.x];
+  const GemmDesc& g = descs[tl.x];
+  if (!g.ta && !g.tb) gemm32_tile_body<false, false>(g, tl.y, tl.z, As, Bs);
+  else if (g.ta && !g.tb) gemm32_tile_body<true, false>(g, tl.y, tl.z, As, Bs);
+  else if (!g.ta && g.tb) gemm32_tile_body<false, true>(g, tl.y, tl.z, As, Bs);
+  else gemm32_tile_body<true, true>(g, tl.y, tl.z, As, Bs);
+}
+void launch_gemm32(const GemmDesc* d, const int4* tiles, int ntiles, hipStream_t s) {
+  if (ntiles > 0) hipLaunchKernelGGL(k_gemm32, dim3(ntiles), dim3(256), 0, s, d, tiles);
+}
+
 // --------------------------------------------------------------------------------- Cholesky
 // Right-looking blocked Cholesky S = R^T R (R upper) of every subdomain's padded S_B.
 __global__ __launch_bounds__(256) void k_potrf_diag(const DenseSub* __restrict__ ds, int p) {
