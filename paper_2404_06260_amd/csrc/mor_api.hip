@@ -1134,8 +1134,11 @@ static int engine_upload(mor_ctx* c, MorEngine& e, Launch& L) {
   GemmBatch gb;
   for (int i = 0; i < n; ++i) {
     const CgSys& S = hs[i];
-    if (S.rc != nullptr)
-      gb.add(gd(S.nc, S.ld, S.nc, L.sys[i]->Ainv, L.sys[i]->ldac, 0, S.rc, S.ld, 0, S.ec, S.ld));
+    if (S.rc != nullptr) {   // converged columns (alpha 0) need no coarse correction
+      GemmDesc g = gd(S.nc, S.ld, S.nc, L.sys[i]->Ainv, L.sys[i]->ldac, 0, S.rc, S.ld, 0, S.ec, S.ld);
+      g.skip = S.alpha;
+      gb.add(g);
+    }
   }
   L.ngt = (int)gb.tiles.size();
   L.coarse_flops = gb.flops();
@@ -1172,10 +1175,12 @@ static int read_counts(mor_ctx* c, MorEngine& e) {
 
 // The coarse products A_c^-1 (P^T r): on the FP32 matrix cores for the FP32 block CG (whose
 // vectors carry FP32 anyway), on the FP64 ones for the FP64 CG.
+// In the iterations (in_loop) the columns that have converged (alpha 0) are skipped; at a
+// (re)start every column is computed (alpha is not yet set).
 template <typename T>
-static void launch_coarse_gemm(const GemmDesc* d, const int4* tiles, int ntiles, hipStream_t s) {
-  if (std::is_same<T, float>::value) launch_gemm32(d, tiles, ntiles, s);
-  else launch_gemm(d, tiles, ntiles, s);
+static void launch_coarse_gemm(const GemmDesc* d, const int4* tiles, int ntiles, hipStream_t s, int in_loop) {
+  if (std::is_same<T, float>::value) launch_gemm32(d, tiles, ntiles, s, in_loop);
+  else launch_gemm(d, tiles, ntiles, s, in_loop);
 }
 
 // Two-level preconditioner at a (re)start, after the block-Jacobi start direction: the coarse
@@ -1184,7 +1189,7 @@ template <typename T>
 static void coarse_start(mor_ctx* c, MorEngine& e, const Launch& L) {
   if (L.ngt == 0) return;
   hipStream_t st = c->st;
-  launch_coarse_gemm<T>(L.gd, L.gt, L.ngt, st);
+  launch_coarse_gemm<T>(L.gd, L.gt, L.ngt, st, 0);
   launch_cg_coarse_dot(e.d_sys, L.cb, L.ncb, 1, st);
   launch_cg_prolong<T>(e.d_sys, L.bk, L.nbk, e.stm.rb, e.stm.v, st);
 }
@@ -1450,7 +1455,7 @@ static int engine_chunk(mor_ctx* c, MorEngine& e) {
     launch_cg_alpha(e.d_sys, La.cb, La.ncb, s);
     launch_cg_update<T>(e.d_sys, La.bk, La.nbk, e.stm.rb, e.stm.v, s);
     if (La.ngt) {   // two-level preconditioner: coarse solve and its part of r'M^-1 r
-      launch_coarse_gemm<T>(La.gd, La.gt, La.ngt, s);
+      launch_coarse_gemm<T>(La.gd, La.gt, La.ngt, s, 1);
       launch_cg_coarse_dot(e.d_sys, La.cb, La.ncb, 0, s);
     }
     launch_cg_beta(e.d_sys, La.cb, La.ncb, s);
@@ -1507,7 +1512,7 @@ static int engine_chunk(mor_ctx* c, MorEngine& e) {
     }
     if (La.ngt) {   // two-level preconditioner: coarse solve and its part of r'M^-1 r
       ScopedTimer tm(c, "cg_coarse", La.coarse_flops);
-      launch_coarse_gemm<T>(La.gd, La.gt, La.ngt, st);
+      launch_coarse_gemm<T>(La.gd, La.gt, La.ngt, st, 1);
       launch_cg_coarse_dot(e.d_sys, La.cb, La.ncb, 0, st);
     }
     launch_cg_beta(e.d_sys, La.cb, La.ncb, st);

@@ -116,6 +116,7 @@ struct GemmDesc {
   double* C; int ldc;
   double alpha, beta;
   int sym;             // compute tiles ti <= tj only, write both triangles (beta must be 0)
+  const double* skip = nullptr;   // or: output columns j with skip[j] == 0 need not be computed
 };
 
 // ---------------------------------------------------------------------------------
@@ -178,9 +179,10 @@ void launch_split_bf16(const SplitDesc* d, const int4* tiles, int ntiles, hipStr
 void launch_gram_bf16(const BfGramDesc* d, const int4* tiles, int ntiles, hipStream_t s);
 void launch_spmm64_rows(const int* rp, const int* col, const double* val, int nrows, int col_limit,
                         const double* X, int ldx, int ncols, double* Y, int ldy, hipStream_t s);
-void launch_gemm(const GemmDesc* d, const int4* tiles, int ntiles, hipStream_t s);
+// use_skip: honour GemmDesc::skip
+void launch_gemm(const GemmDesc* d, const int4* tiles, int ntiles, hipStream_t s, int use_skip = 0);
 // k_gemm's contract on the FP32 matrix cores (FP64 operands rounded to FP32, FP32 accumulation)
-void launch_gemm32(const GemmDesc* d, const int4* tiles, int ntiles, hipStream_t s);
+void launch_gemm32(const GemmDesc* d, const int4* tiles, int ntiles, hipStream_t s, int use_skip = 0);
 void launch_schur(const int* rp, const int* col, const double* Kval, int nI, int nB, const double* E, int lde,
                   double* S, int lds, hipStream_t s);
 void launch_pad_identity(double* S, int M, int MP, hipStream_t s);

@@ -570,6 +570,8 @@ __global__ __launch_bounds__(256) void k_cg_spmm_box(const CgSys* __restrict__ s
   const int ld = S.ld, nz = S.bz;
   const int tid = threadIdx.x;
   const int col = tid & 31, yy = tid >> 5;        // this thread: column c0 + col, footprint row yy
+  // a slice whose columns have all converged is skipped (their alpha is 0: Q is not read)
+  if (!__syncthreads_or(c0 + col < ld && S.active[c0 + col] != 0)) return;
   // P slot of plane z: (z + 3) % 3 (plane -1 is zeros); coefficient and row-id slot: z % 2
   BoxRows q;
   BoxPlane A, B;
@@ -804,6 +806,8 @@ __global__ __launch_bounds__(256) void k_cg_update(const CgSys* __restrict__ sys
     part[q] = cs[q] = 0.0;
     al[q] = act ? (T)S.alpha[c0 + q] : (T)0;
   }
+  // (no skip of converged columns here: the tiles are short, and waiting for alpha before the
+  // first loads cost more than the skipped columns saved)
   if (act) {
     for (int b = tl.y + w; b < bend; b += 4) {
       const int r0 = gld(S.bp + b), nb = gld(S.bp + b + 1) - r0;
@@ -852,6 +856,12 @@ __global__ __launch_bounds__(256) void k_cg_direction(const CgSys* __restrict__ 
   for (int q = 0; q < V; ++q) {
     be[q] = (T)S.beta[c0 + q];
     al[q] = (T)S.alpha[c0 + q];
+  }
+  {   // converged columns (alpha 0) keep X; their P is rebuilt at the next restart
+    int any = 0;
+#pragma unroll
+    for (int q = 0; q < V; ++q) any |= al[q] != (T)0;
+    if (!any) return;
   }
   for (int b = tl.y + w; b < bend; b += 4) {
     const int r0 = gld(S.bp + b), nb = gld(S.bp + b + 1) - r0;
@@ -1455,8 +1465,18 @@ __device__ __forceinline__ void tile_store_sym(double* C, int ldc, int m, int i0
       }
 }
 
+// With use_skip, a tile whose output columns all have skip[j] == 0 is left alone (uniform over
+// the workgroup).
+__device__ __forceinline__ bool gemm_tile_skipped(const GemmDesc& g, int tj, int use_skip) {
+  if (!use_skip || g.skip == nullptr) return false;
+  const int j = tj * 64 + (threadIdx.x & 63);
+  return !__syncthreads_or(j < g.n && g.skip[j] != 0.0);
+}
+
 template <bool TA, bool TB>
-__device__ void gemm_tile_body(const GemmDesc& g, int ti, int tj, double (*As)[kLdsPad], double (*Bs)[kLdsPad]) {
+__device__ void gemm_tile_body(const GemmDesc& g, int ti, int tj, double (*As)[kLdsPad], double (*Bs)[kLdsPad],
+                               int use_skip) {
+  if (gemm_tile_skipped(g, tj, use_skip)) return;
   d4 acc[2][2];
   tile_zero(acc);
   tile_mma<TA, TB>(g.A, g.lda, g.B, g.ldb, g.m, g.n, ti * 64, tj * 64, 0, g.k, As, Bs, acc);
@@ -1467,17 +1487,18 @@ __device__ void gemm_tile_body(const GemmDesc& g, int ti, int tj, double (*As)[k
 // Tiles are listed column tile fastest and dealt round-robin over the XCDs, so that the tiles an
 // XCD runs together share their A row panel in its L2 (grouping consecutive tiles on one XCD
 // instead measured slower on the coarse products, whose panels do not fit in L2 either way).
-__global__ __launch_bounds__(256) void k_gemm(const GemmDesc* __restrict__ descs, const int4* __restrict__ tiles) {
+__global__ __launch_bounds__(256) void k_gemm(const GemmDesc* __restrict__ descs, const int4* __restrict__ tiles,
+                                              int use_skip) {
   __shared__ double As[16][kLdsPad], Bs[16][kLdsPad];
   const int4 tl = tiles[blockIdx.x];
   const GemmDesc& g = descs[tl.x];
-  if (!g.ta && !g.tb) gemm_tile_body<false, false>(g, tl.y, tl.z, As, Bs);
-  else if (g.ta && !g.tb) gemm_tile_body<true, false>(g, tl.y, tl.z, As, Bs);
-  else if (!g.ta && g.tb) gemm_tile_body<false, true>(g, tl.y, tl.z, As, Bs);
-  else gemm_tile_body<true, true>(g, tl.y, tl.z, As, Bs);
+  if (!g.ta && !g.tb) gemm_tile_body<false, false>(g, tl.y, tl.z, As, Bs, use_skip);
+  else if (g.ta && !g.tb) gemm_tile_body<true, false>(g, tl.y, tl.z, As, Bs, use_skip);
+  else if (!g.ta && g.tb) gemm_tile_body<false, true>(g, tl.y, tl.z, As, Bs, use_skip);
+  else gemm_tile_body<true, true>(g, tl.y, tl.z, As, Bs, use_skip);
 }
-void launch_gemm(const GemmDesc* d, const int4* tiles, int ntiles, hipStream_t s) {
-  if (ntiles > 0) hipLaunchKernelGGL(k_gemm, dim3(ntiles), dim3(256), 0, s, d, tiles);
+void launch_gemm(const GemmDesc* d, const int4* tiles, int ntiles, hipStream_t s, int use_skip) {
+  if (ntiles > 0) hipLaunchKernelGGL(k_gemm, dim3(ntiles), dim3(256), 0, s, d, tiles, use_skip);
 }
 
 // ------------------------------------------------------------------------ randomized variant
@@ -1683,7 +1704,9 @@ void launch_gram_bf16(const BfGramDesc* d, const int4* tiles, int ntiles, hipStr
 constexpr int kLdsPad32 = 68;
 
 template <bool TA, bool TB>
-__device__ void gemm32_tile_body(const GemmDesc& g, int ti, int tj, float (*As)[kLdsPad32], float (*Bs)[kLdsPad32]) {
+__device__ void gemm32_tile_body(const GemmDesc& g, int ti, int tj, float (*As)[kLdsPad32], float (*Bs)[kLdsPad32],
+                                 int use_skip) {
+  if (gemm_tile_skipped(g, tj, use_skip)) return;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, wr = w >> 1, wc = w & 1;
   const int i0 = ti * 64, j0 = tj * 64;
   f4 acc[2][2];
@@ -1744,17 +1767,18 @@ __device__ void gemm32_tile_body(const GemmDesc& g, int ti, int tj, float (*As)[
       }
 }
 
-__global__ __launch_bounds__(256) void k_gemm32(const GemmDesc* __restrict__ descs, const int4* __restrict__ tiles) {
+__global__ __launch_bounds__(256) void k_gemm32(const GemmDesc* __restrict__ descs, const int4* __restrict__ tiles,
+                                                int use_skip) {
   __shared__ float As[16][kLdsPad32], Bs[16][kLdsPad32];
   const int4 tl = tiles[blockIdx.x];
   const GemmDesc& g = descs[tl.x];
-  if (!g.ta && !g.tb) gemm32_tile_body<false, false>(g, tl.y, tl.z, As, Bs);
-  else if (g.ta && !g.tb) gemm32_tile_body<true, false>(g, tl.y, tl.z, As, Bs);
-  else if (!g.ta && g.tb) gemm32_tile_body<false, true>(g, tl.y, tl.z, As, Bs);
-  else gemm32_tile_body<true, true>(g, tl.y, tl.z, As, Bs);
+  if (!g.ta && !g.tb) gemm32_tile_body<false, false>(g, tl.y, tl.z, As, Bs, use_skip);
+  else if (g.ta && !g.tb) gemm32_tile_body<true, false>(g, tl.y, tl.z, As, Bs, use_skip);
+  else if (!g.ta && g.tb) gemm32_tile_body<false, true>(g, tl.y, tl.z, As, Bs, use_skip);
+  else gemm32_tile_body<true, true>(g, tl.y, tl.z, As, Bs, use_skip);
 }
-void launch_gemm32(const GemmDesc* d, const int4* tiles, int ntiles, hipStream_t s) {
-  if (ntiles > 0) hipLaunchKernelGGL(k_gemm32, dim3(ntiles), dim3(256), 0, s, d, tiles);
+void launch_gemm32(const GemmDesc* d, const int4* tiles, int ntiles, hipStream_t s, int use_skip) {
+  if (ntiles > 0) hipLaunchKernelGGL(k_gemm32, dim3(ntiles), dim3(256), 0, s, d, tiles, use_skip);
 }
 
 // --------------------------------------------------------------------------------- Cholesky
