@@ -293,6 +293,61 @@ def reduce_local_sketched(mesh, kappa, f_nodal, sets: decomp.LocalSets, rank: in
     return res
 
 
+def reduce_local_sketched_solves(mesh, kappa, f_nodal, sets: decomp.LocalSets, rank: int | None,
+                                 tol: float | None, omega: np.ndarray, keep: bool = False):
+    """The randomized variant of step 2 (Section 6) with the weights applied through sparse
+    solves, so that no solve carries M_i right-hand sides and no M_i x M_i matrix is formed.
+
+    The weight R_BB (Lemma 4.1: S_B = R_BB^T R_BB) enters only as R_BB^{-1} on the right of the
+    weighted lifting operator, and the inverse of the Schur complement is the B block of the
+    inverse of K^+ (Lemma 4.1 with B ordered last), so S_B^{-1} v = [(K^+)^{-1} [0; v]]_B.
+    omega is the random matrix (M_i x l, rows in the order of B), an input here.
+      1. sketch: T = S_B^{-1} omega (l solves with K^+), and Qhat Rhat = R_i C A_II^{-1}(-A_IB) T;
+         this is the paper's sketch with S_i = R_BB^{-T} omega (R_BB^{-1} S_i = S_B^{-1} omega);
+      2. W = Qhat^T R_i C A_II^{-1}(-A_IB) by the left solve (l right-hand sides), as in
+         reduce_local_sketched;
+      3. B = W R_BB^{-1} has B B^T = W S_B^{-1} W^T, with S_B^{-1} W^T from l more solves with
+         K^+; its eigenpairs give sigma^2 and the left singular vectors Uhat of B, which do not
+         depend on how S_B is factored;
+      4. the truncation and the basis R_i^{-1} Qhat Uhat_k, stitched and projected as in the
+         explicit path; q_0 from the zero-boundary load problem.
+    """
+    lm = local_matrices(mesh, kappa, f_nodal, sets)
+    A_II, A_IB, A_BI, _ = blocks(lm.A_plus, lm.nI)
+    lu = spla.splu(A_II)
+    luK = spla.splu(lm.K_plus.tocsc())
+    R_i = la.cholesky(lm.K_i.toarray(), lower=False)
+
+    def sb_inv(V):                                               # S_B^{-1} V, V: M x l
+        rhs = np.zeros((lm.nI + lm.nB, V.shape[1]))
+        rhs[lm.nI:] = V
+        return luK.solve(rhs)[lm.nI:]
+
+    # 1. sketch and its QR
+    T = sb_inv(omega)
+    Xs = lu.solve(-(A_IB @ T))                                    # A_II^{-1} (-A_IB) T
+    Qh, _ = la.qr(R_i @ Xs[lm.C_idx], mode="economic")
+    # 2. W^T = (-A_IB)^T A_II^{-T} (Qhat^T R_i C)^T by the left solve
+    L = np.zeros((lm.nI, Qh.shape[1]))
+    L[lm.C_idx] = R_i.T @ Qh
+    G = lu.solve(L, trans="T")
+    Wt = -(A_BI @ G)                                              # A_IB^T = A_BI (A^+ symmetric)
+    # 3. B B^T = W S_B^{-1} W^T and its eigenpairs (descending)
+    BBt = Wt.T @ sb_inv(Wt)
+    lam, U = la.eigh(0.5 * (BBt + BBt.T))
+    order = np.argsort(lam)[::-1]
+    lam, U = lam[order], U[:, order]
+    s = np.sqrt(np.maximum(lam, 0.0))
+    k = truncation_rank(s, rank, tol)
+    # 4. basis, stitching, projection
+    Phi = la.solve_triangular(R_i, Qh @ U[:, :k], lower=False)
+    q0 = lu.solve(lm.f_plus[:lm.nI])[lm.C_idx]
+    res = _stitch_and_project(lm, sets, s, k, q0, Phi)
+    if keep:
+        return res, dict(lm=lm, Qh=Qh, BBt=BBt, T=T)
+    return res
+
+
 # ----------------------------------------------------------------------------------
 # whole-problem driver (serial, or a process pool over subdomains)
 
@@ -304,24 +359,28 @@ def _work(i):
     r = p.ranks[i] if (p.ranks is not None and rank is None) else rank
     r = int(r) if r is not None else None
     if _G.get("sketches") is not None:
-        return reduce_local_sketched(p.mesh, p.kappa, p.f_nodal, sets[i], r, tol, _G["sketches"][i])
+        route = reduce_local_sketched_solves if _G.get("sketch_solves") else reduce_local_sketched
+        return route(p.mesh, p.kappa, p.f_nodal, sets[i], r, tol, _G["sketches"][i])
     if _G.get("implicit"):
         return reduce_local_implicit(p.mesh, p.kappa, p.f_nodal, sets[i], r, tol)
     return reduce_local(p.mesh, p.kappa, p.f_nodal, sets[i], r, tol)
 
 
 def reduce_all(problem, rank: int | None = None, tol: float | None = None, workers: int = 1,
-               subset=None, sketches=None, implicit: bool = False, order=None) -> list[LocalResult]:
+               subset=None, sketches=None, implicit: bool = False, order=None,
+               sketch_solves: bool = False) -> list[LocalResult]:
     """Every subdomain's local reduction (explicit; through the pencil's sparse factors when
     `implicit`, for subdomains too large for the dense matrices; the randomized variant when
-    `sketches` holds one random matrix per subdomain).  `order`, if given, is the order in which
+    `sketches` holds one random matrix per subdomain, with the weights applied by K^+ solves
+    when `sketch_solves`).  `order`, if given, is the order in which
     a process pool takes the subdomains up (largest first keeps the pool busy to the end); the
     results are always returned in subdomain order."""
     sets = decomp.all_local_sets(problem.mesh, problem.subdomains)
     if rank is None and tol is None and problem.ranks is None:
         rank = problem.rank
     idx = list(range(problem.subdomains.n_sub)) if subset is None else list(subset)
-    _G.update(p=problem, sets=sets, rank=rank, tol=tol, sketches=sketches, implicit=implicit)
+    _G.update(p=problem, sets=sets, rank=rank, tol=tol, sketches=sketches, implicit=implicit,
+              sketch_solves=sketch_solves)
     if workers <= 1:
         return [_work(i) for i in idx]
     import multiprocessing as mp

@@ -214,6 +214,51 @@ def test_full_width_gaussian_sketch_is_exact_and_narrow_sketches_interlace():
         prev = sk.sigma
 
 
+def _span_residual(A, B):
+    """How far the columns of B lie outside span(A), relative to |B|."""
+    P = A @ np.linalg.lstsq(A, B, rcond=None)[0]
+    return np.linalg.norm(P - B) / np.linalg.norm(B)
+
+
+def test_solve_route_of_the_sketch_is_the_papers_sketch_of_a_correlated_test_matrix():
+    """The route with the weights applied by K^+ solves, driven by omega = R_BB^T S_i, is the
+    paper's sketched SVD driven by S_i: S_B^{-1} R_BB^T S_i = R_BB^{-1} S_i with R_BB from a dense
+    Cholesky of the explicit Schur complement (Lemma 4.1), and B B^T = W S_B^{-1} W^T has the
+    squares of the singular values of B = W R_BB^{-1}."""
+    p, s = _sketch_case()
+    lm = reduce.local_matrices(p.mesh, p.kappa, p.f_nodal, s)
+    R_BB = la.cholesky(reduce.schur_H1(lm), lower=False)
+    S = w.sketch_rows(p.mesh.n_nodes, s.B, 24, 0)
+    old = reduce.reduce_local_sketched(p.mesh, p.kappa, p.f_nodal, s, 5, None, S)
+    new = reduce.reduce_local_sketched_solves(p.mesh, p.kappa, p.f_nodal, s, 5, None, R_BB.T @ S)
+    np.testing.assert_allclose(new.sigma, old.sigma, rtol=1e-9, atol=1e-12 * old.sigma[0])
+    assert new.k_eff == old.k_eff
+    np.testing.assert_allclose(new.q0, old.q0, rtol=0, atol=1e-12 * np.abs(old.q0).max())
+    assert _span_residual(new.Phi, old.Phi) < 1e-8
+
+
+def test_solve_route_is_exact_at_full_width_and_interlaces_below():
+    """A Gaussian omega with M_i columns makes T = S_B^{-1} omega span R^M, so the result is the
+    explicit SVD; narrower sketches give singular values no larger than the exact ones (Qhat has
+    orthonormal columns), nondecreasing as the sketch widens."""
+    p, s = _sketch_case()
+    M = s.B.size
+    ex = reduce.reduce_local(p.mesh, p.kappa, p.f_nodal, s, 5)
+    om = w.sketch_rows(p.mesh.n_nodes, s.B, M, 1)
+    full = reduce.reduce_local_sketched_solves(p.mesh, p.kappa, p.f_nodal, s, 5, None, om)
+    np.testing.assert_allclose(full.sigma[:20], ex.sigma[:20], rtol=1e-8)
+    assert full.k_eff == ex.k_eff
+    assert _span_residual(full.Phi, ex.Phi) < 1e-8
+    prev = None
+    for l in (8, 24, 64):
+        sk = reduce.reduce_local_sketched_solves(p.mesh, p.kappa, p.f_nodal, s, 5, None, om[:, :l])
+        assert sk.sigma.size == l
+        assert np.all(sk.sigma <= ex.sigma[:l] * (1 + 1e-10))
+        if prev is not None:
+            assert np.all(sk.sigma[:prev.size] >= prev * (1 - 1e-10))
+        prev = sk.sigma
+
+
 @pytest.mark.parametrize("kappa", ["one", "lognormal"])
 def test_rank_of_the_lifting_equals_the_boundary_dofs_of_omega_i(kappa):
     """The spectrum of the weighted lifting operator reaches rounding at the number of interface
