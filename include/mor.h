@@ -194,9 +194,12 @@ int mor_local_basis_batch(mor_ctx* ctx, int32_t n, const int32_t* sds, const int
                           const double* tols, int32_t* k_eff_out);
 
 /* The randomized local reduction of Section 6 ("Randomized numerical linear algebra"): the
- * sketch Qhat Rhat = R_i C_i A_II^-1 A_IB R_BB^-1 S_i, then the SVD of Qhat^T (weighted Z_i)
- * evaluated with two left solves, so that the A_II solves carry l + 1 and then l right-hand
- * sides instead of M_i + 1.  The H1 solve for S_B keeps all M_i columns.
+ * sketch Qhat Rhat = R_i C_i A_II^-1 A_IB T, then the SVD of B = Qhat^T (weighted Z_i)
+ * evaluated with two left solves.  The weight R_BB (S_B = R_BB^T R_BB, Lemma 4.1) is applied
+ * through solves with the H1 matrix K^+ on all of omega_i^+, whose inverse has S_B^-1 as its
+ * B block: the sketch is T = S_B^-1 S_i (the paper's R_BB^-1 S_i' for S_i' = R_BB^-T S_i), and
+ * B B^T = W S_B^-1 W^T gives the singular values.  Every solve carries l or l + 1 right-hand
+ * sides (two with A_II, two with K^+), and no M_i x M_i matrix is formed.
  * sds, ranks, tols: n values each, host (tols may be NULL), as in mor_local_basis_batch.
  * l: sketch columns, 1..64.  omega[i]: the random matrix S_i of subdomain sds[i], host, M_i x l
  * row-major with rows in the order of the subdomain's interface nodes B (ascending global id;

@@ -100,6 +100,8 @@ struct TimerRec {
 
 struct SubDev {
   int *rp = nullptr, *col = nullptr, *ii_end = nullptr, *rpV = nullptr, *colV = nullptr, *bp = nullptr;
+  int* bpL = nullptr;   // aggregates of all local rows (the K^+ systems of the randomized variant)
+  int* rcbL = nullptr;  // their coarse blocks, per local row
   int *ltet = nullptr, *tetg = nullptr, *nodes = nullptr, *htile = nullptr, *halo = nullptr;
   int *hrowp = nullptr, *hpe = nullptr;
   uint16_t *hpp = nullptr, *hself = nullptr;
@@ -430,6 +432,8 @@ static int create_impl(const mor_mesh* mesh, const mor_coeff* coeff, const mor_s
     r = r ? r : upload(c, &d.nodes, h.nodes.data(), h.nodes.size());
     r = r ? r : upload(c, &d.core, h.core.data(), h.core.size());
     r = r ? r : upload(c, &d.bp, h.bp.data(), h.bp.size());
+    r = r ? r : upload(c, &d.bpL, h.bpL.data(), h.bpL.size());
+    r = r ? r : upload(c, &d.rcbL, h.rcbL.data(), h.rcbL.size());
     r = r ? r : upload(c, &d.htile, h.htile.data(), h.htile.size());
     r = r ? r : upload(c, &d.halo, h.halo.data(), h.halo.size());
     r = r ? r : upload(c, &d.hrowp, h.hrowp.data(), h.hrowp.size());
@@ -787,13 +791,15 @@ struct Slot {
   bool box;                      // the plane-streaming SpMM serves this request's systems
   int ls, rk;                    // sketch columns; directions kept by the K_i-orthonormalisation
   double *Fd;                    // dense FP64 right-hand sides of the A solves, nI x ldA
+  double *FdK;                   // dense FP64 right-hand sides [0; V] of the K^+ solves, nL x ldK
   double *q0v;                   // zero-boundary load solution on V_i
   double *Yk, *Wt, *KWt, *Vs;    // K_i Y, the K_i-orthonormal sketch basis W and K_i W (nV x 64); 64 x 64
   int* info;
   int k_eff;
   // two-level preconditioner (nc > 0): per system P^T r and A_c^-1 P^T r (nc x ld), A_c and then
   // A_c^-1 (MPc x MPc), R^-T (MPc x MPc), the Cholesky diagonal-block inverses, pivot reports
-  int nc, MPc, Tc;
+  // (per system: the K^+ system of the randomized variant has its own coarse blocks)
+  int nc[2], MPc[2], Tc[2];
   double *crc[2], *cec[2], *cA[2], *cY[2], *cD[2];
   int* cinfo;
 };
@@ -807,7 +813,9 @@ static void slot_shape(mor_ctx* c, Slot& q) {
   // the column slices of the CG kernels never straddle a line they only partly use
   q.colsA = q.ls > 0 ? q.ls + 1 : h.nB + 1;   // sketch + load columns, or every interface column + load
   q.ldA = (int)rup(q.colsA, 32);
-  q.colsK = h.nB;
+  // the K system: the H1 solve with every interface column, or (randomized variant) the K^+
+  // solves on all local rows with the sketch's columns
+  q.colsK = q.ls > 0 ? q.ls : h.nB;
   q.ldK = (int)rup(q.colsK, 32);
   const int p = c->opts.oversample > 0 ? c->opts.oversample : std::max(8, q.rank);
   int s = q.rank > 0 && q.ls == 0 ? std::min(64, q.rank + p) : 64;
@@ -821,9 +829,13 @@ static void slot_shape(mor_ctx* c, Slot& q) {
   q.box = q.fp32 && c->opts.box_spmm >= 0 && c->opts.spmm_kind != 2 && !h.smap.empty() && q.d != nullptr &&
           q.d->smap != nullptr;
   const int nblk = (int)h.bp.size() - 1;
-  q.nc = c->opts.coarse ? (nblk + kCoarseAgg - 1) / kCoarseAgg : 0;
-  q.MPc = (int)rup(std::max(q.nc, 1), 64);
-  q.Tc = q.MPc / 64;
+  const int nblkK = q.ls > 0 ? (int)h.bpL.size() - 1 : nblk;
+  for (int w = 0; w < 2; ++w) {
+    const int nb = w == 0 ? nblk : nblkK;
+    q.nc[w] = c->opts.coarse ? (nb + kCoarseAgg - 1) / kCoarseAgg : 0;
+    q.MPc[w] = (int)rup(std::max(q.nc[w], 1), 64);
+    q.Tc[w] = q.MPc[w] / 64;
+  }
 }
 
 // Device bytes of one request (CG blocks, dense matrices, eigensolver blocks), and the carve.
@@ -840,13 +852,14 @@ static bool slot_layout(Slot& q, Take tk) {
   const bool box = q.fp32 && q.box;
   q.s16A = box ? (float*)tk(4 * (size_t)kStencil * h.nI) : nullptr;
   q.s16K = box ? (float*)tk(4 * (size_t)kStencil * h.nI) : nullptr;
-  q.minvA = tk(elt * h.nI * 8); q.minvK = tk(elt * h.nI * 8);
+  const size_t rowsK = q.ls > 0 ? (size_t)h.nL : (size_t)h.nI;   // K^+ on all local rows, or K_II
+  q.minvA = tk(elt * h.nI * 8); q.minvK = tk(elt * rowsK * 8);
   q.XA = tk(elt * h.nI * q.ldA); q.RA = tk(elt * h.nI * q.ldA);
   q.PA = tk(elt * h.nI * q.ldA); q.QA = tk(elt * h.nI * q.ldA);
-  q.XK = tk(elt * h.nI * q.ldK); q.RK = tk(elt * h.nI * q.ldK);
-  q.PK = tk(elt * h.nI * q.ldK); q.QK = tk(elt * h.nI * q.ldK);
+  q.XK = tk(elt * rowsK * q.ldK); q.RK = tk(elt * rowsK * q.ldK);
+  q.PK = tk(elt * rowsK * q.ldK); q.QK = tk(elt * rowsK * q.ldK);
   q.XA64 = q.refine ? (double*)tk(8 * (size_t)h.nI * q.ldA) : nullptr;
-  q.XK64 = q.refine ? (double*)tk(8 * (size_t)h.nI * q.ldK) : nullptr;
+  q.XK64 = q.refine ? (double*)tk(8 * rowsK * q.ldK) : nullptr;
   q.colst[0] = (double*)tk(8 * 8 * (size_t)q.ldA + 64);
   q.colst[1] = (double*)tk(8 * 8 * (size_t)q.ldK + 64);
   if (q.fp32 && !q.refine) {
@@ -864,11 +877,12 @@ static bool slot_layout(Slot& q, Take tk) {
   q.MB = (int)rup(q.M, 128);
   if (sk) {
     q.Fd = (double*)tk(8 * (size_t)h.nI * q.ldA);
+    q.FdK = (double*)tk(8 * rowsK * q.ldK);
     q.q0v = (double*)tk(8 * (size_t)std::max(h.nV, 1));
     q.Yk = (double*)tk(8 * (size_t)h.nV * 64); q.Wt = (double*)tk(8 * (size_t)h.nV * 64);
     q.KWt = (double*)tk(8 * (size_t)h.nV * 64); q.Vs = (double*)tk(8 * 64 * 64);
   } else {
-    q.Fd = q.q0v = q.Yk = q.Wt = q.KWt = q.Vs = nullptr;
+    q.Fd = q.FdK = q.q0v = q.Yk = q.Wt = q.KWt = q.Vs = nullptr;
   }
   if (q.prec == MOR_BF16_SPLIT && !sk) {
     const size_t b = 2 * (size_t)q.MB * q.kpV;
@@ -877,12 +891,12 @@ static bool slot_layout(Slot& q, Take tk) {
   } else {
     q.Xh = q.Xl = q.Yh = q.Yl = nullptr;
   }
-  q.S = (double*)tk(8 * (size_t)q.MP * q.MP);
+  q.S = sk ? nullptr : (double*)tk(8 * (size_t)q.MP * q.MP);   // the randomized variant forms no M x M matrix
   q.G = sk ? nullptr : (double*)tk(8 * (size_t)q.MP * q.MP);
   q.W = sk ? nullptr : (double*)tk(8 * (size_t)q.MP * q.MP);
   q.C = sk ? nullptr : (double*)tk(8 * (size_t)q.MP * q.MP);
-  q.Dinv = (double*)tk(8 * (size_t)q.T * 4096);
-  q.Vb = (double*)tk(8 * (size_t)q.MP * s); q.Yb = (double*)tk(8 * (size_t)q.MP * s);
+  q.Dinv = sk ? nullptr : (double*)tk(8 * (size_t)q.T * 4096);
+  q.Vb = (double*)tk(8 * (size_t)q.MP * (sk ? 64 : s)); q.Yb = (double*)tk(8 * (size_t)q.MP * (sk ? 64 : s));
   q.Ub = sk ? nullptr : (double*)tk(8 * (size_t)q.MP * s);
   q.Zb = sk ? nullptr : (double*)tk(8 * (size_t)q.MP * s);
   q.Vn = sk ? nullptr : (double*)tk(8 * (size_t)q.MP * s);
@@ -894,14 +908,14 @@ static bool slot_layout(Slot& q, Take tk) {
   q.Yf = (double*)tk(8 * (size_t)std::max(1, h.nP) * (s + 2));
   for (int w = 0; w < 2; ++w) {
     const int ld = w == 0 ? q.ldA : q.ldK;
-    const bool on = q.nc > 0;
-    q.crc[w] = on ? (double*)tk(8 * (size_t)q.nc * ld) : nullptr;
-    q.cec[w] = on ? (double*)tk(8 * (size_t)q.nc * ld) : nullptr;
-    q.cA[w] = on ? (double*)tk(8 * (size_t)q.MPc * q.MPc) : nullptr;
-    q.cY[w] = on ? (double*)tk(8 * (size_t)q.MPc * q.MPc) : nullptr;
-    q.cD[w] = on ? (double*)tk(8 * (size_t)q.Tc * 4096) : nullptr;
+    const bool on = q.nc[w] > 0;
+    q.crc[w] = on ? (double*)tk(8 * (size_t)q.nc[w] * ld) : nullptr;
+    q.cec[w] = on ? (double*)tk(8 * (size_t)q.nc[w] * ld) : nullptr;
+    q.cA[w] = on ? (double*)tk(8 * (size_t)q.MPc[w] * q.MPc[w]) : nullptr;
+    q.cY[w] = on ? (double*)tk(8 * (size_t)q.MPc[w] * q.MPc[w]) : nullptr;
+    q.cD[w] = on ? (double*)tk(8 * (size_t)q.Tc[w] * 4096) : nullptr;
   }
-  q.cinfo = q.nc > 0 ? (int*)tk(128) : nullptr;
+  q.cinfo = q.nc[0] > 0 ? (int*)tk(128) : nullptr;
   q.info = (int*)tk(64);
   return q.info != nullptr;
 }
@@ -939,7 +953,8 @@ struct Live {
   size_t bytes = 0;
   SysRun sys[2];
   int status = 0;
-  // randomized variant: 0 H1 solve, 1 sketch solve, 2 left solve (then the small SVD)
+  // randomized variant: 0 first K^+ solve, 1 sketch solve, 2 left solve, 3 second K^+ solve,
+  // 4 done (small SVD, basis and projection)
   int stage = 0;
   int iters_prev = 0;                            // A-system iterations of finished solves
   std::shared_ptr<const std::vector<double>> om; // the random matrix S_i (M x l, host)
@@ -956,8 +971,8 @@ struct Req {
 
 struct Launch {
   std::vector<SysRun*> sys;
-  int4 *sp = nullptr, *bk = nullptr, *hs = nullptr, *bx = nullptr;
-  int nsp = 0, nbk = 0, nhs = 0, nbx = 0;
+  int4 *sp = nullptr, *bk = nullptr, *hs = nullptr, *bx = nullptr, *rs = nullptr;
+  int nsp = 0, nbk = 0, nhs = 0, nbx = 0, nrs = 0;   // rs: row-tile SpMM of the systems without halo tiles
   int2* cb = nullptr;
   int ncb = 0;
   double spmm_bytes = 0;     // algorithmic bytes of the general (halo or row-tile) SpMM launch
@@ -1128,6 +1143,16 @@ static int engine_upload(mor_ctx* c, MorEngine& e, Launch& L) {
         for (int tx = 0; tx < ntx; ++tx) t.push_back(make_int4(i, tx | (ty << 16), c0, 0));
   }
   L.nbx = (int)t.size() - L.nsp - L.nbk - L.nhs;
+  // in the halo mode, systems without halo tiles (the K^+ systems of the randomized variant)
+  // take the row-tile SpMM
+  if (e.sp.halo)
+    for (int i = 0; i < n; ++i) {
+      const CgSys& S = hs[i];
+      if (S.s16 != nullptr || L.sys[i]->nhtile > 0) continue;
+      for (int c0 = 0; c0 < S.ld; c0 += 64 * e.sp.v)
+        for (int r0 = 0; r0 < S.nI; r0 += e.sp.rb) t.push_back(make_int4(i, r0, c0, 0));
+    }
+  L.nrs = (int)t.size() - L.nsp - L.nbk - L.nhs - L.nbx;
   for (int i = 0; i < n; ++i)
     for (int c0 = 0; c0 < hs[i].ld; c0 += 256) cb.push_back(make_int2(i, c0));
   L.ncb = (int)cb.size();
@@ -1158,6 +1183,7 @@ static int engine_upload(mor_ctx* c, MorEngine& e, Launch& L) {
   L.bk = e.d_tiles + L.nsp;
   L.hs = e.d_tiles + L.nsp + L.nbk;
   L.bx = e.d_tiles + L.nsp + L.nbk + L.nhs;
+  L.rs = e.d_tiles + L.nsp + L.nbk + L.nhs + L.nbx;
   L.cb = e.d_cb;
   L.gd = e.d_gd;
   L.gt = e.d_gt;
@@ -1224,13 +1250,13 @@ static int coarse_setup(mor_ctx* c, const std::vector<Live*>& adm) {
   hipStream_t st = c->st;
   std::vector<Live*> ls;
   for (Live* L : adm)
-    if (L->q.nc > 0) ls.push_back(L);
+    if (L->q.nc[0] > 0) ls.push_back(L);
   if (ls.empty()) return 0;
   const int ns = 2 * (int)ls.size();
   int tmax = 0, mpmax = 0;
   for (Live* L : ls) {
-    tmax = std::max(tmax, L->q.Tc);
-    mpmax = std::max(mpmax, L->q.MPc);
+    tmax = std::max(tmax, std::max(L->q.Tc[0], L->q.Tc[1]));
+    mpmax = std::max(mpmax, std::max(L->q.MPc[0], L->q.MPc[1]));
   }
   std::vector<DenseSub> hds(ns);
   std::vector<TrsmDesc> htd(ns);
@@ -1241,7 +1267,7 @@ static int coarse_setup(mor_ctx* c, const std::vector<Live*>& adm) {
   z.add(sizeof(TrsmDesc) * ns);
   z.add(sizeof(GemmDesc) * ns);
   size_t tiles = 0;
-  for (Live* L : ls) tiles += 2 * (size_t)L->q.Tc * L->q.Tc;
+  for (Live* L : ls) tiles += (size_t)L->q.Tc[0] * L->q.Tc[0] + (size_t)L->q.Tc[1] * L->q.Tc[1];
   z.add(sizeof(int4) * tiles);
   char* buf = (char*)dalloc(c, z.total + 4096);
   if (!buf) return fail(MOR_ENOMEM, "device allocation failed (coarse set-up)");
@@ -1258,15 +1284,18 @@ static int coarse_setup(mor_ctx* c, const std::vector<Live*>& adm) {
     launch_fill_i(q.cinfo, 32, 0, st);
     for (int w = 0; w < 2; ++w) {
       const int ld = w == 0 ? q.ldA : q.ldK;
-      launch_fill(q.cA[w], (int64_t)q.MPc * q.MPc, 0.0, st);
-      launch_coarse_assemble(q.d->rp, q.d->col, q.d->ii_end, w == 0 ? q.A64 : q.K64, q.d->rcb, h.nI, q.cA[w], q.MPc,
+      const bool kp = w == 1 && q.ls > 0;   // K^+ on all local rows: every column, the rows' coarse blocks
+      const int nc = q.nc[w], MPc = q.MPc[w], Tc = q.Tc[w];
+      launch_fill(q.cA[w], (int64_t)MPc * MPc, 0.0, st);
+      launch_coarse_assemble(q.d->rp, q.d->col, kp ? q.d->rp + 1 : q.d->ii_end, w == 0 ? q.A64 : q.K64,
+                             kp ? q.d->rcbL : q.d->rcb, kp ? h.nL : h.nI, q.cA[w], MPc,
                              st);
-      launch_pad_identity(q.cA[w], q.nc, q.MPc, st);
-      launch_fill(q.crc[w], (int64_t)q.nc * ld, 0.0, st);
-      launch_fill(q.cec[w], (int64_t)q.nc * ld, 0.0, st);
-      hds[2 * i + w] = DenseSub{q.nc, q.MPc, q.Tc, q.cA[w], nullptr, nullptr, nullptr, q.cD[w], q.cinfo + 16 * w};
-      htd[2 * i + w] = TrsmDesc{ident, mpmax, 0, q.cY[w], q.MPc, q.Tc};
-      gb.add(gd(q.nc, q.nc, q.nc, q.cY[w], q.MPc, 1, q.cY[w], q.MPc, 0, q.cA[w], q.MPc, 1.0, 0.0, 1));
+      launch_pad_identity(q.cA[w], nc, MPc, st);
+      launch_fill(q.crc[w], (int64_t)nc * ld, 0.0, st);
+      launch_fill(q.cec[w], (int64_t)nc * ld, 0.0, st);
+      hds[2 * i + w] = DenseSub{nc, MPc, Tc, q.cA[w], nullptr, nullptr, nullptr, q.cD[w], q.cinfo + 16 * w};
+      htd[2 * i + w] = TrsmDesc{ident, mpmax, 0, q.cY[w], MPc, Tc};
+      gb.add(gd(nc, nc, nc, q.cY[w], MPc, 1, q.cY[w], MPc, 0, q.cA[w], MPc, 1.0, 0.0, 1));
     }
   }
   if (int rc = gemm_upload(c, gb, ar)) return rc;
@@ -1367,8 +1396,10 @@ static int engine_admit(mor_ctx* c, MorEngine& e) {
       launch_box_coeffs(q.d->spos, q.A64, h.nI, q.s16A, st);
       launch_box_coeffs(q.d->spos, q.K64, h.nI, q.s16K, st);
     }
+    const bool sk = q.ls > 0;        // randomized variant: the K system is K^+ on all local rows
+    const int nblkL = (int)h.bpL.size() - 1;
     launch_block_inv<T>(q.d->rp, q.d->col, q.A64, q.d->bp, nblk, q.minvA, st);
-    launch_block_inv<T>(q.d->rp, q.d->col, q.K64, q.d->bp, nblk, q.minvK, st);
+    launch_block_inv<T>(q.d->rp, q.d->col, q.K64, sk ? q.d->bpL : q.d->bp, sk ? nblkL : nblk, q.minvK, st);
     int nnzII = 0;
     for (int r = 0; r < h.nI; ++r) nnzII += h.ii_end[r] - h.rp[r];
     for (int w = 0; w < 2; ++w) {
@@ -1387,11 +1418,11 @@ static int engine_admit(mor_ctx* c, MorEngine& e) {
       S.P = w == 0 ? q.PA : q.PK; S.Q = w == 0 ? q.QA : q.QK;
       S.X64 = w == 0 ? q.XA64 : q.XK64;
       S.tol2 = inner_tol2<T>(c);
-      S.rc = q.nc > 0 ? q.crc[w] : nullptr;
-      S.ec = q.nc > 0 ? q.cec[w] : nullptr;
-      S.nc = q.nc;
-      R.Ainv = q.nc > 0 ? q.cA[w] : nullptr;
-      R.ldac = q.MPc;
+      S.rc = q.nc[w] > 0 ? q.crc[w] : nullptr;
+      S.ec = q.nc[w] > 0 ? q.cec[w] : nullptr;
+      S.nc = q.nc[w];
+      R.Ainv = q.nc[w] > 0 ? q.cA[w] : nullptr;
+      R.ldac = q.MPc[w];
       S.bp = q.d->bp;
       S.nblk = nblk;
       S.minv = w == 0 ? q.minvA : q.minvK;
@@ -1405,7 +1436,18 @@ static int engine_admit(mor_ctx* c, MorEngine& e) {
       if (q.s16A) {
         S.s16 = w == 0 ? q.s16A : q.s16K;
         S.smap = q.d->smap;
-        S.bx = h.bx; S.by = h.by; S.bz = h.bz;
+        S.bx = h.bx; S.bz = h.bz; S.by = h.by;
+      }
+      if (sk && w == 1) {   // K^+ over [I, B]: every row, every column, dense right-hand sides
+        S.nI = h.nL; S.nB = 0;
+        S.ii_end = q.d->rp + 1;
+        S.f = nullptr;
+        S.Fd = q.FdK;
+        S.bp = q.d->bpL;
+        S.nblk = nblkL;
+        S.htile = nullptr; S.halo = nullptr; S.hrowp = nullptr; S.hpe = nullptr; S.hpp = nullptr; S.hself = nullptr;
+        R.nhtile = 0;
+        S.s16 = nullptr; S.smap = nullptr;
       }
       double* cs = q.colst[w];
       const int ld = S.ld;
@@ -1414,17 +1456,17 @@ static int engine_admit(mor_ctx* c, MorEngine& e) {
       R.cnt = e.cnt_free.back();
       e.cnt_free.pop_back();
       S.nactive = e.d_cnt + R.cnt;
-      R.phase = 0; R.iters = 0; R.refines = 0; R.nnzII = nnzII;
+      R.phase = 0; R.iters = 0; R.refines = 0; R.nnzII = sk && w == 1 ? h.rp[h.nL] : nnzII;
       if (w == 0 && q.ls > 0) {
-        R.phase = 2;   // the sketch solve waits for R_BB (randomized variant)
+        R.phase = 2;   // the sketch solve waits for T = S_B^-1 S_i (randomized variant)
         continue;
       }
       Ln.sys.push_back(&R);
     }
-    if (q.ls > 0) {   // the random matrix S_i, zero padded to MP x 64
-      launch_fill(q.Bk, (int64_t)q.MP * 64, 0.0, st);
-      HIPCHK(hipMemcpy2DAsync(q.Bk, 64 * sizeof(double), L->om->data(), q.ls * sizeof(double), q.ls * sizeof(double),
-                              q.M, hipMemcpyHostToDevice, st));
+    if (q.ls > 0) {   // right-hand sides [0; S_i] of the first K^+ solve (S_i: M x l, host)
+      launch_fill(q.FdK, (int64_t)h.nL * q.ldK, 0.0, st);
+      HIPCHK(hipMemcpy2DAsync(q.FdK + (size_t)h.nI * q.ldK, q.ldK * sizeof(double), L->om->data(),
+                              q.ls * sizeof(double), q.ls * sizeof(double), q.M, hipMemcpyHostToDevice, st));
     }
   }
   if (int rc = coarse_setup(c, adm)) return rc;
@@ -1451,6 +1493,7 @@ static int engine_chunk(mor_ctx* c, MorEngine& e) {
       launch_cg_spmm_halo<T>(e.d_sys, La.hs, La.nhs, c->halo_cap, e.sp.cwb, s);
     else
       launch_cg_spmm<T>(e.d_sys, La.sp, La.nsp, e.sp.rb, e.sp.v, s);
+    if (La.nrs > 0) launch_cg_spmm<T>(e.d_sys, La.rs, La.nrs, e.sp.rb, e.sp.v, s);
     launch_cg_spmm_box(e.d_sys, La.bx, La.nbx, s);
     launch_cg_alpha(e.d_sys, La.cb, La.ncb, s);
     launch_cg_update<T>(e.d_sys, La.bk, La.nbk, e.stm.rb, e.stm.v, s);
@@ -1470,7 +1513,7 @@ static int engine_chunk(mor_ctx* c, MorEngine& e) {
                                       (int64_t)(intptr_t)e.d_cb, La.nsp, La.nbk, La.nhs, La.ncb, chunk,
                                       (int64_t)(intptr_t)La.hs, (int64_t)(intptr_t)La.bk, (int64_t)(intptr_t)La.cb,
                                       (int64_t)c->halo_cap, (int64_t)(intptr_t)La.gd, (int64_t)(intptr_t)La.gt,
-                                      La.ngt, (int64_t)(intptr_t)La.bx, La.nbx};
+                                      La.ngt, (int64_t)(intptr_t)La.bx, La.nbx, (int64_t)(intptr_t)La.rs, La.nrs};
     if (!e.gexec || e.g_sys != La.sys || e.g_key != key) {
       if (e.gexec) HIPCHK(hipGraphExecDestroy(e.gexec));
       e.gexec = nullptr;
@@ -1491,18 +1534,25 @@ static int engine_chunk(mor_ctx* c, MorEngine& e) {
     ScopedTimer tm(c, "cg_graph", chunk * (La.spmm_bytes + La.box_bytes + La.stream_bytes));
     HIPCHK(hipGraphLaunch(e.gexec, st));
   }
+  // The SpMM timers' algorithmic bytes count the columns still iterating (converged columns need
+  // no product; the box kernel skips their slices): per system the matrix once, P read and Q
+  // written for the active columns, with the active count taken as the mean of the counts at
+  // the start and the end of the chunk.  Added once the chunk's end count is known.
+  std::vector<int> act0(La.sys.size());
+  for (size_t i = 0; i < La.sys.size(); ++i) act0[i] = e.h_cnt[La.sys[i]->cnt];
   for (int k = 0; k < (c->opts.use_graph ? 0 : chunk); ++k) {
     {
-      if (!e.sp.halo || La.nhs > 0) {
-        ScopedTimer tm(c, "spmm", La.spmm_bytes);
+      if (!e.sp.halo || La.nhs > 0 || La.nrs > 0) {
+        ScopedTimer tm(c, "spmm", 0);
         if (e.sp.halo)
           launch_cg_spmm_halo<T>(e.d_sys, La.hs, La.nhs, c->halo_cap, e.sp.cwb, st);
         else
           launch_cg_spmm<T>(e.d_sys, La.sp, La.nsp, e.sp.rb, e.sp.v, st);
+        if (La.nrs > 0) launch_cg_spmm<T>(e.d_sys, La.rs, La.nrs, e.sp.rb, e.sp.v, st);
       }
     }
     if (La.nbx > 0) {
-      ScopedTimer tm(c, "spmm_box", La.box_bytes);
+      ScopedTimer tm(c, "spmm_box", 0);
       launch_cg_spmm_box(e.d_sys, La.bx, La.nbx, st);
     }
     launch_cg_alpha(e.d_sys, La.cb, La.ncb, st);
@@ -1523,6 +1573,17 @@ static int engine_chunk(mor_ctx* c, MorEngine& e) {
   }
   HIPCHK(hipGetLastError());
   if (int rc = read_counts(c, e)) return rc;
+  if (c->timing && !c->opts.use_graph) {
+    double by[2] = {0.0, 0.0};   // general SpMM, box SpMM
+    for (size_t i = 0; i < La.sys.size(); ++i) {
+      const CgSys& S = La.sys[i]->S;
+      const double act = 0.5 * (act0[i] + e.h_cnt[La.sys[i]->cnt]);
+      by[S.s16 != nullptr] += chunk * ((double)La.sys[i]->nnzII * (4.0 + e.elt) + 4.0 * (S.nI + 1) +
+                                       2.0 * e.elt * (double)S.nI * act);
+    }
+    if (c->timers.count("spmm")) c->timers["spmm"].work += by[0];
+    if (c->timers.count("spmm_box")) c->timers["spmm_box"].work += by[1];
+  }
   // Systems whose inner CG converged: refined systems fold X into the FP64 shadow and test the
   // FP64 residual against the outer target; those above it restart while refinement steps are
   // left, and fail with MOR_ENOTCONV after the last one.  Unrefined systems are done.
@@ -1646,67 +1707,21 @@ static int rank_of(const std::vector<double>& th, int s) {
   return r;
 }
 
+// After the first K^+ solve: the sketch T = S_B^-1 S_i is the B block of its solution; the
+// sketch solve A_II X = [-A_IB T | f_I] starts.
 template <typename T>
-static int rsvd_after_h1(mor_ctx* c, MorEngine& e, std::vector<Live*>& ls) {
+static int rsvd_after_kp1(mor_ctx* c, MorEngine& e, std::vector<Live*>& ls) {
   hipStream_t st = c->st;
-  const int ns = (int)ls.size();
-  std::vector<Slot*> sl(ns);
-  for (int i = 0; i < ns; ++i) sl[i] = &ls[i]->q;
-  StageBuf buf(c, ns * (sizeof(DenseSub) + 4 * sizeof(double*)) + 8 * 256);
-  if (!buf.p) return fail(MOR_ENOMEM, "device allocation failed (sketch stage)");
-  std::vector<DenseSub> hds(ns);
-  int tmax = 0;
-  for (int i = 0; i < ns; ++i) {
-    Slot& q = *sl[i];
-    const HostSub& h = *q.h;
-    ScopedTimer tm(c, "schur", 0);
-    launch_schur(q.d->rp, q.d->col, q.K64, h.nI, h.nB, q.Ec, q.ldEc, q.S, q.MP, st);
-    launch_pad_identity(q.S, q.M, q.MP, st);
-    launch_symmetrize(q.S, q.MP, st);
-    hds[i] = DenseSub{q.M, q.MP, q.T, q.S, nullptr, nullptr, nullptr, q.Dinv, q.info};
-    tmax = std::max(tmax, q.T);
-    launch_fill_i(q.info, 16, 0, st);
-  }
-  DenseSub* dds = (DenseSub*)buf.ar.take(sizeof(DenseSub) * ns);
-  if (!dds) return fail(MOR_ENOMEM, "arena exhausted (sketch stage)");
-  HIPCHK(hipMemcpyAsync(dds, hds.data(), sizeof(DenseSub) * ns, hipMemcpyHostToDevice, st));
-  {
-    ScopedTimer tm(c, "potrf", 0);
-    for (int p = 0; p < tmax; ++p) {
-      launch_potrf_diag(dds, ns, p, st);
-      launch_chol_panel(dds, ns, p, tmax, st);
-      launch_chol_syrk(dds, ns, p, tmax, st);
-    }
-  }
-  std::vector<int> hinfo(ns * 16);
-  for (int i = 0; i < ns; ++i) HIPCHK(hipMemcpyAsync(&hinfo[i * 16], sl[i]->info, 64, hipMemcpyDeviceToHost, st));
-  HIPCHK(hipStreamSynchronize(st));
-  for (int i = 0; i < ns; ++i)
-    if (hinfo[i * 16] != 0) {
-      ls[i]->status = MOR_EDEVICE;
-      g_err = "subdomain " + std::to_string(sl[i]->sd) + ": S_B is not positive definite";
-    }
-  double** PB = ptr_table(c, buf.ar, sl, [](Slot& q) { return q.Bk; });
-  double** PW = ptr_table(c, buf.ar, sl, [](Slot& q) { return q.Wk; });
-  if (!PB || !PW) return fail(MOR_ENOMEM, "arena exhausted (sketch stage)");
-  {
-    ScopedTimer tm(c, "trsm", 0);
-    std::vector<double*> hB(ns), hW(ns);
-    for (int i = 0; i < ns; ++i) {
-      hB[i] = sl[i]->Bk;
-      hW[i] = sl[i]->Wk;
-    }
-    if (int rc = trsm_un_blocked(c, hds, dds, hB, hW)) return rc;   // T = R_BB^-1 S_i
-  }
   Launch Ln;
-  for (int i = 0; i < ns; ++i) {
-    Slot& q = *sl[i];
+  for (Live* L : ls) {
+    Slot& q = L->q;
     const HostSub& h = *q.h;
+    launch_fill(q.Wk, (int64_t)q.MP * 64, 0.0, st);
+    launch_copy_rect(q.Ec + (size_t)h.nI * q.ldEc, q.ldEc, 0, q.Wk, 64, q.M, q.ls, st);
     launch_rhs_sketch(q.d->rp, q.d->col, q.d->ii_end, q.A64, q.f, h.nI, q.Wk, q.ls, q.Fd, q.ldA, st);
-    if (ls[i]->status) continue;
-    SysRun& R = ls[i]->sys[0];
+    SysRun& R = L->sys[0];
     R.S.ncols = q.colsA;
-    ls[i]->stage = 1;
+    L->stage = 1;
     Ln.sys.push_back(&R);
   }
   return start_systems<T>(c, e, Ln);
@@ -1792,6 +1807,27 @@ static int rsvd_after_sketch(mor_ctx* c, MorEngine& e, std::vector<Live*>& ls) {
   return start_systems<T>(c, e, Ln);
 }
 
+// After the left solve A_II G = C^T K_i W: V = A_BI G (M x rk, up to the sign of the lifting),
+// and the second K^+ solve with right-hand sides [0; V] gives S_B^-1 V.
+template <typename T>
+static int rsvd_after_left(mor_ctx* c, MorEngine& e, std::vector<Live*>& ls) {
+  hipStream_t st = c->st;
+  Launch Ln;
+  for (Live* L : ls) {
+    Slot& q = L->q;
+    const HostSub& h = *q.h;
+    launch_bi_product(q.d->rp, q.d->col, q.A64, h.nI, h.nB, q.MP, q.Xc, q.ldXc, q.rk, q.Vb, st);
+    launch_fill(q.FdK, (int64_t)h.nL * q.ldK, 0.0, st);
+    launch_copy_rect(q.Vb, 64, 0, q.FdK + (size_t)h.nI * q.ldK, q.ldK, q.M, q.rk, st);
+    SysRun& R = L->sys[1];
+    L->iters_prev += L->sys[0].iters;
+    R.S.ncols = q.rk;
+    L->stage = 3;
+    Ln.sys.push_back(&R);
+  }
+  return start_systems<T>(c, e, Ln);
+}
+
 static int rsvd_finish(mor_ctx* c, std::vector<Live*>& ls) {
   hipStream_t st = c->st;
   const int ns = (int)ls.size();
@@ -1804,32 +1840,16 @@ static int rsvd_finish(mor_ctx* c, std::vector<Live*>& ls) {
   StageBuf buf(c, ns * (sizeof(DenseSub) + sizeof(TrsmDesc) + 16 * sizeof(double*) + 4 * sizeof(GemmDesc)) +
                       4 * tiles * sizeof(int4) + 64 * 256);
   if (!buf.p) return fail(MOR_ENOMEM, "device allocation failed (sketch stage)");
-  // B^T = R_BB^-T (A_BI G)
-  std::vector<DenseSub> hds(ns);
-  std::vector<TrsmDesc> htd(ns);
-  for (int i = 0; i < ns; ++i) {
-    Slot& q = *sl[i];
-    const HostSub& h = *q.h;
-    launch_bi_product(q.d->rp, q.d->col, q.A64, h.nI, h.nB, q.MP, q.Xc, q.ldXc, q.rk, q.Vb, st);
-    hds[i] = DenseSub{q.M, q.MP, q.T, q.S, nullptr, nullptr, nullptr, q.Dinv, q.info};
-    htd[i] = TrsmDesc{q.Vb, 64, 0, q.Yb, 64, 1};
-  }
-  DenseSub* dds = (DenseSub*)buf.ar.take(sizeof(DenseSub) * ns);
-  TrsmDesc* dtd = (TrsmDesc*)buf.ar.take(sizeof(TrsmDesc) * ns);
-  if (!dds || !dtd) return fail(MOR_ENOMEM, "arena exhausted (sketch stage)");
-  HIPCHK(hipMemcpyAsync(dds, hds.data(), sizeof(DenseSub) * ns, hipMemcpyHostToDevice, st));
-  HIPCHK(hipMemcpyAsync(dtd, htd.data(), sizeof(TrsmDesc) * ns, hipMemcpyHostToDevice, st));
-  {
-    ScopedTimer tm(c, "trsm", 0);
-    if (int rc = trsm_lt_blocked(c, hds, dds, htd)) return rc;
-  }
-  // B B^T and its eigenpairs: sigma^2 and the left singular vectors U
+  // B B^T = V^T S_B^-1 V (B = W R_BB^-1 with V = W^T up to sign) and its eigenpairs: sigma^2 and
+  // the left singular vectors U
   GemmBatch g1;
   std::vector<int> s_of(ns);
   for (int i = 0; i < ns; ++i) {
     Slot& q = *sl[i];
+    const HostSub& h = *q.h;
+    launch_copy_rect(q.Ec + (size_t)h.nI * q.ldEc, q.ldEc, 0, q.Yb, 64, q.M, q.rk, st);   // S_B^-1 V
     s_of[i] = q.rk;
-    g1.add(gd(q.rk, q.rk, q.MP, q.Yb, 64, 1, q.Yb, 64, 0, q.H, q.rk));
+    g1.add(gd(q.rk, q.rk, q.M, q.Vb, 64, 1, q.Yb, 64, 0, q.H, q.rk));
   }
   if (int rc = gemm_upload(c, g1, buf.ar)) return rc;
   gemm_run(c, g1, "sketch_svd");
@@ -1858,7 +1878,7 @@ static int rsvd_finish(mor_ctx* c, std::vector<Live*>& ls) {
   }
   if (int rc = gemm_upload(c, gV, buf.ar)) return rc;
   gemm_run(c, gV, "basis");
-  for (Live* L : ls) L->stage = 3;
+  for (Live* L : ls) L->stage = 4;
   return project_local(c, buf.ar, sl, ls, 0);
 }
 
@@ -1867,27 +1887,29 @@ static int engine_tick(mor_ctx* c, MorEngine& e) {
   if (int rc = engine_admit<T>(c, e)) return rc;
   if (int rc = engine_chunk<T>(c, e)) return rc;
   {   // randomized variant: move the requests whose current solve finished to their next stage
-    std::vector<Live*> s1, s2, s3;
+    std::vector<Live*> s1, s2, s3, s4;
     for (Live* L : e.live) {
       if (L->status || L->q.ls == 0) continue;
       if (L->stage == 0 && L->sys[1].phase == 1) s1.push_back(L);
       else if (L->stage == 1 && L->sys[0].phase == 1) s2.push_back(L);
       else if (L->stage == 2 && L->sys[0].phase == 1) s3.push_back(L);
+      else if (L->stage == 3 && L->sys[1].phase == 1) s4.push_back(L);
     }
     auto run = [&](std::vector<Live*>& v, int rc) {
       if (rc)
         for (Live* L : v)
           if (!L->status) L->status = rc;
     };
-    if (!s3.empty()) run(s3, rsvd_finish(c, s3));
+    if (!s4.empty()) run(s4, rsvd_finish(c, s4));
+    if (!s3.empty()) run(s3, rsvd_after_left<T>(c, e, s3));
     if (!s2.empty()) run(s2, rsvd_after_sketch<T>(c, e, s2));
-    if (!s1.empty()) run(s1, rsvd_after_h1<T>(c, e, s1));
+    if (!s1.empty()) run(s1, rsvd_after_kp1<T>(c, e, s1));
   }
   std::vector<Live*> ready, keep;
   bool iterating = false;
   for (Live* L : e.live) {
     if (L->status) ready.push_back(L);
-    else if (L->q.ls > 0 ? L->stage == 3 : (L->sys[0].phase == 1 && L->sys[1].phase == 1)) ready.push_back(L);
+    else if (L->q.ls > 0 ? L->stage == 4 : (L->sys[0].phase == 1 && L->sys[1].phase == 1)) ready.push_back(L);
     else {
       keep.push_back(L);
       iterating = true;

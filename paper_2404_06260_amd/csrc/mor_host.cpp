@@ -513,9 +513,14 @@ int build_sub(const HostMesh& m, const int32_t* ext, const uint8_t* in_core, int
     s.bp.swap(bp);
     local_tets();
   }
+  s.bpL = s.bp;
+  for (int r = s.nI; r < s.nL; r += 8) s.bpL.push_back(std::min(r + 8, s.nL));
   s.rcb.assign(s.nI, 0);
   for (int b = 0; b + 1 < (int)s.bp.size(); ++b)
     for (int r = s.bp[b]; r < s.bp[b + 1]; ++r) s.rcb[r] = b / kCoarseAgg;
+  s.rcbL.assign(s.nL, 0);
+  for (int b = 0; b + 1 < (int)s.bpL.size(); ++b)
+    for (int r = s.bpL[b]; r < s.bpL[b + 1]; ++r) s.rcbL[r] = b / kCoarseAgg;
   s.ii_end.resize(s.nI);
   for (int r = 0; r < s.nI; ++r) {
     const int32_t* b = s.col.data() + s.rp[r];

@@ -52,6 +52,7 @@ struct HostSub {
   std::vector<uint8_t> core;               // 1 if the local tet lies in omega_i
   std::vector<int32_t> colour_ptr;         // local tets of colour c: [colour_ptr[c], colour_ptr[c+1])
   std::vector<int32_t> bp;                 // aggregates of I rows: block b = rows [bp[b], bp[b+1]), size <= 8
+  std::vector<int32_t> bpL;                // aggregates of all nL rows: bp, then the B rows in runs of 8
   std::vector<int32_t> htile;              // SpMM tiles, 4 ints each: first row, rows, first halo entry, halo size
   std::vector<int32_t> halo;               // each tile's halo rows (local ids < nI), ascending
   std::vector<int32_t> hrowp;              // per I row (+1): start of its padded II entries in hpe / hpp
@@ -59,6 +60,7 @@ struct HostSub {
   std::vector<uint16_t> hpp;               // padded II entries: the column's position in the tile halo
   std::vector<uint16_t> hself;             // per I row: the row's own position in its tile halo
   std::vector<int32_t> rcb;                // per I row: its coarse block (aggregate / kCoarseAgg)
+  std::vector<int32_t> rcbL;               // per local row: its coarse block over the aggregates bpL
   // Box form of the interior (on a Kuhn lattice, when I is a full box of grid points):
   // extents nx, ny, nz; smap[(z*ny + y)*nx + x] = local row of the grid point (x, y, z) of the
   // box; spos[16 r + s] = CSR entry of row r's stencil slot s in the II block, or -1.

@@ -1,7 +1,8 @@
-"""The randomized local reduction (Section 6, two left solves) on the GPU against the oracle's
-randomized reduction with the same random matrices S_i (seeded, from the input generators):
-k_eff exact, singular values, q_0, the span of the modes in the K_i inner product, and the
-reduced solution in the global energy norm."""
+"""The randomized local reduction (Section 6, two left solves, with the weights applied by K^+
+solves: the sketch S_B^-1 S_i and B B^T = W S_B^-1 W^T) on the GPU against the oracle's route of
+the same reading with the same random matrices S_i (seeded, from the input generators): k_eff
+exact, singular values, q_0, the span of the modes in the K_i inner product, and the reduced
+solution in the global energy norm.  Every solve carries l or l + 1 right-hand sides."""
 import sys
 
 import numpy as np
@@ -41,7 +42,7 @@ def test_sketched_matches_oracle(precision, l):
     n = p.subdomains.n_sub
     sets = [odecomp.local_sets(p.mesh, p.subdomains, i) for i in range(n)]
     oms = [w.sketch_rows(p.mesh.n_nodes, s.B, l, i) for i, s in enumerate(sets)]
-    res = oreduce.reduce_all(p, rank=p.rank, workers=4, sketches=oms)
+    res = oreduce.reduce_all(p, rank=p.rank, workers=4, sketches=oms, sketch_solves=True)
     At, bt, _ = oproj.reduced_system(p.mesh, p.kappa, p.subdomains, res)
     x = oproj.solve_reduced(At, bt)
     ut = oproj.reconstruct(p.mesh, res, x)

@@ -501,14 +501,34 @@ def make_config(name: str) -> Problem:
     raise ValueError(name)
 
 
+def _splitmix64(x: np.ndarray) -> np.ndarray:
+    """SplitMix64 output function (Steele, Lea and Flood 2014) on uint64 arrays, wrapping."""
+    with np.errstate(over="ignore"):
+        z = x + np.uint64(0x9E3779B97F4A7C15)
+        z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
+        z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
+    return z ^ (z >> np.uint64(31))
+
+
 def sketch_rows(n_nodes: int, node_ids: np.ndarray, cols: int, sub: int, seed: int = 13) -> np.ndarray:
     """Standard Gaussian random matrix for the randomized local reduction of subdomain `sub`:
     one row per node id in `node_ids` (the subdomain's interface nodes, in the caller's
-    order), `cols` columns.  Row values depend only on (seed, sub, global node id), so every
-    consumer that lists the same nodes gets the same matrix."""
-    rng = np.random.default_rng([seed, sub])
-    table = rng.standard_normal((n_nodes, cols))
-    return np.ascontiguousarray(table[np.asarray(node_ids, dtype=np.int64)])
+    order), `cols` columns.  Entry (node, j) depends only on (seed, sub, global node id, j): two
+    SplitMix64 draws keyed by them feed a Box-Muller transform, so every consumer that lists the
+    same nodes gets the same matrix, a narrower sketch is the leading columns of a wider one, and
+    only the listed rows are generated.  (n_nodes bounds the ids.)"""
+    ids = np.asarray(node_ids, dtype=np.int64)
+    if ids.size and (ids.min() < 0 or ids.max() >= n_nodes):
+        raise ValueError("node id out of range")
+    key = _splitmix64(_splitmix64(np.uint64(seed)) ^ np.uint64(sub))
+    row = _splitmix64(key ^ ids.astype(np.uint64))[:, None]
+    j = np.arange(cols, dtype=np.uint64)[None, :]
+    with np.errstate(over="ignore"):
+        b1 = _splitmix64(row + np.uint64(2) * j)
+        b2 = _splitmix64(row + np.uint64(2) * j + np.uint64(1))
+    u1 = ((b1 >> np.uint64(11)).astype(np.float64) + 0.5) * 2.0 ** -53   # (0, 1)
+    u2 = (b2 >> np.uint64(11)).astype(np.float64) * 2.0 ** -53
+    return np.ascontiguousarray(np.sqrt(-2.0 * np.log(u1)) * np.cos(2.0 * np.pi * u2))
 
 
 def poisson_arrivals(n_requests: int, rate: float, seed: int = 7) -> np.ndarray:
