@@ -1042,7 +1042,9 @@ static int engine_init(mor_ctx* c, MorEngine& e, int elt) {
     e.sp.v = c->opts.spmm_vec > 0 ? c->opts.spmm_vec : 4;
     if (!fp32 && e.sp.v > 2) e.sp.v = 2;
   }
-  e.sp.rb = c->opts.spmm_rows > 0 ? std::min(c->opts.spmm_rows, 64) : 8;
+  // rows per row tile (the row kernels, and the SpMM of row-tile systems): 32 by default, so that
+  // the tile lists the host rebuilds whenever the set of iterating systems changes stay short
+  e.sp.rb = c->opts.spmm_rows > 0 ? std::min(c->opts.spmm_rows, 64) : 32;
   // block kernels hold 8 rows per lane; 64-column tiles measured fastest (C2, C3, C4 tuner sweeps)
   e.stm.v = c->opts.stream_vec > 0 ? c->opts.stream_vec : 1;
   if (!fp32 && e.stm.v > 2) e.stm.v = 2;

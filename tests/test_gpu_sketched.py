@@ -96,3 +96,38 @@ def test_sketched_rejects_plain_fp32_and_wide_sketches():
             mor.mor_local_basis_sketched(m.ctx, [0], [3], [np.zeros((nB, 65))])
     finally:
         m.close()
+
+
+def test_sketched_at_the_papers_sketch_size():
+    """Each subdomain with its own sketch of l_i = floor(M_i / 8) columns (the size the paper's
+    scaling runs use), requests grouped by l_i, FP32 CG with FP64 refinement, against the
+    oracle's route with the same S_i."""
+    import torch
+    from paper_2404_06260_amd import mor
+    p = w.make_problem(12, (2, 2, 2), r=2, rank=6, kappa="lognormal", seed=3, name="sketch")
+    n = p.subdomains.n_sub
+    sets = [odecomp.local_sets(p.mesh, p.subdomains, i) for i in range(n)]
+    ls = [s.B.size // 8 for s in sets]
+    assert min(ls) >= 16 and max(ls) <= 64, ls
+    torch.cuda.set_device(0)
+    tol = TOL["fp32_refine"]
+    m = mor.Mor(p, precision="fp32_refine")
+    try:
+        for l in sorted(set(ls)):
+            ids = [i for i in range(n) if ls[i] == l]
+            oms = [w.sketch_rows(p.mesh.n_nodes, sets[i].B, l, i) for i in ids]
+            k = mor.mor_local_basis_sketched(m.ctx, np.array(ids), np.full(len(ids), p.rank), oms)
+            for j, i in enumerate(ids):
+                r = oreduce.reduce_local_sketched_solves(p.mesh, p.kappa, p.f_nodal, sets[i], p.rank, None, oms[j])
+                assert k[j] == r.k_eff, (i, k[j], r.k_eff)
+                sig = mor.mor_get_sigma(m.ctx, i)
+                ns = min(sig.size, r.k_eff + 1)
+                np.testing.assert_allclose(sig[:ns], r.sigma[:ns], rtol=tol["sigma"], err_msg=f"subdomain {i}")
+                nV = mor.mor_get_sizes(m.ctx, i)[1]
+                Vs = mor.mor_get_basis(m.ctx, i)[np.argsort(mor.mor_get_nodes(m.ctx, i)[:nV])]
+                lm = oreduce.local_matrices(p.mesh, p.kappa, p.f_nodal, r.sets)
+                ang = _sin_angle(Vs[:, 1:], r.Phi, lm.K_i.tocsr())
+                _say(f"[gpu] sketched subdomain {i}: M {sets[i].B.size}, l {l}, k_eff {r.k_eff}, span angle {ang:.2e}")
+                assert ang < tol["angle"], (i, ang)
+    finally:
+        m.close()
