@@ -412,7 +412,8 @@ def main():
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
     kernels = {}
     for name in ("spmm", "spmm_box", "cg_update", "cg_direction", "cg_coarse", "coarse_setup", "cg_graph", "residual64", "assemble", "gram", "gram_split", "gram_bf16",
-                 "schur", "potrf", "trsm", "trsm_basis", "eig", "basis", "project_local", "project", "solve"):
+                 "schur", "potrf", "trsm", "trsm_basis", "eig", "basis", "project_local", "project", "solve",
+                 "host_admit", "host_chunk", "host_stage", "host_dense"):
         n, ms, wk = mor.mor_timing_get(m.ctx, name)
         if n:
             kernels[name] = dict(launches=n, ms_per_step=round(ms / args.steps, 3))

@@ -247,6 +247,20 @@ struct ScopedTimer {
   }
 };
 
+// Host wall time of an engine phase (including its waits for the device), under its own name.
+struct HostTimer {
+  mor_ctx* c;
+  const char* name;
+  std::chrono::steady_clock::time_point t0;
+  HostTimer(mor_ctx* c_, const char* n) : c(c_), name(n), t0(std::chrono::steady_clock::now()) {}
+  ~HostTimer() {
+    if (!c->timing) return;
+    TimerRec& t = c->timers[name];
+    t.ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    t.launches++;
+  }
+};
+
 static void flush_timers(mor_ctx* c) {
   (void)hipStreamSynchronize(c->st);
   for (auto& kv : c->timers) {
@@ -1466,9 +1480,11 @@ static int engine_admit(mor_ctx* c, MorEngine& e) {
       Ln.sys.push_back(&R);
     }
     if (q.ls > 0) {   // right-hand sides [0; S_i] of the first K^+ solve (S_i: M x l, host)
+      // one contiguous copy into Wk (free until the sketch T lands there), then a device copy
+      // into the padded rows: a strided copy from pageable memory goes row by row
       launch_fill(q.FdK, (int64_t)h.nL * q.ldK, 0.0, st);
-      HIPCHK(hipMemcpy2DAsync(q.FdK + (size_t)h.nI * q.ldK, q.ldK * sizeof(double), L->om->data(),
-                              q.ls * sizeof(double), q.ls * sizeof(double), q.M, hipMemcpyHostToDevice, st));
+      HIPCHK(hipMemcpyAsync(q.Wk, L->om->data(), sizeof(double) * (size_t)q.M * q.ls, hipMemcpyHostToDevice, st));
+      launch_copy_rect(q.Wk, q.ls, 0, q.FdK + (size_t)h.nI * q.ldK, q.ldK, q.M, q.ls, st);
     }
   }
   if (int rc = coarse_setup(c, adm)) return rc;
@@ -1886,9 +1902,16 @@ static int rsvd_finish(mor_ctx* c, std::vector<Live*>& ls) {
 
 template <typename T>
 static int engine_tick(mor_ctx* c, MorEngine& e) {
-  if (int rc = engine_admit<T>(c, e)) return rc;
-  if (int rc = engine_chunk<T>(c, e)) return rc;
+  {
+    HostTimer ht(c, "host_admit");
+    if (int rc = engine_admit<T>(c, e)) return rc;
+  }
+  {
+    HostTimer ht(c, "host_chunk");
+    if (int rc = engine_chunk<T>(c, e)) return rc;
+  }
   {   // randomized variant: move the requests whose current solve finished to their next stage
+    HostTimer ht(c, "host_stage");
     std::vector<Live*> s1, s2, s3, s4;
     for (Live* L : e.live) {
       if (L->status || L->q.ls == 0) continue;
@@ -1932,6 +1955,7 @@ static int engine_tick(mor_ctx* c, MorEngine& e) {
     if (!L->status && L->q.ls == 0) ok.push_back(L);
   int rc = 0;
   if (!ok.empty()) {
+    HostTimer ht(c, "host_dense");
     rc = dense_stage(c, ok);
     if (rc)
       for (Live* L : ok)
