@@ -503,30 +503,46 @@ constexpr int kBoxRows = kBoxH * kBoxH;      // halo rows per plane
 constexpr int kBoxChunks = kBoxRows * 8;     // 16-byte chunks of one 128-byte slice per plane
 constexpr int kBoxLd = (kBoxChunks + 255) / 256;   // chunk loads per thread and plane
 
-struct BoxRows {    // one plane's row ids for this thread: its P chunks and its coefficient point
-  int r[kBoxLd];
-  int rc;
+struct BoxRows {    // one plane's row lookups for this thread: its P chunks and its coefficient
+  int r[kBoxLd];    // point, read at clamped coordinates, and which of them lie in the box (bit k:
+  int rc;           // chunk k, bit kBoxLd: the point); the bits are applied where the rows are used
+  unsigned in;
 };
-struct BoxPlane {   // one plane's loads in flight: P chunks, the coefficient chunk, its row
-  u32x4 pv[kBoxLd];
-  u32x4 cv;
-  int rc;
+struct BoxPlane {   // one plane's loads in flight: P chunks, the coefficient chunk, its row,
+  u32x4 pv[kBoxLd]; // and which of them lie in the box (bit k: chunk k, bit kBoxLd: the
+  u32x4 cv;         // coefficients); the others are replaced by zeros when they reach LDS, not
+  int rc;           // before, so that nothing waits for a load until its plane is stored
+  unsigned ok;
 };
 
-__device__ __forceinline__ int box_row(const CgSys& S, int x, int y, int z) {
-  if (x < 0 || y < 0 || z < 0 || x >= S.bx || y >= S.by || z >= S.bz) return -1;
-  return gld(S.smap + ((int64_t)z * S.by + y) * S.bx + x);
+// Grid point -> row lookup.  Branch-free: a point outside the box reads a clamped (valid) entry
+// and `in` says so, so every load of a plane is issued unconditionally and the compiler can count
+// them when it waits for the oldest (a load issued on one path only makes it assume the fewest
+// ops after the awaited one, and drain everything in flight); the result is only used, and so
+// only waited for, when the next plane's loads go out.
+__device__ __forceinline__ int box_lookup(const CgSys& S, int x, int y, int z, bool& in) {
+  in = (unsigned)x < (unsigned)S.bx && (unsigned)y < (unsigned)S.by && (unsigned)z < (unsigned)S.bz;
+  return gld(S.smap + ((int64_t)(in ? z : 0) * S.by + (in ? y : 0)) * S.bx + (in ? x : 0));
+}
+
+__device__ __forceinline__ u32x4 box_keep(bool keep, u32x4 v) {
+  return (u32x4){keep ? v.x : 0u, keep ? v.y : 0u, keep ? v.z : 0u, keep ? v.w : 0u};
 }
 
 __device__ __forceinline__ void box_rows(const CgSys& S, int x0, int y0, int z, BoxRows& q) {
   const int tid = threadIdx.x;
+  unsigned in = 0;
 #pragma unroll
   for (int k = 0; k < kBoxLd; ++k) {
-    const int i = k * 256 + tid, hr = i >> 3;
-    q.r[k] = i < kBoxChunks ? box_row(S, x0 - 1 + hr % kBoxH, y0 - 1 + hr / kBoxH, z) : -1;
+    const int i = k * 256 + tid, hr = i < kBoxChunks ? i >> 3 : 0;
+    bool b;
+    q.r[k] = box_lookup(S, x0 - 1 + hr % kBoxH, y0 - 1 + hr / kBoxH, z, b);
+    in |= b && i < kBoxChunks ? 1u << k : 0u;
   }
   const int pt = tid >> 2;   // coefficient point of this thread: quarter tid % 4 of its 16 values
-  q.rc = box_row(S, x0 + (pt & 7), y0 + (pt >> 3), z);
+  bool b;
+  q.rc = box_lookup(S, x0 + (pt & 7), y0 + (pt >> 3), z, b);
+  q.in = in | (b ? 1u << kBoxLd : 0u);
 }
 
 __device__ __forceinline__ void box_issue(const CgSys& S, const float* __restrict__ P, int c0, const BoxRows& q,
@@ -534,13 +550,15 @@ __device__ __forceinline__ void box_issue(const CgSys& S, const float* __restric
   const int tid = threadIdx.x;
 #pragma unroll
   for (int k = 0; k < kBoxLd; ++k) {
-    const int i = k * 256 + tid;
-    b.pv[k] = (u32x4){0u, 0u, 0u, 0u};
-    if (q.r[k] >= 0) b.pv[k] = *((const MOR_GLOBAL u32x4*)(P + (int64_t)q.r[k] * S.ld + c0 + (i & 7) * 4));
+    const int i = k * 256 + tid;   // rows outside the box read row 0 (zeroed when stored)
+    const int64_t o = (q.in >> k) & 1u ? (int64_t)q.r[k] * S.ld + (i & 7) * 4 : 0;
+    b.pv[k] = *((const MOR_GLOBAL u32x4*)(P + o + c0));
   }
-  b.cv = (u32x4){0u, 0u, 0u, 0u};
-  if (q.rc >= 0) b.cv = *((const MOR_GLOBAL u32x4*)(S.s16 + (int64_t)q.rc * kStencil + (tid & 3) * 4));
-  b.rc = q.rc;
+  const bool pin = (q.in >> kBoxLd) & 1u;
+  const int64_t oc = pin ? (int64_t)q.rc * kStencil + (tid & 3) * 4 : 0;
+  b.cv = *((const MOR_GLOBAL u32x4*)(S.s16 + oc));
+  b.rc = pin ? q.rc : -1;
+  b.ok = q.in;
 }
 
 __device__ __forceinline__ void box_store(const BoxPlane& b, float (*pl)[32], float* cf, int* rid) {
@@ -548,9 +566,9 @@ __device__ __forceinline__ void box_store(const BoxPlane& b, float (*pl)[32], fl
 #pragma unroll
   for (int k = 0; k < kBoxLd; ++k) {
     const int i = k * 256 + tid;
-    if (i < kBoxChunks) *reinterpret_cast<u32x4*>(&pl[i >> 3][(i & 7) * 4]) = b.pv[k];
+    if (i < kBoxChunks) *reinterpret_cast<u32x4*>(&pl[i >> 3][(i & 7) * 4]) = box_keep((b.ok >> k) & 1u, b.pv[k]);
   }
-  *reinterpret_cast<u32x4*>(&cf[tid * 4]) = b.cv;
+  *reinterpret_cast<u32x4*>(&cf[tid * 4]) = box_keep((b.ok >> kBoxLd) & 1u, b.cv);
   if ((tid & 3) == 0) rid[tid >> 2] = b.rc;
 }
 
@@ -573,7 +591,7 @@ __global__ __launch_bounds__(256) void k_cg_spmm_box(const CgSys* __restrict__ s
   // a slice whose columns have all converged is skipped (their alpha is 0: Q is not read)
   if (!__syncthreads_or(c0 + col < ld && S.active[c0 + col] != 0)) return;
   // P slot of plane z: (z + 3) % 3 (plane -1 is zeros); coefficient and row-id slot: z % 2
-  BoxRows q;
+  BoxRows q, qa, qb;
   BoxPlane A, B;
   box_rows(S, x0, y0, -1, q);
   box_issue(S, P, c0, q, A);
@@ -588,51 +606,70 @@ __global__ __launch_bounds__(256) void k_cg_spmm_box(const CgSys* __restrict__ s
   box_issue(S, P, c0, q, A);
   box_rows(S, x0, y0, 3, q);
   box_issue(S, P, c0, q, B);
-  box_rows(S, x0, y0, 4, q);
+  box_rows(S, x0, y0, 4, qa);
   __syncthreads();
   double part = 0.0;
   // one plane: Q rows of plane z from slots (lower, centre, upper); then plane z+2 from `nx`
-  // into the lower slot, the loads of plane z+4 (rows in q) into `nx`, and the rows of z+5
-  auto plane = [&](int z, BoxPlane& nx) {
+  // into the lower slot, the rows of plane z+5 into `qn` and the loads of plane z+4 (rows in
+  // `qz`) into `nx`.  The rows are looked up before the loads go out, so that waiting for them
+  // (next plane) leaves those loads in flight; qa / qb alternate, so nothing in flight is copied.
+  auto plane = [&](int z, BoxPlane& nx, const BoxRows& qz, BoxRows& qn) {
     const int sc = z % 3, su = (z + 1) % 3, sl = (z + 2) % 3, cs = z & 1;
     const float* cfz = cf[cs];
+    // the thread's values of plane slot L at footprint row yy + dy, point xi (-1..8)
+    const int hb = (yy + 1) * kBoxH + 1;
+    auto V = [&](int L, int dy, int xi) { return pl[L][hb + dy * kBoxH + xi][col]; };
+    // sliding windows along x: each LDS value is read once per thread (c: centre plane at rows
+    // y-1 / y / y+1, u: upper plane at y / y+1, l: lower plane at y-1 / y; m / 0 / 1 = x-1 / x / x+1)
+    float cmm = V(sc, -1, -1), cm0 = V(sc, -1, 0), c0m = V(sc, 0, -1), c00 = V(sc, 0, 0), cp0 = V(sc, 1, 0);
+    float u00 = V(su, 0, 0), up0 = V(su, 1, 0);
+    float lmm = V(sl, -1, -1), lm0 = V(sl, -1, 0), l0m = V(sl, 0, -1), l00 = V(sl, 0, 0);
 #pragma unroll
     for (int x = 0; x < kBoxF; ++x) {
-      const int h = (yy + 1) * kBoxH + (x + 1);   // the point's halo position
+      const float c01 = V(sc, 0, x + 1), cp1 = V(sc, 1, x + 1), u01 = V(su, 0, x + 1), up1 = V(su, 1, x + 1);
       const float* c = cfz + (yy * kBoxF + x) * kStencil;
-      float acc = c[0] * pl[sc][h][col];
-      acc += c[1] * pl[sc][h + 1][col];
-      acc += c[2] * pl[sc][h + kBoxH][col];
-      acc += c[3] * pl[su][h][col];
-      acc += c[4] * pl[sc][h + kBoxH + 1][col];
-      acc += c[5] * pl[su][h + 1][col];
-      acc += c[6] * pl[su][h + kBoxH][col];
-      acc += c[7] * pl[su][h + kBoxH + 1][col];
-      acc += c[8] * pl[sc][h - 1][col];
-      acc += c[9] * pl[sc][h - kBoxH][col];
-      acc += c[10] * pl[sl][h][col];
-      acc += c[11] * pl[sc][h - kBoxH - 1][col];
-      acc += c[12] * pl[sl][h - 1][col];
-      acc += c[13] * pl[sl][h - kBoxH][col];
-      acc += c[14] * pl[sl][h - kBoxH - 1][col];
-      const int r = rid[cs][yy * kBoxF + x];   // -1 outside the box
+      float acc = c[0] * c00;
+      acc += c[1] * c01;
+      acc += c[2] * cp0;
+      acc += c[3] * u00;
+      acc += c[4] * cp1;
+      acc += c[5] * u01;
+      acc += c[6] * up0;
+      acc += c[7] * up1;
+      acc += c[8] * c0m;
+      acc += c[9] * cm0;
+      acc += c[10] * l00;
+      acc += c[11] * cmm;
+      acc += c[12] * l0m;
+      acc += c[13] * lm0;
+      acc += c[14] * lmm;
+      // the stores stay conditional (a point outside the box has rid -1): then a wait for plane
+      // z+2 also completes most of plane z+3's loads, but storing such points into spare rows,
+      // which makes every count exact, took 174-186 VGPRs (two workgroups per CU) and was slower
+      const int r = rid[cs][yy * kBoxF + x];
       if (r >= 0) {
         st_nt(Q + (int64_t)r * ld + c0 + col, acc);
-        part += (double)pl[sc][h][col] * (double)acc;
+        part += (double)c00 * (double)acc;
+      }
+      if (x + 1 < kBoxF) {
+        c0m = c00; c00 = c01; cp0 = cp1; u00 = u01; up0 = up1;
+        cmm = cm0; cm0 = V(sc, -1, x + 1);
+        l0m = l00; l00 = V(sl, 0, x + 1);
+        lmm = lm0; lm0 = V(sl, -1, x + 1);
       }
     }
     __syncthreads();
     box_store(nx, pl[sl], cf[cs], rid[cs]);
     __syncthreads();
-    box_issue(S, P, c0, q, nx);
-    box_rows(S, x0, y0, z + 5, q);
+    box_rows(S, x0, y0, z + 5, qn);
+    box_issue(S, P, c0, qz, nx);
   };
   int z = 0;
   for (; z + 1 < nz; z += 2) {
-    plane(z, A);
-    plane(z + 1, B);
+    plane(z, A, qa, qb);
+    plane(z + 1, B, qb, qa);
   }
-  if (z < nz) plane(z, A);
+  if (z < nz) plane(z, A, qa, qb);
   red[yy][col] = part;
   __syncthreads();
   if (tid < 32 && c0 + tid < ld) {
