@@ -711,18 +711,21 @@ void launch_cg_spmm_box(const CgSys* sys, const int4* tiles, int ntiles, hipStre
   const int ld = S.ld;                                        \
   const int bend = min(tl.y + bpt, S.nblk);
 
+// z = row j (< nb) of the block inverse times the block's rows rr (rows past nb zero).  The row
+// holds 8 entries, zero past nb, so all 8 are read without a branch; callers apply it to every j
+// with the row clamped to nb - 1 (the results past nb are not used), so that no branch separates
+// the reads of a block's rows and they go out together.
 template <typename T, int V>
 __device__ __forceinline__ void block_apply(const T* __restrict__ minv, int r0, int nb, const T (&rr)[8][V], int j,
                                             T (&z)[V]) {
+  (void)nb;
 #pragma unroll
   for (int q = 0; q < V; ++q) z[q] = 0;
 #pragma unroll
   for (int k = 0; k < 8; ++k) {
-    if (k < nb) {
-      const T m = gld(minv + (int64_t)(r0 + j) * 8 + k);
+    const T m = gld(minv + (int64_t)(r0 + j) * 8 + k);
 #pragma unroll
-      for (int q = 0; q < V; ++q) z[q] += m * rr[k][q];
-    }
+    for (int q = 0; q < V; ++q) z[q] += m * rr[k][q];
   }
 }
 
@@ -812,16 +815,16 @@ __global__ __launch_bounds__(256) void k_cg_pstart(const CgSys* __restrict__ sys
         }
       }
       if (S.rc != nullptr) coarse_gather<T, V>(nb, rr, cs);
+      T zz[8][V];
 #pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        if (j < nb) {
-          T z[V];
-          block_apply<T, V>(minv, r0, nb, rr, j, z);
+      for (int j = 0; j < 8; ++j) {   // rows past nb: rr is zero, nothing is stored
+        block_apply<T, V>(minv, r0, nb, rr, min(j, nb - 1), zz[j]);
 #pragma unroll
-          for (int q = 0; q < V; ++q) part[q] += (double)rr[j][q] * (double)z[q];
-          st_vec<T, V>(P + (int64_t)(r0 + j) * ld + c0, z);
-        }
+        for (int q = 0; q < V; ++q) part[q] += (double)rr[j][q] * (double)zz[j][q];
       }
+#pragma unroll
+      for (int j = 0; j < 8; ++j)
+        if (j < nb) st_vec<T, V>(P + (int64_t)(r0 + j) * ld + c0, zz[j]);
     }
   }
   const bool whole = tl.y % kCoarseAgg == 0 && (bend - tl.y >= kCoarseAgg || bend == S.nblk);
@@ -864,16 +867,19 @@ __global__ __launch_bounds__(256) void k_cg_update(const CgSys* __restrict__ sys
 #pragma unroll
         for (int q = 0; q < V; ++q) rr[j][q] -= al[q] * qq[j][q];
       if (S.rc != nullptr) coarse_gather<T, V>(nb, rr, cs);
+      // every row's block-Jacobi product before the first store: the compiler keeps the
+      // (scalar) block-inverse loads after a store that may alias them, so between the rows'
+      // stores they went out, and were waited for, one row at a time
 #pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        if (j < nb) {
-          T z[V];
-          block_apply<T, V>(minv, r0, nb, rr, j, z);
+      for (int j = 0; j < 8; ++j) {   // rows past nb: rr is zero and adds nothing
+        T z[V];
+        block_apply<T, V>(minv, r0, nb, rr, min(j, nb - 1), z);
 #pragma unroll
-          for (int q = 0; q < V; ++q) part[q] += (double)rr[j][q] * (double)z[q];
-          st_vec<T, V>(R + (int64_t)(r0 + j) * ld + c0, rr[j]);
-        }
+        for (int q = 0; q < V; ++q) part[q] += (double)rr[j][q] * (double)z[q];
       }
+#pragma unroll
+      for (int j = 0; j < 8; ++j)
+        if (j < nb) st_vec<T, V>(R + (int64_t)(r0 + j) * ld + c0, rr[j]);
     }
   }
   const bool whole = tl.y % kCoarseAgg == 0 && (bend - tl.y >= kCoarseAgg || bend == S.nblk);
@@ -910,31 +916,44 @@ __global__ __launch_bounds__(256) void k_cg_direction(const CgSys* __restrict__ 
 #pragma unroll
       for (int q = 0; q < V; ++q) ec[q] = (T)e[q];
     }
-    T rr[8][V], pp[8][V];
+    // the block's R, P and X rows are all loaded before any store: the compiler keeps a load
+    // after a store that may alias it, so X loads between the rows' stores went out one row at
+    // a time, each waited for in turn (R first: the block-Jacobi products need all its rows)
+    T rr[8][V], pp[8][V], xx[8][V];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      if (j < nb) ld_vec<T, V>(R + (int64_t)(r0 + j) * ld + c0, rr[j]);
+      else {
+#pragma unroll
+        for (int q = 0; q < V; ++q) rr[j][q] = 0;
+      }
+    }
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
       if (j < nb) {
-        ld_vec<T, V>(R + (int64_t)(r0 + j) * ld + c0, rr[j]);
         ld_vec<T, V>(P + (int64_t)(r0 + j) * ld + c0, pp[j]);
+        ld_vec<T, V>(X + (int64_t)(r0 + j) * ld + c0, xx[j]);
       } else {
 #pragma unroll
-        for (int q = 0; q < V; ++q) rr[j][q] = pp[j][q] = 0;
+        for (int q = 0; q < V; ++q) pp[j][q] = xx[j][q] = 0;
+      }
+    }
+    T zz[8][V];   // every new direction is formed before the first store, for the same reason
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {   // rows past nb are not stored
+      block_apply<T, V>(minv, r0, nb, rr, min(j, nb - 1), zz[j]);
+#pragma unroll
+      for (int q = 0; q < V; ++q) {
+        xx[j][q] += al[q] * pp[j][q];
+        zz[j][q] += ec[q] + be[q] * pp[j][q];
       }
     }
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
       if (j < nb) {
         const int64_t o = (int64_t)(r0 + j) * ld + c0;
-        T x[V], z[V];
-        ld_vec<T, V>(X + o, x);
-        block_apply<T, V>(minv, r0, nb, rr, j, z);
-#pragma unroll
-        for (int q = 0; q < V; ++q) {
-          x[q] += al[q] * pp[j][q];
-          z[q] += ec[q] + be[q] * pp[j][q];
-        }
-        st_vec<T, V>(X + o, x);
-        st_vec<T, V>(P + o, z);
+        st_vec<T, V>(X + o, xx[j]);
+        st_vec<T, V>(P + o, zz[j]);
       }
     }
   }
