@@ -392,8 +392,11 @@ class Mor:
             if not torch.cuda.is_available():
                 raise RuntimeError("no HIP device visible to torch")
             # memory from torch's caching allocator; the library orders its work on its own null
-            # stream and synchronizes before it returns or releases memory
+            # stream and synchronizes before it returns or releases memory.  Blocks that earlier
+            # contexts released stay in torch's cache, where the library's default HBM budget
+            # (3/4 of the device's free memory) would not see them: hand them back first.
             torch.cuda.synchronize()
+            torch.cuda.empty_cache()
             self._alloc = _TorchAllocator(None)
             self.opts.dev_alloc = self._alloc.alloc_cb
             self.opts.dev_free = self._alloc.free_cb
