@@ -118,7 +118,9 @@ typedef struct {
   int32_t use_graph;       /* capture each CG chunk in a HIP graph and replay it */
   int32_t dense_batch;     /* finished requests gathered before the dense stage runs while others
                               still iterate (0 = 16; 1 = lowest latency) */
-  size_t hbm_budget_bytes; /* device bytes one batch of local reductions may use (0 = 75% free) */
+  size_t hbm_budget_bytes; /* device bytes one batch of local reductions may use (0 = 75% of the
+                              device memory free when the engine starts, as hipMemGetInfo reports
+                              it: memory a caller's allocator keeps cached counts as used) */
   mor_alloc_fn dev_alloc;  /* NULL: hipMalloc */
   mor_free_fn dev_free;    /* NULL: hipFree */
   void* alloc_user;
