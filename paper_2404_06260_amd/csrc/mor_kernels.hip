@@ -490,13 +490,13 @@ __global__ __launch_bounds__(256) void k_cg_spmm_halo(const CgSys* __restrict__ 
 // plane-streaming stencil.  A workgroup owns an 8 x 8 footprint of the box in (x, y) and one
 // 128-byte column slice, and marches along z.  Three planes of P (the footprint with a one-point
 // ring, z-1, z, z+1) and two planes of stencil coefficients (16 per row, from the assembled
-// matrix) sit in LDS; the loads of planes z+2 and z+3 are in flight in registers while plane z
-// computes, and the grid-point -> row lookups run one plane ahead of those loads, so no load
-// waits on another.  Each P row of the box is fetched once per slice by the workgroup and shared
+// matrix) sit in LDS; the loads of planes z+2 and z+3 are issued into registers before plane z
+// computes, and the grid-point -> row lookups run one plane ahead of those loads, so a lookup
+// never waits on a plane's loads.  Each P row of the box is fetched once per slice by the workgroup and shared
 // with the neighbouring footprints (consecutive workgroups on one XCD) through L2.  Grid points
 // outside the box (interface or Dirichlet nodes) read as zero, and their coefficients are zero.
-// Each thread owns one column and one footprint row of 8 points; per-column p'Q is summed over
-// the workgroup and added once.
+// Each thread owns one column and one footprint row of 8 points, reading each LDS value once
+// through sliding windows along x; per-column p'Q is summed over the workgroup and added once.
 constexpr int kBoxF = 8;                     // footprint edge
 constexpr int kBoxH = kBoxF + 2;             // with the ring
 constexpr int kBoxRows = kBoxH * kBoxH;      // halo rows per plane
