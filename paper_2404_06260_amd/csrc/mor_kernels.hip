@@ -492,9 +492,10 @@ __global__ __launch_bounds__(256) void k_cg_spmm_halo(const CgSys* __restrict__ 
 // ring, z-1, z, z+1) and two planes of stencil coefficients (16 per row, from the assembled
 // matrix) sit in LDS; the loads of planes z+2 and z+3 are issued into registers before plane z
 // computes, and the grid-point -> row lookups run one plane ahead of those loads, so a lookup
-// never waits on a plane's loads.  Each P row of the box is fetched once per slice by the workgroup and shared
-// with the neighbouring footprints (consecutive workgroups on one XCD) through L2.  Grid points
-// outside the box (interface or Dirichlet nodes) read as zero, and their coefficients are zero.
+// never waits on a plane's loads.  Each P row of the box is fetched once per slice by the
+// workgroup and shared with the neighbouring footprints (consecutive workgroups on one XCD)
+// through L2.  Grid points outside the box (interface or Dirichlet nodes) read as zero, and
+// their coefficients are zero.
 // Each thread owns one column and one footprint row of 8 points, reading each LDS value once
 // through sliding windows along x; per-column p'Q is summed over the workgroup and added once.
 constexpr int kBoxF = 8;                     // footprint edge
